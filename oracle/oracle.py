@@ -1,0 +1,306 @@
+"""Python face of the FP64 CPU oracle (``recogs_oracle.c``).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this module. It never imports the HIP
+package, and the HIP package never imports it; the two sides meet only in the
+seeded arrays produced by ``synth``.
+
+Each function restates one step of the method (paper: ReCoGS, arXiv 2511.18441;
+equations cited per function) as a plain definition evaluated in double precision.
+Library primitives used as steps: numpy's stable sort for the (tile, depth, index)
+order and numpy's cumulative sum for the exclusive scan of tile counts.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "recogs_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+# column layout of the per-Gaussian records (mirrors the enums in recogs_oracle.c)
+PCOLS = ["z", "z32", "u", "v", "sa", "sb", "sc", "ca", "cb", "cc", "r", "g", "b",
+         "pr", "pg", "pb", "fr", "fg", "fb", "sigma", "qext", "ex", "ey", "det"]
+ICOLS = ["status", "pxlo", "pxhi", "pylo", "pyhi", "txlo", "txhi", "tylo", "tyhi",
+         "count", "flag", "z32bits", "sel"]
+P = {k: i for i, k in enumerate(PCOLS)}
+I = {k: i for i, k in enumerate(ICOLS)}
+
+Y00 = 1.0 / (2.0 * np.sqrt(np.pi))
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP over query windows, strict IEEE doubles)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                        "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("znear", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        vp = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.orc_sh_basis.argtypes = [i32, f64, f64, f64, vp]
+        L.orc_covariance.argtypes = [i64, vp, vp, vp]
+        L.orc_project.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(_Cam), i32, i32, vp, vp, vp, vp, vp]
+        L.orc_select.argtypes = [i64, vp, vp, ctypes.POINTER(_Cam), f64, f64, f64, vp, f64, vp, vp]
+        L.orc_recolor.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+        L.orc_emit_keys.argtypes = [i64, vp, i32, i64, vp, vp, vp]
+        L.orc_emit_keys.restype = i64
+        L.orc_render_windows.argtypes = [i64, vp, vp, i32, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.orc_backward.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_ncols.argtypes = [i32]
+        L.orc_ncols.restype = i32
+        assert L.orc_ncols(0) == len(PCOLS) and L.orc_ncols(1) == len(ICOLS)
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def camera(cam) -> _Cam:
+    c = _Cam()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    for k, v in enumerate(np.asarray(cam.R, np.float32).reshape(9)):
+        c.R[k] = float(v)
+    for k, v in enumerate(np.asarray(cam.t, np.float32).reshape(3)):
+        c.t[k] = float(v)
+    c.znear = float(cam.znear)
+    return c
+
+
+# ---------------------------------------------------------------------------
+def sh_basis(deg: int, d) -> np.ndarray:
+    """Real SH basis values Y_k(d), k < (deg+1)^2, at a unit direction d (eq. 2)."""
+    out = np.zeros(16)
+    lib().orc_sh_basis(deg, float(d[0]), float(d[1]), float(d[2]), _p(out))
+    return out[: (deg + 1) ** 2]
+
+
+def covariance(log_scales, quats) -> np.ndarray:
+    """eq. (1): Sigma = R S S^T R^T; planes xx, xy, xz, yy, yz, zz."""
+    ls, q = _d(log_scales), _d(quats)
+    n = ls.shape[1]
+    out = np.empty((6, n))
+    lib().orc_covariance(n, _p(ls), _p(q), _p(out))
+    return out
+
+
+@dataclass
+class Projection:
+    f: np.ndarray      # (n, len(PCOLS)) float64
+    i: np.ndarray      # (n, len(ICOLS)) int64
+    tile: tuple
+    width: int
+    height: int
+
+    def col(self, name):
+        return self.f[:, P[name]] if name in P else self.i[:, I[name]]
+
+    @property
+    def tiles_x(self):
+        return -(-self.width // self.tile[0])
+
+    @property
+    def tiles_y(self):
+        return -(-self.height // self.tile[1])
+
+
+def project(scene, cam, tile=(16, 16), cov=None, mask=None, M=None, b=None) -> Projection:
+    """Per-Gaussian depth, EWA conic, colour (eq. 2, optional fused recolour, eq. 6)
+    and tile rectangle (see orc_project)."""
+    n = scene.n
+    means = _d(scene.means)
+    if cov is None:
+        cov = covariance(scene.log_scales, scene.quats)
+    cov = _d(cov)
+    op = _d(scene.opacity_f32())
+    sh = _d(scene.sh_f32())
+    f = np.empty((n, len(PCOLS)))
+    i = np.empty((n, len(ICOLS)), dtype=np.int64)
+    c = camera(cam)
+    mk = Mv = bv = None
+    if mask is not None:
+        mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        Mv = _d(M).reshape(9)
+        bv = _d(b).reshape(3)
+    lib().orc_project(n, _p(means), _p(cov), _p(op), _p(sh), scene.sh_degree, ctypes.byref(c),
+                      int(tile[0]), int(tile[1]),
+                      _p(mk) if mk is not None else None, _p(Mv) if Mv is not None else None,
+                      _p(bv) if bv is not None else None, _p(f), _p(i))
+    return Projection(f, i, tuple(tile), int(cam.width), int(cam.height))
+
+
+def select(scene, cam, sp):
+    """Selection predicate: (mask uint8[n], in-band flag uint8[n])."""
+    n = scene.n
+    means = _d(scene.means)
+    dc = _d(scene.sh_f32()[0:3])
+    mask = np.zeros(n, np.uint8)
+    flag = np.zeros(n, np.uint8)
+    ref = _d(np.asarray(sp.ref, np.float32))
+    lib().orc_select(n, _p(means), _p(dc), ctypes.byref(camera(cam)), float(sp.cx), float(sp.cy),
+                     float(sp.radius), _p(ref), float(sp.color_radius), _p(mask), _p(flag))
+    return mask, flag
+
+
+def recolor(sh, mask, M, b) -> np.ndarray:
+    """Recolour on coefficients (eq. 6 generalised); sh is ([3K], n) float values."""
+    sh = _d(sh)
+    n = sh.shape[1]
+    out = np.empty_like(sh)
+    mk = np.ascontiguousarray(np.asarray(mask, np.uint8))
+    lib().orc_recolor(n, sh.shape[0] // 3, _p(sh), _p(mk), _p(_d(M).reshape(9)),
+                      _p(_d(b).reshape(3)), _p(out))
+    return out
+
+
+def tile_offsets(proj: Projection):
+    """Exclusive scan of the per-Gaussian tile counts, and their total K."""
+    c = proj.col("count")
+    off = np.concatenate([[0], np.cumsum(c)])
+    return off[:-1], int(off[-1])
+
+
+def emit_keys(proj: Projection):
+    """(tile, depth bits, index) triplets in emission order."""
+    n = proj.f.shape[0]
+    K = int(proj.col("count").sum())
+    tile = np.empty(K, np.int64)
+    zb = np.empty(K, np.int64)
+    idx = np.empty(K, np.int64)
+    k = lib().orc_emit_keys(n, _p(proj.i), proj.tiles_x, K, _p(tile), _p(zb), _p(idx))
+    assert k == K
+    return tile, zb, idx
+
+
+def sorted_keys(proj: Projection):
+    """Keys sorted by (tile, float32 depth, index): a stable sort on (tile, depth)."""
+    tile, zb, idx = emit_keys(proj)
+    order = np.lexsort((idx, zb, tile))
+    return tile[order], zb[order], idx[order]
+
+
+def tile_ranges(tile_sorted: np.ndarray, n_tiles: int) -> np.ndarray:
+    """[first, last+1) of each tile in the sorted list; (0, 0) for empty tiles."""
+    r = np.zeros((n_tiles, 2), np.int64)
+    if tile_sorted.size:
+        starts = np.searchsorted(tile_sorted, np.arange(n_tiles), side="left")
+        ends = np.searchsorted(tile_sorted, np.arange(n_tiles), side="right")
+        nz = ends > starts
+        r[nz, 0] = starts[nz]
+        r[nz, 1] = ends[nz]
+    return r
+
+
+@dataclass
+class PixelResult:
+    rgb: np.ndarray     # (npix, 3)
+    T: np.ndarray       # (npix,)
+    last: np.ndarray    # (npix,) int64, -1 when nothing blended
+    nblend: np.ndarray  # (npix,) int64
+    slack: np.ndarray   # (npix,)
+
+
+def render_windows(proj: Projection, windows, bg=(0.0, 0.0, 0.0), brute: bool = False) -> PixelResult:
+    """Per-pixel compositing (eq. 3) for the pixels of each window (x0, y0, w, h),
+    listed window by window in row-major order."""
+    win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 4))
+    npix = int((win[:, 2].astype(np.int64) * win[:, 3]).sum())
+    rgb = np.empty((npix, 3))
+    T = np.empty(npix)
+    last = np.empty(npix, np.int64)
+    nb = np.empty(npix, np.int64)
+    slack = np.empty(npix)
+    n = proj.f.shape[0]
+    lib().orc_render_windows(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), win.shape[0], _p(win), int(brute),
+                             _p(rgb), _p(T), _p(last), _p(nb), _p(slack))
+    return PixelResult(rgb, T, last, nb, slack)
+
+
+def render_image(proj: Projection, bg=(0.0, 0.0, 0.0), brute: bool = False, window: int = 32):
+    """Whole image, HWC, via windows of `window` pixels; returns images of each output."""
+    W, H = proj.width, proj.height
+    wins = [(x, y, min(window, W - x), min(window, H - y))
+            for y in range(0, H, window) for x in range(0, W, window)]
+    r = render_windows(proj, wins, bg, brute)
+    img = np.empty((H, W, 3))
+    T = np.empty((H, W))
+    last = np.empty((H, W), np.int64)
+    nb = np.empty((H, W), np.int64)
+    slack = np.empty((H, W))
+    o = 0
+    for (x, y, w, h) in wins:
+        m = w * h
+        img[y:y + h, x:x + w] = r.rgb[o:o + m].reshape(h, w, 3)
+        T[y:y + h, x:x + w] = r.T[o:o + m].reshape(h, w)
+        last[y:y + h, x:x + w] = r.last[o:o + m].reshape(h, w)
+        nb[y:y + h, x:x + w] = r.nblend[o:o + m].reshape(h, w)
+        slack[y:y + h, x:x + w] = r.slack[o:o + m].reshape(h, w)
+        o += m
+    return PixelResult(img, T, last, nb, slack)
+
+
+def loss_l2(y, target) -> float:
+    """L = mean over all pixels and channels of (y - t)^2."""
+    return float(np.mean((np.asarray(y, np.float64) - np.asarray(target, np.float64)) ** 2))
+
+
+def loss_l2_grad(y, target, count: Optional[int] = None) -> np.ndarray:
+    """dL/dy = 2 (y - t) / count, count = number of pixel channels in the loss."""
+    y = np.asarray(y, np.float64)
+    count = y.size if count is None else count
+    return 2.0 * (y - np.asarray(target, np.float64)) / count
+
+
+@dataclass
+class Grads:
+    dsigma: np.ndarray   # (n,)
+    drgb: np.ndarray     # (n, 3)
+    dc0: np.ndarray      # (3, n)
+    dM: np.ndarray       # (3, 3)
+
+
+def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0)) -> Grads:
+    """Gradients of eq. (8) restricted to opacity, SH DC and the recolour matrix."""
+    n = proj.f.shape[0]
+    g = _d(dldy).reshape(proj.height, proj.width, 3)
+    Mv = _d(np.eye(3) if M is None else M).reshape(9)
+    ds = np.empty(n)
+    dr = np.empty((n, 3))
+    dc = np.empty((3, n))
+    dM = np.empty(9)
+    lib().orc_backward(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), _p(Mv), _p(g),
+                       _p(ds), _p(dr), _p(dc), _p(dM))
+    return Grads(ds, dr, dc, dM.reshape(3, 3))
