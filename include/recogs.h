@@ -1,0 +1,203 @@
+/*
+ * recogs.h -- C ABI of the MI355X (gfx950) select / recolour / splat-render library.
+ *
+ * The operations follow ReCoGS (Rutayisire, Capodieci, Pellacini; arXiv 2511.18441):
+ * a pre-trained 3D Gaussian Splatting scene (Sec. 3.1: covariance eq. 1, SH colour
+ * eq. 2, front-to-back alpha blending eq. 3) has a region selected (Sec. 3.3) and
+ * tinted (Sec. 3.5, eq. 6), is rendered with an HWC output (Sec. 4.3) and
+ * differentiated w.r.t. its colour parameters (Sec. 4.1, eq. 7-8).
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers unless marked (host). The caller owns every
+ *     buffer. The library keeps no device state between calls and allocates no
+ *     device memory; render state lives in a caller-provided workspace.
+ *   - Scene arrays are structure-of-arrays "planes": plane p of an array with
+ *     stride s occupies elements [p*s, p*s + n). All planes of one scene share
+ *     one stride >= n.
+ *   - Every call is enqueued on `stream` (NULL = the null stream) and returns a
+ *     status. Argument errors are found on the host before anything is enqueued.
+ *     recogs_render synchronises `stream` once (to read the number of tile keys);
+ *     the other calls never synchronise.
+ *   - On error, recogs_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread). No call aborts or throws.
+ *   - Float math on the GPU is float32; storage may be f16 / bf16 for opacity and SH.
+ */
+#ifndef RECOGS_H
+#define RECOGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { RECOGS_F32 = 0, RECOGS_F16 = 1, RECOGS_BF16 = 2 } recogs_dtype;
+
+typedef enum {
+    RECOGS_OK = 0,
+    RECOGS_ERR_INVALID = -1,      /* bad argument (null pointer, size, shape, enum)  */
+    RECOGS_ERR_CAPACITY = -2,     /* workspace too small for the tile keys of this view */
+    RECOGS_ERR_UNSUPPORTED = -3,  /* valid but not supported (e.g. tile shape)        */
+    RECOGS_ERR_HIP = -4           /* a HIP runtime call failed; see recogs_last_error */
+} recogs_status;
+
+/* Scene (eq. 1-2). Geometry is frozen while colours are edited (Sec. 3.5).
+ *   means   float [3][stride]          world-space centres x, y, z
+ *   cov3d   float [6][stride]          3D covariance xx, xy, xz, yy, yz, zz (eq. 1)
+ *   opacity storage [stride]           activated opacity sigma in (0, 1)
+ *   sh      storage [(deg+1)^2*3][stride]  SH coefficients, plane = k*3 + channel,
+ *                                      k = l*l + l + m, real SH with Condon-Shortley
+ *                                      phase; displayed colour = max(0, f + 1/2). */
+typedef struct {
+    int64_t n;
+    int64_t stride;
+    int32_t sh_degree;   /* 0..3 */
+    int32_t storage;     /* recogs_dtype of opacity and sh */
+    const float *means;
+    const float *cov3d;
+    const void *opacity;
+    const void *sh;
+} recogs_scene;
+
+/* Pinhole camera (host struct). World -> camera m = R mu + t, axes x right, y down,
+ * z forward. Pixel (px, py) has its centre at (px + 1/2, py + 1/2); a point projects
+ * to (fx m_x / m_z + cx, fy m_y / m_z + cy). Points with depth <= znear are culled. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];          /* row-major */
+    float t[3];
+    float znear;
+} recogs_camera;
+
+/* Selection (host struct): a Gaussian is selected when its depth is > znear, its
+ * projected centre lies in the closed disk (cx, cy, radius) [pixels] and its DC
+ * colour Y00 C0 + 1/2 lies in the closed ball (ref, color_radius). */
+typedef struct {
+    float cx, cy, radius;
+    float ref[3];
+    float color_radius;
+} recogs_select_params;
+
+/* Render options (host struct). */
+typedef struct {
+    int32_t tile_w, tile_h;      /* 8x8, 16x16 or 32x8 */
+    int32_t px_per_thread;       /* 1, 2 or 4 pixels per blend thread */
+    float bg[3];                 /* background colour */
+    /* Optional fused recolour (all three NULL = off): selected Gaussians display
+     * max(0, M (f + 1/2) + b) instead of max(0, f + 1/2). Device pointers:
+     * mask uint8 [n], M float [9] row-major, b float [3]. */
+    const uint8_t *mask;
+    const float *M;
+    const float *b;
+    int32_t keep_backward_state; /* 1: store what recogs_render_backward needs */
+    int32_t profile_stages;      /* 1: time each stage with HIP events on `stream` (the call then
+                                    waits for the blend); times land in ws->stage_ms */
+} recogs_render_opts;
+
+/* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds
+ * the per-Gaussian splat records, the tile keys and their sort buffers, the tile
+ * ranges and the per-pixel state the backward replays. A workspace must outlive the
+ * backward that follows its render and must not be shared by concurrent renders.
+ * Fields are filled by the library; callers only read them. Offsets are bytes from
+ * `base`. */
+typedef struct {
+    void *base;
+    size_t bytes;
+    int64_t n_cap;
+    int32_t width, height, tile_w, tile_h;
+    int64_t key_capacity;
+    int32_t tiles_x, tiles_y;
+    /* buffer offsets */
+    size_t off_rec, off_bwd, off_grad, off_zbits, off_rect, off_count, off_offset, off_scan;
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_status;
+    size_t off_ranges, off_final_T, off_nproc, off_header;
+    size_t scan_chunks, sort_chunks;
+    /* results of the last render, valid when it returned RECOGS_OK (or CAPACITY) */
+    int64_t num_keys;            /* K: tile keys emitted */
+    int32_t sorted_in_alt;       /* 1 if the sorted keys/values are in keys1/vals1 */
+    int32_t sort_passes;
+    int32_t key_bits;            /* significant bits sorted: tile bits + depth bits */
+    int32_t depth_bits;
+    uint32_t depth_min_bits;     /* smallest float32 depth bit pattern among keys */
+    int32_t last_n;
+    /* with profile_stages: milliseconds of [0] preprocess, [1] scan, [2] key-count read-back,
+     * [3] key emission, [4] radix histogram, [5] all radix passes, [6] tile ranges, [7] blend */
+    float stage_ms[8];
+} recogs_workspace;
+
+/* ---- support --------------------------------------------------------------- */
+
+/* Bytes of device memory a workspace needs for scenes of up to n Gaussians,
+ * width x height images, the given tile shape and up to key_capacity tile keys. */
+size_t recogs_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
+                              int64_t key_capacity);
+
+/* Carve `dev_mem` (>= recogs_workspace_bytes(...) bytes, 256-byte aligned) into *ws.
+ * Errors: INVALID for null pointers, bad sizes or too few bytes. */
+recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t bytes, int64_t n,
+                                    int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
+                                    int64_t key_capacity);
+
+/* eq. (1): cov3d = R S S^T R^T from log-scales float [3][stride] and quaternions
+ * float [4][stride] (w, x, y, z; normalised here). Output float [6][stride]. */
+recogs_status recogs_prepare_covariance(const float *log_scales, const float *quats, float *cov3d,
+                                        int64_t n, int64_t stride, hipStream_t stream);
+
+/* ---- the path ---------------------------------------------------------------- */
+
+/* Selection (Sec. 3.3 stand-in): mask uint8 [n] (1 = selected) and *count (device
+ * int32, overwritten) = number selected. */
+recogs_status recogs_select(const recogs_scene *scene, const recogs_camera *cam,
+                            const recogs_select_params *params, uint8_t *mask, int32_t *count,
+                            hipStream_t stream);
+
+/* Recolour (Sec. 3.5, eq. 6 generalised): for every selected i the displayed colour
+ * becomes M (f + 1/2) + b for every view direction, realised on coefficients as
+ * C'_k = M C_k (k >= 1) and C'_0 = M C_0 + ((M - I) 1/2 + b) / Y00.
+ * Reads scene->sh, writes dst_sh (same dtype, degree and stride; may equal
+ * scene->sh). copy_unselected = 1 also copies unselected Gaussians' coefficients;
+ * 0 leaves them untouched in dst_sh. M float [9] row-major and b float [3] are device
+ * pointers; f16/bf16 results are rounded to nearest even. */
+recogs_status recogs_recolor(const recogs_scene *scene, void *dst_sh, const uint8_t *mask,
+                             const float *M, const float *b, int32_t copy_unselected,
+                             hipStream_t stream);
+
+/* Render (eq. 2-3; HWC output, Sec. 4.3): EWA projection, tile binning with a
+ * (tile, depth) key sort, front-to-back compositing with early termination.
+ * image float [height][width][3]. ws must have been initialised for at least this n,
+ * the camera's size and opts' tile shape. Synchronises the stream once.
+ * Errors: INVALID / UNSUPPORTED before any launch; CAPACITY when more tile keys are
+ * needed than ws->key_capacity (ws->num_keys then holds the number needed and the
+ * image is not written); HIP. */
+recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
+                            const recogs_render_opts *opts, recogs_workspace *ws, float *image,
+                            hipStream_t stream);
+
+/* Backward of the render and of the fused recolour (eq. 8, restricted to opacity,
+ * SH DC and the recolour matrix). Needs the workspace of the matching render (run
+ * with keep_backward_state = 1) and its output image. dL_dimage float [H][W][3].
+ * Outputs (overwritten): dL_dopacity float [n], dL_dsh_dc float [3][n] (gradient
+ * w.r.t. the DC coefficients C_0 of each channel), dL_dM float [9] (zero when no
+ * fused recolour). Accumulation order across workgroups is not fixed, so results
+ * may differ in the last bits between runs. */
+recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
+                                     const recogs_render_opts *opts, const recogs_workspace *ws,
+                                     const float *image, const float *dL_dimage, float *dL_dopacity,
+                                     float *dL_dsh_dc, float *dL_dM, hipStream_t stream);
+
+/* L2 loss of an image against a target (the differentiable form's loss, an analog of
+ * eq. 7): loss (device float, overwritten) = scale * sum (y - t)^2 and
+ * dL_dimage = 2 scale (y - t), over `count` floats. scale = 1 / count gives the mean. */
+recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale,
+                             float *dL_dimage, float *loss, hipStream_t stream);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *recogs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RECOGS_H */

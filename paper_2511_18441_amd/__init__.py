@@ -1,0 +1,20 @@
+"""MI355X-native select / recolour / splat-render path of ReCoGS (arXiv 2511.18441).
+
+The compute path is librecogs.so (hand-written HIP for gfx950, C ABI in
+include/recogs.h); this package is its ctypes binding plus a torch.autograd.Function
+over the hand-written backward. Importing it loads the library and fails loudly if it
+has not been built.
+"""
+from .binding import (  # noqa: F401
+    ENTRY_POINTS, RecogsError, DeviceScene, DeviceWorkspace, Scene, Camera, SelectParams, RenderOpts, Workspace,
+    camera_struct, select_struct, opts_struct, render, lib,
+    recogs_workspace_bytes, recogs_workspace_init, recogs_prepare_covariance, recogs_select, recogs_recolor,
+    recogs_render, recogs_render_backward, recogs_loss_l2, recogs_last_error,
+)
+
+lib()
+
+try:  # the autograd wrapper needs torch
+    from .autograd import RecogsRenderFn  # noqa: F401
+except ImportError:  # pragma: no cover
+    pass

@@ -1,0 +1,337 @@
+"""ctypes binding of librecogs.so (include/recogs.h). Argument marshalling only:
+every step of the path runs in the HIP library; torch supplies device memory and
+the current HIP stream.
+
+The C entry points are exposed under their C names (recogs_select, recogs_recolor,
+recogs_render, recogs_render_backward, ...), taking ctypes structs and raw device
+pointers; they raise RecogsError on a non-OK status. Helpers below build those
+structs from torch tensors and the seeded scene containers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librecogs.so")
+
+RECOGS_F32, RECOGS_F16, RECOGS_BF16 = 0, 1, 2
+STATUS = {0: "OK", -1: "INVALID", -2: "CAPACITY", -3: "UNSUPPORTED", -4: "HIP"}
+STORAGE_CODE = {"f32": RECOGS_F32, "f16": RECOGS_F16, "bf16": RECOGS_BF16}
+
+# every entry point declared in include/recogs.h
+ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_prepare_covariance", "recogs_select",
+                "recogs_recolor", "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_last_error")
+
+
+class RecogsError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} -> {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("sh_degree", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("means", ctypes.c_void_p), ("cov3d", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("znear", ctypes.c_float)]
+
+
+class SelectParams(ctypes.Structure):
+    _fields_ = [("cx", ctypes.c_float), ("cy", ctypes.c_float), ("radius", ctypes.c_float),
+                ("ref", ctypes.c_float * 3), ("color_radius", ctypes.c_float)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
+                ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32)]
+
+
+class Workspace(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("n_cap", ctypes.c_int64),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32), ("key_capacity", ctypes.c_int64), ("tiles_x", ctypes.c_int32),
+                ("tiles_y", ctypes.c_int32)] + \
+               [(f, ctypes.c_size_t) for f in (
+                   "off_rec", "off_bwd", "off_grad", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
+                   "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_hist", "off_sort_status",
+                   "off_ranges", "off_final_T", "off_nproc", "off_header", "scan_chunks", "sort_chunks")] + \
+               [("num_keys", ctypes.c_int64), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32), ("depth_min_bits", ctypes.c_uint32),
+                ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8)]
+
+STAGES = ("preprocess", "scan", "readback", "emit", "radix_hist", "radix_passes", "ranges", "blend")
+
+
+_lib = None
+
+
+def lib():
+    """Load librecogs.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_18441_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
+        P = ctypes.POINTER
+        L.recogs_workspace_bytes.argtypes = [i64, i32, i32, i32, i32, i64]
+        L.recogs_workspace_bytes.restype = ctypes.c_size_t
+        L.recogs_workspace_init.argtypes = [P(Workspace), vp, ctypes.c_size_t, i64, i32, i32, i32, i32, i64]
+        L.recogs_prepare_covariance.argtypes = [vp, vp, vp, i64, i64, vp]
+        L.recogs_select.argtypes = [P(Scene), P(Camera), P(SelectParams), vp, vp, vp]
+        L.recogs_recolor.argtypes = [P(Scene), vp, vp, vp, vp, i32, vp]
+        L.recogs_render.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp]
+        L.recogs_render_backward.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp, vp]
+        L.recogs_loss_l2.argtypes = [vp, vp, i64, f32, vp, vp, vp]
+        L.recogs_last_error.restype = ctypes.c_char_p
+        for name in ENTRY_POINTS:
+            if name not in ("recogs_workspace_bytes", "recogs_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise RecogsError(fn, status, lib().recogs_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+# ---------------------------------------------------------------------------
+# the C entry points under their own names
+# ---------------------------------------------------------------------------
+def recogs_workspace_bytes(n, width, height, tile_w, tile_h, key_capacity) -> int:
+    return int(lib().recogs_workspace_bytes(n, width, height, tile_w, tile_h, key_capacity))
+
+
+def recogs_workspace_init(ws: Workspace, dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity):
+    return _check("recogs_workspace_init", lib().recogs_workspace_init(
+        ctypes.byref(ws), dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity))
+
+
+def recogs_prepare_covariance(log_scales, quats, cov3d, n, stride, stream=None):
+    return _check("recogs_prepare_covariance", lib().recogs_prepare_covariance(
+        log_scales, quats, cov3d, n, stride, _stream(stream)))
+
+
+def recogs_select(scene: Scene, cam: Camera, params: SelectParams, mask, count, stream=None):
+    return _check("recogs_select", lib().recogs_select(ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(params),
+                                                       mask, count, _stream(stream)))
+
+
+def recogs_recolor(scene: Scene, dst_sh, mask, M, b, copy_unselected=0, stream=None):
+    return _check("recogs_recolor", lib().recogs_recolor(ctypes.byref(scene), dst_sh, mask, M, b,
+                                                         int(copy_unselected), _stream(stream)))
+
+
+def recogs_render(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, stream=None, check=True):
+    st = lib().recogs_render(ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image,
+                             _stream(stream))
+    return _check("recogs_render", st) if check else st
+
+
+def recogs_render_backward(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
+                           dL_dopacity, dL_dsh_dc, dL_dM, stream=None):
+    return _check("recogs_render_backward", lib().recogs_render_backward(
+        ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage,
+        dL_dopacity, dL_dsh_dc, dL_dM, _stream(stream)))
+
+
+def recogs_loss_l2(image, target, count, scale, dL_dimage, loss, stream=None):
+    return _check("recogs_loss_l2", lib().recogs_loss_l2(image, target, count, float(scale), dL_dimage, loss,
+                                                         _stream(stream)))
+
+
+def recogs_last_error() -> str:
+    return lib().recogs_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    for k, v in enumerate(np.asarray(cam.R, np.float32).reshape(9)):
+        c.R[k] = float(v)
+    for k, v in enumerate(np.asarray(cam.t, np.float32).reshape(3)):
+        c.t[k] = float(v)
+    c.znear = float(cam.znear)
+    return c
+
+
+def select_struct(sp) -> SelectParams:
+    p = SelectParams()
+    p.cx, p.cy, p.radius = float(sp.cx), float(sp.cy), float(sp.radius)
+    for k, v in enumerate(np.asarray(sp.ref, np.float32).reshape(3)):
+        p.ref[k] = float(v)
+    p.color_radius = float(sp.color_radius)
+    return p
+
+
+def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
+                profile=False) -> RenderOpts:
+    o = RenderOpts()
+    o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
+    o.px_per_thread = int(ppt)
+    for k in range(3):
+        o.bg[k] = float(bg[k])
+    o.mask = mask.data_ptr() if mask is not None else None
+    o.M = M.data_ptr() if M is not None else None
+    o.b = b.data_ptr() if b is not None else None
+    o.keep_backward_state = 1 if keep_backward else 0
+    o.profile_stages = 1 if profile else 0
+    return o
+
+
+class DeviceScene:
+    """A scene resident in device memory (torch tensors), plus its C view."""
+
+    def __init__(self, scene, device="cuda", stride: Optional[int] = None):
+        import torch
+        n = scene.n
+        self.n = n
+        self.stride = n if stride is None else int(stride)
+        self.sh_degree = scene.sh_degree
+        self.storage = scene.storage
+        S = self.stride
+
+        def planes(a, dtype):
+            t = torch.zeros((a.shape[0], S), dtype=dtype, device=device)
+            if n:
+                t[:, :n] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+            return t
+        self.means = planes(scene.means, torch.float32)
+        self.log_scales = planes(scene.log_scales, torch.float32)
+        self.quats = planes(scene.quats, torch.float32)
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[scene.storage]
+        if scene.storage == "bf16":
+            op = torch.from_numpy(np.ascontiguousarray(scene.opacity).view(np.int16)).view(torch.bfloat16)
+            sh = torch.from_numpy(np.ascontiguousarray(scene.sh).view(np.int16)).view(torch.bfloat16)
+        else:
+            op = torch.from_numpy(np.ascontiguousarray(scene.opacity))
+            sh = torch.from_numpy(np.ascontiguousarray(scene.sh))
+        self.opacity = torch.zeros(S, dtype=tdt, device=device)
+        self.sh = torch.zeros((sh.shape[0], S), dtype=tdt, device=device)
+        if n:
+            self.opacity[:n] = op.to(device)
+            self.sh[:, :n] = sh.to(device)
+        self.cov3d = torch.empty((6, S), dtype=torch.float32, device=device)
+        recogs_prepare_covariance(self.log_scales.data_ptr(), self.quats.data_ptr(), self.cov3d.data_ptr(), n, S)
+
+    def c_struct(self, sh=None) -> Scene:
+        s = Scene()
+        s.n, s.stride, s.sh_degree = self.n, self.stride, self.sh_degree
+        s.storage = STORAGE_CODE[self.storage]
+        s.means, s.cov3d = self.means.data_ptr(), self.cov3d.data_ptr()
+        s.opacity = self.opacity.data_ptr()
+        s.sh = (self.sh if sh is None else sh).data_ptr()
+        return s
+
+
+class DeviceWorkspace:
+    """Device memory for recogs_render, owned by a torch uint8 tensor."""
+
+    def __init__(self, n, width, height, tile=(16, 16), key_capacity=None, device="cuda"):
+        import torch
+        self.args = (int(n), int(width), int(height), int(tile[0]), int(tile[1]))
+        cap = int(key_capacity if key_capacity is not None else max(1024, 8 * n))
+        self.device = device
+        self._alloc(cap)
+
+    def _alloc(self, cap):
+        import torch
+        nbytes = recogs_workspace_bytes(*self.args, cap)
+        if nbytes == 0:
+            raise RecogsError("recogs_workspace_bytes", -1, "invalid workspace arguments")
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ws = Workspace()
+        recogs_workspace_init(self.ws, self.mem.data_ptr(), nbytes, *self.args, cap)
+
+    def grow(self, needed):
+        self._alloc(int(needed * 1.25) + 1024)
+
+    # views of internal buffers (inspection and tests)
+    def view(self, off, count, dtype):
+        import torch
+        itemsize = torch.empty(0, dtype=dtype).element_size()
+        return self.mem[off: off + count * itemsize].view(dtype)
+
+    def keys_sorted(self):
+        import torch
+        K = int(self.ws.num_keys)
+        off = self.ws.off_keys1 if self.ws.sorted_in_alt else self.ws.off_keys0
+        return self.view(off, K, torch.int64)
+
+    def vals_sorted(self):
+        import torch
+        K = int(self.ws.num_keys)
+        off = self.ws.off_vals1 if self.ws.sorted_in_alt else self.ws.off_vals0
+        return self.view(off, K, torch.int32)
+
+    def counts(self, n):
+        import torch
+        return self.view(self.ws.off_count, n, torch.int32)
+
+    def offsets(self, n):
+        import torch
+        return self.view(self.ws.off_offset, n, torch.int32)
+
+    def zbits(self, n):
+        import torch
+        return self.view(self.ws.off_zbits, n, torch.int32)
+
+    def rects(self, n):
+        import torch
+        return self.view(self.ws.off_rect, 2 * n, torch.int32).view(n, 2)
+
+    def ranges(self):
+        import torch
+        T = self.ws.tiles_x * self.ws.tiles_y
+        return self.view(self.ws.off_ranges, 2 * T, torch.int32).view(T, 2)
+
+    def final_T(self):
+        import torch
+        return self.view(self.ws.off_final_T, self.ws.width * self.ws.height, torch.float32).view(
+            self.ws.height, self.ws.width)
+
+    def nproc(self):
+        import torch
+        return self.view(self.ws.off_nproc, self.ws.width * self.ws.height, torch.int32).view(
+            self.ws.height, self.ws.width)
+
+
+def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
+           M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False):
+    """recogs_render into a (H, W, 3) float32 tensor; grows the workspace once when the
+    view needs more tile keys than it holds."""
+    import torch
+    c = camera_struct(cam)
+    if image is None:
+        image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dscene.means.device)
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile)
+    sc = dscene.c_struct(sh)
+    st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
+    if st == -2 and grow:
+        ws.grow(ws.ws.num_keys)
+        st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
+    _check("recogs_render", st)
+    return image

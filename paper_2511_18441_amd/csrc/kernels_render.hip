@@ -1,0 +1,460 @@
+// Render path kernels: preprocess (EWA projection, SH colour, tile rectangle),
+// exclusive scan of tile counts, key emission, tile ranges, front-to-back blend.
+#include "recogs_internal.hpp"
+
+namespace recogs {
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Real SH basis (eq. 2), degree <= DEG, at unit direction (x, y, z).
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
+    Y[0] = kSH0;
+    if constexpr (DEG >= 1) {
+        Y[1] = -kSH1 * y; Y[2] = kSH1 * z; Y[3] = -kSH1 * x;
+    }
+    if constexpr (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kSH2a * x * y; Y[5] = -kSH2a * y * z; Y[6] = kSH2b * (2.f * zz - xx - yy);
+        Y[7] = -kSH2a * x * z; Y[8] = kSH2c * (xx - yy);
+        if constexpr (DEG >= 3) {
+            Y[9] = -kSH3a * y * (3.f * xx - yy); Y[10] = kSH3b * x * y * z;
+            Y[11] = -kSH3c * y * (4.f * zz - xx - yy); Y[12] = kSH3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+            Y[13] = -kSH3c * x * (4.f * zz - xx - yy); Y[14] = kSH3e * z * (xx - yy);
+            Y[15] = -kSH3a * x * (xx - 3.f * yy);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Preprocess: one thread per Gaussian.
+//   m = R mu + t (compensated); cull depth <= znear.
+//   EWA: J at the 1.3x-frustum-clamped position, Sigma2D = J R Sigma R^T J^T + 0.3 I.
+//   Cull det <= 0 and 255 sigma < 1. Box of q <= 2 ln(255 sigma) + 1/64 -> pixel range
+//   [ceil(u - ex - 1/2), floor(u + ex - 1/2)] clipped -> tile rectangle and count.
+//   Colour max(0, f + 1/2) or, for selected Gaussians of a fused recolour,
+//   max(0, M (f + 1/2) + b).
+// Writes the splat record, depth bits, packed tile rectangle and count; folds the
+// depth range of Gaussians with keys into the workspace header.
+// ---------------------------------------------------------------------------
+template <int DT, int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, RecolorDev rc, int keep_bwd,
+                                                    SplatRec *__restrict__ rec, float4 *__restrict__ bwd,
+                                                    uint32_t *__restrict__ zbits, uint2 *__restrict__ rect,
+                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ header) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cnt = 0, zb = 0;
+    uint2 rr = make_uint2(0u, 0u);
+    if (i < sc.n) {
+        const int64_t S = sc.stride;
+        const float mx = sc.means[i], my = sc.means[S + i], mz = sc.means[2 * S + i];
+        const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
+        zb = __float_as_uint(z);
+        if (z > cam.znear) {
+            const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
+            const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
+            const float iz = 1.0f / z;
+            const float xc = fminf(cam.limx, fmaxf(-cam.limx, x * iz)) * z;
+            const float yc = fminf(cam.limy, fmaxf(-cam.limy, y * iz)) * z;
+            const float j00 = cam.fx * iz, j02 = -cam.fx * xc * iz * iz;
+            const float j11 = cam.fy * iz, j12 = -cam.fy * yc * iz * iz;
+            // T = J R (2 x 3)
+            const float a0 = j00 * cam.R[0] + j02 * cam.R[6], a1 = j00 * cam.R[1] + j02 * cam.R[7],
+                        a2 = j00 * cam.R[2] + j02 * cam.R[8];
+            const float b0 = j11 * cam.R[3] + j12 * cam.R[6], b1 = j11 * cam.R[4] + j12 * cam.R[7],
+                        b2 = j11 * cam.R[5] + j12 * cam.R[8];
+            const float c00 = sc.cov3d[i], c01 = sc.cov3d[S + i], c02 = sc.cov3d[2 * S + i];
+            const float c11 = sc.cov3d[3 * S + i], c12 = sc.cov3d[4 * S + i], c22 = sc.cov3d[5 * S + i];
+            // Sigma T^T columns
+            const float sa0 = c00 * a0 + c01 * a1 + c02 * a2, sa1 = c01 * a0 + c11 * a1 + c12 * a2,
+                        sa2 = c02 * a0 + c12 * a1 + c22 * a2;
+            const float sb0 = c00 * b0 + c01 * b1 + c02 * b2, sb1 = c01 * b0 + c11 * b1 + c12 * b2,
+                        sb2 = c02 * b0 + c12 * b1 + c22 * b2;
+            const float A = a0 * sa0 + a1 * sa1 + a2 * sa2 + kDilation;
+            const float B = a0 * sb0 + a1 * sb1 + a2 * sb2;
+            const float C = b0 * sb0 + b1 * sb1 + b2 * sb2 + kDilation;
+            const float det = A * C - B * B;
+            if (det > 0.f && det < INFINITY) {
+                const float sigma = Store<DT>::ldc(sc.opacity, i);
+                if (255.f * sigma >= 1.f) {
+                    const float level = 2.f * logf(255.f * sigma) + kQSlack;
+                    const float ex = sqrtf(level * A), ey = sqrtf(level * C);
+                    const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
+                    const float fx0 = fmaxf(ceilf(u - ex - 0.5f), 0.f), fx1 = fminf(floorf(u + ex - 0.5f), (float)(cam.W - 1));
+                    const float fy0 = fmaxf(ceilf(v - ey - 0.5f), 0.f), fy1 = fminf(floorf(v + ey - 0.5f), (float)(cam.H - 1));
+                    if (fx0 <= fx1 && fy0 <= fy1) {
+                        const uint32_t tx0 = (uint32_t)fx0 / cam.tw, tx1 = (uint32_t)fx1 / cam.tw;
+                        const uint32_t ty0 = (uint32_t)fy0 / cam.th, ty1 = (uint32_t)fy1 / cam.th;
+                        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                        // colour (eq. 2) at the view direction of the centre
+                        float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+                        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                        dx *= inv; dy *= inv; dz *= inv;
+                        constexpr int NC = (DEG + 1) * (DEG + 1);
+                        float Y[16];
+                        sh_basis<DEG>(dx, dy, dz, Y);
+                        float f[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            float acc = 0.f;
+#pragma unroll
+                            for (int k = 0; k < NC; ++k) acc += Store<DT>::ld(sc.sh, (int64_t)(k * 3 + c) * S + i) * Y[k];
+                            f[c] = acc + 0.5f;
+                        }
+                        float pre[3] = {f[0], f[1], f[2]};
+                        uint32_t flags = 0;
+                        if (rc.mask && rc.mask[i]) {
+                            flags |= 8u;
+#pragma unroll
+                            for (int r = 0; r < 3; ++r)
+                                pre[r] = rc.M[r * 3] * f[0] + rc.M[r * 3 + 1] * f[1] + rc.M[r * 3 + 2] * f[2] + rc.b[r];
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) flags |= (pre[c] > 0.f ? 1u : 0u) << c;
+                        // conic = inverse 2D covariance, folded into a base-2 exponent
+                        const float idet = 1.0f / det;
+                        const float ca = C * idet, cb = -B * idet, cc = A * idet;
+                        SplatRec s;
+                        s.r0 = make_float4(u, v, ex, ey);
+                        s.r1 = make_float4(-0.5f * kLog2e * ca, -kLog2e * cb, -0.5f * kLog2e * cc, log2f(sigma));
+                        s.r2 = make_float4(fmaxf(pre[0], 0.f), fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f), sigma);
+                        rec[i] = s;
+                        if (keep_bwd) bwd[i] = make_float4(f[0], f[1], f[2], __uint_as_float(flags));
+                    }
+                }
+            }
+        }
+        count[i] = cnt;
+        rect[i] = rr;
+        zbits[i] = zb;
+    }
+    // depth range of Gaussians with keys (header zeroed; min kept as complement)
+    const bool has = cnt > 0;
+    const uint32_t zmn = wave_min(has ? zb : 0xffffffffu), zmx = wave_max(has ? zb : 0u);
+    if (lane_id() == 0 && wave_ballot(has)) {
+        atomicMax(&header[H_ZMIN], ~zmn);
+        atomicMax(&header[H_ZMAX], zmx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the tile counts, single pass with decoupled look-back
+// (workgroups take chunk ids from an atomic ticket so every predecessor a
+// workgroup waits for is already running). The last chunk stores the total K.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, uint32_t *__restrict__ off, int64_t n,
+                                              uint64_t *__restrict__ status, uint32_t *__restrict__ header,
+                                              uint32_t nchunks) {
+    __shared__ uint32_t s_chunk;
+    __shared__ uint64_t s_w[4];
+    __shared__ uint64_t s_prefix;
+    if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_SCAN_TICKET], 1u);
+    __syncthreads();
+    const uint32_t chunk = s_chunk;
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint64_t tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? cnt[base + k] : 0u;
+        tsum += v[k];
+    }
+    const uint64_t inc = wave_incl_scan(tsum);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint64_t wpre = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t x = s_w[k];
+        if (k < (int)w) wpre += x;
+        total += x;
+    }
+    if (threadIdx.x == 0) {
+        uint64_t excl = 0;
+        if (chunk == 0) {
+            __hip_atomic_store(&status[0], kFlagInc | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[chunk], kFlagAgg | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = (int64_t)chunk - 1;
+            while (true) {
+                const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t f = s & kFlagMask;
+                if (f == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += s & ~kFlagMask;
+                if (f == kFlagInc) break;
+                --j;
+            }
+            __hip_atomic_store(&status[chunk], kFlagInc | (excl + total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_prefix = excl;
+        if (chunk == nchunks - 1) {
+            const uint64_t K = excl + total;
+            header[H_K_LO] = (uint32_t)K;
+            header[H_K_HI] = (uint32_t)(K >> 32);
+        }
+    }
+    __syncthreads();
+    uint64_t run = s_prefix + wpre + inc - tsum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) off[base + k] = (uint32_t)run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Key emission, wave-cooperative: a wave owns 64 consecutive Gaussians, whose keys
+// occupy one contiguous range (the scan is exclusive). Lane j writes keys j, j+64, ...
+// of that range, finding the owning Gaussian by binary search over the wave's
+// prefix sums, so stores are coalesced however uneven the tile counts are.
+// key = (tile << 32) | float32 depth bits, value = Gaussian index; within a
+// Gaussian tiles go in row-major order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ off,
+                                              const uint2 *__restrict__ rect, const uint32_t *__restrict__ zbits,
+                                              int64_t n, int tiles_x, uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals) {
+    __shared__ uint32_t s_ex[4][64];
+    __shared__ uint2 s_rect[4][64];
+    __shared__ uint32_t s_zb[4][64];
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64;
+    const int64_t g = g0 + lane;
+    uint32_t c = 0, o = 0, zb = 0;
+    uint2 r = make_uint2(0u, 0u);
+    if (g < n) {
+        c = cnt[g];
+        o = off[g];
+        if (c) { r = rect[g]; zb = zbits[g]; }
+    }
+    const uint32_t inc = wave_incl_scan(c);
+    const uint32_t total = __shfl(inc, 63, 64);
+    const uint32_t base = __shfl(o, 0, 64);
+    s_ex[w][lane] = inc - c;
+    s_rect[w][lane] = r;
+    s_zb[w][lane] = zb;
+    __syncthreads();
+    for (uint32_t j = lane; j < total; j += 64) {
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_ex[w][mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t k = j - s_ex[w][lo];
+        const uint2 rr = s_rect[w][lo];
+        const uint32_t tx0 = rr.x & 0xffffu, tx1 = rr.x >> 16, ty0 = rr.y & 0xffffu;
+        const uint32_t wd = tx1 - tx0 + 1;
+        const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
+        keys[base + j] = ((uint64_t)(ty * (uint32_t)tiles_x + tx) << 32) | s_zb[w][lo];
+        vals[base + j] = (uint32_t)(g0 + lo);
+    }
+}
+
+// [first, last+1) of each tile in the sorted keys (ranges zeroed beforehand).
+__global__ __launch_bounds__(256) void k_ranges(const uint64_t *__restrict__ keys, uint32_t K, uint2 *__restrict__ ranges) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t t = (uint32_t)(keys[k] >> 32);
+    if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[t].x = k;
+    if (k == K - 1 || (uint32_t)(keys[k + 1] >> 32) != t) ranges[t].y = k + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Blend (eq. 3), one workgroup per tile, PPT vertically stacked pixels per thread.
+// Workgroup threads form waves that each cover a compact 8 x (8 PPT) pixel block
+// where the tile allows it; a wave skips a splat whose alpha >= 1/255 box misses all
+// of its pixel centres (exact: outside the box alpha < 1/255 holds with margin).
+// Splat records are staged through LDS in batches; a pixel stops when blending the
+// next splat would drop transmittance below 1e-4; the workgroup stops when all of
+// its pixels have. Output HWC image, final transmittance and, per pixel, the count
+// of tile-list entries up to and including the last blended one.
+// ---------------------------------------------------------------------------
+template <int TW, int TH, int PPT>
+__device__ __forceinline__ void thread_pixel(int t, int &lx, int &lrow) {
+    if constexpr (TW % 8 == 0 && (TH / PPT) % 8 == 0) {
+        const int w = t >> 6, l = t & 63;
+        constexpr int WC = TW / 8;
+        lx = (w % WC) * 8 + (l & 7);
+        lrow = (w / WC) * 8 + (l >> 3);
+    } else {
+        lx = t % TW;
+        lrow = t / TW;
+    }
+}
+
+template <int TW, int TH, int PPT>
+__global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+                                                       const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
+                                                       float bg0, float bg1, float bg2, float *__restrict__ image,
+                                                       float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
+#pragma clang fp contract(off)
+    constexpr int NT = TW * TH / PPT;
+    constexpr int BATCH = 256;
+    __shared__ float4 s_r0[BATCH], s_r1[BATCH], s_r2[BATCH];
+    const int tile = blockIdx.x;
+    const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+    const int t = threadIdx.x;
+    int lx, lrow;
+    thread_pixel<TW, TH, PPT>(t, lx, lrow);
+    const int px = tx0 + lx;
+    const float pxc = (float)px + 0.5f;
+    float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    uint32_t last[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = ty0 + lrow * PPT + j;
+        pyc[j] = (float)py + 0.5f;
+        T[j] = 1.f; C0[j] = C1[j] = C2[j] = 0.f; last[j] = 0;
+        done[j] = !(px < W && py < H);
+    }
+    // pixel-centre bounds of this wave (of the whole tile when waves are not blocks)
+    float wx0, wx1, wy0, wy1;
+    if constexpr (TW % 8 == 0 && (TH / PPT) % 8 == 0) {
+        const int w = t >> 6;
+        constexpr int WC = TW / 8;
+        wx0 = (float)(tx0 + (w % WC) * 8) + 0.5f;
+        wx1 = wx0 + 7.f;
+        wy0 = (float)(ty0 + (w / WC) * 8 * PPT) + 0.5f;
+        wy1 = wy0 + (float)(8 * PPT - 1);
+    } else {
+        wx0 = (float)tx0 + 0.5f;
+        wx1 = wx0 + (float)(TW - 1);
+        wy0 = (float)ty0 + 0.5f;
+        wy1 = wy0 + (float)(TH - 1);
+    }
+
+    const uint2 rg = ranges[tile];
+    for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
+        bool mine = true;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) mine = mine && done[j];
+        if (__syncthreads_and(mine)) break;
+        for (int q = t; q < BATCH; q += NT) {
+            const uint32_t k = start + q;
+            if (k < rg.y) {
+                const SplatRec s = rec[vals[k]];
+                s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
+            }
+        }
+        __syncthreads();
+        const int nb = (int)min((uint32_t)BATCH, rg.y - start);
+        for (int q = 0; q < nb; ++q) {
+            bool alive = false;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) alive = alive || !done[j];
+            if (!wave_ballot(alive)) break;
+            const float4 r0 = s_r0[q];
+            if (r0.x + r0.z < wx0 || r0.x - r0.z > wx1 || r0.y + r0.w < wy0 || r0.y - r0.w > wy1) continue;
+            const float4 r1 = s_r1[q], r2 = s_r2[q];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                if (done[j]) continue;
+                const float dx = pxc - r0.x, dy = pyc[j] - r0.y;
+                const float e = __builtin_fmaf(dx, __builtin_fmaf(r1.x, dx, r1.y * dy), __builtin_fmaf(r1.z * dy, dy, r1.w));
+                if (e < kLog2AlphaMin) continue;
+                const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+                const float Tn = T[j] * (1.f - a);
+                if (Tn < kTMin) { done[j] = true; continue; }
+                const float wgt = a * T[j];
+                C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
+                C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
+                C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
+                T[j] = Tn;
+                last[j] = start + q + 1 - rg.x;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = ty0 + lrow * PPT + j;
+        if (px < W && py < H) {
+            const int64_t p = (int64_t)py * W + px;
+            image[p * 3 + 0] = __builtin_fmaf(T[j], bg0, C0[j]);
+            image[p * 3 + 1] = __builtin_fmaf(T[j], bg1, C1[j]);
+            image[p * 3 + 2] = __builtin_fmaf(T[j], bg2, C2[j]);
+            finalT[p] = T[j];
+            nproc[p] = last[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
+}
+
+template <int DT>
+static void preprocess_dt(int deg, dim3 g, hipStream_t st, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc,
+                          int keep, SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, uint32_t *hdr) {
+    switch (deg) {
+    case 0: hipLaunchKernelGGL((k_preprocess<DT, 0>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
+    case 1: hipLaunchKernelGGL((k_preprocess<DT, 1>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
+    case 2: hipLaunchKernelGGL((k_preprocess<DT, 2>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
+    default: hipLaunchKernelGGL((k_preprocess<DT, 3>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
+    }
+}
+
+void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc, int keep,
+                       SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, uint32_t *hdr,
+                       hipStream_t st) {
+    if (sc.n <= 0) return;
+    const dim3 g((unsigned)((sc.n + 255) / 256));
+    if (dt == RECOGS_F32) preprocess_dt<RECOGS_F32>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
+    else if (dt == RECOGS_F16) preprocess_dt<RECOGS_F16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
+    else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
+}
+
+void launch_scan(const uint32_t *cnt, uint32_t *off, int64_t n, uint64_t *status, uint32_t *hdr, hipStream_t st) {
+    if (n <= 0) return;
+    const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, off, n, status, hdr, nchunks);
+}
+
+void launch_emit(const uint32_t *cnt, const uint32_t *off, const uint2 *rect, const uint32_t *zb, int64_t n, int tiles_x,
+                 uint64_t *keys, uint32_t *vals, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cnt, off, rect, zb, n, tiles_x, keys, vals);
+}
+
+void launch_ranges(const uint64_t *keys, uint32_t K, uint2 *ranges, hipStream_t st) {
+    if (K == 0) return;
+    hipLaunchKernelGGL(k_ranges, dim3((K + 255) / 256), dim3(256), 0, st, keys, K, ranges);
+}
+
+template <int TW, int TH, int PPT>
+static void blend_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec, int W,
+                      int H, int tiles_x, const float *bg, float *image, float *finalT, uint32_t *nproc) {
+    hipLaunchKernelGGL((k_blend<TW, TH, PPT>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W, H, tiles_x,
+                       bg[0], bg[1], bg[2], image, finalT, nproc);
+}
+
+bool launch_blend(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
+                  int W, int H, int tiles_x, const float *bg, float *image, float *finalT, uint32_t *nproc,
+                  hipStream_t st) {
+#define RECOGS_BLEND_CASE(A, B, P)                                                                         \
+    if (tw == A && th == B && ppt == P) {                                                                  \
+        blend_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, bg, image, finalT, nproc);        \
+        return true;                                                                                       \
+    }
+    RECOGS_BLEND_CASE(16, 16, 1) RECOGS_BLEND_CASE(16, 16, 2) RECOGS_BLEND_CASE(16, 16, 4)
+    RECOGS_BLEND_CASE(8, 8, 1) RECOGS_BLEND_CASE(8, 8, 2) RECOGS_BLEND_CASE(8, 8, 4)
+    RECOGS_BLEND_CASE(32, 8, 1) RECOGS_BLEND_CASE(32, 8, 2) RECOGS_BLEND_CASE(32, 8, 4)
+#undef RECOGS_BLEND_CASE
+    return false;
+}
+
+}  // namespace recogs

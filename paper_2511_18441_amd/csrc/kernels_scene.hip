@@ -1,0 +1,118 @@
+// Per-Gaussian streaming kernels: covariance (eq. 1), selection, recolour (eq. 6).
+// One thread per Gaussian, planar (SoA) loads: consecutive lanes read consecutive
+// elements of each plane.
+#include "recogs_internal.hpp"
+
+namespace recogs {
+
+// eq. (1): Sigma = R S S^T R^T, S = diag(exp(log_scale)), R from the normalised
+// quaternion (w, x, y, z).
+__global__ __launch_bounds__(256) void k_covariance(const float *__restrict__ ls, const float *__restrict__ q,
+                                                    float *__restrict__ cov, int64_t n, int64_t stride) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float w = q[i], x = q[stride + i], y = q[2 * stride + i], z = q[3 * stride + i];
+    const float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    const float R00 = 1.f - 2.f * (y * y + z * z), R01 = 2.f * (x * y - w * z), R02 = 2.f * (x * z + w * y);
+    const float R10 = 2.f * (x * y + w * z), R11 = 1.f - 2.f * (x * x + z * z), R12 = 2.f * (y * z - w * x);
+    const float R20 = 2.f * (x * z - w * y), R21 = 2.f * (y * z + w * x), R22 = 1.f - 2.f * (x * x + y * y);
+    const float s0 = expf(ls[i]), s1 = expf(ls[stride + i]), s2 = expf(ls[2 * stride + i]);
+    const float M00 = R00 * s0, M01 = R01 * s1, M02 = R02 * s2;
+    const float M10 = R10 * s0, M11 = R11 * s1, M12 = R12 * s2;
+    const float M20 = R20 * s0, M21 = R21 * s1, M22 = R22 * s2;
+    cov[i] = M00 * M00 + M01 * M01 + M02 * M02;
+    cov[stride + i] = M00 * M10 + M01 * M11 + M02 * M12;
+    cov[2 * stride + i] = M00 * M20 + M01 * M21 + M02 * M22;
+    cov[3 * stride + i] = M10 * M10 + M11 * M11 + M12 * M12;
+    cov[4 * stride + i] = M10 * M20 + M11 * M21 + M12 * M22;
+    cov[5 * stride + i] = M20 * M20 + M21 * M21 + M22 * M22;
+}
+
+// Selection: depth > znear, projected centre in the closed disk, DC colour in the
+// closed ball. Count by wave ballot + one atomic per wave.
+template <int DT>
+__global__ __launch_bounds__(256) void k_select(SceneDev sc, CamDev cam, float scx, float scy, float r2,
+                                                float ref0, float ref1, float ref2, float rho2,
+                                                uint8_t *__restrict__ mask, int32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool sel = false;
+    if (i < sc.n) {
+        const float mx = sc.means[i], my = sc.means[sc.stride + i], mz = sc.means[2 * sc.stride + i];
+        const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
+        if (z > cam.znear) {
+            const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
+            const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
+            const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
+            const float du = u - scx, dv = v - scy;
+            const float d2 = du * du + dv * dv;
+            const float c0 = kSH0 * Store<DT>::ldc(sc.sh, i) + 0.5f - ref0;
+            const float c1 = kSH0 * Store<DT>::ldc(sc.sh, sc.stride + i) + 0.5f - ref1;
+            const float c2 = kSH0 * Store<DT>::ldc(sc.sh, 2 * sc.stride + i) + 0.5f - ref2;
+            sel = (d2 <= r2) && (c0 * c0 + c1 * c1 + c2 * c2 <= rho2);
+        }
+        mask[i] = sel ? 1 : 0;
+    }
+    const uint64_t b = wave_ballot(sel);
+    if (lane_id() == 0 && b) atomicAdd(count, (int32_t)__popcll(b));
+}
+
+// Recolour on coefficients: C'_k = M C_k (k >= 1), C'_0 = M C_0 + ((M - I) 1/2 + b)/Y00.
+template <int DT>
+__global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *__restrict__ dst,
+                                                 const uint8_t *__restrict__ mask, const float *__restrict__ Mp,
+                                                 const float *__restrict__ bp, int copy_unselected) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    const bool sel = mask[i] != 0;
+    if (!sel) {
+        if (copy_unselected && dst != sc.sh)
+            for (int p = 0; p < ncoef * 3; ++p) Store<DT>::st(dst, p * sc.stride + i, Store<DT>::ldc(sc.sh, p * sc.stride + i));
+        return;
+    }
+    float M[9], off[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) M[k] = Mp[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bp[r]) / kSH0;
+    for (int k = 0; k < ncoef; ++k) {
+        const int64_t b0 = (int64_t)(k * 3) * sc.stride + i;
+        const float c0 = Store<DT>::ldc(sc.sh, b0), c1 = Store<DT>::ldc(sc.sh, b0 + sc.stride),
+                    c2 = Store<DT>::ldc(sc.sh, b0 + 2 * sc.stride);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
+            if (k == 0) v += off[r];
+            Store<DT>::st(dst, b0 + r * sc.stride, v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_covariance(const float *ls, const float *q, float *cov, int64_t n, int64_t stride, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_covariance, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ls, q, cov, n, stride);
+}
+
+void launch_select(int dt, const SceneDev &sc, const CamDev &cam, const recogs_select_params &p, uint8_t *mask,
+                   int32_t *count, hipStream_t st) {
+    if (sc.n <= 0) return;
+    const dim3 g((unsigned)((sc.n + 255) / 256)), b(256);
+    const float r2 = p.radius * p.radius, rho2 = p.color_radius * p.color_radius;
+    if (dt == RECOGS_F32) hipLaunchKernelGGL(k_select<RECOGS_F32>, g, b, 0, st, sc, cam, p.cx, p.cy, r2, p.ref[0], p.ref[1], p.ref[2], rho2, mask, count);
+    else if (dt == RECOGS_F16) hipLaunchKernelGGL(k_select<RECOGS_F16>, g, b, 0, st, sc, cam, p.cx, p.cy, r2, p.ref[0], p.ref[1], p.ref[2], rho2, mask, count);
+    else hipLaunchKernelGGL(k_select<RECOGS_BF16>, g, b, 0, st, sc, cam, p.cx, p.cy, r2, p.ref[0], p.ref[1], p.ref[2], rho2, mask, count);
+}
+
+void launch_recolor(int dt, const SceneDev &sc, int ncoef, void *dst, const uint8_t *mask, const float *M,
+                    const float *b, int copy_unselected, hipStream_t st) {
+    if (sc.n <= 0) return;
+    const dim3 g((unsigned)((sc.n + 255) / 256)), bl(256);
+    if (dt == RECOGS_F32) hipLaunchKernelGGL(k_recolor<RECOGS_F32>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);
+    else if (dt == RECOGS_F16) hipLaunchKernelGGL(k_recolor<RECOGS_F16>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);
+    else hipLaunchKernelGGL(k_recolor<RECOGS_BF16>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);
+}
+
+}  // namespace recogs

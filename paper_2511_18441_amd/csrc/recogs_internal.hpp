@@ -1,0 +1,183 @@
+// Internal declarations of the HIP library behind include/recogs.h (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/recogs.h"
+
+namespace recogs {
+
+// ---------------------------------------------------------------------------
+// Constants of the rasteriser the paper builds on (Sec. 4: the original Gaussian
+// splatting rasteriser). The paper states none of them; these are that
+// rasteriser's published conventions.
+// ---------------------------------------------------------------------------
+constexpr float kAlphaMax = 0.99f;               // alpha clamp
+constexpr float kTMin = 1e-4f;                   // stop before transmittance drops below
+constexpr float kDilation = 0.3f;                // px^2 added to the 2D covariance diagonal
+constexpr float kFrustumClamp = 1.3f;            // Jacobian evaluated inside 1.3x the frustum
+constexpr float kQSlack = 1.0f / 64.0f;          // extent level = 2 ln(255 sigma) + 1/64
+constexpr float kLog2AlphaMin = -7.9943534368588578f;  // log2(1/255)
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Real SH with the Condon-Shortley phase (eq. 2), values of the closed forms
+// c/(k sqrt(pi)) used by the basis below.
+constexpr float kSH0 = 0.28209479177387814f;     // 1/(2 sqrt pi)
+constexpr float kSH1 = 0.48860251190291992f;     // sqrt3/(2 sqrt pi)
+constexpr float kSH2a = 1.0925484305920792f;     // sqrt15/(2 sqrt pi)
+constexpr float kSH2b = 0.31539156525252005f;    // sqrt5/(4 sqrt pi)
+constexpr float kSH2c = 0.54627421529603959f;    // sqrt15/(4 sqrt pi)
+constexpr float kSH3a = 0.59004358992664352f;    // sqrt(35/2)/(4 sqrt pi)
+constexpr float kSH3b = 2.8906114426405538f;     // sqrt105/(2 sqrt pi)
+constexpr float kSH3c = 0.45704579946446572f;    // sqrt(21/2)/(4 sqrt pi)
+constexpr float kSH3d = 0.37317633259011546f;    // sqrt7/(4 sqrt pi)
+constexpr float kSH3e = 1.4453057213202769f;     // sqrt105/(4 sqrt pi)
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// storage dtype access
+// ---------------------------------------------------------------------------
+template <int DT> struct Store;
+template <> struct Store<RECOGS_F32> {
+    static __device__ __forceinline__ float ld(const void *p, int64_t i) { return __builtin_nontemporal_load((const float *)p + i); }
+    static __device__ __forceinline__ float ldc(const void *p, int64_t i) { return ((const float *)p)[i]; }
+    static __device__ __forceinline__ void st(void *p, int64_t i, float v) { ((float *)p)[i] = v; }
+    static constexpr int bytes = 4;
+};
+template <> struct Store<RECOGS_F16> {
+    static __device__ __forceinline__ float ld(const void *p, int64_t i) { return (float)((const _Float16 *)p)[i]; }
+    static __device__ __forceinline__ float ldc(const void *p, int64_t i) { return (float)((const _Float16 *)p)[i]; }
+    static __device__ __forceinline__ void st(void *p, int64_t i, float v) { ((_Float16 *)p)[i] = (_Float16)v; }
+    static constexpr int bytes = 2;
+};
+template <> struct Store<RECOGS_BF16> {
+    static __device__ __forceinline__ float ld(const void *p, int64_t i) {
+        return __uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
+    }
+    static __device__ __forceinline__ float ldc(const void *p, int64_t i) { return ld(p, i); }
+    static __device__ __forceinline__ void st(void *p, int64_t i, float v) {
+        uint32_t u = __float_as_uint(v);
+        uint16_t r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) r = 0x7fc0u;                      // NaN
+        else r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);           // nearest, ties to even
+        ((uint16_t *)p)[i] = r;
+    }
+    static constexpr int bytes = 2;
+};
+
+// ---------------------------------------------------------------------------
+// Compensated dot product (Ogita, Rump, Oishi 2005, "Dot2"): a0 b0 + a1 b1 + a2 b2 + c
+// as accurate as if computed in twice the working precision, then rounded. Used for
+// the camera-space position so the float32 depth that orders splats is (almost
+// always) the correctly rounded exact depth.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dot3c(float a0, float b0, float a1, float b1, float a2, float b2, float c) {
+#pragma clang fp contract(off)
+    float p0 = a0 * b0, e0 = __builtin_fmaf(a0, b0, -p0);
+    float p1 = a1 * b1, e1 = __builtin_fmaf(a1, b1, -p1);
+    float p2 = a2 * b2, e2 = __builtin_fmaf(a2, b2, -p2);
+    float s = p0 + p1, bb = s - p0, t1 = (p0 - (s - bb)) + (p1 - bb);
+    float s2 = s + p2;
+    bb = s2 - s;
+    float t2 = (s - (s2 - bb)) + (p2 - bb);
+    float s3 = s2 + c;
+    bb = s3 - s2;
+    float t3 = (s2 - (s3 - bb)) + (c - bb);
+    return s3 + (((e0 + e1) + e2) + ((t1 + t2) + t3));
+}
+
+// ---------------------------------------------------------------------------
+// wave64 primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+// number of set bits of m in lanes below this lane
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, 64); v = w < v ? w : v; }
+    return v;
+}
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, 64); v = w > v ? w : v; }
+    return v;
+}
+// inclusive prefix sum across the wave
+template <typename T> __device__ __forceinline__ T wave_incl_scan(T v) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T w = __shfl_up(v, o, 64);
+        if (l >= (uint32_t)o) v += w;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side views of the host structs
+// ---------------------------------------------------------------------------
+struct CamDev {
+    float R[9], t[3];
+    float fx, fy, cx, cy, znear;
+    float limx, limy;       // 1.3 * (W/2)/fx, 1.3 * (H/2)/fy
+    float campos[3];
+    int32_t W, H, tw, th, tiles_x, tiles_y;
+};
+
+struct SceneDev {
+    int64_t n, stride;
+    const float *means;
+    const float *cov3d;
+    const void *opacity;
+    const void *sh;
+};
+
+struct RecolorDev {
+    const uint8_t *mask;   // null = no fused recolour
+    const float *M;
+    const float *b;
+};
+
+// Workspace header words (u32), zeroed before each render.
+enum : int {
+    H_K_LO = 0, H_K_HI = 1,      // number of keys (64-bit)
+    H_ZMIN = 2, H_ZMAX = 3,      // min/max float32 depth bits among splats with keys
+    H_SCAN_TICKET = 4,
+    H_SORT_TICKET = 8,           // 8 words, one per pass
+    H_WORDS = 64
+};
+
+// status words of decoupled look-back (scan): flag in the top 2 bits
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kFlagMask = 3ull << 62;
+// status words of the radix passes (u32): flag in the top 2 bits, count below
+constexpr uint32_t kRFlagAgg = 1u << 30, kRFlagInc = 2u << 30, kRFlagMask = 3u << 30;
+
+constexpr int kScanItems = 16;                       // counts per thread of the scan
+constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
+constexpr int kSortItems = 16;                       // keys per thread per radix pass
+constexpr int kSortChunk = 256 * kSortItems;         // keys per radix workgroup
+constexpr int kMaxPasses = 8;
+
+// Per-Gaussian splat record for compositing: three float4
+//   r0 = (u, v, ex, ey)   centre (pixels) and half-extents of the alpha >= 1/255 box
+//   r1 = (A, B, C, o)     log2(alpha) = o + A dx^2 + B dx dy + C dy^2
+//   r2 = (r, g, b, sigma) clamped colour, activated opacity
+struct SplatRec { float4 r0, r1, r2; };
+
+// key layout: (tile << 32) | float32 depth bits
+__device__ __forceinline__ uint64_t sort_view(uint64_t key, uint32_t zmin, int dbits) {
+    return ((key >> 32) << dbits) | (uint64_t)((uint32_t)key - zmin);
+}
+
+}  // namespace recogs

@@ -1,0 +1,420 @@
+// Host side of the C ABI declared in include/recogs.h: argument validation,
+// workspace carving and the launch sequence of each call.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "recogs_internal.hpp"
+
+namespace recogs {
+// launchers (kernels_*.hip)
+void launch_covariance(const float *, const float *, float *, int64_t, int64_t, hipStream_t);
+void launch_select(int, const SceneDev &, const CamDev &, const recogs_select_params &, uint8_t *, int32_t *, hipStream_t);
+void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const float *, const float *, int, hipStream_t);
+void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
+void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
+                       uint32_t *, uint2 *, uint32_t *, uint32_t *, hipStream_t);
+void launch_scan(const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, hipStream_t);
+void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
+                 hipStream_t);
+void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
+bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
+                  float *, float *, uint32_t *, hipStream_t);
+void launch_radix_hist(const uint64_t *, uint32_t, uint32_t, int, int, uint32_t *, hipStream_t);
+void launch_radix_pass(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int,
+                       const uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
+                      const float *, const uint32_t *, float4 *, hipStream_t);
+void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
+                        hipStream_t);
+void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
+}  // namespace recogs
+
+using namespace recogs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+recogs_status fail(recogs_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+recogs_status hip_check(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RECOGS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return RECOGS_OK;
+}
+
+#define RECOGS_TRY_HIP(call)                                                                          \
+    do {                                                                                              \
+        const hipError_t _e = (call);                                                                 \
+        if (_e != hipSuccess) return fail(RECOGS_ERR_HIP, "%s: %s", #call, hipGetErrorString(_e));     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool tile_supported(int tw, int th) {
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
+}
+
+// Computes every offset of the workspace; returns total bytes.
+size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw, int32_t th, int64_t cap) {
+    const int64_t tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+    const int64_t T = tiles_x * tiles_y;
+    const int64_t P = (int64_t)W * H;
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t scan_chunks = (nn + kScanChunk - 1) / kScanChunk;
+    const int64_t sort_chunks = (cap + kSortChunk - 1) / kSortChunk;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    ws->off_rec = take(sizeof(SplatRec) * nn);
+    ws->off_bwd = take(sizeof(float4) * nn);
+    ws->off_grad = take(sizeof(float4) * nn);
+    ws->off_zbits = take(4 * nn);
+    ws->off_rect = take(8 * nn);
+    ws->off_count = take(4 * nn);
+    ws->off_offset = take(4 * nn);
+    ws->off_keys0 = take(8 * (size_t)(cap > 0 ? cap : 1));
+    ws->off_keys1 = take(8 * (size_t)(cap > 0 ? cap : 1));
+    ws->off_vals0 = take(4 * (size_t)(cap > 0 ? cap : 1));
+    ws->off_vals1 = take(4 * (size_t)(cap > 0 ? cap : 1));
+    ws->off_final_T = take(4 * (size_t)P);
+    ws->off_nproc = take(4 * (size_t)P);
+    // zero-filled region: header, scan status, sort histogram, sort status, tile ranges
+    ws->off_header = take(4 * H_WORDS);
+    ws->off_scan = take(8 * (size_t)scan_chunks);
+    ws->off_hist = take(4 * 256 * kMaxPasses);
+    ws->off_sort_status = take(4 * 256 * (size_t)kMaxPasses * (size_t)(sort_chunks > 0 ? sort_chunks : 1));
+    ws->off_ranges = take(8 * (size_t)T);
+    ws->scan_chunks = (size_t)scan_chunks;
+    ws->sort_chunks = (size_t)sort_chunks;
+    ws->tiles_x = (int32_t)tiles_x;
+    ws->tiles_y = (int32_t)tiles_y;
+    return o;
+}
+
+template <typename T> T *at(const recogs_workspace *ws, size_t off) { return (T *)((char *)ws->base + off); }
+
+// HIP events bracketing the stages of a profiled render (created once per thread)
+struct StageTimer {
+    hipEvent_t ev[9] = {};
+    bool on = false, ready = false;
+    hipStream_t st = nullptr;
+    recogs_status start(bool enable, hipStream_t s) {
+        on = enable;
+        st = s;
+        if (!on) return RECOGS_OK;
+        if (!ready) {
+            for (auto &e : ev)
+                if (hipEventCreate(&e) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventCreate failed");
+            ready = true;
+        }
+        return mark(0);
+    }
+    recogs_status mark(int k) {
+        if (on && hipEventRecord(ev[k], st) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventRecord failed");
+        return RECOGS_OK;
+    }
+    recogs_status finish(recogs_workspace *ws, int last) {
+        if (!on) return RECOGS_OK;
+        if (hipEventSynchronize(ev[last]) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventSynchronize failed");
+        for (int k = 0; k < 8; ++k) {
+            float ms = 0.f;
+            if (k < last) hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            ws->stage_ms[k] = ms;
+        }
+        return RECOGS_OK;
+    }
+};
+thread_local StageTimer g_timer;
+
+recogs_status check_scene(const recogs_scene *sc) {
+    if (!sc) return fail(RECOGS_ERR_INVALID, "scene is NULL");
+    if (sc->n < 0) return fail(RECOGS_ERR_INVALID, "scene n = %lld < 0", (long long)sc->n);
+    if (sc->n > 0x7fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "scene n = %lld exceeds 2^31-1", (long long)sc->n);
+    if (sc->stride < sc->n) return fail(RECOGS_ERR_INVALID, "scene stride %lld < n %lld", (long long)sc->stride, (long long)sc->n);
+    if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(RECOGS_ERR_INVALID, "sh_degree %d not in 0..3", sc->sh_degree);
+    if (sc->storage < RECOGS_F32 || sc->storage > RECOGS_BF16) return fail(RECOGS_ERR_INVALID, "storage dtype %d unknown", sc->storage);
+    if (sc->n > 0 && (!sc->means || !sc->opacity || !sc->sh))
+        return fail(RECOGS_ERR_INVALID, "scene means/opacity/sh pointer is NULL");
+    return RECOGS_OK;
+}
+
+recogs_status check_camera(const recogs_camera *c) {
+    if (!c) return fail(RECOGS_ERR_INVALID, "camera is NULL");
+    if (c->width <= 0 || c->height <= 0 || c->width > 32768 || c->height > 32768)
+        return fail(RECOGS_ERR_INVALID, "image size %dx%d out of range 1..32768", c->width, c->height);
+    if (!(c->fx > 0.f) || !(c->fy > 0.f) || !std::isfinite(c->fx) || !std::isfinite(c->fy))
+        return fail(RECOGS_ERR_INVALID, "focal lengths must be finite and > 0");
+    if (!std::isfinite(c->cx) || !std::isfinite(c->cy) || !std::isfinite(c->znear))
+        return fail(RECOGS_ERR_INVALID, "principal point / znear not finite");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(c->R[k])) return fail(RECOGS_ERR_INVALID, "camera R not finite");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->t[k])) return fail(RECOGS_ERR_INVALID, "camera t not finite");
+    return RECOGS_OK;
+}
+
+CamDev make_cam(const recogs_camera &c, int tw, int th) {
+    CamDev d;
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy; d.znear = c.znear;
+    d.limx = kFrustumClamp * (0.5f * (float)c.width) / c.fx;
+    d.limy = kFrustumClamp * (0.5f * (float)c.height) / c.fy;
+    // camera centre -R^T t, in double then rounded
+    for (int k = 0; k < 3; ++k)
+        d.campos[k] = (float)(-((double)c.R[0 * 3 + k] * c.t[0] + (double)c.R[1 * 3 + k] * c.t[1] + (double)c.R[2 * 3 + k] * c.t[2]));
+    d.W = c.width; d.H = c.height; d.tw = tw; d.th = th;
+    d.tiles_x = (c.width + tw - 1) / tw;
+    d.tiles_y = (c.height + th - 1) / th;
+    return d;
+}
+
+SceneDev make_scene(const recogs_scene &s) {
+    SceneDev d;
+    d.n = s.n; d.stride = s.stride; d.means = s.means; d.cov3d = s.cov3d; d.opacity = s.opacity; d.sh = s.sh;
+    return d;
+}
+
+int bits_for(uint64_t v) {  // bits needed to represent values 0..v
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+recogs_status check_opts(const recogs_render_opts *o) {
+    if (!o) return fail(RECOGS_ERR_INVALID, "render opts is NULL");
+    if (!tile_supported(o->tile_w, o->tile_h))
+        return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8", o->tile_w, o->tile_h);
+    if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
+        return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
+    const bool any = o->mask || o->M || o->b;
+    if (any && !(o->mask && o->M && o->b)) return fail(RECOGS_ERR_INVALID, "fused recolour needs mask, M and b together");
+    return RECOGS_OK;
+}
+
+recogs_status check_ws(const recogs_workspace *ws, const recogs_scene *sc, const recogs_camera *cam,
+                       const recogs_render_opts *o) {
+    if (!ws || !ws->base) return fail(RECOGS_ERR_INVALID, "workspace is NULL or not initialised");
+    if (sc->n > ws->n_cap) return fail(RECOGS_ERR_INVALID, "scene n %lld > workspace capacity %lld", (long long)sc->n, (long long)ws->n_cap);
+    if (cam->width != ws->width || cam->height != ws->height)
+        return fail(RECOGS_ERR_INVALID, "camera %dx%d != workspace %dx%d", cam->width, cam->height, ws->width, ws->height);
+    if (o->tile_w != ws->tile_w || o->tile_h != ws->tile_h)
+        return fail(RECOGS_ERR_INVALID, "tile %dx%d != workspace tile %dx%d", o->tile_w, o->tile_h, ws->tile_w, ws->tile_h);
+    return RECOGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *recogs_last_error(void) { return g_err; }
+
+size_t recogs_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t tile_w, int32_t tile_h, int64_t key_capacity) {
+    if (n < 0 || width <= 0 || height <= 0 || !tile_supported(tile_w, tile_h) || key_capacity < 0) return 0;
+    recogs_workspace ws;
+    memset(&ws, 0, sizeof(ws));
+    return layout(&ws, n, width, height, tile_w, tile_h, key_capacity);
+}
+
+recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t bytes, int64_t n, int32_t width,
+                                    int32_t height, int32_t tile_w, int32_t tile_h, int64_t key_capacity) {
+    g_err[0] = 0;
+    if (!ws || !dev_mem) return fail(RECOGS_ERR_INVALID, "workspace struct or memory is NULL");
+    if ((uintptr_t)dev_mem % kAlign) return fail(RECOGS_ERR_INVALID, "workspace memory not 256-byte aligned");
+    if (n < 0 || width <= 0 || height <= 0 || key_capacity < 0)
+        return fail(RECOGS_ERR_INVALID, "bad workspace sizes");
+    if (key_capacity > 0x3fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "key capacity above 2^30-1");
+    if (!tile_supported(tile_w, tile_h)) return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d unsupported", tile_w, tile_h);
+    memset(ws, 0, sizeof(*ws));
+    const size_t need = layout(ws, n, width, height, tile_w, tile_h, key_capacity);
+    if (bytes < need) return fail(RECOGS_ERR_INVALID, "workspace has %zu bytes, needs %zu", bytes, need);
+    ws->base = dev_mem;
+    ws->bytes = bytes;
+    ws->n_cap = n;
+    ws->width = width; ws->height = height; ws->tile_w = tile_w; ws->tile_h = tile_h;
+    ws->key_capacity = key_capacity;
+    return RECOGS_OK;
+}
+
+recogs_status recogs_prepare_covariance(const float *log_scales, const float *quats, float *cov3d, int64_t n,
+                                        int64_t stride, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n < 0 || stride < n) return fail(RECOGS_ERR_INVALID, "n / stride invalid");
+    if (n > 0 && (!log_scales || !quats || !cov3d)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    launch_covariance(log_scales, quats, cov3d, n, stride, stream);
+    return hip_check("covariance");
+}
+
+recogs_status recogs_select(const recogs_scene *scene, const recogs_camera *cam, const recogs_select_params *params,
+                            uint8_t *mask, int32_t *count, hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_scene(scene)) != RECOGS_OK) return s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if (!params || !count || (scene->n > 0 && !mask)) return fail(RECOGS_ERR_INVALID, "params / mask / count is NULL");
+    launch_fill_u32((uint32_t *)count, 0u, 1, stream);
+    launch_select(scene->storage, make_scene(*scene), make_cam(*cam, 16, 16), *params, mask, count, stream);
+    return hip_check("select");
+}
+
+recogs_status recogs_recolor(const recogs_scene *scene, void *dst_sh, const uint8_t *mask, const float *M, const float *b,
+                             int32_t copy_unselected, hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_scene(scene)) != RECOGS_OK) return s;
+    if (scene->n > 0 && (!dst_sh || !mask || !M || !b)) return fail(RECOGS_ERR_INVALID, "dst_sh / mask / M / b is NULL");
+    const int ncoef = (scene->sh_degree + 1) * (scene->sh_degree + 1);
+    launch_recolor(scene->storage, make_scene(*scene), ncoef, dst_sh, mask, M, b, copy_unselected, stream);
+    return hip_check("recolor");
+}
+
+recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
+                            recogs_workspace *ws, float *image, hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_scene(scene)) != RECOGS_OK) return s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if ((s = check_opts(opts)) != RECOGS_OK) return s;
+    if ((s = check_ws(ws, scene, cam, opts)) != RECOGS_OK) return s;
+    if (!image) return fail(RECOGS_ERR_INVALID, "image is NULL");
+    if (scene->n > 0 && !scene->cov3d) return fail(RECOGS_ERR_INVALID, "scene cov3d is NULL");
+
+    const int64_t n = scene->n;
+    const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
+    const int ntiles = cd.tiles_x * cd.tiles_y;
+    uint32_t *hdr = at<uint32_t>(ws, ws->off_header);
+    SplatRec *rec = at<SplatRec>(ws, ws->off_rec);
+    float4 *bwd = at<float4>(ws, ws->off_bwd);
+    uint32_t *zb = at<uint32_t>(ws, ws->off_zbits);
+    uint2 *rect = at<uint2>(ws, ws->off_rect);
+    uint32_t *cnt = at<uint32_t>(ws, ws->off_count);
+    uint32_t *off = at<uint32_t>(ws, ws->off_offset);
+    uint2 *ranges = at<uint2>(ws, ws->off_ranges);
+
+    StageTimer &tm = g_timer;
+    for (int k = 0; k < 8; ++k) ws->stage_ms[k] = 0.f;
+    if ((s = tm.start(opts->profile_stages != 0, stream)) != RECOGS_OK) return s;
+    // zero header + scan status (contiguous)
+    launch_fill_u32(hdr, 0u, (int64_t)((ws->off_hist - ws->off_header) / 4), stream);
+    RecolorDev rc{opts->mask, opts->M, opts->b};
+    launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
+                      rect, cnt, hdr, stream);
+    if ((s = tm.mark(1)) != RECOGS_OK) return s;
+    launch_scan(cnt, off, n, at<uint64_t>(ws, ws->off_scan), hdr, stream);
+    if ((s = tm.mark(2)) != RECOGS_OK) return s;
+    if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
+
+    uint32_t h[4] = {0, 0, 0, 0};
+    RECOGS_TRY_HIP(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+    RECOGS_TRY_HIP(hipStreamSynchronize(stream));
+    if ((s = tm.mark(3)) != RECOGS_OK) return s;
+    const uint64_t K = n > 0 ? ((uint64_t)h[H_K_LO] | ((uint64_t)h[H_K_HI] << 32)) : 0;
+    ws->num_keys = (int64_t)K;
+    ws->last_n = (int32_t)n;
+    if ((int64_t)K > ws->key_capacity)
+        return fail(RECOGS_ERR_CAPACITY, "view needs %llu tile keys, workspace holds %lld", (unsigned long long)K,
+                    (long long)ws->key_capacity);
+    const uint32_t zmin = ~h[H_ZMIN], zmax = h[H_ZMAX];
+    const int dbits = K ? bits_for((uint64_t)(zmax - zmin)) : 0;
+    const int tbits = bits_for((uint64_t)(ntiles - 1));
+    const int key_bits = tbits + dbits;
+    const int passes = (key_bits + 7) / 8;
+    ws->depth_bits = dbits;
+    ws->depth_min_bits = zmin;
+    ws->key_bits = key_bits;
+    ws->sort_passes = passes;
+
+    const uint32_t chunks = (uint32_t)((K + kSortChunk - 1) / kSortChunk);
+    // zero histogram + sort status of the passes used + ranges
+    uint32_t *hist = at<uint32_t>(ws, ws->off_hist);
+    uint32_t *sstat = at<uint32_t>(ws, ws->off_sort_status);
+    launch_fill_u32(hist, 0u, 256 * kMaxPasses, stream);
+    launch_fill_u32(sstat, 0u, (int64_t)256 * chunks * passes, stream);
+    launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)ntiles, stream);
+
+    uint64_t *k0 = at<uint64_t>(ws, ws->off_keys0), *k1 = at<uint64_t>(ws, ws->off_keys1);
+    uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
+    int alt = 0;
+    if (K > 0) {
+        launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
+        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        launch_radix_hist(k0, (uint32_t)K, zmin, dbits, passes, hist, stream);
+        if ((s = tm.mark(5)) != RECOGS_OK) return s;
+        for (int p = 0; p < passes; ++p) {
+            const uint64_t *kin = alt ? k1 : k0;
+            const uint32_t *vin = alt ? v1 : v0;
+            uint64_t *kout = alt ? k0 : k1;
+            uint32_t *vout = alt ? v0 : v1;
+            launch_radix_pass(kin, vin, kout, vout, (uint32_t)K, zmin, dbits, 8 * p, hist + 256 * p,
+                              sstat + (size_t)256 * chunks * p, hdr + H_SORT_TICKET + p, stream);
+            alt ^= 1;
+        }
+        if ((s = tm.mark(6)) != RECOGS_OK) return s;
+        launch_ranges(alt ? k1 : k0, (uint32_t)K, ranges, stream);
+    } else {
+        for (int k = 4; k <= 6; ++k)
+            if ((s = tm.mark(k)) != RECOGS_OK) return s;
+    }
+    if ((s = tm.mark(7)) != RECOGS_OK) return s;
+    ws->sorted_in_alt = alt;
+    if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
+    if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0, rec, cam->width,
+                      cam->height, cd.tiles_x, opts->bg, image, at<float>(ws, ws->off_final_T),
+                      at<uint32_t>(ws, ws->off_nproc), stream))
+        return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
+    if ((s = tm.mark(8)) != RECOGS_OK) return s;
+    if ((s = hip_check("blend")) != RECOGS_OK) return s;
+    return tm.finish(ws, 8);
+}
+
+recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
+                                     const recogs_workspace *ws, const float *image, const float *dL_dimage,
+                                     float *dL_dopacity, float *dL_dsh_dc, float *dL_dM, hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_scene(scene)) != RECOGS_OK) return s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if ((s = check_opts(opts)) != RECOGS_OK) return s;
+    if ((s = check_ws(ws, scene, cam, opts)) != RECOGS_OK) return s;
+    if (!opts->keep_backward_state) return fail(RECOGS_ERR_INVALID, "render must keep backward state for the backward");
+    if (ws->last_n != scene->n) return fail(RECOGS_ERR_INVALID, "workspace holds a render of %d Gaussians, scene has %lld", ws->last_n, (long long)scene->n);
+    if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || !dL_dsh_dc)))
+        return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
+    const int64_t n = scene->n;
+    const int ntiles = ws->tiles_x * ws->tiles_y;
+    float4 *acc = at<float4>(ws, ws->off_grad);
+    launch_fill_u32((uint32_t *)acc, 0u, 4 * n, stream);
+    launch_fill_u32((uint32_t *)dL_dM, 0u, 9, stream);
+    const uint32_t *vals = ws->sorted_in_alt ? at<uint32_t>(ws, ws->off_vals1) : at<uint32_t>(ws, ws->off_vals0);
+    if (ws->num_keys > 0) {
+        if (!launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges), vals,
+                              at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, ws->tiles_x, image, dL_dimage,
+                              at<uint32_t>(ws, ws->off_nproc), acc, stream))
+            return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
+    }
+    launch_grad_finish(acc, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, dL_dsh_dc,
+                       dL_dM, stream);
+    return hip_check("backward");
+}
+
+recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,
+                             float *loss, hipStream_t stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(RECOGS_ERR_INVALID, "count < 0");
+    if (!loss || (count > 0 && (!image || !target || !dL_dimage))) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    launch_fill_u32((uint32_t *)loss, 0u, 1, stream);
+    launch_loss_l2(image, target, count, scale, dL_dimage, loss, stream);
+    return hip_check("loss_l2");
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, per hot-path step.
+
+Integer outputs (selection masks, depth keys, tile rectangles and counts, sorted
+order, tile ranges) must match exactly except for decisions the oracle flags as
+lying within float32 rounding of their threshold; pixels must match within 2e-3
+(float32 path) plus the oracle's per-pixel bound for in-band threshold decisions.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import assert_pixels, crop_windows, gpu_run, pull
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 2e-3
+TOL_F16 = 1e-2
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2511_18441_amd as R
+    return R
+
+
+def _oracle(w, orc, tile=(16, 16), fused=None, view=0, cov=None):
+    v = w.views[view]
+    sc = w.scenes[v.scene]
+    if fused is None:
+        return orc.project(sc, v.camera, tile, cov=cov)
+    return orc.project(sc, v.camera, tile, cov=cov, mask=fused[0], M=fused[1], b=fused[2])
+
+
+# ---------------------------------------------------------------------------
+# covariance (eq. 1), selection, recolour (eq. 6)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", ["tiny", "mid"])
+def test_covariance(R, orc, cfg):
+    w = synth.make_tiny() if cfg == "tiny" else synth.make_mid(n=50_000)
+    d = R.DeviceScene(w.scene)
+    got = d.cov3d[:, : w.scene.n].cpu().numpy().astype(np.float64)
+    ref = orc.covariance(w.scene.log_scales, w.scene.quats)
+    scale = ref[0] + ref[3] + ref[5]
+    assert np.all(np.abs(got - ref) <= 4e-6 * scale + 1e-30)
+
+
+@pytest.mark.parametrize("cfg,storage", [("tiny", "f32"), ("mid", "f32"), ("mid", "f16"), ("mid", "bf16")])
+def test_select(R, orc, cfg, storage):
+    import torch
+    w = synth.make_tiny() if cfg == "tiny" else synth.make_mid()
+    sc = w.scene if storage == "f32" else w.scene.with_storage(storage)
+    d = R.DeviceScene(sc)
+    mask = torch.empty(sc.n, dtype=torch.uint8, device="cuda")
+    count = torch.empty(1, dtype=torch.int32, device="cuda")
+    R.recogs_select(d.c_struct(), R.camera_struct(w.view.camera), R.select_struct(w.view.select),
+                    mask.data_ptr(), count.data_ptr())
+    got = mask.cpu().numpy()
+    ref, flag = orc.select(sc, w.view.camera, w.view.select)
+    diff = (got != ref)
+    assert not (diff & (flag == 0)).any(), np.nonzero(diff & (flag == 0))[0][:10]
+    assert int(count.item()) == int(got.sum())
+    assert ref.sum() > 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("which", ["affine", "hue"])
+def test_recolor(R, orc, storage, which):
+    import torch
+    w = synth.make_mid(n=60_000)
+    sc = w.scene if storage == "f32" else w.scene.with_storage(storage)
+    rng = np.random.default_rng(3)
+    maskn = (rng.random(sc.n) < 0.3).astype(np.uint8)
+    rec = w.view.recolor if which == "affine" else synth.RecolorParams(synth.hue_rotation(120.0), np.zeros(3, np.float32))
+    d = R.DeviceScene(sc)
+    mask = torch.from_numpy(maskn).cuda()
+    M = torch.from_numpy(rec.M.reshape(9)).cuda()
+    b = torch.from_numpy(rec.b).cuda()
+    dst = d.sh.clone()
+    R.recogs_recolor(d.c_struct(), dst.data_ptr(), mask.data_ptr(), M.data_ptr(), b.data_ptr(), 0)
+    got = dst.float().cpu().numpy().astype(np.float64)
+    ref = orc.recolor(sc.sh_f32(), maskn, rec.M.astype(np.float64), rec.b.astype(np.float64))
+    if storage == "f32":
+        tol = 4e-6 * (1 + np.abs(ref))
+    else:
+        ulp = {"f16": 2.0 ** -10, "bf16": 2.0 ** -7}[storage]
+        tol = ulp * np.maximum(np.abs(ref), 2.0 ** -14) + 4e-6 * (1 + np.abs(ref))
+    assert np.all(np.abs(got - ref) <= tol)
+    # unselected untouched
+    keep = maskn == 0
+    assert np.array_equal(got[:, keep], sc.sh_f32()[:, keep].astype(np.float64))
+    if which == "hue":  # exact channel permutation (r, g, b) -> (b, r, g) on every band
+        sel = maskn == 1
+        src = sc.sh_f32().astype(np.float64)
+        for k in range(16):
+            assert np.array_equal(got[3 * k + 0, sel], src[3 * k + 2, sel])
+            assert np.array_equal(got[3 * k + 1, sel], src[3 * k + 0, sel])
+
+
+# ---------------------------------------------------------------------------
+# render steps: preprocess, scan, emit + sort, ranges, blend
+# ---------------------------------------------------------------------------
+def _check_integer_steps(w, orc, p, pr, n):
+    status = pr.col("status")
+    flag = pr.col("flag").astype(bool)
+    # depth key: float32 rounding of the exact depth
+    zmis = (p["zbits"] != pr.col("z32bits")) & (status != 1)
+    assert zmis.sum() <= max(2, n // 100_000), int(zmis.sum())
+    # tile rectangle and count
+    cnt_ref = pr.col("count")
+    ok = ~flag & ~zmis
+    assert np.array_equal(p["counts"][ok], cnt_ref[ok]), np.nonzero(p["counts"][ok] != cnt_ref[ok])[0][:10]
+    has = ok & (cnt_ref > 0)
+    r = p["rects"]
+    assert np.array_equal(r[has, 0] & 0xFFFF, pr.col("txlo")[has])
+    assert np.array_equal(r[has, 0] >> 16, pr.col("txhi")[has])
+    assert np.array_equal(r[has, 1] & 0xFFFF, pr.col("tylo")[has])
+    assert np.array_equal(r[has, 1] >> 16, pr.col("tyhi")[has])
+    # scan: exclusive prefix sum of the counts, total K
+    c = p["counts"]
+    assert np.array_equal(p["offsets"], np.concatenate([[0], np.cumsum(c)[:-1]]))
+    assert p["K"] == int(c.sum())
+    # sorted keys: non-decreasing (tile, depth); equal keys in index order (stable)
+    keys = p["keys"]
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    zb = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    vals = p["vals"]
+    order_ok = (tile[1:] > tile[:-1]) | ((tile[1:] == tile[:-1]) & ((zb[1:] > zb[:-1]) | ((zb[1:] == zb[:-1]) & (vals[1:] > vals[:-1]))))
+    assert order_ok.all()
+    assert np.array_equal(zb, p["zbits"][vals])
+    # against the oracle's sorted (tile, depth, index) list without flagged Gaussians
+    ts, zs, ids = orc.sorted_keys(pr)
+    bad = flag | zmis
+    keep_o = ~bad[ids]
+    keep_g = ~bad[vals]
+    assert np.array_equal(tile[keep_g], ts[keep_o])
+    assert np.array_equal(zb[keep_g], zs[keep_o])
+    assert np.array_equal(vals[keep_g], ids[keep_o])
+    # tile ranges: consistent with the GPU's own sorted keys ...
+    ntile = p["ranges"].shape[0]
+    lo = np.searchsorted(tile, np.arange(ntile), side="left")
+    hi = np.searchsorted(tile, np.arange(ntile), side="right")
+    prop = np.where((hi > lo)[:, None], np.stack([lo, hi], 1), 0)
+    assert np.array_equal(p["ranges"], prop)
+    # ... and, per tile not touched by a flagged Gaussian, as long as the oracle's
+    ref = orc.tile_ranges(ts, ntile)
+    touched = np.zeros(ntile, bool)
+    touched[ts[bad[ids]]] = True
+    touched[tile[bad[vals]]] = True
+    len_g = p["ranges"][:, 1] - p["ranges"][:, 0]
+    len_o = ref[:, 1] - ref[:, 0]
+    assert np.array_equal(len_g[~touched], len_o[~touched])
+    if not bad.any():
+        assert np.array_equal(p["ranges"], ref)
+    return zmis
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "mid"])
+def test_render_full_image(R, orc, cfg):
+    w = synth.make_tiny() if cfg == "tiny" else synth.make_mid()
+    n = w.scene.n
+    out = gpu_run(w)
+    p = pull(out, n)
+    pr = _oracle(w, orc)
+    zmis = _check_integer_steps(w, orc, p, pr, n)
+    ref = orc.render_image(pr, brute=(cfg == "tiny"))
+    err, nband = assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, cfg)
+    assert err <= TOL_F32
+    assert nband <= max(5, p["img"].shape[0] * p["img"].shape[1] // 1000)
+    # transmittance and last blended splat
+    assert np.all(np.abs(p["T"] - ref.T) <= TOL_F32 + ref.slack)
+    print(f"{cfg}: K={p['K']} max|err| outside band {err:.2e}, in-band pixels {nband}, depth mismatches {int(zmis.sum())}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_render_1m_1080p_crops(R, orc, storage):
+    """1,000,000 Gaussians, SH degree 3, 1920x1080: integer steps on the whole frame,
+    pixels on 64 seeded 32x32 crops."""
+    w32 = synth.make_precision()
+    w = w32 if storage == "f32" else synth.make_precision(storage=storage)
+    n = w.scene.n
+    out = gpu_run(w)
+    p = pull(out, n)
+    pr = _oracle(w, orc)
+    _check_integer_steps(w, orc, p, pr, n)
+    wins = crop_windows(w, w.extra["crops"])
+    ref = orc.render_windows(pr, wins)
+    got = np.concatenate([p["img"][y:y + 32, x:x + 32].reshape(-1, 3) for (x, y, _, _) in wins])
+    err, nband = assert_pixels(got, ref.rgb, ref.slack, TOL_F32, f"{storage} vs oracle on stored inputs")
+    if storage != "f32":
+        ref32 = orc.render_windows(_oracle(w32, orc), wins)
+        err32, _ = assert_pixels(got, ref32.rgb, ref32.slack, TOL_F16, f"{storage} vs oracle on float32 inputs")
+        print(f"{storage}: error vs float32-input oracle {err32:.2e}")
+    print(f"{storage}: K={p['K']} crops max|err| {err:.2e} in-band {nband}")
+
+
+def test_fused_recolor_render(R, orc):
+    """Selection + fused affine recolour on the mid scene (the displayed colour of the
+    selected Gaussians is M (f + 1/2) + b)."""
+    w = synth.make_mid()
+    mask, _ = orc.select(w.scene, w.view.camera, w.view.select)
+    fused = (mask, w.view.recolor.M, w.view.recolor.b)
+    out = gpu_run(w, fused=fused)
+    p = pull(out, w.scene.n)
+    pr = _oracle(w, orc, fused=(mask, w.view.recolor.M.astype(np.float64), w.view.recolor.b.astype(np.float64)))
+    ref = orc.render_image(pr)
+    assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, "fused recolour")
+
+
+def test_separate_recolor_then_render_equals_fused(R, orc):
+    """recogs_recolor on coefficients then render == render with the fused recolour
+    (within float32 rounding), tying eq. (6)'s coefficient form to its colour form."""
+    import torch
+    w = synth.make_mid(n=100_000)
+    mask, _ = orc.select(w.scene, w.view.camera, w.view.select)
+    rec = w.view.recolor
+    a = gpu_run(w, fused=(mask, rec.M, rec.b))
+    d = a["dscene"]
+    dst = d.sh.clone()
+    R.recogs_recolor(d.c_struct(), dst.data_ptr(), a["mask"].data_ptr(), a["M"].data_ptr(), a["b"].data_ptr(), 0)
+    ws = R.DeviceWorkspace(w.scene.n, w.view.camera.width, w.view.camera.height)
+    img = R.render(d, w.view.camera, ws, sh=dst)
+    torch.cuda.synchronize()
+    assert (img - a["img"]).abs().max().item() <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+def test_tile_shape_and_ppt_do_not_change_bits(R):
+    w = synth.make_mid(n=100_000)
+    base = gpu_run(w, tile=(16, 16), ppt=1)["img"].cpu().numpy()
+    for tile in [(16, 16), (8, 8), (32, 8)]:
+        for ppt in [1, 2, 4]:
+            img = gpu_run(w, tile=tile, ppt=ppt)["img"].cpu().numpy()
+            assert np.array_equal(img, base), (tile, ppt, np.abs(img - base).max())
+
+
+def test_hue_permutation_exact_and_identity_exact(R):
+    w = synth.make_mid(n=100_000)
+    n = w.scene.n
+    ones = np.ones(n, np.uint8)
+    plain = gpu_run(w)["img"].cpu().numpy()
+    hue = gpu_run(w, fused=(ones, synth.hue_rotation(120.0), np.zeros(3, np.float32)))["img"].cpu().numpy()
+    assert np.array_equal(hue[..., 0], plain[..., 2])
+    assert np.array_equal(hue[..., 1], plain[..., 0])
+    assert np.array_equal(hue[..., 2], plain[..., 1])
+    ident = gpu_run(w, fused=(ones, np.eye(3, dtype=np.float32), np.zeros(3, np.float32)))["img"].cpu().numpy()
+    assert np.array_equal(ident, plain)
+
+
+def test_deterministic(R):
+    w = synth.make_mid(n=100_000)
+    a = gpu_run(w)
+    b = gpu_run(w, ws=a["ws"], dscene=a["dscene"])
+    assert np.array_equal(a["img"].cpu().numpy(), b["img"].cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_empty_scene_and_background(R):
+    w = synth.make_tiny()
+    empty = w.scene.subset(np.arange(0))
+    w0 = synth.Workload("empty", [empty], w.views)
+    img = gpu_run(w0, bg=(0.25, 0.5, 0.75))["img"].cpu().numpy()
+    assert np.array_equal(img, np.broadcast_to(np.float32([0.25, 0.5, 0.75]), img.shape))
+
+
+def test_all_behind_camera(R):
+    w = synth.make_tiny()
+    c = w.view.camera
+    # flip the viewing direction: looking away from the scene
+    R_ = c.R.copy()
+    R_[2] = -R_[2]
+    R_[0] = -R_[0]
+    behind = synth.Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, R_, np.float32([0, 0, -3]), c.znear)
+    w1 = synth.Workload("behind", [w.scene], [synth.View(0, behind, w.view.select, w.view.recolor)])
+    out = gpu_run(w1)
+    assert out["ws"].ws.num_keys == 0
+    assert np.array_equal(out["img"].cpu().numpy(), np.zeros((c.height, c.width, 3), np.float32))
+
+
+@pytest.mark.parametrize("size", [(97, 61), (1, 1), (33, 200)])
+def test_ragged_image_sizes(R, orc, size):
+    W, H = size
+    w = synth.make_tiny()
+    c = synth.orbit_camera(W, H, 60.0, 3.0, 0.4, 0.3)
+    w1 = synth.Workload("ragged", [w.scene], [synth.View(0, c, w.view.select, w.view.recolor)])
+    for tile in [(16, 16), (32, 8)]:
+        out = gpu_run(w1, tile=tile)
+        p = pull(out, w.scene.n)
+        pr = orc.project(w.scene, c, tile)
+        _check_integer_steps(w1, orc, p, pr, w.scene.n)
+        ref = orc.render_image(pr, brute=True)
+        assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, f"{size} {tile}")
+
+
+def test_capacity_error_reports_needed_keys(R):
+    import torch
+    w = synth.make_tiny()
+    d = R.DeviceScene(w.scene)
+    ws = R.DeviceWorkspace(w.scene.n, 128, 128, (16, 16), key_capacity=100)
+    img = torch.empty((128, 128, 3), device="cuda")
+    with pytest.raises(R.RecogsError) as e:
+        R.render(d, w.view.camera, ws, image=img, grow=False)
+    assert e.value.status == -2
+    need = int(ws.ws.num_keys)
+    assert need > 100
+    R.render(d, w.view.camera, ws, image=img, grow=True)
+    torch.cuda.synchronize()
+    assert int(ws.ws.num_keys) == need
+
+
+def test_stride_larger_than_n(R, orc):
+    w = synth.make_tiny()
+    d = R.DeviceScene(w.scene, stride=w.scene.n + 1000)
+    out = gpu_run(w, dscene=d)
+    pr = orc.project(w.scene, w.view.camera)
+    ref = orc.render_image(pr, brute=True)
+    assert_pixels(out["img"].cpu().numpy().astype(np.float64), ref.rgb, ref.slack, TOL_F32, "stride")
