@@ -131,13 +131,6 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, Rec
         rect[i] = rr;
         zbits[i] = zb;
     }
-    // depth range of Gaussians with keys (header zeroed; min kept as complement)
-    const bool has = cnt > 0;
-    const uint32_t zmn = wave_min(has ? zb : 0xffffffffu), zmx = wave_max(has ? zb : 0u);
-    if (lane_id() == 0 && wave_ballot(has)) {
-        atomicMax(&header[H_ZMIN], ~zmn);
-        atomicMax(&header[H_ZMAX], zmx);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -145,11 +138,14 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, Rec
 // (workgroups take chunk ids from an atomic ticket so every predecessor a
 // workgroup waits for is already running). The last chunk stores the total K.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, uint32_t *__restrict__ off, int64_t n,
-                                              uint64_t *__restrict__ status, uint32_t *__restrict__ header,
-                                              uint32_t nchunks) {
+// The depth range (min / max float32 depth bits of Gaussians with keys) is folded
+// in here too: one pair of atomics per chunk.
+__global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
+                                              uint32_t *__restrict__ off, int64_t n, uint64_t *__restrict__ status,
+                                              uint32_t *__restrict__ header, uint32_t nchunks) {
     __shared__ uint32_t s_chunk;
     __shared__ uint64_t s_w[4];
+    __shared__ uint32_t s_zmn[4], s_zmx[4];
     __shared__ uint64_t s_prefix;
     if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_SCAN_TICKET], 1u);
     __syncthreads();
@@ -158,14 +154,31 @@ __global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, 
     const int64_t base = (int64_t)chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
     uint64_t tsum = 0;
+    uint32_t zmn = 0xffffffffu, zmx = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = (base + k < n) ? cnt[base + k] : 0u;
         tsum += v[k];
+        if (v[k]) {
+            const uint32_t z = zbits[base + k];
+            zmn = min(zmn, z);
+            zmx = max(zmx, z);
+        }
     }
+    zmn = wave_min(zmn);
+    zmx = wave_max(zmx);
     const uint64_t inc = wave_incl_scan(tsum);
     if (lane == 63) s_w[w] = inc;
+    if (lane == 0) { s_zmn[w] = zmn; s_zmx[w] = zmx; }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        zmn = min(min(s_zmn[0], s_zmn[1]), min(s_zmn[2], s_zmn[3]));
+        zmx = max(max(s_zmx[0], s_zmx[1]), max(s_zmx[2], s_zmx[3]));
+        if (zmx >= zmn) {  // the header keeps the minimum as its complement (zero-initialised)
+            atomicMax(&header[H_ZMIN], ~zmn);
+            atomicMax(&header[H_ZMAX], zmx);
+        }
+    }
     uint64_t wpre = 0, total = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -176,22 +189,37 @@ __global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, 
     if (threadIdx.x == 0) {
         uint64_t excl = 0;
         if (chunk == 0) {
-            __hip_atomic_store(&status[0], kFlagInc | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&status[0], kFlagInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&status[chunk], kFlagAgg | total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&status[chunk], kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // windowed look-back (see the radix pass)
             int64_t j = (int64_t)chunk - 1;
             while (true) {
-                const uint64_t s = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint64_t f = s & kFlagMask;
-                if (f == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+                uint64_t s[kLookback];
+#pragma unroll
+                for (int k = 0; k < kLookback; ++k)
+                    s[k] = (j - k >= 0) ? __hip_atomic_load(&status[j - k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : kFlagInc;
+                bool stop = false, done = false;
+                int used = 0;
+#pragma unroll
+                for (int k = 0; k < kLookback; ++k) {
+                    if (!stop) {
+                        const uint64_t f = s[k] & kFlagMask;
+                        if (f == 0) {
+                            stop = true;
+                        } else {
+                            excl += s[k] & ~kFlagMask;
+                            ++used;
+                            if (f == kFlagInc) stop = done = true;
+                        }
+                    }
                 }
-                excl += s & ~kFlagMask;
-                if (f == kFlagInc) break;
-                --j;
+                if (done) break;
+                j -= used;
+                if (used == 0) __builtin_amdgcn_s_sleep(1);
             }
-            __hip_atomic_store(&status[chunk], kFlagInc | (excl + total), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&status[chunk], kFlagInc | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         s_prefix = excl;
         if (chunk == nchunks - 1) {
@@ -418,10 +446,11 @@ void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, c
     else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
 }
 
-void launch_scan(const uint32_t *cnt, uint32_t *off, int64_t n, uint64_t *status, uint32_t *hdr, hipStream_t st) {
+void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *status, uint32_t *hdr,
+                 hipStream_t st) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, off, n, status, hdr, nchunks);
+    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, status, hdr, nchunks);
 }
 
 void launch_emit(const uint32_t *cnt, const uint32_t *off, const uint2 *rect, const uint32_t *zb, int64_t n, int tiles_x,

@@ -113,22 +113,38 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
     // decoupled look-back over earlier chunks for digit t
     uint32_t excl = 0;
     if (chunk == 0) {
-        __hip_atomic_store(&status[t], kRFlagInc | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&status[t], kRFlagInc | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-        __hip_atomic_store(&status[chunk * 256 + t], kRFlagAgg | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&status[chunk * 256 + t], kRFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // windowed look-back: kLookback predecessors loaded at once, consumed in order
+        // until an inclusive prefix is found; a not-yet-published entry ends the window
         int64_t j = (int64_t)chunk - 1;
         while (true) {
-            const uint32_t s = __hip_atomic_load(&status[j * 256 + t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t f = s & kRFlagMask;
-            if (f == 0) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+            uint32_t s[kLookback];
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k)
+                s[k] = (j - k >= 0) ? __hip_atomic_load(&status[(j - k) * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : kRFlagInc;
+            bool stop = false, done = false;
+            int used = 0;
+#pragma unroll
+            for (int k = 0; k < kLookback; ++k) {
+                if (!stop) {
+                    const uint32_t f = s[k] & kRFlagMask;
+                    if (f == 0) {
+                        stop = true;
+                    } else {
+                        excl += s[k] & ~kRFlagMask;
+                        ++used;
+                        if (f == kRFlagInc) stop = done = true;
+                    }
+                }
             }
-            excl += s & ~kRFlagMask;
-            if (f == kRFlagInc) break;
-            --j;
+            if (done) break;
+            j -= used;
+            if (used == 0) __builtin_amdgcn_s_sleep(1);
         }
-        __hip_atomic_store(&status[chunk * 256 + t], kRFlagInc | (excl + tot), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&status[chunk * 256 + t], kRFlagInc | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     uint32_t total;
     const uint32_t gpre = block_excl_scan256(ghist[t], s_w, total);

@@ -168,6 +168,7 @@ constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgrou
 constexpr int kSortItems = 16;                       // keys per thread per radix pass
 constexpr int kSortChunk = 256 * kSortItems;         // keys per radix workgroup
 constexpr int kMaxPasses = 8;
+constexpr int kLookback = 16;                        // predecessors read per look-back step
 
 // Per-Gaussian splat record for compositing: three float4
 //   r0 = (u, v, ex, ey)   centre (pixels) and half-extents of the alpha >= 1/255 box

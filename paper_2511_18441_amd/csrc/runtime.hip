@@ -16,7 +16,7 @@ void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const f
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
                        uint32_t *, uint2 *, uint32_t *, uint32_t *, hipStream_t);
-void launch_scan(const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, hipStream_t);
+void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, hipStream_t);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
@@ -310,7 +310,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
                       rect, cnt, hdr, stream);
     if ((s = tm.mark(1)) != RECOGS_OK) return s;
-    launch_scan(cnt, off, n, at<uint64_t>(ws, ws->off_scan), hdr, stream);
+    launch_scan(cnt, zb, off, n, at<uint64_t>(ws, ws->off_scan), hdr, stream);
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
 
