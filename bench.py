@@ -30,17 +30,19 @@ def log(*a):
 
 
 def algorithmic_model(st, storage_bytes, deg, keep_bwd=False):
-    """Bytes (and blend flops) each stage must move for this frame's counts."""
-    N, V, K, S, P, T, Pix, E, Keff = (st[k] for k in ("N", "V", "K", "S", "passes", "tiles", "pix", "evals", "keff"))
+    """Bytes (and blend flops) each stage must move for this frame's counts
+    (default sort: depth sort of the V Gaussians with keys, then 32-bit tile keys)."""
+    N, V, K, S, P, Pd, T, Pix, E, Keff = (st[k] for k in ("N", "V", "K", "S", "passes", "dpasses", "tiles", "pix",
+                                                           "evals", "keff"))
     nc = 3 * (deg + 1) ** 2
     b = {
         "recolor": N * 1 + S * nc * storage_bytes * 2,
         "preprocess": N * (12 + 24 + storage_bytes) + V * nc * storage_bytes + V * 48 + N * 16 + (V * 16 if keep_bwd else 0),
-        "scan": N * 8,
-        "emit": N * 8 + V * 12 + K * 12,
-        "radix_hist": K * 8,
-        "radix_passes": P * K * 24,
-        "ranges": K * 8 + T * 8,
+        "scan": N * 8 + V * 12,
+        "depth_sort": V * 4 + Pd * V * 16,
+        "emit": V * 16 + K * 8,
+        "key_sort": K * 4 + P * K * 16,
+        "ranges": K * 4 + T * 8,
         "blend": Keff * 52 + T * 8 + Pix * 20,
     }
     return b, {"blend": E * BLEND_FLOPS_PER_EVAL}
@@ -168,6 +170,7 @@ def main():
     V = int((cnt != 0).sum().item())
     S = int(count.item())
     P = int(ws.ws.sort_passes)
+    Pd = int(ws.ws.depth_passes)
     T = ws.ws.tiles_x * ws.ws.tiles_y
     nproc = ws.nproc().to(torch.int64)
     E = int(nproc.sum().item())
@@ -176,9 +179,9 @@ def main():
     npad = torch.zeros((Hp, Wp), dtype=torch.int64, device=dev)
     npad[:cam.height, :cam.width] = nproc
     keff = int(npad.view(ws.ws.tiles_y, th, ws.ws.tiles_x, tw).amax(dim=(1, 3)).sum().item())
-    st = dict(N=n, V=V, K=K, S=S, passes=P, tiles=T, pix=cam.width * cam.height, evals=E, keff=keff)
+    st = dict(N=n, V=V, K=K, S=S, passes=P, dpasses=Pd, tiles=T, pix=cam.width * cam.height, evals=E, keff=keff)
     bytes_, flops = algorithmic_model(st, sb, w.scene.sh_degree)
-    launches = {"radix_passes": P}
+    launches = {"key_sort": P + 1, "depth_sort": Pd + 1}
     per_kernel = {}
     for k, t in stages.items():
         if k == "readback":

@@ -95,6 +95,13 @@ typedef struct {
     int32_t keep_backward_state; /* 1: store what recogs_render_backward needs */
     int32_t profile_stages;      /* 1: time each stage with HIP events on `stream` (the call then
                                     waits for the blend); times land in ws->stage_ms */
+    /* How the (tile, depth, index) order of the tile lists is produced; both give the
+     * same order. 0 (default): sort the Gaussians with keys by depth (32-bit keys),
+     * emit their tile keys in that order, then stable-sort the tile ids (the LSD
+     * depth digits sorted before the keys are duplicated). 1: emit 64-bit keys
+     * (tile << 32) | depth bits in index order and radix-sort them. */
+    int32_t sort_mode;
+    int32_t reserved;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds
@@ -114,17 +121,22 @@ typedef struct {
     size_t off_rec, off_bwd, off_grad, off_zbits, off_rect, off_count, off_offset, off_scan;
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_status;
     size_t off_ranges, off_final_T, off_nproc, off_header;
+    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_dstatus, off_estatus, off_vstatus;
     size_t scan_chunks, sort_chunks;
     /* results of the last render, valid when it returned RECOGS_OK (or CAPACITY) */
     int64_t num_keys;            /* K: tile keys emitted */
+    int64_t num_visible;         /* V: Gaussians with at least one tile key */
+    int32_t sort_mode;           /* sort_mode of the last render */
+    int32_t key_bytes;           /* 8: sorted keys are (tile << 32) | depth bits; 4: tile ids */
     int32_t sorted_in_alt;       /* 1 if the sorted keys/values are in keys1/vals1 */
-    int32_t sort_passes;
+    int32_t sort_passes;         /* passes over the K keys */
+    int32_t depth_passes;        /* passes over the V depth keys (sort_mode 0) */
     int32_t key_bits;            /* significant bits sorted: tile bits + depth bits */
     int32_t depth_bits;
     uint32_t depth_min_bits;     /* smallest float32 depth bit pattern among keys */
     int32_t last_n;
     /* with profile_stages: milliseconds of [0] preprocess, [1] scan, [2] key-count read-back,
-     * [3] key emission, [4] radix histogram, [5] all radix passes, [6] tile ranges, [7] blend */
+     * [3] depth sort, [4] key emission, [5] key sort, [6] tile ranges, [7] blend */
     float stage_ms[8];
 } recogs_workspace;
 

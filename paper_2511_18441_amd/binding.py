@@ -53,7 +53,8 @@ class SelectParams(ctypes.Structure):
 class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
-                ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32)]
+                ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
+                ("sort_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Workspace(ctypes.Structure):
@@ -64,12 +65,15 @@ class Workspace(ctypes.Structure):
                [(f, ctypes.c_size_t) for f in (
                    "off_rec", "off_bwd", "off_grad", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
                    "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_hist", "off_sort_status",
-                   "off_ranges", "off_final_T", "off_nproc", "off_header", "scan_chunks", "sort_chunks")] + \
-               [("num_keys", ctypes.c_int64), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
-                ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32), ("depth_min_bits", ctypes.c_uint32),
-                ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8)]
+                   "off_ranges", "off_final_T", "off_nproc", "off_header", "off_dkeys0", "off_dkeys1", "off_dvals0",
+                   "off_dvals1", "off_dhist", "off_dstatus", "off_estatus", "off_vstatus", "scan_chunks",
+                   "sort_chunks")] + \
+               [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("sort_mode", ctypes.c_int32),
+                ("key_bytes", ctypes.c_int32), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("depth_passes", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32),
+                ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8)]
 
-STAGES = ("preprocess", "scan", "readback", "emit", "radix_hist", "radix_passes", "ranges", "blend")
+STAGES = ("preprocess", "scan", "readback", "depth_sort", "emit", "key_sort", "ranges", "blend")
 
 
 _lib = None
@@ -188,7 +192,7 @@ def select_struct(sp) -> SelectParams:
 
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
-                profile=False) -> RenderOpts:
+                profile=False, sort_mode=0) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -199,6 +203,7 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.b = b.data_ptr() if b is not None else None
     o.keep_backward_state = 1 if keep_backward else 0
     o.profile_stages = 1 if profile else 0
+    o.sort_mode = int(sort_mode)
     return o
 
 
@@ -276,10 +281,11 @@ class DeviceWorkspace:
         return self.mem[off: off + count * itemsize].view(dtype)
 
     def keys_sorted(self):
+        """Sorted keys: int64 (tile << 32) | depth bits (sort_mode 1) or int32 tile ids (sort_mode 0)."""
         import torch
         K = int(self.ws.num_keys)
         off = self.ws.off_keys1 if self.ws.sorted_in_alt else self.ws.off_keys0
-        return self.view(off, K, torch.int64)
+        return self.view(off, K, torch.int64 if self.ws.key_bytes == 8 else torch.int32)
 
     def vals_sorted(self):
         import torch
@@ -320,14 +326,15 @@ class DeviceWorkspace:
 
 
 def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
-           M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False):
+           M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False,
+           sort_mode=0):
     """recogs_render into a (H, W, 3) float32 tensor; grows the workspace once when the
     view needs more tile keys than it holds."""
     import torch
     c = camera_struct(cam)
     if image is None:
         image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dscene.means.device)
-    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile)
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode)
     sc = dscene.c_struct(sh)
     st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     if st == -2 and grow:

@@ -134,43 +134,63 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, Rec
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of the tile counts, single pass with decoupled look-back
-// (workgroups take chunk ids from an atomic ticket so every predecessor a
-// workgroup waits for is already running). The last chunk stores the total K.
+// Exclusive scan of the tile counts, single pass with decoupled look-back. Also:
+//   - the compaction of the Gaussians with keys (index order kept) into
+//     (depth bits, index) pairs, the input of the depth sort, via a second
+//     look-back on the number of such Gaussians;
+//   - the depth range (min / max depth bits of Gaussians with keys): one pair of
+//     atomics per chunk.
+// The last chunk stores K (keys) and V (Gaussians with keys) in the header.
 // ---------------------------------------------------------------------------
-// The depth range (min / max float32 depth bits of Gaussians with keys) is folded
-// in here too: one pair of atomics per chunk.
 __global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                               uint32_t *__restrict__ off, int64_t n, uint64_t *__restrict__ status,
-                                              uint32_t *__restrict__ header, uint32_t nchunks) {
+                                              uint32_t *__restrict__ vstatus, uint32_t *__restrict__ dkeys,
+                                              uint32_t *__restrict__ dvals, uint32_t *__restrict__ header,
+                                              uint32_t nchunks) {
     __shared__ uint32_t s_chunk;
     __shared__ uint64_t s_w[4];
+    __shared__ uint32_t s_wv[4];
     __shared__ uint32_t s_zmn[4], s_zmx[4];
     __shared__ uint64_t s_prefix;
+    __shared__ uint32_t s_vprefix;
     if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_SCAN_TICKET], 1u);
     __syncthreads();
     const uint32_t chunk = s_chunk;
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     const int64_t base = (int64_t)chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
+    uint32_t v[kScanItems], z[kScanItems];
     uint64_t tsum = 0;
+    uint32_t vsum = 0;
     uint32_t zmn = 0xffffffffu, zmx = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = (base + k < n) ? cnt[base + k] : 0u;
         tsum += v[k];
+        z[k] = 0;
         if (v[k]) {
-            const uint32_t z = zbits[base + k];
-            zmn = min(zmn, z);
-            zmx = max(zmx, z);
+            z[k] = zbits[base + k];
+            zmn = min(zmn, z[k]);
+            zmx = max(zmx, z[k]);
+            ++vsum;
         }
     }
     zmn = wave_min(zmn);
     zmx = wave_max(zmx);
     const uint64_t inc = wave_incl_scan(tsum);
-    if (lane == 63) s_w[w] = inc;
+    const uint32_t vinc = wave_incl_scan(vsum);
+    if (lane == 63) { s_w[w] = inc; s_wv[w] = vinc; }
     if (lane == 0) { s_zmn[w] = zmn; s_zmx[w] = zmx; }
     __syncthreads();
+    uint64_t wpre = 0, total = 0;
+    uint32_t wvpre = 0, vtotal = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t x = s_w[k];
+        const uint32_t y = s_wv[k];
+        if (k < (int)w) { wpre += x; wvpre += y; }
+        total += x;
+        vtotal += y;
+    }
     if (threadIdx.x == 0) {
         zmn = min(min(s_zmn[0], s_zmn[1]), min(s_zmn[2], s_zmn[3]));
         zmx = max(max(s_zmx[0], s_zmx[1]), max(s_zmx[2], s_zmx[3]));
@@ -178,62 +198,30 @@ __global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, 
             atomicMax(&header[H_ZMIN], ~zmn);
             atomicMax(&header[H_ZMAX], zmx);
         }
-    }
-    uint64_t wpre = 0, total = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t x = s_w[k];
-        if (k < (int)w) wpre += x;
-        total += x;
-    }
-    if (threadIdx.x == 0) {
-        uint64_t excl = 0;
-        if (chunk == 0) {
-            __hip_atomic_store(&status[0], kFlagInc | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&status[chunk], kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // windowed look-back (see the radix pass)
-            int64_t j = (int64_t)chunk - 1;
-            while (true) {
-                uint64_t s[kLookback];
-#pragma unroll
-                for (int k = 0; k < kLookback; ++k)
-                    s[k] = (j - k >= 0) ? __hip_atomic_load(&status[j - k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                        : kFlagInc;
-                bool stop = false, done = false;
-                int used = 0;
-#pragma unroll
-                for (int k = 0; k < kLookback; ++k) {
-                    if (!stop) {
-                        const uint64_t f = s[k] & kFlagMask;
-                        if (f == 0) {
-                            stop = true;
-                        } else {
-                            excl += s[k] & ~kFlagMask;
-                            ++used;
-                            if (f == kFlagInc) stop = done = true;
-                        }
-                    }
-                }
-                if (done) break;
-                j -= used;
-                if (used == 0) __builtin_amdgcn_s_sleep(1);
-            }
-            __hip_atomic_store(&status[chunk], kFlagInc | (excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        const uint64_t excl = lookback<uint64_t>(status, chunk, total, kFlagAgg, kFlagInc, kFlagMask);
         s_prefix = excl;
         if (chunk == nchunks - 1) {
             const uint64_t K = excl + total;
             header[H_K_LO] = (uint32_t)K;
             header[H_K_HI] = (uint32_t)(K >> 32);
         }
+    } else if (threadIdx.x == 64) {
+        const uint32_t vex = lookback<uint32_t>(vstatus, chunk, vtotal, kRFlagAgg, kRFlagInc, kRFlagMask);
+        s_vprefix = vex;
+        if (chunk == nchunks - 1) header[H_V] = vex + vtotal;
     }
     __syncthreads();
     uint64_t run = s_prefix + wpre + inc - tsum;
+    uint32_t vrun = s_vprefix + wvpre + vinc - vsum;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) off[base + k] = (uint32_t)run;
         run += v[k];
+        if (v[k]) {
+            dkeys[vrun] = z[k];
+            dvals[vrun] = (uint32_t)(base + k);
+            ++vrun;
+        }
     }
 }
 
@@ -284,6 +272,91 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
         keys[base + j] = ((uint64_t)(ty * (uint32_t)tiles_x + tx) << 32) | s_zb[w][lo];
         vals[base + j] = (uint32_t)(g0 + lo);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Key emission in depth order: the Gaussians with keys, already sorted by (depth,
+// index), emit (tile id, index) pairs; a stable sort on the tile id then yields the
+// (tile, depth, index) order. A workgroup takes 4,096 consecutive depth-ordered
+// Gaussians (atomic ticket): wave w handles groups r = 0..15 of 64 consecutive ones.
+// The tile counts are scanned per group and across the 64 groups, the workgroup's
+// output offset comes from decoupled look-back, and each wave then writes the keys
+// of each of its groups cooperatively (one contiguous range per group: coalesced
+// stores, owner found by binary search over the group's prefix sums).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit_sorted(const uint32_t *__restrict__ order, uint32_t V,
+                                                     const uint32_t *__restrict__ cnt, const uint2 *__restrict__ rect,
+                                                     int tiles_x, uint32_t *__restrict__ status,
+                                                     uint32_t *__restrict__ header, uint32_t *__restrict__ tkeys,
+                                                     uint32_t *__restrict__ tvals) {
+    constexpr int R = kEmitItems;
+    __shared__ uint32_t s_chunk, s_prefix;
+    __shared__ uint32_t s_gsum[4 * R];     // per-group totals, then per-group exclusive prefix
+    __shared__ uint32_t s_ex[4][64];
+    __shared__ uint2 s_rect[4][64];
+    __shared__ uint32_t s_g[4][64];
+    if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_EMIT_TICKET], 1u);
+    __syncthreads();
+    const uint32_t chunk = s_chunk;
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t j0 = chunk * (uint32_t)kEmitChunk + w * (64 * R) + lane;
+    uint32_t c[R], inc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t j = j0 + r * 64;
+        c[r] = j < V ? cnt[order[j]] : 0u;
+        inc[r] = wave_incl_scan(c[r]);
+        if (lane == 63) s_gsum[w * R + r] = inc[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive scan of the 64 group totals (one wave)
+        const uint32_t v = s_gsum[threadIdx.x];
+        const uint32_t x = wave_incl_scan(v);
+        s_gsum[threadIdx.x] = x - v;
+        const uint32_t total = __shfl(x, 63, 64);
+        if (threadIdx.x == 0) s_prefix = lookback<uint32_t>(status, chunk, total, kRFlagAgg, kRFlagInc, kRFlagMask);
+    }
+    __syncthreads();
+    const uint32_t cbase = s_prefix;
+    for (int r = 0; r < R; ++r) {
+        const uint32_t j = j0 + r * 64;
+        const uint32_t g = j < V ? order[j] : 0u;
+        s_ex[w][lane] = inc[r] - c[r];
+        s_rect[w][lane] = c[r] ? rect[g] : make_uint2(0u, 0u);
+        s_g[w][lane] = g;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t base = cbase + s_gsum[w * R + r];
+        const uint32_t gtotal = __shfl(inc[r], 63, 64);
+        for (uint32_t q = lane; q < gtotal; q += 64) {
+            int lo = 0, hi = 63;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_ex[w][mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t k = q - s_ex[w][lo];
+            const uint2 rr = s_rect[w][lo];
+            const uint32_t tx0 = rr.x & 0xffffu, tx1 = rr.x >> 16, ty0 = rr.y & 0xffffu;
+            const uint32_t wd = tx1 - tx0 + 1;
+            const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
+            tkeys[base + q] = ty * (uint32_t)tiles_x + tx;
+            tvals[base + q] = s_g[w][lo];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// [first, last+1) of each tile in tile-sorted 32-bit tile ids (ranges zeroed beforehand).
+__global__ __launch_bounds__(256) void k_ranges32(const uint32_t *__restrict__ tiles, uint32_t K, uint2 *__restrict__ ranges) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t t = tiles[k];
+    if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
+    if (k == K - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
 }
 
 // [first, last+1) of each tile in the sorted keys (ranges zeroed beforehand).
@@ -446,11 +519,24 @@ void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, c
     else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
 }
 
-void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *status, uint32_t *hdr,
-                 hipStream_t st) {
+void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *status,
+                 uint32_t *vstatus, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, hipStream_t st) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, status, hdr, nchunks);
+    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, status, vstatus, dkeys, dvals, hdr,
+                       nchunks);
+}
+
+void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint32_t *cnt, const uint2 *rect, int tiles_x,
+                        uint32_t *status, uint32_t *hdr, uint32_t *tkeys, uint32_t *tvals, hipStream_t st) {
+    if (V == 0) return;
+    hipLaunchKernelGGL(k_emit_sorted, dim3((V + kEmitChunk - 1) / kEmitChunk), dim3(256), 0, st, order, V, cnt, rect,
+                       tiles_x, status, hdr, tkeys, tvals);
+}
+
+void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st) {
+    if (K == 0) return;
+    hipLaunchKernelGGL(k_ranges32, dim3((K + 255) / 256), dim3(256), 0, st, tiles, K, ranges);
 }
 
 void launch_emit(const uint32_t *cnt, const uint32_t *off, const uint2 *rect, const uint32_t *zb, int64_t n, int tiles_x,

@@ -1,22 +1,30 @@
-// Device radix sort of the 64-bit (tile, depth) keys with 32-bit values.
+// Device radix sort (stable LSD, up to 8-bit digits) with 32-bit values, used for
+// the (tile, depth) order of the tile lists.
 //
-// Stable LSD sort with 8-bit digits over only the significant bits: the digits are
-// taken from the view  (tile << dbits) | (depth_bits - min_depth_bits),  whose order
-// equals the order of the stored key (tile << 32) | depth_bits for the keys of one
-// render, and which needs ceil(log2 tiles) + dbits bits instead of 64.
+// Keys are 64-bit (tile << 32) | depth_bits or 32-bit (depth bits or tile id). The
+// digits come from a view of the key that keeps only its significant bits:
+//   KV_TILE_DEPTH (64-bit): (tile << dbits) | (depth_bits - zmin)
+//   KV_SUB        (32-bit): key - zmin
+// Both views preserve the key order among the keys of one render.
 //
-// One histogram pass counts the digits of every pass at once; then each pass is a
-// single kernel ("onesweep"): a workgroup takes a chunk of 4,096 keys from an atomic
-// ticket, ranks them stably per digit with wave ballots (64-lane match masks built
-// from 8 ballots, rank = popcount of the lower lanes), publishes its per-digit counts
-// and resolves its global offsets by decoupled look-back over earlier chunks, then
-// stages the chunk through LDS in digit order so global writes are contiguous runs.
+// One histogram kernel counts the digits of every pass at once; each pass is then a
+// single kernel: a workgroup takes a chunk of 4,096 keys from an atomic ticket,
+// ranks them stably per digit with wave ballots (a 64-lane match mask built from
+// one ballot per digit bit, rank = popcount of the lower lanes), publishes its
+// per-digit counts and resolves its global offsets by windowed decoupled look-back
+// over earlier chunks (relaxed agent-scope atomics: the counts are the only data
+// exchanged), then stages the chunk through LDS in digit order so global writes
+// are contiguous runs.
 #include "recogs_internal.hpp"
 
 namespace recogs {
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint32_t zmin, int dbits, int shift) {
-    return (uint32_t)(sort_view(key, zmin, dbits) >> shift) & 255u;
+enum : int { KV_TILE_DEPTH = 0, KV_SUB = 1 };
+
+template <typename KT, int VIEW>
+__device__ __forceinline__ uint32_t digit_of(KT key, uint32_t zmin, int dbits, int shift, uint32_t dmask) {
+    if constexpr (VIEW == KV_TILE_DEPTH) return (uint32_t)(sort_view((uint64_t)key, zmin, dbits) >> shift) & dmask;
+    else return ((uint32_t)key - zmin) >> shift & dmask;
 }
 
 // exclusive scan of one value per thread over a 256-thread workgroup
@@ -37,14 +45,22 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_w
     return pre + inc - v;
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__ keys, uint32_t K, uint32_t zmin,
-                                                    int dbits, int passes, uint32_t *__restrict__ ghist) {
+// Digit histograms of all passes. Pass p uses bits [shift_p, shift_p + bits_p) of the
+// view, shift_p = sum of earlier bits; `bits` packs bits_p in nibbles.
+template <typename KT, int VIEW>
+__global__ __launch_bounds__(256) void k_radix_hist(const KT *__restrict__ keys, uint32_t K, uint32_t zmin, int dbits,
+                                                    int passes, uint32_t bits, uint32_t *__restrict__ ghist) {
     __shared__ uint32_t h[kMaxPasses][256];
     for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&h[0][0])[i] = 0;
     __syncthreads();
     for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < K; k += gridDim.x * 256) {
-        const uint64_t x = sort_view(keys[k], zmin, dbits);
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(x >> (8 * p)) & 255u], 1u);
+        const KT key = keys[k];
+        int shift = 0;
+        for (int p = 0; p < passes; ++p) {
+            const int nb = (bits >> (4 * p)) & 15;
+            atomicAdd(&h[p][digit_of<KT, VIEW>(key, zmin, dbits, shift, (1u << nb) - 1u)], 1u);
+            shift += nb;
+        }
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p) {
@@ -53,9 +69,10 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
-                                                    uint32_t zmin, int dbits, int shift,
+template <typename KT, int VIEW>
+__global__ __launch_bounds__(256) void k_radix_pass(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                    KT *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
+                                                    uint32_t zmin, int dbits, int shift, int nbits,
                                                     const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
                                                     uint32_t *__restrict__ ticket) {
     __shared__ uint32_t s_whist[4][256];   // per-wave digit counts, then per-wave digit prefix
@@ -63,23 +80,24 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
     __shared__ uint32_t s_lstart[256];     // position in the LDS stage of each digit
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_chunk;
-    __shared__ uint64_t s_keys[kSortChunk];
+    __shared__ KT s_keys[kSortChunk];
     __shared__ uint32_t s_vals[kSortChunk];
 
     const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    const uint32_t dmask = (1u << nbits) - 1u;
     if (t == 0) s_chunk = atomicAdd(ticket, 1u);
     for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
     __syncthreads();
     const uint32_t chunk = s_chunk;
     const uint32_t cbase = chunk * (uint32_t)kSortChunk;
 
-    uint64_t key[kSortItems];
+    KT key[kSortItems];
     uint32_t val[kSortItems], rank[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
         const bool valid = idx < K;
-        key[r] = valid ? kin[idx] : 0ull;
+        key[r] = valid ? kin[idx] : (KT)0;
         val[r] = valid ? vin[idx] : 0u;
     }
     // stable rank within the wave, round by round
@@ -87,10 +105,9 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
         const bool valid = idx < K;
-        const uint32_t d = digit_of(key[r], zmin, dbits, shift);
+        const uint32_t d = digit_of<KT, VIEW>(key[r], zmin, dbits, shift, dmask);
         uint64_t m = wave_ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < nbits; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bb = wave_ballot(bit);
             m &= bit ? bb : ~bb;
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
         if (idx < K) {
-            const uint32_t d = digit_of(key[r], zmin, dbits, shift);
+            const uint32_t d = digit_of<KT, VIEW>(key[r], zmin, dbits, shift, dmask);
             const uint32_t pos = s_lstart[d] + s_whist[w][d] + rank[r];
             s_keys[pos] = key[r];
             s_vals[pos] = val[r];
@@ -164,8 +181,8 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
     __syncthreads();
     const uint32_t nvalid = min((uint32_t)kSortChunk, K - cbase);
     for (uint32_t j = t; j < nvalid; j += 256) {
-        const uint64_t k = s_keys[j];
-        const uint32_t d = digit_of(k, zmin, dbits, shift);
+        const KT k = s_keys[j];
+        const uint32_t d = digit_of<KT, VIEW>(k, zmin, dbits, shift, dmask);
         const uint32_t dst = s_gbase[d] + (j - s_lstart[d]);
         kout[dst] = k;
         vout[dst] = s_vals[j];
@@ -173,20 +190,54 @@ __global__ __launch_bounds__(256) void k_radix_pass(const uint64_t *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-void launch_radix_hist(const uint64_t *keys, uint32_t K, uint32_t zmin, int dbits, int passes, uint32_t *ghist,
-                       hipStream_t st) {
-    if (K == 0) return;
+// Host side: sort K (key, value) pairs across the two buffers over `total_bits`
+// significant bits (passes of equal width, <= 8 bits each). Returns 1 if the result
+// is in the alternate buffers (kb/vb), 0 if in ka/va. `status` holds
+// passes x ceil(K/4096) x 256 zeroed words, `ghist` 8 x 256 zeroed words, `tickets`
+// one zeroed word per pass.
+// ---------------------------------------------------------------------------
+int sort_passes(int total_bits) { return (total_bits + 7) / 8; }
+
+template <typename KT, int VIEW>
+static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
+                      uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
+    if (K == 0 || total_bits == 0) return 0;
+    const int passes = sort_passes(total_bits);
+    const int per = (total_bits + passes - 1) / passes;
+    uint32_t bits = 0;
+    int rem = total_bits;
+    for (int p = 0; p < passes; ++p) {
+        const int nb = rem < per ? rem : per;
+        bits |= (uint32_t)nb << (4 * p);
+        rem -= nb;
+    }
     uint32_t blocks = (K + 256 * 16 - 1) / (256 * 16);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_radix_hist, dim3(blocks), dim3(256), 0, st, keys, K, zmin, dbits, passes, ghist);
+    hipLaunchKernelGGL((k_radix_hist<KT, VIEW>), dim3(blocks), dim3(256), 0, st, ka, K, zmin, dbits, passes, bits, ghist);
+    const uint32_t chunks = (K + kSortChunk - 1) / kSortChunk;
+    int alt = 0, shift = 0;
+    for (int p = 0; p < passes; ++p) {
+        const int nb = (bits >> (4 * p)) & 15;
+        const KT *kin = alt ? kb : ka;
+        const uint32_t *vin = alt ? vb : va;
+        KT *kout = alt ? ka : kb;
+        uint32_t *vout = alt ? va : vb;
+        hipLaunchKernelGGL((k_radix_pass<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits,
+                           shift, nb, ghist + 256 * p, status + (size_t)256 * chunks * p, tickets + p);
+        alt ^= 1;
+        shift += nb;
+    }
+    return alt;
 }
 
-void launch_radix_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, uint32_t K, uint32_t zmin,
-                       int dbits, int shift, const uint32_t *ghist, uint32_t *status, uint32_t *ticket, hipStream_t st) {
-    if (K == 0) return;
-    const uint32_t chunks = (K + kSortChunk - 1) / kSortChunk;
-    hipLaunchKernelGGL(k_radix_pass, dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits, shift, ghist,
-                       status, ticket);
+int radix_sort_tile_depth64(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits,
+                            int total_bits, uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
+    return radix_sort<uint64_t, KV_TILE_DEPTH>(ka, va, kb, vb, K, zmin, dbits, total_bits, ghist, status, tickets, st);
+}
+
+int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K, uint32_t sub, int total_bits,
+                   uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, status, tickets, st);
 }
 
 }  // namespace recogs

@@ -16,15 +16,21 @@ void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const f
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
                        uint32_t *, uint2 *, uint32_t *, uint32_t *, hipStream_t);
-void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, hipStream_t);
+void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
+                 uint32_t *, hipStream_t);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
+void launch_emit_sorted(const uint32_t *, uint32_t, const uint32_t *, const uint2 *, int, uint32_t *, uint32_t *,
+                        uint32_t *, uint32_t *, hipStream_t);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
+void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                   float *, float *, uint32_t *, hipStream_t);
-void launch_radix_hist(const uint64_t *, uint32_t, uint32_t, int, int, uint32_t *, hipStream_t);
-void launch_radix_pass(const uint64_t *, const uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int,
-                       const uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+int sort_passes(int total_bits);
+int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
+                            uint32_t *, uint32_t *, hipStream_t);
+int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
+                   uint32_t *, hipStream_t);
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                       const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
@@ -88,11 +94,21 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     ws->off_vals1 = take(4 * (size_t)(cap > 0 ? cap : 1));
     ws->off_final_T = take(4 * (size_t)P);
     ws->off_nproc = take(4 * (size_t)P);
-    // zero-filled region: header, scan status, sort histogram, sort status, tile ranges
+    ws->off_dkeys0 = take(4 * nn);
+    ws->off_dkeys1 = take(4 * nn);
+    ws->off_dvals0 = take(4 * nn);
+    ws->off_dvals1 = take(4 * nn);
+    // zeroed before the preprocess: header, scan status, compaction status
     ws->off_header = take(4 * H_WORDS);
     ws->off_scan = take(8 * (size_t)scan_chunks);
+    ws->off_vstatus = take(4 * (size_t)scan_chunks);
+    // zeroed after the key count is known (only the part in use): histograms, look-back
+    // status of the sorts and of the depth-ordered emission, tile ranges
     ws->off_hist = take(4 * 256 * kMaxPasses);
+    ws->off_dhist = take(4 * 256 * kMaxPasses);
     ws->off_sort_status = take(4 * 256 * (size_t)kMaxPasses * (size_t)(sort_chunks > 0 ? sort_chunks : 1));
+    ws->off_dstatus = take(4 * 256 * (size_t)4 * (size_t)((nn + kSortChunk - 1) / kSortChunk));
+    ws->off_estatus = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
     ws->off_ranges = take(8 * (size_t)T);
     ws->scan_chunks = (size_t)scan_chunks;
     ws->sort_chunks = (size_t)sort_chunks;
@@ -139,7 +155,7 @@ thread_local StageTimer g_timer;
 recogs_status check_scene(const recogs_scene *sc) {
     if (!sc) return fail(RECOGS_ERR_INVALID, "scene is NULL");
     if (sc->n < 0) return fail(RECOGS_ERR_INVALID, "scene n = %lld < 0", (long long)sc->n);
-    if (sc->n > 0x7fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "scene n = %lld exceeds 2^31-1", (long long)sc->n);
+    if (sc->n > 0x3fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "scene n = %lld exceeds 2^30-1", (long long)sc->n);
     if (sc->stride < sc->n) return fail(RECOGS_ERR_INVALID, "scene stride %lld < n %lld", (long long)sc->stride, (long long)sc->n);
     if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(RECOGS_ERR_INVALID, "sh_degree %d not in 0..3", sc->sh_degree);
     if (sc->storage < RECOGS_F32 || sc->storage > RECOGS_BF16) return fail(RECOGS_ERR_INVALID, "storage dtype %d unknown", sc->storage);
@@ -195,6 +211,7 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (!o) return fail(RECOGS_ERR_INVALID, "render opts is NULL");
     if (!tile_supported(o->tile_w, o->tile_h))
         return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8", o->tile_w, o->tile_h);
+    if (o->sort_mode != 0 && o->sort_mode != 1) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0 or 1", o->sort_mode);
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
         return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
     const bool any = o->mask || o->M || o->b;
@@ -304,61 +321,76 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     StageTimer &tm = g_timer;
     for (int k = 0; k < 8; ++k) ws->stage_ms[k] = 0.f;
     if ((s = tm.start(opts->profile_stages != 0, stream)) != RECOGS_OK) return s;
-    // zero header + scan status (contiguous)
+    const int mode = opts->sort_mode;
+    uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
+    uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
+    // zero header, scan status and compaction status (contiguous)
     launch_fill_u32(hdr, 0u, (int64_t)((ws->off_hist - ws->off_header) / 4), stream);
     RecolorDev rc{opts->mask, opts->M, opts->b};
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
                       rect, cnt, hdr, stream);
     if ((s = tm.mark(1)) != RECOGS_OK) return s;
-    launch_scan(cnt, zb, off, n, at<uint64_t>(ws, ws->off_scan), hdr, stream);
+    launch_scan(cnt, zb, off, n, at<uint64_t>(ws, ws->off_scan), at<uint32_t>(ws, ws->off_vstatus), dk0, dv0, hdr, stream);
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
 
-    uint32_t h[4] = {0, 0, 0, 0};
+    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     RECOGS_TRY_HIP(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
     RECOGS_TRY_HIP(hipStreamSynchronize(stream));
     if ((s = tm.mark(3)) != RECOGS_OK) return s;
     const uint64_t K = n > 0 ? ((uint64_t)h[H_K_LO] | ((uint64_t)h[H_K_HI] << 32)) : 0;
+    const uint32_t V = n > 0 ? h[H_V] : 0;
     ws->num_keys = (int64_t)K;
+    ws->num_visible = V;
     ws->last_n = (int32_t)n;
+    ws->sort_mode = mode;
     if ((int64_t)K > ws->key_capacity)
         return fail(RECOGS_ERR_CAPACITY, "view needs %llu tile keys, workspace holds %lld", (unsigned long long)K,
                     (long long)ws->key_capacity);
     const uint32_t zmin = ~h[H_ZMIN], zmax = h[H_ZMAX];
     const int dbits = K ? bits_for((uint64_t)(zmax - zmin)) : 0;
     const int tbits = bits_for((uint64_t)(ntiles - 1));
-    const int key_bits = tbits + dbits;
-    const int passes = (key_bits + 7) / 8;
+    const int key_bits = mode == 0 ? tbits : tbits + dbits;
     ws->depth_bits = dbits;
     ws->depth_min_bits = zmin;
-    ws->key_bits = key_bits;
-    ws->sort_passes = passes;
+    ws->key_bits = tbits + dbits;
+    ws->sort_passes = K ? sort_passes(key_bits) : 0;
+    ws->depth_passes = (mode == 0 && V) ? sort_passes(dbits) : 0;
+    ws->key_bytes = mode == 0 ? 4 : 8;
 
+    // zero what the sorts, the emission and the ranges use
     const uint32_t chunks = (uint32_t)((K + kSortChunk - 1) / kSortChunk);
-    // zero histogram + sort status of the passes used + ranges
-    uint32_t *hist = at<uint32_t>(ws, ws->off_hist);
-    uint32_t *sstat = at<uint32_t>(ws, ws->off_sort_status);
-    launch_fill_u32(hist, 0u, 256 * kMaxPasses, stream);
-    launch_fill_u32(sstat, 0u, (int64_t)256 * chunks * passes, stream);
+    const uint32_t vchunks = (V + kSortChunk - 1) / kSortChunk;
+    uint32_t *hist = at<uint32_t>(ws, ws->off_hist), *dhist = at<uint32_t>(ws, ws->off_dhist);
+    uint32_t *sstat = at<uint32_t>(ws, ws->off_sort_status), *dstat = at<uint32_t>(ws, ws->off_dstatus);
+    launch_fill_u32(hist, 0u, 2 * 256 * kMaxPasses, stream);  // hist and dhist are adjacent
+    launch_fill_u32(sstat, 0u, (int64_t)256 * chunks * ws->sort_passes, stream);
+    if (mode == 0) {
+        launch_fill_u32(dstat, 0u, (int64_t)256 * vchunks * ws->depth_passes, stream);
+        launch_fill_u32(at<uint32_t>(ws, ws->off_estatus), 0u, (V + kEmitChunk - 1) / kEmitChunk, stream);
+    }
     launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)ntiles, stream);
 
     uint64_t *k0 = at<uint64_t>(ws, ws->off_keys0), *k1 = at<uint64_t>(ws, ws->off_keys1);
     uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
     int alt = 0;
-    if (K > 0) {
-        launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
+    if (K > 0 && mode == 0) {
+        // depth sort of the V Gaussians with keys (compacted in index order by the scan)
+        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, dstat, hdr + H_DSORT_TICKET, stream);
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
-        launch_radix_hist(k0, (uint32_t)K, zmin, dbits, passes, hist, stream);
+        uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
+        launch_emit_sorted(dalt ? dv1 : dv0, V, cnt, rect, cd.tiles_x, at<uint32_t>(ws, ws->off_estatus), hdr, t0, v0,
+                           stream);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        for (int p = 0; p < passes; ++p) {
-            const uint64_t *kin = alt ? k1 : k0;
-            const uint32_t *vin = alt ? v1 : v0;
-            uint64_t *kout = alt ? k0 : k1;
-            uint32_t *vout = alt ? v0 : v1;
-            launch_radix_pass(kin, vin, kout, vout, (uint32_t)K, zmin, dbits, 8 * p, hist + 256 * p,
-                              sstat + (size_t)256 * chunks * p, hdr + H_SORT_TICKET + p, stream);
-            alt ^= 1;
-        }
+        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, sstat, hdr + H_SORT_TICKET, stream);
+        if ((s = tm.mark(6)) != RECOGS_OK) return s;
+        launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream);
+    } else if (K > 0) {
+        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
+        if ((s = tm.mark(5)) != RECOGS_OK) return s;
+        alt = radix_sort_tile_depth64(k0, v0, k1, v1, (uint32_t)K, zmin, dbits, key_bits, hist, sstat,
+                                      hdr + H_SORT_TICKET, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges(alt ? k1 : k0, (uint32_t)K, ranges, stream);
     } else {

@@ -6,7 +6,7 @@ import synth
 
 
 def gpu_run(w, view=0, tile=(16, 16), ppt=1, fused=None, keep_backward=False, key_capacity=None, ws=None,
-            dscene=None, bg=(0.0, 0.0, 0.0)):
+            dscene=None, bg=(0.0, 0.0, 0.0), sort_mode=0):
     """Render view `view` of workload `w` through recogs_render. `fused` = (mask uint8 np, M, b)."""
     import torch
     import paper_2511_18441_amd as R
@@ -22,7 +22,7 @@ def gpu_run(w, view=0, tile=(16, 16), ppt=1, fused=None, keep_backward=False, ke
         mask = torch.from_numpy(np.asarray(fused[0], np.uint8)).cuda()
         M = torch.from_numpy(np.asarray(fused[1], np.float32).reshape(9)).cuda()
         b = torch.from_numpy(np.asarray(fused[2], np.float32).reshape(3)).cuda()
-    img = R.render(dscene, cam, ws, tile, ppt, bg, mask, M, b, keep_backward)
+    img = R.render(dscene, cam, ws, tile, ppt, bg, mask, M, b, keep_backward, sort_mode=sort_mode)
     torch.cuda.synchronize()
     return dict(img=img, ws=ws, dscene=dscene, mask=mask, M=M, b=b, cam=cam, tile=tile, ppt=ppt)
 
@@ -30,17 +30,26 @@ def gpu_run(w, view=0, tile=(16, 16), ppt=1, fused=None, keep_backward=False, ke
 def pull(out, n):
     """Integer outputs of the last render as numpy arrays."""
     ws = out["ws"]
-    keys = ws.keys_sorted().cpu().numpy().view(np.uint64)
+    keys = ws.keys_sorted().cpu().numpy()
+    zbits = ws.zbits(n).cpu().numpy().view(np.uint32).astype(np.int64)
+    vals = ws.vals_sorted().cpu().numpy().view(np.uint32).astype(np.int64)
+    if keys.dtype == np.int64:  # (tile << 32) | depth bits
+        keys = keys.view(np.uint64)
+        tile = (keys >> np.uint64(32)).astype(np.int64)
+        kz = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    else:  # tile ids; the depth comes from the value's Gaussian
+        tile = keys.view(np.uint32).astype(np.int64)
+        kz = zbits[vals]
     return dict(
+        tile=tile, kz=kz,
         img=out["img"].cpu().numpy().astype(np.float64),
         T=ws.final_T().cpu().numpy().astype(np.float64),
         nproc=ws.nproc().cpu().numpy().astype(np.int64),
         counts=ws.counts(n).cpu().numpy().view(np.uint32).astype(np.int64),
         offsets=ws.offsets(n).cpu().numpy().view(np.uint32).astype(np.int64),
-        zbits=ws.zbits(n).cpu().numpy().view(np.uint32).astype(np.int64),
+        zbits=zbits,
         rects=ws.rects(n).cpu().numpy().view(np.uint32).astype(np.int64),
-        keys=keys,
-        vals=ws.vals_sorted().cpu().numpy().view(np.uint32).astype(np.int64),
+        vals=vals,
         ranges=ws.ranges().cpu().numpy().view(np.uint32).astype(np.int64),
         K=int(ws.ws.num_keys),
     )

@@ -1,0 +1,172 @@
+"""Backward of the blend and the fused recolour (eq. 8 restricted to opacity, SH DC
+and the recolour matrix) and the L2 loss gradient, through the C ABI, against the
+FP64 oracle (whose gradient is itself pinned to central finite differences on the
+CPU) and, loosely, against finite differences of the GPU's own float32 forward."""
+import functools
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def _wfd():
+    """4,096 seeded Gaussians of the 1M-Gaussian differentiation scene, 64x64 (view 0)."""
+    return synth.make_diff_fd()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2511_18441_amd as R
+    return R
+
+
+def _setup(R, orc, w, g_seed=21):
+    import torch
+    v = w.view
+    sc = w.scene
+    mask, _ = orc.select(sc, v.camera, v.select)
+    M = v.recolor.M
+    b = v.recolor.b
+    d = R.DeviceScene(sc)
+    ws = R.DeviceWorkspace(sc.n, v.camera.width, v.camera.height)
+    tm = torch.from_numpy(mask).cuda()
+    tM = torch.from_numpy(M.reshape(9).copy()).cuda()
+    tb = torch.from_numpy(b.copy()).cuda()
+    g = synth.random_image(g_seed, (v.camera.height, v.camera.width, 3))
+    return d, ws, tm, tM, tb, mask, M, b, g
+
+
+def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1):
+    import torch
+    img = R.render(d, cam, ws, tile, ppt, mask=tm, M=tM, b=tb, keep_backward=True)
+    gt = torch.from_numpy(g).cuda()
+    n = d.n
+    dop = torch.empty(n, device="cuda")
+    ddc = torch.empty((3, n), device="cuda")
+    dM = torch.empty(9, device="cuda")
+    o = R.opts_struct(tile, ppt, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
+                             dop.data_ptr(), ddc.data_ptr(), dM.data_ptr())
+    torch.cuda.synchronize()
+    return img, dop.cpu().numpy().astype(np.float64), ddc.cpu().numpy().astype(np.float64), \
+        dM.cpu().numpy().astype(np.float64).reshape(3, 3)
+
+
+def _close(got, ref, rel, what):
+    scale = max(np.abs(ref).max(), 1e-12)
+    err = np.abs(got - ref)
+    bad = err > rel * scale + rel * np.abs(ref)
+    assert not bad.any(), f"{what}: {int(bad.sum())} entries off; max err {err.max():.3e} (scale {scale:.3e})"
+    return float(err.max() / scale)
+
+
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 1), ((8, 8), 2), ((32, 8), 4)])
+def test_backward_vs_oracle(R, orc, tile, ppt):
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    pr = orc.project(w.scene, cam, tile, mask=mask, M=M.astype(np.float64), b=b.astype(np.float64))
+    ref = orc.render_image(pr, brute=True)
+    # pixels with an in-band threshold decision get no upstream gradient on either side
+    g = np.where((ref.slack > 0)[..., None], 0.0, g).astype(np.float32)
+    assert (ref.slack > 0).mean() < 0.02
+    d_ws = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
+    img, dop, ddc, dM = _gpu_grads(R, d, d_ws, cam, tm, tM, tb, g, tile, ppt)
+    gr = orc.backward(pr, g, M=M.astype(np.float64))
+    e1 = _close(dop, gr.dsigma, 2e-3, "dL/dopacity")
+    e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
+    e3 = _close(dM, gr.dM, 2e-3, "dL/dM")
+    assert mask.sum() > 0 and np.abs(gr.dM).max() > 0
+    print(f"relative max errors: dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")
+
+
+def test_backward_matches_gpu_finite_differences(R, orc):
+    """Central differences of the GPU's own float32 loss sum(g * y) w.r.t. M (loose: the
+    float32 forward has ~1e-7 relative noise, the step is 1e-2)."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    _, _, _, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g)
+    gt = torch.from_numpy(g).cuda().double()
+    h = 1e-2
+    for k in range(9):
+        vals = []
+        for sgn in (1, -1):
+            Mp = M.reshape(9).astype(np.float64).copy()
+            Mp[k] += sgn * h
+            tMp = torch.from_numpy(Mp.astype(np.float32)).cuda()
+            img = R.render(d, cam, ws, mask=tm, M=tMp, b=tb)
+            vals.append(float((img.double() * gt).sum().item()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - dM.flat[k]) <= 2e-3 * max(1.0, abs(fd)), (k, fd, dM.flat[k])
+
+
+def test_autograd_function_matches_direct_backward(R, orc):
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    _, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g)
+    # leaves sharing the scene's own storage: the opacity array and its first 3 SH planes
+    op = torch.nn.Parameter(d.opacity, requires_grad=True)
+    leaf_dc = torch.nn.Parameter(d.sh.narrow(0, 0, 3), requires_grad=True)
+    Mt = torch.from_numpy(M.copy()).cuda().requires_grad_(True)
+    ws2 = R.DeviceWorkspace(w.scene.n, cam.width, cam.height)
+    img = R.RecogsRenderFn.apply(op, leaf_dc, Mt, d, cam, ws2, tm, tb)
+    loss = (img * torch.from_numpy(g).cuda()).sum()
+    loss.backward()
+    np.testing.assert_allclose(op.grad[: d.n].cpu().numpy(), dop, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(leaf_dc.grad[:, : d.n].cpu().numpy(), ddc, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(Mt.grad.cpu().numpy(), dM, rtol=1e-5, atol=1e-6)
+
+
+def test_loss_l2(R, orc):
+    import torch
+    y = synth.random_image(5, (72, 128, 3))
+    t = synth.random_image(6, (72, 128, 3))
+    ty, tt = torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()
+    dl = torch.empty_like(ty)
+    loss = torch.empty(1, device="cuda")
+    cnt = y.size
+    R.recogs_loss_l2(ty.data_ptr(), tt.data_ptr(), cnt, 1.0 / cnt, dl.data_ptr(), loss.data_ptr())
+    torch.cuda.synchronize()
+    ref_loss = orc.loss_l2(y, t)
+    ref_g = orc.loss_l2_grad(y, t)
+    assert abs(loss.item() - ref_loss) <= 1e-5 * ref_loss
+    np.testing.assert_allclose(dl.cpu().numpy(), ref_g, rtol=1e-6, atol=1e-12)
+
+
+def test_backward_without_recolor_and_zero_gradient(R, orc):
+    """No fused recolour: dL/dM is zero and dL/dC0 = Y00 gh; a zero upstream gradient
+    gives zero gradients."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d = R.DeviceScene(w.scene)
+    ws = R.DeviceWorkspace(w.scene.n, cam.width, cam.height)
+    img = R.render(d, cam, ws, keep_backward=True)
+    n = d.n
+    pr = orc.project(w.scene, cam)
+    band = orc.render_image(pr, brute=True).slack > 0
+    for gz in (False, True):
+        g = np.zeros((cam.height, cam.width, 3), np.float32) if gz else synth.random_image(3, (cam.height, cam.width, 3))
+        g = np.where(band[..., None], 0.0, g).astype(np.float32)
+        gt = torch.from_numpy(g).cuda()
+        dop = torch.empty(n, device="cuda")
+        ddc = torch.empty((3, n), device="cuda")
+        dM = torch.full((9,), 7.0, device="cuda")
+        o = R.opts_struct(keep_backward=True)
+        R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
+                                 dop.data_ptr(), ddc.data_ptr(), dM.data_ptr())
+        torch.cuda.synchronize()
+        assert np.all(dM.cpu().numpy() == 0)
+        if gz:
+            assert np.all(dop.cpu().numpy() == 0) and np.all(ddc.cpu().numpy() == 0)
+        else:
+            gr = orc.backward(pr, g)
+            _close(ddc.cpu().numpy().astype(np.float64), gr.dc0, 2e-3, "dC0 without recolour")

@@ -120,10 +120,7 @@ def _check_integer_steps(w, orc, p, pr, n):
     assert np.array_equal(p["offsets"], np.concatenate([[0], np.cumsum(c)[:-1]]))
     assert p["K"] == int(c.sum())
     # sorted keys: non-decreasing (tile, depth); equal keys in index order (stable)
-    keys = p["keys"]
-    tile = (keys >> np.uint64(32)).astype(np.int64)
-    zb = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    vals = p["vals"]
+    tile, zb, vals = p["tile"], p["kz"], p["vals"]
     order_ok = (tile[1:] > tile[:-1]) | ((tile[1:] == tile[:-1]) & ((zb[1:] > zb[:-1]) | ((zb[1:] == zb[:-1]) & (vals[1:] > vals[:-1]))))
     assert order_ok.all()
     assert np.array_equal(zb, p["zbits"][vals])
@@ -154,11 +151,12 @@ def _check_integer_steps(w, orc, p, pr, n):
     return zmis
 
 
+@pytest.mark.parametrize("sort_mode", [0, 1])
 @pytest.mark.parametrize("cfg", ["tiny", "mid"])
-def test_render_full_image(R, orc, cfg):
+def test_render_full_image(R, orc, cfg, sort_mode):
     w = synth.make_tiny() if cfg == "tiny" else synth.make_mid()
     n = w.scene.n
-    out = gpu_run(w)
+    out = gpu_run(w, sort_mode=sort_mode)
     p = pull(out, n)
     pr = _oracle(w, orc)
     zmis = _check_integer_steps(w, orc, p, pr, n)
@@ -171,14 +169,14 @@ def test_render_full_image(R, orc, cfg):
     print(f"{cfg}: K={p['K']} max|err| outside band {err:.2e}, in-band pixels {nband}, depth mismatches {int(zmis.sum())}")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_render_1m_1080p_crops(R, orc, storage):
+@pytest.mark.parametrize("storage,sort_mode", [("f32", 0), ("f32", 1), ("f16", 0), ("bf16", 0)])
+def test_render_1m_1080p_crops(R, orc, storage, sort_mode):
     """1,000,000 Gaussians, SH degree 3, 1920x1080: integer steps on the whole frame,
     pixels on 64 seeded 32x32 crops."""
     w32 = synth.make_precision()
     w = w32 if storage == "f32" else synth.make_precision(storage=storage)
     n = w.scene.n
-    out = gpu_run(w)
+    out = gpu_run(w, sort_mode=sort_mode)
     p = pull(out, n)
     pr = _oracle(w, orc)
     _check_integer_steps(w, orc, p, pr, n)
@@ -226,13 +224,14 @@ def test_separate_recolor_then_render_equals_fused(R, orc):
 # ---------------------------------------------------------------------------
 # invariants
 # ---------------------------------------------------------------------------
-def test_tile_shape_and_ppt_do_not_change_bits(R):
+def test_tile_shape_ppt_and_sort_mode_do_not_change_bits(R):
     w = synth.make_mid(n=100_000)
     base = gpu_run(w, tile=(16, 16), ppt=1)["img"].cpu().numpy()
     for tile in [(16, 16), (8, 8), (32, 8)]:
         for ppt in [1, 2, 4]:
-            img = gpu_run(w, tile=tile, ppt=ppt)["img"].cpu().numpy()
-            assert np.array_equal(img, base), (tile, ppt, np.abs(img - base).max())
+            for mode in [0, 1]:
+                img = gpu_run(w, tile=tile, ppt=ppt, sort_mode=mode)["img"].cpu().numpy()
+                assert np.array_equal(img, base), (tile, ppt, mode, np.abs(img - base).max())
 
 
 def test_hue_permutation_exact_and_identity_exact(R):
@@ -286,8 +285,8 @@ def test_ragged_image_sizes(R, orc, size):
     w = synth.make_tiny()
     c = synth.orbit_camera(W, H, 60.0, 3.0, 0.4, 0.3)
     w1 = synth.Workload("ragged", [w.scene], [synth.View(0, c, w.view.select, w.view.recolor)])
-    for tile in [(16, 16), (32, 8)]:
-        out = gpu_run(w1, tile=tile)
+    for tile, mode in [((16, 16), 0), ((32, 8), 0), ((8, 8), 1)]:
+        out = gpu_run(w1, tile=tile, sort_mode=mode)
         p = pull(out, w.scene.n)
         pr = orc.project(w.scene, c, tile)
         _check_integer_steps(w1, orc, p, pr, w.scene.n)
