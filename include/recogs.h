@@ -119,9 +119,9 @@ typedef struct {
     int32_t tiles_x, tiles_y;
     /* buffer offsets */
     size_t off_rec, off_bwd, off_grad, off_zbits, off_rect, off_count, off_offset, off_scan;
-    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_status;
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_count;
     size_t off_ranges, off_final_T, off_nproc, off_header;
-    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_dstatus, off_estatus, off_vstatus;
+    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_esum;
     size_t scan_chunks, sort_chunks;
     /* results of the last render, valid when it returned RECOGS_OK (or CAPACITY) */
     int64_t num_keys;            /* K: tile keys emitted */

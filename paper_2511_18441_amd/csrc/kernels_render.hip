@@ -134,94 +134,150 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, Rec
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of the tile counts, single pass with decoupled look-back. Also:
+// Exclusive scan of the tile counts, reduce-then-scan (no waiting between
+// workgroups). Besides the key offsets it produces
 //   - the compaction of the Gaussians with keys (index order kept) into
-//     (depth bits, index) pairs, the input of the depth sort, via a second
-//     look-back on the number of such Gaussians;
-//   - the depth range (min / max depth bits of Gaussians with keys): one pair of
-//     atomics per chunk.
-// The last chunk stores K (keys) and V (Gaussians with keys) in the header.
+//     (depth bits, index) pairs, the input of the depth sort;
+//   - the depth range (min / max depth bits of Gaussians with keys).
+// reduce: per chunk of 4,096 Gaussians the key count, the count of Gaussians with
+// keys and the depth range; top: one workgroup scans the chunk partials and writes
+// the totals K, V and the depth range to the header; down: per chunk, offsets and
+// compaction from the chunk's prefixes.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_scan(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
-                                              uint32_t *__restrict__ off, int64_t n, uint64_t *__restrict__ status,
-                                              uint32_t *__restrict__ vstatus, uint32_t *__restrict__ dkeys,
-                                              uint32_t *__restrict__ dvals, uint32_t *__restrict__ header,
-                                              uint32_t nchunks) {
-    __shared__ uint32_t s_chunk;
-    __shared__ uint64_t s_w[4];
-    __shared__ uint32_t s_wv[4];
-    __shared__ uint32_t s_zmn[4], s_zmx[4];
-    __shared__ uint64_t s_prefix;
-    __shared__ uint32_t s_vprefix;
-    if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_SCAN_TICKET], 1u);
-    __syncthreads();
-    const uint32_t chunk = s_chunk;
+template <typename T, int NW>
+__device__ __forceinline__ T block_excl_scan(T v, T *s_w, T &total) {
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)chunk * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems], z[kScanItems];
+    const T inc = wave_incl_scan(v);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    T pre = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const T x = s_w[k];
+        if (k < (int)w) pre += x;
+        total += x;
+    }
+    __syncthreads();
+    return pre + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
+                                                     int64_t n, uint64_t *__restrict__ pk, uint32_t *__restrict__ pv,
+                                                     uint32_t *__restrict__ pzmn, uint32_t *__restrict__ pzmx) {
+    __shared__ uint64_t s_k[4];
+    __shared__ uint32_t s_v[4], s_zmn[4], s_zmx[4];
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint64_t tsum = 0;
+    uint32_t vsum = 0, zmn = 0xffffffffu, zmx = 0u;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const uint32_t v = (base + k < n) ? cnt[base + k] : 0u;
+        tsum += v;
+        if (v) {
+            const uint32_t z = zbits[base + k];
+            zmn = min(zmn, z);
+            zmx = max(zmx, z);
+            ++vsum;
+        }
+    }
+    tsum = wave_sum(tsum);
+    vsum = wave_sum(vsum);
+    zmn = wave_min(zmn);
+    zmx = wave_max(zmx);
+    if (lane == 0) { s_k[w] = tsum; s_v[w] = vsum; s_zmn[w] = zmn; s_zmx[w] = zmx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pk[blockIdx.x] = s_k[0] + s_k[1] + s_k[2] + s_k[3];
+        pv[blockIdx.x] = s_v[0] + s_v[1] + s_v[2] + s_v[3];
+        pzmn[blockIdx.x] = min(min(s_zmn[0], s_zmn[1]), min(s_zmn[2], s_zmn[3]));
+        pzmx[blockIdx.x] = max(max(s_zmx[0], s_zmx[1]), max(s_zmx[2], s_zmx[3]));
+    }
+}
+
+// One workgroup: exclusive scans of the chunk partials in place; header gets K, V and
+// the depth range (minimum stored as its complement).
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, uint32_t *__restrict__ pv,
+                                                   const uint32_t *__restrict__ pzmn, const uint32_t *__restrict__ pzmx,
+                                                   uint32_t nchunks, uint32_t *__restrict__ header) {
+    __shared__ uint64_t s_wk[16];
+    __shared__ uint32_t s_wv[16], s_zmn[16], s_zmx[16];
+    const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    uint64_t runk = 0;
+    uint32_t runv = 0, zmn = 0xffffffffu, zmx = 0u;
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += 1024) {
+        const uint32_t c = c0 + t;
+        const uint64_t k = c < nchunks ? pk[c] : 0ull;
+        const uint32_t v = c < nchunks ? pv[c] : 0u;
+        if (c < nchunks) { zmn = min(zmn, pzmn[c]); zmx = max(zmx, pzmx[c]); }
+        uint64_t ktot;
+        uint32_t vtot;
+        const uint64_t ek = block_excl_scan<uint64_t, 16>(k, s_wk, ktot);
+        const uint32_t ev = block_excl_scan<uint32_t, 16>(v, s_wv, vtot);
+        if (c < nchunks) { pk[c] = runk + ek; pv[c] = runv + ev; }
+        runk += ktot;
+        runv += vtot;
+    }
+    zmn = wave_min(zmn);
+    zmx = wave_max(zmx);
+    if (lane == 0) { s_zmn[w] = zmn; s_zmx[w] = zmx; }
+    __syncthreads();
+    if (t == 0) {
+        for (int k = 1; k < 16; ++k) { zmn = min(zmn, s_zmn[k]); zmx = max(zmx, s_zmx[k]); }
+        zmn = min(zmn, s_zmn[0]);
+        zmx = max(zmx, s_zmx[0]);
+        header[H_K_LO] = (uint32_t)runk;
+        header[H_K_HI] = (uint32_t)(runk >> 32);
+        header[H_V] = runv;
+        header[H_ZMIN] = runv ? ~zmn : 0u;
+        header[H_ZMAX] = runv ? zmx : 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
+                                                   uint32_t *__restrict__ off, int64_t n, const uint64_t *__restrict__ pk,
+                                                   const uint32_t *__restrict__ pv, uint32_t *__restrict__ dkeys,
+                                                   uint32_t *__restrict__ dvals) {
+    __shared__ uint64_t s_wk[4];
+    __shared__ uint32_t s_wv[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
     uint64_t tsum = 0;
     uint32_t vsum = 0;
-    uint32_t zmn = 0xffffffffu, zmx = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = (base + k < n) ? cnt[base + k] : 0u;
         tsum += v[k];
-        z[k] = 0;
-        if (v[k]) {
-            z[k] = zbits[base + k];
-            zmn = min(zmn, z[k]);
-            zmx = max(zmx, z[k]);
-            ++vsum;
-        }
+        vsum += v[k] ? 1u : 0u;
     }
-    zmn = wave_min(zmn);
-    zmx = wave_max(zmx);
-    const uint64_t inc = wave_incl_scan(tsum);
-    const uint32_t vinc = wave_incl_scan(vsum);
-    if (lane == 63) { s_w[w] = inc; s_wv[w] = vinc; }
-    if (lane == 0) { s_zmn[w] = zmn; s_zmx[w] = zmx; }
-    __syncthreads();
-    uint64_t wpre = 0, total = 0;
-    uint32_t wvpre = 0, vtotal = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t x = s_w[k];
-        const uint32_t y = s_wv[k];
-        if (k < (int)w) { wpre += x; wvpre += y; }
-        total += x;
-        vtotal += y;
-    }
-    if (threadIdx.x == 0) {
-        zmn = min(min(s_zmn[0], s_zmn[1]), min(s_zmn[2], s_zmn[3]));
-        zmx = max(max(s_zmx[0], s_zmx[1]), max(s_zmx[2], s_zmx[3]));
-        if (zmx >= zmn) {  // the header keeps the minimum as its complement (zero-initialised)
-            atomicMax(&header[H_ZMIN], ~zmn);
-            atomicMax(&header[H_ZMAX], zmx);
-        }
-        const uint64_t excl = lookback<uint64_t>(status, chunk, total, kFlagAgg, kFlagInc, kFlagMask);
-        s_prefix = excl;
-        if (chunk == nchunks - 1) {
-            const uint64_t K = excl + total;
-            header[H_K_LO] = (uint32_t)K;
-            header[H_K_HI] = (uint32_t)(K >> 32);
-        }
-    } else if (threadIdx.x == 64) {
-        const uint32_t vex = lookback<uint32_t>(vstatus, chunk, vtotal, kRFlagAgg, kRFlagInc, kRFlagMask);
-        s_vprefix = vex;
-        if (chunk == nchunks - 1) header[H_V] = vex + vtotal;
-    }
-    __syncthreads();
-    uint64_t run = s_prefix + wpre + inc - tsum;
-    uint32_t vrun = s_vprefix + wvpre + vinc - vsum;
+    uint64_t ktot;
+    uint32_t vtot;
+    uint64_t run = pk[blockIdx.x] + block_excl_scan<uint64_t, 4>(tsum, s_wk, ktot);
+    uint32_t vrun = pv[blockIdx.x] + block_excl_scan<uint32_t, 4>(vsum, s_wv, vtot);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) off[base + k] = (uint32_t)run;
         run += v[k];
         if (v[k]) {
-            dkeys[vrun] = z[k];
+            dkeys[vrun] = zbits[base + k];
             dvals[vrun] = (uint32_t)(base + k);
             ++vrun;
         }
+    }
+}
+
+// One workgroup: exclusive scan in place of a u32 array of chunk partials.
+__global__ __launch_bounds__(1024) void k_scan_top_u32(uint32_t *__restrict__ a, uint32_t count) {
+    __shared__ uint32_t s_w[16];
+    uint32_t run = 0;
+    for (uint32_t c0 = 0; c0 < count; c0 += 1024) {
+        const uint32_t c = c0 + threadIdx.x;
+        const uint32_t v = c < count ? a[c] : 0u;
+        uint32_t tot;
+        const uint32_t e = block_excl_scan<uint32_t, 16>(v, s_w, tot);
+        if (c < count) a[c] = run + e;
+        run += tot;
     }
 }
 
@@ -277,53 +333,71 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
 // ---------------------------------------------------------------------------
 // Key emission in depth order: the Gaussians with keys, already sorted by (depth,
 // index), emit (tile id, index) pairs; a stable sort on the tile id then yields the
-// (tile, depth, index) order. A workgroup takes 4,096 consecutive depth-ordered
-// Gaussians (atomic ticket): wave w handles groups r = 0..15 of 64 consecutive ones.
-// The tile counts are scanned per group and across the 64 groups, the workgroup's
-// output offset comes from decoupled look-back, and each wave then writes the keys
-// of each of its groups cooperatively (one contiguous range per group: coalesced
-// stores, owner found by binary search over the group's prefix sums).
+// (tile, depth, index) order. Reduce-then-scan over chunks of 1,024 depth-ordered
+// Gaussians: k_emit_reduce sums each chunk's tile counts, k_scan_top_u32 turns the
+// sums into chunk offsets, k_emit_down writes. In k_emit_down wave w handles groups
+// r of 64 consecutive Gaussians; a group's keys form one contiguous range, written
+// cooperatively (coalesced stores, owner found by binary search over the group's
+// prefix sums).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_emit_sorted(const uint32_t *__restrict__ order, uint32_t V,
-                                                     const uint32_t *__restrict__ cnt, const uint2 *__restrict__ rect,
-                                                     int tiles_x, uint32_t *__restrict__ status,
-                                                     uint32_t *__restrict__ header, uint32_t *__restrict__ tkeys,
-                                                     uint32_t *__restrict__ tvals) {
+__global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict__ order, uint32_t V,
+                                                     const uint32_t *__restrict__ cnt, uint32_t *__restrict__ esum) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t base = blockIdx.x * (uint32_t)kEmitChunk + threadIdx.x;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kEmitItems; ++r) {
+        const uint32_t j = base + r * 256;
+        if (j < V) sum += cnt[order[j]];
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) esum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+__global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ order, uint32_t V,
+                                                   const uint32_t *__restrict__ cnt, const uint2 *__restrict__ rect,
+                                                   int tiles_x, const uint32_t *__restrict__ epre,
+                                                   uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals) {
     constexpr int R = kEmitItems;
-    __shared__ uint32_t s_chunk, s_prefix;
     __shared__ uint32_t s_gsum[4 * R];     // per-group totals, then per-group exclusive prefix
     __shared__ uint32_t s_ex[4][64];
     __shared__ uint2 s_rect[4][64];
     __shared__ uint32_t s_g[4][64];
-    if (threadIdx.x == 0) s_chunk = atomicAdd(&header[H_EMIT_TICKET], 1u);
-    __syncthreads();
-    const uint32_t chunk = s_chunk;
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-    const uint32_t j0 = chunk * (uint32_t)kEmitChunk + w * (64 * R) + lane;
-    uint32_t c[R], inc[R];
+    const uint32_t j0 = blockIdx.x * (uint32_t)kEmitChunk + w * (64 * R) + lane;
+    uint32_t c[R], inc[R], g[R];
+    uint2 rr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t j = j0 + r * 64;
-        c[r] = j < V ? cnt[order[j]] : 0u;
+        g[r] = j < V ? order[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t j = j0 + r * 64;
+        c[r] = j < V ? cnt[g[r]] : 0u;
+        rr[r] = j < V ? rect[g[r]] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         inc[r] = wave_incl_scan(c[r]);
         if (lane == 63) s_gsum[w * R + r] = inc[r];
     }
     __syncthreads();
-    if (threadIdx.x < 64) {  // exclusive scan of the 64 group totals (one wave)
-        const uint32_t v = s_gsum[threadIdx.x];
+    if (threadIdx.x < 64) {  // exclusive scan of the 4R group totals (one wave)
+        const uint32_t v = threadIdx.x < 4 * R ? s_gsum[threadIdx.x] : 0u;
         const uint32_t x = wave_incl_scan(v);
-        s_gsum[threadIdx.x] = x - v;
-        const uint32_t total = __shfl(x, 63, 64);
-        if (threadIdx.x == 0) s_prefix = lookback<uint32_t>(status, chunk, total, kRFlagAgg, kRFlagInc, kRFlagMask);
+        if (threadIdx.x < 4 * R) s_gsum[threadIdx.x] = x - v;
     }
     __syncthreads();
-    const uint32_t cbase = s_prefix;
+    const uint32_t cbase = epre[blockIdx.x];
+#pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t j = j0 + r * 64;
-        const uint32_t g = j < V ? order[j] : 0u;
         s_ex[w][lane] = inc[r] - c[r];
-        s_rect[w][lane] = c[r] ? rect[g] : make_uint2(0u, 0u);
-        s_g[w][lane] = g;
+        s_rect[w][lane] = rr[r];
+        s_g[w][lane] = g[r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -337,8 +411,8 @@ __global__ __launch_bounds__(256) void k_emit_sorted(const uint32_t *__restrict_
                 else hi = mid - 1;
             }
             const uint32_t k = q - s_ex[w][lo];
-            const uint2 rr = s_rect[w][lo];
-            const uint32_t tx0 = rr.x & 0xffffu, tx1 = rr.x >> 16, ty0 = rr.y & 0xffffu;
+            const uint2 rc = s_rect[w][lo];
+            const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
             const uint32_t wd = tx1 - tx0 + 1;
             const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
             tkeys[base + q] = ty * (uint32_t)tiles_x + tx;
@@ -519,19 +593,22 @@ void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, c
     else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
 }
 
-void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *status,
-                 uint32_t *vstatus, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, hipStream_t st) {
+void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *pk, uint32_t *pv,
+                 uint32_t *pzmn, uint32_t *pzmx, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, hipStream_t st) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, status, vstatus, dkeys, dvals, hdr,
-                       nchunks);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, hdr);
+    hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals);
 }
 
 void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint32_t *cnt, const uint2 *rect, int tiles_x,
-                        uint32_t *status, uint32_t *hdr, uint32_t *tkeys, uint32_t *tvals, hipStream_t st) {
+                        uint32_t *esum, uint32_t *tkeys, uint32_t *tvals, hipStream_t st) {
     if (V == 0) return;
-    hipLaunchKernelGGL(k_emit_sorted, dim3((V + kEmitChunk - 1) / kEmitChunk), dim3(256), 0, st, order, V, cnt, rect,
-                       tiles_x, status, hdr, tkeys, tvals);
+    const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
+    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, cnt, esum);
+    hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
+    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, cnt, rect, tiles_x, esum, tkeys, tvals);
 }
 
 void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st) {

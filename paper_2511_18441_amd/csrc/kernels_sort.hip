@@ -7,14 +7,16 @@
 //   KV_SUB        (32-bit): key - zmin
 // Both views preserve the key order among the keys of one render.
 //
-// One histogram kernel counts the digits of every pass at once; each pass is then a
-// single kernel: a workgroup takes a chunk of 4,096 keys from an atomic ticket,
-// ranks them stably per digit with wave ballots (a 64-lane match mask built from
-// one ballot per digit bit, rank = popcount of the lower lanes), publishes its
-// per-digit counts and resolves its global offsets by windowed decoupled look-back
-// over earlier chunks (relaxed agent-scope atomics: the counts are the only data
-// exchanged), then stages the chunk through LDS in digit order so global writes
-// are contiguous runs.
+// One histogram kernel counts the digits of every pass at once. Each pass is then
+// reduce-then-scan, with no waiting between workgroups:
+//   up:      per chunk of 4,096 keys, the digit counts -> matrix [digit][chunk]
+//   rowscan: one workgroup per digit scans its row (plus the digit's global base)
+//   down:    per chunk, keys are ranked stably per digit with wave ballots (a
+//            64-lane match mask built from one ballot per digit bit, rank = popcount
+//            of the lower lanes), staged through LDS in digit order and written as
+//            contiguous runs at the offsets of the matrix.
+// A single-pass "decoupled look-back" form was measured slower here: its prefix
+// frontier advances only a window of chunks per cross-XCD round trip.
 #include "recogs_internal.hpp"
 
 namespace recogs {
@@ -69,27 +71,65 @@ __global__ __launch_bounds__(256) void k_radix_hist(const KT *__restrict__ keys,
     }
 }
 
+// per-chunk digit counts -> cnt[digit * chunks + chunk]
 template <typename KT, int VIEW>
-__global__ __launch_bounds__(256) void k_radix_pass(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
+__global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, uint32_t K, uint32_t zmin, int dbits,
+                                                  int shift, int nbits, uint32_t *__restrict__ cnt, uint32_t chunks) {
+    __shared__ uint32_t h[256];
+    const uint32_t t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const uint32_t dmask = (1u << nbits) - 1u;
+    const uint32_t base = blockIdx.x * (uint32_t)kSortChunk;
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t idx = base + r * 256 + t;
+        if (idx < K) atomicAdd(&h[digit_of<KT, VIEW>(kin[idx], zmin, dbits, shift, dmask)], 1u);
+    }
+    __syncthreads();
+    if (t <= dmask) cnt[(size_t)t * chunks + blockIdx.x] = h[t];
+}
+
+// workgroup d: cnt[d][c] <- base(d) + sum_{c' < c} cnt[d][c'], base(d) = sum_{d' < d} ghist[d']
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks,
+                                                       const uint32_t *__restrict__ ghist) {
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_base;
+    const uint32_t d = blockIdx.x, t = threadIdx.x;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan256(ghist[t], s_w, tot);
+    if (t == d) s_base = ex;
+    __syncthreads();
+    uint32_t run = s_base;
+    uint32_t *row = cnt + (size_t)d * chunks;
+    for (uint32_t c0 = 0; c0 < chunks; c0 += 256) {
+        const uint32_t c = c0 + t;
+        const uint32_t v = c < chunks ? row[c] : 0u;
+        const uint32_t e = block_excl_scan256(v, s_w, tot);
+        if (c < chunks) row[c] = run + e;
+        run += tot;
+    }
+}
+
+template <typename KT, int VIEW>
+__global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     KT *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
                                                     uint32_t zmin, int dbits, int shift, int nbits,
-                                                    const uint32_t *__restrict__ ghist, uint32_t *__restrict__ status,
-                                                    uint32_t *__restrict__ ticket) {
+                                                    const uint32_t *__restrict__ off, uint32_t chunks) {
     __shared__ uint32_t s_whist[4][256];   // per-wave digit counts, then per-wave digit prefix
     __shared__ uint32_t s_gbase[256];      // global position of this chunk's first key of each digit
     __shared__ uint32_t s_lstart[256];     // position in the LDS stage of each digit
     __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_chunk;
     __shared__ KT s_keys[kSortChunk];
     __shared__ uint32_t s_vals[kSortChunk];
 
     const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const uint32_t dmask = (1u << nbits) - 1u;
-    if (t == 0) s_chunk = atomicAdd(ticket, 1u);
-    for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t chunk = s_chunk;
+    const uint32_t chunk = blockIdx.x;
     const uint32_t cbase = chunk * (uint32_t)kSortChunk;
+    for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
+    if (t <= dmask) s_gbase[t] = off[(size_t)t * chunks + chunk];
+    __syncthreads();
 
     KT key[kSortItems];
     uint32_t val[kSortItems], rank[kSortItems];
@@ -100,7 +140,7 @@ __global__ __launch_bounds__(256) void k_radix_pass(const KT *__restrict__ kin, 
         key[r] = valid ? kin[idx] : (KT)0;
         val[r] = valid ? vin[idx] : 0u;
     }
-    // stable rank within the wave, round by round
+    // stable rank within the wave, round by round (wave w holds a contiguous quarter)
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
@@ -127,45 +167,7 @@ __global__ __launch_bounds__(256) void k_radix_pass(const KT *__restrict__ kin, 
         s_whist[ww][t] = tot;
         tot += c;
     }
-    // decoupled look-back over earlier chunks for digit t
-    uint32_t excl = 0;
-    if (chunk == 0) {
-        __hip_atomic_store(&status[t], kRFlagInc | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(&status[chunk * 256 + t], kRFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // windowed look-back: kLookback predecessors loaded at once, consumed in order
-        // until an inclusive prefix is found; a not-yet-published entry ends the window
-        int64_t j = (int64_t)chunk - 1;
-        while (true) {
-            uint32_t s[kLookback];
-#pragma unroll
-            for (int k = 0; k < kLookback; ++k)
-                s[k] = (j - k >= 0) ? __hip_atomic_load(&status[(j - k) * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                    : kRFlagInc;
-            bool stop = false, done = false;
-            int used = 0;
-#pragma unroll
-            for (int k = 0; k < kLookback; ++k) {
-                if (!stop) {
-                    const uint32_t f = s[k] & kRFlagMask;
-                    if (f == 0) {
-                        stop = true;
-                    } else {
-                        excl += s[k] & ~kRFlagMask;
-                        ++used;
-                        if (f == kRFlagInc) stop = done = true;
-                    }
-                }
-            }
-            if (done) break;
-            j -= used;
-            if (used == 0) __builtin_amdgcn_s_sleep(1);
-        }
-        __hip_atomic_store(&status[chunk * 256 + t], kRFlagInc | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     uint32_t total;
-    const uint32_t gpre = block_excl_scan256(ghist[t], s_w, total);
-    s_gbase[t] = gpre + excl;
     s_lstart[t] = block_excl_scan256(tot, s_w, total);
     __syncthreads();
 #pragma unroll
@@ -192,15 +194,14 @@ __global__ __launch_bounds__(256) void k_radix_pass(const KT *__restrict__ kin, 
 // ---------------------------------------------------------------------------
 // Host side: sort K (key, value) pairs across the two buffers over `total_bits`
 // significant bits (passes of equal width, <= 8 bits each). Returns 1 if the result
-// is in the alternate buffers (kb/vb), 0 if in ka/va. `status` holds
-// passes x ceil(K/4096) x 256 zeroed words, `ghist` 8 x 256 zeroed words, `tickets`
-// one zeroed word per pass.
+// is in the alternate buffers (kb/vb), 0 if in ka/va. `ghist` holds 8 x 256 zeroed
+// words; `cnt` 256 x ceil(K / 4096) words of scratch.
 // ---------------------------------------------------------------------------
 int sort_passes(int total_bits) { return (total_bits + 7) / 8; }
 
 template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
-                      uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
+                      uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
     if (K == 0 || total_bits == 0) return 0;
     const int passes = sort_passes(total_bits);
     const int per = (total_bits + passes - 1) / passes;
@@ -222,8 +223,11 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         const uint32_t *vin = alt ? vb : va;
         KT *kout = alt ? ka : kb;
         uint32_t *vout = alt ? va : vb;
-        hipLaunchKernelGGL((k_radix_pass<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits,
-                           shift, nb, ghist + 256 * p, status + (size_t)256 * chunks * p, tickets + p);
+        hipLaunchKernelGGL((k_radix_up<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,
+                           chunks);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, ghist + 256 * p);
+        hipLaunchKernelGGL((k_radix_down<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits,
+                           shift, nb, cnt, chunks);
         alt ^= 1;
         shift += nb;
     }
@@ -231,13 +235,13 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
 }
 
 int radix_sort_tile_depth64(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits,
-                            int total_bits, uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
-    return radix_sort<uint64_t, KV_TILE_DEPTH>(ka, va, kb, vb, K, zmin, dbits, total_bits, ghist, status, tickets, st);
+                            int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
+    return radix_sort<uint64_t, KV_TILE_DEPTH>(ka, va, kb, vb, K, zmin, dbits, total_bits, ghist, cnt, st);
 }
 
 int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K, uint32_t sub, int total_bits,
-                   uint32_t *ghist, uint32_t *status, uint32_t *tickets, hipStream_t st) {
-    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, status, tickets, st);
+                   uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st);
 }
 
 }  // namespace recogs

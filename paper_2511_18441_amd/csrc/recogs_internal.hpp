@@ -152,27 +152,17 @@ struct RecolorDev {
 // Workspace header words (u32), zeroed before each render.
 enum : int {
     H_K_LO = 0, H_K_HI = 1,      // number of keys (64-bit)
-    H_ZMIN = 2, H_ZMAX = 3,      // min/max float32 depth bits among splats with keys
-    H_SCAN_TICKET = 4,
-    H_V = 5,                     // number of Gaussians with keys
-    H_EMIT_TICKET = 6,
-    H_SORT_TICKET = 8,           // 8 words, one per pass of the key sort
-    H_DSORT_TICKET = 16,         // 8 words, one per pass of the depth sort
+    H_ZMIN = 2, H_ZMAX = 3,      // complement of min / max float32 depth bits among splats with keys
+    H_V = 4,                     // number of Gaussians with keys
     H_WORDS = 64
 };
-
-// status words of decoupled look-back (scan): flag in the top 2 bits
-constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kFlagMask = 3ull << 62;
-// status words of the radix passes (u32): flag in the top 2 bits, count below
-constexpr uint32_t kRFlagAgg = 1u << 30, kRFlagInc = 2u << 30, kRFlagMask = 3u << 30;
 
 constexpr int kScanItems = 16;                       // counts per thread of the scan
 constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
 constexpr int kSortItems = 16;                       // keys per thread per radix pass
 constexpr int kSortChunk = 256 * kSortItems;         // keys per radix workgroup
 constexpr int kMaxPasses = 8;
-constexpr int kLookback = 16;                        // predecessors read per look-back step
-constexpr int kEmitItems = 1;                        // groups of 64 per wave in the depth-ordered emission
+constexpr int kEmitItems = 4;                        // groups of 64 per wave in the depth-ordered emission
 constexpr int kEmitChunk = 256 * kEmitItems;         // depth-ordered Gaussians per emission workgroup
 
 // Per-Gaussian splat record for compositing: three float4
@@ -180,50 +170,6 @@ constexpr int kEmitChunk = 256 * kEmitItems;         // depth-ordered Gaussians 
 //   r1 = (A, B, C, o)     log2(alpha) = o + A dx^2 + B dx dy + C dy^2
 //   r2 = (r, g, b, sigma) clamped colour, activated opacity
 struct SplatRec { float4 r0, r1, r2; };
-
-// Windowed decoupled look-back for one value (chunk > 0): publishes `agg` as the
-// chunk's aggregate, reads kLookback predecessors at once and consumes them in order
-// until an inclusive prefix is found (a not-yet-published entry ends the window),
-// then publishes the inclusive prefix and returns the exclusive one. Chunk ids come
-// from an atomic ticket, so every predecessor is already running. Relaxed
-// agent-scope atomics: the status words are the only data exchanged, and release /
-// acquire at agent scope would write back / invalidate the XCD's L2.
-template <typename W>
-__device__ __forceinline__ W lookback(W *status, uint32_t chunk, W agg, W flag_agg, W flag_inc, W flag_mask) {
-    if (chunk == 0) {
-        __hip_atomic_store(&status[0], flag_inc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0;
-    }
-    __hip_atomic_store(&status[chunk], flag_agg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    W excl = 0;
-    int64_t j = (int64_t)chunk - 1;
-    while (true) {
-        W s[kLookback];
-#pragma unroll
-        for (int k = 0; k < kLookback; ++k)
-            s[k] = (j - k >= 0) ? __hip_atomic_load(&status[j - k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : flag_inc;
-        bool stop = false, done = false;
-        int used = 0;
-#pragma unroll
-        for (int k = 0; k < kLookback; ++k) {
-            if (!stop) {
-                const W f = s[k] & flag_mask;
-                if (f == 0) {
-                    stop = true;
-                } else {
-                    excl += s[k] & ~flag_mask;
-                    ++used;
-                    if (f == flag_inc) stop = done = true;
-                }
-            }
-        }
-        if (done) break;
-        j -= used;
-        if (used == 0) __builtin_amdgcn_s_sleep(1);
-    }
-    __hip_atomic_store(&status[chunk], flag_inc | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return excl;
-}
 
 // key layout: (tile << 32) | float32 depth bits
 __device__ __forceinline__ uint64_t sort_view(uint64_t key, uint32_t zmin, int dbits) {

@@ -17,20 +17,20 @@ void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
                        uint32_t *, uint2 *, uint32_t *, uint32_t *, hipStream_t);
 void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
-                 uint32_t *, hipStream_t);
+                 uint32_t *, uint32_t *, uint32_t *, hipStream_t);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint32_t *, const uint2 *, int, uint32_t *, uint32_t *,
-                        uint32_t *, uint32_t *, hipStream_t);
+                        uint32_t *, hipStream_t);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                   float *, float *, uint32_t *, hipStream_t);
 int sort_passes(int total_bits);
 int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
-                            uint32_t *, uint32_t *, hipStream_t);
+                            uint32_t *, hipStream_t);
 int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                   uint32_t *, hipStream_t);
+                   hipStream_t);
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                       const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
@@ -98,17 +98,16 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     ws->off_dkeys1 = take(4 * nn);
     ws->off_dvals0 = take(4 * nn);
     ws->off_dvals1 = take(4 * nn);
-    // zeroed before the preprocess: header, scan status, compaction status
+    // scan partials per chunk: key count (u64), count with keys, depth min, depth max
+    ws->off_scan = take(20 * (size_t)scan_chunks);
+    ws->off_esum = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
+    // radix digit-count matrix [256][chunks], shared by the depth sort and the key sort
+    const int64_t cnt_chunks = sort_chunks > (nn + kSortChunk - 1) / kSortChunk ? sort_chunks : (nn + kSortChunk - 1) / kSortChunk;
+    ws->off_sort_count = take(4 * 256 * (size_t)(cnt_chunks > 0 ? cnt_chunks : 1));
+    // zeroed each render: header; histograms; tile ranges
     ws->off_header = take(4 * H_WORDS);
-    ws->off_scan = take(8 * (size_t)scan_chunks);
-    ws->off_vstatus = take(4 * (size_t)scan_chunks);
-    // zeroed after the key count is known (only the part in use): histograms, look-back
-    // status of the sorts and of the depth-ordered emission, tile ranges
     ws->off_hist = take(4 * 256 * kMaxPasses);
     ws->off_dhist = take(4 * 256 * kMaxPasses);
-    ws->off_sort_status = take(4 * 256 * (size_t)kMaxPasses * (size_t)(sort_chunks > 0 ? sort_chunks : 1));
-    ws->off_dstatus = take(4 * 256 * (size_t)4 * (size_t)((nn + kSortChunk - 1) / kSortChunk));
-    ws->off_estatus = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
     ws->off_ranges = take(8 * (size_t)T);
     ws->scan_chunks = (size_t)scan_chunks;
     ws->sort_chunks = (size_t)sort_chunks;
@@ -324,13 +323,18 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     const int mode = opts->sort_mode;
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
     uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
-    // zero header, scan status and compaction status (contiguous)
-    launch_fill_u32(hdr, 0u, (int64_t)((ws->off_hist - ws->off_header) / 4), stream);
+    // zero the header
+    launch_fill_u32(hdr, 0u, H_WORDS, stream);
     RecolorDev rc{opts->mask, opts->M, opts->b};
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
                       rect, cnt, hdr, stream);
     if ((s = tm.mark(1)) != RECOGS_OK) return s;
-    launch_scan(cnt, zb, off, n, at<uint64_t>(ws, ws->off_scan), at<uint32_t>(ws, ws->off_vstatus), dk0, dv0, hdr, stream);
+    {
+        const size_t sc_n = ws->scan_chunks;
+        uint64_t *pk = at<uint64_t>(ws, ws->off_scan);
+        uint32_t *pv = (uint32_t *)(pk + sc_n);
+        launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, stream);
+    }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
 
@@ -358,39 +362,29 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     ws->depth_passes = (mode == 0 && V) ? sort_passes(dbits) : 0;
     ws->key_bytes = mode == 0 ? 4 : 8;
 
-    // zero what the sorts, the emission and the ranges use
-    const uint32_t chunks = (uint32_t)((K + kSortChunk - 1) / kSortChunk);
-    const uint32_t vchunks = (V + kSortChunk - 1) / kSortChunk;
+    // zero the histograms (adjacent) and the tile ranges
     uint32_t *hist = at<uint32_t>(ws, ws->off_hist), *dhist = at<uint32_t>(ws, ws->off_dhist);
-    uint32_t *sstat = at<uint32_t>(ws, ws->off_sort_status), *dstat = at<uint32_t>(ws, ws->off_dstatus);
-    launch_fill_u32(hist, 0u, 2 * 256 * kMaxPasses, stream);  // hist and dhist are adjacent
-    launch_fill_u32(sstat, 0u, (int64_t)256 * chunks * ws->sort_passes, stream);
-    if (mode == 0) {
-        launch_fill_u32(dstat, 0u, (int64_t)256 * vchunks * ws->depth_passes, stream);
-        launch_fill_u32(at<uint32_t>(ws, ws->off_estatus), 0u, (V + kEmitChunk - 1) / kEmitChunk, stream);
-    }
-    launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)ntiles, stream);
+    uint32_t *scount = at<uint32_t>(ws, ws->off_sort_count);
+    launch_fill_u32(hist, 0u, (int64_t)((ws->off_ranges - ws->off_hist) / 4) + 2 * (int64_t)ntiles, stream);
 
     uint64_t *k0 = at<uint64_t>(ws, ws->off_keys0), *k1 = at<uint64_t>(ws, ws->off_keys1);
     uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
     int alt = 0;
     if (K > 0 && mode == 0) {
         // depth sort of the V Gaussians with keys (compacted in index order by the scan)
-        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, dstat, hdr + H_DSORT_TICKET, stream);
+        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, scount, stream);
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
-        launch_emit_sorted(dalt ? dv1 : dv0, V, cnt, rect, cd.tiles_x, at<uint32_t>(ws, ws->off_estatus), hdr, t0, v0,
-                           stream);
+        launch_emit_sorted(dalt ? dv1 : dv0, V, cnt, rect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, sstat, hdr + H_SORT_TICKET, stream);
+        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream);
     } else if (K > 0) {
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        alt = radix_sort_tile_depth64(k0, v0, k1, v1, (uint32_t)K, zmin, dbits, key_bits, hist, sstat,
-                                      hdr + H_SORT_TICKET, stream);
+        alt = radix_sort_tile_depth64(k0, v0, k1, v1, (uint32_t)K, zmin, dbits, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges(alt ? k1 : k0, (uint32_t)K, ranges, stream);
     } else {
