@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, nargs=2, default=[16, 16])
-    ap.add_argument("--ppt", type=int, default=1)
+    ap.add_argument("--ppt", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")

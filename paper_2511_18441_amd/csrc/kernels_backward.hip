@@ -16,34 +16,24 @@
 namespace recogs {
 
 template <int TW, int TH, int PPT>
-__device__ __forceinline__ void bwd_thread_pixel(int t, int &lx, int &lrow) {
-    if constexpr (TW % 8 == 0 && (TH / PPT) % 8 == 0) {
-        const int w = t >> 6, l = t & 63;
-        constexpr int WC = TW / 8;
-        lx = (w % WC) * 8 + (l & 7);
-        lrow = (w / WC) * 8 + (l >> 3);
-    } else {
-        lx = t % TW;
-        lrow = t / TW;
-    }
-}
-
-template <int TW, int TH, int PPT>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                            const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                            const float *__restrict__ image, const float *__restrict__ dldy,
                                                            const uint32_t *__restrict__ nproc,
                                                            float4 *__restrict__ acc) {
 #pragma clang fp contract(off)
-    constexpr int NT = TW * TH / PPT;
+    using Map = TileMap<TW, TH, PPT>;
+    constexpr int NT = Map::NT;
     constexpr int BATCH = 256;
     __shared__ float4 s_r0[BATCH], s_r1[BATCH], s_r2[BATCH];
     __shared__ uint32_t s_gid[BATCH];
+    __shared__ uint8_t s_mask[BATCH];
     const int tile = blockIdx.x;
     const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
     const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(Map::wave(t));
     int lx, lrow;
-    bwd_thread_pixel<TW, TH, PPT>(t, lx, lrow);
+    Map::pixel(t, lx, lrow);
     const int px = tx0 + lx;
     const float pxc = (float)px + 0.5f;
     float pyc[PPT], T[PPT], A0[PPT], A1[PPT], A2[PPT], y0[PPT], y1[PPT], y2[PPT], g0[PPT], g1[PPT], g2[PPT];
@@ -76,6 +66,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const SplatRec s = rec[gid];
                 s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
                 s_gid[q] = gid;
+                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
             }
         }
         __syncthreads();
@@ -83,14 +74,16 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
         for (int q = 0; q < nb; ++q) {
             const uint32_t krel = start + q - rg.x;
             if (!wave_ballot(krel < npmax)) break;
+            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
+            if (!((m >> w) & 1u)) continue;
             const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
+            const ExpRow er = exp_row(r1, pxc - r0.x);
             float ds = 0.f, dr = 0.f, dg = 0.f, db = 0.f;
             bool any = false;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 if (krel >= np[j]) continue;
-                const float dx = pxc - r0.x, dy = pyc[j] - r0.y;
-                const float e = __builtin_fmaf(dx, __builtin_fmaf(r1.x, dx, r1.y * dy), __builtin_fmaf(r1.z * dy, dy, r1.w));
+                const float e = exp_at(er, r1, pyc[j] - r0.y);
                 if (e < kLog2AlphaMin) continue;
                 const float araw = __builtin_amdgcn_exp2f(e);
                 const float a = fminf(kAlphaMax, araw);

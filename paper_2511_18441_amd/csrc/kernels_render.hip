@@ -340,15 +340,26 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
 // cooperatively (coalesced stores, owner found by binary search over the group's
 // prefix sums).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rect_count(uint2 r) {
+    return ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
+}
+
+// also gathers each depth-ordered Gaussian's tile rectangle once (srect, coalesced
+// for k_emit_down); every Gaussian in the order has at least one key
 __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict__ order, uint32_t V,
-                                                     const uint32_t *__restrict__ cnt, uint32_t *__restrict__ esum) {
+                                                     const uint2 *__restrict__ rect, uint2 *__restrict__ srect,
+                                                     uint32_t *__restrict__ esum) {
     __shared__ uint32_t s_w[4];
     const uint32_t base = blockIdx.x * (uint32_t)kEmitChunk + threadIdx.x;
     uint32_t sum = 0;
 #pragma unroll
     for (int r = 0; r < kEmitItems; ++r) {
         const uint32_t j = base + r * 256;
-        if (j < V) sum += cnt[order[j]];
+        if (j < V) {
+            const uint2 rc = rect[order[j]];
+            srect[j] = rc;
+            sum += rect_count(rc);
+        }
     }
     sum = wave_sum(sum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
@@ -357,9 +368,9 @@ __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict_
 }
 
 __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ order, uint32_t V,
-                                                   const uint32_t *__restrict__ cnt, const uint2 *__restrict__ rect,
-                                                   int tiles_x, const uint32_t *__restrict__ epre,
-                                                   uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals) {
+                                                   const uint2 *__restrict__ srect, int tiles_x,
+                                                   const uint32_t *__restrict__ epre, uint32_t *__restrict__ tkeys,
+                                                   uint32_t *__restrict__ tvals) {
     constexpr int R = kEmitItems;
     __shared__ uint32_t s_gsum[4 * R];     // per-group totals, then per-group exclusive prefix
     __shared__ uint32_t s_ex[4][64];
@@ -377,8 +388,8 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t j = j0 + r * 64;
-        c[r] = j < V ? cnt[g[r]] : 0u;
-        rr[r] = j < V ? rect[g[r]] : make_uint2(0u, 0u);
+        rr[r] = j < V ? srect[j] : make_uint2(0u, 0u);
+        c[r] = j < V ? rect_count(rr[r]) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -443,42 +454,32 @@ __global__ __launch_bounds__(256) void k_ranges(const uint64_t *__restrict__ key
 }
 
 // ---------------------------------------------------------------------------
-// Blend (eq. 3), one workgroup per tile, PPT vertically stacked pixels per thread.
-// Workgroup threads form waves that each cover a compact 8 x (8 PPT) pixel block
-// where the tile allows it; a wave skips a splat whose alpha >= 1/255 box misses all
-// of its pixel centres (exact: outside the box alpha < 1/255 holds with margin).
-// Splat records are staged through LDS in batches; a pixel stops when blending the
-// next splat would drop transmittance below 1e-4; the workgroup stops when all of
+// Blend (eq. 3), one workgroup per tile (see TileMap for the thread -> pixel map).
+// Splat records of the tile's sorted list are staged through LDS in batches; while
+// staging, each record gets a bit mask of the wave regions its alpha >= 1/255 box
+// meets, so a wave skips a splat with one scalar test. Per pixel: alpha =
+// min(0.99, 2^e) with e from exp_row/exp_at, skipped below 1/255; the pixel stops
+// when blending would drop transmittance below 1e-4; the workgroup stops when all
 // its pixels have. Output HWC image, final transmittance and, per pixel, the count
 // of tile-list entries up to and including the last blended one.
 // ---------------------------------------------------------------------------
-template <int TW, int TH, int PPT>
-__device__ __forceinline__ void thread_pixel(int t, int &lx, int &lrow) {
-    if constexpr (TW % 8 == 0 && (TH / PPT) % 8 == 0) {
-        const int w = t >> 6, l = t & 63;
-        constexpr int WC = TW / 8;
-        lx = (w % WC) * 8 + (l & 7);
-        lrow = (w / WC) * 8 + (l >> 3);
-    } else {
-        lx = t % TW;
-        lrow = t / TW;
-    }
-}
-
 template <int TW, int TH, int PPT>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                        const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                        float bg0, float bg1, float bg2, float *__restrict__ image,
                                                        float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
 #pragma clang fp contract(off)
-    constexpr int NT = TW * TH / PPT;
+    using Map = TileMap<TW, TH, PPT>;
+    constexpr int NT = Map::NT;
     constexpr int BATCH = 256;
     __shared__ float4 s_r0[BATCH], s_r1[BATCH], s_r2[BATCH];
+    __shared__ uint8_t s_mask[BATCH];
     const int tile = blockIdx.x;
     const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
     const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(Map::wave(t));
     int lx, lrow;
-    thread_pixel<TW, TH, PPT>(t, lx, lrow);
+    Map::pixel(t, lx, lrow);
     const int px = tx0 + lx;
     const float pxc = (float)px + 0.5f;
     float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
@@ -490,21 +491,6 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict_
         pyc[j] = (float)py + 0.5f;
         T[j] = 1.f; C0[j] = C1[j] = C2[j] = 0.f; last[j] = 0;
         done[j] = !(px < W && py < H);
-    }
-    // pixel-centre bounds of this wave (of the whole tile when waves are not blocks)
-    float wx0, wx1, wy0, wy1;
-    if constexpr (TW % 8 == 0 && (TH / PPT) % 8 == 0) {
-        const int w = t >> 6;
-        constexpr int WC = TW / 8;
-        wx0 = (float)(tx0 + (w % WC) * 8) + 0.5f;
-        wx1 = wx0 + 7.f;
-        wy0 = (float)(ty0 + (w / WC) * 8 * PPT) + 0.5f;
-        wy1 = wy0 + (float)(8 * PPT - 1);
-    } else {
-        wx0 = (float)tx0 + 0.5f;
-        wx1 = wx0 + (float)(TW - 1);
-        wy0 = (float)ty0 + 0.5f;
-        wy1 = wy0 + (float)(TH - 1);
     }
 
     const uint2 rg = ranges[tile];
@@ -518,23 +504,26 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict_
             if (k < rg.y) {
                 const SplatRec s = rec[vals[k]];
                 s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
+                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
             }
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
+        const uint32_t krel0 = start + 1 - rg.x;
         for (int q = 0; q < nb; ++q) {
             bool alive = false;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) alive = alive || !done[j];
             if (!wave_ballot(alive)) break;
-            const float4 r0 = s_r0[q];
-            if (r0.x + r0.z < wx0 || r0.x - r0.z > wx1 || r0.y + r0.w < wy0 || r0.y - r0.w > wy1) continue;
-            const float4 r1 = s_r1[q], r2 = s_r2[q];
+            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
+            if (!((m >> w) & 1u)) continue;
+            const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
+            const ExpRow er = exp_row(r1, pxc - r0.x);
+            const uint32_t kq = krel0 + (uint32_t)q;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 if (done[j]) continue;
-                const float dx = pxc - r0.x, dy = pyc[j] - r0.y;
-                const float e = __builtin_fmaf(dx, __builtin_fmaf(r1.x, dx, r1.y * dy), __builtin_fmaf(r1.z * dy, dy, r1.w));
+                const float e = exp_at(er, r1, pyc[j] - r0.y);
                 if (e < kLog2AlphaMin) continue;
                 const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
                 const float Tn = T[j] * (1.f - a);
@@ -544,7 +533,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict_
                 C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
                 C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
                 T[j] = Tn;
-                last[j] = start + q + 1 - rg.x;
+                last[j] = kq;
             }
         }
     }
@@ -602,13 +591,13 @@ void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int6
     hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals);
 }
 
-void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint32_t *cnt, const uint2 *rect, int tiles_x,
+void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, uint2 *srect, int tiles_x,
                         uint32_t *esum, uint32_t *tkeys, uint32_t *tvals, hipStream_t st) {
     if (V == 0) return;
     const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
-    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, cnt, esum);
+    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum);
     hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
-    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, cnt, rect, tiles_x, esum, tkeys, tvals);
+    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, srect, tiles_x, esum, tkeys, tvals);
 }
 
 void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st) {

@@ -171,6 +171,72 @@ constexpr int kEmitChunk = 256 * kEmitItems;         // depth-ordered Gaussians 
 //   r2 = (r, g, b, sigma) clamped colour, activated opacity
 struct SplatRec { float4 r0, r1, r2; };
 
+// ---------------------------------------------------------------------------
+// Thread -> pixel map of the blend kernels (forward and backward): a workgroup of
+// TW*TH/PPT threads covers one TW x TH tile, each thread PPT vertically stacked
+// pixels. Where the tile allows it, each wave covers a compact 8 x (8 PPT) block
+// ("wave region"); otherwise the wave region is the whole tile.
+// ---------------------------------------------------------------------------
+template <int TW, int TH, int PPT> struct TileMap {
+    static constexpr int NT = TW * TH / PPT;
+    static constexpr bool BLOCKS = (TW % 8 == 0) && ((TH / PPT) % 8 == 0);
+    static constexpr int NW = BLOCKS ? NT / 64 : 1;
+    static __device__ __forceinline__ void pixel(int t, int &lx, int &lrow) {
+        if constexpr (BLOCKS) {
+            const int w = t >> 6, l = t & 63;
+            lx = (w % (TW / 8)) * 8 + (l & 7);
+            lrow = (w / (TW / 8)) * 8 + (l >> 3);
+        } else {
+            lx = t % TW;
+            lrow = t / TW;
+        }
+    }
+    static __device__ __forceinline__ int wave(int t) { return BLOCKS ? (t >> 6) : 0; }
+    // pixel-centre bounds of wave region w, relative to the tile origin
+    static __device__ __forceinline__ void bounds(int w, float &x0, float &x1, float &y0, float &y1) {
+        if constexpr (BLOCKS) {
+            x0 = (float)((w % (TW / 8)) * 8) + 0.5f;
+            x1 = x0 + 7.f;
+            y0 = (float)((w / (TW / 8)) * 8 * PPT) + 0.5f;
+            y1 = y0 + (float)(8 * PPT - 1);
+        } else {
+            x0 = 0.5f; x1 = (float)TW - 0.5f;
+            y0 = 0.5f; y1 = (float)TH - 0.5f;
+        }
+    }
+    // bit w set when the splat's alpha >= 1/255 box (centre u, v, half-extents ex, ey)
+    // meets a pixel centre of wave region w. Outside the box q exceeds 2 ln(255 sigma)
+    // + 1/64, so alpha < 1/255 there by a margin far above float32 error: skipping is exact.
+    static __device__ __forceinline__ uint32_t wave_mask(float4 r0, float tx0, float ty0) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            float x0, x1, y0, y1;
+            bounds(w, x0, x1, y0, y1);
+            const bool hit = !(r0.x + r0.z < tx0 + x0 || r0.x - r0.z > tx0 + x1 || r0.y + r0.w < ty0 + y0 ||
+                               r0.y - r0.w > ty0 + y1);
+            m |= (hit ? 1u : 0u) << w;
+        }
+        return m;
+    }
+};
+
+// log2(alpha) of a splat at pixel-centre offset (dx, dy) from its centre, with the same
+// float32 operations in forward and backward (they must take identical threshold
+// decisions). Factored so the PPT pixels of a thread, which share dx, share work:
+//   e = dy (C dy + B dx) + (A dx^2 + o),   r1 = (A, B, C, o).
+struct ExpRow { float ax, bx; };
+__device__ __forceinline__ ExpRow exp_row(float4 r1, float dx) {
+#pragma clang fp contract(off)
+    ExpRow r;
+    r.ax = __builtin_fmaf(r1.x * dx, dx, r1.w);
+    r.bx = r1.y * dx;
+    return r;
+}
+__device__ __forceinline__ float exp_at(ExpRow r, float4 r1, float dy) {
+    return __builtin_fmaf(dy, __builtin_fmaf(r1.z, dy, r.bx), r.ax);
+}
+
 // key layout: (tile << 32) | float32 depth bits
 __device__ __forceinline__ uint64_t sort_view(uint64_t key, uint32_t zmin, int dbits) {
     return ((key >> 32) << dbits) | (uint64_t)((uint32_t)key - zmin);

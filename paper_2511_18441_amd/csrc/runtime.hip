@@ -20,8 +20,8 @@ void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64
                  uint32_t *, uint32_t *, uint32_t *, hipStream_t);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
-void launch_emit_sorted(const uint32_t *, uint32_t, const uint32_t *, const uint2 *, int, uint32_t *, uint32_t *,
-                        uint32_t *, hipStream_t);
+void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
+                        hipStream_t);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
@@ -375,7 +375,10 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, scount, stream);
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
-        launch_emit_sorted(dalt ? dv1 : dv0, V, cnt, rect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream);
+        // the depth-ordered rectangles (8 bytes each) reuse both depth-key buffers, which are
+        // adjacent and no longer needed once the order (values) is known
+        uint2 *srect = (uint2 *)dk0;
+        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
