@@ -206,6 +206,69 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
+/* ---- batched form ------------------------------------------------------------ */
+
+/* One render of a batch (host struct): a scene, a camera, an optional fused recolour
+ * (device mask uint8 [scene.n], M float [9], b float [3]; all NULL = none) and the
+ * output image float [H][W][3] (device). Views may share scenes. */
+typedef struct {
+    recogs_scene scene;
+    recogs_camera cam;
+    const uint8_t *mask;
+    const float *M;
+    const float *b;
+    float *image;
+} recogs_batch_view;
+
+/* Batch workspace: device memory carved by recogs_batch_init (filled by the library). */
+typedef struct {
+    void *base;
+    size_t bytes;
+    int32_t nviews, tile_w, tile_h, px_per_thread;
+    int32_t storage, sh_degree;
+    int64_t pairs;               /* sum over views of the scene sizes */
+    int64_t tiles;               /* sum over views of the tile counts */
+    int64_t key_capacity;
+    int32_t tile_bits;           /* significant bits of the global tile ids */
+    int32_t persistent_blocks;   /* workgroups of the persistent blend */
+    uint32_t preprocess_blocks;
+    int32_t reserved;
+    size_t off_views, off_vtab, off_rec, off_zbits, off_rect, off_count, off_offset;
+    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_scan, off_esum, off_sort_count;
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_header, off_hist, off_dhist, off_ranges, off_order;
+    size_t scan_chunks;
+    /* filled by recogs_batch_readback */
+    int64_t num_keys;            /* keys the batch needs */
+    int64_t num_visible;         /* (view, Gaussian) pairs with keys */
+    int32_t overflow;            /* 1: num_keys > key_capacity, nothing was rendered */
+    int32_t sorted_in_alt;
+} recogs_batch_workspace;
+
+/* Bytes for a batch of these views with the given tile shape and key capacity
+ * (0 on invalid arguments). */
+size_t recogs_batch_workspace_bytes(const recogs_batch_view *views /* host [nviews] */, int32_t nviews,
+                                    int32_t tile_w, int32_t tile_h, int64_t key_capacity);
+
+/* Carve dev_mem for the batch and upload its view table (a synchronous copy; the views'
+ * device pointers are captured here and used by every recogs_render_batch call).
+ * opts: tile shape, px_per_thread and background; all views must share the storage
+ * dtype and SH degree of their scenes. Errors: INVALID / UNSUPPORTED / HIP. */
+recogs_status recogs_batch_init(recogs_batch_workspace *ws, void *dev_mem, size_t bytes,
+                                const recogs_batch_view *views, int32_t nviews, const recogs_render_opts *opts,
+                                int64_t key_capacity);
+
+/* Render every view of the batch (an analog of the paper's concurrent editor streams,
+ * Sec. 4): one preprocess over all (view, Gaussian) pairs, one count scan, one depth
+ * sort, one emission of global tile keys, one tile sort, one persistent blend whose
+ * workgroups take tiles largest-list-first from an atomic queue. Enqueues work only:
+ * no host synchronisation, no allocation, no memset nodes -- the call can be captured
+ * in a HIP graph and replayed. When the keys exceed the capacity nothing is drawn and
+ * the overflow flag is set (see recogs_batch_readback). */
+recogs_status recogs_render_batch(const recogs_batch_workspace *ws, hipStream_t stream);
+
+/* Synchronises `stream` and reads the key count and overflow flag of the last batch. */
+recogs_status recogs_batch_readback(recogs_batch_workspace *ws, hipStream_t stream);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *recogs_last_error(void);
 

@@ -1,0 +1,121 @@
+"""Autotuner of the blend launch shape: tile (8x8, 16x16, 32x8) x pixels per thread
+(1, 2, 4).
+
+For a workload it times every candidate (HIP-graph replays of the batch, or eager
+renders of one view), checks that every candidate's images are bit-identical to the
+first one's (the tile lists and the per-pixel arithmetic do not depend on the launch
+shape, so any difference is a bug), and returns the fastest. Results are cached in a
+JSON file keyed by the device name and the workload's shape.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+CANDIDATES: Tuple[Tuple[Tuple[int, int], int], ...] = tuple(
+    ((tw, th), p) for (tw, th) in ((16, 16), (32, 8), (8, 8)) for p in (1, 2, 4))
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "recogs_autotune.json")
+
+
+def _signature(kind: str, parts: Sequence) -> str:
+    import torch
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    h = hashlib.sha1(json.dumps([kind, name, list(map(str, parts))]).encode()).hexdigest()[:16]
+    return f"{kind}:{h}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, key, value):
+    d = _load(path)
+    d[key] = value
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1)
+    os.replace(tmp, path)
+
+
+def tune_batch(dscenes, views, candidates=CANDIDATES, reps: int = 5, cache: Optional[str] = DEFAULT_CACHE,
+               bg=(0.0, 0.0, 0.0)) -> Dict:
+    """Pick (tile, px_per_thread) for a batch. `views` as for DeviceBatch. Returns
+    {"tile": [w, h], "ppt": p, "ms": t, "table": [...]}; raises if candidates disagree."""
+    import torch
+
+    from .binding import DeviceBatch
+    sig = _signature("batch", [(d.n, d.storage, d.sh_degree) for d in dscenes] +
+                     [(s, c.width, c.height) for (s, c, *_r) in views] + [list(candidates)])
+    if cache:
+        hit = _load(cache).get(sig)
+        if hit:
+            return hit
+    ref: Optional[List] = None
+    table = []
+    for tile, ppt in candidates:
+        b = DeviceBatch(dscenes, views, tile, ppt, bg)
+        g = b.capture_graph()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        imgs = [im.clone() for im in b.images]
+        if ref is None:
+            ref = imgs
+        elif not all(torch.equal(a, r) for a, r in zip(imgs, ref)):
+            raise RuntimeError(f"autotune: tile {tile} ppt {ppt} changed the output bits")
+        table.append({"tile": list(tile), "ppt": ppt, "ms": round(ms, 4)})
+        del g, b
+    best = min(table, key=lambda r: r["ms"])
+    res = {"tile": best["tile"], "ppt": best["ppt"], "ms": best["ms"], "table": table, "tuned_at": time.time()}
+    if cache:
+        _store(cache, sig, res)
+    return res
+
+
+def tune_render(dscene, cam, candidates=CANDIDATES, reps: int = 10, cache: Optional[str] = DEFAULT_CACHE) -> Dict:
+    """Pick (tile, px_per_thread) for single-view renders of one scene and camera size."""
+    import torch
+
+    from .binding import DeviceWorkspace, render
+    sig = _signature("render", [dscene.n, dscene.storage, dscene.sh_degree, cam.width, cam.height, list(candidates)])
+    if cache:
+        hit = _load(cache).get(sig)
+        if hit:
+            return hit
+    ref = None
+    table = []
+    for tile, ppt in candidates:
+        ws = DeviceWorkspace(dscene.n, cam.width, cam.height, tile)
+        img = render(dscene, cam, ws, tile, ppt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            render(dscene, cam, ws, tile, ppt, image=img)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / reps
+        out = img.clone()
+        if ref is None:
+            ref = out
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"autotune: tile {tile} ppt {ppt} changed the output bits")
+        table.append({"tile": list(tile), "ppt": ppt, "ms": round(ms, 4)})
+    best = min(table, key=lambda r: r["ms"])
+    res = {"tile": best["tile"], "ppt": best["ppt"], "ms": best["ms"], "table": table, "tuned_at": time.time()}
+    if cache:
+        _store(cache, sig, res)
+    return res

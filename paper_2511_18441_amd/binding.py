@@ -341,3 +341,131 @@ def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, 
         st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     _check("recogs_render", st)
     return image
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+class BatchView(ctypes.Structure):
+    _fields_ = [("scene", Scene), ("cam", Camera), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("image", ctypes.c_void_p)]
+
+
+class BatchWorkspace(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("nviews", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("sh_degree", ctypes.c_int32), ("pairs", ctypes.c_int64),
+                ("tiles", ctypes.c_int64), ("key_capacity", ctypes.c_int64), ("tile_bits", ctypes.c_int32),
+                ("persistent_blocks", ctypes.c_int32), ("preprocess_blocks", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)] + \
+               [(f, ctypes.c_size_t) for f in (
+                   "off_views", "off_vtab", "off_rec", "off_zbits", "off_rect", "off_count", "off_offset",
+                   "off_dkeys0", "off_dkeys1", "off_dvals0", "off_dvals1", "off_scan", "off_esum", "off_sort_count",
+                   "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_header", "off_hist", "off_dhist",
+                   "off_ranges", "off_order", "scan_chunks")] + \
+               [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("overflow", ctypes.c_int32),
+                ("sorted_in_alt", ctypes.c_int32)]
+
+
+BATCH_ENTRY_POINTS = ("recogs_batch_workspace_bytes", "recogs_batch_init", "recogs_render_batch",
+                      "recogs_batch_readback")
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        P = ctypes.POINTER
+        L.recogs_batch_workspace_bytes.argtypes = [P(BatchView), i32, i32, i32, i64]
+        L.recogs_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.recogs_batch_init.argtypes = [P(BatchWorkspace), vp, ctypes.c_size_t, P(BatchView), i32, P(RenderOpts), i64]
+        L.recogs_batch_init.restype = ctypes.c_int
+        L.recogs_render_batch.argtypes = [P(BatchWorkspace), vp]
+        L.recogs_render_batch.restype = ctypes.c_int
+        L.recogs_batch_readback.argtypes = [P(BatchWorkspace), vp]
+        L.recogs_batch_readback.restype = ctypes.c_int
+        L._batch_ready = True
+    return L
+
+
+def recogs_batch_workspace_bytes(views, nviews, tile_w, tile_h, key_capacity) -> int:
+    return int(_batch_lib().recogs_batch_workspace_bytes(views, nviews, tile_w, tile_h, key_capacity))
+
+
+def recogs_batch_init(ws: BatchWorkspace, dev_mem, nbytes, views, nviews, opts: RenderOpts, key_capacity):
+    return _check("recogs_batch_init", _batch_lib().recogs_batch_init(ctypes.byref(ws), dev_mem, nbytes, views, nviews,
+                                                                      ctypes.byref(opts), key_capacity))
+
+
+def recogs_render_batch(ws: BatchWorkspace, stream=None):
+    return _check("recogs_render_batch", _batch_lib().recogs_render_batch(ctypes.byref(ws), _stream(stream)))
+
+
+def recogs_batch_readback(ws: BatchWorkspace, stream=None):
+    return _check("recogs_batch_readback", _batch_lib().recogs_batch_readback(ctypes.byref(ws), _stream(stream)))
+
+
+class DeviceBatch:
+    """A batch of (scene, view) renders: output images (torch tensors), the C view table
+    and a workspace. The key capacity, unless given, comes from one dry run (capacity 0:
+    the counts are computed, nothing is drawn) times `headroom`."""
+
+    def __init__(self, dscenes, views, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), key_capacity=None,
+                 headroom=1.25, device="cuda"):
+        import torch
+        self.dscenes = list(dscenes)
+        self.device = device
+        self.views_py = list(views)  # (scene index, camera, mask|None, M|None, b|None)
+        n = len(self.views_py)
+        self.images = [torch.zeros((c.height, c.width, 3), dtype=torch.float32, device=device)
+                       for (_, c, *_rest) in self.views_py]
+        self.c_views = (BatchView * n)()
+        self._keep = []
+        for k, (si, cam, mask, M, b) in enumerate(self.views_py):
+            bv = self.c_views[k]
+            bv.scene = self.dscenes[si].c_struct()
+            bv.cam = camera_struct(cam)
+            if mask is not None:
+                Mc = M.contiguous().reshape(9)
+                bc = b.contiguous().reshape(3)
+                self._keep += [mask, Mc, bc]
+                bv.mask, bv.M, bv.b = mask.data_ptr(), Mc.data_ptr(), bc.data_ptr()
+            bv.image = self.images[k].data_ptr()
+        self.opts = opts_struct(tile, ppt, bg)
+        self.tile, self.ppt = tuple(tile), int(ppt)
+        if key_capacity is None:
+            self._init(0)
+            self.render()
+            self.readback()
+            key_capacity = int(self.ws.num_keys * headroom) + 1024
+        self._init(int(key_capacity))
+
+    def _init(self, cap):
+        import torch
+        n = len(self.views_py)
+        nbytes = recogs_batch_workspace_bytes(self.c_views, n, self.opts.tile_w, self.opts.tile_h, cap)
+        if nbytes == 0:
+            raise RecogsError("recogs_batch_workspace_bytes", -1, "invalid batch")
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ws = BatchWorkspace()
+        recogs_batch_init(self.ws, self.mem.data_ptr(), nbytes, self.c_views, n, self.opts, cap)
+
+    def render(self, stream=None):
+        recogs_render_batch(self.ws, stream)
+
+    def readback(self, stream=None):
+        recogs_batch_readback(self.ws, stream)
+        return int(self.ws.num_keys), bool(self.ws.overflow)
+
+    def capture_graph(self):
+        """A torch.cuda.CUDAGraph (a HIP graph on ROCm) replaying recogs_render_batch."""
+        import torch
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.render()  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(g):
+            self.render()
+        return g

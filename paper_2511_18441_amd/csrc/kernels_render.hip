@@ -1,6 +1,6 @@
 // Render path kernels: preprocess (EWA projection, SH colour, tile rectangle),
 // exclusive scan of tile counts, key emission, tile ranges, front-to-back blend.
-#include "recogs_internal.hpp"
+#include "render_device.hpp"
 
 namespace recogs {
 
@@ -8,129 +8,13 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// Real SH basis (eq. 2), degree <= DEG, at unit direction (x, y, z).
-template <int DEG>
-__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
-    Y[0] = kSH0;
-    if constexpr (DEG >= 1) {
-        Y[1] = -kSH1 * y; Y[2] = kSH1 * z; Y[3] = -kSH1 * x;
-    }
-    if constexpr (DEG >= 2) {
-        const float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = kSH2a * x * y; Y[5] = -kSH2a * y * z; Y[6] = kSH2b * (2.f * zz - xx - yy);
-        Y[7] = -kSH2a * x * z; Y[8] = kSH2c * (xx - yy);
-        if constexpr (DEG >= 3) {
-            Y[9] = -kSH3a * y * (3.f * xx - yy); Y[10] = kSH3b * x * y * z;
-            Y[11] = -kSH3c * y * (4.f * zz - xx - yy); Y[12] = kSH3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
-            Y[13] = -kSH3c * x * (4.f * zz - xx - yy); Y[14] = kSH3e * z * (xx - yy);
-            Y[15] = -kSH3a * x * (xx - 3.f * yy);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Preprocess: one thread per Gaussian.
-//   m = R mu + t (compensated); cull depth <= znear.
-//   EWA: J at the 1.3x-frustum-clamped position, Sigma2D = J R Sigma R^T J^T + 0.3 I.
-//   Cull det <= 0 and 255 sigma < 1. Box of q <= 2 ln(255 sigma) + 1/64 -> pixel range
-//   [ceil(u - ex - 1/2), floor(u + ex - 1/2)] clipped -> tile rectangle and count.
-//   Colour max(0, f + 1/2) or, for selected Gaussians of a fused recolour,
-//   max(0, M (f + 1/2) + b).
-// Writes the splat record, depth bits, packed tile rectangle and count; folds the
-// depth range of Gaussians with keys into the workspace header.
-// ---------------------------------------------------------------------------
 template <int DT, int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, RecolorDev rc, int keep_bwd,
                                                     SplatRec *__restrict__ rec, float4 *__restrict__ bwd,
                                                     uint32_t *__restrict__ zbits, uint2 *__restrict__ rect,
-                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ header) {
+                                                    uint32_t *__restrict__ count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t cnt = 0, zb = 0;
-    uint2 rr = make_uint2(0u, 0u);
-    if (i < sc.n) {
-        const int64_t S = sc.stride;
-        const float mx = sc.means[i], my = sc.means[S + i], mz = sc.means[2 * S + i];
-        const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
-        zb = __float_as_uint(z);
-        if (z > cam.znear) {
-            const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
-            const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
-            const float iz = 1.0f / z;
-            const float xc = fminf(cam.limx, fmaxf(-cam.limx, x * iz)) * z;
-            const float yc = fminf(cam.limy, fmaxf(-cam.limy, y * iz)) * z;
-            const float j00 = cam.fx * iz, j02 = -cam.fx * xc * iz * iz;
-            const float j11 = cam.fy * iz, j12 = -cam.fy * yc * iz * iz;
-            // T = J R (2 x 3)
-            const float a0 = j00 * cam.R[0] + j02 * cam.R[6], a1 = j00 * cam.R[1] + j02 * cam.R[7],
-                        a2 = j00 * cam.R[2] + j02 * cam.R[8];
-            const float b0 = j11 * cam.R[3] + j12 * cam.R[6], b1 = j11 * cam.R[4] + j12 * cam.R[7],
-                        b2 = j11 * cam.R[5] + j12 * cam.R[8];
-            const float c00 = sc.cov3d[i], c01 = sc.cov3d[S + i], c02 = sc.cov3d[2 * S + i];
-            const float c11 = sc.cov3d[3 * S + i], c12 = sc.cov3d[4 * S + i], c22 = sc.cov3d[5 * S + i];
-            // Sigma T^T columns
-            const float sa0 = c00 * a0 + c01 * a1 + c02 * a2, sa1 = c01 * a0 + c11 * a1 + c12 * a2,
-                        sa2 = c02 * a0 + c12 * a1 + c22 * a2;
-            const float sb0 = c00 * b0 + c01 * b1 + c02 * b2, sb1 = c01 * b0 + c11 * b1 + c12 * b2,
-                        sb2 = c02 * b0 + c12 * b1 + c22 * b2;
-            const float A = a0 * sa0 + a1 * sa1 + a2 * sa2 + kDilation;
-            const float B = a0 * sb0 + a1 * sb1 + a2 * sb2;
-            const float C = b0 * sb0 + b1 * sb1 + b2 * sb2 + kDilation;
-            const float det = A * C - B * B;
-            if (det > 0.f && det < INFINITY) {
-                const float sigma = Store<DT>::ldc(sc.opacity, i);
-                if (255.f * sigma >= 1.f) {
-                    const float level = 2.f * logf(255.f * sigma) + kQSlack;
-                    const float ex = sqrtf(level * A), ey = sqrtf(level * C);
-                    const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
-                    const float fx0 = fmaxf(ceilf(u - ex - 0.5f), 0.f), fx1 = fminf(floorf(u + ex - 0.5f), (float)(cam.W - 1));
-                    const float fy0 = fmaxf(ceilf(v - ey - 0.5f), 0.f), fy1 = fminf(floorf(v + ey - 0.5f), (float)(cam.H - 1));
-                    if (fx0 <= fx1 && fy0 <= fy1) {
-                        const uint32_t tx0 = (uint32_t)fx0 / cam.tw, tx1 = (uint32_t)fx1 / cam.tw;
-                        const uint32_t ty0 = (uint32_t)fy0 / cam.th, ty1 = (uint32_t)fy1 / cam.th;
-                        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
-                        // colour (eq. 2) at the view direction of the centre
-                        float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
-                        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-                        dx *= inv; dy *= inv; dz *= inv;
-                        constexpr int NC = (DEG + 1) * (DEG + 1);
-                        float Y[16];
-                        sh_basis<DEG>(dx, dy, dz, Y);
-                        float f[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float acc = 0.f;
-#pragma unroll
-                            for (int k = 0; k < NC; ++k) acc += Store<DT>::ld(sc.sh, (int64_t)(k * 3 + c) * S + i) * Y[k];
-                            f[c] = acc + 0.5f;
-                        }
-                        float pre[3] = {f[0], f[1], f[2]};
-                        uint32_t flags = 0;
-                        if (rc.mask && rc.mask[i]) {
-                            flags |= 8u;
-#pragma unroll
-                            for (int r = 0; r < 3; ++r)
-                                pre[r] = rc.M[r * 3] * f[0] + rc.M[r * 3 + 1] * f[1] + rc.M[r * 3 + 2] * f[2] + rc.b[r];
-                        }
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) flags |= (pre[c] > 0.f ? 1u : 0u) << c;
-                        // conic = inverse 2D covariance, folded into a base-2 exponent
-                        const float idet = 1.0f / det;
-                        const float ca = C * idet, cb = -B * idet, cc = A * idet;
-                        SplatRec s;
-                        s.r0 = make_float4(u, v, ex, ey);
-                        s.r1 = make_float4(-0.5f * kLog2e * ca, -kLog2e * cb, -0.5f * kLog2e * cc, log2f(sigma));
-                        s.r2 = make_float4(fmaxf(pre[0], 0.f), fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f), sigma);
-                        rec[i] = s;
-                        if (keep_bwd) bwd[i] = make_float4(f[0], f[1], f[2], __uint_as_float(flags));
-                    }
-                }
-            }
-        }
-        count[i] = cnt;
-        rect[i] = rr;
-        zbits[i] = zb;
-    }
+    if (i < sc.n) preprocess_one<DT, DEG>(sc, cam, rc, keep_bwd, i, i, rec, bwd, zbits, rect, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +84,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
 // the depth range (minimum stored as its complement).
 __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, uint32_t *__restrict__ pv,
                                                    const uint32_t *__restrict__ pzmn, const uint32_t *__restrict__ pzmx,
-                                                   uint32_t nchunks, uint32_t *__restrict__ header) {
+                                                   uint32_t nchunks, uint64_t key_capacity, uint32_t *__restrict__ header) {
     __shared__ uint64_t s_wk[16];
     __shared__ uint32_t s_wv[16], s_zmn[16], s_zmx[16];
     const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
@@ -232,6 +116,9 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, ui
         header[H_V] = runv;
         header[H_ZMIN] = runv ? ~zmn : 0u;
         header[H_ZMAX] = runv ? zmx : 0u;
+        header[H_ZMIN_RAW] = runv ? zmn : 0u;
+        header[H_KEFF] = runk <= key_capacity ? (uint32_t)runk : 0u;
+        header[H_OVERFLOW] = runk > key_capacity ? 1u : 0u;
     }
 }
 
@@ -348,7 +235,8 @@ __device__ __forceinline__ uint32_t rect_count(uint2 r) {
 // for k_emit_down); every Gaussian in the order has at least one key
 __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict__ order, uint32_t V,
                                                      const uint2 *__restrict__ rect, uint2 *__restrict__ srect,
-                                                     uint32_t *__restrict__ esum) {
+                                                     uint32_t *__restrict__ esum, const uint32_t *dynV) {
+    if (dynV) V = *dynV;
     __shared__ uint32_t s_w[4];
     const uint32_t base = blockIdx.x * (uint32_t)kEmitChunk + threadIdx.x;
     uint32_t sum = 0;
@@ -367,11 +255,18 @@ __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) esum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
+// Batches (nviews > 1): values are (view, Gaussian) pair indices and tile ids are global,
+// tile_base(view) + local id; vtab[v] = (pair_base, tile_base, tiles_x, -) per view.
 __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ order, uint32_t V,
                                                    const uint2 *__restrict__ srect, int tiles_x,
                                                    const uint32_t *__restrict__ epre, uint32_t *__restrict__ tkeys,
-                                                   uint32_t *__restrict__ tvals) {
+                                                   uint32_t *__restrict__ tvals, const uint32_t *dynV,
+                                                   const uint32_t *overflow, const uint4 *__restrict__ vtab, int nviews) {
+    if (dynV) V = *dynV;
+    if (overflow && *overflow) return;
+    if (blockIdx.x * (uint32_t)kEmitChunk >= V) return;
     constexpr int R = kEmitItems;
+    __shared__ uint32_t s_tb[4][64], s_tx[4][64];
     __shared__ uint32_t s_gsum[4 * R];     // per-group totals, then per-group exclusive prefix
     __shared__ uint32_t s_ex[4][64];
     __shared__ uint2 s_rect[4][64];
@@ -391,6 +286,22 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
         rr[r] = j < V ? srect[j] : make_uint2(0u, 0u);
         c[r] = j < V ? rect_count(rr[r]) : 0u;
     }
+    uint32_t tb[R], txn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        tb[r] = 0;
+        txn[r] = (uint32_t)tiles_x;
+        if (nviews > 1) {  // view of the pair: last v with pair_base <= g
+            int lo = 0, hi = nviews - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (vtab[mid].x <= g[r]) lo = mid;
+                else hi = mid - 1;
+            }
+            tb[r] = vtab[lo].y;
+            txn[r] = vtab[lo].z;
+        }
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         inc[r] = wave_incl_scan(c[r]);
@@ -409,6 +320,8 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
         s_ex[w][lane] = inc[r] - c[r];
         s_rect[w][lane] = rr[r];
         s_g[w][lane] = g[r];
+        s_tb[w][lane] = tb[r];
+        s_tx[w][lane] = txn[r];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -426,7 +339,7 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
             const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
             const uint32_t wd = tx1 - tx0 + 1;
             const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
-            tkeys[base + q] = ty * (uint32_t)tiles_x + tx;
+            tkeys[base + q] = s_tb[w][lo] + ty * s_tx[w][lo] + tx;
             tvals[base + q] = s_g[w][lo];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -436,12 +349,14 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
 }
 
 // [first, last+1) of each tile in tile-sorted 32-bit tile ids (ranges zeroed beforehand).
-__global__ __launch_bounds__(256) void k_ranges32(const uint32_t *__restrict__ tiles, uint32_t K, uint2 *__restrict__ ranges) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    const uint32_t t = tiles[k];
-    if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
-    if (k == K - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
+__global__ __launch_bounds__(256) void k_ranges32(const uint32_t *__restrict__ tiles, uint32_t K, uint2 *__restrict__ ranges,
+                                                  const uint32_t *dynK) {
+    if (dynK) K = *dynK;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        const uint32_t t = tiles[k];
+        if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
+        if (k == K - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
+    }
 }
 
 // [first, last+1) of each tile in the sorted keys (ranges zeroed beforehand).
@@ -468,87 +383,10 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict_
                                                        const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                        float bg0, float bg1, float bg2, float *__restrict__ image,
                                                        float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
-#pragma clang fp contract(off)
-    using Map = TileMap<TW, TH, PPT>;
-    constexpr int NT = Map::NT;
-    constexpr int BATCH = 256;
-    __shared__ float4 s_r0[BATCH], s_r1[BATCH], s_r2[BATCH];
-    __shared__ uint8_t s_mask[BATCH];
-    const int tile = blockIdx.x;
-    const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
-    const int t = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(Map::wave(t));
-    int lx, lrow;
-    Map::pixel(t, lx, lrow);
-    const int px = tx0 + lx;
-    const float pxc = (float)px + 0.5f;
-    float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
-    uint32_t last[PPT];
-    bool done[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int py = ty0 + lrow * PPT + j;
-        pyc[j] = (float)py + 0.5f;
-        T[j] = 1.f; C0[j] = C1[j] = C2[j] = 0.f; last[j] = 0;
-        done[j] = !(px < W && py < H);
-    }
-
-    const uint2 rg = ranges[tile];
-    for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
-        bool mine = true;
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) mine = mine && done[j];
-        if (__syncthreads_and(mine)) break;
-        for (int q = t; q < BATCH; q += NT) {
-            const uint32_t k = start + q;
-            if (k < rg.y) {
-                const SplatRec s = rec[vals[k]];
-                s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
-                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
-            }
-        }
-        __syncthreads();
-        const int nb = (int)min((uint32_t)BATCH, rg.y - start);
-        const uint32_t krel0 = start + 1 - rg.x;
-        for (int q = 0; q < nb; ++q) {
-            bool alive = false;
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) alive = alive || !done[j];
-            if (!wave_ballot(alive)) break;
-            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
-            if (!((m >> w) & 1u)) continue;
-            const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
-            const ExpRow er = exp_row(r1, pxc - r0.x);
-            const uint32_t kq = krel0 + (uint32_t)q;
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                if (done[j]) continue;
-                const float e = exp_at(er, r1, pyc[j] - r0.y);
-                if (e < kLog2AlphaMin) continue;
-                const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
-                const float Tn = T[j] * (1.f - a);
-                if (Tn < kTMin) { done[j] = true; continue; }
-                const float wgt = a * T[j];
-                C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
-                C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
-                C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
-                T[j] = Tn;
-                last[j] = kq;
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const int py = ty0 + lrow * PPT + j;
-        if (px < W && py < H) {
-            const int64_t p = (int64_t)py * W + px;
-            image[p * 3 + 0] = __builtin_fmaf(T[j], bg0, C0[j]);
-            image[p * 3 + 1] = __builtin_fmaf(T[j], bg1, C1[j]);
-            image[p * 3 + 2] = __builtin_fmaf(T[j], bg2, C2[j]);
-            finalT[p] = T[j];
-            nproc[p] = last[j];
-        }
-    }
+    __shared__ float4 s_r0[kBlendBatch], s_r1[kBlendBatch], s_r2[kBlendBatch];
+    __shared__ uint8_t s_mask[kBlendBatch];
+    blend_tile<TW, TH, PPT>(blockIdx.x, ranges[blockIdx.x], vals, rec, W, H, tiles_x, bg0, bg1, bg2, image, finalT, nproc,
+                            s_r0, s_r1, s_r2, s_mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,46 +401,51 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
 
 template <int DT>
 static void preprocess_dt(int deg, dim3 g, hipStream_t st, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc,
-                          int keep, SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, uint32_t *hdr) {
+                          int keep, SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt) {
     switch (deg) {
-    case 0: hipLaunchKernelGGL((k_preprocess<DT, 0>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
-    case 1: hipLaunchKernelGGL((k_preprocess<DT, 1>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
-    case 2: hipLaunchKernelGGL((k_preprocess<DT, 2>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
-    default: hipLaunchKernelGGL((k_preprocess<DT, 3>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr); break;
+    case 0: hipLaunchKernelGGL((k_preprocess<DT, 0>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
+    case 1: hipLaunchKernelGGL((k_preprocess<DT, 1>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
+    case 2: hipLaunchKernelGGL((k_preprocess<DT, 2>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
+    default: hipLaunchKernelGGL((k_preprocess<DT, 3>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
     }
 }
 
 void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc, int keep,
-                       SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, uint32_t *hdr,
-                       hipStream_t st) {
+                       SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, hipStream_t st) {
     if (sc.n <= 0) return;
     const dim3 g((unsigned)((sc.n + 255) / 256));
-    if (dt == RECOGS_F32) preprocess_dt<RECOGS_F32>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
-    else if (dt == RECOGS_F16) preprocess_dt<RECOGS_F16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
-    else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, hdr);
+    if (dt == RECOGS_F32) preprocess_dt<RECOGS_F32>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
+    else if (dt == RECOGS_F16) preprocess_dt<RECOGS_F16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
+    else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
 }
 
 void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *pk, uint32_t *pv,
-                 uint32_t *pzmn, uint32_t *pzmx, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, hipStream_t st) {
+                 uint32_t *pzmn, uint32_t *pzmx, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, int64_t key_capacity,
+                 hipStream_t st) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, hdr);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr);
     hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals);
 }
 
+// V is the count or, with dynV, its upper bound; hdr (optional) supplies the overflow flag.
 void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, uint2 *srect, int tiles_x,
-                        uint32_t *esum, uint32_t *tkeys, uint32_t *tvals, hipStream_t st) {
+                        uint32_t *esum, uint32_t *tkeys, uint32_t *tvals, hipStream_t st, const uint32_t *dynV,
+                        const uint32_t *hdr, const uint4 *vtab, int nviews) {
     if (V == 0) return;
     const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
-    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum);
+    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum, dynV);
     hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
-    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, srect, tiles_x, esum, tkeys, tvals);
+    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, srect, tiles_x, esum, tkeys, tvals, dynV,
+                       hdr ? hdr + H_OVERFLOW : nullptr, vtab, nviews);
 }
 
-void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st) {
+void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st, const uint32_t *dynK) {
     if (K == 0) return;
-    hipLaunchKernelGGL(k_ranges32, dim3((K + 255) / 256), dim3(256), 0, st, tiles, K, ranges);
+    uint32_t blocks = (K + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_ranges32, dim3(blocks), dim3(256), 0, st, tiles, K, ranges, dynK);
 }
 
 void launch_emit(const uint32_t *cnt, const uint32_t *off, const uint2 *rect, const uint32_t *zb, int64_t n, int tiles_x,

@@ -49,9 +49,19 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_w
 
 // Digit histograms of all passes. Pass p uses bits [shift_p, shift_p + bits_p) of the
 // view, shift_p = sum of earlier bits; `bits` packs bits_p in nibbles.
+// Counts and the depth minimum may live in device memory (dyn_count, dyn_zmin non-null:
+// the graph-capturable batch, whose host code never reads them back); grids are then
+// sized for the capacity and workgroups past the live count return at once.
+__device__ __forceinline__ void dyn_args(const uint32_t *dyn_count, const uint32_t *dyn_zmin, uint32_t &K, uint32_t &zmin) {
+    if (dyn_count) K = *dyn_count;
+    if (dyn_zmin) zmin = *dyn_zmin;
+}
+
 template <typename KT, int VIEW>
 __global__ __launch_bounds__(256) void k_radix_hist(const KT *__restrict__ keys, uint32_t K, uint32_t zmin, int dbits,
-                                                    int passes, uint32_t bits, uint32_t *__restrict__ ghist) {
+                                                    int passes, uint32_t bits, uint32_t *__restrict__ ghist,
+                                                    const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+    dyn_args(dyn_count, dyn_zmin, K, zmin);
     __shared__ uint32_t h[kMaxPasses][256];
     for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&h[0][0])[i] = 0;
     __syncthreads();
@@ -74,7 +84,10 @@ __global__ __launch_bounds__(256) void k_radix_hist(const KT *__restrict__ keys,
 // per-chunk digit counts -> cnt[digit * chunks + chunk]
 template <typename KT, int VIEW>
 __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, uint32_t K, uint32_t zmin, int dbits,
-                                                  int shift, int nbits, uint32_t *__restrict__ cnt, uint32_t chunks) {
+                                                  int shift, int nbits, uint32_t *__restrict__ cnt, uint32_t chunks,
+                                                  const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+    dyn_args(dyn_count, dyn_zmin, K, zmin);
+    if (blockIdx.x * (uint32_t)kSortChunk >= K) return;
     __shared__ uint32_t h[256];
     const uint32_t t = threadIdx.x;
     h[t] = 0;
@@ -92,7 +105,10 @@ __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, ui
 
 // workgroup d: cnt[d][c] <- base(d) + sum_{c' < c} cnt[d][c'], base(d) = sum_{d' < d} ghist[d']
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks,
-                                                       const uint32_t *__restrict__ ghist) {
+                                                       const uint32_t *__restrict__ ghist, uint32_t K,
+                                                       const uint32_t *dyn_count) {
+    if (dyn_count) K = *dyn_count;
+    const uint32_t live = (K + kSortChunk - 1) / kSortChunk;   // chunks holding keys; row stride stays `chunks`
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_base;
     const uint32_t d = blockIdx.x, t = threadIdx.x;
@@ -102,11 +118,11 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cn
     __syncthreads();
     uint32_t run = s_base;
     uint32_t *row = cnt + (size_t)d * chunks;
-    for (uint32_t c0 = 0; c0 < chunks; c0 += 256) {
+    for (uint32_t c0 = 0; c0 < live; c0 += 256) {
         const uint32_t c = c0 + t;
-        const uint32_t v = c < chunks ? row[c] : 0u;
+        const uint32_t v = c < live ? row[c] : 0u;
         const uint32_t e = block_excl_scan256(v, s_w, tot);
-        if (c < chunks) row[c] = run + e;
+        if (c < live) row[c] = run + e;
         run += tot;
     }
 }
@@ -115,7 +131,10 @@ template <typename KT, int VIEW>
 __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     KT *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
                                                     uint32_t zmin, int dbits, int shift, int nbits,
-                                                    const uint32_t *__restrict__ off, uint32_t chunks) {
+                                                    const uint32_t *__restrict__ off, uint32_t chunks,
+                                                    const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+    dyn_args(dyn_count, dyn_zmin, K, zmin);
+    if (blockIdx.x * (uint32_t)kSortChunk >= K) return;
     __shared__ uint32_t s_whist[4][256];   // per-wave digit counts, then per-wave digit prefix
     __shared__ uint32_t s_gbase[256];      // global position of this chunk's first key of each digit
     __shared__ uint32_t s_lstart[256];     // position in the LDS stage of each digit
@@ -201,8 +220,9 @@ int sort_passes(int total_bits) { return (total_bits + 7) / 8; }
 
 template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
-                      uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
-    if (K == 0 || total_bits == 0) return 0;
+                      uint32_t *ghist, uint32_t *cnt, hipStream_t st, const uint32_t *dyn_count = nullptr,
+                      const uint32_t *dyn_zmin = nullptr) {
+    if (K == 0 || total_bits == 0) return 0;   // K is the count, or its upper bound with dyn_count
     const int passes = sort_passes(total_bits);
     const int per = (total_bits + passes - 1) / passes;
     uint32_t bits = 0;
@@ -214,7 +234,8 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
     }
     uint32_t blocks = (K + 256 * 16 - 1) / (256 * 16);
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_radix_hist<KT, VIEW>), dim3(blocks), dim3(256), 0, st, ka, K, zmin, dbits, passes, bits, ghist);
+    hipLaunchKernelGGL((k_radix_hist<KT, VIEW>), dim3(blocks), dim3(256), 0, st, ka, K, zmin, dbits, passes, bits, ghist,
+                       dyn_count, dyn_zmin);
     const uint32_t chunks = (K + kSortChunk - 1) / kSortChunk;
     int alt = 0, shift = 0;
     for (int p = 0; p < passes; ++p) {
@@ -224,10 +245,10 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         KT *kout = alt ? ka : kb;
         uint32_t *vout = alt ? va : vb;
         hipLaunchKernelGGL((k_radix_up<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,
-                           chunks);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, ghist + 256 * p);
+                           chunks, dyn_count, dyn_zmin);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, ghist + 256 * p, K, dyn_count);
         hipLaunchKernelGGL((k_radix_down<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits,
-                           shift, nb, cnt, chunks);
+                           shift, nb, cnt, chunks, dyn_count, dyn_zmin);
         alt ^= 1;
         shift += nb;
     }
@@ -242,6 +263,13 @@ int radix_sort_tile_depth64(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *
 int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K, uint32_t sub, int total_bits,
                    uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
     return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st);
+}
+
+// The same with the count and the subtracted minimum read from device memory; K_max
+// bounds the count (sizes the grids and the count matrix).
+int radix_sort_u32_dyn(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K_max, const uint32_t *dyn_count,
+                       const uint32_t *dyn_sub, int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K_max, 0u, 0, total_bits, ghist, cnt, st, dyn_count, dyn_sub);
 }
 
 }  // namespace recogs

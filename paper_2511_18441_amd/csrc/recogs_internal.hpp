@@ -154,7 +154,25 @@ enum : int {
     H_K_LO = 0, H_K_HI = 1,      // number of keys (64-bit)
     H_ZMIN = 2, H_ZMAX = 3,      // complement of min / max float32 depth bits among splats with keys
     H_V = 4,                     // number of Gaussians with keys
-    H_WORDS = 64
+    H_KEFF = 5,                  // keys emitted: K if it fits the capacity, else 0
+    H_OVERFLOW = 6,              // 1 when K exceeds the key capacity (nothing is emitted)
+    H_ZMIN_RAW = 7,              // min depth bits (not complemented)
+    H_QUEUE = 8,                 // work counter of the persistent blend
+    H_ORDER_HIST = 16,           // 32 words: tiles per list-length class
+    H_ORDER_CUR = 48,            // 32 words: scatter cursors of the length classes
+    H_WORDS = 128
+};
+
+// Per-view description of a batch (device memory): the view's scene, camera and
+// fused recolour, its output, and where its pairs, preprocess blocks and tiles start
+// in the batch's flattened index spaces.
+struct ViewDev {
+    SceneDev sc;
+    CamDev cam;
+    RecolorDev rc;
+    float *image;
+    float bg[3];
+    uint32_t pair_base, blk_base, tile_base, ntiles;
 };
 
 constexpr int kScanItems = 16;                       // counts per thread of the scan

@@ -1,0 +1,224 @@
+// Device functions shared by the single-view and the batched render kernels
+// (preprocess of one Gaussian, blend of one tile).
+#pragma once
+
+#include "recogs_internal.hpp"
+
+namespace recogs {
+
+// Real SH basis (eq. 2), degree <= DEG, at unit direction (x, y, z).
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
+    Y[0] = kSH0;
+    if constexpr (DEG >= 1) {
+        Y[1] = -kSH1 * y; Y[2] = kSH1 * z; Y[3] = -kSH1 * x;
+    }
+    if constexpr (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kSH2a * x * y; Y[5] = -kSH2a * y * z; Y[6] = kSH2b * (2.f * zz - xx - yy);
+        Y[7] = -kSH2a * x * z; Y[8] = kSH2c * (xx - yy);
+        if constexpr (DEG >= 3) {
+            Y[9] = -kSH3a * y * (3.f * xx - yy); Y[10] = kSH3b * x * y * z;
+            Y[11] = -kSH3c * y * (4.f * zz - xx - yy); Y[12] = kSH3d * z * (2.f * zz - 3.f * xx - 3.f * yy);
+            Y[13] = -kSH3c * x * (4.f * zz - xx - yy); Y[14] = kSH3e * z * (xx - yy);
+            Y[15] = -kSH3a * x * (xx - 3.f * yy);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Preprocess: one thread per Gaussian.
+//   m = R mu + t (compensated); cull depth <= znear.
+//   EWA: J at the 1.3x-frustum-clamped position, Sigma2D = J R Sigma R^T J^T + 0.3 I.
+//   Cull det <= 0 and 255 sigma < 1. Box of q <= 2 ln(255 sigma) + 1/64 -> pixel range
+//   [ceil(u - ex - 1/2), floor(u + ex - 1/2)] clipped -> tile rectangle and count.
+//   Colour max(0, f + 1/2) or, for selected Gaussians of a fused recolour,
+//   max(0, M (f + 1/2) + b).
+// Writes the splat record, depth bits, packed tile rectangle and count; folds the
+// depth range of Gaussians with keys into the workspace header.
+// ---------------------------------------------------------------------------
+// Gaussian i of the scene, outputs at index o (o = i for one view; the (view,
+// Gaussian) pair index in a batch).
+template <int DT, int DEG>
+__device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev &cam, const RecolorDev &rc, int keep_bwd,
+                                               int64_t i, int64_t o, SplatRec *__restrict__ rec, float4 *__restrict__ bwd,
+                                               uint32_t *__restrict__ zbits, uint2 *__restrict__ rect,
+                                               uint32_t *__restrict__ count) {
+    uint32_t cnt = 0, zb = 0;
+    uint2 rr = make_uint2(0u, 0u);
+    {
+        const int64_t S = sc.stride;
+        const float mx = sc.means[i], my = sc.means[S + i], mz = sc.means[2 * S + i];
+        const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
+        zb = __float_as_uint(z);
+        if (z > cam.znear) {
+            const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
+            const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
+            const float iz = 1.0f / z;
+            const float xc = fminf(cam.limx, fmaxf(-cam.limx, x * iz)) * z;
+            const float yc = fminf(cam.limy, fmaxf(-cam.limy, y * iz)) * z;
+            const float j00 = cam.fx * iz, j02 = -cam.fx * xc * iz * iz;
+            const float j11 = cam.fy * iz, j12 = -cam.fy * yc * iz * iz;
+            // T = J R (2 x 3)
+            const float a0 = j00 * cam.R[0] + j02 * cam.R[6], a1 = j00 * cam.R[1] + j02 * cam.R[7],
+                        a2 = j00 * cam.R[2] + j02 * cam.R[8];
+            const float b0 = j11 * cam.R[3] + j12 * cam.R[6], b1 = j11 * cam.R[4] + j12 * cam.R[7],
+                        b2 = j11 * cam.R[5] + j12 * cam.R[8];
+            const float c00 = sc.cov3d[i], c01 = sc.cov3d[S + i], c02 = sc.cov3d[2 * S + i];
+            const float c11 = sc.cov3d[3 * S + i], c12 = sc.cov3d[4 * S + i], c22 = sc.cov3d[5 * S + i];
+            // Sigma T^T columns
+            const float sa0 = c00 * a0 + c01 * a1 + c02 * a2, sa1 = c01 * a0 + c11 * a1 + c12 * a2,
+                        sa2 = c02 * a0 + c12 * a1 + c22 * a2;
+            const float sb0 = c00 * b0 + c01 * b1 + c02 * b2, sb1 = c01 * b0 + c11 * b1 + c12 * b2,
+                        sb2 = c02 * b0 + c12 * b1 + c22 * b2;
+            const float A = a0 * sa0 + a1 * sa1 + a2 * sa2 + kDilation;
+            const float B = a0 * sb0 + a1 * sb1 + a2 * sb2;
+            const float C = b0 * sb0 + b1 * sb1 + b2 * sb2 + kDilation;
+            const float det = A * C - B * B;
+            if (det > 0.f && det < INFINITY) {
+                const float sigma = Store<DT>::ldc(sc.opacity, i);
+                if (255.f * sigma >= 1.f) {
+                    const float level = 2.f * logf(255.f * sigma) + kQSlack;
+                    const float ex = sqrtf(level * A), ey = sqrtf(level * C);
+                    const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
+                    const float fx0 = fmaxf(ceilf(u - ex - 0.5f), 0.f), fx1 = fminf(floorf(u + ex - 0.5f), (float)(cam.W - 1));
+                    const float fy0 = fmaxf(ceilf(v - ey - 0.5f), 0.f), fy1 = fminf(floorf(v + ey - 0.5f), (float)(cam.H - 1));
+                    if (fx0 <= fx1 && fy0 <= fy1) {
+                        const uint32_t tx0 = (uint32_t)fx0 / cam.tw, tx1 = (uint32_t)fx1 / cam.tw;
+                        const uint32_t ty0 = (uint32_t)fy0 / cam.th, ty1 = (uint32_t)fy1 / cam.th;
+                        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                        // colour (eq. 2) at the view direction of the centre
+                        float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+                        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                        dx *= inv; dy *= inv; dz *= inv;
+                        constexpr int NC = (DEG + 1) * (DEG + 1);
+                        float Y[16];
+                        sh_basis<DEG>(dx, dy, dz, Y);
+                        float f[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            float acc = 0.f;
+#pragma unroll
+                            for (int k = 0; k < NC; ++k) acc += Store<DT>::ld(sc.sh, (int64_t)(k * 3 + c) * S + i) * Y[k];
+                            f[c] = acc + 0.5f;
+                        }
+                        float pre[3] = {f[0], f[1], f[2]};
+                        uint32_t flags = 0;
+                        if (rc.mask && rc.mask[i]) {
+                            flags |= 8u;
+#pragma unroll
+                            for (int r = 0; r < 3; ++r)
+                                pre[r] = rc.M[r * 3] * f[0] + rc.M[r * 3 + 1] * f[1] + rc.M[r * 3 + 2] * f[2] + rc.b[r];
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) flags |= (pre[c] > 0.f ? 1u : 0u) << c;
+                        // conic = inverse 2D covariance, folded into a base-2 exponent
+                        const float idet = 1.0f / det;
+                        const float ca = C * idet, cb = -B * idet, cc = A * idet;
+                        SplatRec s;
+                        s.r0 = make_float4(u, v, ex, ey);
+                        s.r1 = make_float4(-0.5f * kLog2e * ca, -kLog2e * cb, -0.5f * kLog2e * cc, log2f(sigma));
+                        s.r2 = make_float4(fmaxf(pre[0], 0.f), fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f), sigma);
+                        rec[o] = s;
+                        if (keep_bwd) bwd[o] = make_float4(f[0], f[1], f[2], __uint_as_float(flags));
+                    }
+                }
+            }
+        }
+        count[o] = cnt;
+        rect[o] = rr;
+        zbits[o] = zb;
+    }
+}
+
+constexpr int kBlendBatch = 256;   // splat records staged per LDS batch
+
+// One tile (local index `tile` of a W x H image with tiles_x tiles per row) whose
+// sorted list is vals[rg.x, rg.y); finalT / nproc may be null.
+template <int TW, int TH, int PPT>
+__device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *__restrict__ vals,
+                                           const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
+                                           float bg1, float bg2, float *__restrict__ image, float *__restrict__ finalT,
+                                           uint32_t *__restrict__ nproc, float4 *s_r0, float4 *s_r1, float4 *s_r2,
+                                           uint8_t *s_mask) {
+#pragma clang fp contract(off)
+    using Map = TileMap<TW, TH, PPT>;
+    constexpr int NT = Map::NT;
+    constexpr int BATCH = kBlendBatch;
+    const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+    const int t = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(Map::wave(t));
+    int lx, lrow;
+    Map::pixel(t, lx, lrow);
+    const int px = tx0 + lx;
+    const float pxc = (float)px + 0.5f;
+    float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    uint32_t last[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = ty0 + lrow * PPT + j;
+        pyc[j] = (float)py + 0.5f;
+        T[j] = 1.f; C0[j] = C1[j] = C2[j] = 0.f; last[j] = 0;
+        done[j] = !(px < W && py < H);
+    }
+
+    for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
+        bool mine = true;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) mine = mine && done[j];
+        if (__syncthreads_and(mine)) break;
+        for (int q = t; q < BATCH; q += NT) {
+            const uint32_t k = start + q;
+            if (k < rg.y) {
+                const SplatRec s = rec[vals[k]];
+                s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
+                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+            }
+        }
+        __syncthreads();
+        const int nb = (int)min((uint32_t)BATCH, rg.y - start);
+        const uint32_t krel0 = start + 1 - rg.x;
+        for (int q = 0; q < nb; ++q) {
+            bool alive = false;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) alive = alive || !done[j];
+            if (!wave_ballot(alive)) break;
+            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
+            if (!((m >> w) & 1u)) continue;
+            const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
+            const ExpRow er = exp_row(r1, pxc - r0.x);
+            const uint32_t kq = krel0 + (uint32_t)q;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                if (done[j]) continue;
+                const float e = exp_at(er, r1, pyc[j] - r0.y);
+                if (e < kLog2AlphaMin) continue;
+                const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+                const float Tn = T[j] * (1.f - a);
+                if (Tn < kTMin) { done[j] = true; continue; }
+                const float wgt = a * T[j];
+                C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
+                C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
+                C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
+                T[j] = Tn;
+                last[j] = kq;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = ty0 + lrow * PPT + j;
+        if (px < W && py < H) {
+            const int64_t p = (int64_t)py * W + px;
+            image[p * 3 + 0] = __builtin_fmaf(T[j], bg0, C0[j]);
+            image[p * 3 + 1] = __builtin_fmaf(T[j], bg1, C1[j]);
+            image[p * 3 + 2] = __builtin_fmaf(T[j], bg2, C2[j]);
+            if (finalT) finalT[p] = T[j];
+            if (nproc) nproc[p] = last[j];
+        }
+    }
+}
+
+}  // namespace recogs

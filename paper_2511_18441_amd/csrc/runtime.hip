@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "recogs_internal.hpp"
 
@@ -15,15 +17,15 @@ void launch_select(int, const SceneDev &, const CamDev &, const recogs_select_pa
 void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const float *, const float *, int, hipStream_t);
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
-                       uint32_t *, uint2 *, uint32_t *, uint32_t *, hipStream_t);
+                       uint32_t *, uint2 *, uint32_t *, hipStream_t);
 void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
-                 uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+                 uint32_t *, uint32_t *, uint32_t *, int64_t, hipStream_t);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
-                        hipStream_t);
+                        hipStream_t, const uint32_t *, const uint32_t *, const uint4 *, int);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
-void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t);
+void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                   float *, float *, uint32_t *, hipStream_t);
 int sort_passes(int total_bits);
@@ -36,6 +38,13 @@ bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const
 void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
                         hipStream_t);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
+int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
+                       uint32_t *, uint32_t *, hipStream_t);
+void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
+                             hipStream_t);
+void launch_tile_order(const uint2 *, uint32_t, uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+bool launch_blend_persistent(int, int, int, uint32_t, const ViewDev *, int, const uint2 *, const uint32_t *,
+                             const SplatRec *, const uint32_t *, uint32_t, uint32_t *, hipStream_t);
 }  // namespace recogs
 
 using namespace recogs;
@@ -327,13 +336,13 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     launch_fill_u32(hdr, 0u, H_WORDS, stream);
     RecolorDev rc{opts->mask, opts->M, opts->b};
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
-                      rect, cnt, hdr, stream);
+                      rect, cnt, stream);
     if ((s = tm.mark(1)) != RECOGS_OK) return s;
     {
         const size_t sc_n = ws->scan_chunks;
         uint64_t *pk = at<uint64_t>(ws, ws->off_scan);
         uint32_t *pv = (uint32_t *)(pk + sc_n);
-        launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, stream);
+        launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream);
     }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
@@ -378,11 +387,12 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         // the depth-ordered rectangles (8 bytes each) reuse both depth-key buffers, which are
         // adjacent and no longer needed once the order (values) is known
         uint2 *srect = (uint2 *)dk0;
-        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream);
+        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream,
+                           nullptr, nullptr, nullptr, 1);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
-        launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream);
+        launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream, nullptr);
     } else if (K > 0) {
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
@@ -444,6 +454,206 @@ recogs_status recogs_loss_l2(const float *image, const float *target, int64_t co
     launch_fill_u32((uint32_t *)loss, 0u, 1, stream);
     launch_loss_l2(image, target, count, scale, dL_dimage, loss, stream);
     return hip_check("loss_l2");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaxViews = 4096;
+
+recogs_status check_batch(const recogs_batch_view *views, int32_t nviews) {
+    if (!views || nviews <= 0 || nviews > kMaxViews) return fail(RECOGS_ERR_INVALID, "batch of %d views (1..%d)", nviews, kMaxViews);
+    char msg[sizeof(g_err)];
+    for (int v = 0; v < nviews; ++v) {
+        recogs_status s;
+        if ((s = check_scene(&views[v].scene)) != RECOGS_OK || (s = check_camera(&views[v].cam)) != RECOGS_OK) {
+            memcpy(msg, g_err, sizeof(msg));
+            return fail(s, "view %d: %s", v, msg);
+        }
+        if (views[v].scene.n > 0 && !views[v].scene.cov3d) return fail(RECOGS_ERR_INVALID, "view %d: cov3d is NULL", v);
+        if (!views[v].image) return fail(RECOGS_ERR_INVALID, "view %d: image is NULL", v);
+        const bool any = views[v].mask || views[v].M || views[v].b;
+        if (any && !(views[v].mask && views[v].M && views[v].b))
+            return fail(RECOGS_ERR_INVALID, "view %d: fused recolour needs mask, M and b together", v);
+        if (views[v].scene.storage != views[0].scene.storage || views[v].scene.sh_degree != views[0].scene.sh_degree)
+            return fail(RECOGS_ERR_UNSUPPORTED, "view %d: all scenes of a batch share storage dtype and SH degree", v);
+    }
+    return RECOGS_OK;
+}
+
+size_t batch_layout(recogs_batch_workspace *ws, const recogs_batch_view *views, int32_t nviews, int32_t tw, int32_t th,
+                    int64_t cap) {
+    int64_t P = 0, T = 0;
+    for (int v = 0; v < nviews; ++v) {
+        P += views[v].scene.n;
+        T += (int64_t)((views[v].cam.width + tw - 1) / tw) * ((views[v].cam.height + th - 1) / th);
+    }
+    const int64_t pp = P > 0 ? P : 1;
+    const int64_t cc = cap > 0 ? cap : 1;
+    const int64_t scan_chunks = (pp + kScanChunk - 1) / kScanChunk;
+    const int64_t cnt_chunks = std::max((pp + kSortChunk - 1) / kSortChunk, (cc + kSortChunk - 1) / kSortChunk);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    ws->off_views = take(sizeof(ViewDev) * (size_t)nviews);
+    ws->off_vtab = take(sizeof(uint4) * (size_t)nviews);
+    ws->off_rec = take(sizeof(SplatRec) * (size_t)pp);
+    ws->off_zbits = take(4 * (size_t)pp);
+    ws->off_rect = take(8 * (size_t)pp);
+    ws->off_count = take(4 * (size_t)pp);
+    ws->off_offset = take(4 * (size_t)pp);
+    ws->off_dkeys0 = take(4 * (size_t)pp);
+    ws->off_dkeys1 = take(4 * (size_t)pp);
+    ws->off_dvals0 = take(4 * (size_t)pp);
+    ws->off_dvals1 = take(4 * (size_t)pp);
+    ws->off_scan = take(20 * (size_t)scan_chunks);
+    ws->off_esum = take(4 * (size_t)((pp + kEmitChunk - 1) / kEmitChunk));
+    ws->off_sort_count = take(4 * 256 * (size_t)cnt_chunks);
+    ws->off_keys0 = take(4 * (size_t)cc);
+    ws->off_keys1 = take(4 * (size_t)cc);
+    ws->off_vals0 = take(4 * (size_t)cc);
+    ws->off_vals1 = take(4 * (size_t)cc);
+    ws->off_order = take(4 * (size_t)(T > 0 ? T : 1));
+    // zeroed each batch (contiguous): header, histograms, tile ranges
+    ws->off_header = take(4 * H_WORDS);
+    ws->off_hist = take(4 * 256 * kMaxPasses);
+    ws->off_dhist = take(4 * 256 * kMaxPasses);
+    ws->off_ranges = take(8 * (size_t)(T > 0 ? T : 1));
+    ws->scan_chunks = (size_t)scan_chunks;
+    ws->pairs = P;
+    ws->tiles = T;
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t recogs_batch_workspace_bytes(const recogs_batch_view *views, int32_t nviews, int32_t tile_w, int32_t tile_h,
+                                    int64_t key_capacity) {
+    if (check_batch(views, nviews) != RECOGS_OK || !tile_supported(tile_w, tile_h) || key_capacity < 0) return 0;
+    recogs_batch_workspace ws;
+    memset(&ws, 0, sizeof(ws));
+    return batch_layout(&ws, views, nviews, tile_w, tile_h, key_capacity);
+}
+
+recogs_status recogs_batch_init(recogs_batch_workspace *ws, void *dev_mem, size_t bytes, const recogs_batch_view *views,
+                                int32_t nviews, const recogs_render_opts *opts, int64_t key_capacity) {
+    g_err[0] = 0;
+    recogs_status s;
+    if (!ws || !dev_mem) return fail(RECOGS_ERR_INVALID, "workspace struct or memory is NULL");
+    if ((uintptr_t)dev_mem % kAlign) return fail(RECOGS_ERR_INVALID, "workspace memory not 256-byte aligned");
+    if ((s = check_batch(views, nviews)) != RECOGS_OK) return s;
+    if ((s = check_opts(opts)) != RECOGS_OK) return s;
+    if (key_capacity < 0 || key_capacity > 0x7fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "key capacity not in 0..2^31-1");
+    memset(ws, 0, sizeof(*ws));
+    const size_t need = batch_layout(ws, views, nviews, opts->tile_w, opts->tile_h, key_capacity);
+    if (bytes < need) return fail(RECOGS_ERR_INVALID, "batch workspace has %zu bytes, needs %zu", bytes, need);
+    if (ws->pairs > 0x7fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "batch of %lld pairs exceeds 2^31-1", (long long)ws->pairs);
+    if (ws->tiles > (1LL << 30)) return fail(RECOGS_ERR_UNSUPPORTED, "batch of %lld tiles exceeds 2^30", (long long)ws->tiles);
+    ws->base = dev_mem;
+    ws->bytes = bytes;
+    ws->nviews = nviews;
+    ws->tile_w = opts->tile_w;
+    ws->tile_h = opts->tile_h;
+    ws->px_per_thread = opts->px_per_thread;
+    ws->storage = views[0].scene.storage;
+    ws->sh_degree = views[0].scene.sh_degree;
+    ws->key_capacity = key_capacity;
+    ws->tile_bits = bits_for((uint64_t)(ws->tiles > 0 ? ws->tiles - 1 : 0));
+    int dev = 0, cus = 0;
+    RECOGS_TRY_HIP(hipGetDevice(&dev));
+    RECOGS_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ws->persistent_blocks = (cus > 0 ? cus : 256) * 8;
+    // view table
+    ViewDev *vd = (ViewDev *)calloc((size_t)nviews, sizeof(ViewDev));
+    uint4 *vt = (uint4 *)calloc((size_t)nviews, sizeof(uint4));
+    if (!vd || !vt) {
+        free(vd);
+        free(vt);
+        return fail(RECOGS_ERR_INVALID, "host allocation of the view table failed");
+    }
+    uint32_t pair = 0, blk = 0, tile = 0;
+    for (int v = 0; v < nviews; ++v) {
+        const recogs_batch_view &bv = views[v];
+        vd[v].sc = make_scene(bv.scene);
+        vd[v].cam = make_cam(bv.cam, opts->tile_w, opts->tile_h);
+        vd[v].rc = RecolorDev{bv.mask, bv.M, bv.b};
+        vd[v].image = bv.image;
+        for (int c = 0; c < 3; ++c) vd[v].bg[c] = opts->bg[c];
+        vd[v].pair_base = pair;
+        vd[v].blk_base = blk;
+        vd[v].tile_base = tile;
+        vd[v].ntiles = (uint32_t)(vd[v].cam.tiles_x * vd[v].cam.tiles_y);
+        vt[v] = make_uint4(pair, tile, (uint32_t)vd[v].cam.tiles_x, 0u);
+        pair += (uint32_t)bv.scene.n;
+        blk += (uint32_t)((bv.scene.n + 255) / 256);
+        tile += vd[v].ntiles;
+    }
+    ws->preprocess_blocks = blk;
+    hipError_t e1 = hipMemcpy((char *)dev_mem + ws->off_views, vd, sizeof(ViewDev) * (size_t)nviews, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy((char *)dev_mem + ws->off_vtab, vt, sizeof(uint4) * (size_t)nviews, hipMemcpyHostToDevice);
+    free(vd);
+    free(vt);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(RECOGS_ERR_HIP, "uploading the view table: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return RECOGS_OK;
+}
+
+recogs_status recogs_render_batch(const recogs_batch_workspace *ws, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!ws || !ws->base || ws->nviews <= 0) return fail(RECOGS_ERR_INVALID, "batch workspace not initialised");
+    auto B = [&](size_t off) { return (char *)ws->base + off; };
+    uint32_t *hdr = (uint32_t *)B(ws->off_header);
+    const ViewDev *views = (const ViewDev *)B(ws->off_views);
+    SplatRec *rec = (SplatRec *)B(ws->off_rec);
+    uint32_t *zb = (uint32_t *)B(ws->off_zbits), *cnt = (uint32_t *)B(ws->off_count), *off = (uint32_t *)B(ws->off_offset);
+    uint2 *rect = (uint2 *)B(ws->off_rect);
+    uint32_t *dk0 = (uint32_t *)B(ws->off_dkeys0), *dk1 = (uint32_t *)B(ws->off_dkeys1);
+    uint32_t *dv0 = (uint32_t *)B(ws->off_dvals0), *dv1 = (uint32_t *)B(ws->off_dvals1);
+    uint32_t *k0 = (uint32_t *)B(ws->off_keys0), *k1 = (uint32_t *)B(ws->off_keys1);
+    uint32_t *v0 = (uint32_t *)B(ws->off_vals0), *v1 = (uint32_t *)B(ws->off_vals1);
+    uint32_t *hist = (uint32_t *)B(ws->off_hist), *dhist = (uint32_t *)B(ws->off_dhist);
+    uint32_t *scount = (uint32_t *)B(ws->off_sort_count);
+    uint2 *ranges = (uint2 *)B(ws->off_ranges);
+    const uint32_t P = (uint32_t)ws->pairs, T = (uint32_t)ws->tiles, cap = (uint32_t)ws->key_capacity;
+    // header, histograms and ranges are contiguous
+    launch_fill_u32(hdr, 0u, (int64_t)((ws->off_ranges - ws->off_header) / 4) + 2 * (int64_t)T, stream);
+    launch_preprocess_batch(ws->storage, ws->sh_degree, ws->preprocess_blocks, views, ws->nviews, rec, zb, rect, cnt, stream);
+    {
+        const size_t sc_n = ws->scan_chunks;
+        uint64_t *pk = (uint64_t *)B(ws->off_scan);
+        uint32_t *pv = (uint32_t *)(pk + sc_n);
+        launch_scan(cnt, zb, off, P, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream);
+    }
+    // depth sort of the pairs with keys over all 32 depth bits above the minimum
+    const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, P, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist, scount, stream);
+    launch_emit_sorted(dalt ? dv1 : dv0, P, rect, (uint2 *)dk0, 0, (uint32_t *)B(ws->off_esum), k0, v0, stream, hdr + H_V,
+                       hdr, (const uint4 *)B(ws->off_vtab), ws->nviews);
+    const int alt = radix_sort_u32_dyn(k0, v0, k1, v1, cap, hdr + H_KEFF, nullptr, ws->tile_bits, hist, scount, stream);
+    launch_ranges32(alt ? k1 : k0, cap, ranges, stream, hdr + H_KEFF);
+    launch_tile_order(ranges, T, hdr + H_ORDER_HIST, hdr + H_ORDER_CUR, (uint32_t *)B(ws->off_order), stream);
+    if (!launch_blend_persistent(ws->tile_w, ws->tile_h, ws->px_per_thread, (uint32_t)ws->persistent_blocks, views,
+                                 ws->nviews, ranges, alt ? v1 : v0, rec, (const uint32_t *)B(ws->off_order), T,
+                                 hdr + H_QUEUE, stream))
+        return fail(RECOGS_ERR_UNSUPPORTED, "no persistent blend for this tile / px_per_thread");
+    return hip_check("render_batch");
+}
+
+recogs_status recogs_batch_readback(recogs_batch_workspace *ws, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!ws || !ws->base) return fail(RECOGS_ERR_INVALID, "batch workspace not initialised");
+    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    RECOGS_TRY_HIP(hipMemcpyAsync(h, (char *)ws->base + ws->off_header, sizeof(h), hipMemcpyDeviceToHost, stream));
+    RECOGS_TRY_HIP(hipStreamSynchronize(stream));
+    ws->num_keys = (int64_t)((uint64_t)h[H_K_LO] | ((uint64_t)h[H_K_HI] << 32));
+    ws->num_visible = h[H_V];
+    ws->overflow = (int32_t)h[H_OVERFLOW];
+    ws->sorted_in_alt = ws->tile_bits > 0 ? (sort_passes(ws->tile_bits) & 1) : 0;
+    return RECOGS_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,133 @@
+"""The C-ABI library: exports, struct layout and host-side argument errors (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "recogs.h")
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2511_18441_amd as R
+    return R
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(recogs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported(R):
+    names = declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", R.binding.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (recogs_[a-z0-9_]+)", out))
+    assert set(names) <= exported, set(names) - exported
+    assert set(R.ENTRY_POINTS) | set(R.BATCH_ENTRY_POINTS) == set(names)
+
+
+PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "recogs.h"
+#define S(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  S(recogs_scene) S(recogs_camera) S(recogs_select_params) S(recogs_render_opts) S(recogs_workspace)
+  S(recogs_batch_view) S(recogs_batch_workspace)
+  O(recogs_render_opts, mask) O(recogs_render_opts, sort_mode)
+  O(recogs_workspace, off_rec) O(recogs_workspace, num_keys) O(recogs_workspace, stage_ms)
+  O(recogs_batch_workspace, pairs) O(recogs_batch_workspace, off_views) O(recogs_batch_workspace, num_keys)
+  O(recogs_batch_view, image)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_binding(R):
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write(PROBE)
+        subprocess.run(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", src, "-o", exe], check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in lines if l)
+    C = {"recogs_scene": R.Scene, "recogs_camera": R.Camera, "recogs_select_params": R.SelectParams,
+         "recogs_render_opts": R.RenderOpts, "recogs_workspace": R.Workspace, "recogs_batch_view": R.BatchView,
+         "recogs_batch_workspace": R.BatchWorkspace}
+    for name, cls in C.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+    for key, v in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(C[t], f).offset == int(v), key
+
+
+def test_host_argument_errors_before_any_launch(R):
+    B = R.binding
+    cam = B.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy = 64, 64, 50.0, 50.0, 32.0, 32.0
+    cam.R[0] = cam.R[4] = cam.R[8] = 1.0
+    sc = B.Scene()
+    sc.n, sc.stride, sc.sh_degree, sc.storage = 0, 0, 0, 0
+    ws = B.Workspace()
+    opts = B.opts_struct((16, 16), 1)
+
+    def status(fn, *a):
+        with pytest.raises(R.RecogsError) as e:
+            fn(*a)
+        assert R.recogs_last_error() != ""
+        return e.value.status
+
+    # workspace not initialised
+    assert status(B.recogs_render, sc, cam, opts, ws, 1, 0) == -1
+    # unsupported tile shape / pixels per thread
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 8), 1), ws, 1, 0) == -3
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 3), ws, 1, 0) == -3
+    # invalid scene fields
+    bad = B.Scene()
+    bad.n, bad.stride, bad.sh_degree = 10, 5, 0
+    assert status(B.recogs_select, bad, cam, B.SelectParams(), 1, 1, 0) == -1
+    bad.stride, bad.sh_degree = 10, 4
+    assert status(B.recogs_select, bad, cam, B.SelectParams(), 1, 1, 0) == -1
+    bad.sh_degree, bad.storage = 0, 7
+    assert status(B.recogs_select, bad, cam, B.SelectParams(), 1, 1, 0) == -1
+    bad.storage = 0
+    assert status(B.recogs_select, bad, cam, B.SelectParams(), 1, 1, 0) == -1  # null pointers with n > 0
+    # invalid camera
+    cam2 = B.Camera()
+    assert status(B.recogs_select, sc, cam2, B.SelectParams(), 1, 1, 0) == -1
+    # half a fused recolour
+    o2 = B.opts_struct((16, 16), 1)
+    o2.mask = 8
+    assert status(B.recogs_render, sc, cam, o2, ws, 1, 0) == -1
+    # workspace sizing and carving
+    assert R.recogs_workspace_bytes(-1, 64, 64, 16, 16, 10) == 0
+    assert R.recogs_workspace_bytes(10, 64, 64, 16, 8, 10) == 0
+    need = R.recogs_workspace_bytes(100, 64, 64, 16, 16, 1000)
+    assert need > 0
+    assert status(R.recogs_workspace_init, ws, 256, need - 1, 100, 64, 64, 16, 16, 1000) == -1
+    assert status(R.recogs_workspace_init, ws, 257, need, 100, 64, 64, 16, 16, 1000) == -1
+    # loss
+    assert status(B.recogs_loss_l2, 0, 0, 10, 1.0, 0, 0, 0) == -1
+    # batch: empty, and mixed storage
+    views = (B.BatchView * 2)()
+    assert R.recogs_batch_workspace_bytes(views, 0, 16, 16, 10) == 0
+    for k in range(2):
+        views[k].scene = sc
+        views[k].cam = cam
+        views[k].image = 64
+    views[1].scene.storage = 1
+    assert R.recogs_batch_workspace_bytes(views, 2, 16, 16, 10) == 0
+    bw = B.BatchWorkspace()
+    assert status(R.recogs_batch_init, bw, 256, 1 << 20, views, 2, opts, 10) == -3
+    assert status(R.recogs_render_batch, bw, 0) == -1
