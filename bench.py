@@ -5,11 +5,21 @@ the FP64 CPU oracle timed beside it.
 A step (frame) = recogs_recolor of the selected Gaussians (out of place, from the
 pristine SH into the render copy, so frames do not compound the edit) followed by
 recogs_render of the edited scene. Inputs are resident in HBM before timing starts.
+The timed frames record HIP events between the render's stages on the render stream
+(profile mode 2: recorded, never waited on); the dominant kernel's average duration
+comes from those events.
+
+Besides the headline (FP32 storage) the same run measures the other forms on the same
+GPU: FP16 and BF16 storage of the same scene, the batched form (8 scenes of 0.1M-3M
+Gaussians x 4 views, one HIP-graph replay per batch, tile shape and pixels per thread
+from the autotuner; beside it the same 32 renders one call at a time), and the
+differentiation form (8 views at 1280x720: forward, L2 loss and backward).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|bf16]
-                  [--no-cpu-baseline] [--copy-calibration]
+                  [--no-cpu-baseline] [--no-forms] [--copy-calibration]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,12 +31,39 @@ if ROOT not in sys.path:
 
 METRIC = "recolor+render frames/s (1M Gaussians, 1080p) and HBM-roofline fraction"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz)
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz, packed FMA)
 BLEND_FLOPS_PER_EVAL = 23        # dx, dy, exponent (2 mul + 3 fma), test, exp2, clamp, T, weight, 3 fma
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_16x16_ppt2_1M_1080p_f32.traffic.txt")
+BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
+                 "paper_2511_18441_amd/csrc/recogs_internal.hpp")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def blend_source_sha1():
+    h = hashlib.sha1()
+    for p in BLEND_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprof counter summary, or
+    None when there is none or the blend sources changed since it was taken."""
+    try:
+        kv = dict(l.split(":", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ":" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("blend_sources_sha1") != blend_source_sha1():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_model(st, storage_bytes, deg, keep_bwd=False):
@@ -48,141 +85,112 @@ def algorithmic_model(st, storage_bytes, deg, keep_bwd=False):
     return b, {"blend": E * BLEND_FLOPS_PER_EVAL}
 
 
-def cpu_baseline(w, sample_windows=24):
-    """The oracle as it stands on this host: recolour + projection of every Gaussian,
-    per-pixel compositing of a sample of 32x32 windows, extrapolated to a frame."""
-    import numpy as np
-    from oracle import oracle as orc
-    orc.lib()
-    v = w.view
-    t0 = time.perf_counter()
-    mask, _ = orc.select(w.scene, v.camera, v.select)
-    t1 = time.perf_counter()
-    sh2 = orc.recolor(w.scene.sh_f32(), mask, v.recolor.M.astype(np.float64), v.recolor.b.astype(np.float64))
-    t2 = time.perf_counter()
-    import synth
-    sc2 = synth.Scene(w.scene.means, w.scene.log_scales, w.scene.quats, w.scene.opacity, sh2, w.scene.sh_degree)
-    pr = orc.project(sc2, v.camera, (16, 16))
-    t3 = time.perf_counter()
-    rng = np.random.default_rng(7)
-    W, H = v.camera.width, v.camera.height
-    wins = [(int(rng.integers(0, W - 32)), int(rng.integers(0, H - 32)), 32, 32) for _ in range(sample_windows)]
-    orc.render_windows(pr, wins)
-    t4 = time.perf_counter()
-    frac = sample_windows * 32 * 32 / (W * H)
-    t_frame = (t2 - t1) + (t3 - t2) + (t4 - t3) / frac
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / t_frame, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": (f"recolour ({t2 - t1:.2f} s) and projection ({t3 - t2:.2f} s, 1 thread) of all "
-                       f"{w.scene.n} Gaussians, then per-pixel compositing of {sample_windows} random 32x32 windows "
-                       f"({t4 - t3:.2f} s on {cores} threads, {100 * frac:.2f}% of the frame) scaled to the whole frame"),
-            "seconds_measured": round(t4 - t0, 2)}
+class Single:
+    """One scene + view resident on the GPU, with its selection mask, recolour and
+    workspace: a frame is recolour (selected, out of place) + render."""
 
+    def __init__(self, R, w, dev, tile, ppt):
+        import torch
+        self.R, self.w, self.tile, self.ppt = R, w, tuple(tile), int(ppt)
+        v = w.view
+        self.cam = v.camera
+        self.n = w.scene.n
+        self.d = R.DeviceScene(w.scene, device=dev)
+        self.scs = self.d.c_struct()
+        self.camc = R.camera_struct(self.cam)
+        self.selc = R.select_struct(v.select)
+        self.mask = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        self.count = torch.empty(1, dtype=torch.int32, device=dev)
+        self.select()
+        self.M = torch.from_numpy(v.recolor.M.reshape(9)).to(dev)
+        self.b = torch.from_numpy(v.recolor.b).to(dev)
+        self.render_sh = self.d.sh.clone()
+        self.ws = R.DeviceWorkspace(self.n, self.cam.width, self.cam.height, self.tile, key_capacity=16 * self.n,
+                                    device=dev)
+        self.image = torch.empty((self.cam.height, self.cam.width, 3), dtype=torch.float32, device=dev)
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--tile", type=int, nargs=2, default=[16, 16])
-    ap.add_argument("--ppt", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this path has no multi-GPU form (see DESIGN.md, sharding)",
-              file=sys.stderr)
-        sys.exit(2)
+    def select(self):
+        self.R.recogs_select(self.scs, self.camc, self.selc, self.mask.data_ptr(), self.count.data_ptr())
 
-    import numpy as np
-    import torch
+    def recolor(self):
+        self.R.recogs_recolor(self.scs, self.render_sh.data_ptr(), self.mask.data_ptr(), self.M.data_ptr(),
+                              self.b.data_ptr(), 0)
 
-    import paper_2511_18441_amd as R
-    import synth
+    def frame(self, profile=0):
+        self.recolor()
+        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
+                      profile=profile)
 
-    dev = "cuda:0"
-    torch.cuda.set_device(0)
-    log(f"bench: generating 1M-Gaussian scene ({args.storage})")
-    w = synth.make_precision(storage=args.storage)
-    v = w.view
-    cam = v.camera
-    n = w.scene.n
-    sb = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
-    d = R.DeviceScene(w.scene, device=dev)
-    scs = d.c_struct()
-    camc = R.camera_struct(cam)
-    mask = torch.empty(n, dtype=torch.uint8, device=dev)
-    count = torch.empty(1, dtype=torch.int32, device=dev)
-    R.recogs_select(scs, camc, R.select_struct(v.select), mask.data_ptr(), count.data_ptr())
-    M = torch.from_numpy(v.recolor.M.reshape(9)).to(dev)
-    bvec = torch.from_numpy(v.recolor.b).to(dev)
-    render_sh = d.sh.clone()
-    ws = R.DeviceWorkspace(n, cam.width, cam.height, tuple(args.tile), key_capacity=16 * n, device=dev)
-    image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dev)
-    tile = tuple(args.tile)
-
-    def step(profile=False):
-        R.recogs_recolor(scs, render_sh.data_ptr(), mask.data_ptr(), M.data_ptr(), bvec.data_ptr(), 0)
-        R.render(d, cam, ws, tile, args.ppt, image=image, sh=render_sh, profile=profile)
-
-    log("bench: warmup")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} frames")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = 1000.0 * (t1 - t0) / args.steps
-    ms_ev = ev0.elapsed_time(ev1) / args.steps
-    fps = 1000.0 / ms
-
-    # per-stage durations (HIP events recorded by the library on the render stream)
-    log("bench: stage profile")
-    nprof = max(5, min(20, args.steps))
-    stage = np.zeros(8)
-    rec_ms = 0.0
-    for _ in range(nprof):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        R.recogs_recolor(scs, render_sh.data_ptr(), mask.data_ptr(), M.data_ptr(), bvec.data_ptr(), 0)
-        e1.record()
-        R.render(d, cam, ws, tile, args.ppt, image=image, sh=render_sh, profile=True)
+    def timed(self, steps, profile):
+        """Wall-clock ms per frame over `steps` frames, bracketed by device syncs."""
+        import torch
         torch.cuda.synchronize()
-        rec_ms += e0.elapsed_time(e1)
-        stage += np.array(ws.ws.stage_ms[:])
-    stage /= nprof
-    rec_ms /= nprof
-    stages = dict(zip(R.binding.STAGES, stage.tolist()))
-    stages["recolor"] = rec_ms
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.frame(profile)
+        torch.cuda.synchronize()
+        return 1000.0 * (time.perf_counter() - t0) / steps
 
-    # counts of this frame
-    K = int(ws.ws.num_keys)
-    cnt = ws.counts(n)
-    V = int((cnt != 0).sum().item())
-    S = int(count.item())
-    P = int(ws.ws.sort_passes)
-    Pd = int(ws.ws.depth_passes)
-    T = ws.ws.tiles_x * ws.ws.tiles_y
-    nproc = ws.nproc().to(torch.int64)
-    E = int(nproc.sum().item())
-    th, tw = tile[1], tile[0]
-    Hp, Wp = ws.ws.tiles_y * th, ws.ws.tiles_x * tw
-    npad = torch.zeros((Hp, Wp), dtype=torch.int64, device=dev)
-    npad[:cam.height, :cam.width] = nproc
-    keff = int(npad.view(ws.ws.tiles_y, th, ws.ws.tiles_x, tw).amax(dim=(1, 3)).sum().item())
-    st = dict(N=n, V=V, K=K, S=S, passes=P, dpasses=Pd, tiles=T, pix=cam.width * cam.height, evals=E, keff=keff)
-    bytes_, flops = algorithmic_model(st, sb, w.scene.sh_degree)
-    launches = {"key_sort": P + 1, "depth_sort": Pd + 1}
-    per_kernel = {}
+    def event_ms(self, fn, reps):
+        import torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def measure(self, steps, warmup):
+        """Warm-up; the timed frames, whose blend launches are bracketed by HIP events on
+        the render stream (mode 2: recorded, never waited on); the same number of frames
+        without any event (overhead check); then a short pass with events between all
+        stages (mode 1, waits per frame) for the per-stage breakdown."""
+        import numpy as np
+        for _ in range(warmup):
+            self.frame()
+        ws = self.ws.ws
+        self.R.recogs_workspace_profile_flush(ws)
+        for k in range(8):
+            ws.stage_ms_sum[k] = 0.0
+        ws.profiled_frames = 0
+        ms = self.timed(steps, 2)
+        blend_ms, nfr = self.ws.blend_time()
+        ms_plain = self.timed(steps, 0)
+        nprof = max(5, min(20, steps))
+        acc = np.zeros(8)
+        for _ in range(nprof):
+            self.frame(1)
+            acc += np.array(ws.stage_ms[:])
+        stages = dict(zip(self.R.binding.STAGES, (acc / nprof).tolist()))
+        stages["recolor"] = self.event_ms(self.recolor, max(10, steps // 2))
+        sel_ms = self.event_ms(self.select, max(10, steps // 2))
+        return {"ms": ms, "ms_no_events": ms_plain, "stages": stages, "blend_ms_timed": blend_ms,
+                "profiled_frames": nfr, "select_ms": sel_ms}
+
+    def counts(self):
+        import torch
+        ws = self.ws
+        K = int(ws.ws.num_keys)
+        cnt = ws.counts(self.n)
+        V = int((cnt != 0).sum().item())
+        S = int(self.count.item())
+        T = ws.ws.tiles_x * ws.ws.tiles_y
+        nproc = ws.nproc().to(torch.int64)
+        E = int(nproc.sum().item())
+        tw, th = self.tile
+        Hp, Wp = ws.ws.tiles_y * th, ws.ws.tiles_x * tw
+        npad = torch.zeros((Hp, Wp), dtype=torch.int64, device=nproc.device)
+        npad[:self.cam.height, :self.cam.width] = nproc
+        keff = int(npad.view(ws.ws.tiles_y, th, ws.ws.tiles_x, tw).amax(dim=(1, 3)).sum().item())
+        return dict(N=self.n, V=V, K=K, S=S, passes=int(ws.ws.sort_passes), dpasses=int(ws.ws.depth_passes), tiles=T,
+                    pix=self.cam.width * self.cam.height, evals=E, keff=keff)
+
+
+def stage_table(stages, bytes_, flops, st):
+    launches = {"key_sort": st["passes"] + 1, "depth_sort": st["dpasses"] + 1}
+    out = {}
     for k, t in stages.items():
         if k == "readback":
             continue
@@ -193,39 +201,277 @@ def main():
             ent["GBps"] = round(bytes_[k] / (t * 1e-3) / 1e9, 1)
         if k in flops and t > 0:
             ent["TFLOPs"] = round(flops[k] / (t * 1e-3) / 1e12, 2)
-        per_kernel[k] = ent
-    dom = max((k for k in per_kernel), key=lambda k: per_kernel[k]["ms_per_frame"])
+        out[k] = ent
+    return out, launches
+
+
+def form_single(R, storage, tile, ppt, steps, warmup, dev):
+    import synth
+    log(f"bench: form {storage} storage")
+    w = synth.make_precision(storage=storage)
+    s = Single(R, w, dev, tile, ppt)
+    m = s.measure(steps, warmup)
+    st = s.counts()
+    sb = {"f32": 4, "f16": 2, "bf16": 2}[storage]
+    bytes_, _ = algorithmic_model(st, sb, w.scene.sh_degree)
+    fps = 1000.0 / m["ms"]
+    tot = sum(bytes_.values())
+    res = {"storage": storage, "frames_per_s": round(fps, 2), "ms_per_frame": round(m["ms"], 4),
+           "gaussians_per_s": round(fps * s.n, 1), "blend_ms": round(m["blend_ms_timed"], 4),
+           "preprocess_ms": round(m["stages"]["preprocess"], 4), "recolor_ms": round(m["stages"]["recolor"], 4),
+           "frame_hbm_frac": round(tot * fps / 1e9 / HBM_PEAK_GBS, 4), "K": st["K"], "V": st["V"]}
+    del s
+    return res
+
+
+def form_batch(R, steps, warmup, dev):
+    """8 scenes (0.1M..3M Gaussians, FP16, SH 3) x 4 views, each view with its own
+    selection and hue rotation fused into the render; one HIP-graph replay per batch."""
+    import torch
+
+    import synth
+    from paper_2511_18441_amd import autotune
+    log("bench: form batch: generating 8 scenes (9.35M Gaussians)")
+    w = synth.make_batch()
+    dscenes = [R.DeviceScene(sc, device=dev) for sc in w.scenes]
+    views = []
+    for v in w.views:
+        d = dscenes[v.scene]
+        mask = torch.zeros(max(d.n, 1), dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+        R.recogs_select(d.c_struct(), R.camera_struct(v.camera), R.select_struct(v.select), mask.data_ptr(),
+                        cnt.data_ptr())
+        views.append((v.scene, v.camera, mask, torch.from_numpy(v.recolor.M.reshape(9).copy()).to(dev),
+                      torch.from_numpy(v.recolor.b.copy()).to(dev)))
+    log("bench: form batch: autotuning the blend shape")
+    tuned = autotune.tune_batch(dscenes, views, reps=3, cache=None)
+    tile, ppt = tuple(tuned["tile"]), tuned["ppt"]
+    b = R.DeviceBatch(dscenes, views, tile, ppt)
+    g = b.capture_graph()
+    for _ in range(max(2, warmup // 4)):
+        g.replay()
+    reps = max(5, steps // 10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    K, ovf = b.readback()
+    pairs = sum(dscenes[si].n for (si, *_r) in views)
+    pix = sum(c.width * c.height for (_, c, *_r) in views)
+    del g, b
+    # the same 32 renders, one recogs_render call each (fused recolour, same blend shape)
+    log("bench: form batch: the same renders one call at a time")
+    wss = {}
+    imgs = []
+    for (si, cam, mask, M, bb) in views:
+        key = (si, cam.width, cam.height)
+        if key not in wss:
+            wss[key] = R.DeviceWorkspace(dscenes[si].n, cam.width, cam.height, tile, device=dev)
+        imgs.append(torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dev))
+
+    def singles():
+        for k, (si, cam, mask, M, bb) in enumerate(views):
+            R.render(dscenes[si], cam, wss[(si, cam.width, cam.height)], tile, ppt, mask=mask, M=M, b=bb,
+                     image=imgs[k])
+    singles()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(3, reps // 2)):
+        singles()
+    torch.cuda.synchronize()
+    ms_single = 1000.0 * (time.perf_counter() - t0) / max(3, reps // 2)
+    nv = len(views)
+    return {"renders_per_batch": nv, "scenes": [d.n for d in dscenes], "storage": "f16", "tile": f"{tile[0]}x{tile[1]}",
+            "px_per_thread": ppt, "autotune_ms": {f"{r['tile'][0]}x{r['tile'][1]}p{r['ppt']}": r["ms"]
+                                                   for r in tuned["table"]},
+            "ms_per_batch": round(ms, 3), "frames_per_s": round(nv * 1000.0 / ms, 1),
+            "gaussians_per_s": round(pairs * 1000.0 / ms, 1), "megapixels_per_s": round(pix / ms / 1e3, 1),
+            "keys": K, "overflow": ovf,
+            "one_call_each": {"ms_per_32_renders": round(ms_single, 3),
+                              "frames_per_s": round(nv * 1000.0 / ms_single, 1)}}
+
+
+def form_diff(R, steps, warmup, dev):
+    """1M Gaussians (FP32, SH 3), 8 views at 1280x720: render with the fused recolour
+    (keeping the backward state), L2 loss against a seeded target, backward to the
+    opacities, the SH DC coefficients and M."""
+    import torch
+
+    import synth
+    log("bench: form diff: 1M Gaussians, 8 views at 1280x720")
+    w = synth.make_diff()
+    d = R.DeviceScene(w.scene, device=dev)
+    n = d.n
+    sc = d.c_struct()
+    v0 = w.views[0]
+    mask = torch.empty(n, dtype=torch.uint8, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    R.recogs_select(sc, R.camera_struct(v0.camera), R.select_struct(v0.select), mask.data_ptr(), cnt.data_ptr())
+    M = torch.from_numpy(v0.recolor.M.reshape(9).copy()).to(dev)
+    Mt = torch.from_numpy(w.extra["M_target"].reshape(9).copy()).to(dev)
+    b = torch.zeros(3, dtype=torch.float32, device=dev)
+    W, H = v0.camera.width, v0.camera.height
+    ws = [R.DeviceWorkspace(n, W, H, (16, 16), device=dev) for _ in w.views]
+    targets = []
+    for k, v in enumerate(w.views):
+        t = R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=Mt, b=b).clone()
+        t += torch.from_numpy(synth.random_image(w.extra["noise_seed"] + k, (H, W, 3), w.extra["noise_sd"])).to(dev)
+        targets.append(t)
+    imgs = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in w.views]
+    dimg = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    dop = torch.empty(n, dtype=torch.float32, device=dev)
+    ddc = torch.empty((3, n), dtype=torch.float32, device=dev)
+    dM = torch.empty(9, dtype=torch.float32, device=dev)
+    scale = 1.0 / (len(w.views) * H * W * 3)
+    cams = [R.camera_struct(v.camera) for v in w.views]
+    o = R.opts_struct((16, 16), 2, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True)
+
+    def step():
+        loss.zero_()
+        for k, v in enumerate(w.views):
+            R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+            R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
+                             loss.data_ptr())
+            R.recogs_render_backward(sc, cams[k], o, ws[k].ws, imgs[k].data_ptr(), dimg.data_ptr(), dop.data_ptr(),
+                                     ddc.data_ptr(), dM.data_ptr())
+    for _ in range(max(2, warmup // 4)):
+        step()
+    reps = max(3, steps // 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    # forward alone, for the backward's share
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for k, v in enumerate(w.views):
+            R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+    torch.cuda.synchronize()
+    ms_fwd = 1000.0 * (time.perf_counter() - t0) / reps
+    return {"views": len(w.views), "width": W, "height": H, "gaussians": n,
+            "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
+            "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.item()),
+            "grad_M_norm": float(dM.norm().item())}
+
+
+def cpu_baseline(w):
+    """The oracle as it stands on this host, on one whole frame of the same workload:
+    recolour and projection of every Gaussian (one thread), then per-pixel compositing
+    of the whole image, window by window (OpenMP over 32x32 windows)."""
+    import numpy as np
+
+    import synth
+    from oracle import oracle as orc
+    orc.lib()
+    v = w.view
+    t0 = time.perf_counter()
+    mask, _ = orc.select(w.scene, v.camera, v.select)
+    t1 = time.perf_counter()
+    sh2 = orc.recolor(w.scene.sh_f32(), mask, v.recolor.M.astype(np.float64), v.recolor.b.astype(np.float64))
+    t2 = time.perf_counter()
+    sc2 = synth.Scene(w.scene.means, w.scene.log_scales, w.scene.quats, w.scene.opacity, sh2, w.scene.sh_degree)
+    pr = orc.project(sc2, v.camera, (16, 16))
+    t3 = time.perf_counter()
+    W, H = v.camera.width, v.camera.height
+    wins = [(x, y, min(32, W - x), min(32, H - y)) for y in range(0, H, 32) for x in range(0, W, 32)]
+    orc.render_windows(pr, wins)
+    t4 = time.perf_counter()
+    t_frame = t4 - t1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(1.0 / t_frame, 6), "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": (f"one whole {W}x{H} frame of the same workload: recolour ({t2 - t1:.2f} s) and projection "
+                       f"({t3 - t2:.2f} s, 1 thread) of all {w.scene.n} Gaussians, per-pixel compositing of "
+                       f"{len(wins)} windows ({t4 - t3:.2f} s on {cores} threads); selection ({t1 - t0:.2f} s) "
+                       "not counted, as on the GPU"),
+            "seconds_measured": round(t4 - t0, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--tile", type=int, nargs=2, default=[16, 16])
+    ap.add_argument("--ppt", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this path has no multi-GPU form (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2511_18441_amd as R
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    tile = tuple(args.tile)
+    tw, th = tile
+    log(f"bench: generating 1M-Gaussian scene ({args.storage})")
+    w = synth.make_precision(storage=args.storage)
+    s = Single(R, w, dev, tile, args.ppt)
+    log(f"bench: warmup {args.warmup}, timing {args.steps} frames")
+    m = s.measure(args.steps, args.warmup)
+    ms = m["ms"]
+    fps = 1000.0 / ms
+    st = s.counts()
+    sb = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    bytes_, flops = algorithmic_model(st, sb, w.scene.sh_degree)
+    per_kernel, launches = stage_table(m["stages"], bytes_, flops, st)
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_frame"])
     nl = launches.get(dom, 1)
-    avg = stages[dom] / nl
+    avg = m["stages"][dom] / nl
     if dom == "blend":
+        avg = m["blend_ms_timed"]  # measured over the timed frames themselves
+        kname = f"k_blend<{tw},{th},{args.ppt}>"
         ach = flops["blend"] / (avg * 1e-3) / 1e12
-        roof = {"kernel": "k_blend<16,16,1>", "bound": "alu", "achieved": round(ach, 3),
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg, 4),
-                "work_per_launch": f"{E} pixel-splat evaluations x {BLEND_FLOPS_PER_EVAL} flops"}
+        traffic = recorded_traffic(kname) if args.storage == "f32" else None
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": kname,
+                "avg_launch_ms": round(avg, 4), "launches_timed": m["profiled_frames"],
+                "work_per_launch": f"{st['evals']} pixel-splat evaluations x {BLEND_FLOPS_PER_EVAL} flops",
+                "alg_bytes_per_launch": int(bytes_["blend"]),
+                "hbm_GBps_alg": round(bytes_["blend"] / (avg * 1e-3) / 1e9, 1)}
     else:
         ach = bytes_[dom] / nl / (avg * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_ms": round(avg, 4),
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_ms": round(avg, 4), "launches_timed": m["profiled_frames"],
                 "work_per_launch": f"{int(bytes_[dom] / nl)} algorithmic bytes"}
     tot_bytes = sum(bytes_.values())
     res = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"1M Gaussians SH deg 3, 1920x1080, 16x16 tiles, {args.storage} storage; "
-                               "recolor(selected) + render", "gaussians": n, "width": cam.width,
-                   "height": cam.height, "sh_degree": 3, "storage": args.storage, "tile": f"{tw}x{th}",
+        "config": {"workload": f"1M Gaussians SH deg 3, 1920x1080, {tw}x{th} tiles, {args.storage} storage; "
+                               "recolor(selected) + render", "gaussians": s.n, "width": s.cam.width,
+                   "height": s.cam.height, "sh_degree": 3, "storage": args.storage, "tile": f"{tw}x{th}",
                    "px_per_thread": args.ppt},
-        "gaussians_per_s": round(fps * n, 1),
+        "gaussians_per_s": round(fps * s.n, 1),
         "frame_hbm_roofline": {"alg_bytes_per_frame": int(tot_bytes),
                                "GBps": round(tot_bytes * fps / 1e9, 1),
                                "frac": round(tot_bytes * fps / 1e9 / HBM_PEAK_GBS, 4)},
-        "ms_per_step_gpu_events": round(ms_ev, 4),
+        "ms_per_step_without_blend_events": round(m["ms_no_events"], 4),
+        "stage_breakdown": "separate pass with events between all stages (waits per frame)",
+        "select_ms": round(m["select_ms"], 4),
+        "select_recolor_render_fps": round(1000.0 / (ms + m["select_ms"]), 2),
         "roofline": roof,
         "stages": per_kernel,
         "counts": st,
     }
+    del s
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -234,6 +480,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = 1 << 30
+        del src, dst
+    if not args.no_forms:
+        forms = {}
+        for stg in ("f32", "f16", "bf16"):
+            if stg != args.storage:
+                forms[stg] = form_single(R, stg, tile, args.ppt, args.steps, args.warmup, dev)
+        forms["batch"] = form_batch(R, args.steps, args.warmup, dev)
+        forms["diff"] = form_diff(R, args.steps, args.warmup, dev)
+        res["forms"] = forms
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("bench: oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline(w)

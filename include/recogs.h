@@ -93,8 +93,16 @@ typedef struct {
     const float *M;
     const float *b;
     int32_t keep_backward_state; /* 1: store what recogs_render_backward needs */
-    int32_t profile_stages;      /* 1: time each stage with HIP events on `stream` (the call then
-                                    waits for the blend); times land in ws->stage_ms */
+    /* Stage timing with HIP events recorded on `stream`.
+     * 0: off. 1: events between all stages; this call waits for its blend and writes the
+     * durations to ws->stage_ms. 2: the blend's duration, accumulated without waiting:
+     * events are recorded just before and after the blend launch only (an event between
+     * two kernels delays the second one's dispatch by microseconds), and the duration
+     * of the workspace's previous mode-2 call (complete by then) is added to
+     * ws->stage_ms_sum[7] with ws->profiled_frames incremented, at this call's
+     * key-count read-back; recogs_workspace_profile_flush adds the last one. Mode 2
+     * creates its event objects on first use; recogs_workspace_release destroys them. */
+    int32_t profile_stages;
     /* How the (tile, depth, index) order of the tile lists is produced; both give the
      * same order. 0 (default): sort the Gaussians with keys by depth (32-bit keys),
      * emit their tile keys in that order, then stable-sort the tile ids (the LSD
@@ -138,6 +146,11 @@ typedef struct {
     /* with profile_stages: milliseconds of [0] preprocess, [1] scan, [2] key-count read-back,
      * [3] depth sort, [4] key emission, [5] key sort, [6] tile ranges, [7] blend */
     float stage_ms[8];
+    /* with profile_stages = 2: [7] sums the blend's milliseconds over profiled_frames
+     * calls (the other entries stay 0); zeroed by recogs_workspace_init */
+    double stage_ms_sum[8];
+    int64_t profiled_frames;
+    void *profile_state;         /* host-side event objects of mode 2 (library-owned) */
 } recogs_workspace;
 
 /* ---- support --------------------------------------------------------------- */
@@ -152,6 +165,15 @@ size_t recogs_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t 
 recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t bytes, int64_t n,
                                     int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
                                     int64_t key_capacity);
+
+/* Wait for the workspace's last profile_stages = 2 render and add its stage durations
+ * to stage_ms_sum / profiled_frames. OK when nothing is pending. */
+recogs_status recogs_workspace_profile_flush(recogs_workspace *ws);
+
+/* Destroy the event objects that profile_stages = 2 created (no-op otherwise). Call it
+ * before re-initialising or dropping a workspace that was profiled in mode 2; the
+ * device memory stays the caller's. */
+void recogs_workspace_release(recogs_workspace *ws);
 
 /* eq. (1): cov3d = R S S^T R^T from log-scales float [3][stride] and quaternions
  * float [4][stride] (w, x, y, z; normalised here). Output float [6][stride]. */

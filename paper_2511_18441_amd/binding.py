@@ -23,8 +23,9 @@ STATUS = {0: "OK", -1: "INVALID", -2: "CAPACITY", -3: "UNSUPPORTED", -4: "HIP"}
 STORAGE_CODE = {"f32": RECOGS_F32, "f16": RECOGS_F16, "bf16": RECOGS_BF16}
 
 # every entry point declared in include/recogs.h
-ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_prepare_covariance", "recogs_select",
-                "recogs_recolor", "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_last_error")
+ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_workspace_profile_flush",
+                "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
+                "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -70,7 +71,9 @@ class Workspace(ctypes.Structure):
                [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("sort_mode", ctypes.c_int32),
                 ("key_bytes", ctypes.c_int32), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("depth_passes", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32),
-                ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8)]
+                ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8),
+                ("stage_ms_sum", ctypes.c_double * 8), ("profiled_frames", ctypes.c_int64),
+                ("profile_state", ctypes.c_void_p)]
 
 STAGES = ("preprocess", "scan", "readback", "depth_sort", "emit", "key_sort", "ranges", "blend")
 
@@ -83,13 +86,16 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_18441_amd.build`")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python paper_2511_18441_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
         P = ctypes.POINTER
         L.recogs_workspace_bytes.argtypes = [i64, i32, i32, i32, i32, i64]
         L.recogs_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_workspace_init.argtypes = [P(Workspace), vp, ctypes.c_size_t, i64, i32, i32, i32, i32, i64]
+        L.recogs_workspace_profile_flush.argtypes = [P(Workspace)]
+        L.recogs_workspace_release.argtypes = [P(Workspace)]
+        L.recogs_workspace_release.restype = None
         L.recogs_prepare_covariance.argtypes = [vp, vp, vp, i64, i64, vp]
         L.recogs_select.argtypes = [P(Scene), P(Camera), P(SelectParams), vp, vp, vp]
         L.recogs_recolor.argtypes = [P(Scene), vp, vp, vp, vp, i32, vp]
@@ -98,7 +104,7 @@ def lib():
         L.recogs_loss_l2.argtypes = [vp, vp, i64, f32, vp, vp, vp]
         L.recogs_last_error.restype = ctypes.c_char_p
         for name in ENTRY_POINTS:
-            if name not in ("recogs_workspace_bytes", "recogs_last_error"):
+            if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -127,6 +133,14 @@ def recogs_workspace_bytes(n, width, height, tile_w, tile_h, key_capacity) -> in
 def recogs_workspace_init(ws: Workspace, dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity):
     return _check("recogs_workspace_init", lib().recogs_workspace_init(
         ctypes.byref(ws), dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity))
+
+
+def recogs_workspace_profile_flush(ws: Workspace):
+    return _check("recogs_workspace_profile_flush", lib().recogs_workspace_profile_flush(ctypes.byref(ws)))
+
+
+def recogs_workspace_release(ws: Workspace) -> None:
+    lib().recogs_workspace_release(ctypes.byref(ws))
 
 
 def recogs_prepare_covariance(log_scales, quats, cov3d, n, stride, stream=None):
@@ -201,7 +215,7 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.M = M.data_ptr() if M is not None else None
     o.b = b.data_ptr() if b is not None else None
     o.keep_backward_state = 1 if keep_backward else 0
-    o.profile_stages = 1 if profile else 0
+    o.profile_stages = int(profile)  # False/True -> 0/1; 2 = accumulate without waiting
     o.sort_mode = int(sort_mode)
     return o
 
@@ -266,9 +280,28 @@ class DeviceWorkspace:
         nbytes = recogs_workspace_bytes(*self.args, cap)
         if nbytes == 0:
             raise RecogsError("recogs_workspace_bytes", -1, "invalid workspace arguments")
+        self.release()
         self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ws = Workspace()
         recogs_workspace_init(self.ws, self.mem.data_ptr(), nbytes, *self.args, cap)
+
+    def release(self):
+        ws = getattr(self, "ws", None)
+        if ws is not None and ws.profile_state:
+            recogs_workspace_release(ws)
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def blend_time(self):
+        """Mean blend milliseconds over the profile_stages=2 renders so far (waits for the
+        last one) and their count."""
+        recogs_workspace_profile_flush(self.ws)
+        n = int(self.ws.profiled_frames)
+        return (self.ws.stage_ms_sum[7] / n if n else 0.0), n
 
     def grow(self, needed):
         self._alloc(int(needed * 1.25) + 1024)

@@ -1,6 +1,7 @@
 """Build step of the HIP library: compiles csrc/*.hip for gfx950 into librecogs.so.
 
-Usage: python -m paper_2511_18441_amd.build   (or call build()).
+Usage: python paper_2511_18441_amd/build.py   (run as a file: importing the package
+loads the library this builds)
 """
 import glob
 import os

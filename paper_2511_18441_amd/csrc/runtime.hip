@@ -128,27 +128,84 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
 template <typename T> T *at(const recogs_workspace *ws, size_t off) { return (T *)((char *)ws->base + off); }
 
 // HIP events bracketing the stages of a profiled render (created once per thread)
+// Stage timing. Mode 1 uses the thread's own events and waits for the blend; mode 2
+// brackets the blend with one of the workspace's two event pairs, does not wait, and
+// harvests the other pair (recorded by the previous call, complete once this call's
+// read-back returned).
+struct ProfileSet {
+    hipEvent_t ev[9];
+    bool pending;
+};
+struct ProfileState {
+    ProfileSet set[2];
+    int cur;
+};
+
+void harvest(recogs_workspace *ws, ProfileSet &p) {
+    if (!p.pending) return;
+    p.pending = false;
+    if (hipEventSynchronize(p.ev[8]) != hipSuccess) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.ev[7], p.ev[8]) == hipSuccess) ws->stage_ms_sum[7] += ms;
+    ws->profiled_frames += 1;
+}
+
 struct StageTimer {
-    hipEvent_t ev[9] = {};
-    bool on = false, ready = false;
+    hipEvent_t own[9] = {};
+    bool own_ready = false;
+    hipEvent_t *ev = nullptr;
+    ProfileSet *set = nullptr;
+    int mode = 0;
     hipStream_t st = nullptr;
-    recogs_status start(bool enable, hipStream_t s) {
-        on = enable;
+    recogs_status start(int m, recogs_workspace *ws, hipStream_t s) {
+        mode = m;
         st = s;
-        if (!on) return RECOGS_OK;
-        if (!ready) {
-            for (auto &e : ev)
-                if (hipEventCreate(&e) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventCreate failed");
-            ready = true;
+        set = nullptr;
+        if (mode == 0) return RECOGS_OK;
+        if (mode == 1) {
+            if (!own_ready) {
+                for (auto &e : own)
+                    if (hipEventCreate(&e) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventCreate failed");
+                own_ready = true;
+            }
+            ev = own;
+            return mark(0);
         }
-        return mark(0);
-    }
-    recogs_status mark(int k) {
-        if (on && hipEventRecord(ev[k], st) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventRecord failed");
+        ProfileState *ps = (ProfileState *)ws->profile_state;
+        if (!ps) {
+            ps = (ProfileState *)calloc(1, sizeof(ProfileState));
+            if (!ps) return fail(RECOGS_ERR_INVALID, "host allocation of profile state failed");
+            for (auto &ps_set : ps->set)
+                for (auto &e : ps_set.ev)
+                    if (hipEventCreate(&e) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventCreate failed");
+            ws->profile_state = ps;
+        }
+        set = &ps->set[ps->cur];
+        harvest(ws, *set);  // left over from two calls ago (normally already harvested)
+        ev = set->ev;
         return RECOGS_OK;
     }
+    // mode 2 records only the blend's bracket (7, 8): each event between two kernels
+    // delays the second one's dispatch by a few microseconds
+    recogs_status mark(int k) {
+        if (mode == 0 || (mode == 2 && k < 7)) return RECOGS_OK;
+        if (hipEventRecord(ev[k], st) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventRecord failed");
+        return RECOGS_OK;
+    }
+    // after the key-count read-back: the previous mode-2 call has completed
+    void after_readback(recogs_workspace *ws) {
+        if (mode != 2) return;
+        ProfileState *ps = (ProfileState *)ws->profile_state;
+        harvest(ws, ps->set[ps->cur ^ 1]);
+    }
     recogs_status finish(recogs_workspace *ws, int last) {
-        if (!on) return RECOGS_OK;
+        if (mode == 2) {
+            ProfileState *ps = (ProfileState *)ws->profile_state;
+            set->pending = true;
+            ps->cur ^= 1;
+            return RECOGS_OK;
+        }
+        if (mode != 1) return RECOGS_OK;
         if (hipEventSynchronize(ev[last]) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventSynchronize failed");
         for (int k = 0; k < 8; ++k) {
             float ms = 0.f;
@@ -220,6 +277,8 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (!tile_supported(o->tile_w, o->tile_h))
         return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8", o->tile_w, o->tile_h);
     if (o->sort_mode != 0 && o->sort_mode != 1) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0 or 1", o->sort_mode);
+    if (o->profile_stages < 0 || o->profile_stages > 2)
+        return fail(RECOGS_ERR_INVALID, "profile_stages %d not 0, 1 or 2", o->profile_stages);
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
         return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
     const bool any = o->mask || o->M || o->b;
@@ -269,6 +328,26 @@ recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t 
     ws->width = width; ws->height = height; ws->tile_w = tile_w; ws->tile_h = tile_h;
     ws->key_capacity = key_capacity;
     return RECOGS_OK;
+}
+
+recogs_status recogs_workspace_profile_flush(recogs_workspace *ws) {
+    g_err[0] = 0;
+    if (!ws) return fail(RECOGS_ERR_INVALID, "workspace is NULL");
+    ProfileState *ps = (ProfileState *)ws->profile_state;
+    if (!ps) return RECOGS_OK;
+    harvest(ws, ps->set[ps->cur]);      // older
+    harvest(ws, ps->set[ps->cur ^ 1]);  // latest
+    return RECOGS_OK;
+}
+
+void recogs_workspace_release(recogs_workspace *ws) {
+    if (!ws || !ws->profile_state) return;
+    ProfileState *ps = (ProfileState *)ws->profile_state;
+    for (auto &st : ps->set)
+        for (auto &e : st.ev)
+            if (e) hipEventDestroy(e);
+    free(ps);
+    ws->profile_state = nullptr;
 }
 
 recogs_status recogs_prepare_covariance(const float *log_scales, const float *quats, float *cov3d, int64_t n,
@@ -328,7 +407,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
 
     StageTimer &tm = g_timer;
     for (int k = 0; k < 8; ++k) ws->stage_ms[k] = 0.f;
-    if ((s = tm.start(opts->profile_stages != 0, stream)) != RECOGS_OK) return s;
+    if ((s = tm.start(opts->profile_stages, ws, stream)) != RECOGS_OK) return s;
     const int mode = opts->sort_mode;
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
     uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
@@ -350,6 +429,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     RECOGS_TRY_HIP(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
     RECOGS_TRY_HIP(hipStreamSynchronize(stream));
+    tm.after_readback(ws);
     if ((s = tm.mark(3)) != RECOGS_OK) return s;
     const uint64_t K = n > 0 ? ((uint64_t)h[H_K_LO] | ((uint64_t)h[H_K_HI] << 32)) : 0;
     const uint32_t V = n > 0 ? h[H_V] : 0;

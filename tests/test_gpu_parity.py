@@ -254,6 +254,31 @@ def test_deterministic(R):
     assert np.array_equal(a["img"].cpu().numpy(), b["img"].cpu().numpy())
 
 
+def test_stage_profiling_modes_leave_the_image_unchanged(R):
+    import torch
+    w = synth.make_mid(n=50_000)
+    v = w.view
+    d = R.DeviceScene(w.scene)
+    ws = R.DeviceWorkspace(d.n, v.camera.width, v.camera.height)
+    ref = R.render(d, v.camera, ws, (16, 16), 2).clone()
+    img = R.render(d, v.camera, ws, (16, 16), 2, profile=1)
+    assert torch.equal(img, ref)
+    assert ws.ws.stage_ms[7] > 0 and ws.ws.profiled_frames == 0
+    for _ in range(3):
+        img = R.render(d, v.camera, ws, (16, 16), 2, profile=2)
+    assert torch.equal(img, ref)
+    assert ws.ws.profiled_frames == 2  # the third is harvested by the flush
+    blend_ms, nfr = ws.blend_time()
+    assert nfr == 3 and blend_ms > 0 and ws.ws.stage_ms_sum[0] == 0
+    R.recogs_workspace_profile_flush(ws.ws)  # nothing pending: no change
+    assert ws.ws.profiled_frames == 3
+    ws.release()
+    assert not ws.ws.profile_state
+    img = R.render(d, v.camera, ws, (16, 16), 2, profile=2)  # recreated on demand
+    assert torch.equal(img, ref)
+    assert ws.blend_time()[1] == 4
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
