@@ -170,7 +170,12 @@ class Single:
                 "profiled_frames": nfr, "select_ms": sel_ms}
 
     def counts(self):
+        """Counts of the frame, from one more render that also writes the per-pixel state
+        (the same tile lists and arithmetic; that blend variant also stores each pixel's
+        list count, from which the evaluations are summed)."""
         import torch
+        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
+                      keep_backward=True)
         ws = self.ws
         K = int(ws.ws.num_keys)
         cnt = ws.counts(self.n)
@@ -189,7 +194,7 @@ class Single:
 
 
 def stage_table(stages, bytes_, flops, st):
-    launches = {"key_sort": st["passes"] + 1, "depth_sort": st["dpasses"] + 1}
+    launches = {"key_sort": 3 * st["passes"], "depth_sort": 3 * st["dpasses"]}
     out = {}
     for k, t in stages.items():
         if k == "readback":

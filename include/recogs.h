@@ -3,8 +3,8 @@
  *
  * The operations follow ReCoGS (Rutayisire, Capodieci, Pellacini; arXiv 2511.18441):
  * a pre-trained 3D Gaussian Splatting scene (Sec. 3.1: covariance eq. 1, SH colour
- * eq. 2, front-to-back alpha blending eq. 3) has a region selected (Sec. 3.3) and
- * tinted (Sec. 3.5, eq. 6), is rendered with an HWC output (Sec. 4.3) and
+ * eq. 2, front-to-back alpha blending eq. 3) has a region selected (Sec. 3.2) and
+ * tinted (Sec. 3.3, eq. 6), is rendered with an HWC output (Sec. 4.2) and
  * differentiated w.r.t. its colour parameters (Sec. 4.1, eq. 7-8).
  *
  * Conventions shared by every call
@@ -43,7 +43,7 @@ typedef enum {
     RECOGS_ERR_HIP = -4           /* a HIP runtime call failed; see recogs_last_error */
 } recogs_status;
 
-/* Scene (eq. 1-2). Geometry is frozen while colours are edited (Sec. 3.5).
+/* Scene (eq. 1-2). Geometry is frozen while colours are edited (Sec. 3.3).
  *   means   float [3][stride]          world-space centres x, y, z
  *   cov3d   float [6][stride]          3D covariance xx, xy, xz, yy, yz, zz (eq. 1)
  *   opacity storage [stride]           activated opacity sigma in (0, 1)
@@ -92,7 +92,9 @@ typedef struct {
     const uint8_t *mask;
     const float *M;
     const float *b;
-    int32_t keep_backward_state; /* 1: store what recogs_render_backward needs */
+    int32_t keep_backward_state; /* 1: store what recogs_render_backward needs (per-Gaussian colour
+                                    state, per-pixel final transmittance and list count); 0: the
+                                    workspace's final_T / nproc are not written */
     /* Stage timing with HIP events recorded on `stream`.
      * 0: off. 1: events between all stages; this call waits for its blend and writes the
      * durations to ws->stage_ms. 2: the blend's duration, accumulated without waiting:
@@ -126,10 +128,10 @@ typedef struct {
     int64_t key_capacity;
     int32_t tiles_x, tiles_y;
     /* buffer offsets */
-    size_t off_rec, off_bwd, off_grad, off_zbits, off_rect, off_count, off_offset, off_scan;
+    size_t off_rec, off_bwd, off_grad, off_gpart, off_zbits, off_rect, off_count, off_offset, off_scan;
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_count;
     size_t off_ranges, off_final_T, off_nproc, off_header;
-    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_esum;
+    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_esum, off_efirst;
     size_t scan_chunks, sort_chunks;
     /* results of the last render, valid when it returned RECOGS_OK (or CAPACITY) */
     int64_t num_keys;            /* K: tile keys emitted */
@@ -182,13 +184,13 @@ recogs_status recogs_prepare_covariance(const float *log_scales, const float *qu
 
 /* ---- the path ---------------------------------------------------------------- */
 
-/* Selection (Sec. 3.3 stand-in): mask uint8 [n] (1 = selected) and *count (device
+/* Selection (Sec. 3.2 stand-in): mask uint8 [n] (1 = selected) and *count (device
  * int32, overwritten) = number selected. */
 recogs_status recogs_select(const recogs_scene *scene, const recogs_camera *cam,
                             const recogs_select_params *params, uint8_t *mask, int32_t *count,
                             hipStream_t stream);
 
-/* Recolour (Sec. 3.5, eq. 6 generalised): for every selected i the displayed colour
+/* Recolour (Sec. 3.3, eq. 6 generalised): for every selected i the displayed colour
  * becomes M (f + 1/2) + b for every view direction, realised on coefficients as
  * C'_k = M C_k (k >= 1) and C'_0 = M C_0 + ((M - I) 1/2 + b) / Y00.
  * Reads scene->sh, writes dst_sh (same dtype, degree and stride; may equal
@@ -199,7 +201,7 @@ recogs_status recogs_recolor(const recogs_scene *scene, void *dst_sh, const uint
                              const float *M, const float *b, int32_t copy_unselected,
                              hipStream_t stream);
 
-/* Render (eq. 2-3; HWC output, Sec. 4.3): EWA projection, tile binning with a
+/* Render (eq. 2-3; HWC output, Sec. 4.2): EWA projection, tile binning with a
  * (tile, depth) key sort, front-to-back compositing with early termination.
  * image float [height][width][3]. ws must have been initialised for at least this n,
  * the camera's size and opts' tile shape. Synchronises the stream once.
@@ -256,7 +258,7 @@ typedef struct {
     uint32_t preprocess_blocks;
     int32_t reserved;
     size_t off_views, off_vtab, off_rec, off_zbits, off_rect, off_count, off_offset;
-    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_scan, off_esum, off_sort_count;
+    size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_scan, off_esum, off_efirst, off_sort_count;
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_header, off_hist, off_dhist, off_ranges, off_order;
     size_t scan_chunks;
     /* filled by recogs_batch_readback */

@@ -9,7 +9,7 @@
  *   - covariance Sigma = R S S^T R^T                           (Sec. 3.1, eq. 1)
  *   - view-dependent colour from SH coefficients, degree <= 3  (Sec. 3.1, eq. 2)
  *   - per-pixel front-to-back alpha blending                   (Sec. 3.1, eq. 3)
- *   - the tint c* = t c, generalised to an affine 3x3 recolour (Sec. 3.5, eq. 6)
+ *   - the tint c* = t c, generalised to an affine 3x3 recolour (Sec. 3.3, eq. 6)
  *   - gradients of the blended image w.r.t. opacity, SH DC and the recolour
  *     matrix                                                    (Sec. 4.1, eq. 8)
  * plus the per-Gaussian screen-disk / colour-ball selection predicate and the
@@ -342,7 +342,7 @@ void orc_project(int64_t n, const double *means, const double *cov, const double
 
 /* ---------------------------------------------------------------------------
  * Selection predicate (per Gaussian; stand-in for the paper's brush selection,
- * Sec. 3.3): selected iff float32 depth > znear, the unclamped projected centre
+ * Sec. 3.2): selected iff float32 depth > znear, the unclamped projected centre
  * lies in the closed disk (cx, cy, r), and the DC colour Y00 C0 + 1/2 lies in the
  * closed ball (ref, rho). flag = 1 when either inequality is within its band.
  * dc: [3][n] DC coefficients.

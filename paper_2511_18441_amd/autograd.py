@@ -2,7 +2,7 @@
 
 Differentiable inputs: the activated opacities, the SH DC coefficients (the first
 three planes of the scene's SH array) and the fused recolour matrix M; gradients of
-eq. (8) restricted to those, as the refit of the paper updates colour only (Sec. 3.5).
+eq. (8) restricted to those, as the refit of the paper updates colour only (Sec. 3.3).
 """
 from __future__ import annotations
 

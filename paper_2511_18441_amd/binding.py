@@ -64,10 +64,10 @@ class Workspace(ctypes.Structure):
                 ("tile_h", ctypes.c_int32), ("key_capacity", ctypes.c_int64), ("tiles_x", ctypes.c_int32),
                 ("tiles_y", ctypes.c_int32)] + \
                [(f, ctypes.c_size_t) for f in (
-                   "off_rec", "off_bwd", "off_grad", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
+                   "off_rec", "off_bwd", "off_grad", "off_gpart", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
                    "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_hist", "off_sort_count",
                    "off_ranges", "off_final_T", "off_nproc", "off_header", "off_dkeys0", "off_dkeys1", "off_dvals0",
-                   "off_dvals1", "off_dhist", "off_esum", "scan_chunks", "sort_chunks")] + \
+                   "off_dvals1", "off_dhist", "off_esum", "off_efirst", "scan_chunks", "sort_chunks")] + \
                [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("sort_mode", ctypes.c_int32),
                 ("key_bytes", ctypes.c_int32), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("depth_passes", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32),
@@ -393,7 +393,7 @@ class BatchWorkspace(ctypes.Structure):
                 ("reserved", ctypes.c_int32)] + \
                [(f, ctypes.c_size_t) for f in (
                    "off_views", "off_vtab", "off_rec", "off_zbits", "off_rect", "off_count", "off_offset",
-                   "off_dkeys0", "off_dkeys1", "off_dvals0", "off_dvals1", "off_scan", "off_esum", "off_sort_count",
+                   "off_dkeys0", "off_dkeys1", "off_dvals0", "off_dvals1", "off_scan", "off_esum", "off_efirst", "off_sort_count",
                    "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_header", "off_hist", "off_dhist",
                    "off_ranges", "off_order", "scan_chunks")] + \
                [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("overflow", ctypes.c_int32),

@@ -11,9 +11,11 @@
 //   dL/dsigma_i += dL/dalpha_i G_i(p)   (0 where alpha is clamped at 0.99)
 // Per splat the workgroup's pixels are summed per wave (shuffles), then one atomic
 // per wave adds to the Gaussian's accumulator.
-#include "recogs_internal.hpp"
+#include "render_device.hpp"
 
 namespace recogs {
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 
 template <int TW, int TH, int PPT>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
@@ -24,10 +26,8 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 #pragma clang fp contract(off)
     using Map = TileMap<TW, TH, PPT>;
     constexpr int NT = Map::NT;
-    constexpr int BATCH = 256;
-    __shared__ float4 s_r0[BATCH], s_r1[BATCH], s_r2[BATCH];
-    __shared__ uint32_t s_gid[BATCH];
-    __shared__ uint8_t s_mask[BATCH];
+    constexpr int BATCH = kBlendBatch;
+    __shared__ BlendStage sm;   // BlendRec.pad holds the Gaussian index, rgb.w the opacity
     const int tile = blockIdx.x;
     const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
     const int t = threadIdx.x;
@@ -64,9 +64,13 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
             if (k < rg.y) {
                 const uint32_t gid = vals[k];
                 const SplatRec s = rec[gid];
-                s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
-                s_gid[q] = gid;
-                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                BlendRec b;
+                b.uv = make_float2(s.r0.x, s.r0.y);
+                b.mask = Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                b.pad = gid;
+                b.r1 = s.r1;
+                b.rgb = s.r2;
+                sm.r[q] = b;
             }
         }
         __syncthreads();
@@ -74,20 +78,25 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
         for (int q = 0; q < nb; ++q) {
             const uint32_t krel = start + q - rg.x;
             if (!wave_ballot(krel < npmax)) break;
-            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
+            const BlendRec &b = sm.r[q];
+            const uint32_t m = __builtin_amdgcn_readfirstlane(b.mask);
             if (!((m >> w) & 1u)) continue;
-            const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
-            const ExpRow er = exp_row(r1, pxc - r0.x);
+            const float2 uv = b.uv;
+            const float4 r1 = b.r1, r2 = b.rgb;
+            const float inv_sigma = 1.f / r2.w;
+            const ExpRow er = exp_row(r1, pxc - uv.x);
             float ds = 0.f, dr = 0.f, dg = 0.f, db = 0.f;
             bool any = false;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                if (krel >= np[j]) continue;
-                const float e = exp_at(er, r1, pyc[j] - r0.y);
-                if (e < kLog2AlphaMin) continue;
+                // the forward's decisions, replayed with its arithmetic: entries up to the
+                // pixel's last blended one, alpha at or above 1/255
+                const float e = exp_at(er, r1, pyc[j] - uv.y);
+                const bool act = krel < np[j] && !(e < kLog2AlphaMin);
+                any = any || act;
                 const float araw = __builtin_amdgcn_exp2f(e);
                 const float a = fminf(kAlphaMax, araw);
-                const float wgt = a * T[j];
+                const float wgt = act ? a * T[j] : 0.f;
                 const float c0 = r2.x * wgt, c1 = r2.y * wgt, c2 = r2.z * wgt;
                 const float R0 = y0[j] - A0[j] - c0, R1 = y1[j] - A1[j] - c1, R2 = y2[j] - A2[j] - c2;
                 const float inv1ma = 1.f / (1.f - a);
@@ -96,15 +105,15 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 dr += wgt * g0[j];
                 dg += wgt * g1[j];
                 db += wgt * g2[j];
-                if (araw < kAlphaMax) ds += dal * (araw / r2.w);
+                ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
                 A0[j] += c0; A1[j] += c1; A2[j] += c2;
-                T[j] = T[j] * (1.f - a);
-                any = true;
+                T[j] = act ? T[j] * (1.f - a) : T[j];
             }
             if (wave_ballot(any)) {
-                ds = wave_sum(ds); dr = wave_sum(dr); dg = wave_sum(dg); db = wave_sum(db);
+                constexpr int L = NT < 64 ? NT : 64;
+                ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
                 if (lane_id() == 0) {
-                    float *pa = (float *)&acc[s_gid[q]];
+                    float *pa = (float *)&acc[b.pad];
                     atomicAdd(pa + 0, ds);
                     atomicAdd(pa + 1, dr);
                     atomicAdd(pa + 2, dg);
@@ -118,10 +127,13 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 // Per Gaussian: dL/dsigma, and the chain through the clamp, the fused recolour and
 // the DC term: gh = dL/drgb where the pre-clamp colour > 0;
 //   selected:   dL/dC0 = Y00 M^T gh, dL/dM += gh (f + 1/2)^T;  unselected: dL/dC0 = Y00 gh.
+// dL/dM is reduced without atomics: each workgroup writes its 9 partial sums to
+// part[block][9] and k_dm_reduce adds them in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ acc, const float4 *__restrict__ bwd,
                                                      const uint32_t *__restrict__ count, int64_t n,
                                                      const float *__restrict__ M, float *__restrict__ dop,
-                                                     float *__restrict__ ddc, float *__restrict__ dM) {
+                                                     float *__restrict__ ddc, float *__restrict__ part) {
+    __shared__ float s_dm[4][9];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float m[9];
     bool sel = false;
@@ -150,14 +162,36 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
             for (int c = 0; c < 3; ++c) ddc[c * n + i] = kSH0 * gh[c];
         }
     }
-    if (M && wave_ballot(sel)) {
+    if (!M) return;  // uniform: no recolour, no dL/dM
+    const uint32_t w = threadIdx.x >> 6;
+    if (wave_ballot(sel)) {
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float v = wave_sum(sel ? gh[r] * f[c] : 0.f);
-                if (lane_id() == 0) atomicAdd(&dM[r * 3 + c], v);
+                if (lane_id() == 0) s_dm[w][r * 3 + c] = v;
             }
+    } else if (lane_id() < 9) {
+        s_dm[w][lane_id()] = 0.f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9)
+        part[(size_t)blockIdx.x * 9 + threadIdx.x] =
+            ((s_dm[0][threadIdx.x] + s_dm[1][threadIdx.x]) + s_dm[2][threadIdx.x]) + s_dm[3][threadIdx.x];
+}
+
+// dM[k] = sum over blocks of part[block][k], one workgroup, fixed summation order
+__global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ part, uint32_t nblocks, float *__restrict__ dM) {
+    __shared__ float s_w[4];
+    for (int k = 0; k < 9; ++k) {
+        float v = 0.f;
+        for (uint32_t b = threadIdx.x; b < nblocks; b += 256) v += part[(size_t)b * 9 + k];
+        v = wave_sum(v);
+        if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) dM[k] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+        __syncthreads();
     }
 }
 
@@ -200,16 +234,21 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
     return false;
 }
 
+// part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n)
 void launch_grad_finish(const float4 *acc, const float4 *bwd, const uint32_t *count, int64_t n, const float *M, float *dop,
-                        float *ddc, float *dM, hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, bwd, count, n, M, dop, ddc, dM);
+                        float *ddc, float *dM, float *part, hipStream_t st) {
+    const uint32_t blocks = (uint32_t)((n + 255) / 256);
+    if (n > 0)
+        hipLaunchKernelGGL(k_grad_finish, dim3(blocks), dim3(256), 0, st, acc, bwd, count, n, M, dop, ddc, part);
+    if (M && n > 0) hipLaunchKernelGGL(k_dm_reduce, dim3(1), dim3(256), 0, st, part, blocks, dM);
+    else launch_fill_u32((uint32_t *)dM, 0u, 9, st);
 }
 
 void launch_loss_l2(const float *y, const float *tg, int64_t count, float scale, float *dldy, float *loss, hipStream_t st) {
     if (count <= 0) return;
+    // few workgroups: each adds its partial sum with one same-address atomic
     int64_t blocks = (count + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 512) blocks = 512;
     hipLaunchKernelGGL(k_loss_l2, dim3((unsigned)blocks), dim3(256), 0, st, y, tg, count, scale, dldy, loss);
 }
 

@@ -100,8 +100,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_persistent(const ViewDev
                                                                   const SplatRec *__restrict__ rec,
                                                                   const uint32_t *__restrict__ order, uint32_t ntiles,
                                                                   uint32_t *__restrict__ queue) {
-    __shared__ float4 s_r0[256], s_r1[256], s_r2[256];
-    __shared__ uint8_t s_mask[256];
+    __shared__ BlendStage sm;
     __shared__ uint32_t s_item;
     while (true) {
         __syncthreads();
@@ -112,8 +111,8 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_persistent(const ViewDev
         const uint32_t gt = order[item];
         const int v = view_of_tile(views, nviews, gt);
         const ViewDev &vw = views[v];
-        blend_tile<TW, TH, PPT>((int)(gt - vw.tile_base), ranges[gt], vals, rec, vw.cam.W, vw.cam.H, vw.cam.tiles_x,
-                                vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr, nullptr, s_r0, s_r1, s_r2, s_mask);
+        blend_tile<TW, TH, PPT, false>((int)(gt - vw.tile_base), ranges[gt], vals, rec, vw.cam.W, vw.cam.H, vw.cam.tiles_x,
+                                vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr, nullptr, sm);
     }
 }
 

@@ -220,12 +220,16 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
 // ---------------------------------------------------------------------------
 // Key emission in depth order: the Gaussians with keys, already sorted by (depth,
 // index), emit (tile id, index) pairs; a stable sort on the tile id then yields the
-// (tile, depth, index) order. Reduce-then-scan over chunks of 1,024 depth-ordered
-// Gaussians: k_emit_reduce sums each chunk's tile counts, k_scan_top_u32 turns the
-// sums into chunk offsets, k_emit_down writes. In k_emit_down wave w handles groups
-// r of 64 consecutive Gaussians; a group's keys form one contiguous range, written
-// cooperatively (coalesced stores, owner found by binary search over the group's
-// prefix sums).
+// (tile, depth, index) order.
+//   k_emit_reduce:  per chunk of 1,024 depth-ordered Gaussians, gathers each one's
+//                   tile rectangle once and sums the chunk's key counts
+//   k_scan_top_u32: chunk sums -> chunk key offsets
+//   k_emit_offsets: per-Gaussian key offsets, and for every block of kEmitKeys keys
+//                   the Gaussian owning its first key
+//   k_emit_down:    one workgroup per block of kEmitKeys keys (the work is balanced by
+//                   keys, not by Gaussians, whose counts range from 1 to thousands);
+//                   the owner of each key comes from a max-scan of the Gaussians'
+//                   start positions in LDS, and keys are written coalesced
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t rect_count(uint2 r) {
     return ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
@@ -255,96 +259,143 @@ __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) esum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-// Batches (nviews > 1): values are (view, Gaussian) pair indices and tile ids are global,
-// tile_base(view) + local id; vtab[v] = (pair_base, tile_base, tiles_x, -) per view.
-__global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ order, uint32_t V,
-                                                   const uint2 *__restrict__ srect, int tiles_x,
-                                                   const uint32_t *__restrict__ epre, uint32_t *__restrict__ tkeys,
-                                                   uint32_t *__restrict__ tvals, const uint32_t *dynV,
-                                                   const uint32_t *overflow, const uint4 *__restrict__ vtab, int nviews) {
+constexpr uint32_t kEmitKeys = 2048;   // keys per workgroup of k_emit_down (256 threads x 8)
+
+__global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ srect, uint32_t V,
+                                                      const uint32_t *__restrict__ epre, uint32_t *__restrict__ eoff,
+                                                      uint32_t *__restrict__ efirst, uint32_t nblk,
+                                                      const uint32_t *dynV, const uint32_t *overflow) {
     if (dynV) V = *dynV;
     if (overflow && *overflow) return;
-    if (blockIdx.x * (uint32_t)kEmitChunk >= V) return;
-    constexpr int R = kEmitItems;
-    __shared__ uint32_t s_tb[4][64], s_tx[4][64];
-    __shared__ uint32_t s_gsum[4 * R];     // per-group totals, then per-group exclusive prefix
-    __shared__ uint32_t s_ex[4][64];
-    __shared__ uint2 s_rect[4][64];
-    __shared__ uint32_t s_g[4][64];
-    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-    const uint32_t j0 = blockIdx.x * (uint32_t)kEmitChunk + w * (64 * R) + lane;
-    uint32_t c[R], inc[R], g[R];
-    uint2 rr[R];
+    const uint32_t base = blockIdx.x * (uint32_t)kEmitChunk;
+    if (base >= V) return;
+    __shared__ uint32_t s_w[4];
+    const uint32_t t = threadIdx.x;
+    constexpr int R = kEmitChunk / 256;
+    uint32_t c[R], sum = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t j = j0 + r * 64;
-        g[r] = j < V ? order[j] : 0u;
+    for (int r = 0; r < R; ++r) {  // thread t holds Gaussians base + R t + r (blocked)
+        const uint32_t j = base + R * t + r;
+        c[r] = j < V ? rect_count(srect[j]) : 0u;
+        sum += c[r];
     }
+    uint32_t tot;
+    uint32_t run = epre[blockIdx.x] + block_excl_scan<uint32_t, 4>(sum, s_w, tot);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t j = j0 + r * 64;
-        rr[r] = j < V ? srect[j] : make_uint2(0u, 0u);
-        c[r] = j < V ? rect_count(rr[r]) : 0u;
-    }
-    uint32_t tb[R], txn[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        tb[r] = 0;
-        txn[r] = (uint32_t)tiles_x;
-        if (nviews > 1) {  // view of the pair: last v with pair_base <= g
-            int lo = 0, hi = nviews - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (vtab[mid].x <= g[r]) lo = mid;
-                else hi = mid - 1;
-            }
-            tb[r] = vtab[lo].y;
-            txn[r] = vtab[lo].z;
+        const uint32_t j = base + R * t + r;
+        if (j < V) {
+            eoff[j] = run;
+            // key blocks whose first key lies in [run, run + c)
+            for (uint32_t b = (run + kEmitKeys - 1) / kEmitKeys; b < nblk && b * kEmitKeys < run + c[r]; ++b) efirst[b] = j;
+            run += c[r];
         }
     }
+}
+
+// exclusive max-scan over the workgroup of one value per thread (256 threads; 0 for thread 0)
+__device__ __forceinline__ uint32_t block_excl_max256(uint32_t v, uint32_t *s_w) {
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = v;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        inc[r] = wave_incl_scan(c[r]);
-        if (lane == 63) s_gsum[w * R + r] = inc[r];
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t x = __shfl_up(inc, o, 64);
+        if (lane >= (uint32_t)o) inc = x > inc ? x : inc;
     }
+    if (lane == 63) s_w[w] = inc;
     __syncthreads();
-    if (threadIdx.x < 64) {  // exclusive scan of the 4R group totals (one wave)
-        const uint32_t v = threadIdx.x < 4 * R ? s_gsum[threadIdx.x] : 0u;
-        const uint32_t x = wave_incl_scan(v);
-        if (threadIdx.x < 4 * R) s_gsum[threadIdx.x] = x - v;
-    }
-    __syncthreads();
-    const uint32_t cbase = epre[blockIdx.x];
+    uint32_t pre = __shfl_up(inc, 1, 64);
+    if (lane == 0) pre = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        s_ex[w][lane] = inc[r] - c[r];
-        s_rect[w][lane] = rr[r];
-        s_g[w][lane] = g[r];
-        s_tb[w][lane] = tb[r];
-        s_tx[w][lane] = txn[r];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t base = cbase + s_gsum[w * R + r];
-        const uint32_t gtotal = __shfl(inc[r], 63, 64);
-        for (uint32_t q = lane; q < gtotal; q += 64) {
-            int lo = 0, hi = 63;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_ex[w][mid] <= q) lo = mid;
-                else hi = mid - 1;
+    for (int k = 0; k < 4; ++k)
+        if (k < (int)w) pre = s_w[k] > pre ? s_w[k] : pre;
+    __syncthreads();
+    return pre;
+}
+
+// Batches (nviews > 1): values are (view, Gaussian) pair indices and tile ids are global,
+// tile_base(view) + local id; vtab[v] = (pair_base, tile_base, tiles_x, -) per view.
+__global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ order, uint32_t V, uint32_t K,
+                                                   const uint2 *__restrict__ srect, const uint32_t *__restrict__ eoff,
+                                                   const uint32_t *__restrict__ efirst, int tiles_x,
+                                                   uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
+                                                   const uint32_t *dynV, const uint32_t *dynK, const uint32_t *overflow,
+                                                   const uint4 *__restrict__ vtab, int nviews) {
+    if (dynV) V = *dynV;
+    if (dynK) K = *dynK;
+    if (overflow && *overflow) return;
+    const uint32_t k0 = blockIdx.x * kEmitKeys;
+    if (k0 >= K) return;
+    const uint32_t k1 = min(K, k0 + kEmitKeys);
+    constexpr int E = kEmitKeys / 256;
+    __shared__ uint32_t s_own[kEmitKeys];
+    __shared__ uint32_t s_st[256], s_val[256], s_tb[256], s_tx[256];
+    __shared__ uint2 s_rect[256];
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_end;
+    const uint32_t t = threadIdx.x;
+    uint32_t g = efirst[blockIdx.x];  // owns key k0
+    uint32_t kb = k0;
+    while (kb < k1) {
+        // a round: up to 256 consecutive Gaussians from g, and the keys they own in [kb, k1)
+        const uint32_t gi = g + t;
+        const uint32_t st = gi < V ? eoff[gi] : 0xffffffffu;
+        const bool in = gi < V && st < k1;
+        if (in) {
+            const uint2 rc = srect[gi];
+            const uint32_t gv = order[gi];
+            uint32_t tb = 0, txn = (uint32_t)tiles_x;
+            if (nviews > 1) {  // view of the pair: last v with pair_base <= gv
+                int lo = 0, hi = nviews - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (vtab[mid].x <= gv) lo = mid;
+                    else hi = mid - 1;
+                }
+                tb = vtab[lo].y;
+                txn = vtab[lo].z;
             }
-            const uint32_t k = q - s_ex[w][lo];
-            const uint2 rc = s_rect[w][lo];
+            s_st[t] = st;
+            s_rect[t] = rc;
+            s_val[t] = gv;
+            s_tb[t] = tb;
+            s_tx[t] = txn;
+            if (t == 255) s_end = min(k1, st + rect_count(rc));
+        } else if (t == 255) {
+            s_end = k1;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) s_own[e * 256 + t] = 0u;
+        __syncthreads();
+        const uint32_t ke = s_end;
+        // starts strictly increase and Gaussian g starts at or before kb
+        if (in && t > 0 && st < ke) s_own[st - kb] = t;
+        __syncthreads();
+        // owner of every key: inclusive max-scan of the marks (thread t: entries E t ..)
+        uint32_t loc[E], m = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t x = s_own[E * t + e];
+            m = x > m ? x : m;
+            loc[e] = m;
+        }
+        const uint32_t pre = block_excl_max256(m, s_w);
+#pragma unroll
+        for (int e = 0; e < E; ++e) s_own[E * t + e] = loc[e] > pre ? loc[e] : pre;
+        __syncthreads();
+        for (uint32_t q = kb + t; q < ke; q += 256) {
+            const uint32_t i = s_own[q - kb];
+            const uint32_t k = q - s_st[i];
+            const uint2 rc = s_rect[i];
             const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
             const uint32_t wd = tx1 - tx0 + 1;
             const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
-            tkeys[base + q] = s_tb[w][lo] + ty * s_tx[w][lo] + tx;
-            tvals[base + q] = s_g[w][lo];
+            tkeys[q] = s_tb[i] + ty * s_tx[i] + tx;
+            tvals[q] = s_val[i];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __syncthreads();
+        kb = ke;
+        g += 256;
     }
 }
 
@@ -375,18 +426,18 @@ __global__ __launch_bounds__(256) void k_ranges(const uint64_t *__restrict__ key
 // meets, so a wave skips a splat with one scalar test. Per pixel: alpha =
 // min(0.99, 2^e) with e from exp_row/exp_at, skipped below 1/255; the pixel stops
 // when blending would drop transmittance below 1e-4; the workgroup stops when all
-// its pixels have. Output HWC image, final transmittance and, per pixel, the count
-// of tile-list entries up to and including the last blended one.
+// its pixels have. Output HWC image and, with STATE (for the backward), the final
+// transmittance and per pixel the count of tile-list entries up to and including
+// the last blended one.
 // ---------------------------------------------------------------------------
-template <int TW, int TH, int PPT>
+template <int TW, int TH, int PPT, bool STATE>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                        const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                        float bg0, float bg1, float bg2, float *__restrict__ image,
                                                        float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
-    __shared__ float4 s_r0[kBlendBatch], s_r1[kBlendBatch], s_r2[kBlendBatch];
-    __shared__ uint8_t s_mask[kBlendBatch];
-    blend_tile<TW, TH, PPT>(blockIdx.x, ranges[blockIdx.x], vals, rec, W, H, tiles_x, bg0, bg1, bg2, image, finalT, nproc,
-                            s_r0, s_r1, s_r2, s_mask);
+    __shared__ BlendStage sm;
+    blend_tile<TW, TH, PPT, STATE>(blockIdx.x, ranges[blockIdx.x], vals, rec, W, H, tiles_x, bg0, bg1, bg2, image, finalT,
+                                   nproc, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -431,15 +482,21 @@ void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int6
 
 // V is the count or, with dynV, its upper bound; hdr (optional) supplies the overflow flag.
 void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, uint2 *srect, int tiles_x,
-                        uint32_t *esum, uint32_t *tkeys, uint32_t *tvals, hipStream_t st, const uint32_t *dynV,
-                        const uint32_t *hdr, const uint4 *vtab, int nviews) {
-    if (V == 0) return;
+                        uint32_t *esum, uint32_t *eoff, uint32_t *efirst, uint32_t K, uint32_t *tkeys, uint32_t *tvals,
+                        hipStream_t st, const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr,
+                        const uint4 *vtab, int nviews) {
+    if (V == 0 || K == 0) return;
     const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
+    const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
+    const uint32_t *ovf = hdr ? hdr + H_OVERFLOW : nullptr;
     hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum, dynV);
     hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
-    hipLaunchKernelGGL(k_emit_down, dim3(chunks), dim3(256), 0, st, order, V, srect, tiles_x, esum, tkeys, tvals, dynV,
-                       hdr ? hdr + H_OVERFLOW : nullptr, vtab, nviews);
+    hipLaunchKernelGGL(k_emit_offsets, dim3(chunks), dim3(256), 0, st, srect, V, esum, eoff, efirst, nblk, dynV, ovf);
+    hipLaunchKernelGGL(k_emit_down, dim3(nblk), dim3(256), 0, st, order, V, K, srect, eoff, efirst, tiles_x, tkeys, tvals,
+                       dynV, dynK, ovf, vtab, nviews);
 }
+
+uint32_t emit_blocks(uint32_t K) { return (K + kEmitKeys - 1) / kEmitKeys; }
 
 void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st, const uint32_t *dynK) {
     if (K == 0) return;
@@ -462,8 +519,12 @@ void launch_ranges(const uint64_t *keys, uint32_t K, uint2 *ranges, hipStream_t 
 template <int TW, int TH, int PPT>
 static void blend_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec, int W,
                       int H, int tiles_x, const float *bg, float *image, float *finalT, uint32_t *nproc) {
-    hipLaunchKernelGGL((k_blend<TW, TH, PPT>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W, H, tiles_x,
-                       bg[0], bg[1], bg[2], image, finalT, nproc);
+    if (finalT)
+        hipLaunchKernelGGL((k_blend<TW, TH, PPT, true>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W, H,
+                           tiles_x, bg[0], bg[1], bg[2], image, finalT, nproc);
+    else
+        hipLaunchKernelGGL((k_blend<TW, TH, PPT, false>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W,
+                           H, tiles_x, bg[0], bg[1], bg[2], image, nullptr, nullptr);
 }
 
 bool launch_blend(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,

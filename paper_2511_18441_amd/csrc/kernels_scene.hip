@@ -30,34 +30,67 @@ __global__ __launch_bounds__(256) void k_covariance(const float *__restrict__ ls
 }
 
 // Selection: depth > znear, projected centre in the closed disk, DC colour in the
-// closed ball. Count by wave ballot + one atomic per wave.
+// closed ball. The count is reduced per workgroup (wave ballots, then LDS) and added
+// with one atomic per workgroup: same-address device atomics are serialised far
+// from the CU, so a grid-stride loop over at most kSelectBlocks workgroups bounds them.
+constexpr unsigned kSelectBlocks = 1024;
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_select(SceneDev sc, CamDev cam, float scx, float scy, float r2,
                                                 float ref0, float ref1, float ref2, float rho2,
                                                 uint8_t *__restrict__ mask, int32_t *__restrict__ count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool sel = false;
-    if (i < sc.n) {
-        const float mx = sc.means[i], my = sc.means[sc.stride + i], mz = sc.means[2 * sc.stride + i];
-        const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
-        if (z > cam.znear) {
-            const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
-            const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
-            const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
-            const float du = u - scx, dv = v - scy;
-            const float d2 = du * du + dv * dv;
-            const float c0 = kSH0 * Store<DT>::ldc(sc.sh, i) + 0.5f - ref0;
-            const float c1 = kSH0 * Store<DT>::ldc(sc.sh, sc.stride + i) + 0.5f - ref1;
-            const float c2 = kSH0 * Store<DT>::ldc(sc.sh, 2 * sc.stride + i) + 0.5f - ref2;
-            sel = (d2 <= r2) && (c0 * c0 + c1 * c1 + c2 * c2 <= rho2);
+    __shared__ uint32_t s_cnt[4];
+    uint32_t wave_cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - threadIdx.x < sc.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool sel = false;
+        if (i < sc.n) {
+            const float mx = sc.means[i], my = sc.means[sc.stride + i], mz = sc.means[2 * sc.stride + i];
+            const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
+            if (z > cam.znear) {
+                const float x = dot3c(cam.R[0], mx, cam.R[1], my, cam.R[2], mz, cam.t[0]);
+                const float y = dot3c(cam.R[3], mx, cam.R[4], my, cam.R[5], mz, cam.t[1]);
+                const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
+                const float du = u - scx, dv = v - scy;
+                const float d2 = du * du + dv * dv;
+                const float c0 = kSH0 * Store<DT>::ldc(sc.sh, i) + 0.5f - ref0;
+                const float c1 = kSH0 * Store<DT>::ldc(sc.sh, sc.stride + i) + 0.5f - ref1;
+                const float c2 = kSH0 * Store<DT>::ldc(sc.sh, 2 * sc.stride + i) + 0.5f - ref2;
+                sel = (d2 <= r2) && (c0 * c0 + c1 * c1 + c2 * c2 <= rho2);
+            }
+            mask[i] = sel ? 1 : 0;
         }
-        mask[i] = sel ? 1 : 0;
+        wave_cnt += (uint32_t)__popcll(wave_ballot(sel));
     }
-    const uint64_t b = wave_ballot(sel);
-    if (lane_id() == 0 && b) atomicAdd(count, (int32_t)__popcll(b));
+    if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = wave_cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t c = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (c) atomicAdd(count, (int32_t)c);
+    }
 }
 
 // Recolour on coefficients: C'_k = M C_k (k >= 1), C'_0 = M C_0 + ((M - I) 1/2 + b)/Y00.
+// A selected thread loads all its coefficients before it stores any (dst may alias
+// the source), so the loads of one Gaussian overlap instead of taking one memory
+// round trip per coefficient.
+template <int DT, int NC>
+__device__ __forceinline__ void recolor_one(const SceneDev &sc, void *__restrict__ dst, int64_t i, const float *M,
+                                            const float *off) {
+    float c[3 * NC];
+#pragma unroll
+    for (int p = 0; p < 3 * NC; ++p) c[p] = Store<DT>::ldc(sc.sh, p * sc.stride + i);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            float v = M[r * 3] * c[3 * k] + M[r * 3 + 1] * c[3 * k + 1] + M[r * 3 + 2] * c[3 * k + 2];
+            if (k == 0) v += off[r];
+            Store<DT>::st(dst, (int64_t)(3 * k + r) * sc.stride + i, v);
+        }
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *__restrict__ dst,
                                                  const uint8_t *__restrict__ mask, const float *__restrict__ Mp,
@@ -75,16 +108,11 @@ __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *_
     for (int k = 0; k < 9; ++k) M[k] = Mp[k];
 #pragma unroll
     for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bp[r]) / kSH0;
-    for (int k = 0; k < ncoef; ++k) {
-        const int64_t b0 = (int64_t)(k * 3) * sc.stride + i;
-        const float c0 = Store<DT>::ldc(sc.sh, b0), c1 = Store<DT>::ldc(sc.sh, b0 + sc.stride),
-                    c2 = Store<DT>::ldc(sc.sh, b0 + 2 * sc.stride);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
-            if (k == 0) v += off[r];
-            Store<DT>::st(dst, b0 + r * sc.stride, v);
-        }
+    switch (ncoef) {
+    case 1: recolor_one<DT, 1>(sc, dst, i, M, off); break;
+    case 4: recolor_one<DT, 4>(sc, dst, i, M, off); break;
+    case 9: recolor_one<DT, 9>(sc, dst, i, M, off); break;
+    default: recolor_one<DT, 16>(sc, dst, i, M, off); break;
     }
 }
 
@@ -99,7 +127,8 @@ void launch_covariance(const float *ls, const float *q, float *cov, int64_t n, i
 void launch_select(int dt, const SceneDev &sc, const CamDev &cam, const recogs_select_params &p, uint8_t *mask,
                    int32_t *count, hipStream_t st) {
     if (sc.n <= 0) return;
-    const dim3 g((unsigned)((sc.n + 255) / 256)), b(256);
+    const int64_t need = (sc.n + 255) / 256;
+    const dim3 g((unsigned)(need < kSelectBlocks ? need : kSelectBlocks)), b(256);
     const float r2 = p.radius * p.radius, rho2 = p.color_radius * p.color_radius;
     if (dt == RECOGS_F32) hipLaunchKernelGGL(k_select<RECOGS_F32>, g, b, 0, st, sc, cam, p.cx, p.cy, r2, p.ref[0], p.ref[1], p.ref[2], rho2, mask, count);
     else if (dt == RECOGS_F16) hipLaunchKernelGGL(k_select<RECOGS_F16>, g, b, 0, st, sc, cam, p.cx, p.cy, r2, p.ref[0], p.ref[1], p.ref[2], rho2, mask, count);

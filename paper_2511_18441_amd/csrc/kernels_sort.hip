@@ -7,14 +7,14 @@
 //   KV_SUB        (32-bit): key - zmin
 // Both views preserve the key order among the keys of one render.
 //
-// One histogram kernel counts the digits of every pass at once. Each pass is then
-// reduce-then-scan, with no waiting between workgroups:
+// Each pass is reduce-then-scan, with no waiting between workgroups:
 //   up:      per chunk of 4,096 keys, the digit counts -> matrix [digit][chunk]
-//   rowscan: one workgroup per digit scans its row (plus the digit's global base)
-//   down:    per chunk, keys are ranked stably per digit with wave ballots (a
-//            64-lane match mask built from one ballot per digit bit, rank = popcount
-//            of the lower lanes), staged through LDS in digit order and written as
-//            contiguous runs at the offsets of the matrix.
+//   rowscan: one workgroup per digit scans its row in place and writes the row total
+//   down:    per chunk, the digits' global bases come from an exclusive scan of the
+//            row totals (256 words, done by every workgroup); keys are ranked stably
+//            per digit with wave ballots (a 64-lane match mask built from one ballot
+//            per digit bit, rank = popcount of the lower lanes), staged through LDS in
+//            digit order and written as contiguous runs at the offsets of the matrix.
 // A single-pass "decoupled look-back" form was measured slower here: its prefix
 // frontier advances only a window of chunks per cross-XCD round trip.
 #include "recogs_internal.hpp"
@@ -47,8 +47,6 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *s_w
     return pre + inc - v;
 }
 
-// Digit histograms of all passes. Pass p uses bits [shift_p, shift_p + bits_p) of the
-// view, shift_p = sum of earlier bits; `bits` packs bits_p in nibbles.
 // Counts and the depth minimum may live in device memory (dyn_count, dyn_zmin non-null:
 // the graph-capturable batch, whose host code never reads them back); grids are then
 // sized for the capacity and workgroups past the live count return at once.
@@ -57,45 +55,22 @@ __device__ __forceinline__ void dyn_args(const uint32_t *dyn_count, const uint32
     if (dyn_zmin) zmin = *dyn_zmin;
 }
 
-template <typename KT, int VIEW>
-__global__ __launch_bounds__(256) void k_radix_hist(const KT *__restrict__ keys, uint32_t K, uint32_t zmin, int dbits,
-                                                    int passes, uint32_t bits, uint32_t *__restrict__ ghist,
-                                                    const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
-    dyn_args(dyn_count, dyn_zmin, K, zmin);
-    __shared__ uint32_t h[kMaxPasses][256];
-    for (int i = threadIdx.x; i < kMaxPasses * 256; i += 256) (&h[0][0])[i] = 0;
-    __syncthreads();
-    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < K; k += gridDim.x * 256) {
-        const KT key = keys[k];
-        int shift = 0;
-        for (int p = 0; p < passes; ++p) {
-            const int nb = (bits >> (4 * p)) & 15;
-            atomicAdd(&h[p][digit_of<KT, VIEW>(key, zmin, dbits, shift, (1u << nb) - 1u)], 1u);
-            shift += nb;
-        }
-    }
-    __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t v = h[p][threadIdx.x];
-        if (v) atomicAdd(&ghist[p * 256 + threadIdx.x], v);
-    }
-}
-
-// per-chunk digit counts -> cnt[digit * chunks + chunk]
-template <typename KT, int VIEW>
+// per-chunk digit counts -> cnt[digit * chunks + chunk]; a chunk is 256 x ITEMS keys
+template <typename KT, int VIEW, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, uint32_t K, uint32_t zmin, int dbits,
                                                   int shift, int nbits, uint32_t *__restrict__ cnt, uint32_t chunks,
                                                   const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+    constexpr uint32_t CHUNK = 256 * ITEMS;
     dyn_args(dyn_count, dyn_zmin, K, zmin);
-    if (blockIdx.x * (uint32_t)kSortChunk >= K) return;
+    if (blockIdx.x * CHUNK >= K) return;
     __shared__ uint32_t h[256];
     const uint32_t t = threadIdx.x;
     h[t] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << nbits) - 1u;
-    const uint32_t base = blockIdx.x * (uint32_t)kSortChunk;
+    const uint32_t base = blockIdx.x * CHUNK;
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base + r * 256 + t;
         if (idx < K) atomicAdd(&h[digit_of<KT, VIEW>(kin[idx], zmin, dbits, shift, dmask)], 1u);
     }
@@ -103,66 +78,68 @@ __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, ui
     if (t <= dmask) cnt[(size_t)t * chunks + blockIdx.x] = h[t];
 }
 
-// workgroup d: cnt[d][c] <- base(d) + sum_{c' < c} cnt[d][c'], base(d) = sum_{d' < d} ghist[d']
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks,
-                                                       const uint32_t *__restrict__ ghist, uint32_t K,
+// workgroup d: cnt[d][c] <- sum_{c' < c} cnt[d][c'];  tot[d] <- sum_c cnt[d][c]
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks, uint32_t chunk_keys,
+                                                       uint32_t *__restrict__ tot, uint32_t K,
                                                        const uint32_t *dyn_count) {
     if (dyn_count) K = *dyn_count;
-    const uint32_t live = (K + kSortChunk - 1) / kSortChunk;   // chunks holding keys; row stride stays `chunks`
+    const uint32_t live = (K + chunk_keys - 1) / chunk_keys;   // chunks holding keys; row stride stays `chunks`
     __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_base;
     const uint32_t d = blockIdx.x, t = threadIdx.x;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan256(ghist[t], s_w, tot);
-    if (t == d) s_base = ex;
-    __syncthreads();
-    uint32_t run = s_base;
+    uint32_t run = 0, total;
     uint32_t *row = cnt + (size_t)d * chunks;
     for (uint32_t c0 = 0; c0 < live; c0 += 256) {
         const uint32_t c = c0 + t;
         const uint32_t v = c < live ? row[c] : 0u;
-        const uint32_t e = block_excl_scan256(v, s_w, tot);
+        const uint32_t e = block_excl_scan256(v, s_w, total);
         if (c < live) row[c] = run + e;
-        run += tot;
+        run += total;
     }
+    if (t == 0) tot[d] = run;
 }
 
-template <typename KT, int VIEW>
+template <typename KT, int VIEW, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     KT *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
                                                     uint32_t zmin, int dbits, int shift, int nbits,
-                                                    const uint32_t *__restrict__ off, uint32_t chunks,
-                                                    const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+                                                    const uint32_t *__restrict__ off, const uint32_t *__restrict__ dtot,
+                                                    uint32_t chunks, const uint32_t *dyn_count,
+                                                    const uint32_t *dyn_zmin) {
+    constexpr uint32_t CHUNK = 256 * ITEMS;
     dyn_args(dyn_count, dyn_zmin, K, zmin);
-    if (blockIdx.x * (uint32_t)kSortChunk >= K) return;
+    if (blockIdx.x * CHUNK >= K) return;
     __shared__ uint32_t s_whist[4][256];   // per-wave digit counts, then per-wave digit prefix
     __shared__ uint32_t s_gbase[256];      // global position of this chunk's first key of each digit
     __shared__ uint32_t s_lstart[256];     // position in the LDS stage of each digit
     __shared__ uint32_t s_w[4];
-    __shared__ KT s_keys[kSortChunk];
-    __shared__ uint32_t s_vals[kSortChunk];
+    __shared__ KT s_keys[CHUNK];
+    __shared__ uint32_t s_vals[CHUNK];
 
     const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const uint32_t dmask = (1u << nbits) - 1u;
     const uint32_t chunk = blockIdx.x;
-    const uint32_t cbase = chunk * (uint32_t)kSortChunk;
+    const uint32_t cbase = chunk * (uint32_t)CHUNK;
     for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
-    if (t <= dmask) s_gbase[t] = off[(size_t)t * chunks + chunk];
+    {
+        uint32_t all;
+        const uint32_t dbase = block_excl_scan256(t <= dmask ? dtot[t] : 0u, s_w, all);
+        if (t <= dmask) s_gbase[t] = dbase + off[(size_t)t * chunks + chunk];
+    }
     __syncthreads();
 
-    KT key[kSortItems];
-    uint32_t val[kSortItems], rank[kSortItems];
+    KT key[ITEMS];
+    uint32_t val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = cbase + w * (64 * ITEMS) + r * 64 + lane;
         const bool valid = idx < K;
         key[r] = valid ? kin[idx] : (KT)0;
         val[r] = valid ? vin[idx] : 0u;
     }
     // stable rank within the wave, round by round (wave w holds a contiguous quarter)
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = cbase + w * (64 * ITEMS) + r * 64 + lane;
         const bool valid = idx < K;
         const uint32_t d = digit_of<KT, VIEW>(key[r], zmin, dbits, shift, dmask);
         uint64_t m = wave_ballot(valid);
@@ -190,8 +167,8 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
     s_lstart[t] = block_excl_scan256(tot, s_w, total);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t idx = cbase + w * (64 * kSortItems) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t idx = cbase + w * (64 * ITEMS) + r * 64 + lane;
         if (idx < K) {
             const uint32_t d = digit_of<KT, VIEW>(key[r], zmin, dbits, shift, dmask);
             const uint32_t pos = s_lstart[d] + s_whist[w][d] + rank[r];
@@ -200,7 +177,7 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
         }
     }
     __syncthreads();
-    const uint32_t nvalid = min((uint32_t)kSortChunk, K - cbase);
+    const uint32_t nvalid = min((uint32_t)CHUNK, K - cbase);
     for (uint32_t j = t; j < nvalid; j += 256) {
         const KT k = s_keys[j];
         const uint32_t d = digit_of<KT, VIEW>(k, zmin, dbits, shift, dmask);
@@ -213,10 +190,29 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
 // ---------------------------------------------------------------------------
 // Host side: sort K (key, value) pairs across the two buffers over `total_bits`
 // significant bits (passes of equal width, <= 8 bits each). Returns 1 if the result
-// is in the alternate buffers (kb/vb), 0 if in ka/va. `ghist` holds 8 x 256 zeroed
-// words; `cnt` 256 x ceil(K / 4096) words of scratch.
+// is in the alternate buffers (kb/vb), 0 if in ka/va. `ghist` holds 8 x 256 words
+// (each pass's digit totals); `cnt` 256 x ceil(K / 4096) words of scratch.
 // ---------------------------------------------------------------------------
 int sort_passes(int total_bits) { return (total_bits + 7) / 8; }
+
+// keys per thread of a pass over K keys: long chunks (long contiguous output runs) when
+// there are enough keys to fill the GPU with them, shorter ones otherwise
+static int sort_items(uint32_t K) { return K >= (1u << 22) ? 16 : (K >= (1u << 20) ? 8 : 4); }
+
+// words of the digit-count matrix a sort of K keys needs, and the most any sort of at
+// most K_max keys needs (the chunk length grows with K, so the need is not monotonic)
+static size_t count_words(uint64_t K) {
+    const uint64_t kk = K > 0xffffffffull ? 0xffffffffull : K;
+    const uint64_t chunk = 256ull * (uint64_t)sort_items((uint32_t)kk);
+    const uint64_t chunks = (K + chunk - 1) / chunk;
+    return 256 * (size_t)(chunks > 0 ? chunks : 1);
+}
+size_t sort_count_words(uint64_t K_max) {
+    const uint64_t a = K_max < (1ull << 20) - 1 ? K_max : (1ull << 20) - 1;
+    const uint64_t b = K_max < (1ull << 22) - 1 ? K_max : (1ull << 22) - 1;
+    const size_t wa = count_words(a), wb = count_words(b), wc = count_words(K_max);
+    return wa > wb ? (wa > wc ? wa : wc) : (wb > wc ? wb : wc);
+}
 
 template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
@@ -232,11 +228,9 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         bits |= (uint32_t)nb << (4 * p);
         rem -= nb;
     }
-    uint32_t blocks = (K + 256 * 16 - 1) / (256 * 16);
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_radix_hist<KT, VIEW>), dim3(blocks), dim3(256), 0, st, ka, K, zmin, dbits, passes, bits, ghist,
-                       dyn_count, dyn_zmin);
-    const uint32_t chunks = (K + kSortChunk - 1) / kSortChunk;
+    const int items = sort_items(K);
+    const uint32_t chunk_keys = 256u * (uint32_t)items;
+    const uint32_t chunks = (K + chunk_keys - 1) / chunk_keys;
     int alt = 0, shift = 0;
     for (int p = 0; p < passes; ++p) {
         const int nb = (bits >> (4 * p)) & 15;
@@ -244,11 +238,17 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         const uint32_t *vin = alt ? vb : va;
         KT *kout = alt ? ka : kb;
         uint32_t *vout = alt ? va : vb;
-        hipLaunchKernelGGL((k_radix_up<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,
-                           chunks, dyn_count, dyn_zmin);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, ghist + 256 * p, K, dyn_count);
-        hipLaunchKernelGGL((k_radix_down<KT, VIEW>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits,
-                           shift, nb, cnt, chunks, dyn_count, dyn_zmin);
+        uint32_t *tot = ghist + 256 * p;
+#define RECOGS_PASS(IT)                                                                                                    \
+    hipLaunchKernelGGL((k_radix_up<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,    \
+                       chunks, dyn_count, dyn_zmin);                                                                       \
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, chunk_keys, tot, K, dyn_count);     \
+    hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits, \
+                       shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin);
+        if (items == 16) { RECOGS_PASS(16) }
+        else if (items == 8) { RECOGS_PASS(8) }
+        else { RECOGS_PASS(4) }
+#undef RECOGS_PASS
         alt ^= 1;
         shift += nb;
     }

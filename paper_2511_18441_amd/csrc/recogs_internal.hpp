@@ -113,6 +113,26 @@ template <typename T> __device__ __forceinline__ T wave_max(T v) {
     for (int o = 32; o > 0; o >>= 1) { T w = __shfl_xor(v, o, 64); v = w > v ? w : v; }
     return v;
 }
+// Sum of a float over the first LANES lanes of the wave (64, or 32 / 16 when the
+// workgroup is smaller than a wave: the lanes past it do not exist and hold no
+// defined value) with DPP moves, each step one VALU add and no LDS crossbar: pairs,
+// quads, half rows and rows by lane permutes (every lane then holds its 16-lane
+// row's sum), then rows 0+1 and 2+3 by the row-15 broadcast and all four by the
+// row-31 broadcast. The total ends in lane LANES-1 and is returned to every lane.
+template <int CTRL, int ROW_MASK> __device__ __forceinline__ float dpp_add(float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+template <int LANES> __device__ __forceinline__ float wave_sum_dpp(float v) {
+    static_assert(LANES == 64 || LANES == 32 || LANES == 16, "16, 32 or 64 lanes");
+    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    if constexpr (LANES >= 32) v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    if constexpr (LANES == 64) v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANES - 1));
+}
+
 // inclusive prefix sum across the wave
 template <typename T> __device__ __forceinline__ T wave_incl_scan(T v) {
     const uint32_t l = lane_id();
@@ -177,10 +197,8 @@ struct ViewDev {
 
 constexpr int kScanItems = 16;                       // counts per thread of the scan
 constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
-constexpr int kSortItems = 16;                       // keys per thread per radix pass
-constexpr int kSortChunk = 256 * kSortItems;         // keys per radix workgroup
 constexpr int kMaxPasses = 8;
-constexpr int kEmitItems = 4;                        // groups of 64 per wave in the depth-ordered emission
+constexpr int kEmitItems = 4;                        // depth-ordered Gaussians per thread (emission reduce / offsets)
 constexpr int kEmitChunk = 256 * kEmitItems;         // depth-ordered Gaussians per emission workgroup
 
 // Per-Gaussian splat record for compositing: three float4

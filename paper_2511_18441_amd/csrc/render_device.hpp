@@ -132,16 +132,37 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev 
     }
 }
 
-constexpr int kBlendBatch = 256;   // splat records staged per LDS batch
+constexpr int kBlendBatch = 128;   // splat records staged per LDS batch (small enough for 8 waves per SIMD)
+
+// LDS staging of one batch: only what the per-pixel loop reads (the extent box is
+// used at staging, for the wave mask, and not kept). One 48-byte record per splat,
+// so a wave reads all of it from one address register.
+struct BlendRec {
+    float2 uv;        // projected centre
+    uint32_t mask;    // wave regions the alpha >= 1/255 box meets
+    uint32_t pad;
+    float4 r1;        // base-2 conic terms and log2 sigma
+    float4 rgb;       // colour (w unused)
+};
+struct BlendStage {
+    BlendRec r[kBlendBatch];
+};
 
 // One tile (local index `tile` of a W x H image with tiles_x tiles per row) whose
-// sorted list is vals[rg.x, rg.y); finalT / nproc may be null.
-template <int TW, int TH, int PPT>
+// sorted list is vals[rg.x, rg.y). With STATE the final transmittance and the
+// per-pixel count of list entries up to the last blended one are written (the
+// backward replays them); finalT / nproc are then non-null.
+//
+// Per pixel the transmittance T carries the state: T > 0 while compositing; at the
+// splat that would take it below 1e-4 it becomes -T (stopped, |T| is final). Every
+// lane evaluates every splat its wave takes, and selects leave a pixel that is
+// stopped, below the alpha threshold or stopping unchanged (C + r * 0 == C exactly),
+// so the per-pixel arithmetic is that of eq. 3 with no divergent branches.
+template <int TW, int TH, int PPT, bool STATE>
 __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *__restrict__ vals,
                                            const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
                                            float bg1, float bg2, float *__restrict__ image, float *__restrict__ finalT,
-                                           uint32_t *__restrict__ nproc, float4 *s_r0, float4 *s_r1, float4 *s_r2,
-                                           uint8_t *s_mask) {
+                                           uint32_t *__restrict__ nproc, BlendStage &sm) {
 #pragma clang fp contract(off)
     using Map = TileMap<TW, TH, PPT>;
     constexpr int NT = Map::NT;
@@ -155,26 +176,31 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
     const float pxc = (float)px + 0.5f;
     float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
     uint32_t last[PPT];
-    bool done[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int py = ty0 + lrow * PPT + j;
         pyc[j] = (float)py + 0.5f;
-        T[j] = 1.f; C0[j] = C1[j] = C2[j] = 0.f; last[j] = 0;
-        done[j] = !(px < W && py < H);
+        T[j] = (px < W && py < H) ? 1.f : -1.f;  // pixels outside the image start stopped
+        C0[j] = C1[j] = C2[j] = 0.f;
+        last[j] = 0;
     }
 
     for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
-        bool mine = true;
+        bool stopped = true;
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) mine = mine && done[j];
-        if (__syncthreads_and(mine)) break;
+        for (int j = 0; j < PPT; ++j) stopped = stopped && !(T[j] > 0.f);
+        if (__syncthreads_and(stopped)) break;
         for (int q = t; q < BATCH; q += NT) {
             const uint32_t k = start + q;
             if (k < rg.y) {
                 const SplatRec s = rec[vals[k]];
-                s_r0[q] = s.r0; s_r1[q] = s.r1; s_r2[q] = s.r2;
-                s_mask[q] = (uint8_t)Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                BlendRec b;
+                b.uv = make_float2(s.r0.x, s.r0.y);
+                b.mask = Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                b.pad = 0u;
+                b.r1 = s.r1;
+                b.rgb = s.r2;
+                sm.r[q] = b;
             }
         }
         __syncthreads();
@@ -183,27 +209,28 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
         for (int q = 0; q < nb; ++q) {
             bool alive = false;
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) alive = alive || !done[j];
+            for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
             if (!wave_ballot(alive)) break;
-            const uint32_t m = __builtin_amdgcn_readfirstlane((uint32_t)s_mask[q]);
+            const BlendRec &b = sm.r[q];
+            const uint32_t m = __builtin_amdgcn_readfirstlane(b.mask);
             if (!((m >> w) & 1u)) continue;
-            const float4 r0 = s_r0[q], r1 = s_r1[q], r2 = s_r2[q];
-            const ExpRow er = exp_row(r1, pxc - r0.x);
-            const uint32_t kq = krel0 + (uint32_t)q;
+            const float2 uv = b.uv;
+            const float4 r1 = b.r1, r2 = b.rgb;
+            const ExpRow er = exp_row(r1, pxc - uv.x);
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                if (done[j]) continue;
-                const float e = exp_at(er, r1, pyc[j] - r0.y);
-                if (e < kLog2AlphaMin) continue;
+                const float e = exp_at(er, r1, pyc[j] - uv.y);
                 const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
                 const float Tn = T[j] * (1.f - a);
-                if (Tn < kTMin) { done[j] = true; continue; }
-                const float wgt = a * T[j];
+                const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
+                const bool stop = Tn < kTMin;
+                const bool bl = ok && !stop;
+                const float wgt = bl ? a * T[j] : 0.f;
                 C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
                 C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
                 C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
-                T[j] = Tn;
-                last[j] = kq;
+                if constexpr (STATE) last[j] = bl ? krel0 + (uint32_t)q : last[j];
+                T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
             }
         }
     }
@@ -212,11 +239,14 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
         const int py = ty0 + lrow * PPT + j;
         if (px < W && py < H) {
             const int64_t p = (int64_t)py * W + px;
-            image[p * 3 + 0] = __builtin_fmaf(T[j], bg0, C0[j]);
-            image[p * 3 + 1] = __builtin_fmaf(T[j], bg1, C1[j]);
-            image[p * 3 + 2] = __builtin_fmaf(T[j], bg2, C2[j]);
-            if (finalT) finalT[p] = T[j];
-            if (nproc) nproc[p] = last[j];
+            const float Tf = fabsf(T[j]);
+            image[p * 3 + 0] = __builtin_fmaf(Tf, bg0, C0[j]);
+            image[p * 3 + 1] = __builtin_fmaf(Tf, bg1, C1[j]);
+            image[p * 3 + 2] = __builtin_fmaf(Tf, bg2, C2[j]);
+            if constexpr (STATE) {
+                finalT[p] = Tf;
+                nproc[p] = last[j];
+            }
         }
     }
 }

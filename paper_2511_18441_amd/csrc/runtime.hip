@@ -23,7 +23,10 @@ void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
-                        hipStream_t, const uint32_t *, const uint32_t *, const uint4 *, int);
+                        uint32_t, uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *,
+                        const uint32_t *, const uint4 *, int);
+uint32_t emit_blocks(uint32_t K);
+size_t sort_count_words(uint64_t K_max);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
@@ -36,7 +39,7 @@ int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uin
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
                       const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
-                        hipStream_t);
+                        float *, hipStream_t);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
@@ -87,12 +90,12 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     const int64_t P = (int64_t)W * H;
     const int64_t nn = n > 0 ? n : 1;
     const int64_t scan_chunks = (nn + kScanChunk - 1) / kScanChunk;
-    const int64_t sort_chunks = (cap + kSortChunk - 1) / kSortChunk;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     ws->off_rec = take(sizeof(SplatRec) * nn);
     ws->off_bwd = take(sizeof(float4) * nn);
     ws->off_grad = take(sizeof(float4) * nn);
+    ws->off_gpart = take(sizeof(float) * 9 * (size_t)((nn + 255) / 256));
     ws->off_zbits = take(4 * nn);
     ws->off_rect = take(8 * nn);
     ws->off_count = take(4 * nn);
@@ -110,16 +113,17 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     // scan partials per chunk: key count (u64), count with keys, depth min, depth max
     ws->off_scan = take(20 * (size_t)scan_chunks);
     ws->off_esum = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
-    // radix digit-count matrix [256][chunks], shared by the depth sort and the key sort
-    const int64_t cnt_chunks = sort_chunks > (nn + kSortChunk - 1) / kSortChunk ? sort_chunks : (nn + kSortChunk - 1) / kSortChunk;
-    ws->off_sort_count = take(4 * 256 * (size_t)(cnt_chunks > 0 ? cnt_chunks : 1));
+    ws->off_efirst = take(4 * ((size_t)emit_blocks((uint32_t)(cap > 0 ? cap : 1)) + 1));
+    // radix digit-count matrix [256][chunks], shared by the depth sort (up to n keys) and
+    // the key sort (up to cap keys)
+    ws->off_sort_count = take(4 * std::max(sort_count_words((uint64_t)nn), sort_count_words((uint64_t)(cap > 0 ? cap : 1))));
     // zeroed each render: header; histograms; tile ranges
     ws->off_header = take(4 * H_WORDS);
     ws->off_hist = take(4 * 256 * kMaxPasses);
     ws->off_dhist = take(4 * 256 * kMaxPasses);
     ws->off_ranges = take(8 * (size_t)T);
     ws->scan_chunks = (size_t)scan_chunks;
-    ws->sort_chunks = (size_t)sort_chunks;
+    ws->sort_chunks = std::max(sort_count_words((uint64_t)nn), sort_count_words((uint64_t)(cap > 0 ? cap : 1))) / 256;
     ws->tiles_x = (int32_t)tiles_x;
     ws->tiles_y = (int32_t)tiles_y;
     return o;
@@ -127,7 +131,6 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
 
 template <typename T> T *at(const recogs_workspace *ws, size_t off) { return (T *)((char *)ws->base + off); }
 
-// HIP events bracketing the stages of a profiled render (created once per thread)
 // Stage timing. Mode 1 uses the thread's own events and waits for the blend; mode 2
 // brackets the blend with one of the workspace's two event pairs, does not wait, and
 // harvests the other pair (recorded by the previous call, complete once this call's
@@ -467,8 +470,10 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         // the depth-ordered rectangles (8 bytes each) reuse both depth-key buffers, which are
         // adjacent and no longer needed once the order (values) is known
         uint2 *srect = (uint2 *)dk0;
-        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), t0, v0, stream,
-                           nullptr, nullptr, nullptr, 1);
+        // per-Gaussian key offsets go to the depth-value buffer the sort left free
+        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1,
+                           at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, t0, v0, stream, nullptr, nullptr, nullptr,
+                           nullptr, 1);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
@@ -488,8 +493,9 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     ws->sorted_in_alt = alt;
     if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0, rec, cam->width,
-                      cam->height, cd.tiles_x, opts->bg, image, at<float>(ws, ws->off_final_T),
-                      at<uint32_t>(ws, ws->off_nproc), stream))
+                      cam->height, cd.tiles_x, opts->bg, image,
+                      opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
+                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
     if ((s = tm.mark(8)) != RECOGS_OK) return s;
     if ((s = hip_check("blend")) != RECOGS_OK) return s;
@@ -513,7 +519,6 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
     const int ntiles = ws->tiles_x * ws->tiles_y;
     float4 *acc = at<float4>(ws, ws->off_grad);
     launch_fill_u32((uint32_t *)acc, 0u, 4 * n, stream);
-    launch_fill_u32((uint32_t *)dL_dM, 0u, 9, stream);
     const uint32_t *vals = ws->sorted_in_alt ? at<uint32_t>(ws, ws->off_vals1) : at<uint32_t>(ws, ws->off_vals0);
     if (ws->num_keys > 0) {
         if (!launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges), vals,
@@ -522,7 +527,7 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
             return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
     }
     launch_grad_finish(acc, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, dL_dsh_dc,
-                       dL_dM, stream);
+                       dL_dM, at<float>(ws, ws->off_gpart), stream);
     return hip_check("backward");
 }
 
@@ -575,7 +580,7 @@ size_t batch_layout(recogs_batch_workspace *ws, const recogs_batch_view *views, 
     const int64_t pp = P > 0 ? P : 1;
     const int64_t cc = cap > 0 ? cap : 1;
     const int64_t scan_chunks = (pp + kScanChunk - 1) / kScanChunk;
-    const int64_t cnt_chunks = std::max((pp + kSortChunk - 1) / kSortChunk, (cc + kSortChunk - 1) / kSortChunk);
+
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     ws->off_views = take(sizeof(ViewDev) * (size_t)nviews);
@@ -591,7 +596,8 @@ size_t batch_layout(recogs_batch_workspace *ws, const recogs_batch_view *views, 
     ws->off_dvals1 = take(4 * (size_t)pp);
     ws->off_scan = take(20 * (size_t)scan_chunks);
     ws->off_esum = take(4 * (size_t)((pp + kEmitChunk - 1) / kEmitChunk));
-    ws->off_sort_count = take(4 * 256 * (size_t)cnt_chunks);
+    ws->off_efirst = take(4 * ((size_t)emit_blocks((uint32_t)cc) + 1));
+    ws->off_sort_count = take(4 * std::max(sort_count_words((uint64_t)pp), sort_count_words((uint64_t)cc)));
     ws->off_keys0 = take(4 * (size_t)cc);
     ws->off_keys1 = take(4 * (size_t)cc);
     ws->off_vals0 = take(4 * (size_t)cc);
@@ -711,8 +717,9 @@ recogs_status recogs_render_batch(const recogs_batch_workspace *ws, hipStream_t 
     }
     // depth sort of the pairs with keys over all 32 depth bits above the minimum
     const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, P, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist, scount, stream);
-    launch_emit_sorted(dalt ? dv1 : dv0, P, rect, (uint2 *)dk0, 0, (uint32_t *)B(ws->off_esum), k0, v0, stream, hdr + H_V,
-                       hdr, (const uint4 *)B(ws->off_vtab), ws->nviews);
+    launch_emit_sorted(dalt ? dv1 : dv0, P, rect, (uint2 *)dk0, 0, (uint32_t *)B(ws->off_esum), dalt ? dv0 : dv1,
+                       (uint32_t *)B(ws->off_efirst), cap, k0, v0, stream, hdr + H_V, hdr + H_KEFF, hdr,
+                       (const uint4 *)B(ws->off_vtab), ws->nviews);
     const int alt = radix_sort_u32_dyn(k0, v0, k1, v1, cap, hdr + H_KEFF, nullptr, ws->tile_bits, hist, scount, stream);
     launch_ranges32(alt ? k1 : k0, cap, ranges, stream, hdr + H_KEFF);
     launch_tile_order(ranges, T, hdr + H_ORDER_HIST, hdr + H_ORDER_CUR, (uint32_t *)B(ws->off_order), stream);

@@ -156,7 +156,7 @@ def _check_integer_steps(w, orc, p, pr, n):
 def test_render_full_image(R, orc, cfg, sort_mode):
     w = synth.make_tiny() if cfg == "tiny" else synth.make_mid()
     n = w.scene.n
-    out = gpu_run(w, sort_mode=sort_mode)
+    out = gpu_run(w, sort_mode=sort_mode, keep_backward=True)
     p = pull(out, n)
     pr = _oracle(w, orc)
     zmis = _check_integer_steps(w, orc, p, pr, n)
@@ -164,8 +164,17 @@ def test_render_full_image(R, orc, cfg, sort_mode):
     err, nband = assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, cfg)
     assert err <= TOL_F32
     assert nband <= max(5, p["img"].shape[0] * p["img"].shape[1] // 1000)
-    # transmittance and last blended splat
+    # transmittance, and the last blended splat (the entry nproc - 1 of the pixel's tile
+    # list) wherever no threshold decision lies in the rounding band
     assert np.all(np.abs(p["T"] - ref.T) <= TOL_F32 + ref.slack)
+    H, W = p["nproc"].shape
+    ys, xs = np.mgrid[0:H, 0:W]
+    tid = (ys // 16) * ((W + 15) // 16) + xs // 16
+    first = p["ranges"][tid, 0].astype(np.int64)
+    np_ = p["nproc"]
+    gid = np.where(np_ > 0, p["vals"][np.clip(first + np_ - 1, 0, len(p["vals"]) - 1)], -1)
+    clean = ref.slack == 0
+    assert np.array_equal(gid[clean], ref.last[clean])
     print(f"{cfg}: K={p['K']} max|err| outside band {err:.2e}, in-band pixels {nband}, depth mismatches {int(zmis.sum())}")
 
 
@@ -232,6 +241,9 @@ def test_tile_shape_ppt_and_sort_mode_do_not_change_bits(R):
             for mode in [0, 1]:
                 img = gpu_run(w, tile=tile, ppt=ppt, sort_mode=mode)["img"].cpu().numpy()
                 assert np.array_equal(img, base), (tile, ppt, mode, np.abs(img - base).max())
+        # the blend that also writes the backward's per-pixel state draws the same bits
+        img = gpu_run(w, tile=tile, ppt=2, keep_backward=True)["img"].cpu().numpy()
+        assert np.array_equal(img, base), (tile, "keep_backward")
 
 
 def test_hue_permutation_exact_and_identity_exact(R):
