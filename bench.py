@@ -80,7 +80,7 @@ def algorithmic_model(st, storage_bytes, deg, keep_bwd=False):
         "emit": V * 16 + K * 8,
         "key_sort": K * 4 + P * K * 16,
         "ranges": K * 4 + T * 8,
-        "blend": Keff * 52 + T * 8 + Pix * 20,
+        "blend": Keff * 52 + T * 8 + Pix * (20 if keep_bwd else 12),
     }
     return b, {"blend": E * BLEND_FLOPS_PER_EVAL}
 
@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--ppt", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
+    ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff"], default=None,
+                    help="run only this form and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
     args = ap.parse_args()
@@ -424,6 +426,15 @@ def main():
     torch.cuda.set_device(0)
     tile = tuple(args.tile)
     tw, th = tile
+    if args.only_form:
+        if args.only_form == "batch":
+            res = form_batch(R, args.steps, args.warmup, dev)
+        elif args.only_form == "diff":
+            res = form_diff(R, args.steps, args.warmup, dev)
+        else:
+            res = form_single(R, args.only_form, tile, args.ppt, args.steps, args.warmup, dev)
+        print(json.dumps({"form": args.only_form, **res}), flush=True)
+        return
     log(f"bench: generating 1M-Gaussian scene ({args.storage})")
     w = synth.make_precision(storage=args.storage)
     s = Single(R, w, dev, tile, args.ppt)

@@ -128,7 +128,7 @@ typedef struct {
     int64_t key_capacity;
     int32_t tiles_x, tiles_y;
     /* buffer offsets */
-    size_t off_rec, off_bwd, off_grad, off_gpart, off_zbits, off_rect, off_count, off_offset, off_scan;
+    size_t off_rec, off_bwd, off_gpart, off_zbits, off_rect, off_count, off_offset, off_scan;
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_sort_count;
     size_t off_ranges, off_final_T, off_nproc, off_header;
     size_t off_dkeys0, off_dkeys1, off_dvals0, off_dvals1, off_dhist, off_esum, off_efirst;
@@ -217,8 +217,10 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
  * with keep_backward_state = 1) and its output image. dL_dimage float [H][W][3].
  * Outputs (overwritten): dL_dopacity float [n], dL_dsh_dc float [3][n] (gradient
  * w.r.t. the DC coefficients C_0 of each channel), dL_dM float [9] (zero when no
- * fused recolour). Accumulation order across workgroups is not fixed, so results
- * may differ in the last bits between runs. */
+ * fused recolour). No atomics: every sum is taken in a fixed order, so results are
+ * bit-identical between runs. The backward uses the workspace's sorted-key buffers
+ * (keys0/keys1) as per-key gradient scratch; the tile lists and the rest of the
+ * render's state stay valid, so it may be called again on the same render. */
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
                                      const recogs_render_opts *opts, const recogs_workspace *ws,
                                      const float *image, const float *dL_dimage, float *dL_dopacity,

@@ -64,7 +64,7 @@ class Workspace(ctypes.Structure):
                 ("tile_h", ctypes.c_int32), ("key_capacity", ctypes.c_int64), ("tiles_x", ctypes.c_int32),
                 ("tiles_y", ctypes.c_int32)] + \
                [(f, ctypes.c_size_t) for f in (
-                   "off_rec", "off_bwd", "off_grad", "off_gpart", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
+                   "off_rec", "off_bwd", "off_gpart", "off_zbits", "off_rect", "off_count", "off_offset", "off_scan",
                    "off_keys0", "off_keys1", "off_vals0", "off_vals1", "off_hist", "off_sort_count",
                    "off_ranges", "off_final_T", "off_nproc", "off_header", "off_dkeys0", "off_dkeys1", "off_dvals0",
                    "off_dvals1", "off_dhist", "off_esum", "off_efirst", "scan_chunks", "sort_chunks")] + \

@@ -9,8 +9,12 @@
 //   dL/drgb_i   += alpha_i T_i g
 //   dL/dalpha_i  = g . (rgb_i T_i - R_i / (1 - alpha_i))
 //   dL/dsigma_i += dL/dalpha_i G_i(p)   (0 where alpha is clamped at 0.99)
-// Per splat the workgroup's pixels are summed per wave (shuffles), then one atomic
-// per wave adds to the Gaussian's accumulator.
+// No float atomics: every (Gaussian, tile) pair owns one slot of a per-key gradient
+// array, Gaussian-contiguous (slot = the Gaussian's key offset from the count scan +
+// the tile's row-major rank in its tile rectangle). A splat's sums over one wave come
+// from DPP reductions, the waves of the tile add theirs in LDS, and one float4 store
+// per (splat, tile) writes the slot; k_grad_finish then sums each Gaussian's slots in
+// a fixed order, so the gradients are deterministic.
 #include "render_device.hpp"
 
 namespace recogs {
@@ -19,37 +23,46 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 
 template <int TW, int TH, int PPT>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-                                                           const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
+                                                           const SplatRec *__restrict__ rec, const uint2 *__restrict__ rect,
+                                                           const uint32_t *__restrict__ koff, int W, int H, int tiles_x,
                                                            const float *__restrict__ image, const float *__restrict__ dldy,
                                                            const uint32_t *__restrict__ nproc,
-                                                           float4 *__restrict__ acc) {
+                                                           float4 *__restrict__ gk) {
 #pragma clang fp contract(off)
     using Map = TileMap<TW, TH, PPT>;
     constexpr int NT = Map::NT;
+    constexpr int NW = (NT + 63) / 64;
     constexpr int BATCH = kBlendBatch;
-    __shared__ BlendStage sm;   // BlendRec.pad holds the Gaussian index, rgb.w the opacity
+    __shared__ BlendStage sm;   // BlendRec.pad holds the (Gaussian, tile) slot, rgb.w the opacity
+    __shared__ float4 s_acc[NW][BATCH];
     const int tile = blockIdx.x;
-    const int tx0 = (tile % tiles_x) * TW, ty0 = (tile / tiles_x) * TH;
+    const uint32_t tcx = (uint32_t)(tile % tiles_x), tcy = (uint32_t)(tile / tiles_x);
+    const int tx0 = (int)tcx * TW, ty0 = (int)tcy * TH;
     const int t = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(Map::wave(t));
+    const int wv = t >> 6;   // this thread's wave in the workgroup (slot of s_acc)
     int lx, lrow;
     Map::pixel(t, lx, lrow);
     const int px = tx0 + lx;
     const float pxc = (float)px + 0.5f;
-    float pyc[PPT], T[PPT], A0[PPT], A1[PPT], A2[PPT], y0[PPT], y1[PPT], y2[PPT], g0[PPT], g1[PPT], g2[PPT];
+    // Per pixel only g-weighted sums are carried: with s_i = g . rgb_i and
+    // Gr = g . (y - A) (the g-weighted colour not yet accounted for, starting at g . y),
+    // g . R_i = Gr - alpha_i T_i s_i, so dL/dalpha_i = T_i s_i - (Gr - alpha_i T_i s_i) / (1 - alpha_i)
+    // and Gr decreases by alpha_i T_i s_i after splat i.
+    float pyc[PPT], T[PPT], Gr[PPT], g0[PPT], g1[PPT], g2[PPT];
     uint32_t np[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int py = ty0 + lrow * PPT + j;
         pyc[j] = (float)py + 0.5f;
-        T[j] = 1.f; A0[j] = A1[j] = A2[j] = 0.f;
+        T[j] = 1.f;
         np[j] = 0;
-        y0[j] = y1[j] = y2[j] = g0[j] = g1[j] = g2[j] = 0.f;
+        Gr[j] = g0[j] = g1[j] = g2[j] = 0.f;
         if (px < W && py < H) {
             const int64_t p = (int64_t)py * W + px;
             np[j] = nproc[p];
-            y0[j] = image[p * 3]; y1[j] = image[p * 3 + 1]; y2[j] = image[p * 3 + 2];
             g0[j] = dldy[p * 3]; g1[j] = dldy[p * 3 + 1]; g2[j] = dldy[p * 3 + 2];
+            Gr[j] = g0[j] * image[p * 3] + g1[j] * image[p * 3 + 1] + g2[j] * image[p * 3 + 2];
         }
     }
     uint32_t npmax = 0;
@@ -64,14 +77,18 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
             if (k < rg.y) {
                 const uint32_t gid = vals[k];
                 const SplatRec s = rec[gid];
+                const uint2 rc = rect[gid];
+                const uint32_t rx0 = rc.x & 0xffffu, rx1 = rc.x >> 16, ry0 = rc.y & 0xffffu;
                 BlendRec b;
                 b.uv = make_float2(s.r0.x, s.r0.y);
                 b.mask = Map::wave_mask(s.r0, (float)tx0, (float)ty0);
-                b.pad = gid;
+                b.pad = koff[gid] + (tcy - ry0) * (rx1 - rx0 + 1) + (tcx - rx0);
                 b.r1 = s.r1;
                 b.rgb = s.r2;
                 sm.r[q] = b;
             }
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) s_acc[ww][q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
@@ -97,29 +114,31 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const float araw = __builtin_amdgcn_exp2f(e);
                 const float a = fminf(kAlphaMax, araw);
                 const float wgt = act ? a * T[j] : 0.f;
-                const float c0 = r2.x * wgt, c1 = r2.y * wgt, c2 = r2.z * wgt;
-                const float R0 = y0[j] - A0[j] - c0, R1 = y1[j] - A1[j] - c1, R2 = y2[j] - A2[j] - c2;
-                const float inv1ma = 1.f / (1.f - a);
-                const float dal = g0[j] * (r2.x * T[j] - R0 * inv1ma) + g1[j] * (r2.y * T[j] - R1 * inv1ma) +
-                                  g2[j] * (r2.z * T[j] - R2 * inv1ma);
+                const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
+                const float ws = wgt * sg;
+                const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
                 dr += wgt * g0[j];
                 dg += wgt * g1[j];
                 db += wgt * g2[j];
                 ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
-                A0[j] += c0; A1[j] += c1; A2[j] += c2;
+                Gr[j] -= ws;
                 T[j] = act ? T[j] * (1.f - a) : T[j];
             }
             if (wave_ballot(any)) {
                 constexpr int L = NT < 64 ? NT : 64;
                 ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
-                if (lane_id() == 0) {
-                    float *pa = (float *)&acc[b.pad];
-                    atomicAdd(pa + 0, ds);
-                    atomicAdd(pa + 1, dr);
-                    atomicAdd(pa + 2, dg);
-                    atomicAdd(pa + 3, db);
-                }
+                if (lane_id() == 0) s_acc[wv][q] = make_float4(ds, dr, dg, db);
             }
+        }
+        __syncthreads();
+        for (int q = t; q < nb; q += NT) {
+            float4 v = s_acc[0][q];
+#pragma unroll
+            for (int ww = 1; ww < NW; ++ww) {
+                const float4 x = s_acc[ww][q];
+                v.x += x.x; v.y += x.y; v.z += x.z; v.w += x.w;
+            }
+            if (v.x != 0.f || v.y != 0.f || v.z != 0.f || v.w != 0.f) gk[sm.r[q].pad] = v;
         }
     }
 }
@@ -129,9 +148,9 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 //   selected:   dL/dC0 = Y00 M^T gh, dL/dM += gh (f + 1/2)^T;  unselected: dL/dC0 = Y00 gh.
 // dL/dM is reduced without atomics: each workgroup writes its 9 partial sums to
 // part[block][9] and k_dm_reduce adds them in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ acc, const float4 *__restrict__ bwd,
-                                                     const uint32_t *__restrict__ count, int64_t n,
-                                                     const float *__restrict__ M, float *__restrict__ dop,
+__global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ gk, const uint32_t *__restrict__ koff,
+                                                     const float4 *__restrict__ bwd, const uint32_t *__restrict__ count,
+                                                     int64_t n, const float *__restrict__ M, float *__restrict__ dop,
                                                      float *__restrict__ ddc, float *__restrict__ part) {
     __shared__ float s_dm[4][9];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,8 +160,13 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
     if (i < n) {
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t flags = 0;
-        if (count[i] > 0) {
-            a = acc[i];
+        const uint32_t c = count[i];
+        if (c > 0) {
+            const float4 *slot = gk + koff[i];
+            for (uint32_t k = 0; k < c; ++k) {  // the Gaussian's (Gaussian, tile) slots, in order
+                const float4 x = slot[k];
+                a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+            }
             const float4 b = bwd[i];
             flags = __float_as_uint(b.w);
             f[0] = b.x; f[1] = b.y; f[2] = b.z;
@@ -213,19 +237,20 @@ __global__ __launch_bounds__(256) void k_loss_l2(const float *__restrict__ y, co
 
 // ---------------------------------------------------------------------------
 template <int TW, int TH, int PPT>
-static void bwd_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec, int W, int H,
-                    int tiles_x, const float *image, const float *dldy, const uint32_t *nproc, float4 *acc) {
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W, H, tiles_x,
-                       image, dldy, nproc, acc);
+static void bwd_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
+                    const uint2 *rect, const uint32_t *koff, int W, int H, int tiles_x, const float *image,
+                    const float *dldy, const uint32_t *nproc, float4 *gk) {
+    hipLaunchKernelGGL((k_blend_bwd<TW, TH, PPT>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, rect, koff, W,
+                       H, tiles_x, image, dldy, nproc, gk);
 }
 
 bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
-                      int W, int H, int tiles_x, const float *image, const float *dldy, const uint32_t *nproc, float4 *acc,
-                      hipStream_t st) {
-#define RECOGS_BWD_CASE(A, B, P)                                                                     \
-    if (tw == A && th == B && ppt == P) {                                                            \
-        bwd_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, image, dldy, nproc, acc);     \
-        return true;                                                                                 \
+                      const uint2 *rect, const uint32_t *koff, int W, int H, int tiles_x, const float *image,
+                      const float *dldy, const uint32_t *nproc, float4 *gk, hipStream_t st) {
+#define RECOGS_BWD_CASE(A, B, P)                                                                                 \
+    if (tw == A && th == B && ppt == P) {                                                                        \
+        bwd_one<A, B, P>(ntiles, st, ranges, vals, rec, rect, koff, W, H, tiles_x, image, dldy, nproc, gk);      \
+        return true;                                                                                             \
     }
     RECOGS_BWD_CASE(16, 16, 1) RECOGS_BWD_CASE(16, 16, 2) RECOGS_BWD_CASE(16, 16, 4)
     RECOGS_BWD_CASE(8, 8, 1) RECOGS_BWD_CASE(8, 8, 2) RECOGS_BWD_CASE(8, 8, 4)
@@ -235,11 +260,11 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
 }
 
 // part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n)
-void launch_grad_finish(const float4 *acc, const float4 *bwd, const uint32_t *count, int64_t n, const float *M, float *dop,
-                        float *ddc, float *dM, float *part, hipStream_t st) {
+void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bwd, const uint32_t *count, int64_t n,
+                        const float *M, float *dop, float *ddc, float *dM, float *part, hipStream_t st) {
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
     if (n > 0)
-        hipLaunchKernelGGL(k_grad_finish, dim3(blocks), dim3(256), 0, st, acc, bwd, count, n, M, dop, ddc, part);
+        hipLaunchKernelGGL(k_grad_finish, dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, ddc, part);
     if (M && n > 0) hipLaunchKernelGGL(k_dm_reduce, dim3(1), dim3(256), 0, st, part, blocks, dM);
     else launch_fill_u32((uint32_t *)dM, 0u, 9, st);
 }

@@ -36,10 +36,10 @@ int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint
                             uint32_t *, hipStream_t);
 int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
                    hipStream_t);
-bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
-                      const float *, const uint32_t *, float4 *, hipStream_t);
-void launch_grad_finish(const float4 *, const float4 *, const uint32_t *, int64_t, const float *, float *, float *, float *,
-                        float *, hipStream_t);
+bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
+                      int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
+void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
+                        float *, float *, float *, hipStream_t);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
@@ -94,7 +94,6 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     ws->off_rec = take(sizeof(SplatRec) * nn);
     ws->off_bwd = take(sizeof(float4) * nn);
-    ws->off_grad = take(sizeof(float4) * nn);
     ws->off_gpart = take(sizeof(float) * 9 * (size_t)((nn + 255) / 256));
     ws->off_zbits = take(4 * nn);
     ws->off_rect = take(8 * nn);
@@ -517,17 +516,20 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
     const int64_t n = scene->n;
     const int ntiles = ws->tiles_x * ws->tiles_y;
-    float4 *acc = at<float4>(ws, ws->off_grad);
-    launch_fill_u32((uint32_t *)acc, 0u, 4 * n, stream);
+    // per-(Gaussian, tile) gradient slots, 16 bytes per key: the span of both sorted-key
+    // buffers (adjacent, 16 bytes per key of capacity), which the backward does not read
+    float4 *gk = at<float4>(ws, ws->off_keys0);
+    const uint32_t *koff = at<uint32_t>(ws, ws->off_offset);
     const uint32_t *vals = ws->sorted_in_alt ? at<uint32_t>(ws, ws->off_vals1) : at<uint32_t>(ws, ws->off_vals0);
     if (ws->num_keys > 0) {
+        launch_fill_u32((uint32_t *)gk, 0u, 4 * ws->num_keys, stream);
         if (!launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges), vals,
-                              at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, ws->tiles_x, image, dL_dimage,
-                              at<uint32_t>(ws, ws->off_nproc), acc, stream))
+                              at<SplatRec>(ws, ws->off_rec), at<uint2>(ws, ws->off_rect), koff, cam->width, cam->height,
+                              ws->tiles_x, image, dL_dimage, at<uint32_t>(ws, ws->off_nproc), gk, stream))
             return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
     }
-    launch_grad_finish(acc, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, dL_dsh_dc,
-                       dL_dM, at<float>(ws, ws->off_gpart), stream);
+    launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity,
+                       dL_dsh_dc, dL_dM, at<float>(ws, ws->off_gpart), stream);
     return hip_check("backward");
 }
 

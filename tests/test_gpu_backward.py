@@ -84,6 +84,33 @@ def test_backward_vs_oracle(R, orc, tile, ppt):
     print(f"relative max errors: dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")
 
 
+def test_backward_is_deterministic_and_repeatable(R, orc):
+    """No atomics: two renders + backwards give the same bits, and a second backward
+    on the same render (its per-key scratch overwritten) gives them too."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    a = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (16, 16), 2)
+    c = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (16, 16), 2)
+    img = a[0]
+    gt = torch.from_numpy(g).cuda()
+    n = d.n
+    dop = torch.empty(n, device="cuda")
+    ddc = torch.empty((3, n), device="cuda")
+    dM = torch.empty(9, device="cuda")
+    o = R.opts_struct((16, 16), 2, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, c[0].data_ptr(), gt.data_ptr(),
+                             dop.data_ptr(), ddc.data_ptr(), dM.data_ptr())
+    torch.cuda.synchronize()
+    again = (dop.cpu().numpy().astype(np.float64), ddc.cpu().numpy().astype(np.float64),
+             dM.cpu().numpy().astype(np.float64).reshape(3, 3))
+    assert torch.equal(a[0], c[0])
+    for x, y, z in zip(a[1:], c[1:], again):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    assert np.abs(a[1]).max() > 0
+
+
 def test_backward_matches_gpu_finite_differences(R, orc):
     """Central differences of the GPU's own float32 loss sum(g * y) w.r.t. M (loose: the
     float32 forward has ~1e-7 relative noise, the step is 1e-2)."""
