@@ -81,7 +81,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const uint32_t rx0 = rc.x & 0xffffu, rx1 = rc.x >> 16, ry0 = rc.y & 0xffffu;
                 BlendRec b;
                 b.uv = make_float2(s.r0.x, s.r0.y);
-                b.mask = Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                b.mask = Map::wave_mask(s.r0, s.r1, (float)tx0, (float)ty0);
                 b.pad = koff[gid] + (tcy - ry0) * (rx1 - rx0 + 1) + (tcx - rx0);
                 b.r1 = s.r1;
                 b.rgb = s.r2;

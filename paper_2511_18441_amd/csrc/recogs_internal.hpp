@@ -213,6 +213,30 @@ struct SplatRec { float4 r0, r1, r2; };
 // pixels. Where the tile allows it, each wave covers a compact 8 x (8 PPT) block
 // ("wave region"); otherwise the wave region is the whole tile.
 // ---------------------------------------------------------------------------
+// Largest e(dx, dy) = A dx^2 + B dx dy + C dy^2 + o (r1 = (A, B, C, o), A, C < 0: a
+// concave quadratic with its maximum o at the splat centre) over the rectangle
+// [dx0, dx1] x [dy0, dy1]. With the centre outside, the maximum lies on an edge; on
+// each edge the 1-D maximum is at the clamped stationary point.
+__device__ __forceinline__ float emax_rect(float4 r1, float dx0, float dx1, float dy0, float dy1) {
+    if (dx0 <= 0.f && 0.f <= dx1 && dy0 <= 0.f && 0.f <= dy1) return r1.w;
+    const float ia = -0.5f / r1.x, ic = -0.5f / r1.z;   // 1 / (-2A), 1 / (-2C)
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float X = k ? dx1 : dx0;
+        const float dy = fminf(fmaxf(r1.y * X * ic, dy0), dy1);
+        m = fmaxf(m, (r1.x * X + r1.y * dy) * X + r1.z * dy * dy + r1.w);
+        const float Y = k ? dy1 : dy0;
+        const float dx = fminf(fmaxf(r1.y * Y * ia, dx0), dx1);
+        m = fmaxf(m, (r1.z * Y + r1.y * dx) * Y + r1.x * dx * dx + r1.w);
+    }
+    return m;
+}
+// exponent margin of the region test (alpha 0.3 % below 1/255), far above the float32
+// error of either evaluation: pixel offsets dx = (px + 1/2) - u are exact (Sterbenz)
+// and the quadratic carries a few ulps
+constexpr float kMaskMargin = 4e-3f;
+
 template <int TW, int TH, int PPT> struct TileMap {
     static constexpr int NT = TW * TH / PPT;
     static constexpr bool BLOCKS = (TW % 8 == 0) && ((TH / PPT) % 8 == 0);
@@ -240,17 +264,22 @@ template <int TW, int TH, int PPT> struct TileMap {
             y0 = 0.5f; y1 = (float)TH - 0.5f;
         }
     }
-    // bit w set when the splat's alpha >= 1/255 box (centre u, v, half-extents ex, ey)
-    // meets a pixel centre of wave region w. Outside the box q exceeds 2 ln(255 sigma)
-    // + 1/64, so alpha < 1/255 there by a margin far above float32 error: skipping is exact.
-    static __device__ __forceinline__ uint32_t wave_mask(float4 r0, float tx0, float ty0) {
+    // bit w set when the splat can reach alpha >= 1/255 at a pixel centre of wave region
+    // w: its alpha >= 1/255 box (centre u, v, half-extents ex, ey) meets the region's
+    // pixel-centre rectangle, and the largest base-2 exponent over that rectangle
+    // (exact maximum of the concave quadratic, see emax_rect) is at least the threshold
+    // less a margin far above float32 error. Skipping a region is therefore exact.
+    static __device__ __forceinline__ uint32_t wave_mask(float4 r0, float4 r1, float tx0, float ty0) {
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             float x0, x1, y0, y1;
             bounds(w, x0, x1, y0, y1);
-            const bool hit = !(r0.x + r0.z < tx0 + x0 || r0.x - r0.z > tx0 + x1 || r0.y + r0.w < ty0 + y0 ||
-                               r0.y - r0.w > ty0 + y1);
+            bool hit = !(r0.x + r0.z < tx0 + x0 || r0.x - r0.z > tx0 + x1 || r0.y + r0.w < ty0 + y0 ||
+                         r0.y - r0.w > ty0 + y1);
+            if (hit)
+                hit = emax_rect(r1, tx0 + x0 - r0.x, tx0 + x1 - r0.x, ty0 + y0 - r0.y, ty0 + y1 - r0.y) >=
+                      kLog2AlphaMin - kMaskMargin;
             m |= (hit ? 1u : 0u) << w;
         }
         return m;

@@ -196,7 +196,7 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
                 const SplatRec s = rec[vals[k]];
                 BlendRec b;
                 b.uv = make_float2(s.r0.x, s.r0.y);
-                b.mask = Map::wave_mask(s.r0, (float)tx0, (float)ty0);
+                b.mask = Map::wave_mask(s.r0, s.r1, (float)tx0, (float)ty0);
                 b.pad = 0u;
                 b.r1 = s.r1;
                 b.rgb = s.r2;
