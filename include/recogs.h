@@ -111,7 +111,13 @@ typedef struct {
      * depth digits sorted before the keys are duplicated). 1: emit 64-bit keys
      * (tile << 32) | depth bits in index order and radix-sort them. */
     int32_t sort_mode;
-    int32_t reserved;
+    /* 1: no host synchronisation (the render may be captured in a HIP graph). The
+     * key count, capacity decision and overflow flag stay on the device: a view with
+     * more keys than ws->key_capacity draws only the background, and
+     * recogs_workspace_readback reports num_keys / num_visible afterwards
+     * (num_keys > key_capacity: overflowed). Needs sort_mode 0; profile_stages 0 or 2.
+     * 0: the render reads the key count back once (eager capacity check). */
+    int32_t graph_mode;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds
@@ -167,6 +173,10 @@ size_t recogs_workspace_bytes(int64_t n, int32_t width, int32_t height, int32_t 
 recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t bytes, int64_t n,
                                     int32_t width, int32_t height, int32_t tile_w, int32_t tile_h,
                                     int64_t key_capacity);
+
+/* After a graph_mode render: wait for it and fill ws->num_keys (keys the view needs),
+ * ws->num_visible and ws->depth_min_bits from the device header. */
+recogs_status recogs_workspace_readback(recogs_workspace *ws, hipStream_t stream);
 
 /* Wait for the workspace's last profile_stages = 2 render and add its stage durations
  * to stage_ms_sum / profiled_frames. OK when nothing is pending. */

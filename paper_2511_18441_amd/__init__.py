@@ -8,7 +8,7 @@ has not been built.
 from .binding import (  # noqa: F401
     ENTRY_POINTS, RecogsError, DeviceScene, DeviceWorkspace, Scene, Camera, SelectParams, RenderOpts, Workspace,
     camera_struct, select_struct, opts_struct, render, lib,
-    recogs_workspace_bytes, recogs_workspace_init, recogs_workspace_profile_flush, recogs_workspace_release,
+    recogs_workspace_bytes, recogs_workspace_init, recogs_workspace_readback, recogs_workspace_profile_flush, recogs_workspace_release,
     recogs_prepare_covariance, recogs_select, recogs_recolor,
     recogs_render, recogs_render_backward, recogs_loss_l2, recogs_last_error,
     BATCH_ENTRY_POINTS, BatchView, BatchWorkspace, DeviceBatch, recogs_batch_workspace_bytes, recogs_batch_init,

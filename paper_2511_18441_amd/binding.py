@@ -23,7 +23,8 @@ STATUS = {0: "OK", -1: "INVALID", -2: "CAPACITY", -3: "UNSUPPORTED", -4: "HIP"}
 STORAGE_CODE = {"f32": RECOGS_F32, "f16": RECOGS_F16, "bf16": RECOGS_BF16}
 
 # every entry point declared in include/recogs.h
-ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_workspace_profile_flush",
+ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_workspace_readback",
+                "recogs_workspace_profile_flush",
                 "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_last_error")
 
@@ -55,7 +56,7 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
-                ("sort_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32)]
 
 
 class Workspace(ctypes.Structure):
@@ -93,6 +94,7 @@ def lib():
         L.recogs_workspace_bytes.argtypes = [i64, i32, i32, i32, i32, i64]
         L.recogs_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_workspace_init.argtypes = [P(Workspace), vp, ctypes.c_size_t, i64, i32, i32, i32, i32, i64]
+        L.recogs_workspace_readback.argtypes = [P(Workspace), vp]
         L.recogs_workspace_profile_flush.argtypes = [P(Workspace)]
         L.recogs_workspace_release.argtypes = [P(Workspace)]
         L.recogs_workspace_release.restype = None
@@ -133,6 +135,10 @@ def recogs_workspace_bytes(n, width, height, tile_w, tile_h, key_capacity) -> in
 def recogs_workspace_init(ws: Workspace, dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity):
     return _check("recogs_workspace_init", lib().recogs_workspace_init(
         ctypes.byref(ws), dev_mem, nbytes, n, width, height, tile_w, tile_h, key_capacity))
+
+
+def recogs_workspace_readback(ws: Workspace, stream=None):
+    return _check("recogs_workspace_readback", lib().recogs_workspace_readback(ctypes.byref(ws), _stream(stream)))
 
 
 def recogs_workspace_profile_flush(ws: Workspace):
@@ -205,7 +211,7 @@ def select_struct(sp) -> SelectParams:
 
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
-                profile=False, sort_mode=0) -> RenderOpts:
+                profile=False, sort_mode=0, graph_mode=False) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -217,6 +223,7 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.keep_backward_state = 1 if keep_backward else 0
     o.profile_stages = int(profile)  # False/True -> 0/1; 2 = accumulate without waiting
     o.sort_mode = int(sort_mode)
+    o.graph_mode = 1 if graph_mode else 0
     return o
 
 
@@ -296,6 +303,11 @@ class DeviceWorkspace:
         except Exception:
             pass
 
+    def readback(self, stream=None):
+        """After graph_mode renders: (num_keys, num_visible) of the last one."""
+        recogs_workspace_readback(self.ws, stream)
+        return int(self.ws.num_keys), int(self.ws.num_visible)
+
     def blend_time(self):
         """Mean blend milliseconds over the profile_stages=2 renders so far (waits for the
         last one) and their count."""
@@ -359,14 +371,15 @@ class DeviceWorkspace:
 
 def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
            M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False,
-           sort_mode=0):
+           sort_mode=0, graph_mode=False):
     """recogs_render into a (H, W, 3) float32 tensor; grows the workspace once when the
-    view needs more tile keys than it holds."""
+    view needs more tile keys than it holds (eager mode). With graph_mode nothing is
+    read back: check ws.readback() (num_keys > key_capacity means it overflowed)."""
     import torch
     c = camera_struct(cam)
     if image is None:
         image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dscene.means.device)
-    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode)
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode)
     sc = dscene.c_struct(sh)
     st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     if st == -2 and grow:

@@ -279,6 +279,10 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (!tile_supported(o->tile_w, o->tile_h))
         return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8", o->tile_w, o->tile_h);
     if (o->sort_mode != 0 && o->sort_mode != 1) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0 or 1", o->sort_mode);
+    if (o->graph_mode != 0 && o->graph_mode != 1) return fail(RECOGS_ERR_INVALID, "graph_mode %d not 0 or 1", o->graph_mode);
+    if (o->graph_mode && o->sort_mode != 0) return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode needs sort_mode 0");
+    if (o->graph_mode && o->profile_stages == 1)
+        return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode renders do not wait: use profile_stages 0 or 2");
     if (o->profile_stages < 0 || o->profile_stages > 2)
         return fail(RECOGS_ERR_INVALID, "profile_stages %d not 0, 1 or 2", o->profile_stages);
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
@@ -300,6 +304,65 @@ recogs_status check_ws(const recogs_workspace *ws, const recogs_scene *sc, const
 }
 
 }  // namespace
+
+// The rest of a render in graph mode: no host synchronisation. Counts, the depth
+// minimum, the capacity decision and the overflow flag stay in the workspace header;
+// grids are sized for n Gaussians and key_capacity keys and workgroups past the live
+// counts return at once (sort mode 0, all 32 depth bits above the minimum).
+static recogs_status render_async(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
+                                  recogs_workspace *ws, float *image, hipStream_t stream, const CamDev &cd,
+                                  StageTimer &tm) {
+    recogs_status s;
+    const int64_t n = scene->n;
+    const int ntiles = cd.tiles_x * cd.tiles_y;
+    const uint32_t cap = (uint32_t)ws->key_capacity;
+    uint32_t *hdr = at<uint32_t>(ws, ws->off_header);
+    uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
+    uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
+    uint32_t *t0 = at<uint32_t>(ws, ws->off_keys0), *t1 = at<uint32_t>(ws, ws->off_keys1);
+    uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
+    uint32_t *hist = at<uint32_t>(ws, ws->off_hist), *dhist = at<uint32_t>(ws, ws->off_dhist);
+    uint32_t *scount = at<uint32_t>(ws, ws->off_sort_count);
+    uint2 *ranges = at<uint2>(ws, ws->off_ranges);
+    const int tbits = bits_for((uint64_t)(ntiles - 1));
+    ws->num_keys = -1;   // known after recogs_workspace_readback
+    ws->num_visible = -1;
+    ws->last_n = (int32_t)n;
+    ws->sort_mode = 0;
+    ws->depth_bits = 32;
+    ws->depth_min_bits = 0;
+    ws->key_bits = tbits + 32;
+    ws->sort_passes = sort_passes(tbits);
+    ws->depth_passes = sort_passes(32);
+    ws->key_bytes = 4;
+    int alt = 0;
+    if (n > 0 && cap > 0) {
+        const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, (uint32_t)n, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist, scount,
+                                            stream);
+        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        launch_emit_sorted(dalt ? dv1 : dv0, (uint32_t)n, at<uint2>(ws, ws->off_rect), (uint2 *)dk0, cd.tiles_x,
+                           at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1, at<uint32_t>(ws, ws->off_efirst), cap, t0, v0,
+                           stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+        if ((s = tm.mark(5)) != RECOGS_OK) return s;
+        alt = radix_sort_u32_dyn(t0, v0, t1, v1, cap, hdr + H_KEFF, nullptr, tbits, hist, scount, stream);
+        if ((s = tm.mark(6)) != RECOGS_OK) return s;
+        launch_ranges32(alt ? t1 : t0, cap, ranges, stream, hdr + H_KEFF);
+    } else {
+        for (int k = 4; k <= 6; ++k)
+            if ((s = tm.mark(k)) != RECOGS_OK) return s;
+    }
+    if ((s = tm.mark(7)) != RECOGS_OK) return s;
+    ws->sorted_in_alt = alt;
+    if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
+    if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0,
+                      at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, cd.tiles_x, opts->bg, image,
+                      opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
+                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
+        return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
+    if ((s = tm.mark(8)) != RECOGS_OK) return s;
+    if ((s = hip_check("blend")) != RECOGS_OK) return s;
+    return tm.finish(ws, 8);
+}
 
 extern "C" {
 
@@ -339,6 +402,19 @@ recogs_status recogs_workspace_profile_flush(recogs_workspace *ws) {
     if (!ps) return RECOGS_OK;
     harvest(ws, ps->set[ps->cur]);      // older
     harvest(ws, ps->set[ps->cur ^ 1]);  // latest
+    return RECOGS_OK;
+}
+
+recogs_status recogs_workspace_readback(recogs_workspace *ws, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!ws || !ws->base) return fail(RECOGS_ERR_INVALID, "workspace not initialised");
+    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    RECOGS_TRY_HIP(hipMemcpyAsync(h, at<uint32_t>(ws, ws->off_header), sizeof(h), hipMemcpyDeviceToHost, stream));
+    RECOGS_TRY_HIP(hipStreamSynchronize(stream));
+    const bool any = ws->last_n > 0;
+    ws->num_keys = any ? (int64_t)((uint64_t)h[H_K_LO] | ((uint64_t)h[H_K_HI] << 32)) : 0;
+    ws->num_visible = any ? h[H_V] : 0;
+    ws->depth_min_bits = any ? h[H_ZMIN_RAW] : 0;
     return RECOGS_OK;
 }
 
@@ -413,8 +489,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     const int mode = opts->sort_mode;
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
     uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
-    // zero the header
-    launch_fill_u32(hdr, 0u, H_WORDS, stream);
+    // zero the header (in graph mode also the digit totals and tile ranges, adjacent)
+    launch_fill_u32(hdr, 0u,
+                    opts->graph_mode ? (int64_t)((ws->off_ranges - ws->off_header) / 4) + 2 * (int64_t)ntiles
+                                     : (int64_t)H_WORDS,
+                    stream);
     RecolorDev rc{opts->mask, opts->M, opts->b};
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
                       rect, cnt, stream);
@@ -427,6 +506,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
+    if (opts->graph_mode) return render_async(scene, cam, opts, ws, image, stream, cd, tm);
 
     uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     RECOGS_TRY_HIP(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
@@ -512,6 +592,9 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
     if ((s = check_ws(ws, scene, cam, opts)) != RECOGS_OK) return s;
     if (!opts->keep_backward_state) return fail(RECOGS_ERR_INVALID, "render must keep backward state for the backward");
     if (ws->last_n != scene->n) return fail(RECOGS_ERR_INVALID, "workspace holds a render of %d Gaussians, scene has %lld", ws->last_n, (long long)scene->n);
+    if (ws->num_keys < 0)
+        return fail(RECOGS_ERR_INVALID, "after a graph_mode render, call recogs_workspace_readback before the backward");
+    if (ws->num_keys > ws->key_capacity) return fail(RECOGS_ERR_INVALID, "the render overflowed its key capacity");
     if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || !dL_dsh_dc)))
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
     const int64_t n = scene->n;
