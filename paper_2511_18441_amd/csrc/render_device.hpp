@@ -206,31 +206,52 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
         __syncthreads();
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
         const uint32_t krel0 = start + 1 - rg.x;
-        for (int q = 0; q < nb; ++q) {
-            bool alive = false;
+        // the batch's records this wave takes, as a scalar bit set per 64 records; the
+        // loop walks its set bits in order
+        constexpr int L = NT < 64 ? NT : 64;   // lanes of a wave (a workgroup may be a partial wave)
+        uint64_t todo[BATCH / 64];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
-            if (!wave_ballot(alive)) break;
-            const BlendRec &b = sm.r[q];
-            const uint32_t m = __builtin_amdgcn_readfirstlane(b.mask);
-            if (!((m >> w) & 1u)) continue;
-            const float2 uv = b.uv;
-            const float4 r1 = b.r1, r2 = b.rgb;
-            const ExpRow er = exp_row(r1, pxc - uv.x);
+        for (int c = 0; c < BATCH / 64; ++c) {
+            todo[c] = 0;
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                const float e = exp_at(er, r1, pyc[j] - uv.y);
-                const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
-                const float Tn = T[j] * (1.f - a);
-                const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
-                const bool stop = Tn < kTMin;
-                const bool bl = ok && !stop;
-                const float wgt = bl ? a * T[j] : 0.f;
-                C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
-                C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
-                C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
-                if constexpr (STATE) last[j] = bl ? krel0 + (uint32_t)q : last[j];
-                T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
+            for (int sub = 0; sub < 64 / L; ++sub) {
+                const int q = c * 64 + sub * L + (int)lane_id();
+                todo[c] |= wave_ballot(q < nb && ((sm.r[q].mask >> w) & 1u)) << (sub * L);
+            }
+        }
+        bool quit = false;
+#pragma unroll
+        for (int c = 0; c < BATCH / 64; ++c) {
+            uint64_t mm = todo[c];
+            while (mm && !quit) {
+                const int q = c * 64 + (int)__builtin_ctzll(mm);
+                mm &= mm - 1;
+                bool alive = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
+                if (!wave_ballot(alive)) {
+                    quit = true;
+                    break;
+                }
+                const BlendRec &b = sm.r[q];
+                const float2 uv = b.uv;
+                const float4 r1 = b.r1, r2 = b.rgb;
+                const ExpRow er = exp_row(r1, pxc - uv.x);
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const float e = exp_at(er, r1, pyc[j] - uv.y);
+                    const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+                    const float Tn = T[j] * (1.f - a);
+                    const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
+                    const bool stop = Tn < kTMin;
+                    const bool bl = ok && !stop;
+                    const float wgt = bl ? a * T[j] : 0.f;
+                    C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
+                    C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
+                    C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
+                    if constexpr (STATE) last[j] = bl ? krel0 + (uint32_t)q : last[j];
+                    T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
+                }
             }
         }
     }
