@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, nargs=2, default=[16, 16])
-    ap.add_argument("--ppt", type=int, default=2)
+    ap.add_argument("--ppt", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
     ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff"], default=None,

@@ -92,42 +92,62 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
-        for (int q = 0; q < nb; ++q) {
-            const uint32_t krel = start + q - rg.x;
-            if (!wave_ballot(krel < npmax)) break;
-            const BlendRec &b = sm.r[q];
-            const uint32_t m = __builtin_amdgcn_readfirstlane(b.mask);
-            if (!((m >> w) & 1u)) continue;
-            const float2 uv = b.uv;
-            const float4 r1 = b.r1, r2 = b.rgb;
-            const float inv_sigma = 1.f / r2.w;
-            const ExpRow er = exp_row(r1, pxc - uv.x);
-            float ds = 0.f, dr = 0.f, dg = 0.f, db = 0.f;
-            bool any = false;
+        // the batch's records this wave takes (scalar bit sets), walked in order while
+        // some pixel of the wave still replays
+        constexpr int L = NT < 64 ? NT : 64;
+        uint64_t todo[BATCH / 64];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                // the forward's decisions, replayed with its arithmetic: entries up to the
-                // pixel's last blended one, alpha at or above 1/255
-                const float e = exp_at(er, r1, pyc[j] - uv.y);
-                const bool act = krel < np[j] && !(e < kLog2AlphaMin);
-                any = any || act;
-                const float araw = __builtin_amdgcn_exp2f(e);
-                const float a = fminf(kAlphaMax, araw);
-                const float wgt = act ? a * T[j] : 0.f;
-                const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
-                const float ws = wgt * sg;
-                const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
-                dr += wgt * g0[j];
-                dg += wgt * g1[j];
-                db += wgt * g2[j];
-                ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
-                Gr[j] -= ws;
-                T[j] = act ? T[j] * (1.f - a) : T[j];
+        for (int c = 0; c < BATCH / 64; ++c) {
+            todo[c] = 0;
+#pragma unroll
+            for (int sub = 0; sub < 64 / L; ++sub) {
+                const int q = c * 64 + sub * L + (int)lane_id();
+                todo[c] |= wave_ballot(q < nb && ((sm.r[q].mask >> w) & 1u)) << (sub * L);
             }
-            if (wave_ballot(any)) {
-                constexpr int L = NT < 64 ? NT : 64;
-                ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
-                if (lane_id() == 0) s_acc[wv][q] = make_float4(ds, dr, dg, db);
+        }
+        bool quit = false;
+#pragma unroll
+        for (int c = 0; c < BATCH / 64; ++c) {
+            uint64_t mm = todo[c];
+            while (mm && !quit) {
+                const int q = c * 64 + (int)__builtin_ctzll(mm);
+                mm &= mm - 1;
+                const uint32_t krel = start + q - rg.x;
+                if (!wave_ballot(krel < npmax)) {
+                    quit = true;
+                    break;
+                }
+                const BlendRec &b = sm.r[q];
+                const float2 uv = b.uv;
+                const float4 r1 = b.r1, r2 = b.rgb;
+                const float inv_sigma = 1.f / r2.w;
+                const ExpRow er = exp_row(r1, pxc - uv.x);
+                float ds = 0.f, dr = 0.f, dg = 0.f, db = 0.f;
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    // the forward's decisions, replayed with its arithmetic: entries up to
+                    // the pixel's last blended one, alpha at or above 1/255
+                    const float e = exp_at(er, r1, pyc[j] - uv.y);
+                    const bool act = krel < np[j] && !(e < kLog2AlphaMin);
+                    any = any || act;
+                    const float araw = __builtin_amdgcn_exp2f(e);
+                    const float a = fminf(kAlphaMax, araw);
+                    const float wgt = act ? a * T[j] : 0.f;
+                    const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
+                    const float ws = wgt * sg;
+                    const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
+                    dr += wgt * g0[j];
+                    dg += wgt * g1[j];
+                    db += wgt * g2[j];
+                    ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
+                    Gr[j] -= ws;
+                    T[j] = act ? T[j] * (1.f - a) : T[j];
+                }
+                if (wave_ballot(any)) {
+                    ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
+                    if (lane_id() == 0) s_acc[wv][q] = make_float4(ds, dr, dg, db);
+                }
             }
         }
         __syncthreads();
