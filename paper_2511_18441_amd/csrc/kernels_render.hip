@@ -52,15 +52,17 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
     __shared__ uint64_t s_k[4];
     __shared__ uint32_t s_v[4], s_zmn[4], s_zmx[4];
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    // striped (coalesced): only sums, minima and maxima are taken here
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
     uint64_t tsum = 0;
     uint32_t vsum = 0, zmn = 0xffffffffu, zmx = 0u;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t v = (base + k < n) ? cnt[base + k] : 0u;
+        const int64_t i = base + (int64_t)k * 256;
+        const uint32_t v = (i < n) ? cnt[i] : 0u;
         tsum += v;
         if (v) {
-            const uint32_t z = zbits[base + k];
+            const uint32_t z = zbits[i];
             zmn = min(zmn, z);
             zmx = max(zmx, z);
             ++vsum;
@@ -122,35 +124,70 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, ui
     }
 }
 
+// Down-sweep over one chunk of 4,096 counts. Loads and stores are coalesced through
+// LDS: counts and depth bits come in striped, each thread scans 16 consecutive ones,
+// and the offsets and the compacted (depth bits, index) pairs go out striped.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }   // LDS padding: no 16-way bank conflicts
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                                    uint32_t *__restrict__ off, int64_t n, const uint64_t *__restrict__ pk,
                                                    const uint32_t *__restrict__ pv, uint32_t *__restrict__ dkeys,
                                                    uint32_t *__restrict__ dvals) {
     __shared__ uint64_t s_wk[4];
     __shared__ uint32_t s_wv[4];
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    __shared__ uint32_t s_a[kScanChunk + kScanChunk / 32];
+    __shared__ uint32_t s_dk[kScanChunk], s_dv[kScanChunk];
+    const int t = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int i = k * 256 + t;
+        s_a[scan_pad(i)] = (c0 + i < n) ? cnt[c0 + i] : 0u;
+    }
+    __syncthreads();
     uint32_t v[kScanItems];
     uint64_t tsum = 0;
     uint32_t vsum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? cnt[base + k] : 0u;
+        v[k] = s_a[scan_pad(t * kScanItems + k)];
         tsum += v[k];
         vsum += v[k] ? 1u : 0u;
     }
     uint64_t ktot;
     uint32_t vtot;
     uint64_t run = pk[blockIdx.x] + block_excl_scan<uint64_t, 4>(tsum, s_wk, ktot);
-    uint32_t vrun = pv[blockIdx.x] + block_excl_scan<uint32_t, 4>(vsum, s_wv, vtot);
+    uint32_t vloc = block_excl_scan<uint32_t, 4>(vsum, s_wv, vtot);   // (the scans end with a barrier)
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) off[base + k] = (uint32_t)run;
-        run += v[k];
+        const int i = k * 256 + t;
+        s_a[scan_pad(i)] = (c0 + i < n) ? zbits[c0 + i] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
         if (v[k]) {
-            dkeys[vrun] = zbits[base + k];
-            dvals[vrun] = (uint32_t)(base + k);
-            ++vrun;
+            const int i = t * kScanItems + k;
+            s_dk[vloc] = s_a[scan_pad(i)];
+            s_dv[vloc] = (uint32_t)(c0 + i);
+            ++vloc;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        s_a[scan_pad(t * kScanItems + k)] = (uint32_t)run;
+        run += v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int i = k * 256 + t;
+        if (c0 + i < n) off[c0 + i] = s_a[scan_pad(i)];
+    }
+    const uint32_t vbase = pv[blockIdx.x];
+    for (uint32_t j = t; j < vtot; j += 256) {
+        dkeys[vbase + j] = s_dk[j];
+        dvals[vbase + j] = s_dv[j];
     }
 }
 
@@ -400,13 +437,35 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
 }
 
 // [first, last+1) of each tile in tile-sorted 32-bit tile ids (ranges zeroed beforehand).
+// A thread takes 4 consecutive keys with one 16-byte load (the last group of a ragged
+// K key by key) and compares each with its neighbour.
 __global__ __launch_bounds__(256) void k_ranges32(const uint32_t *__restrict__ tiles, uint32_t K, uint2 *__restrict__ ranges,
                                                   const uint32_t *dynK) {
     if (dynK) K = *dynK;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-        const uint32_t t = tiles[k];
-        if (k == 0 || tiles[k - 1] != t) ranges[t].x = k;
-        if (k == K - 1 || tiles[k + 1] != t) ranges[t].y = k + 1;
+    const uint32_t groups = (K + 3) / 4;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const uint32_t k0 = 4 * g;
+        uint32_t v[4];
+        if (k0 + 3 < K) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(tiles + k0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = k0 + j < K ? tiles[k0 + j] : 0xffffffffu;
+        }
+        uint32_t prev = k0 > 0 ? tiles[k0 - 1] : 0xffffffffu;
+        const uint32_t next = k0 + 4 < K ? tiles[k0 + 4] : 0xffffffffu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t k = k0 + j;
+            if (k < K) {
+                const uint32_t t = v[j];
+                const uint32_t after = j < 3 ? v[j + 1] : next;
+                if (prev != t) ranges[t].x = k;
+                if (k == K - 1 || after != t) ranges[t].y = k + 1;
+                prev = t;
+            }
+        }
     }
 }
 
@@ -500,7 +559,7 @@ uint32_t emit_blocks(uint32_t K) { return (K + kEmitKeys - 1) / kEmitKeys; }
 
 void launch_ranges32(const uint32_t *tiles, uint32_t K, uint2 *ranges, hipStream_t st, const uint32_t *dynK) {
     if (K == 0) return;
-    uint32_t blocks = (K + 255) / 256;
+    uint32_t blocks = ((K + 3) / 4 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_ranges32, dim3(blocks), dim3(256), 0, st, tiles, K, ranges, dynK);
 }
