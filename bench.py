@@ -36,7 +36,7 @@ METRIC = "recolor+render frames/s (1M Gaussians, 1080p) and HBM-roofline fractio
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz, packed FMA)
 BLEND_FLOPS_PER_EVAL = 23        # dx, dy, exponent (2 mul + 3 fma), test, exp2, clamp, T, weight, 3 fma
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_16x16_ppt2_1M_1080p_f32.traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
 
@@ -53,11 +53,12 @@ def blend_source_sha1():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, tile, ppt):
     """HBM bytes per launch of `kernel` from the committed rocprof counter summary, or
     None when there is none or the blend sources changed since it was taken."""
+    path = TRAFFIC_FILE.format(tw=tile[0], th=tile[1], ppt=ppt)
     try:
-        kv = dict(l.split(":", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ":" in l and not l.startswith("#"))
+        kv = dict(l.split(":", 1) for l in open(path).read().splitlines() if ":" in l and not l.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
@@ -460,7 +461,7 @@ def main():
         avg = m["blend_ms_timed"]  # measured over the timed frames themselves
         kname = f"k_blend<{tw},{th},{args.ppt}>"
         ach = flops["blend"] / (avg * 1e-3) / 1e12
-        traffic = recorded_traffic(kname) if args.storage == "f32" else None
+        traffic = recorded_traffic(kname, tile, args.ppt) if args.storage == "f32" else None
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": round(avg, 4), "launches_timed": m["profiled_frames"],
