@@ -211,7 +211,7 @@ struct StageTimer {
         if (hipEventSynchronize(ev[last]) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventSynchronize failed");
         for (int k = 0; k < 8; ++k) {
             float ms = 0.f;
-            if (k < last) hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            if (k < last && hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) ms = 0.f;
             ws->stage_ms[k] = ms;
         }
         return RECOGS_OK;
@@ -423,7 +423,7 @@ void recogs_workspace_release(recogs_workspace *ws) {
     ProfileState *ps = (ProfileState *)ws->profile_state;
     for (auto &st : ps->set)
         for (auto &e : st.ev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     free(ps);
     ws->profile_state = nullptr;
 }
