@@ -73,6 +73,7 @@ def lib():
         L.orc_emit_keys.restype = i64
         L.orc_render_windows.argtypes = [i64, vp, vp, i32, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp]
         L.orc_backward.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_backward_windows.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.orc_ncols.argtypes = [i32]
         L.orc_ncols.restype = i32
         assert L.orc_ncols(0) == len(PCOLS) and L.orc_ncols(1) == len(ICOLS)
@@ -292,8 +293,10 @@ class Grads:
     dM: np.ndarray       # (3, 3)
 
 
-def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0)) -> Grads:
-    """Gradients of eq. (8) restricted to opacity, SH DC and the recolour matrix."""
+def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0), windows=None) -> Grads:
+    """Gradients of eq. (8) restricted to opacity, SH DC and the recolour matrix.
+    With `windows` [(x0, y0, w, h), ...] dL/dy must be zero outside them and only
+    their pixels are visited (candidates gathered per window, as for rendering)."""
     n = proj.f.shape[0]
     g = _d(dldy).reshape(proj.height, proj.width, 3)
     Mv = _d(np.eye(3) if M is None else M).reshape(9)
@@ -301,6 +304,16 @@ def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0)) -> Grads:
     dr = np.empty((n, 3))
     dc = np.empty((3, n))
     dM = np.empty(9)
-    lib().orc_backward(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), _p(Mv), _p(g),
-                       _p(ds), _p(dr), _p(dc), _p(dM))
+    if windows is None:
+        lib().orc_backward(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), _p(Mv), _p(g),
+                           _p(ds), _p(dr), _p(dc), _p(dM))
+    else:
+        win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 4))
+        inside = np.zeros((proj.height, proj.width), bool)
+        for (x0, y0, w, h) in win:
+            inside[y0:y0 + h, x0:x0 + w] = True
+        if np.any(g[~inside] != 0):
+            raise ValueError("dL/dy is nonzero outside the windows")
+        lib().orc_backward_windows(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), _p(Mv), _p(g),
+                                   len(win), win.ctypes.data_as(ctypes.c_void_p), _p(ds), _p(dr), _p(dc), _p(dM))
     return Grads(ds, dr, dc, dM.reshape(3, 3))

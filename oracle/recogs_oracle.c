@@ -639,74 +639,74 @@ void orc_render_windows(int64_t n, const double *proj, const int64_t *iproj, int
  *   unselected: dL/dC0 = Y00 gh
  * Skipped and terminated splats receive nothing. Single-threaded.
  * ------------------------------------------------------------------------- */
-void orc_backward(int64_t n, const double *proj, const int64_t *iproj, int32_t W, int32_t H,
-                  const double *bg, const double *M, const double *dldy /* [H][W][3] */,
-                  double *dsigma /* [n] */, double *drgb /* [n][3] */, double *dc0 /* [3][n] */,
-                  double *dM /* [9] */)
+
+/* One pixel's terms, over the candidate Gaussians list[0..nl) (a superset of the
+ * Gaussians with alpha >= 1/255 at the pixel), accumulated into dsigma and drgb. */
+static void backward_pixel(int64_t nl, const int64_t *list, const double *proj, double pxc, double pyc,
+                           const double *bg, const double *g, cand_t *buf, double *Tl, double *dsigma, double *drgb)
 {
-    const double y00 = 1.0 / (2.0 * sqrt(M_PI));
+    int64_t nc = 0;
+    for (int64_t j = 0; j < nl; ++j) {
+        const int64_t i = list[j];
+        const double *p = proj + i * P_NCOL;
+        const double dx = pxc - p[P_U], dy = pyc - p[P_V];
+        const double qv = p[P_CA] * dx * dx + 2.0 * p[P_CB] * dx * dy + p[P_CC] * dy * dy;
+        const double a = p[P_SIGMA] * exp(-0.5 * qv);
+        if (a >= ALPHA_MIN) {
+            buf[nc].z32 = p[P_Z32];
+            buf[nc].idx = i;
+            buf[nc].alpha = a;
+            ++nc;
+        }
+    }
+    qsort(buf, (size_t)nc, sizeof(cand_t), cand_cmp);
+    /* forward: which are blended, and their T */
+    double T = 1.0, y[3] = {0, 0, 0};
+    int64_t nbl = 0;
+    for (int64_t k = 0; k < nc; ++k) {
+        const double a = buf[k].alpha < ALPHA_MAX ? buf[k].alpha : ALPHA_MAX;
+        const double Tn = T * (1.0 - a);
+        if (Tn < T_MIN) break;
+        const double *p = proj + buf[k].idx * P_NCOL;
+        for (int c = 0; c < 3; ++c) y[c] += p[P_R + c] * a * T;
+        Tl[k] = T;
+        T = Tn;
+        ++nbl;
+    }
+    for (int c = 0; c < 3; ++c) y[c] += T * bg[c];
+    double Acc[3] = {0, 0, 0};
+    for (int64_t k = 0; k < nbl; ++k) {
+        const int64_t i = buf[k].idx;
+        const double *p = proj + i * P_NCOL;
+        const double araw = buf[k].alpha;
+        const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
+        const double Ti = Tl[k];
+        double dalpha = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double contrib = p[P_R + c] * a * Ti;
+            const double R = y[c] - Acc[c] - contrib;
+            drgb[i * 3 + c] += a * Ti * g[c];
+            dalpha += g[c] * (p[P_R + c] * Ti - R / (1.0 - a));
+            Acc[c] += contrib;
+        }
+        if (araw < ALPHA_MAX) dsigma[i] += dalpha * (araw / p[P_SIGMA]);
+    }
+}
+
+static void backward_zero(int64_t n, double *dsigma, double *drgb, double *dc0, double *dM)
+{
     for (int64_t i = 0; i < n; ++i) {
         dsigma[i] = 0;
         for (int c = 0; c < 3; ++c) drgb[i * 3 + c] = 0, dc0[c * n + i] = 0;
     }
     for (int k = 0; k < 9; ++k) dM[k] = 0;
-    int64_t nl = 0;
-    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    for (int64_t i = 0; i < n; ++i)
-        if (visible_for_pixels(iproj + i * I_NCOL, proj + i * P_NCOL)) list[nl++] = i;
-    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
-    double *Tl = (double *)malloc(sizeof(double) * (size_t)(nl > 0 ? nl : 1));
-    for (int32_t py = 0; py < H; ++py)
-        for (int32_t px = 0; px < W; ++px) {
-            const double pxc = px + 0.5, pyc = py + 0.5;
-            const double *g = dldy + ((int64_t)py * W + px) * 3;
-            int64_t nc = 0;
-            for (int64_t j = 0; j < nl; ++j) {
-                const int64_t i = list[j];
-                const double *p = proj + i * P_NCOL;
-                const double dx = pxc - p[P_U], dy = pyc - p[P_V];
-                const double qv = p[P_CA] * dx * dx + 2.0 * p[P_CB] * dx * dy + p[P_CC] * dy * dy;
-                const double a = p[P_SIGMA] * exp(-0.5 * qv);
-                if (a >= ALPHA_MIN) {
-                    buf[nc].z32 = p[P_Z32];
-                    buf[nc].idx = i;
-                    buf[nc].alpha = a;
-                    ++nc;
-                }
-            }
-            qsort(buf, (size_t)nc, sizeof(cand_t), cand_cmp);
-            /* forward: which are blended, and their T */
-            double T = 1.0, y[3] = {0, 0, 0};
-            int64_t nbl = 0;
-            for (int64_t k = 0; k < nc; ++k) {
-                const double a = buf[k].alpha < ALPHA_MAX ? buf[k].alpha : ALPHA_MAX;
-                const double Tn = T * (1.0 - a);
-                if (Tn < T_MIN) break;
-                const double *p = proj + buf[k].idx * P_NCOL;
-                for (int c = 0; c < 3; ++c) y[c] += p[P_R + c] * a * T;
-                Tl[k] = T;
-                T = Tn;
-                ++nbl;
-            }
-            for (int c = 0; c < 3; ++c) y[c] += T * bg[c];
-            double Acc[3] = {0, 0, 0};
-            for (int64_t k = 0; k < nbl; ++k) {
-                const int64_t i = buf[k].idx;
-                const double *p = proj + i * P_NCOL;
-                const double araw = buf[k].alpha;
-                const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
-                const double Ti = Tl[k];
-                double dalpha = 0;
-                for (int c = 0; c < 3; ++c) {
-                    const double contrib = p[P_R + c] * a * Ti;
-                    const double R = y[c] - Acc[c] - contrib;
-                    drgb[i * 3 + c] += a * Ti * g[c];
-                    dalpha += g[c] * (p[P_R + c] * Ti - R / (1.0 - a));
-                    Acc[c] += contrib;
-                }
-                if (araw < ALPHA_MAX) dsigma[i] += dalpha * (araw / p[P_SIGMA]);
-            }
-        }
+}
+
+/* the per-Gaussian chain through the clamp, the fused recolour and the DC term */
+static void backward_chain(int64_t n, const double *proj, const int64_t *iproj, const double *M, const double *drgb,
+                           double *dc0, double *dM)
+{
+    const double y00 = 1.0 / (2.0 * sqrt(M_PI));
     for (int64_t i = 0; i < n; ++i) {
         const double *p = proj + i * P_NCOL;
         const int64_t *q = iproj + i * I_NCOL;
@@ -722,8 +722,69 @@ void orc_backward(int64_t n, const double *proj, const int64_t *iproj, int32_t W
             for (int c = 0; c < 3; ++c) dc0[c * n + i] = y00 * gh[c];
         }
     }
+}
+
+/* Whole image, every visible Gaussian tried at every pixel. */
+void orc_backward(int64_t n, const double *proj, const int64_t *iproj, int32_t W, int32_t H,
+                  const double *bg, const double *M, const double *dldy /* [H][W][3] */,
+                  double *dsigma /* [n] */, double *drgb /* [n][3] */, double *dc0 /* [3][n] */,
+                  double *dM /* [9] */)
+{
+    backward_zero(n, dsigma, drgb, dc0, dM);
+    int64_t nl = 0;
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i)
+        if (visible_for_pixels(iproj + i * I_NCOL, proj + i * P_NCOL)) list[nl++] = i;
+    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
+    double *Tl = (double *)malloc(sizeof(double) * (size_t)(nl > 0 ? nl : 1));
+    for (int32_t py = 0; py < H; ++py)
+        for (int32_t px = 0; px < W; ++px)
+            backward_pixel(nl, list, proj, px + 0.5, py + 0.5, bg, dldy + ((int64_t)py * W + px) * 3, buf, Tl, dsigma,
+                           drgb);
+    backward_chain(n, proj, iproj, M, drgb, dc0, dM);
     free(Tl);
     free(buf);
+    free(list);
+}
+
+/* The same where dL/dy is zero outside the given windows (x0, y0, w, h): only their
+ * pixels are visited, each with the Gaussians whose alpha >= 1/255 box (as in
+ * orc_render_windows) meets the window as candidates. Windows in order, pixels
+ * row-major inside each. */
+void orc_backward_windows(int64_t n, const double *proj, const int64_t *iproj, int32_t W, int32_t H,
+                          const double *bg, const double *M, const double *dldy /* [H][W][3] */,
+                          int64_t nwin, const int32_t *win /* [nwin][4] */,
+                          double *dsigma, double *drgb, double *dc0, double *dM)
+{
+    (void)H;
+    backward_zero(n, dsigma, drgb, dc0, dM);
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t w = 0; w < nwin; ++w) {
+        const int32_t x0 = win[w * 4 + 0], y0 = win[w * 4 + 1], ww = win[w * 4 + 2], wh = win[w * 4 + 3];
+        int64_t nl = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t *q = iproj + i * I_NCOL;
+            const double *p = proj + i * P_NCOL;
+            if (!visible_for_pixels(q, p)) continue;
+            const double lev = box_level(p);
+            if (!(lev > 0)) continue;
+            const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
+            if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) continue;
+            if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) continue;
+            list[nl++] = i;
+        }
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
+        double *Tl = (double *)malloc(sizeof(double) * (size_t)(nl > 0 ? nl : 1));
+        for (int32_t yy = 0; yy < wh; ++yy)
+            for (int32_t xx = 0; xx < ww; ++xx) {
+                const int64_t px = x0 + xx, py = y0 + yy;
+                backward_pixel(nl, list, proj, px + 0.5, py + 0.5, bg, dldy + (py * W + px) * 3, buf, Tl, dsigma,
+                               drgb);
+            }
+        free(Tl);
+        free(buf);
+    }
+    backward_chain(n, proj, iproj, M, drgb, dc0, dM);
     free(list);
 }
 

@@ -197,3 +197,41 @@ def test_backward_without_recolor_and_zero_gradient(R, orc):
         else:
             gr = orc.backward(pr, g)
             _close(ddc.cpu().numpy().astype(np.float64), gr.dc0, 2e-3, "dC0 without recolour")
+
+
+def test_backward_full_size_on_windows_vs_oracle(R, orc):
+    """The differentiation workload at full size (1,000,000 Gaussians, 1280x720, view
+    0, the fused recolour M0 on the selection): the upstream gradient is nonzero on
+    four 32x32 windows only, so the oracle's backward visits just those pixels."""
+    import torch
+    w = synth.make_diff()
+    v = w.view
+    cam = v.camera
+    sc = w.scene
+    mask, _ = orc.select(sc, cam, v.select)
+    M = v.recolor.M.astype(np.float64)
+    b = v.recolor.b.astype(np.float64)
+    pr = orc.project(sc, cam, (16, 16), mask=mask, M=M, b=b)
+    wins = [(320, 192, 32, 32), (640, 352, 32, 32), (96, 608, 32, 32), (1152, 64, 32, 32)]
+    ref = orc.render_windows(pr, wins)
+    rng = np.random.default_rng(33)
+    g = np.zeros((cam.height, cam.width, 3), np.float32)
+    o = 0
+    for (x0, y0, ww, wh) in wins:
+        slack = ref.slack[o:o + ww * wh].reshape(wh, ww)
+        blk = rng.standard_normal((wh, ww, 3)).astype(np.float32)
+        blk[slack > 0] = 0.0   # in-band threshold decisions get no upstream gradient
+        g[y0:y0 + wh, x0:x0 + ww] = blk
+        o += ww * wh
+    gr = orc.backward(pr, g.astype(np.float64), M=M, windows=wins)
+    d = R.DeviceScene(sc)
+    ws = R.DeviceWorkspace(sc.n, cam.width, cam.height, (16, 16))
+    tm = torch.from_numpy(mask).cuda()
+    tM = torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda()
+    tb = torch.from_numpy(v.recolor.b.copy()).cuda()
+    img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (16, 16), 1)
+    e1 = _close(dop, gr.dsigma, 2e-3, "dL/dopacity")
+    e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
+    e3 = _close(dM, gr.dM, 2e-3, "dL/dM")
+    assert np.abs(gr.dsigma).max() > 0 and np.abs(gr.dM).max() > 0
+    print(f"full size: relative max errors dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")

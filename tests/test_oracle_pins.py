@@ -417,6 +417,28 @@ def _loss_and_state(orc, sc, cam, mask, M, b, g):
     return float((r.rgb * g).sum()), r, pr
 
 
+def test_windowed_backward_equals_whole_image(orc):
+    """With dL/dy zero outside some windows, visiting only their pixels with the
+    per-window candidate lists gives the whole-image backward (pixel order aside)."""
+    w = synth.make_diff_fd(n=20000, n_sub=600, size=48)
+    sc, cam = w.scene, w.view.camera
+    rng = np.random.default_rng(21)
+    mask = (rng.random(sc.n) < 0.4).astype(np.uint8)
+    M = (np.eye(3) + 0.2 * rng.standard_normal((3, 3))).astype(np.float64)
+    pr = orc.project(sc, cam, (16, 16), mask=mask, M=M, b=np.zeros(3))
+    wins = [(0, 0, 16, 16), (16, 32, 16, 16), (30, 5, 12, 9)]
+    g = np.zeros((cam.height, cam.width, 3))
+    for (x0, y0, ww, wh) in wins:
+        g[y0:y0 + wh, x0:x0 + ww] = rng.standard_normal((wh, ww, 3))
+    full = orc.backward(pr, g, M=M)
+    part = orc.backward(pr, g, M=M, windows=wins)
+    for a, b in ((full.dsigma, part.dsigma), (full.dc0, part.dc0), (full.dM, part.dM)):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * max(1.0, np.abs(a).max()))
+    assert np.abs(full.dsigma).max() > 0 and np.abs(full.dM).max() > 0
+    with pytest.raises(ValueError):
+        orc.backward(pr, np.ones_like(g), M=M, windows=wins)
+
+
 def test_gradients_match_central_differences(orc):
     w = synth.make_diff_fd(n=20000, n_sub=96, size=24)
     sc, cam = w.scene, w.view.camera
