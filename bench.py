@@ -178,26 +178,32 @@ class Single:
                 "profiled_frames": nfr, "select_ms": sel_ms}
 
     def counts(self):
-        """Counts of the frame, from one more render that also writes the per-pixel state
-        (the same tile lists and arithmetic; that blend variant also stores each pixel's
-        list count, from which the evaluations are summed)."""
+        """Counts of the frame. K, V and the sort passes are those of the timed launch
+        shape. The blend's nominal work (`evals`) is fixed independently of that shape:
+        per pixel, the entries of its 16x16-tile list (the reference rasteriser's tiling)
+        up to and including its last blended splat, summed over pixels; one more render
+        at 16x16 tiles that also writes the per-pixel state gives it. `keff` is the
+        per-tile maximum of that count, summed over 16x16 tiles."""
         import torch
-        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
-                      keep_backward=True)
+        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh)
         ws = self.ws
         K = int(ws.ws.num_keys)
         cnt = ws.counts(self.n)
         V = int((cnt != 0).sum().item())
         S = int(self.count.item())
         T = ws.ws.tiles_x * ws.ws.tiles_y
-        nproc = ws.nproc().to(torch.int64)
+        passes, dpasses = int(ws.ws.sort_passes), int(ws.ws.depth_passes)
+        ref = self.R.DeviceWorkspace(self.n, self.cam.width, self.cam.height, (16, 16), key_capacity=16 * self.n,
+                                     device=self.image.device)
+        self.R.render(self.d, self.cam, ref, (16, 16), 1, image=self.image, sh=self.render_sh, keep_backward=True)
+        nproc = ref.nproc().to(torch.int64)
         E = int(nproc.sum().item())
-        tw, th = self.tile
-        Hp, Wp = ws.ws.tiles_y * th, ws.ws.tiles_x * tw
+        Hp, Wp = ref.ws.tiles_y * 16, ref.ws.tiles_x * 16
         npad = torch.zeros((Hp, Wp), dtype=torch.int64, device=nproc.device)
         npad[:self.cam.height, :self.cam.width] = nproc
-        keff = int(npad.view(ws.ws.tiles_y, th, ws.ws.tiles_x, tw).amax(dim=(1, 3)).sum().item())
-        return dict(N=self.n, V=V, K=K, S=S, passes=int(ws.ws.sort_passes), dpasses=int(ws.ws.depth_passes), tiles=T,
+        keff = int(npad.view(ref.ws.tiles_y, 16, ref.ws.tiles_x, 16).amax(dim=(1, 3)).sum().item())
+        del ref
+        return dict(N=self.n, V=V, K=K, S=S, passes=passes, dpasses=dpasses, tiles=T,
                     pix=self.cam.width * self.cam.height, evals=E, keff=keff)
 
 
@@ -306,7 +312,10 @@ def form_batch(R, steps, warmup, dev):
                               "frames_per_s": round(nv * 1000.0 / ms_single, 1)}}
 
 
-def form_diff(R, steps, warmup, dev):
+DIFF_TILE, DIFF_PPT = (32, 16), 1
+
+
+def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     """1M Gaussians (FP32, SH 3), 8 views at 1280x720: render with the fused recolour
     (keeping the backward state), L2 loss against a seeded target, backward to the
     opacities, the SH DC coefficients and M."""
@@ -326,10 +335,10 @@ def form_diff(R, steps, warmup, dev):
     Mt = torch.from_numpy(w.extra["M_target"].reshape(9).copy()).to(dev)
     b = torch.zeros(3, dtype=torch.float32, device=dev)
     W, H = v0.camera.width, v0.camera.height
-    ws = [R.DeviceWorkspace(n, W, H, (16, 16), device=dev) for _ in w.views]
+    ws = [R.DeviceWorkspace(n, W, H, tile, device=dev) for _ in w.views]
     targets = []
     for k, v in enumerate(w.views):
-        t = R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=Mt, b=b).clone()
+        t = R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=Mt, b=b).clone()
         t += torch.from_numpy(synth.random_image(w.extra["noise_seed"] + k, (H, W, 3), w.extra["noise_sd"])).to(dev)
         targets.append(t)
     imgs = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in w.views]
@@ -340,12 +349,12 @@ def form_diff(R, steps, warmup, dev):
     dM = torch.empty(9, dtype=torch.float32, device=dev)
     scale = 1.0 / (len(w.views) * H * W * 3)
     cams = [R.camera_struct(v.camera) for v in w.views]
-    o = R.opts_struct((16, 16), 2, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True)
+    o = R.opts_struct(tile, ppt, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True)
 
     def step():
         loss.zero_()
         for k, v in enumerate(w.views):
-            R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
             R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
                              loss.data_ptr())
             R.recogs_render_backward(sc, cams[k], o, ws[k].ws, imgs[k].data_ptr(), dimg.data_ptr(), dop.data_ptr(),
@@ -364,10 +373,10 @@ def form_diff(R, steps, warmup, dev):
     t0 = time.perf_counter()
     for _ in range(reps):
         for k, v in enumerate(w.views):
-            R.render(d, v.camera, ws[k], (16, 16), 2, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / reps
-    return {"views": len(w.views), "width": W, "height": H, "gaussians": n,
+    return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
             "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
             "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.item()),
             "grad_M_norm": float(dM.norm().item())}
@@ -411,8 +420,11 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--tile", type=int, nargs=2, default=[16, 16])
-    ap.add_argument("--ppt", type=int, default=1)
+    ap.add_argument("--tile", type=int, nargs=2, default=[32, 32])
+    ap.add_argument("--ppt", type=int, default=2)
+    ap.add_argument("--diff-tile", type=int, nargs=2, default=None,
+                    help="tile shape of the differentiation form when run alone (--only-form diff)")
+    ap.add_argument("--diff-ppt", type=int, default=DIFF_PPT)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
     ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff"], default=None,
@@ -438,7 +450,8 @@ def main():
         if args.only_form == "batch":
             res = form_batch(R, args.steps, args.warmup, dev)
         elif args.only_form == "diff":
-            res = form_diff(R, args.steps, args.warmup, dev)
+            res = form_diff(R, args.steps, args.warmup, dev,
+                            DIFF_TILE if args.diff_tile is None else tuple(args.diff_tile), args.diff_ppt)
         else:
             res = form_single(R, args.only_form, tile, args.ppt, args.steps, args.warmup, dev)
         print(json.dumps({"form": args.only_form, **res}), flush=True)
@@ -459,13 +472,15 @@ def main():
     avg = m["stages"][dom] / nl
     if dom == "blend":
         avg = m["blend_ms_timed"]  # measured over the timed frames themselves
-        kname = f"k_blend<{tw},{th},{args.ppt}>"
+        region = tw % 8 == 0 and th % (8 * args.ppt) == 0
+        kname = f"k_blend_region<{tw},{th},{args.ppt}>" if region else f"k_blend<{tw},{th},{args.ppt}>"
         ach = flops["blend"] / (avg * 1e-3) / 1e12
         traffic = recorded_traffic(kname, tile, args.ppt) if args.storage == "f32" else None
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": round(avg, 4), "launches_timed": m["profiled_frames"],
-                "work_per_launch": f"{st['evals']} pixel-splat evaluations x {BLEND_FLOPS_PER_EVAL} flops",
+                "work_per_launch": f"{st['evals']} pixel-splat evaluations (16x16-tile lists) x "
+                                   f"{BLEND_FLOPS_PER_EVAL} flops",
                 "alg_bytes_per_launch": int(bytes_["blend"]),
                 "hbm_GBps_alg": round(bytes_["blend"] / (avg * 1e-3) / 1e9, 1)}
     else:

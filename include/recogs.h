@@ -83,8 +83,11 @@ typedef struct {
 
 /* Render options (host struct). */
 typedef struct {
-    int32_t tile_w, tile_h;      /* 8x8, 16x16 or 32x8 */
-    int32_t px_per_thread;       /* 1, 2 or 4 pixels per blend thread */
+    int32_t tile_w, tile_h;      /* sort tile: 8x8, 16x16, 32x8, 32x16 or 32x32 */
+    int32_t px_per_thread;       /* 1, 2 or 4 pixels per blend thread. Where tile_h is a multiple
+                                    of 8 * px_per_thread the blend runs one wave per 8 x
+                                    8*px_per_thread block of a tile; otherwise one workgroup
+                                    per tile. Outputs are bit-identical for every shape. */
     float bg[3];                 /* background colour */
     /* Optional fused recolour (all three NULL = off): selected Gaussians display
      * max(0, M (f + 1/2) + b) instead of max(0, f + 1/2). Device pointers:

@@ -1,5 +1,5 @@
-"""Autotuner of the blend launch shape: tile (8x8, 16x16, 32x8) x pixels per thread
-(1, 2, 4).
+"""Autotuner of the tile shape (the sort tile, which also fixes the blend's launch) and
+the pixels per blend thread.
 
 For a workload it times every candidate (HIP-graph replays of the batch, or eager
 renders of one view), checks that every candidate's images are bit-identical to the
@@ -15,8 +15,11 @@ import os
 import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
-CANDIDATES: Tuple[Tuple[Tuple[int, int], int], ...] = tuple(
-    ((tw, th), p) for (tw, th) in ((16, 16), (32, 8), (8, 8)) for p in (1, 2, 4))
+# larger tiles mean fewer (splat, tile) keys to sort; the blend's cost per pixel is
+# about the same for every shape that runs in region form
+CANDIDATES: Tuple[Tuple[Tuple[int, int], int], ...] = (
+    ((32, 32), 1), ((32, 32), 2), ((32, 32), 4), ((32, 16), 1), ((32, 16), 2),
+    ((16, 16), 1), ((16, 16), 2), ((32, 8), 1), ((32, 8), 2), ((8, 8), 1))
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "recogs_autotune.json")
 

@@ -275,6 +275,8 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
     RECOGS_BWD_CASE(16, 16, 1) RECOGS_BWD_CASE(16, 16, 2) RECOGS_BWD_CASE(16, 16, 4)
     RECOGS_BWD_CASE(8, 8, 1) RECOGS_BWD_CASE(8, 8, 2) RECOGS_BWD_CASE(8, 8, 4)
     RECOGS_BWD_CASE(32, 8, 1) RECOGS_BWD_CASE(32, 8, 2) RECOGS_BWD_CASE(32, 8, 4)
+    RECOGS_BWD_CASE(32, 16, 1) RECOGS_BWD_CASE(32, 16, 2) RECOGS_BWD_CASE(32, 16, 4)
+    RECOGS_BWD_CASE(32, 32, 1) RECOGS_BWD_CASE(32, 32, 2) RECOGS_BWD_CASE(32, 32, 4)
 #undef RECOGS_BWD_CASE
     return false;
 }

@@ -116,6 +116,28 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_persistent(const ViewDev
     }
 }
 
+// Region form for the batch: one wave per 8 x 8*PPT region of every tile of every
+// view, tiles taken in queue order (longest lists first). Workgroup b runs on XCD
+// b mod 8; a tile's regions take consecutive workgroups of one XCD and the tiles are
+// dealt to the XCDs in turn.
+template <int TW, int TH, int PPT>
+__global__ __launch_bounds__(64) void k_blend_region_batch(const ViewDev *__restrict__ views, int nviews,
+                                                          const uint2 *__restrict__ ranges,
+                                                          const uint32_t *__restrict__ vals,
+                                                          const SplatRec *__restrict__ rec,
+                                                          const uint32_t *__restrict__ order, uint32_t ntiles) {
+    constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
+    __shared__ BlendRec sm[64];
+    const uint32_t b = blockIdx.x, j = b >> 3;
+    const uint32_t item = (j / NR) * 8u + (b & 7u);
+    if (item >= ntiles) return;
+    const uint32_t gt = order[item];
+    const int v = view_of_tile(views, nviews, gt);
+    const ViewDev &vw = views[v];
+    blend_region<TW, TH, PPT, false>((int)(gt - vw.tile_base), (int)(j % NR), ranges[gt], vals, rec, vw.cam.W, vw.cam.H,
+                                     vw.cam.tiles_x, vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr, nullptr, sm);
+}
+
 // ---------------------------------------------------------------------------
 template <int DT>
 static void preprocess_batch_dt(int deg, uint32_t blocks, hipStream_t st, const ViewDev *views, int nviews, SplatRec *rec,
@@ -150,8 +172,15 @@ template <int TW, int TH, int PPT>
 static void persistent_one(uint32_t grid, hipStream_t st, const ViewDev *views, int nviews, const uint2 *ranges,
                            const uint32_t *vals, const SplatRec *rec, const uint32_t *order, uint32_t ntiles,
                            uint32_t *queue) {
-    hipLaunchKernelGGL((k_blend_persistent<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st, views, nviews, ranges, vals,
-                       rec, order, ntiles, queue);
+    if constexpr (region_shape(TW, TH, PPT)) {
+        constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
+        const dim3 g((unsigned)((ntiles + 7u) / 8u * 8u * NR));
+        hipLaunchKernelGGL((k_blend_region_batch<TW, TH, PPT>), g, dim3(64), 0, st, views, nviews, ranges, vals, rec, order,
+                           ntiles);
+    } else {
+        hipLaunchKernelGGL((k_blend_persistent<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st, views, nviews, ranges,
+                           vals, rec, order, ntiles, queue);
+    }
 }
 
 bool launch_blend_persistent(int tw, int th, int ppt, uint32_t grid, const ViewDev *views, int nviews, const uint2 *ranges,
@@ -165,6 +194,8 @@ bool launch_blend_persistent(int tw, int th, int ppt, uint32_t grid, const ViewD
     RECOGS_PERS_CASE(16, 16, 1) RECOGS_PERS_CASE(16, 16, 2) RECOGS_PERS_CASE(16, 16, 4)
     RECOGS_PERS_CASE(8, 8, 1) RECOGS_PERS_CASE(8, 8, 2) RECOGS_PERS_CASE(8, 8, 4)
     RECOGS_PERS_CASE(32, 8, 1) RECOGS_PERS_CASE(32, 8, 2) RECOGS_PERS_CASE(32, 8, 4)
+    RECOGS_PERS_CASE(32, 16, 1) RECOGS_PERS_CASE(32, 16, 2) RECOGS_PERS_CASE(32, 16, 4)
+    RECOGS_PERS_CASE(32, 32, 1) RECOGS_PERS_CASE(32, 32, 2) RECOGS_PERS_CASE(32, 32, 4)
 #undef RECOGS_PERS_CASE
     return false;
 }

@@ -91,6 +91,14 @@ __device__ __forceinline__ float dot3c(float a0, float b0, float a1, float b1, f
 // ---------------------------------------------------------------------------
 // wave64 primitives
 // ---------------------------------------------------------------------------
+// Orders LDS accesses among the lanes of one wave (a wave's LDS operations execute in
+// issue order, so no wait is needed; the fences keep the compiler from moving memory
+// operations across this point). Not a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 // number of set bits of m in lanes below this lane
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
@@ -219,7 +227,9 @@ struct SplatRec { float4 r0, r1, r2; };
 // each edge the 1-D maximum is at the clamped stationary point.
 __device__ __forceinline__ float emax_rect(float4 r1, float dx0, float dx1, float dy0, float dy1) {
     if (dx0 <= 0.f && 0.f <= dx1 && dy0 <= 0.f && 0.f <= dy1) return r1.w;
-    const float ia = -0.5f / r1.x, ic = -0.5f / r1.z;   // 1 / (-2A), 1 / (-2C)
+    // 1 / (-2A), 1 / (-2C) to about 1 ulp: they only place the candidate maximiser on
+    // an edge, where an error of that size changes the value by far less than the margin
+    const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
     float m = -INFINITY;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -236,6 +246,20 @@ __device__ __forceinline__ float emax_rect(float4 r1, float dx0, float dx1, floa
 // error of either evaluation: pixel offsets dx = (px + 1/2) - u are exact (Sterbenz)
 // and the quadratic carries a few ulps
 constexpr float kMaskMargin = 4e-3f;
+
+// true when the splat can reach alpha >= 1/255 at a pixel centre of the rectangle
+// [x0, x1] x [y0, y1] (absolute pixel-centre coordinates): its alpha >= 1/255 box
+// (centre u, v, half-extents ex, ey in r0) meets the rectangle, and the largest
+// base-2 exponent over it (exact maximum of the concave quadratic, see emax_rect) is
+// at least the threshold less a margin far above float32 error. Skipping a region
+// that fails is therefore exact.
+__device__ __forceinline__ bool region_hit(float4 r0, float4 r1, float x0, float x1, float y0, float y1) {
+    if (r0.x + r0.z < x0 || r0.x - r0.z > x1 || r0.y + r0.w < y0 || r0.y - r0.w > y1) return false;
+    return emax_rect(r1, x0 - r0.x, x1 - r0.x, y0 - r0.y, y1 - r0.y) >= kLog2AlphaMin - kMaskMargin;
+}
+
+// Tile shapes whose blend runs in region form (one wave per 8 x 8*PPT block).
+constexpr bool region_shape(int tw, int th, int ppt) { return tw % 8 == 0 && th % (8 * ppt) == 0; }
 
 template <int TW, int TH, int PPT> struct TileMap {
     static constexpr int NT = TW * TH / PPT;
@@ -264,23 +288,14 @@ template <int TW, int TH, int PPT> struct TileMap {
             y0 = 0.5f; y1 = (float)TH - 0.5f;
         }
     }
-    // bit w set when the splat can reach alpha >= 1/255 at a pixel centre of wave region
-    // w: its alpha >= 1/255 box (centre u, v, half-extents ex, ey) meets the region's
-    // pixel-centre rectangle, and the largest base-2 exponent over that rectangle
-    // (exact maximum of the concave quadratic, see emax_rect) is at least the threshold
-    // less a margin far above float32 error. Skipping a region is therefore exact.
+    // bit w set when region_hit holds for wave region w
     static __device__ __forceinline__ uint32_t wave_mask(float4 r0, float4 r1, float tx0, float ty0) {
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             float x0, x1, y0, y1;
             bounds(w, x0, x1, y0, y1);
-            bool hit = !(r0.x + r0.z < tx0 + x0 || r0.x - r0.z > tx0 + x1 || r0.y + r0.w < ty0 + y0 ||
-                         r0.y - r0.w > ty0 + y1);
-            if (hit)
-                hit = emax_rect(r1, tx0 + x0 - r0.x, tx0 + x1 - r0.x, ty0 + y0 - r0.y, ty0 + y1 - r0.y) >=
-                      kLog2AlphaMin - kMaskMargin;
-            m |= (hit ? 1u : 0u) << w;
+            m |= (region_hit(r0, r1, tx0 + x0, tx0 + x1, ty0 + y0, ty0 + y1) ? 1u : 0u) << w;
         }
         return m;
     }

@@ -148,6 +148,33 @@ struct BlendStage {
     BlendRec r[kBlendBatch];
 };
 
+// One splat record applied to the PPT pixels of a thread (eq. 3, front to back).
+// `idx` is the record's 1-based position in its tile list (kept, with STATE, as the
+// count up to the last blended entry).
+template <int PPT, bool STATE>
+__device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const float *pyc, float *T, float *C0, float *C1,
+                                           float *C2, uint32_t *last, uint32_t idx) {
+#pragma clang fp contract(off)
+    const float2 uv = b.uv;
+    const float4 r1 = b.r1, r2 = b.rgb;
+    const ExpRow er = exp_row(r1, pxc - uv.x);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const float e = exp_at(er, r1, pyc[j] - uv.y);
+        const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
+        const float Tn = T[j] * (1.f - a);
+        const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
+        const bool stop = Tn < kTMin;
+        const bool bl = ok && !stop;
+        const float wgt = bl ? a * T[j] : 0.f;
+        C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
+        C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
+        C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
+        if constexpr (STATE) last[j] = bl ? idx : last[j];
+        T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
+    }
+}
+
 // One tile (local index `tile` of a W x H image with tiles_x tiles per row) whose
 // sorted list is vals[rg.x, rg.y). With STATE the final transmittance and the
 // per-pixel count of list entries up to the last blended one are written (the
@@ -233,31 +260,113 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
                     quit = true;
                     break;
                 }
-                const BlendRec &b = sm.r[q];
-                const float2 uv = b.uv;
-                const float4 r1 = b.r1, r2 = b.rgb;
-                const ExpRow er = exp_row(r1, pxc - uv.x);
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const float e = exp_at(er, r1, pyc[j] - uv.y);
-                    const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
-                    const float Tn = T[j] * (1.f - a);
-                    const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
-                    const bool stop = Tn < kTMin;
-                    const bool bl = ok && !stop;
-                    const float wgt = bl ? a * T[j] : 0.f;
-                    C0[j] = __builtin_fmaf(r2.x, wgt, C0[j]);
-                    C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
-                    C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
-                    if constexpr (STATE) last[j] = bl ? krel0 + (uint32_t)q : last[j];
-                    T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
-                }
+                blend_step<PPT, STATE>(sm.r[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q);
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int py = ty0 + lrow * PPT + j;
+        if (px < W && py < H) {
+            const int64_t p = (int64_t)py * W + px;
+            const float Tf = fabsf(T[j]);
+            image[p * 3 + 0] = __builtin_fmaf(Tf, bg0, C0[j]);
+            image[p * 3 + 1] = __builtin_fmaf(Tf, bg1, C1[j]);
+            image[p * 3 + 2] = __builtin_fmaf(Tf, bg2, C2[j]);
+            if constexpr (STATE) {
+                finalT[p] = Tf;
+                nproc[p] = last[j];
+            }
+        }
+    }
+}
+
+// Region form of the same blend: one wave, alone in its workgroup, composites the
+// 8 x 8*PPT pixel region `sub` of tile `tile` (regions numbered row-major, TW / 8 per
+// row). It reads the tile's whole list 64 records at a time, one per lane, and takes
+// those that pass region_hit for its own region, in list order. No barrier couples
+// the regions of a tile: a region whose pixels have all stopped retires at once, so
+// the sort tile can be larger than the region without the early-stopped pixels
+// holding the rest. The per-pixel arithmetic and the list positions kept with STATE
+// are those of blend_tile, so both forms give bit-identical outputs.
+template <int TW, int TH, int PPT, bool STATE>
+__device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const uint32_t *__restrict__ vals,
+                                             const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
+                                             float bg1, float bg2, float *__restrict__ image,
+                                             float *__restrict__ finalT, uint32_t *__restrict__ nproc,
+                                             BlendRec *sm /* [64] */) {
+#pragma clang fp contract(off)
+    static_assert(TW % 8 == 0 && TH % (8 * PPT) == 0, "regions of 8 x 8*PPT pixels");
+    const int l = (int)lane_id();
+    const int bx = (tile % tiles_x) * TW + (sub % (TW / 8)) * 8;
+    const int by = (tile / tiles_x) * TH + (sub / (TW / 8)) * 8 * PPT;
+    const int px = bx + (l & 7);
+    const float pxc = (float)px + 0.5f;
+    const float x0 = (float)bx + 0.5f, x1 = x0 + 7.f;
+    const float y0 = (float)by + 0.5f, y1 = y0 + (float)(8 * PPT - 1);
+    float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    uint32_t last[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = by + (l >> 3) * PPT + j;
+        pyc[j] = (float)py + 0.5f;
+        T[j] = (px < W && py < H) ? 1.f : -1.f;  // pixels outside the image start stopped
+        C0[j] = C1[j] = C2[j] = 0.f;
+        last[j] = 0;
+    }
+    // Software pipeline over chunks of 64 list entries (one per lane): the records of
+    // chunk c are in registers while chunk c - 1 is composited, and the list values of
+    // chunk c + 1 are on their way, so the two dependent loads are off the critical path.
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    uint32_t vnext = 0;
+    {
+        const uint32_t k = rg.x + (uint32_t)l;
+        if (k < rg.y) {
+            const SplatRec *s = rec + vals[k];
+            p0 = s->r0; p1 = s->r1; p2 = s->r2;
+        }
+        if (k + 64u < rg.y) vnext = vals[k + 64u];
+    }
+    for (uint32_t start = rg.x; start < rg.y; start += 64) {
+        bool alive = false;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
+        if (!wave_ballot(alive)) break;
+        const bool hit = start + (uint32_t)l < rg.y && region_hit(p0, p1, x0, x1, y0, y1);
+        if (hit) {
+            BlendRec b;
+            b.uv = make_float2(p0.x, p0.y);
+            b.mask = 0u;
+            b.pad = 0u;
+            b.r1 = p1;
+            b.rgb = p2;
+            sm[l] = b;
+        }
+        uint64_t mm = wave_ballot(hit);
+        wave_sync();   // the lanes' LDS writes before any lane reads
+        {
+            const uint32_t k = start + 64u + (uint32_t)l;
+            if (k < rg.y) {
+                const SplatRec *s = rec + vnext;
+                p0 = s->r0; p1 = s->r1; p2 = s->r2;
+            }
+            if (k + 64u < rg.y) vnext = vals[k + 64u];
+        }
+        const uint32_t krel0 = start + 1 - rg.x;
+        while (mm) {
+            const int q = (int)__builtin_ctzll(mm);
+            mm &= mm - 1;
+            bool live = false;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) live = live || T[j] > 0.f;
+            if (!wave_ballot(live)) break;
+            blend_step<PPT, STATE>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q);
+        }
+        wave_sync();   // all reads of this chunk before the next chunk's writes
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = by + (l >> 3) * PPT + j;
         if (px < W && py < H) {
             const int64_t p = (int64_t)py * W + px;
             const float Tf = fabsf(T[j]);

@@ -80,7 +80,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool tile_supported(int tw, int th) {
-    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
+    return (tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8) || (tw == 32 && th == 16) ||
+           (tw == 32 && th == 32);
 }
 
 // Computes every offset of the workspace; returns total bytes.
@@ -277,7 +278,7 @@ int bits_for(uint64_t v) {  // bits needed to represent values 0..v
 recogs_status check_opts(const recogs_render_opts *o) {
     if (!o) return fail(RECOGS_ERR_INVALID, "render opts is NULL");
     if (!tile_supported(o->tile_w, o->tile_h))
-        return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8", o->tile_w, o->tile_h);
+        return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8, 32x16, 32x32", o->tile_w, o->tile_h);
     if (o->sort_mode != 0 && o->sort_mode != 1) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0 or 1", o->sort_mode);
     if (o->graph_mode != 0 && o->graph_mode != 1) return fail(RECOGS_ERR_INVALID, "graph_mode %d not 0 or 1", o->graph_mode);
     if (o->graph_mode && o->sort_mode != 0) return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode needs sort_mode 0");

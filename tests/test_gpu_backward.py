@@ -64,7 +64,7 @@ def _close(got, ref, rel, what):
     return float(err.max() / scale)
 
 
-@pytest.mark.parametrize("tile,ppt", [((16, 16), 1), ((8, 8), 2), ((32, 8), 4)])
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 1), ((8, 8), 2), ((32, 8), 4), ((32, 32), 2), ((32, 16), 1)])
 def test_backward_vs_oracle(R, orc, tile, ppt):
     w = _wfd()
     cam = w.view.camera
@@ -211,7 +211,7 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
     mask, _ = orc.select(sc, cam, v.select)
     M = v.recolor.M.astype(np.float64)
     b = v.recolor.b.astype(np.float64)
-    pr = orc.project(sc, cam, (16, 16), mask=mask, M=M, b=b)
+    pr = orc.project(sc, cam, (32, 16), mask=mask, M=M, b=b)
     wins = [(320, 192, 32, 32), (640, 352, 32, 32), (96, 608, 32, 32), (1152, 64, 32, 32)]
     ref = orc.render_windows(pr, wins)
     rng = np.random.default_rng(33)
@@ -225,11 +225,11 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
         o += ww * wh
     gr = orc.backward(pr, g.astype(np.float64), M=M, windows=wins)
     d = R.DeviceScene(sc)
-    ws = R.DeviceWorkspace(sc.n, cam.width, cam.height, (16, 16))
+    ws = R.DeviceWorkspace(sc.n, cam.width, cam.height, (32, 16))
     tm = torch.from_numpy(mask).cuda()
     tM = torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda()
     tb = torch.from_numpy(v.recolor.b.copy()).cuda()
-    img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (16, 16), 1)
+    img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (32, 16), 1)
     e1 = _close(dop, gr.dsigma, 2e-3, "dL/dopacity")
     e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
     e3 = _close(dM, gr.dM, 2e-3, "dL/dM")

@@ -27,7 +27,7 @@ def _setup(R, n=100_000):
     return w, v, d, mask, M, b
 
 
-@pytest.mark.parametrize("tile,ppt", [((16, 16), 2), ((8, 8), 1), ((32, 8), 4)])
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 2), ((8, 8), 1), ((32, 8), 4), ((32, 32), 2)])
 def test_graph_mode_equals_eager(R, tile, ppt):
     import torch
     w, v, d, mask, M, b = _setup(R)

@@ -178,23 +178,26 @@ def test_render_full_image(R, orc, cfg, sort_mode):
     print(f"{cfg}: K={p['K']} max|err| outside band {err:.2e}, in-band pixels {nband}, depth mismatches {int(zmis.sum())}")
 
 
-@pytest.mark.parametrize("storage,sort_mode", [("f32", 0), ("f32", 1), ("f16", 0), ("bf16", 0)])
-def test_render_1m_1080p_crops(R, orc, storage, sort_mode):
+@pytest.mark.parametrize("storage,sort_mode,tile,ppt", [("f32", 0, (32, 32), 2), ("f32", 0, (16, 16), 1),
+                                                       ("f32", 1, (16, 16), 1), ("f16", 0, (32, 32), 2),
+                                                       ("bf16", 0, (16, 16), 1)])
+def test_render_1m_1080p_crops(R, orc, storage, sort_mode, tile, ppt):
     """1,000,000 Gaussians, SH degree 3, 1920x1080: integer steps on the whole frame,
-    pixels on 64 seeded 32x32 crops."""
+    pixels on 64 seeded 32x32 crops (32x32 tiles with 2 pixels per thread is the
+    benchmarked launch)."""
     w32 = synth.make_precision()
     w = w32 if storage == "f32" else synth.make_precision(storage=storage)
     n = w.scene.n
-    out = gpu_run(w, sort_mode=sort_mode)
+    out = gpu_run(w, tile=tile, ppt=ppt, sort_mode=sort_mode)
     p = pull(out, n)
-    pr = _oracle(w, orc)
+    pr = _oracle(w, orc, tile=tile)
     _check_integer_steps(w, orc, p, pr, n)
     wins = crop_windows(w, w.extra["crops"])
     ref = orc.render_windows(pr, wins)
     got = np.concatenate([p["img"][y:y + 32, x:x + 32].reshape(-1, 3) for (x, y, _, _) in wins])
     err, nband = assert_pixels(got, ref.rgb, ref.slack, TOL_F32, f"{storage} vs oracle on stored inputs")
     if storage != "f32":
-        ref32 = orc.render_windows(_oracle(w32, orc), wins)
+        ref32 = orc.render_windows(_oracle(w32, orc, tile=tile), wins)
         err32, _ = assert_pixels(got, ref32.rgb, ref32.slack, TOL_F16, f"{storage} vs oracle on float32 inputs")
         print(f"{storage}: error vs float32-input oracle {err32:.2e}")
     print(f"{storage}: K={p['K']} crops max|err| {err:.2e} in-band {nband}")
@@ -236,7 +239,7 @@ def test_separate_recolor_then_render_equals_fused(R, orc):
 def test_tile_shape_ppt_and_sort_mode_do_not_change_bits(R):
     w = synth.make_mid(n=100_000)
     base = gpu_run(w, tile=(16, 16), ppt=1)["img"].cpu().numpy()
-    for tile in [(16, 16), (8, 8), (32, 8)]:
+    for tile in [(16, 16), (8, 8), (32, 8), (32, 16), (32, 32)]:
         for ppt in [1, 2, 4]:
             for mode in [0, 1]:
                 img = gpu_run(w, tile=tile, ppt=ppt, sort_mode=mode)["img"].cpu().numpy()
