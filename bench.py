@@ -180,10 +180,10 @@ class Single:
     def counts(self):
         """Counts of the frame. K, V and the sort passes are those of the timed launch
         shape. The blend's nominal work (`evals`) is fixed independently of that shape:
-        per pixel, the entries of its 16x16-tile list (the reference rasteriser's tiling)
-        up to and including its last blended splat, summed over pixels; one more render
-        at 16x16 tiles that also writes the per-pixel state gives it. `keff` is the
-        per-tile maximum of that count, summed over 16x16 tiles."""
+        per pixel, the entries of its 16x16-tile list (the tiling of the 3DGS rasteriser
+        the paper builds on) up to and including its last blended splat, summed over
+        pixels; one more render at 16x16 tiles that also writes the per-pixel state
+        gives it. `keff` is the per-tile maximum of that count, summed over 16x16 tiles."""
         import torch
         self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh)
         ws = self.ws
@@ -513,6 +513,15 @@ def main():
         "counts": st,
     }
     del s
+    if tuple(tile) != (16, 16):
+        # the same frame at the 16x16 tiles of the 3DGS rasteriser (same images, bit for bit)
+        log("bench: the same frame at 16x16 tiles, 1 px/thread")
+        s16 = Single(R, w, dev, (16, 16), 1)
+        m16 = s16.measure(args.steps, args.warmup)
+        res["at_16x16_tiles"] = {"px_per_thread": 1, "frames_per_s": round(1000.0 / m16["ms"], 2),
+                                 "ms_per_step": round(m16["ms"], 4), "blend_ms": round(m16["blend_ms_timed"], 4),
+                                 "stages_ms": {k: round(v, 4) for k, v in m16["stages"].items()}}
+        del s16
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
