@@ -142,7 +142,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                     db += wgt * g2[j];
                     ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
                     Gr[j] -= ws;
-                    T[j] = act ? T[j] * (1.f - a) : T[j];
+                    T[j] = act ? __builtin_fmaf(-a, T[j], T[j]) : T[j];
                 }
                 if (wave_ballot(any)) {
                     ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);

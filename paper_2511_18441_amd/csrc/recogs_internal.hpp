@@ -223,24 +223,24 @@ struct SplatRec { float4 r0, r1, r2; };
 // ---------------------------------------------------------------------------
 // Largest e(dx, dy) = A dx^2 + B dx dy + C dy^2 + o (r1 = (A, B, C, o), A, C < 0: a
 // concave quadratic with its maximum o at the splat centre) over the rectangle
-// [dx0, dx1] x [dy0, dy1]. With the centre outside, the maximum lies on an edge; on
-// each edge the 1-D maximum is at the clamped stationary point.
+// [dx0, dx1] x [dy0, dy1]. With the centre outside, the maximiser lies on an edge that
+// faces the centre: from any other boundary point the direction to the centre points
+// into the rectangle, along which e increases. So only the vertical line nearest the
+// centre (x = clamp(0, dx0, dx1)) and the horizontal one (y = clamp(0, dy0, dy1)) are
+// searched; where the centre's x lies in [dx0, dx1] that line passes through the
+// centre and, lying inside the rectangle, cannot exceed the maximum. On each line the
+// 1-D maximum is at the clamped stationary point.
 __device__ __forceinline__ float emax_rect(float4 r1, float dx0, float dx1, float dy0, float dy1) {
     if (dx0 <= 0.f && 0.f <= dx1 && dy0 <= 0.f && 0.f <= dy1) return r1.w;
     // 1 / (-2A), 1 / (-2C) to about 1 ulp: they only place the candidate maximiser on
-    // an edge, where an error of that size changes the value by far less than the margin
+    // its line, where an error of that size changes the value by far less than the margin
     const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
-    float m = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float X = k ? dx1 : dx0;
-        const float dy = fminf(fmaxf(r1.y * X * ic, dy0), dy1);
-        m = fmaxf(m, (r1.x * X + r1.y * dy) * X + r1.z * dy * dy + r1.w);
-        const float Y = k ? dy1 : dy0;
-        const float dx = fminf(fmaxf(r1.y * Y * ia, dx0), dx1);
-        m = fmaxf(m, (r1.z * Y + r1.y * dx) * Y + r1.x * dx * dx + r1.w);
-    }
-    return m;
+    const float X = fminf(fmaxf(0.f, dx0), dx1), Y = fminf(fmaxf(0.f, dy0), dy1);
+    const float dy = fminf(fmaxf(r1.y * X * ic, dy0), dy1);
+    const float mx = (r1.x * X + r1.y * dy) * X + r1.z * dy * dy + r1.w;
+    const float dx = fminf(fmaxf(r1.y * Y * ia, dx0), dx1);
+    const float my = (r1.z * Y + r1.y * dx) * Y + r1.x * dx * dx + r1.w;
+    return fmaxf(mx, my);
 }
 // exponent margin of the region test (alpha 0.3 % below 1/255), far above the float32
 // error of either evaluation: pixel offsets dx = (px + 1/2) - u are exact (Sterbenz)

@@ -162,7 +162,7 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
     for (int j = 0; j < PPT; ++j) {
         const float e = exp_at(er, r1, pyc[j] - uv.y);
         const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
-        const float Tn = T[j] * (1.f - a);
+        const float Tn = __builtin_fmaf(-a, T[j], T[j]);   // T (1 - alpha), rounded once
         const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
         const bool stop = Tn < kTMin;
         const bool bl = ok && !stop;
@@ -171,7 +171,8 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
         C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
         C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
         if constexpr (STATE) last[j] = bl ? idx : last[j];
-        T[j] = ok ? (stop ? -T[j] : Tn) : T[j];
+        const float Ts = stop ? -T[j] : Tn;   // two selects: this form compiles to v_cndmask
+        T[j] = ok ? Ts : T[j];
     }
 }
 
