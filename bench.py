@@ -421,7 +421,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, nargs=2, default=[32, 32])
-    ap.add_argument("--ppt", type=int, default=2)
+    ap.add_argument("--ppt", type=int, default=1)
     ap.add_argument("--diff-tile", type=int, nargs=2, default=None,
                     help="tile shape of the differentiation form when run alone (--only-form diff)")
     ap.add_argument("--diff-ppt", type=int, default=DIFF_PPT)

@@ -138,7 +138,7 @@ def test_batch_full_size_sampled_views_vs_oracle(R, orc):
                         count.data_ptr())
         views.append((v.scene, v.camera, mask, torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda(),
                        torch.from_numpy(v.recolor.b.copy()).cuda()))
-    b = R.DeviceBatch(dscenes, views, (32, 32), 2)
+    b = R.DeviceBatch(dscenes, views, (32, 32), 1)
     b.render()
     k, ovf = b.readback()
     assert not ovf and k > 40_000_000

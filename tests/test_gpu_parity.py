@@ -178,12 +178,12 @@ def test_render_full_image(R, orc, cfg, sort_mode):
     print(f"{cfg}: K={p['K']} max|err| outside band {err:.2e}, in-band pixels {nband}, depth mismatches {int(zmis.sum())}")
 
 
-@pytest.mark.parametrize("storage,sort_mode,tile,ppt", [("f32", 0, (32, 32), 2), ("f32", 0, (16, 16), 1),
-                                                       ("f32", 1, (16, 16), 1), ("f16", 0, (32, 32), 2),
+@pytest.mark.parametrize("storage,sort_mode,tile,ppt", [("f32", 0, (32, 32), 1), ("f32", 0, (16, 16), 1),
+                                                       ("f32", 1, (32, 32), 2), ("f16", 0, (32, 32), 1),
                                                        ("bf16", 0, (16, 16), 1)])
 def test_render_1m_1080p_crops(R, orc, storage, sort_mode, tile, ppt):
     """1,000,000 Gaussians, SH degree 3, 1920x1080: integer steps on the whole frame,
-    pixels on 64 seeded 32x32 crops (32x32 tiles with 2 pixels per thread is the
+    pixels on 64 seeded 32x32 crops (32x32 tiles with 1 pixel per thread is the
     benchmarked launch)."""
     w32 = synth.make_precision()
     w = w32 if storage == "f32" else synth.make_precision(storage=storage)
