@@ -235,10 +235,11 @@ __device__ __forceinline__ float emax_rect(float4 r1, float dx0, float dx1, floa
     // 1 / (-2A), 1 / (-2C) to about 1 ulp: they only place the candidate maximiser on
     // its line, where an error of that size changes the value by far less than the margin
     const float ia = -0.5f * __builtin_amdgcn_rcpf(r1.x), ic = -0.5f * __builtin_amdgcn_rcpf(r1.z);
-    const float X = fminf(fmaxf(0.f, dx0), dx1), Y = fminf(fmaxf(0.f, dy0), dy1);
-    const float dy = fminf(fmaxf(r1.y * X * ic, dy0), dy1);
+    // clamps as one median-of-three each (the bounds are ordered and nothing is NaN)
+    const float X = __builtin_amdgcn_fmed3f(0.f, dx0, dx1), Y = __builtin_amdgcn_fmed3f(0.f, dy0, dy1);
+    const float dy = __builtin_amdgcn_fmed3f(r1.y * X * ic, dy0, dy1);
     const float mx = (r1.x * X + r1.y * dy) * X + r1.z * dy * dy + r1.w;
-    const float dx = fminf(fmaxf(r1.y * Y * ia, dx0), dx1);
+    const float dx = __builtin_amdgcn_fmed3f(r1.y * Y * ia, dx0, dx1);
     const float my = (r1.z * Y + r1.y * dx) * Y + r1.x * dx * dx + r1.w;
     return fmaxf(mx, my);
 }

@@ -334,14 +334,10 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
         for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
         if (!wave_ballot(alive)) break;
         const bool hit = start + (uint32_t)l < rg.y && region_hit(p0, p1, x0, x1, y0, y1);
-        if (hit) {
-            BlendRec b;
-            b.uv = make_float2(p0.x, p0.y);
-            b.mask = 0u;
-            b.pad = 0u;
-            b.r1 = p1;
-            b.rgb = p2;
-            sm[l] = b;
+        if (hit) {   // (the mask fields of the record are not used in this form)
+            sm[l].uv = make_float2(p0.x, p0.y);
+            sm[l].r1 = p1;
+            sm[l].rgb = p2;
         }
         uint64_t mm = wave_ballot(hit);
         wave_sync();   // the lanes' LDS writes before any lane reads
