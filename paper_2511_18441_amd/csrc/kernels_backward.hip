@@ -120,9 +120,10 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const BlendRec &b = sm.r[q];
                 const float2 uv = b.uv;
                 const float4 r1 = b.r1, r2 = b.rgb;
-                const float inv_sigma = 1.f / r2.w;
+                // 1 / sigma to about 1 ulp: it only scales this splat's opacity gradient
+                const float inv_sigma = __builtin_amdgcn_rcpf(r2.w);
                 const ExpRow er = exp_row(r1, pxc - uv.x);
-                float ds = 0.f, dr = 0.f, dg = 0.f, db = 0.f;
+                float ds, dr, dg, db;
                 bool any = false;
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
@@ -137,10 +138,12 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                     const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
                     const float ws = wgt * sg;
                     const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
-                    dr += wgt * g0[j];
-                    dg += wgt * g1[j];
-                    db += wgt * g2[j];
-                    ds += (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
+                    const float vs = (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
+                    if (j == 0) {   // (no adds of zero: x + 0 is not folded, for the sign of zero)
+                        dr = wgt * g0[j]; dg = wgt * g1[j]; db = wgt * g2[j]; ds = vs;
+                    } else {
+                        dr += wgt * g0[j]; dg += wgt * g1[j]; db += wgt * g2[j]; ds += vs;
+                    }
                     Gr[j] -= ws;
                     T[j] = act ? __builtin_fmaf(-a, T[j], T[j]) : T[j];
                 }
