@@ -343,7 +343,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         targets.append(t)
     imgs = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in w.views]
     dimg = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
-    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    loss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)   # one slot per view
     dop = torch.empty(n, dtype=torch.float32, device=dev)
     ddc = torch.empty((3, n), dtype=torch.float32, device=dev)
     dM = torch.empty(9, dtype=torch.float32, device=dev)
@@ -352,11 +352,10 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     o = R.opts_struct(tile, ppt, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True)
 
     def step():
-        loss.zero_()
         for k, v in enumerate(w.views):
             R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
             R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
-                             loss.data_ptr())
+                             loss.data_ptr() + 4 * k)
             R.recogs_render_backward(sc, cams[k], o, ws[k].ws, imgs[k].data_ptr(), dimg.data_ptr(), dop.data_ptr(),
                                      ddc.data_ptr(), dM.data_ptr())
     for _ in range(max(2, warmup // 4)):
@@ -378,7 +377,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / reps
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
             "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
-            "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.item()),
+            "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.sum().item()),
             "grad_M_norm": float(dM.norm().item())}
 
 

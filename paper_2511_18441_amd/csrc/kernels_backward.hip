@@ -230,24 +230,46 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
 
 // dM[k] = sum over blocks of part[block][k], one workgroup, fixed summation order
 __global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ part, uint32_t nblocks, float *__restrict__ dM) {
-    __shared__ float s_w[4];
+    // thread t adds blocks t, t + 256, ... in order, all nine sums at once (independent
+    // loads); then a fixed tree over lanes and waves: the order never depends on timing
+    __shared__ float s_w[4][9];
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = 0.f;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] += part[(size_t)b * 9 + k];
+    }
+#pragma unroll
     for (int k = 0; k < 9; ++k) {
-        float v = 0.f;
-        for (uint32_t b = threadIdx.x; b < nblocks; b += 256) v += part[(size_t)b * 9 + k];
-        v = wave_sum(v);
-        if (lane_id() == 0) s_w[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) dM[k] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
-        __syncthreads();
+        const float x = wave_sum(v[k]);
+        if (lane_id() == 0) s_w[threadIdx.x >> 6][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        const int k = threadIdx.x;
+        dM[k] = ((s_w[0][k] + s_w[1][k]) + s_w[2][k]) + s_w[3][k];
     }
 }
 
-// L2 loss: loss += scale sum (y - t)^2, dL/dy = 2 scale (y - t)
+// L2 loss: loss += scale sum (y - t)^2, dL/dy = 2 scale (y - t). With vec (all three
+// arrays 16-byte aligned) each thread takes 4 consecutive elements per step with one
+// 16-byte access per array; the remainder (or everything, without vec) one by one.
 __global__ __launch_bounds__(256) void k_loss_l2(const float *__restrict__ y, const float *__restrict__ tg, int64_t count,
-                                                 float scale, float *__restrict__ dldy, float *__restrict__ loss) {
+                                                 float scale, float *__restrict__ dldy, float *__restrict__ loss, int vec) {
     __shared__ float s_w[4];
     float sum = 0.f;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n4 = vec ? count / 4 : 0;
+    const float4 *y4 = reinterpret_cast<const float4 *>(y), *t4 = reinterpret_cast<const float4 *>(tg);
+    float4 *d4 = reinterpret_cast<float4 *>(dldy);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 a = y4[i], b = t4[i];
+        const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+        d4[i] = make_float4(2.f * scale * d.x, 2.f * scale * d.y, 2.f * scale * d.z, 2.f * scale * d.w);
+        sum += d.x * d.x + d.y * d.y + d.z * d.z + d.w * d.w;
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         const float d = y[i] - tg[i];
         dldy[i] = 2.f * scale * d;
         sum += d * d;
@@ -299,7 +321,9 @@ void launch_loss_l2(const float *y, const float *tg, int64_t count, float scale,
     // few workgroups: each adds its partial sum with one same-address atomic
     int64_t blocks = (count + 255) / 256;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(k_loss_l2, dim3((unsigned)blocks), dim3(256), 0, st, y, tg, count, scale, dldy, loss);
+    const int vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(tg) | reinterpret_cast<uintptr_t>(dldy)) &
+                     15u) == 0;
+    hipLaunchKernelGGL(k_loss_l2, dim3((unsigned)blocks), dim3(256), 0, st, y, tg, count, scale, dldy, loss, vec);
 }
 
 }  // namespace recogs

@@ -166,6 +166,17 @@ def test_loss_l2(R, orc):
     ref_g = orc.loss_l2_grad(y, t)
     assert abs(loss.item() - ref_loss) <= 1e-5 * ref_loss
     np.testing.assert_allclose(dl.cpu().numpy(), ref_g, rtol=1e-6, atol=1e-12)
+    # arrays that are not 16-byte aligned (one float in) and a count that is not a
+    # multiple of 4 take the element-wise path; the loss is overwritten, not added to
+    yf, tf = ty.reshape(-1), tt.reshape(-1)
+    dlf = torch.zeros(cnt, device="cuda")
+    m = cnt - 2
+    R.recogs_loss_l2(yf[1:].data_ptr(), tf[1:].data_ptr(), m, 1.0 / m, dlf[1:].data_ptr(), loss.data_ptr())
+    torch.cuda.synchronize()
+    y1, t1 = y.reshape(-1)[1:1 + m], t.reshape(-1)[1:1 + m]
+    assert abs(loss.item() - orc.loss_l2(y1, t1)) <= 1e-5 * orc.loss_l2(y1, t1)
+    np.testing.assert_allclose(dlf[1:1 + m].cpu().numpy(), orc.loss_l2_grad(y1, t1), rtol=1e-6, atol=1e-12)
+    assert dlf[0].item() == 0.0 and dlf[1 + m].item() == 0.0
 
 
 def test_backward_without_recolor_and_zero_gradient(R, orc):
