@@ -6,7 +6,8 @@
 // tiles of all views one global tile-id space (view v owns [tile_base_v, +ntiles_v)).
 // Preprocess writes per-pair records; the count scan, the depth sort, the emission
 // (global tile ids) and the tile-id sort are the single-view kernels run over pairs;
-// the blend is persistent: workgroups take global tiles from an atomic queue in
+// the blend is persistent: workgroups take global tiles (or, in region form, one-wave
+// workgroups take (tile, region) items from per-XCD queues) from atomic queues in
 // largest-list-first order, so uneven views share the GPU without a tail of idle CUs.
 #include "render_device.hpp"
 
@@ -116,26 +117,36 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_persistent(const ViewDev
     }
 }
 
-// Region form for the batch: one wave per 8 x 8*PPT region of every tile of every
-// view, tiles taken in queue order (longest lists first). Workgroup b runs on XCD
-// b mod 8; a tile's regions take consecutive workgroups of one XCD and the tiles are
-// dealt to the XCDs in turn.
+// Persistent region form: `grid` one-wave workgroups take (tile, region) items from
+// per-XCD queues until theirs is exhausted (every wave reaches that exit). Tile j of
+// the longest-first order belongs to queue j mod 8 and its regions are consecutive
+// items of that queue, so its list is read through one L2; workgroup b takes items
+// from queue b mod 8, the XCD it runs on when workgroups are dealt to the XCDs in turn
+// (any other placement only costs locality).
 template <int TW, int TH, int PPT>
-__global__ __launch_bounds__(64) void k_blend_region_batch(const ViewDev *__restrict__ views, int nviews,
-                                                          const uint2 *__restrict__ ranges,
-                                                          const uint32_t *__restrict__ vals,
-                                                          const SplatRec *__restrict__ rec,
-                                                          const uint32_t *__restrict__ order, uint32_t ntiles) {
+__global__ __launch_bounds__(64) void k_blend_region_persistent(const ViewDev *__restrict__ views, int nviews,
+                                                               const uint2 *__restrict__ ranges,
+                                                               const uint32_t *__restrict__ vals,
+                                                               const SplatRec *__restrict__ rec,
+                                                               const uint32_t *__restrict__ order, uint32_t ntiles,
+                                                               uint32_t *__restrict__ xqueue) {
     constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
     __shared__ BlendRec sm[64];
-    const uint32_t b = blockIdx.x, j = b >> 3;
-    const uint32_t item = (j / NR) * 8u + (b & 7u);
-    if (item >= ntiles) return;
-    const uint32_t gt = order[item];
-    const int v = view_of_tile(views, nviews, gt);
-    const ViewDev &vw = views[v];
-    blend_region<TW, TH, PPT, false>((int)(gt - vw.tile_base), (int)(j % NR), ranges[gt], vals, rec, vw.cam.W, vw.cam.H,
-                                     vw.cam.tiles_x, vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr, nullptr, sm);
+    const uint32_t x = blockIdx.x & 7u;
+    const uint32_t nitems = (ntiles > x ? (ntiles - x + 7u) / 8u : 0u) * NR;
+    uint32_t *q = xqueue + 32u * x;
+    while (true) {
+        uint32_t m = 0;
+        if (lane_id() == 0) m = atomicAdd(q, 1u);
+        m = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
+        if (m >= nitems) break;
+        const uint32_t gt = order[(m / NR) * 8u + x];
+        const int v = view_of_tile(views, nviews, gt);
+        const ViewDev &vw = views[v];
+        blend_region<TW, TH, PPT, false>((int)(gt - vw.tile_base), (int)(m % NR), ranges[gt], vals, rec, vw.cam.W,
+                                         vw.cam.H, vw.cam.tiles_x, vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr,
+                                         nullptr, sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -173,10 +184,9 @@ static void persistent_one(uint32_t grid, hipStream_t st, const ViewDev *views, 
                            const uint32_t *vals, const SplatRec *rec, const uint32_t *order, uint32_t ntiles,
                            uint32_t *queue) {
     if constexpr (region_shape(TW, TH, PPT)) {
-        constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
-        const dim3 g((unsigned)((ntiles + 7u) / 8u * 8u * NR));
-        hipLaunchKernelGGL((k_blend_region_batch<TW, TH, PPT>), g, dim3(64), 0, st, views, nviews, ranges, vals, rec, order,
-                           ntiles);
+        // 32 one-wave workgroups per CU (grid = CUs x 8); `queue` is the header's H_QUEUE word
+        hipLaunchKernelGGL((k_blend_region_persistent<TW, TH, PPT>), dim3(grid * 4), dim3(64), 0, st, views, nviews, ranges,
+                           vals, rec, order, ntiles, queue + (H_XQUEUE - H_QUEUE));
     } else {
         hipLaunchKernelGGL((k_blend_persistent<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st, views, nviews, ranges,
                            vals, rec, order, ntiles, queue);

@@ -188,7 +188,9 @@ enum : int {
     H_QUEUE = 8,                 // work counter of the persistent blend
     H_ORDER_HIST = 16,           // 32 words: tiles per list-length class
     H_ORDER_CUR = 48,            // 32 words: scatter cursors of the length classes
-    H_WORDS = 128
+    H_XQUEUE = 128,              // 8 x 32 words: per-XCD work counters of the persistent
+                                 // region blend, one per 128-byte line
+    H_WORDS = 384
 };
 
 // Per-view description of a batch (device memory): the view's scene, camera and
