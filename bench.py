@@ -93,9 +93,9 @@ class Single:
     """One scene + view resident on the GPU, with its selection mask, recolour and
     workspace: a frame is recolour (selected, out of place) + render."""
 
-    def __init__(self, R, w, dev, tile, ppt):
+    def __init__(self, R, w, dev, tile, ppt, chw=False):
         import torch
-        self.R, self.w, self.tile, self.ppt = R, w, tuple(tile), int(ppt)
+        self.R, self.w, self.tile, self.ppt, self.chw = R, w, tuple(tile), int(ppt), bool(chw)
         v = w.view
         self.cam = v.camera
         self.n = w.scene.n
@@ -111,7 +111,8 @@ class Single:
         self.render_sh = self.d.sh.clone()
         self.ws = R.DeviceWorkspace(self.n, self.cam.width, self.cam.height, self.tile, key_capacity=16 * self.n,
                                     device=dev)
-        self.image = torch.empty((self.cam.height, self.cam.width, 3), dtype=torch.float32, device=dev)
+        shape = (3, self.cam.height, self.cam.width) if self.chw else (self.cam.height, self.cam.width, 3)
+        self.image = torch.empty(shape, dtype=torch.float32, device=dev)
 
     def select(self):
         self.R.recogs_select(self.scs, self.camc, self.selc, self.mask.data_ptr(), self.count.data_ptr())
@@ -123,7 +124,7 @@ class Single:
     def frame(self, profile=0, graph_mode=True):
         self.recolor()
         self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
-                      profile=profile, graph_mode=graph_mode)
+                      profile=profile, graph_mode=graph_mode, chw=self.chw)
 
     def timed(self, steps, profile, graph_mode=True):
         """Wall-clock ms per frame over `steps` frames, bracketed by device syncs."""
@@ -521,6 +522,13 @@ def main():
                                  "ms_per_step": round(m16["ms"], 4), "blend_ms": round(m16["blend_ms_timed"], 4),
                                  "stages_ms": {k: round(v, 4) for k, v in m16["stages"].items()}}
         del s16
+    # the paper's layout experiment (Sec. 4.2): the same frame writing CHW instead of HWC
+    log("bench: the same frame with CHW output")
+    sc = Single(R, w, dev, tile, args.ppt, chw=True)
+    mc = sc.measure(args.steps, args.warmup)
+    res["output_layout"] = {"hwc": {"frames_per_s": round(fps, 2), "blend_ms": round(m["blend_ms_timed"], 4)},
+                            "chw": {"frames_per_s": round(1000.0 / mc["ms"], 2), "blend_ms": round(mc["blend_ms_timed"], 4)}}
+    del sc
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

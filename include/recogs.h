@@ -121,6 +121,11 @@ typedef struct {
      * (num_keys > key_capacity: overflowed). Needs sort_mode 0; profile_stages 0 or 2.
      * 0: the render reads the key count back once (eager capacity check). */
     int32_t graph_mode;
+    /* Output layout (Sec. 4.2 compares the two). 0 (default): image float [H][W][3]
+     * (HWC, the layout the paper switches the rasteriser to). 1: float [3][H][W] (CHW,
+     * the rasteriser's original layout); the values are the same bits, only the
+     * addresses differ. recogs_render_backward needs an HWC render. */
+    int32_t output_chw;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds

@@ -56,7 +56,7 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
-                ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32)]
+                ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("output_chw", ctypes.c_int32)]
 
 
 class Workspace(ctypes.Structure):
@@ -211,7 +211,7 @@ def select_struct(sp) -> SelectParams:
 
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
-                profile=False, sort_mode=0, graph_mode=False) -> RenderOpts:
+                profile=False, sort_mode=0, graph_mode=False, chw=False) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -224,6 +224,7 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.profile_stages = int(profile)  # False/True -> 0/1; 2 = accumulate without waiting
     o.sort_mode = int(sort_mode)
     o.graph_mode = 1 if graph_mode else 0
+    o.output_chw = 1 if chw else 0
     return o
 
 
@@ -371,15 +372,17 @@ class DeviceWorkspace:
 
 def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
            M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False,
-           sort_mode=0, graph_mode=False):
-    """recogs_render into a (H, W, 3) float32 tensor; grows the workspace once when the
-    view needs more tile keys than it holds (eager mode). With graph_mode nothing is
-    read back: check ws.readback() (num_keys > key_capacity means it overflowed)."""
+           sort_mode=0, graph_mode=False, chw=False):
+    """recogs_render into a (H, W, 3) float32 tensor ((3, H, W) with chw); grows the
+    workspace once when the view needs more tile keys than it holds (eager mode). With
+    graph_mode nothing is read back: check ws.readback() (num_keys > key_capacity means
+    it overflowed)."""
     import torch
     c = camera_struct(cam)
     if image is None:
-        image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dscene.means.device)
-    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode)
+        shape = (3, cam.height, cam.width) if chw else (cam.height, cam.width, 3)
+        image = torch.empty(shape, dtype=torch.float32, device=dscene.means.device)
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode, chw)
     sc = dscene.c_struct(sh)
     st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     if st == -2 and grow:

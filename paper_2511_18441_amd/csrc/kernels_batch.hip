@@ -113,7 +113,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_persistent(const ViewDev
         const int v = view_of_tile(views, nviews, gt);
         const ViewDev &vw = views[v];
         blend_tile<TW, TH, PPT, false>((int)(gt - vw.tile_base), ranges[gt], vals, rec, vw.cam.W, vw.cam.H, vw.cam.tiles_x,
-                                vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr, nullptr, sm);
+                                vw.bg[0], vw.bg[1], vw.bg[2], vw.image, 0, nullptr, nullptr, sm);
     }
 }
 
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(64) void k_blend_region_persistent(const ViewDev *_
         const int v = view_of_tile(views, nviews, gt);
         const ViewDev &vw = views[v];
         blend_region<TW, TH, PPT, false>((int)(gt - vw.tile_base), (int)(m % NR), ranges[gt], vals, rec, vw.cam.W,
-                                         vw.cam.H, vw.cam.tiles_x, vw.bg[0], vw.bg[1], vw.bg[2], vw.image, nullptr,
-                                         nullptr, sm);
+                                         vw.cam.H, vw.cam.tiles_x, vw.bg[0], vw.bg[1], vw.bg[2], vw.image, 0,
+                                         nullptr, nullptr, sm);
     }
 }
 

@@ -493,10 +493,10 @@ template <int TW, int TH, int PPT, bool STATE>
 __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                        const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                        float bg0, float bg1, float bg2, float *__restrict__ image,
-                                                       float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
+                                                       int chw, float *__restrict__ finalT, uint32_t *__restrict__ nproc) {
     __shared__ BlendStage sm;
-    blend_tile<TW, TH, PPT, STATE>(blockIdx.x, ranges[blockIdx.x], vals, rec, W, H, tiles_x, bg0, bg1, bg2, image, finalT,
-                                   nproc, sm);
+    blend_tile<TW, TH, PPT, STATE>(blockIdx.x, ranges[blockIdx.x], vals, rec, W, H, tiles_x, bg0, bg1, bg2, image, chw,
+                                   finalT, nproc, sm);
 }
 
 // Region form: one wave per 8 x 8*PPT region. Workgroup b runs on XCD b mod 8; the
@@ -506,7 +506,7 @@ template <int TW, int TH, int PPT, bool STATE>
 __global__ __launch_bounds__(64) void k_blend_region(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                     const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                     uint32_t ntiles, float bg0, float bg1, float bg2,
-                                                    float *__restrict__ image, float *__restrict__ finalT,
+                                                    float *__restrict__ image, int chw, float *__restrict__ finalT,
                                                     uint32_t *__restrict__ nproc) {
     constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
     __shared__ BlendRec sm[64];
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(64) void k_blend_region(const uint2 *__restrict__ r
     const uint32_t tile = (j / NR) * 8u + (b & 7u);
     if (tile >= ntiles) return;
     blend_region<TW, TH, PPT, STATE>((int)tile, (int)(j % NR), ranges[tile], vals, rec, W, H, tiles_x, bg0, bg1, bg2,
-                                     image, finalT, nproc, sm);
+                                     image, chw, finalT, nproc, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -595,32 +595,33 @@ void launch_ranges(const uint64_t *keys, uint32_t K, uint2 *ranges, hipStream_t 
 
 template <int TW, int TH, int PPT>
 static void blend_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec, int W,
-                      int H, int tiles_x, const float *bg, float *image, float *finalT, uint32_t *nproc) {
+                      int H, int tiles_x, const float *bg, float *image, int chw, float *finalT, uint32_t *nproc) {
     if constexpr (region_shape(TW, TH, PPT)) {
-    constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
-    const dim3 g((unsigned)(((uint32_t)ntiles + 7u) / 8u * 8u * NR));
-    if (finalT)
-        hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, true>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
-                           (uint32_t)ntiles, bg[0], bg[1], bg[2], image, finalT, nproc);
-    else
-        hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, false>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
-                           (uint32_t)ntiles, bg[0], bg[1], bg[2], image, nullptr, nullptr);
+        constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
+        const dim3 g((unsigned)(((uint32_t)ntiles + 7u) / 8u * 8u * NR));
+        if (finalT)
+            hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, true>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
+                               (uint32_t)ntiles, bg[0], bg[1], bg[2], image, chw, finalT, nproc);
+        else
+            hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, false>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
+                               (uint32_t)ntiles, bg[0], bg[1], bg[2], image, chw, nullptr, nullptr);
     } else {
-    if (finalT)
-        hipLaunchKernelGGL((k_blend<TW, TH, PPT, true>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W, H,
-                           tiles_x, bg[0], bg[1], bg[2], image, finalT, nproc);
-    else
-        hipLaunchKernelGGL((k_blend<TW, TH, PPT, false>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W,
-                           H, tiles_x, bg[0], bg[1], bg[2], image, nullptr, nullptr);
+        if (finalT)
+            hipLaunchKernelGGL((k_blend<TW, TH, PPT, true>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W,
+                               H, tiles_x, bg[0], bg[1], bg[2], image, chw, finalT, nproc);
+        else
+            hipLaunchKernelGGL((k_blend<TW, TH, PPT, false>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec,
+                               W, H, tiles_x, bg[0], bg[1], bg[2], image, chw, nullptr, nullptr);
     }
 }
 
+// chw: write the image as [3][H][W] instead of [H][W][3]
 bool launch_blend(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
-                  int W, int H, int tiles_x, const float *bg, float *image, float *finalT, uint32_t *nproc,
+                  int W, int H, int tiles_x, const float *bg, float *image, int chw, float *finalT, uint32_t *nproc,
                   hipStream_t st) {
 #define RECOGS_BLEND_CASE(A, B, P)                                                                         \
     if (tw == A && th == B && ppt == P) {                                                                  \
-        blend_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, bg, image, finalT, nproc);        \
+        blend_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, bg, image, chw, finalT, nproc);   \
         return true;                                                                                       \
     }
     RECOGS_BLEND_CASE(16, 16, 1) RECOGS_BLEND_CASE(16, 16, 2) RECOGS_BLEND_CASE(16, 16, 4)

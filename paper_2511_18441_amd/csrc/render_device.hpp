@@ -148,6 +148,21 @@ struct BlendStage {
     BlendRec r[kBlendBatch];
 };
 
+// Final colour of one pixel (index p = y W + x of an image of HW pixels): HWC, or CHW
+// with chw (the two layouts of Sec. 4.2).
+__device__ __forceinline__ void store_pixel(float *__restrict__ image, int64_t p, int64_t HW, int chw, float r, float g,
+                                            float b) {
+    if (chw) {
+        image[p] = r;
+        image[HW + p] = g;
+        image[2 * HW + p] = b;
+    } else {
+        image[p * 3 + 0] = r;
+        image[p * 3 + 1] = g;
+        image[p * 3 + 2] = b;
+    }
+}
+
 // One splat record applied to the PPT pixels of a thread (eq. 3, front to back).
 // `idx` is the record's 1-based position in its tile list (kept, with STATE, as the
 // count up to the last blended entry).
@@ -189,8 +204,8 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
 template <int TW, int TH, int PPT, bool STATE>
 __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *__restrict__ vals,
                                            const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
-                                           float bg1, float bg2, float *__restrict__ image, float *__restrict__ finalT,
-                                           uint32_t *__restrict__ nproc, BlendStage &sm) {
+                                           float bg1, float bg2, float *__restrict__ image, int chw,
+                                           float *__restrict__ finalT, uint32_t *__restrict__ nproc, BlendStage &sm) {
 #pragma clang fp contract(off)
     using Map = TileMap<TW, TH, PPT>;
     constexpr int NT = Map::NT;
@@ -271,9 +286,8 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
         if (px < W && py < H) {
             const int64_t p = (int64_t)py * W + px;
             const float Tf = fabsf(T[j]);
-            image[p * 3 + 0] = __builtin_fmaf(Tf, bg0, C0[j]);
-            image[p * 3 + 1] = __builtin_fmaf(Tf, bg1, C1[j]);
-            image[p * 3 + 2] = __builtin_fmaf(Tf, bg2, C2[j]);
+            store_pixel(image, p, (int64_t)W * H, chw, __builtin_fmaf(Tf, bg0, C0[j]), __builtin_fmaf(Tf, bg1, C1[j]),
+                        __builtin_fmaf(Tf, bg2, C2[j]));
             if constexpr (STATE) {
                 finalT[p] = Tf;
                 nproc[p] = last[j];
@@ -293,7 +307,7 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
 template <int TW, int TH, int PPT, bool STATE>
 __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const uint32_t *__restrict__ vals,
                                              const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
-                                             float bg1, float bg2, float *__restrict__ image,
+                                             float bg1, float bg2, float *__restrict__ image, int chw,
                                              float *__restrict__ finalT, uint32_t *__restrict__ nproc,
                                              BlendRec *sm /* [64] */) {
 #pragma clang fp contract(off)
@@ -367,9 +381,8 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
         if (px < W && py < H) {
             const int64_t p = (int64_t)py * W + px;
             const float Tf = fabsf(T[j]);
-            image[p * 3 + 0] = __builtin_fmaf(Tf, bg0, C0[j]);
-            image[p * 3 + 1] = __builtin_fmaf(Tf, bg1, C1[j]);
-            image[p * 3 + 2] = __builtin_fmaf(Tf, bg2, C2[j]);
+            store_pixel(image, p, (int64_t)W * H, chw, __builtin_fmaf(Tf, bg0, C0[j]), __builtin_fmaf(Tf, bg1, C1[j]),
+                        __builtin_fmaf(Tf, bg2, C2[j]));
             if constexpr (STATE) {
                 finalT[p] = Tf;
                 nproc[p] = last[j];

@@ -30,7 +30,7 @@ size_t sort_count_words(uint64_t K_max);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
-                  float *, float *, uint32_t *, hipStream_t);
+                  float *, int, float *, uint32_t *, hipStream_t);
 int sort_passes(int total_bits);
 int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
                             uint32_t *, hipStream_t);
@@ -288,6 +288,7 @@ recogs_status check_opts(const recogs_render_opts *o) {
         return fail(RECOGS_ERR_INVALID, "profile_stages %d not 0, 1 or 2", o->profile_stages);
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
         return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
+    if (o->output_chw != 0 && o->output_chw != 1) return fail(RECOGS_ERR_INVALID, "output_chw %d not 0 or 1", o->output_chw);
     const bool any = o->mask || o->M || o->b;
     if (any && !(o->mask && o->M && o->b)) return fail(RECOGS_ERR_INVALID, "fused recolour needs mask, M and b together");
     return RECOGS_OK;
@@ -356,7 +357,7 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     ws->sorted_in_alt = alt;
     if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0,
-                      at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, cd.tiles_x, opts->bg, image,
+                      at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, cd.tiles_x, opts->bg, image, opts->output_chw,
                       opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
                       opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
@@ -573,7 +574,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     ws->sorted_in_alt = alt;
     if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0, rec, cam->width,
-                      cam->height, cd.tiles_x, opts->bg, image,
+                      cam->height, cd.tiles_x, opts->bg, image, opts->output_chw,
                       opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
                       opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
@@ -592,6 +593,7 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
     if ((s = check_opts(opts)) != RECOGS_OK) return s;
     if ((s = check_ws(ws, scene, cam, opts)) != RECOGS_OK) return s;
     if (!opts->keep_backward_state) return fail(RECOGS_ERR_INVALID, "render must keep backward state for the backward");
+    if (opts->output_chw) return fail(RECOGS_ERR_UNSUPPORTED, "the backward takes an HWC render (output_chw 0)");
     if (ws->last_n != scene->n) return fail(RECOGS_ERR_INVALID, "workspace holds a render of %d Gaussians, scene has %lld", ws->last_n, (long long)scene->n);
     if (ws->num_keys < 0)
         return fail(RECOGS_ERR_INVALID, "after a graph_mode render, call recogs_workspace_readback before the backward");

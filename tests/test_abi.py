@@ -93,6 +93,10 @@ def test_host_argument_errors_before_any_launch(R):
     # unsupported tile shape / pixels per thread
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 8), 1), ws, 1, 0) == -3
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 3), ws, 1, 0) == -3
+    # output layout flag outside {0, 1}
+    o_bad = B.opts_struct((16, 16), 1)
+    o_bad.output_chw = 2
+    assert status(B.recogs_render, sc, cam, o_bad, ws, 1, 0) == -1
     # invalid scene fields
     bad = B.Scene()
     bad.n, bad.stride, bad.sh_degree = 10, 5, 0

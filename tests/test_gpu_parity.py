@@ -249,6 +249,29 @@ def test_tile_shape_ppt_and_sort_mode_do_not_change_bits(R):
         assert np.array_equal(img, base), (tile, "keep_backward")
 
 
+def test_chw_output_is_the_hwc_image_transposed(R):
+    """The CHW layout (the rasteriser's original one, Sec. 4.2) holds the same bits as the
+    HWC image, in the region form, the tile form and with the backward state kept; the
+    backward refuses a CHW render."""
+    import torch
+    w = synth.make_mid(n=100_000)
+    d = R.DeviceScene(w.scene)
+    cam = w.view.camera
+    for tile, ppt, keep in [((32, 32), 1, False), ((16, 16), 2, True), ((32, 8), 2, False), ((8, 8), 4, True)]:
+        ws = R.DeviceWorkspace(d.n, cam.width, cam.height, tile)
+        hwc = R.render(d, cam, ws, tile, ppt, (0.1, 0.2, 0.3), keep_backward=keep).clone()
+        chw = R.render(d, cam, ws, tile, ppt, (0.1, 0.2, 0.3), keep_backward=keep, chw=True)
+        assert chw.shape == (3, cam.height, cam.width)
+        assert torch.equal(chw.permute(1, 2, 0), hwc), (tile, ppt)
+    o = R.opts_struct((8, 8), 4, (0.1, 0.2, 0.3), keep_backward=True, chw=True)
+    n = d.n
+    buf = [torch.empty(n, device="cuda"), torch.empty(3 * n, device="cuda"), torch.empty(9, device="cuda")]
+    with pytest.raises(R.RecogsError) as e:
+        R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, chw.data_ptr(), chw.data_ptr(),
+                                 buf[0].data_ptr(), buf[1].data_ptr(), buf[2].data_ptr())
+    assert e.value.status == -3
+
+
 def test_hue_permutation_exact_and_identity_exact(R):
     w = synth.make_mid(n=100_000)
     n = w.scene.n
