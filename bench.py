@@ -425,6 +425,9 @@ def main():
     ap.add_argument("--diff-tile", type=int, nargs=2, default=None,
                     help="tile shape of the differentiation form when run alone (--only-form diff)")
     ap.add_argument("--diff-ppt", type=int, default=DIFF_PPT)
+    ap.add_argument("--layout", choices=["hwc", "chw"], default="hwc", help="output layout of the timed frame")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison frames (16x16 tiles, the other output layout)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
     ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff"], default=None,
@@ -458,7 +461,7 @@ def main():
         return
     log(f"bench: generating 1M-Gaussian scene ({args.storage})")
     w = synth.make_precision(storage=args.storage)
-    s = Single(R, w, dev, tile, args.ppt)
+    s = Single(R, w, dev, tile, args.ppt, chw=args.layout == "chw")
     log(f"bench: warmup {args.warmup}, timing {args.steps} frames")
     m = s.measure(args.steps, args.warmup)
     ms = m["ms"]
@@ -497,7 +500,7 @@ def main():
         "config": {"workload": f"1M Gaussians SH deg 3, 1920x1080, {tw}x{th} tiles, {args.storage} storage; "
                                "recolor(selected) + render", "gaussians": s.n, "width": s.cam.width,
                    "height": s.cam.height, "sh_degree": 3, "storage": args.storage, "tile": f"{tw}x{th}",
-                   "px_per_thread": args.ppt},
+                   "px_per_thread": args.ppt, "layout": args.layout},
         "gaussians_per_s": round(fps * s.n, 1),
         "frame_hbm_roofline": {"alg_bytes_per_frame": int(tot_bytes),
                                "GBps": round(tot_bytes * fps / 1e9, 1),
@@ -513,7 +516,7 @@ def main():
         "counts": st,
     }
     del s
-    if tuple(tile) != (16, 16):
+    if tuple(tile) != (16, 16) and not args.no_compare:
         # the same frame at the 16x16 tiles of the 3DGS rasteriser (same images, bit for bit)
         log("bench: the same frame at 16x16 tiles, 1 px/thread")
         s16 = Single(R, w, dev, (16, 16), 1)
@@ -522,13 +525,16 @@ def main():
                                  "ms_per_step": round(m16["ms"], 4), "blend_ms": round(m16["blend_ms_timed"], 4),
                                  "stages_ms": {k: round(v, 4) for k, v in m16["stages"].items()}}
         del s16
-    # the paper's layout experiment (Sec. 4.2): the same frame writing CHW instead of HWC
-    log("bench: the same frame with CHW output")
-    sc = Single(R, w, dev, tile, args.ppt, chw=True)
-    mc = sc.measure(args.steps, args.warmup)
-    res["output_layout"] = {"hwc": {"frames_per_s": round(fps, 2), "blend_ms": round(m["blend_ms_timed"], 4)},
-                            "chw": {"frames_per_s": round(1000.0 / mc["ms"], 2), "blend_ms": round(mc["blend_ms_timed"], 4)}}
-    del sc
+    if not args.no_compare:
+        # the paper's layout experiment (Sec. 4.2): the same frame in the other output layout
+        other = "hwc" if args.layout == "chw" else "chw"
+        log(f"bench: the same frame with {other.upper()} output")
+        sc = Single(R, w, dev, tile, args.ppt, chw=other == "chw")
+        mc = sc.measure(args.steps, args.warmup)
+        res["output_layout"] = {args.layout: {"frames_per_s": round(fps, 2), "blend_ms": round(m["blend_ms_timed"], 4)},
+                                other: {"frames_per_s": round(1000.0 / mc["ms"], 2),
+                                        "blend_ms": round(mc["blend_ms_timed"], 4)}}
+        del sc
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
