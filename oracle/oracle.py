@@ -285,6 +285,31 @@ def loss_l2_grad(y, target, count: Optional[int] = None) -> np.ndarray:
     return 2.0 * (y - np.asarray(target, np.float64)) / count
 
 
+def loss_l1(y, target) -> float:
+    """L1 = mean over all pixels and channels of |y - t| (the L1 term of eq. 7)."""
+    return float(np.mean(np.abs(np.asarray(y, np.float64) - np.asarray(target, np.float64))))
+
+
+def loss_l1_grad(y, target, count: Optional[int] = None) -> np.ndarray:
+    """dL1/dy = sign(y - t) / count (Sec. 4.1), with sign(0) = 0."""
+    y = np.asarray(y, np.float64)
+    count = y.size if count is None else count
+    return np.sign(y - np.asarray(target, np.float64)) / count
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15):
+    """One Adam step (the optimiser that moves the SH coefficients, Sec. 3.3 / 4.1):
+    m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2, and with the bias corrections
+    m^ = m / (1 - b1^step), v^ = v / (1 - b2^step): p <- p - lr m^ / (sqrt(v^) + eps).
+    step counts from 1. Returns (param, m, v), all float64."""
+    p, g = np.asarray(param, np.float64), np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
 @dataclass
 class Grads:
     dsigma: np.ndarray   # (n,)
@@ -317,3 +342,31 @@ def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0), windows=None) -
         lib().orc_backward_windows(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), _p(Mv), _p(g),
                                    len(win), win.ctypes.data_as(ctypes.c_void_p), _p(ds), _p(dr), _p(dc), _p(dM))
     return Grads(ds, dr, dc, dM.reshape(3, 3))
+
+
+def sh_grad(scene, cam, proj: Projection, grads: Grads, M=None) -> np.ndarray:
+    """dL/dC for every SH coefficient, planes [3 (deg+1)^2][n] (plane = k * 3 + c, the
+    scene's layout). The colour of eq. 2 is linear in the coefficients,
+    f_c = sum_k C_{k,c} Y_k(d) with d = (mu - campos) / |mu - campos|, so
+    dL/dC_{k,c} = Y_k(d) g_c, where g is the gradient at f: the colour gradient of eq. 8
+    masked where max(0, .) clamps and, for Gaussians the fused recolour selected (they
+    display M (f + 1/2) + b), multiplied by M^T. Gaussians that reach no pixel get 0."""
+    n = proj.f.shape[0]
+    deg = int(scene.sh_degree)
+    K = (deg + 1) ** 2
+    Mv = np.eye(3) if M is None else np.asarray(M, np.float64).reshape(3, 3)
+    R = np.asarray(cam.R, np.float32).astype(np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float32).astype(np.float64)
+    campos = -R.T @ t
+    means = np.asarray(scene.means, np.float32).astype(np.float64)
+    out = np.zeros((3 * K, n))
+    for i in range(n):
+        gh = np.array([grads.drgb[i, c] if proj.f[i, P["pr"] + c] > 0 else 0.0 for c in range(3)])
+        if not gh.any():
+            continue
+        g = Mv.T @ gh if proj.i[i, I["sel"]] else gh
+        d = means[:, i] - campos
+        Y = sh_basis(deg, d / np.linalg.norm(d))
+        for k in range(K):
+            out[k * 3:(k + 1) * 3, i] = Y[k] * g
+    return out

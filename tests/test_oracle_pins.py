@@ -537,3 +537,76 @@ def test_loss_gradient_definition(orc):
     y2[1, 2, 0] += h
     fd = (orc.loss_l2(y2, t) - orc.loss_l2(y, t)) / h
     assert abs(fd - g[1, 2, 0]) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# background optimiser pieces (Sec. 3.3 / 4.1): L1 term of eq. 7, gradients of every
+# SH band (eq. 2 is linear in the coefficients), the Adam step
+# ---------------------------------------------------------------------------
+def test_sh_grad_matches_central_differences(orc):
+    """dL/dC_{k,c} for bands 1..3 (and DC) against central differences of the oracle's
+    own forward, with the fused recolour on half of the Gaussians (the M^T chain)."""
+    w = synth.make_diff_fd(n=20000, n_sub=96, size=24)
+    sc, cam = w.scene, w.view.camera
+    rng = np.random.default_rng(19)
+    mask = (rng.random(sc.n) < 0.5).astype(np.uint8)
+    M = (np.eye(3) + 0.2 * rng.standard_normal((3, 3))).astype(np.float64)
+    b = np.zeros(3)
+    g = rng.standard_normal((cam.height, cam.width, 3))
+    L0, r0, pr0 = _loss_and_state(orc, sc, cam, mask, M, b, g)
+    gr = orc.backward(pr0, g, M=M)
+    dsh = orc.sh_grad(sc, cam, pr0, gr, M=M)
+    K = (sc.sh_degree + 1) ** 2
+    assert dsh.shape == (3 * K, sc.n)
+    # the DC planes are the DC gradient of eq. 8's chain
+    np.testing.assert_allclose(dsh[0:3], gr.dc0, rtol=1e-12, atol=1e-300)
+
+    def same_decisions(ra, rb):
+        return np.array_equal(ra.nblend, rb.nblend) and np.array_equal(ra.last, rb.last)
+
+    h = 1e-6
+    checked = 0
+    used = np.unique(r0.last[r0.last >= 0])
+    for i in used[:10]:
+        for k in (1, 3, 6, 11, 15):
+            c = int(rng.integers(0, 3))
+            def perturbed(delta):
+                sh = sc.sh.astype(np.float64).copy()
+                sh[k * 3 + c, i] += delta
+                s2 = synth.Scene(sc.means, sc.log_scales, sc.quats, sc.opacity.astype(np.float64), sh, sc.sh_degree)
+                return _scene64_loss(orc, s2, cam, mask, M, b, g)
+            (Lp, rp), (Lm, rm) = perturbed(h), perturbed(-h)
+            if not same_decisions(rp, rm):
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - dsh[k * 3 + c, i]) <= 1e-5 * max(1.0, abs(fd)), (i, k, c, fd, dsh[k * 3 + c, i])
+            checked += 1
+    assert checked >= 30
+
+
+def test_loss_l1_gradient_definition(orc):
+    y = np.random.default_rng(2).random((4, 5, 3))
+    t = np.random.default_rng(3).random((4, 5, 3))
+    g = orc.loss_l1_grad(y, t)
+    h = 1e-7
+    for idx in [(1, 2, 0), (3, 4, 2), (0, 0, 1)]:
+        y2 = y.copy()
+        y2[idx] += h
+        fd = (orc.loss_l1(y2, t) - orc.loss_l1(y, t)) / h
+        assert abs(fd - g[idx]) < 1e-6
+    assert orc.loss_l1_grad(np.ones(4), np.ones(4)).tolist() == [0.0] * 4   # sign(0) = 0
+
+
+def test_adam_closed_forms(orc):
+    """With a constant gradient the bias-corrected moments equal g and g^2 at every
+    step, so each step moves a coefficient by lr g / (|g| + eps): the first step, and
+    t steps in a row, in closed form."""
+    rng = np.random.default_rng(5)
+    p0 = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    lr, eps = 0.01, 1e-8
+    p, m, v = orc.adam_step(p0, g, np.zeros(50), np.zeros(50), 1, lr, eps=eps)
+    np.testing.assert_allclose(p, p0 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    for step in range(2, 8):
+        p, m, v = orc.adam_step(p, g, m, v, step, lr, eps=eps)
+    np.testing.assert_allclose(p, p0 - 7 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-13)
