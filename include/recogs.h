@@ -250,6 +250,41 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
+/* ---- background optimiser (Sec. 3.3, 4.1) -------------------------------------- */
+
+/* The backward of recogs_render_backward with the gradient of every SH coefficient
+ * instead of the DC term only: the optimiser of Sec. 3.3 refits the SH coefficients
+ * (Sec. 4.1 keeps only dL/dC_l^m of the rasteriser's gradients, eq. 8). The colour of
+ * eq. 2 is linear in the coefficients, so dL/dC_{k,c} = Y_k(d) g_c, with d the view
+ * direction of the Gaussian's centre and g the colour gradient through the clamp and,
+ * for Gaussians the fused recolour selected, through M (g = M^T gh).
+ * dL_dsh: device float [3 (sh_degree + 1)^2][scene.stride], plane k * 3 + c: the scene's
+ * SH layout, so an optimiser can step the coefficient planes with it directly. Entries
+ * 0..n-1 of every plane are written (zero for Gaussians that reach no pixel); the
+ * padding entries n..stride-1 are left as they are.
+ * Everything else (arguments, requirements, determinism, errors) as for
+ * recogs_render_backward; the DC planes equal its dL_dsh_dc bit for bit. */
+recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_camera *cam,
+                                        const recogs_render_opts *opts, const recogs_workspace *ws,
+                                        const float *image, const float *dL_dimage, float *dL_dopacity,
+                                        float *dL_dsh, float *dL_dM, hipStream_t stream);
+
+/* L1 term of the loss of eq. 7, with the gradient Sec. 4.1 writes out:
+ * loss (device float, overwritten) = scale * sum |y - t| and
+ * dL_dimage = scale * sign(y - t) (sign(0) = 0), over `count` floats; scale = 1 / count
+ * gives the mean. Device pointers of any alignment. INVALID: count < 0, NULL pointer. */
+recogs_status recogs_loss_l1(const float *image, const float *target, int64_t count, float scale,
+                             float *dL_dimage, float *loss, hipStream_t stream);
+
+/* One Adam step over `count` float parameters (the optimiser that moves the SH
+ * coefficients toward the edited views, Sec. 3.3): m <- beta1 m + (1 - beta1) g,
+ * v <- beta2 v + (1 - beta2) g^2, param <- param - lr (m / c1) / (sqrt(v / c2) + eps) with
+ * c1 = 1 - beta1^step, c2 = 1 - beta2^step. param, m, v are updated in place (device,
+ * caller-owned; m and v start at zero), grad is read; step counts from 1.
+ * INVALID: count < 0, step < 1, beta outside [0, 1), eps <= 0, NULL pointer. */
+recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr,
+                               float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
+
 /* ---- batched form ------------------------------------------------------------ */
 
 /* One render of a batch (host struct): a scene, a camera, an optional fused recolour

@@ -26,7 +26,8 @@ STORAGE_CODE = {"f32": RECOGS_F32, "f16": RECOGS_F16, "bf16": RECOGS_BF16}
 ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_workspace_readback",
                 "recogs_workspace_profile_flush",
                 "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
-                "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_last_error")
+                "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
+                "recogs_loss_l1", "recogs_adam_step", "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -104,6 +105,10 @@ def lib():
         L.recogs_render.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp]
         L.recogs_render_backward.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp, vp]
         L.recogs_loss_l2.argtypes = [vp, vp, i64, f32, vp, vp, vp]
+        L.recogs_render_backward_sh.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp,
+                                                vp]
+        L.recogs_loss_l1.argtypes = [vp, vp, i64, f32, vp, vp, vp]
+        L.recogs_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
         L.recogs_last_error.restype = ctypes.c_char_p
         for name in ENTRY_POINTS:
             if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release"):
@@ -180,6 +185,23 @@ def recogs_render_backward(scene: Scene, cam: Camera, opts: RenderOpts, ws: Work
 def recogs_loss_l2(image, target, count, scale, dL_dimage, loss, stream=None):
     return _check("recogs_loss_l2", lib().recogs_loss_l2(image, target, count, float(scale), dL_dimage, loss,
                                                          _stream(stream)))
+
+
+def recogs_render_backward_sh(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
+                              dL_dopacity, dL_dsh, dL_dM, stream=None):
+    return _check("recogs_render_backward_sh", lib().recogs_render_backward_sh(
+        ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage, dL_dopacity,
+        dL_dsh, dL_dM, _stream(stream)))
+
+
+def recogs_loss_l1(image, target, count, scale, dL_dimage, loss, stream=None):
+    return _check("recogs_loss_l1", lib().recogs_loss_l1(image, target, count, float(scale), dL_dimage, loss,
+                                                         _stream(stream)))
+
+
+def recogs_adam_step(param, grad, m, v, count, lr, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
+    return _check("recogs_adam_step", lib().recogs_adam_step(param, grad, m, v, count, float(lr), float(beta1),
+                                                             float(beta2), float(eps), int(step), _stream(stream)))
 
 
 def recogs_last_error() -> str:

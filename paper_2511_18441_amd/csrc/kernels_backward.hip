@@ -166,18 +166,23 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
     }
 }
 
-// Per Gaussian: dL/dsigma, and the chain through the clamp, the fused recolour and
-// the DC term: gh = dL/drgb where the pre-clamp colour > 0;
-//   selected:   dL/dC0 = Y00 M^T gh, dL/dM += gh (f + 1/2)^T;  unselected: dL/dC0 = Y00 gh.
+// Per Gaussian: dL/dsigma, and the chain through the clamp and the fused recolour to
+// the colour before them: gh = dL/drgb where the pre-clamp colour > 0, g = M^T gh for
+// selected Gaussians (dL/dM += gh (f + 1/2)^T) and g = gh otherwise. The colour of
+// eq. 2 is linear in the SH coefficients, so dL/dC_{k,c} = Y_k(d) g_c:
+//   DEG < 0:  the DC term only, out[c][n] = Y00 g_c;
+//   DEG >= 0: every coefficient, out[(k * 3 + c) * stride + i] = Y_k(d) g_c (the scene's
+//             plane layout), d the view direction.
 // dL/dM is reduced without atomics: each workgroup writes its 9 partial sums to
 // part[block][9] and k_dm_reduce adds them in a fixed order (deterministic).
+template <int DEG>
 __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ gk, const uint32_t *__restrict__ koff,
                                                      const float4 *__restrict__ bwd, const uint32_t *__restrict__ count,
                                                      int64_t n, const float *__restrict__ M, float *__restrict__ dop,
-                                                     float *__restrict__ ddc, float *__restrict__ part) {
+                                                     float *__restrict__ out, float *__restrict__ part,
+                                                     const float *__restrict__ means, int64_t stride, CamDev cam) {
     __shared__ float s_dm[4][9];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float m[9];
     bool sel = false;
     float gh[3] = {0.f, 0.f, 0.f}, f[3] = {0.f, 0.f, 0.f};
     if (i < n) {
@@ -199,14 +204,30 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         gh[2] = (flags & 4u) ? a.w : 0.f;
         sel = (flags & 8u) != 0;
         dop[i] = a.x;
+        float g[3];
         if (sel) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) m[k] = M[k];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ddc[c * n + i] = kSH0 * (m[c] * gh[0] + m[3 + c] * gh[1] + m[6 + c] * gh[2]);
+            for (int c = 0; c < 3; ++c) g[c] = M[c] * gh[0] + M[3 + c] * gh[1] + M[6 + c] * gh[2];
         } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ddc[c * n + i] = kSH0 * gh[c];
+            for (int c = 0; c < 3; ++c) g[c] = gh[c];
+        }
+        if constexpr (DEG < 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[c * n + i] = kSH0 * g[c];
+        } else {
+            constexpr int NC = (DEG + 1) * (DEG + 1);
+            float Y[16];
+            if (c > 0) {
+                view_basis<DEG>(cam, means[i], means[stride + i], means[2 * stride + i], Y);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) Y[k] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) out[(int64_t)(k * 3 + c) * stride + i] = Y[k] * g[c];
         }
     }
     if (!M) return;  // uniform: no recolour, no dL/dM
@@ -306,12 +327,26 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
     return false;
 }
 
-// part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n)
+// part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n).
+// deg < 0: out = dL/dC0 [3][n]; deg 0..3: out = dL/dSH [3 (deg + 1)^2][stride], which needs
+// the centres (means, plane stride) and the camera.
 void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bwd, const uint32_t *count, int64_t n,
-                        const float *M, float *dop, float *ddc, float *dM, float *part, hipStream_t st) {
+                        const float *M, float *dop, float *out, float *dM, float *part, int deg, const float *means,
+                        int64_t stride, const CamDev &cam, hipStream_t st) {
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
-    if (n > 0)
-        hipLaunchKernelGGL(k_grad_finish, dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, ddc, part);
+    if (n > 0) {
+#define RECOGS_FIN(D)                                                                                             \
+    hipLaunchKernelGGL(k_grad_finish<D>, dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, out, part, \
+                       means, stride, cam)
+        switch (deg) {
+        case 0: RECOGS_FIN(0); break;
+        case 1: RECOGS_FIN(1); break;
+        case 2: RECOGS_FIN(2); break;
+        case 3: RECOGS_FIN(3); break;
+        default: RECOGS_FIN(-1); break;
+        }
+#undef RECOGS_FIN
+    }
     if (M && n > 0) hipLaunchKernelGGL(k_dm_reduce, dim3(1), dim3(256), 0, st, part, blocks, dM);
     else launch_fill_u32((uint32_t *)dM, 0u, 9, st);
 }

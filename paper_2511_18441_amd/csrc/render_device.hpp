@@ -26,6 +26,16 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *Y) {
     }
 }
 
+// The basis at the view direction d = (mu - campos) / |mu - campos| of a centre mu: the
+// forward colour and the SH gradients of the backward use these same values.
+template <int DEG>
+__device__ __forceinline__ void view_basis(const CamDev &cam, float mx, float my, float mz, float *Y) {
+    float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    sh_basis<DEG>(dx, dy, dz, Y);
+}
+
 // ---------------------------------------------------------------------------
 // Preprocess: one thread per Gaussian.
 //   m = R mu + t (compensated); cull depth <= znear.
@@ -89,12 +99,9 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev 
                         cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
                         rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
                         // colour (eq. 2) at the view direction of the centre
-                        float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
-                        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-                        dx *= inv; dy *= inv; dz *= inv;
                         constexpr int NC = (DEG + 1) * (DEG + 1);
                         float Y[16];
-                        sh_basis<DEG>(dx, dy, dz, Y);
+                        view_basis<DEG>(cam, mx, my, mz, Y);
                         float f[3];
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {

@@ -39,8 +39,10 @@ int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uin
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
-                        float *, float *, float *, hipStream_t);
+                        float *, float *, float *, int, const float *, int64_t, const CamDev &, hipStream_t);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
+void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
+void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
@@ -583,9 +585,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     return tm.finish(ws, 8);
 }
 
-recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
-                                     const recogs_workspace *ws, const float *image, const float *dL_dimage,
-                                     float *dL_dopacity, float *dL_dsh_dc, float *dL_dM, hipStream_t stream) {
+// The backward of both entry points: out = dL/dC0 [3][n], or with all_bands
+// dL/dSH [3 (deg + 1)^2][scene stride].
+static recogs_status backward_impl(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
+                                   const recogs_workspace *ws, const float *image, const float *dL_dimage,
+                                   float *dL_dopacity, float *out, float *dL_dM, bool all_bands, hipStream_t stream) {
     g_err[0] = 0;
     recogs_status s;
     if ((s = check_scene(scene)) != RECOGS_OK) return s;
@@ -598,7 +602,7 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
     if (ws->num_keys < 0)
         return fail(RECOGS_ERR_INVALID, "after a graph_mode render, call recogs_workspace_readback before the backward");
     if (ws->num_keys > ws->key_capacity) return fail(RECOGS_ERR_INVALID, "the render overflowed its key capacity");
-    if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || !dL_dsh_dc)))
+    if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || !out)))
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
     const int64_t n = scene->n;
     const int ntiles = ws->tiles_x * ws->tiles_y;
@@ -614,9 +618,24 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
                               ws->tiles_x, image, dL_dimage, at<uint32_t>(ws, ws->off_nproc), gk, stream))
             return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
     }
-    launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity,
-                       dL_dsh_dc, dL_dM, at<float>(ws, ws->off_gpart), stream);
+    const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
+    launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, out,
+                       dL_dM, at<float>(ws, ws->off_gpart), all_bands ? scene->sh_degree : -1, scene->means,
+                       scene->stride, cd, stream);
     return hip_check("backward");
+}
+
+recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
+                                     const recogs_workspace *ws, const float *image, const float *dL_dimage,
+                                     float *dL_dopacity, float *dL_dsh_dc, float *dL_dM, hipStream_t stream) {
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh_dc, dL_dM, false, stream);
+}
+
+recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_camera *cam,
+                                        const recogs_render_opts *opts, const recogs_workspace *ws, const float *image,
+                                        const float *dL_dimage, float *dL_dopacity, float *dL_dsh, float *dL_dM,
+                                        hipStream_t stream) {
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh, dL_dM, true, stream);
 }
 
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,
@@ -627,6 +646,29 @@ recogs_status recogs_loss_l2(const float *image, const float *target, int64_t co
     launch_fill_u32((uint32_t *)loss, 0u, 1, stream);
     launch_loss_l2(image, target, count, scale, dL_dimage, loss, stream);
     return hip_check("loss_l2");
+}
+
+recogs_status recogs_loss_l1(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,
+                             float *loss, hipStream_t stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(RECOGS_ERR_INVALID, "count < 0");
+    if (!loss || (count > 0 && (!image || !target || !dL_dimage))) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    launch_fill_u32((uint32_t *)loss, 0u, 1, stream);
+    launch_loss_l1(image, target, count, scale, dL_dimage, loss, stream);
+    return hip_check("loss_l1");
+}
+
+recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,
+                               float beta2, float eps, int32_t step, hipStream_t stream) {
+    g_err[0] = 0;
+    if (count < 0) return fail(RECOGS_ERR_INVALID, "count < 0");
+    if (step < 1) return fail(RECOGS_ERR_INVALID, "step %d < 1", step);
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(RECOGS_ERR_INVALID, "beta1, beta2 must lie in [0, 1) and eps > 0");
+    if (count > 0 && (!param || !grad || !m || !v)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
+    launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, (float)c1, (float)c2, stream);
+    return hip_check("adam_step");
 }
 
 }  // extern "C"

@@ -123,6 +123,12 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(R.recogs_workspace_init, ws, 257, need, 100, 64, 64, 16, 16, 1000) == -1
     # loss
     assert status(B.recogs_loss_l2, 0, 0, 10, 1.0, 0, 0, 0) == -1
+    assert status(B.recogs_loss_l1, 0, 0, 10, 1.0, 0, 0, 0) == -1
+    assert status(B.recogs_loss_l1, 0, 0, -1, 1.0, 0, 0, 0) == -1
+    # (param, grad, m, v, count, lr, beta1, beta2, eps, step, stream)
+    assert status(B.recogs_adam_step, 0, 0, 0, 0, 10, 1e-3, 0.9, 0.999, 1e-15, 1, 0) == -1  # NULL arrays
+    assert status(B.recogs_adam_step, 0, 0, 0, 0, 0, 1e-3, 0.9, 0.999, 1e-15, 0, 0) == -1   # step counts from 1
+    assert status(B.recogs_adam_step, 0, 0, 0, 0, 0, 1e-3, 1.0, 0.999, 1e-15, 1, 0) == -1   # beta outside [0, 1)
     # batch: empty, and mixed storage
     views = (B.BatchView * 2)()
     assert R.recogs_batch_workspace_bytes(views, 0, 16, 16, 10) == 0

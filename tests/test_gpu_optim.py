@@ -1,0 +1,118 @@
+"""Pieces of the background optimiser (Sec. 3.3 / 4.1) through the C ABI: the gradient
+of every SH coefficient, the L1 term of eq. 7 and the Adam step, against the FP64
+oracle (pinned on the CPU by central differences and closed forms); then a few steps of
+SH-only refitting toward a recoloured target, which must lower the loss."""
+import numpy as np
+import pytest
+
+import synth
+from tests.test_gpu_backward import _close, _setup, _wfd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2511_18441_amd as R
+    return R
+
+
+@pytest.mark.parametrize("tile,ppt", [((16, 16), 1), ((32, 16), 1)])
+def test_backward_sh_vs_oracle(R, orc, tile, ppt):
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    pr = orc.project(w.scene, cam, tile, mask=mask, M=M.astype(np.float64), b=b.astype(np.float64))
+    ref = orc.render_image(pr, brute=True)
+    g = np.where((ref.slack > 0)[..., None], 0.0, g).astype(np.float32)
+    ws = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
+    img = R.render(d, cam, ws, tile, ppt, mask=tm, M=tM, b=tb, keep_backward=True)
+    gt = torch.from_numpy(g).cuda()
+    n, K = d.n, (w.scene.sh_degree + 1) ** 2
+    o = R.opts_struct(tile, ppt, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    dop, dsh, dM = torch.empty(n, device="cuda"), torch.full((3 * K, d.stride), 7.0, device="cuda"), torch.empty(9, device="cuda")
+    R.recogs_render_backward_sh(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
+                                dop.data_ptr(), dsh.data_ptr(), dM.data_ptr())
+    dop2, ddc, dM2 = torch.empty(n, device="cuda"), torch.empty((3, n), device="cuda"), torch.empty(9, device="cuda")
+    R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
+                             dop2.data_ptr(), ddc.data_ptr(), dM2.data_ptr())
+    torch.cuda.synchronize()
+    # the DC planes, the opacity and M gradients are those of recogs_render_backward, bit for bit
+    assert torch.equal(dsh[0:3, :n], ddc) and torch.equal(dop, dop2) and torch.equal(dM, dM2)
+    gr = orc.backward(pr, g, M=M.astype(np.float64))
+    ref_sh = orc.sh_grad(w.scene, cam, pr, gr, M=M.astype(np.float64))
+    got = dsh[:, :n].cpu().numpy().astype(np.float64)
+    assert np.isfinite(got).all()
+    e = _close(got, ref_sh, 2e-3, "dL/dSH")
+    print(f"{tile} ppt {ppt}: dL/dSH rel max err {e:.2e}")
+
+
+def test_loss_l1_vs_oracle(R, orc):
+    import torch
+    y = synth.random_image(7, (72, 128, 3))
+    t = synth.random_image(8, (72, 128, 3))
+    ty, tt = torch.from_numpy(y).cuda().reshape(-1), torch.from_numpy(t).cuda().reshape(-1)
+    cnt = y.size
+    loss = torch.empty(1, device="cuda")
+    for off, m in ((0, cnt), (1, cnt - 2)):   # 16-byte aligned, then one float in with a ragged count
+        dl = torch.zeros(cnt, device="cuda")
+        R.recogs_loss_l1(ty[off:].data_ptr(), tt[off:].data_ptr(), m, 1.0 / m, dl[off:].data_ptr(), loss.data_ptr())
+        torch.cuda.synchronize()
+        y1, t1 = y.reshape(-1)[off:off + m], t.reshape(-1)[off:off + m]
+        assert abs(loss.item() - orc.loss_l1(y1, t1)) <= 1e-5 * orc.loss_l1(y1, t1)
+        np.testing.assert_allclose(dl[off:off + m].cpu().numpy(), orc.loss_l1_grad(y1, t1), rtol=1e-6, atol=0)
+
+
+def test_adam_vs_oracle(R, orc):
+    import torch
+    rng = np.random.default_rng(3)
+    n = 100_003
+    p0 = rng.standard_normal(n).astype(np.float32)
+    p, m, v = torch.from_numpy(p0).cuda(), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    rp, rm, rv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    mabs = np.zeros(n)   # the same recurrence over |g|: the scale of m's float32 rounding
+    for step in range(1, 6):
+        g = (rng.standard_normal(n) * 10.0 ** rng.integers(-3, 1, n)).astype(np.float32)
+        R.recogs_adam_step(p.data_ptr(), torch.from_numpy(g).cuda().data_ptr(), m.data_ptr(), v.data_ptr(), n, 1e-3,
+                           0.9, 0.999, 1e-15, step)
+        # the same hyperparameter values the C ABI receives (float32)
+        f = lambda x: float(np.float32(x))  # noqa: E731
+        rp, rm, rv = orc.adam_step(rp, g, rm, rv, step, f(1e-3), f(0.9), f(0.999), f(1e-15))
+        mabs = 0.9 * mabs + 0.1 * np.abs(g.astype(np.float64))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p.cpu().numpy(), rp, rtol=0, atol=2e-6)
+    # m can cancel to near zero: bound its error by a few float32 ulps of the terms' magnitude
+    assert np.all(np.abs(m.cpu().numpy() - rm) <= 1e-6 * mabs + 1e-12)
+    np.testing.assert_allclose(v.cpu().numpy(), rv, rtol=1e-5, atol=0)
+    with pytest.raises(R.RecogsError):
+        R.recogs_adam_step(p.data_ptr(), p.data_ptr(), m.data_ptr(), v.data_ptr(), n, 1e-3, step=0)
+
+
+def test_sh_refit_lowers_the_l1_loss(R, orc):
+    """SH-only refitting (geometry frozen, Sec. 3.3): the target is the same view with
+    the selection recoloured by another matrix; Adam steps on the SH coefficients
+    driven by the L1 loss must bring the render toward it."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    Mt = torch.from_numpy(w.extra["M_target"].reshape(9).copy()).cuda()
+    target = R.render(d, cam, ws, mask=tm, M=Mt, b=tb).clone()
+    n, K = d.n, (w.scene.sh_degree + 1) ** 2
+    sh = d.sh.clone()                       # the coefficients being refitted (f32 planes)
+    m, v = torch.zeros_like(sh), torch.zeros_like(sh)
+    dl, loss = torch.empty_like(target), torch.empty(1, device="cuda")
+    dop, dsh, dM = torch.empty(n, device="cuda"), torch.zeros((3 * K, d.stride), device="cuda"), torch.empty(9, device="cuda")
+    o = R.opts_struct((16, 16), 1, keep_backward=True)
+    cnt = target.numel()
+    losses = []
+    for step in range(1, 31):
+        img = R.render(d, cam, ws, keep_backward=True, sh=sh)
+        R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt, 1.0 / cnt, dl.data_ptr(), loss.data_ptr())
+        R.recogs_render_backward_sh(d.c_struct(sh), R.camera_struct(cam), o, ws.ws, img.data_ptr(), dl.data_ptr(),
+                                    dop.data_ptr(), dsh.data_ptr(), dM.data_ptr())
+        R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3, step=step)
+        losses.append(loss.item())
+    print("L1 loss over the refit:", [round(x, 5) for x in losses[::5]], round(losses[-1], 5))
+    assert losses[-1] < 0.5 * losses[0]
