@@ -382,6 +382,71 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             "grad_M_norm": float(dM.norm().item())}
 
 
+def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
+    """SH-only refitting (the background optimiser, Sec. 3.3): 1M Gaussians (FP32, SH 3),
+    the 8 views at 1280x720 taken in turn, one per step: render keeping the backward
+    state, L1 loss against the view recoloured by the target matrix (plus seeded noise),
+    the gradient of every SH coefficient, one Adam step on all of them."""
+    import torch
+
+    import synth
+    log("bench: form refit: 1M Gaussians, SH-only Adam steps at 1280x720")
+    w = synth.make_diff()
+    d = R.DeviceScene(w.scene, device=dev)
+    n, K = d.n, (w.scene.sh_degree + 1) ** 2
+    v0 = w.views[0]
+    mask = torch.empty(n, dtype=torch.uint8, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    R.recogs_select(d.c_struct(), R.camera_struct(v0.camera), R.select_struct(v0.select), mask.data_ptr(), cnt.data_ptr())
+    Mt = torch.from_numpy(w.extra["M_target"].reshape(9).copy()).to(dev)
+    b = torch.zeros(3, dtype=torch.float32, device=dev)
+    W, H = v0.camera.width, v0.camera.height
+    ws = R.DeviceWorkspace(n, W, H, tile, device=dev)
+    targets = []
+    for k, v in enumerate(w.views):
+        t = R.render(d, v.camera, ws, tile, ppt, mask=mask, M=Mt, b=b).clone()
+        t += torch.from_numpy(synth.random_image(w.extra["noise_seed"] + k, (H, W, 3), w.extra["noise_sd"])).to(dev)
+        targets.append(t)
+    sh = d.sh.clone()
+    m, v = torch.zeros_like(sh), torch.zeros_like(sh)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    dimg = torch.empty_like(img)
+    loss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
+    dop = torch.empty(n, dtype=torch.float32, device=dev)
+    dsh = torch.zeros((3 * K, d.stride), dtype=torch.float32, device=dev)
+    dM = torch.empty(9, dtype=torch.float32, device=dev)
+    cams = [R.camera_struct(v.camera) for v in w.views]
+    o = R.opts_struct(tile, ppt, keep_backward=True)
+    sc = d.c_struct(sh)
+    cnt_px = H * W * 3
+    state = {"step": 0}
+
+    def step():
+        k = state["step"] % len(w.views)
+        state["step"] += 1
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh)
+        R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, 1.0 / cnt_px, dimg.data_ptr(),
+                         loss.data_ptr() + 4 * k)
+        R.recogs_render_backward_sh(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
+                                    dsh.data_ptr(), dM.data_ptr())
+        R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
+                           step=state["step"])
+    for _ in range(max(8, warmup)):
+        step()
+    torch.cuda.synchronize()
+    first = float(loss.mean().item())
+    reps = max(16, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
+            "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "ms_per_step": round(ms, 3),
+            "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
+            "l1_loss_mean_after_warmup": first, "l1_loss_mean_end": float(loss.mean().item())}
+
+
 def cpu_baseline(w):
     """The oracle as it stands on this host, on one whole frame of the same workload:
     recolour and projection of every Gaussian (one thread), then per-pixel compositing
@@ -430,7 +495,7 @@ def main():
                     help="skip the comparison frames (16x16 tiles, the other output layout)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
-    ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff"], default=None,
+    ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff", "refit"], default=None,
                     help="run only this form and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
@@ -452,6 +517,8 @@ def main():
     if args.only_form:
         if args.only_form == "batch":
             res = form_batch(R, args.steps, args.warmup, dev)
+        elif args.only_form == "refit":
+            res = form_refit(R, args.steps, args.warmup, dev)
         elif args.only_form == "diff":
             res = form_diff(R, args.steps, args.warmup, dev,
                             DIFF_TILE if args.diff_tile is None else tuple(args.diff_tile), args.diff_ppt)
@@ -551,6 +618,7 @@ def main():
                 forms[stg] = form_single(R, stg, tile, args.ppt, args.steps, args.warmup, dev)
         forms["batch"] = form_batch(R, args.steps, args.warmup, dev)
         forms["diff"] = form_diff(R, args.steps, args.warmup, dev)
+        forms["refit"] = form_refit(R, args.steps, args.warmup, dev)
         res["forms"] = forms
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -344,14 +344,16 @@ def backward(proj: Projection, dldy, M=None, bg=(0.0, 0.0, 0.0), windows=None) -
     return Grads(ds, dr, dc, dM.reshape(3, 3))
 
 
-def sh_grad(scene, cam, proj: Projection, grads: Grads, M=None) -> np.ndarray:
+def sh_grad(scene, cam, proj: Projection, grads: Grads, M=None, idx=None) -> np.ndarray:
     """dL/dC for every SH coefficient, planes [3 (deg+1)^2][n] (plane = k * 3 + c, the
     scene's layout). The colour of eq. 2 is linear in the coefficients,
     f_c = sum_k C_{k,c} Y_k(d) with d = (mu - campos) / |mu - campos|, so
     dL/dC_{k,c} = Y_k(d) g_c, where g is the gradient at f: the colour gradient of eq. 8
     masked where max(0, .) clamps and, for Gaussians the fused recolour selected (they
-    display M (f + 1/2) + b), multiplied by M^T. Gaussians that reach no pixel get 0."""
+    display M (f + 1/2) + b), multiplied by M^T. Gaussians that reach no pixel get 0.
+    With idx, only those Gaussians' columns, [3 (deg+1)^2][len(idx)]."""
     n = proj.f.shape[0]
+    cols = np.arange(n) if idx is None else np.asarray(idx, np.int64)
     deg = int(scene.sh_degree)
     K = (deg + 1) ** 2
     Mv = np.eye(3) if M is None else np.asarray(M, np.float64).reshape(3, 3)
@@ -359,8 +361,8 @@ def sh_grad(scene, cam, proj: Projection, grads: Grads, M=None) -> np.ndarray:
     t = np.asarray(cam.t, np.float32).astype(np.float64)
     campos = -R.T @ t
     means = np.asarray(scene.means, np.float32).astype(np.float64)
-    out = np.zeros((3 * K, n))
-    for i in range(n):
+    out = np.zeros((3 * K, len(cols)))
+    for j, i in enumerate(cols):
         gh = np.array([grads.drgb[i, c] if proj.f[i, P["pr"] + c] > 0 else 0.0 for c in range(3)])
         if not gh.any():
             continue
@@ -368,5 +370,5 @@ def sh_grad(scene, cam, proj: Projection, grads: Grads, M=None) -> np.ndarray:
         d = means[:, i] - campos
         Y = sh_basis(deg, d / np.linalg.norm(d))
         for k in range(K):
-            out[k * 3:(k + 1) * 3, i] = Y[k] * g
+            out[k * 3:(k + 1) * 3, j] = Y[k] * g
     return out

@@ -245,4 +245,18 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
     e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
     e3 = _close(dM, gr.dM, 2e-3, "dL/dM")
     assert np.abs(gr.dsigma).max() > 0 and np.abs(gr.dM).max() > 0
-    print(f"full size: relative max errors dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")
+    # every SH coefficient, on the Gaussians the windows reach
+    K = (sc.sh_degree + 1) ** 2
+    o = R.opts_struct((32, 16), 1, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    gt = torch.from_numpy(g).cuda()
+    dsh = torch.zeros((3 * K, d.stride), device="cuda")
+    t1, t9 = torch.empty(sc.n, device="cuda"), torch.empty(9, device="cuda")
+    R.recogs_render_backward_sh(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
+                                t1.data_ptr(), dsh.data_ptr(), t9.data_ptr())
+    torch.cuda.synchronize()
+    touched = np.nonzero(np.abs(gr.drgb).sum(axis=1) > 0)[0]
+    assert len(touched) > 100
+    ref_sh = orc.sh_grad(sc, cam, pr, gr, M=M, idx=touched)
+    e4 = _close(dsh[:, touched].cpu().numpy().astype(np.float64), ref_sh, 2e-3, "dL/dSH")
+    print(f"full size: relative max errors dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e} dSH {e4:.2e} "
+          f"({len(touched)} Gaussians)")
