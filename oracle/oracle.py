@@ -310,6 +310,63 @@ def adam_step(param, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+SSIM_WINDOW, SSIM_SIGMA, SSIM_C1, SSIM_C2 = 11, 1.5, 0.01 ** 2, 0.03 ** 2
+
+
+def _ssim_kernel() -> np.ndarray:
+    """Normalised 1-D Gaussian of the 11 x 11 SSIM window (sigma 1.5); the 2-D window is
+    its outer product."""
+    r = np.arange(SSIM_WINDOW) - SSIM_WINDOW // 2
+    g = np.exp(-(r * r) / (2.0 * SSIM_SIGMA ** 2))
+    return g / g.sum()
+
+
+def _blur(a: np.ndarray) -> np.ndarray:
+    """2-D correlation of an (H, W) array with the window, zero outside the image (the
+    window is symmetric, so this is also the convolution)."""
+    g = _ssim_kernel()
+    h = SSIM_WINDOW // 2
+    H, W = a.shape
+    p = np.zeros((H + 2 * h, W + 2 * h))
+    p[h:h + H, h:h + W] = a
+    t = sum(g[k] * p[:, k:k + W] for k in range(SSIM_WINDOW))          # along x
+    return sum(g[k] * t[k:k + H, :] for k in range(SSIM_WINDOW))       # along y
+
+
+def ssim(y, target):
+    """Mean SSIM over all pixels and channels of two (H, W, 3) images (the SSIM term of
+    eq. 7): per channel, local means, variances and covariance under the 11 x 11 Gaussian
+    window (zero padding), S = (2 mu_y mu_t + C1)(2 s_yt + C2) / ((mu_y^2 + mu_t^2 + C1)
+    (s_y^2 + s_t^2 + C2)) with C1 = 0.01^2, C2 = 0.03^2. Returns (value, dSSIM/dy).
+    The gradient: S depends on y through mu_y = G*y, E_yy = G*(y^2) and E_yt = G*(y t),
+    so dS/dy_q = (G * a)_q + 2 y_q (G * b)_q + t_q (G * c)_q with a, b, c the partial
+    derivatives of S with respect to those three maps."""
+    y = np.asarray(y, np.float64)
+    t = np.asarray(target, np.float64)
+    H, W, C = y.shape
+    total = 0.0
+    grad = np.zeros_like(y)
+    N = H * W * C
+    for c in range(C):
+        x, z = y[..., c], t[..., c]
+        mx, mz = _blur(x), _blur(z)
+        sxx = _blur(x * x) - mx * mx
+        szz = _blur(z * z) - mz * mz
+        sxz = _blur(x * z) - mx * mz
+        l1, l2 = 2 * mx * mz + SSIM_C1, mx * mx + mz * mz + SSIM_C1
+        c1, c2 = 2 * sxz + SSIM_C2, sxx + szz + SSIM_C2
+        S = l1 * c1 / (l2 * c2)
+        total += S.sum()
+        dS_dsxz = 2 * l1 / (l2 * c2)
+        dS_dsxx = -l1 * c1 / (l2 * c2 * c2)
+        dS_dmx = 2 * mz * c1 / (l2 * c2) - l1 * c1 * 2 * mx / (l2 * l2 * c2)
+        a = dS_dmx - 2 * mx * dS_dsxx - mz * dS_dsxz      # through mu_x, sigma_x^2 and sigma_xt
+        b = dS_dsxx                                       # through E[x^2]
+        cc = dS_dsxz                                      # through E[x t]
+        grad[..., c] = (_blur(a) + 2 * x * _blur(b) + z * _blur(cc)) / N
+    return total / N, grad
+
+
 @dataclass
 class Grads:
     dsigma: np.ndarray   # (n,)

@@ -610,3 +610,45 @@ def test_adam_closed_forms(orc):
     for step in range(2, 8):
         p, m, v = orc.adam_step(p, g, m, v, step, lr, eps=eps)
     np.testing.assert_allclose(p, p0 - 7 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-13)
+
+
+def test_ssim_against_brute_force_windows(orc):
+    """The SSIM term of eq. 7 against a direct evaluation: for every pixel and channel,
+    explicit 11 x 11 window sums with weights g_i g_j (zero outside the image)."""
+    rng = np.random.default_rng(4)
+    H, W = 6, 7
+    y, t = rng.random((H, W, 3)), rng.random((H, W, 3))
+    r = np.arange(11) - 5
+    g1 = np.exp(-(r * r) / (2 * 1.5 ** 2))
+    g1 /= g1.sum()
+    tot = 0.0
+    for c in range(3):
+        for py in range(H):
+            for px in range(W):
+                s = np.zeros(5)
+                for dy in range(-5, 6):
+                    for dx in range(-5, 6):
+                        qy, qx = py + dy, px + dx
+                        if 0 <= qy < H and 0 <= qx < W:
+                            a, b = y[qy, qx, c], t[qy, qx, c]
+                            s += g1[dy + 5] * g1[dx + 5] * np.array([a, b, a * a, b * b, a * b])
+                mx, mt, exx, ett, ext = s
+                sx, st, sxt = exx - mx * mx, ett - mt * mt, ext - mx * mt
+                tot += (2 * mx * mt + 1e-4) * (2 * sxt + 9e-4) / ((mx * mx + mt * mt + 1e-4) * (sx + st + 9e-4))
+    val, _ = orc.ssim(y, t)
+    assert abs(val - tot / (H * W * 3)) < 1e-13
+
+
+def test_ssim_gradient_and_identity(orc):
+    rng = np.random.default_rng(6)
+    y, t = rng.random((13, 18, 3)), rng.random((13, 18, 3))
+    v, g = orc.ssim(y, t)
+    h = 1e-6
+    for idx in [(0, 0, 0), (6, 9, 1), (12, 17, 2), (2, 16, 0), (12, 0, 1)]:
+        yp, ym = y.copy(), y.copy()
+        yp[idx] += h
+        ym[idx] -= h
+        fd = (orc.ssim(yp, t)[0] - orc.ssim(ym, t)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-8 * max(1.0, abs(fd)), (idx, fd, g[idx])
+    one, g0 = orc.ssim(y, y)
+    assert abs(one - 1.0) < 1e-14 and np.abs(g0).max() < 1e-15   # a maximum: value 1, gradient 0
