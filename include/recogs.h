@@ -276,6 +276,20 @@ recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_
 recogs_status recogs_loss_l1(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
+/* SSIM term of eq. 7, lambda (1 - SSIM), over two HWC float images [height][width][3]:
+ * per channel, local means, variances and covariance under the 11 x 11 Gaussian window
+ * (sigma 1.5, zero outside the image), S = (2 mu_y mu_t + C1)(2 s_yt + C2) /
+ * ((mu_y^2 + mu_t^2 + C1)(s_y^2 + s_t^2 + C2)), C1 = 0.01^2, C2 = 0.03^2, averaged over
+ * all pixels and channels. loss (device float, overwritten) = weight (1 - SSIM);
+ * dL_dimage = -weight dSSIM/dimage, written (accumulate 0) or added (accumulate 1, so
+ * that eq. 7 is recogs_loss_l1 with scale (1 - lambda) / count, then this with weight
+ * lambda). workspace: device scratch of recogs_dssim_workspace_bytes (9 floats per
+ * pixel), 4-byte aligned. INVALID: bad size, flag, pointer or workspace. */
+size_t recogs_dssim_workspace_bytes(int32_t width, int32_t height);
+recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t width, int32_t height, float weight,
+                                float *dL_dimage, int32_t accumulate, float *loss, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream);
+
 /* One Adam step over `count` float parameters (the optimiser that moves the SH
  * coefficients toward the edited views, Sec. 3.3): m <- beta1 m + (1 - beta1) g,
  * v <- beta2 v + (1 - beta2) g^2, param <- param - lr (m / c1) / (sqrt(v / c2) + eps) with

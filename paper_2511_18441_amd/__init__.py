@@ -11,7 +11,7 @@ from .binding import (  # noqa: F401
     recogs_workspace_bytes, recogs_workspace_init, recogs_workspace_readback, recogs_workspace_profile_flush, recogs_workspace_release,
     recogs_prepare_covariance, recogs_select, recogs_recolor,
     recogs_render, recogs_render_backward, recogs_loss_l2, recogs_render_backward_sh, recogs_loss_l1,
-    recogs_adam_step, recogs_last_error,
+    recogs_adam_step, recogs_dssim_workspace_bytes, recogs_loss_dssim, recogs_last_error,
     BATCH_ENTRY_POINTS, BatchView, BatchWorkspace, DeviceBatch, recogs_batch_workspace_bytes, recogs_batch_init,
     recogs_render_batch, recogs_batch_readback,
 )

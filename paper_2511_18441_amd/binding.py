@@ -27,7 +27,8 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_workspace_profile_flush",
                 "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
-                "recogs_loss_l1", "recogs_adam_step", "recogs_last_error")
+                "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
+                "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -109,9 +110,13 @@ def lib():
                                                 vp]
         L.recogs_loss_l1.argtypes = [vp, vp, i64, f32, vp, vp, vp]
         L.recogs_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
+        L.recogs_dssim_workspace_bytes.argtypes = [i32, i32]
+        L.recogs_dssim_workspace_bytes.restype = ctypes.c_size_t
+        L.recogs_loss_dssim.argtypes = [vp, vp, i32, i32, f32, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.recogs_last_error.restype = ctypes.c_char_p
         for name in ENTRY_POINTS:
-            if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release"):
+            if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release",
+                            "recogs_dssim_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -202,6 +207,17 @@ def recogs_loss_l1(image, target, count, scale, dL_dimage, loss, stream=None):
 def recogs_adam_step(param, grad, m, v, count, lr, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
     return _check("recogs_adam_step", lib().recogs_adam_step(param, grad, m, v, count, float(lr), float(beta1),
                                                              float(beta2), float(eps), int(step), _stream(stream)))
+
+
+def recogs_dssim_workspace_bytes(width, height) -> int:
+    return int(lib().recogs_dssim_workspace_bytes(int(width), int(height)))
+
+
+def recogs_loss_dssim(image, target, width, height, weight, dL_dimage, accumulate, loss, workspace, workspace_bytes,
+                      stream=None):
+    return _check("recogs_loss_dssim", lib().recogs_loss_dssim(image, target, int(width), int(height), float(weight),
+                                                               dL_dimage, int(accumulate), loss, workspace,
+                                                               int(workspace_bytes), _stream(stream)))
 
 
 def recogs_last_error() -> str:

@@ -1,8 +1,13 @@
-// Pieces of the background optimiser (Sec. 3.3 / 4.1): the L1 term of the loss of
-// eq. 7 with its gradient, and the Adam step that moves the SH coefficients.
+// Pieces of the background optimiser (Sec. 3.3 / 4.1): the L1 and SSIM terms of the
+// loss of eq. 7 with their gradients, and the Adam step that moves the SH coefficients.
+#include <cmath>
+#include <cstring>
+
 #include "recogs_internal.hpp"
 
 namespace recogs {
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 
 // loss = scale sum |y - t| (overwritten by the caller's fill), dL/dy = scale sign(y - t)
 // with sign(0) = 0. With vec (all three arrays 16-byte aligned) 4 elements per step.
@@ -66,6 +71,159 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, fl
     int64_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p, g, m, v, count, lr, b1, b2, eps, c1, c2);
+}
+
+// ---------------------------------------------------------------------------
+// SSIM term of eq. 7 over HWC float images, per channel, with the 11 x 11 Gaussian
+// window (sigma 1.5, zero outside the image): local means, variances and covariance
+// are separable blurs; S = (2 mu_y mu_t + C1)(2 s_yt + C2) / ((mu_y^2 + mu_t^2 + C1)
+// (s_y^2 + s_t^2 + C2)). Its gradient: S depends on y through mu_y = G*y, E_yy = G*(y^2)
+// and E_yt = G*(y t), so dS/dy = G*a + 2 y (G*b) + t (G*c) with a, b, c the partial
+// derivatives of S in those maps. Two passes, each a 16 x 16 output tile per
+// workgroup with its 26 x 26 input halo in LDS, blurred along x then along y:
+//   k_ssim_fwd: the three maps a, b, c per pixel and channel, and the sum of S;
+//   k_ssim_bwd: the blurs of a, b, c and the gradient.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kSsimR = 5;                     // window radius (11 taps)
+constexpr int kSsimT = 16;                    // output tile edge
+constexpr int kSsimH = kSsimT + 2 * kSsimR;   // halo tile edge (26)
+constexpr float kSsimC1 = 0.01f * 0.01f, kSsimC2 = 0.03f * 0.03f;
+}  // namespace
+
+struct SsimWindow { float g[2 * kSsimR + 1]; };
+
+// loads channel c of an HWC image's halo tile (zero outside the image) into s[26][26]
+__device__ __forceinline__ void ssim_load(const float *__restrict__ img, int W, int H, int c, int ox, int oy,
+                                          float *s /* [kSsimH * kSsimH] */) {
+    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
+        const int x = ox + k % kSsimH - kSsimR, y = oy + k / kSsimH - kSsimR;
+        s[k] = (x >= 0 && x < W && y >= 0 && y < H) ? img[((int64_t)y * W + x) * 3 + c] : 0.f;
+    }
+}
+// the same for a planar map [H][W]
+__device__ __forceinline__ void ssim_load_plane(const float *__restrict__ m, int W, int H, int ox, int oy, float *s) {
+    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
+        const int x = ox + k % kSsimH - kSsimR, y = oy + k / kSsimH - kSsimR;
+        s[k] = (x >= 0 && x < W && y >= 0 && y < H) ? m[(int64_t)y * W + x] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
+                                                  SsimWindow win, float *__restrict__ maps, float *__restrict__ loss,
+                                                  float neg_scale) {
+    __shared__ float s_y[kSsimH * kSsimH], s_t[kSsimH * kSsimH];
+    __shared__ float s_h[5][kSsimH][kSsimT];   // x-blurred y, t, y^2, t^2, y t
+    __shared__ float s_w[4];
+    const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
+    const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
+    const int px = ox + tx, py = oy + ty;
+    const int64_t HW = (int64_t)W * H;
+    float ssum = 0.f;
+    for (int c = 0; c < 3; ++c) {
+        __syncthreads();
+        ssim_load(y, W, H, c, ox, oy, s_y);
+        ssim_load(t, W, H, c, ox, oy, s_t);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
+            const int r = k / kSsimT, cx = k % kSsimT;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+            for (int j = 0; j <= 2 * kSsimR; ++j) {
+                const float u = s_y[r * kSsimH + cx + j], v = s_t[r * kSsimH + cx + j], g = win.g[j];
+                a0 += g * u; a1 += g * v; a2 += g * (u * u); a3 += g * (v * v); a4 += g * (u * v);
+            }
+            s_h[0][r][cx] = a0; s_h[1][r][cx] = a1; s_h[2][r][cx] = a2; s_h[3][r][cx] = a3; s_h[4][r][cx] = a4;
+        }
+        __syncthreads();
+        float my = 0.f, mt = 0.f, eyy = 0.f, ett = 0.f, eyt = 0.f;
+#pragma unroll
+        for (int j = 0; j <= 2 * kSsimR; ++j) {
+            const float g = win.g[j];
+            my += g * s_h[0][ty + j][tx]; mt += g * s_h[1][ty + j][tx];
+            eyy += g * s_h[2][ty + j][tx]; ett += g * s_h[3][ty + j][tx]; eyt += g * s_h[4][ty + j][tx];
+        }
+        if (px < W && py < H) {
+            const float syy = eyy - my * my, stt = ett - mt * mt, syt = eyt - my * mt;
+            const float l1 = 2.f * my * mt + kSsimC1, l2 = my * my + mt * mt + kSsimC1;
+            const float c1 = 2.f * syt + kSsimC2, c2 = syy + stt + kSsimC2;
+            const float il2c2 = 1.f / (l2 * c2);
+            const float S = l1 * c1 * il2c2;
+            const float dS_dsyt = 2.f * l1 * il2c2;
+            const float dS_dsyy = -S / c2;
+            const float dS_dmy = 2.f * mt * c1 * il2c2 - S * 2.f * my / l2;
+            const int64_t p = (int64_t)py * W + px;
+            maps[(3 * c + 0) * HW + p] = dS_dmy - 2.f * my * dS_dsyy - mt * dS_dsyt;   // a
+            maps[(3 * c + 1) * HW + p] = dS_dsyy;                                    // b
+            maps[(3 * c + 2) * HW + p] = dS_dsyt;                                    // c
+            ssum += S;
+        }
+    }
+    ssum = wave_sum(ssum);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = ssum;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, neg_scale * (((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]));
+}
+
+__global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
+                                                  SsimWindow win, const float *__restrict__ maps, float gscale,
+                                                  int accumulate, float *__restrict__ dldy) {
+    __shared__ float s_m[3][kSsimH * kSsimH];
+    __shared__ float s_h[3][kSsimH][kSsimT];
+    const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
+    const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
+    const int px = ox + tx, py = oy + ty;
+    const int64_t HW = (int64_t)W * H;
+    for (int c = 0; c < 3; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) ssim_load_plane(maps + (3 * c + q) * HW, W, H, ox, oy, s_m[q]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
+            const int r = k / kSsimT, cx = k % kSsimT;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+            for (int j = 0; j <= 2 * kSsimR; ++j) {
+                const float g = win.g[j];
+                a0 += g * s_m[0][r * kSsimH + cx + j]; a1 += g * s_m[1][r * kSsimH + cx + j]; a2 += g * s_m[2][r * kSsimH + cx + j];
+            }
+            s_h[0][r][cx] = a0; s_h[1][r][cx] = a1; s_h[2][r][cx] = a2;
+        }
+        __syncthreads();
+        float ga = 0.f, gb = 0.f, gc = 0.f;
+#pragma unroll
+        for (int j = 0; j <= 2 * kSsimR; ++j) {
+            const float g = win.g[j];
+            ga += g * s_h[0][ty + j][tx]; gb += g * s_h[1][ty + j][tx]; gc += g * s_h[2][ty + j][tx];
+        }
+        if (px < W && py < H) {
+            const int64_t p = ((int64_t)py * W + px) * 3 + c;
+            const float d = gscale * (ga + 2.f * y[p] * gb + t[p] * gc);
+            dldy[p] = accumulate ? dldy[p] + d : d;
+        }
+    }
+}
+
+// maps: 9 floats per pixel of scratch. loss <- weight (1 - mean S) (filled with weight
+// first); dL/dy (=, or += with accumulate) -weight dS/dy averaged over 3 H W values.
+void launch_dssim(const float *y, const float *t, int W, int H, float weight, float *dldy, int accumulate, float *loss,
+                  float *maps, hipStream_t st) {
+    SsimWindow win;
+    double g[2 * kSsimR + 1], sum = 0.0;
+    for (int j = 0; j <= 2 * kSsimR; ++j) {
+        const double r = j - kSsimR;
+        g[j] = std::exp(-(r * r) / (2.0 * 1.5 * 1.5));
+        sum += g[j];
+    }
+    for (int j = 0; j <= 2 * kSsimR; ++j) win.g[j] = (float)(g[j] / sum);
+    uint32_t wbits;
+    std::memcpy(&wbits, &weight, 4);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(loss), wbits, 1, st);
+    if (W <= 0 || H <= 0) return;
+    const double N = 3.0 * (double)W * (double)H;
+    const dim3 grid((unsigned)((W + kSsimT - 1) / kSsimT), (unsigned)((H + kSsimT - 1) / kSsimT));
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, loss, (float)(-weight / N));
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, (float)(-weight / N), accumulate, dldy);
 }
 
 }  // namespace recogs

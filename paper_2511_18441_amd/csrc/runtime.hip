@@ -43,6 +43,7 @@ void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const 
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
+void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
@@ -656,6 +657,26 @@ recogs_status recogs_loss_l1(const float *image, const float *target, int64_t co
     launch_fill_u32((uint32_t *)loss, 0u, 1, stream);
     launch_loss_l1(image, target, count, scale, dL_dimage, loss, stream);
     return hip_check("loss_l1");
+}
+
+size_t recogs_dssim_workspace_bytes(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return 0;
+    return (size_t)9 * sizeof(float) * (size_t)width * (size_t)height;
+}
+
+recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t width, int32_t height, float weight,
+                                float *dL_dimage, int32_t accumulate, float *loss, void *workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+    g_err[0] = 0;
+    if (width <= 0 || height <= 0) return fail(RECOGS_ERR_INVALID, "image %dx%d", width, height);
+    if (accumulate != 0 && accumulate != 1) return fail(RECOGS_ERR_INVALID, "accumulate %d not 0 or 1", accumulate);
+    if (!image || !target || !dL_dimage || !loss || !workspace) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    if (workspace_bytes < recogs_dssim_workspace_bytes(width, height))
+        return fail(RECOGS_ERR_INVALID, "workspace of %zu bytes, needs %zu", workspace_bytes,
+                    recogs_dssim_workspace_bytes(width, height));
+    if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(RECOGS_ERR_INVALID, "workspace not 4-byte aligned");
+    launch_dssim(image, target, width, height, weight, dL_dimage, accumulate, loss, (float *)workspace, stream);
+    return hip_check("loss_dssim");
 }
 
 recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,

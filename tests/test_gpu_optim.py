@@ -1,5 +1,5 @@
 """Pieces of the background optimiser (Sec. 3.3 / 4.1) through the C ABI: the gradient
-of every SH coefficient, the L1 term of eq. 7 and the Adam step, against the FP64
+of every SH coefficient, the L1 and SSIM terms of eq. 7 and the Adam step, against the FP64
 oracle (pinned on the CPU by central differences and closed forms); then a few steps of
 SH-only refitting toward a recoloured target, which must lower the loss."""
 import numpy as np
@@ -64,6 +64,37 @@ def test_loss_l1_vs_oracle(R, orc):
         np.testing.assert_allclose(dl[off:off + m].cpu().numpy(), orc.loss_l1_grad(y1, t1), rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("H,W", [(72, 128), (37, 50)])
+def test_dssim_vs_oracle(R, orc, H, W):
+    """The SSIM term of eq. 7 and its gradient (written, then accumulated onto an L1
+    gradient as eq. 7 combines them), on images whose size is not a multiple of the
+    kernels' 16 x 16 tiles."""
+    import torch
+    y = synth.random_image(9, (H, W, 3))
+    t = (0.7 * y + 0.3 * synth.random_image(10, (H, W, 3))).astype(np.float32)   # correlated, as a target is
+    ty, tt = torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()
+    nb = R.recogs_dssim_workspace_bytes(W, H)
+    ws = torch.empty(nb // 4, device="cuda")
+    lam = 0.2
+    loss = torch.empty(1, device="cuda")
+    dl = torch.full_like(ty, 5.0)
+    R.recogs_loss_dssim(ty.data_ptr(), tt.data_ptr(), W, H, lam, dl.data_ptr(), 0, loss.data_ptr(), ws.data_ptr(), nb)
+    torch.cuda.synchronize()
+    val, g = orc.ssim(y, t)
+    assert abs(loss.item() - lam * (1.0 - val)) <= 1e-5
+    e = _close(dl.cpu().numpy().astype(np.float64), -lam * g, 1e-3, "dL/dy (SSIM)")
+    # eq. 7: (1 - lambda) L1 + lambda (1 - SSIM), the SSIM gradient added to the L1 one
+    n = y.size
+    l1 = torch.empty(1, device="cuda")
+    R.recogs_loss_l1(ty.data_ptr(), tt.data_ptr(), n, (1 - lam) / n, dl.data_ptr(), l1.data_ptr())
+    R.recogs_loss_dssim(ty.data_ptr(), tt.data_ptr(), W, H, lam, dl.data_ptr(), 1, loss.data_ptr(), ws.data_ptr(), nb)
+    torch.cuda.synchronize()
+    ref = (1 - lam) * orc.loss_l1_grad(y, t) - lam * g
+    e2 = _close(dl.cpu().numpy().astype(np.float64), ref, 1e-3, "dL/dy (eq. 7)")
+    assert abs(l1.item() - (1 - lam) * orc.loss_l1(y, t)) <= 1e-5
+    print(f"{H}x{W}: SSIM {val:.6f}, gradient rel err {e:.2e}, eq. 7 gradient rel err {e2:.2e}")
+
+
 def test_adam_vs_oracle(R, orc):
     import torch
     rng = np.random.default_rng(3)
@@ -92,7 +123,7 @@ def test_adam_vs_oracle(R, orc):
 def test_sh_refit_lowers_the_l1_loss(R, orc):
     """SH-only refitting (geometry frozen, Sec. 3.3): the target is the same view with
     the selection recoloured by another matrix; Adam steps on the SH coefficients
-    driven by the L1 loss must bring the render toward it."""
+    driven by the loss of eq. 7 must bring the render toward it (L1 distance tracked)."""
     import torch
     w = _wfd()
     cam = w.view.camera
@@ -107,9 +138,17 @@ def test_sh_refit_lowers_the_l1_loss(R, orc):
     o = R.opts_struct((16, 16), 1, keep_backward=True)
     cnt = target.numel()
     losses = []
+    lam = 0.2
+    nb = R.recogs_dssim_workspace_bytes(cam.width, cam.height)
+    sws = torch.empty(nb // 4, device="cuda")
+    ls = torch.empty(1, device="cuda")
     for step in range(1, 31):
         img = R.render(d, cam, ws, keep_backward=True, sh=sh)
+        # eq. 7: (1 - lambda) L1 + lambda (1 - SSIM)
         R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt, 1.0 / cnt, dl.data_ptr(), loss.data_ptr())
+        R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt, (1 - lam) / cnt, dl.data_ptr(), ls.data_ptr())
+        R.recogs_loss_dssim(img.data_ptr(), target.data_ptr(), cam.width, cam.height, lam, dl.data_ptr(), 1,
+                            ls.data_ptr(), sws.data_ptr(), nb)
         R.recogs_render_backward_sh(d.c_struct(sh), R.camera_struct(cam), o, ws.ws, img.data_ptr(), dl.data_ptr(),
                                     dop.data_ptr(), dsh.data_ptr(), dM.data_ptr())
         R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3, step=step)
