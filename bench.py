@@ -385,8 +385,9 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
 def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     """SH-only refitting (the background optimiser, Sec. 3.3): 1M Gaussians (FP32, SH 3),
     the 8 views at 1280x720 taken in turn, one per step: render keeping the backward
-    state, L1 loss against the view recoloured by the target matrix (plus seeded noise),
-    the gradient of every SH coefficient, one Adam step on all of them."""
+    state, the loss of eq. 7 (0.8 L1 + 0.2 (1 - SSIM)) against the view recoloured by the
+    target matrix (plus seeded noise), the gradient of every SH coefficient, one Adam
+    step on all of them."""
     import torch
 
     import synth
@@ -419,14 +420,20 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     o = R.opts_struct(tile, ppt, keep_backward=True)
     sc = d.c_struct(sh)
     cnt_px = H * W * 3
+    lam = 0.2
+    nb = R.recogs_dssim_workspace_bytes(W, H)
+    sws = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    lss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
     state = {"step": 0}
 
     def step():
         k = state["step"] % len(w.views)
         state["step"] += 1
         R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh)
-        R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, 1.0 / cnt_px, dimg.data_ptr(),
+        R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
                          loss.data_ptr() + 4 * k)
+        R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
+                            sws.data_ptr(), nb)
         R.recogs_render_backward_sh(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
                                     dsh.data_ptr(), dM.data_ptr())
         R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
@@ -434,7 +441,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     for _ in range(max(8, warmup)):
         step()
     torch.cuda.synchronize()
-    first = float(loss.mean().item())
+    first = float((loss + lss).mean().item())
     reps = max(16, steps // 4)
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -444,7 +451,8 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
-            "l1_loss_mean_after_warmup": first, "l1_loss_mean_end": float(loss.mean().item())}
+            "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first,
+            "loss_mean_end": float((loss + lss).mean().item())}
 
 
 def cpu_baseline(w):
