@@ -72,6 +72,7 @@ def lib():
         L.orc_emit_keys.argtypes = [i64, vp, i32, i64, vp, vp, vp]
         L.orc_emit_keys.restype = i64
         L.orc_render_windows.argtypes = [i64, vp, vp, i32, i32, vp, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.orc_depth_windows.argtypes = [i64, vp, vp, i32, i32, f64, i64, vp, vp, vp]
         L.orc_backward.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.orc_backward_windows.argtypes = [i64, vp, vp, i32, i32, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.orc_ncols.argtypes = [i32]
@@ -248,6 +249,21 @@ def render_windows(proj: Projection, windows, bg=(0.0, 0.0, 0.0), brute: bool = 
     lib().orc_render_windows(n, _p(proj.f), _p(proj.i), proj.width, proj.height, _p(_d(bg)), win.shape[0], _p(win), int(brute),
                              _p(rgb), _p(T), _p(last), _p(nb), _p(slack))
     return PixelResult(rgb, T, last, nb, slack)
+
+
+def depth_windows(proj: Projection, windows, tau: float = 0.5):
+    """Rough depth map (Sec. 3.2) for the pixels of each window: the float32 depth of the
+    blended splat whose blending takes the transmittance below tau (0 if it never does),
+    and a flag where a float32 evaluation could decide differently. Reading: the paper
+    leaves tau unstated; 0.5 makes it the median depth it describes."""
+    win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 4))
+    npix = int((win[:, 2].astype(np.int64) * win[:, 3]).sum())
+    depth = np.empty(npix)
+    flag = np.empty(npix, np.int32)
+    n = proj.f.shape[0]
+    lib().orc_depth_windows(n, _p(proj.f), _p(proj.i), proj.width, proj.height, float(tau), win.shape[0], _p(win),
+                            _p(depth), flag.ctypes.data_as(ctypes.c_void_p))
+    return depth, flag
 
 
 def render_image(proj: Projection, bg=(0.0, 0.0, 0.0), brute: bool = False, window: int = 32):

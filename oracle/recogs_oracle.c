@@ -490,10 +490,10 @@ static double box_level(const double *p)
     return 2.0 * log(s) + Q_SLACK;
 }
 
-static void composite_pixel(int64_t ncand_all, const int64_t *list, const double *proj, const int64_t *iproj,
-                            double pxc, double pyc, double du, const double *bg, cand_t *buf,
-                            double *out_rgb, double *out_T, int64_t *out_last, int64_t *out_nb,
-                            double *out_slack)
+/* The splats of `list` whose alpha at the pixel centre reaches the threshold (less
+ * its rounding band), sorted front to back (z32, then index); returns their count. */
+static int64_t gather_candidates(int64_t ncand_all, const int64_t *list, const double *proj, double pxc, double pyc,
+                                 double du, cand_t *buf)
 {
     int64_t nc = 0;
     for (int64_t j = 0; j < ncand_all; ++j) {
@@ -509,9 +509,18 @@ static void composite_pixel(int64_t ncand_all, const int64_t *list, const double
             buf[nc].band = alpha_band(p, dx, dy, qv, du);
             ++nc;
         }
-        (void)iproj;
     }
     qsort(buf, (size_t)nc, sizeof(cand_t), cand_cmp);
+    return nc;
+}
+
+static void composite_pixel(int64_t ncand_all, const int64_t *list, const double *proj, const int64_t *iproj,
+                            double pxc, double pyc, double du, const double *bg, cand_t *buf,
+                            double *out_rgb, double *out_T, int64_t *out_last, int64_t *out_nb,
+                            double *out_slack)
+{
+    (void)iproj;
+    const int64_t nc = gather_candidates(ncand_all, list, proj, pxc, pyc, du, buf);
 
     /* forward pass */
     double T = 1.0, C[3] = {0, 0, 0};
@@ -617,6 +626,75 @@ void orc_render_windows(int64_t n, const double *proj, const int64_t *iproj, int
                 const int64_t o = offs[w] + (int64_t)yy * ww + xx;
                 composite_pixel(nl, list, proj, iproj, x0 + xx + 0.5, y0 + yy + 0.5, du, bg, buf,
                                 out_rgb + 3 * o, out_T + o, out_last + o, out_nb + o, out_slack + o);
+            }
+        free(buf);
+        free(list);
+    }
+    free(offs);
+}
+
+/* Rough depth map (Sec. 3.2): following eq. 3's front-to-back order, the depth of the
+ * blended splat whose blending takes the transmittance below tau; 0 where it never
+ * falls below tau (before the pixel stops). The depth is the splat's float32 depth
+ * (z32, the sort key). flag = 1 where a float32 evaluation could decide differently:
+ * an alpha near 1/255, or the transmittance within its rounding band of tau, at one of
+ * the splats up to and including the crossing. */
+static void depth_pixel(int64_t ncand_all, const int64_t *list, const double *proj, double pxc, double pyc, double du,
+                        double tau, cand_t *buf, double *out_depth, int32_t *out_flag)
+{
+    const int64_t nc = gather_candidates(ncand_all, list, proj, pxc, pyc, du, buf);
+    double T = 1.0, relT = TERM_BAND_MIN;
+    double depth = 0.0;
+    int32_t flag = 0;
+    for (int64_t k = 0; k < nc; ++k) {
+        const double araw = buf[k].alpha;
+        const double a = araw < ALPHA_MAX ? araw : ALPHA_MAX;
+        if (fabs(araw * 255.0 - 1.0) <= buf[k].band) flag = 1;
+        if (araw < ALPHA_MIN) continue;
+        const double Tn = T * (1.0 - a);
+        if (araw < ALPHA_MAX) relT += buf[k].band * a / (1.0 - a);
+        if (fabs(Tn / T_MIN - 1.0) <= relT) flag = 1;
+        if (Tn < T_MIN) break;  /* not blended: the pixel stops */
+        if (fabs(Tn / tau - 1.0) <= relT) flag = 1;
+        if (Tn < tau) {
+            depth = buf[k].z32;
+            break;
+        }
+        T = Tn;
+    }
+    *out_depth = depth;
+    *out_flag = flag;
+}
+
+void orc_depth_windows(int64_t n, const double *proj, const int64_t *iproj, int32_t width, int32_t height, double tau,
+                       int64_t nwin, const int32_t *win /* [nwin][4]: x0 y0 w h */, double *out_depth,
+                       int32_t *out_flag)
+{
+    int64_t *offs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nwin + 1));
+    offs[0] = 0;
+    for (int64_t w = 0; w < nwin; ++w) offs[w + 1] = offs[w] + (int64_t)win[w * 4 + 2] * win[w * 4 + 3];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t w = 0; w < nwin; ++w) {
+        const int32_t x0 = win[w * 4 + 0], y0 = win[w * 4 + 1], ww = win[w * 4 + 2], wh = win[w * 4 + 3];
+        int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+        int64_t nl = 0;
+        const double du = ldexp((double)(width > height ? width : height), -22);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t *q = iproj + i * I_NCOL;
+            const double *p = proj + i * P_NCOL;
+            if (!visible_for_pixels(q, p)) continue;
+            const double lev = box_level(p);
+            if (!(lev > 0)) continue;
+            const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
+            if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) continue;
+            if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) continue;
+            list[nl++] = i;
+        }
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
+        for (int32_t yy = 0; yy < wh; ++yy)
+            for (int32_t xx = 0; xx < ww; ++xx) {
+                const int64_t o = offs[w] + (int64_t)yy * ww + xx;
+                depth_pixel(nl, list, proj, x0 + xx + 0.5, y0 + yy + 0.5, du, tau, buf, out_depth + o, out_flag + o);
             }
         free(buf);
         free(list);
