@@ -126,6 +126,15 @@ typedef struct {
      * the rasteriser's original layout); the values are the same bits, only the
      * addresses differ. recogs_render_backward needs an HWC render. */
     int32_t output_chw;
+    /* Rough depth map (Sec. 3.2): with depth_map non-NULL (device float [H][W]) the blend
+     * also writes, per pixel, the float32 depth of the blended splat that takes the
+     * transmittance from >= depth_tau to < depth_tau (front to back, eq. 3), and 0 where
+     * the transmittance never falls below depth_tau before the pixel stops. Needs
+     * 0 < depth_tau <= 1 (INVALID otherwise) and a tile whose height is a multiple of
+     * 8 * px_per_thread (UNSUPPORTED otherwise); single-view renders only (batch
+     * workspaces reject it). NULL: no depth map, depth_tau ignored. */
+    float *depth_map;
+    float depth_tau;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds

@@ -58,7 +58,8 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("px_per_thread", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
-                ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("output_chw", ctypes.c_int32)]
+                ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("output_chw", ctypes.c_int32),
+                ("depth_map", ctypes.c_void_p), ("depth_tau", ctypes.c_float)]
 
 
 class Workspace(ctypes.Structure):
@@ -249,7 +250,7 @@ def select_struct(sp) -> SelectParams:
 
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
-                profile=False, sort_mode=0, graph_mode=False, chw=False) -> RenderOpts:
+                profile=False, sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -263,6 +264,8 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.sort_mode = int(sort_mode)
     o.graph_mode = 1 if graph_mode else 0
     o.output_chw = 1 if chw else 0
+    o.depth_map = depth.data_ptr() if depth is not None else None
+    o.depth_tau = float(depth_tau)
     return o
 
 
@@ -410,17 +413,21 @@ class DeviceWorkspace:
 
 def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
            M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False,
-           sort_mode=0, graph_mode=False, chw=False):
+           sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5):
     """recogs_render into a (H, W, 3) float32 tensor ((3, H, W) with chw); grows the
     workspace once when the view needs more tile keys than it holds (eager mode). With
     graph_mode nothing is read back: check ws.readback() (num_keys > key_capacity means
-    it overflowed)."""
+    it overflowed). depth: a (H, W) float32 tensor that receives the rough depth map
+    (Sec. 3.2) at threshold depth_tau."""
     import torch
     c = camera_struct(cam)
     if image is None:
         shape = (3, cam.height, cam.width) if chw else (cam.height, cam.width, 3)
         image = torch.empty(shape, dtype=torch.float32, device=dscene.means.device)
-    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode, chw)
+    if depth is not None:
+        if tuple(depth.shape) != (cam.height, cam.width) or depth.dtype != torch.float32 or not depth.is_contiguous():
+            raise ValueError("depth must be a contiguous float32 (H, W) tensor")
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode, chw, depth, depth_tau)
     sc = dscene.c_struct(sh)
     st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     if st == -2 and grow:

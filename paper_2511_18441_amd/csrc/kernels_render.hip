@@ -501,20 +501,22 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend(const uint2 *__restrict_
 
 // Region form: one wave per 8 x 8*PPT region. Workgroup b runs on XCD b mod 8; the
 // regions of a tile take consecutive workgroups of one XCD (so its list is read
-// through one L2), and the tiles are dealt to the XCDs in turn.
-template <int TW, int TH, int PPT, bool STATE>
+// through one L2), and the tiles are dealt to the XCDs in turn. DEPTH: also the rough
+// depth map (depth [H][W], from the per-record depth bits zbits and threshold tau).
+template <int TW, int TH, int PPT, bool STATE, bool DEPTH>
 __global__ __launch_bounds__(64) void k_blend_region(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
                                                     const SplatRec *__restrict__ rec, int W, int H, int tiles_x,
                                                     uint32_t ntiles, float bg0, float bg1, float bg2,
                                                     float *__restrict__ image, int chw, float *__restrict__ finalT,
-                                                    uint32_t *__restrict__ nproc) {
+                                                    uint32_t *__restrict__ nproc, const uint32_t *__restrict__ zbits,
+                                                    float tau, float *__restrict__ depth) {
     constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
     __shared__ BlendRec sm[64];
     const uint32_t b = blockIdx.x, j = b >> 3;
     const uint32_t tile = (j / NR) * 8u + (b & 7u);
     if (tile >= ntiles) return;
-    blend_region<TW, TH, PPT, STATE>((int)tile, (int)(j % NR), ranges[tile], vals, rec, W, H, tiles_x, bg0, bg1, bg2,
-                                     image, chw, finalT, nproc, sm);
+    blend_region<TW, TH, PPT, STATE, DEPTH>((int)tile, (int)(j % NR), ranges[tile], vals, rec, W, H, tiles_x, bg0, bg1,
+                                            bg2, image, chw, finalT, nproc, sm, zbits, tau, depth);
 }
 
 // ---------------------------------------------------------------------------
@@ -595,16 +597,19 @@ void launch_ranges(const uint64_t *keys, uint32_t K, uint2 *ranges, hipStream_t 
 
 template <int TW, int TH, int PPT>
 static void blend_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec, int W,
-                      int H, int tiles_x, const float *bg, float *image, int chw, float *finalT, uint32_t *nproc) {
+                      int H, int tiles_x, const float *bg, float *image, int chw, float *finalT, uint32_t *nproc,
+                      const uint32_t *zbits, float tau, float *depth) {
     if constexpr (region_shape(TW, TH, PPT)) {
         constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
         const dim3 g((unsigned)(((uint32_t)ntiles + 7u) / 8u * 8u * NR));
-        if (finalT)
-            hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, true>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
-                               (uint32_t)ntiles, bg[0], bg[1], bg[2], image, chw, finalT, nproc);
-        else
-            hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, false>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,
-                               (uint32_t)ntiles, bg[0], bg[1], bg[2], image, chw, nullptr, nullptr);
+#define RECOGS_REGION(S, D)                                                                                          \
+    hipLaunchKernelGGL((k_blend_region<TW, TH, PPT, S, D>), g, dim3(64), 0, st, ranges, vals, rec, W, H, tiles_x,    \
+                       (uint32_t)ntiles, bg[0], bg[1], bg[2], image, chw, finalT, nproc, zbits, tau, depth)
+        if (finalT && depth) RECOGS_REGION(true, true);
+        else if (finalT) RECOGS_REGION(true, false);
+        else if (depth) RECOGS_REGION(false, true);
+        else RECOGS_REGION(false, false);
+#undef RECOGS_REGION
     } else {
         if (finalT)
             hipLaunchKernelGGL((k_blend<TW, TH, PPT, true>), dim3(ntiles), dim3(TW * TH / PPT), 0, st, ranges, vals, rec, W,
@@ -615,14 +620,17 @@ static void blend_one(int ntiles, hipStream_t st, const uint2 *ranges, const uin
     }
 }
 
-// chw: write the image as [3][H][W] instead of [H][W][3]
+// chw: write the image as [3][H][W] instead of [H][W][3]. depth non-null: also the
+// rough depth map (region shapes only: false otherwise, nothing launched).
 bool launch_blend(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
                   int W, int H, int tiles_x, const float *bg, float *image, int chw, float *finalT, uint32_t *nproc,
-                  hipStream_t st) {
-#define RECOGS_BLEND_CASE(A, B, P)                                                                         \
-    if (tw == A && th == B && ppt == P) {                                                                  \
-        blend_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, bg, image, chw, finalT, nproc);   \
-        return true;                                                                                       \
+                  const uint32_t *zbits, float tau, float *depth, hipStream_t st) {
+    if (depth && !region_shape(tw, th, ppt)) return false;
+#define RECOGS_BLEND_CASE(A, B, P)                                                                                      \
+    if (tw == A && th == B && ppt == P) {                                                                               \
+        blend_one<A, B, P>(ntiles, st, ranges, vals, rec, W, H, tiles_x, bg, image, chw, finalT, nproc, zbits, tau,    \
+                           depth);                                                                                      \
+        return true;                                                                                                    \
     }
     RECOGS_BLEND_CASE(16, 16, 1) RECOGS_BLEND_CASE(16, 16, 2) RECOGS_BLEND_CASE(16, 16, 4)
     RECOGS_BLEND_CASE(8, 8, 1) RECOGS_BLEND_CASE(8, 8, 2) RECOGS_BLEND_CASE(8, 8, 4)

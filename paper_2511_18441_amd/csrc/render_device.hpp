@@ -172,10 +172,13 @@ __device__ __forceinline__ void store_pixel(float *__restrict__ image, int64_t p
 
 // One splat record applied to the PPT pixels of a thread (eq. 3, front to back).
 // `idx` is the record's 1-based position in its tile list (kept, with STATE, as the
-// count up to the last blended entry).
-template <int PPT, bool STATE>
+// count up to the last blended entry). With DEPTH, cross[j] takes the position of the
+// blended splat that takes the pixel's transmittance from >= tau to < tau (the rough
+// depth of Sec. 3.2; at most one splat per pixel does, as T only decreases).
+template <int PPT, bool STATE, bool DEPTH = false>
 __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const float *pyc, float *T, float *C0, float *C1,
-                                           float *C2, uint32_t *last, uint32_t idx) {
+                                           float *C2, uint32_t *last, uint32_t idx, uint32_t *cross = nullptr,
+                                           float tau = 0.f) {
 #pragma clang fp contract(off)
     const float2 uv = b.uv;
     const float4 r1 = b.r1, r2 = b.rgb;
@@ -193,6 +196,7 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
         C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
         C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
         if constexpr (STATE) last[j] = bl ? idx : last[j];
+        if constexpr (DEPTH) cross[j] = (bl && Tn < tau && T[j] >= tau) ? idx : cross[j];
         const float Ts = stop ? -T[j] : Tn;   // two selects: this form compiles to v_cndmask
         T[j] = ok ? Ts : T[j];
     }
@@ -310,13 +314,16 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
 // the regions of a tile: a region whose pixels have all stopped retires at once, so
 // the sort tile can be larger than the region without the early-stopped pixels
 // holding the rest. The per-pixel arithmetic and the list positions kept with STATE
-// are those of blend_tile, so both forms give bit-identical outputs.
-template <int TW, int TH, int PPT, bool STATE>
+// are those of blend_tile, so both forms give bit-identical outputs. With DEPTH the
+// rough depth map (Sec. 3.2) is written too: per pixel, the float32 depth (zbits, per
+// record) of the splat whose blending takes T below tau, 0 where none does.
+template <int TW, int TH, int PPT, bool STATE, bool DEPTH = false>
 __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const uint32_t *__restrict__ vals,
                                              const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
                                              float bg1, float bg2, float *__restrict__ image, int chw,
                                              float *__restrict__ finalT, uint32_t *__restrict__ nproc,
-                                             BlendRec *sm /* [64] */) {
+                                             BlendRec *sm /* [64] */, const uint32_t *__restrict__ zbits = nullptr,
+                                             float tau = 0.f, float *__restrict__ depth = nullptr) {
 #pragma clang fp contract(off)
     static_assert(TW % 8 == 0 && TH % (8 * PPT) == 0, "regions of 8 x 8*PPT pixels");
     const int l = (int)lane_id();
@@ -327,7 +334,7 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
     const float x0 = (float)bx + 0.5f, x1 = x0 + 7.f;
     const float y0 = (float)by + 0.5f, y1 = y0 + (float)(8 * PPT - 1);
     float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
-    uint32_t last[PPT];
+    uint32_t last[PPT], cross[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int py = by + (l >> 3) * PPT + j;
@@ -335,6 +342,7 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
         T[j] = (px < W && py < H) ? 1.f : -1.f;  // pixels outside the image start stopped
         C0[j] = C1[j] = C2[j] = 0.f;
         last[j] = 0;
+        cross[j] = 0;
     }
     // Software pipeline over chunks of 64 list entries (one per lane): the records of
     // chunk c are in registers while chunk c - 1 is composited, and the list values of
@@ -378,7 +386,7 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
 #pragma unroll
             for (int j = 0; j < PPT; ++j) live = live || T[j] > 0.f;
             if (!wave_ballot(live)) break;
-            blend_step<PPT, STATE>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q);
+            blend_step<PPT, STATE, DEPTH>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q, cross, tau);
         }
         wave_sync();   // all reads of this chunk before the next chunk's writes
     }
@@ -394,6 +402,7 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
                 finalT[p] = Tf;
                 nproc[p] = last[j];
             }
+            if constexpr (DEPTH) depth[p] = cross[j] ? __uint_as_float(zbits[vals[rg.x + cross[j] - 1u]]) : 0.f;
         }
     }
 }

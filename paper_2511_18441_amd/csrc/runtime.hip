@@ -30,7 +30,7 @@ size_t sort_count_words(uint64_t K_max);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
 bool launch_blend(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, int, int, int, const float *,
-                  float *, int, float *, uint32_t *, hipStream_t);
+                  float *, int, float *, uint32_t *, const uint32_t *, float, float *, hipStream_t);
 int sort_passes(int total_bits);
 int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
                             uint32_t *, hipStream_t);
@@ -292,6 +292,11 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
         return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
     if (o->output_chw != 0 && o->output_chw != 1) return fail(RECOGS_ERR_INVALID, "output_chw %d not 0 or 1", o->output_chw);
+    if (o->depth_map && !region_shape(o->tile_w, o->tile_h, o->px_per_thread))
+        return fail(RECOGS_ERR_UNSUPPORTED, "depth_map needs tile_h a multiple of 8 * px_per_thread (%dx%d, %d)",
+                    o->tile_w, o->tile_h, o->px_per_thread);
+    if (o->depth_map && !(o->depth_tau > 0.f && o->depth_tau <= 1.f))
+        return fail(RECOGS_ERR_INVALID, "depth_tau %g not in (0, 1]", (double)o->depth_tau);
     const bool any = o->mask || o->M || o->b;
     if (any && !(o->mask && o->M && o->b)) return fail(RECOGS_ERR_INVALID, "fused recolour needs mask, M and b together");
     return RECOGS_OK;
@@ -362,7 +367,8 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0,
                       at<SplatRec>(ws, ws->off_rec), cam->width, cam->height, cd.tiles_x, opts->bg, image, opts->output_chw,
                       opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
-                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
+                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr,
+                      at<uint32_t>(ws, ws->off_zbits), opts->depth_tau, opts->depth_map, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
     if ((s = tm.mark(8)) != RECOGS_OK) return s;
     if ((s = hip_check("blend")) != RECOGS_OK) return s;
@@ -579,7 +585,8 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0, rec, cam->width,
                       cam->height, cd.tiles_x, opts->bg, image, opts->output_chw,
                       opts->keep_backward_state ? at<float>(ws, ws->off_final_T) : nullptr,
-                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr, stream))
+                      opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr,
+                      at<uint32_t>(ws, ws->off_zbits), opts->depth_tau, opts->depth_map, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
     if ((s = tm.mark(8)) != RECOGS_OK) return s;
     if ((s = hip_check("blend")) != RECOGS_OK) return s;
@@ -785,6 +792,7 @@ recogs_status recogs_batch_init(recogs_batch_workspace *ws, void *dev_mem, size_
     if ((uintptr_t)dev_mem % kAlign) return fail(RECOGS_ERR_INVALID, "workspace memory not 256-byte aligned");
     if ((s = check_batch(views, nviews)) != RECOGS_OK) return s;
     if ((s = check_opts(opts)) != RECOGS_OK) return s;
+    if (opts->depth_map) return fail(RECOGS_ERR_UNSUPPORTED, "batch renders write no depth map");
     if (key_capacity < 0 || key_capacity > 0x7fffffffLL) return fail(RECOGS_ERR_UNSUPPORTED, "key capacity not in 0..2^31-1");
     memset(ws, 0, sizeof(*ws));
     const size_t need = batch_layout(ws, views, nviews, opts->tile_w, opts->tile_h, key_capacity);

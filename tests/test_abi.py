@@ -43,7 +43,8 @@ PROBE = r"""
 int main(void) {
   S(recogs_scene) S(recogs_camera) S(recogs_select_params) S(recogs_render_opts) S(recogs_workspace)
   S(recogs_batch_view) S(recogs_batch_workspace)
-  O(recogs_render_opts, mask) O(recogs_render_opts, sort_mode)
+  O(recogs_render_opts, mask) O(recogs_render_opts, sort_mode) O(recogs_render_opts, depth_map)
+  O(recogs_render_opts, depth_tau)
   O(recogs_workspace, off_rec) O(recogs_workspace, num_keys) O(recogs_workspace, stage_ms)
   O(recogs_batch_workspace, pairs) O(recogs_batch_workspace, off_views) O(recogs_batch_workspace, num_keys)
   O(recogs_batch_view, image)
@@ -72,6 +73,16 @@ def test_struct_layout_matches_binding(R):
             assert getattr(C[t], f).offset == int(v), key
 
 
+class _Ptr:
+    """Stands in for a device tensor: only its address is read."""
+
+    def __init__(self, addr):
+        self.addr = addr
+
+    def data_ptr(self):
+        return self.addr
+
+
 def test_host_argument_errors_before_any_launch(R):
     B = R.binding
     cam = B.Camera()
@@ -97,6 +108,12 @@ def test_host_argument_errors_before_any_launch(R):
     o_bad = B.opts_struct((16, 16), 1)
     o_bad.output_chw = 2
     assert status(B.recogs_render, sc, cam, o_bad, ws, 1, 0) == -1
+    # rough depth map: threshold outside (0, 1], a tile form without one wave per region
+    dep = 64  # any non-NULL device address: the options are refused before any launch
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, depth=_Ptr(dep), depth_tau=0.0), ws, 1, 0) == -1
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, depth=_Ptr(dep), depth_tau=1.5), ws, 1, 0) == -1
+    assert status(B.recogs_render, sc, cam, B.opts_struct((32, 8), 2, depth=_Ptr(dep)), ws, 1, 0) == -3
+    assert status(B.recogs_render, sc, cam, B.opts_struct((8, 8), 4, depth=_Ptr(dep)), ws, 1, 0) == -3
     # invalid scene fields
     bad = B.Scene()
     bad.n, bad.stride, bad.sh_degree = 10, 5, 0
@@ -143,4 +160,6 @@ def test_host_argument_errors_before_any_launch(R):
     assert R.recogs_batch_workspace_bytes(views, 2, 16, 16, 10) == 0
     bw = B.BatchWorkspace()
     assert status(R.recogs_batch_init, bw, 256, 1 << 20, views, 2, opts, 10) == -3
+    views[1].scene.storage = 0
+    assert status(R.recogs_batch_init, bw, 256, 1 << 20, views, 2, B.opts_struct((16, 16), 1, depth=_Ptr(64)), 10) == -3
     assert status(R.recogs_render_batch, bw, 0) == -1
