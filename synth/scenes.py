@@ -416,3 +416,20 @@ def random_image(seed: int, shape, scale: float = 1.0) -> np.ndarray:
     """Seeded image-shaped array, e.g. an upstream gradient dL/dy."""
     rng = np.random.default_rng(seed)
     return (scale * rng.standard_normal(shape)).astype(np.float32)
+
+
+def brush_mask(width: int, height: int, cx: float, cy: float, r: float) -> np.ndarray:
+    """A 2D selection as a user's brush would paint it: uint8 (H, W), 1 on the pixels
+    whose centres lie in the disk of radius r around (cx, cy)."""
+    yy, xx = np.mgrid[0:height, 0:width]
+    return (((xx + 0.5 - cx) ** 2 + (yy + 0.5 - cy) ** 2) <= r * r).astype(np.uint8)
+
+
+def sample_keep(seed: int, mask: np.ndarray, frac: float = 0.7) -> np.ndarray:
+    """Uniform sample without replacement of floor(frac * count) of the mask's pixels:
+    uint8, 1 on the kept ones (the random draw of the unprojection)."""
+    rng = np.random.default_rng(seed)
+    flat = np.flatnonzero(np.asarray(mask).reshape(-1))
+    keep = np.zeros(np.asarray(mask).size, np.uint8)
+    keep[rng.choice(flat, size=int(frac * flat.size), replace=False)] = 1
+    return keep.reshape(np.asarray(mask).shape)
