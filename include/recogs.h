@@ -308,6 +308,45 @@ recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t
 recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr,
                                float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
 
+/* ---- pixel selection (Sec. 3.2, 3.3) ----------------------------------------- */
+
+/* Unprojection of a 2D selection to a world point cloud (Sec. 3.2, 3D selection).
+ * Takes the pixels with mask != 0, keep != 0 (the uniform sample the method draws,
+ * e.g. 70% of the selection; keep NULL = every pixel) and depth > 0 (pixels without a
+ * surface are skipped), in row-major pixel order, and writes each one's world point
+ * X = R^T (m - t), m = d ((x + 1/2 - cx) / fx, (y + 1/2 - cy) / fy, 1), d its depth
+ * (camera-space z, as the rough depth map of the render holds it). Device pointers:
+ * mask, keep uint8 [H][W]; depth float [H][W]; points float [3][capacity] (planar, the
+ * layout of scene means); count uint32 [1] receives the number of selected pixels,
+ * which may exceed capacity (points past capacity are not written). workspace: device
+ * memory of recogs_unproject_workspace_bytes(W, H) bytes, 4-byte aligned, overwritten.
+ * No host synchronisation. INVALID: bad camera, capacity, pointer or workspace. */
+size_t recogs_unproject_workspace_bytes(int32_t width, int32_t height);
+recogs_status recogs_unproject(const recogs_camera *cam, const uint8_t *mask, const uint8_t *keep, const float *depth,
+                               float *points, int64_t capacity, uint32_t *count, void *workspace,
+                               size_t workspace_bytes, hipStream_t stream);
+
+/* A point cloud drawn into a view as its selection mask (Sec. 3.2: the cloud is drawn
+ * as screen-space squares of one size, depth-tested against the rough depth map;
+ * Sec. 3.3: the mask of each training view). Point i (points float [3][stride], n of
+ * them) at m = R X + t is skipped when m_z <= znear; otherwise the square of side
+ * quad_px around (u, v) = (fx m_x / m_z + cx, fy m_y / m_z + cy) covers the pixels whose
+ * centres lie in [u - quad_px/2, u + quad_px/2) x [v - quad_px/2, v + quad_px/2), and a
+ * covered pixel is marked where depth (float [H][W], or NULL = no test) is 0 or
+ * m_z <= depth (1 + depth_eps). mask uint8 [H][W] is overwritten: 1 marked, 0 not.
+ * INVALID: bad camera, n < 0, stride < n, quad_px not in (0, 64], depth_eps < 0, NULL
+ * pointer. */
+recogs_status recogs_reproject_mask(const recogs_camera *cam, const float *points, int64_t n, int64_t stride,
+                                    float quad_px, const float *depth, float depth_eps, uint8_t *mask,
+                                    hipStream_t stream);
+
+/* The edit of Sec. 3.3 (eq. 6's colour filter on pixels): out = t c per channel where
+ * mask != 0, c elsewhere. image, out float [pixels][3] (HWC; out may be image); mask
+ * uint8 [pixels]; t: host float [3], read during the call. INVALID: pixels < 0, NULL
+ * pointer, t not finite. */
+recogs_status recogs_tint(const float *image, const uint8_t *mask, const float t[3], float *out, int64_t pixels,
+                          hipStream_t stream);
+
 /* ---- batched form ------------------------------------------------------------ */
 
 /* One render of a batch (host struct): a scene, a camera, an optional fused recolour

@@ -28,6 +28,7 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
+                "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
                 "recogs_last_error")
 
 
@@ -114,10 +115,15 @@ def lib():
         L.recogs_dssim_workspace_bytes.argtypes = [i32, i32]
         L.recogs_dssim_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_loss_dssim.argtypes = [vp, vp, i32, i32, f32, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.recogs_unproject_workspace_bytes.argtypes = [i32, i32]
+        L.recogs_unproject_workspace_bytes.restype = ctypes.c_size_t
+        L.recogs_unproject.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        L.recogs_reproject_mask.argtypes = [P(Camera), vp, i64, i64, f32, vp, f32, vp, vp]
+        L.recogs_tint.argtypes = [vp, vp, P(f32), vp, i64, vp]
         L.recogs_last_error.restype = ctypes.c_char_p
         for name in ENTRY_POINTS:
             if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release",
-                            "recogs_dssim_workspace_bytes"):
+                            "recogs_dssim_workspace_bytes", "recogs_unproject_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -208,6 +214,69 @@ def recogs_loss_l1(image, target, count, scale, dL_dimage, loss, stream=None):
 def recogs_adam_step(param, grad, m, v, count, lr, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
     return _check("recogs_adam_step", lib().recogs_adam_step(param, grad, m, v, count, float(lr), float(beta1),
                                                              float(beta2), float(eps), int(step), _stream(stream)))
+
+
+def recogs_unproject_workspace_bytes(width, height) -> int:
+    return int(lib().recogs_unproject_workspace_bytes(int(width), int(height)))
+
+
+def recogs_unproject(cam: Camera, mask, keep, depth, points, capacity, count, workspace, workspace_bytes, stream=None):
+    return _check("recogs_unproject", lib().recogs_unproject(ctypes.byref(cam), mask, keep, depth, points, int(capacity),
+                                                             count, workspace, int(workspace_bytes), _stream(stream)))
+
+
+def recogs_reproject_mask(cam: Camera, points, n, stride, quad_px, depth, depth_eps, mask, stream=None):
+    return _check("recogs_reproject_mask", lib().recogs_reproject_mask(ctypes.byref(cam), points, int(n), int(stride),
+                                                                       float(quad_px), depth, float(depth_eps), mask,
+                                                                       _stream(stream)))
+
+
+def recogs_tint(image, mask, t, out, pixels, stream=None):
+    tt = (ctypes.c_float * 3)(*[float(x) for x in t])
+    return _check("recogs_tint", lib().recogs_tint(image, mask, tt, out, int(pixels), _stream(stream)))
+
+
+def unproject(cam, mask, keep, depth, capacity=None):
+    """recogs_unproject on device tensors: mask, keep (or None) uint8 (H, W), depth
+    float32 (H, W). Returns the points as a (3, count) float32 view of a (3, capacity)
+    tensor (capacity defaults to the number of mask pixels) and the selected count."""
+    import torch
+    c = camera_struct(cam)
+    dev = depth.device
+    cap = int(mask.numel()) if capacity is None else int(capacity)
+    pts = torch.empty((3, max(cap, 1)), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    nb = recogs_unproject_workspace_bytes(cam.width, cam.height)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    recogs_unproject(c, mask.data_ptr(), keep.data_ptr() if keep is not None else None, depth.data_ptr(),
+                     pts.data_ptr(), cap, cnt.data_ptr(), ws.data_ptr(), nb, _stream(None))
+    n = int(cnt.item())
+    return pts[:, :min(n, cap)], n
+
+
+def reproject_mask(cam, points, quad_px, depth=None, depth_eps=0.0, mask=None):
+    """recogs_reproject_mask of a (3, n) float32 device tensor (any column stride)
+    into a uint8 (H, W) mask."""
+    import torch
+    c = camera_struct(cam)
+    if mask is None:
+        mask = torch.empty((cam.height, cam.width), dtype=torch.uint8, device=points.device)
+    n = points.shape[1]
+    stride = points.stride(0) if n > 0 else 0
+    if n > 0 and points.stride(1) != 1:
+        raise ValueError("points must have unit column stride")
+    recogs_reproject_mask(c, points.data_ptr() if n > 0 else None, n, stride, quad_px,
+                          depth.data_ptr() if depth is not None else None, depth_eps, mask.data_ptr())
+    return mask
+
+
+def tint(image, mask, t, out=None):
+    """recogs_tint of an (H, W, 3) float32 image with a uint8 (H, W) mask."""
+    import torch
+    if out is None:
+        out = torch.empty_like(image)
+    recogs_tint(image.data_ptr(), mask.data_ptr(), t, out.data_ptr(), image.numel() // 3)
+    return out
 
 
 def recogs_dssim_workspace_bytes(width, height) -> int:

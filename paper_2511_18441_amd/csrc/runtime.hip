@@ -44,6 +44,11 @@ void launch_loss_l2(const float *, const float *, int64_t, float, float *, float
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
 void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t);
+uint32_t unproject_blocks(int64_t);
+void launch_unproject(const CamDev &, const uint8_t *, const uint8_t *, const float *, int64_t, uint32_t *, uint32_t *,
+                      float *, int64_t, hipStream_t);
+void launch_reproject(const CamDev &, const float *, int64_t, int64_t, float, const float *, float, uint8_t *, hipStream_t);
+void launch_tint(const float *, const uint8_t *, const float *, float *, int64_t, hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
@@ -697,6 +702,52 @@ recogs_status recogs_adam_step(float *param, const float *grad, float *m, float 
     const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
     launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, (float)c1, (float)c2, stream);
     return hip_check("adam_step");
+}
+
+size_t recogs_unproject_workspace_bytes(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return 0;
+    return align_up((size_t)4 * ((size_t)unproject_blocks((int64_t)width * height) + 1));
+}
+
+recogs_status recogs_unproject(const recogs_camera *cam, const uint8_t *mask, const uint8_t *keep, const float *depth,
+                               float *points, int64_t capacity, uint32_t *count, void *workspace, size_t workspace_bytes,
+                               hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if (capacity < 0 || capacity > 0xffffffffLL) return fail(RECOGS_ERR_INVALID, "capacity %lld not in 0..2^32-1", (long long)capacity);
+    if (!mask || !depth || !count || !workspace || (capacity > 0 && !points)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    if (workspace_bytes < recogs_unproject_workspace_bytes(cam->width, cam->height))
+        return fail(RECOGS_ERR_INVALID, "workspace of %zu bytes, needs %zu", workspace_bytes,
+                    recogs_unproject_workspace_bytes(cam->width, cam->height));
+    if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(RECOGS_ERR_INVALID, "workspace not 4-byte aligned");
+    launch_unproject(make_cam(*cam, 16, 16), mask, keep, depth, (int64_t)cam->width * cam->height, (uint32_t *)workspace,
+                     count, points, capacity, stream);
+    return hip_check("unproject");
+}
+
+recogs_status recogs_reproject_mask(const recogs_camera *cam, const float *points, int64_t n, int64_t stride,
+                                    float quad_px, const float *depth, float depth_eps, uint8_t *mask,
+                                    hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if (n < 0 || n > 0x7fffffffLL || stride < n) return fail(RECOGS_ERR_INVALID, "n %lld / stride %lld", (long long)n, (long long)stride);
+    if (!(quad_px > 0.f && quad_px <= 64.f)) return fail(RECOGS_ERR_INVALID, "quad_px %g not in (0, 64]", (double)quad_px);
+    if (!(depth_eps >= 0.f && std::isfinite(depth_eps))) return fail(RECOGS_ERR_INVALID, "depth_eps %g not finite and >= 0", (double)depth_eps);
+    if (!mask || (n > 0 && !points)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    launch_reproject(make_cam(*cam, 16, 16), points, n, stride, quad_px, depth, depth_eps, mask, stream);
+    return hip_check("reproject_mask");
+}
+
+recogs_status recogs_tint(const float *image, const uint8_t *mask, const float t[3], float *out, int64_t pixels,
+                          hipStream_t stream) {
+    g_err[0] = 0;
+    if (pixels < 0) return fail(RECOGS_ERR_INVALID, "pixels < 0");
+    if (!t || (pixels > 0 && (!image || !mask || !out))) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(t[2])) return fail(RECOGS_ERR_INVALID, "tint not finite");
+    launch_tint(image, mask, t, out, pixels, stream);
+    return hip_check("tint");
 }
 
 }  // extern "C"

@@ -114,6 +114,20 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, depth=_Ptr(dep), depth_tau=1.5), ws, 1, 0) == -1
     assert status(B.recogs_render, sc, cam, B.opts_struct((32, 8), 2, depth=_Ptr(dep)), ws, 1, 0) == -3
     assert status(B.recogs_render, sc, cam, B.opts_struct((8, 8), 4, depth=_Ptr(dep)), ws, 1, 0) == -3
+    # selection steps
+    assert R.recogs_unproject_workspace_bytes(0, 5) == 0 and R.recogs_unproject_workspace_bytes(64, 64) >= 4 * 5
+    nb = R.recogs_unproject_workspace_bytes(64, 64)
+    assert status(B.recogs_unproject, cam, 8, 0, 8, 8, -1, 8, 256, nb, 0) == -1          # capacity < 0
+    assert status(B.recogs_unproject, cam, 0, 0, 8, 8, 10, 8, 256, nb, 0) == -1          # mask NULL
+    assert status(B.recogs_unproject, cam, 8, 0, 8, 8, 10, 8, 256, nb - 1, 0) == -1      # workspace too small
+    assert status(B.recogs_unproject, cam, 8, 0, 8, 8, 10, 8, 258, nb, 0) == -1          # workspace misaligned
+    assert status(B.recogs_reproject_mask, cam, 8, 10, 5, 2.0, 0, 0.0, 8, 0) == -1       # stride < n
+    assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 0.0, 0, 0.0, 8, 0) == -1      # quad_px 0
+    assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 65.0, 0, 0.0, 8, 0) == -1     # quad_px > 64
+    assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 2.0, 0, -1.0, 8, 0) == -1     # depth_eps < 0
+    assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 2.0, 0, 0.0, 0, 0) == -1      # mask NULL
+    assert status(B.recogs_tint, 8, 8, (1.0, float("nan"), 1.0), 8, 10, 0) == -1
+    assert status(B.recogs_tint, 0, 8, (1.0, 1.0, 1.0), 8, 10, 0) == -1
     # invalid scene fields
     bad = B.Scene()
     bad.n, bad.stride, bad.sh_degree = 10, 5, 0

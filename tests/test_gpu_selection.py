@@ -1,0 +1,156 @@
+"""Selection steps around the renderer on the GPU (Sec. 3.2, 3.3): unprojection of a
+sampled 2D selection, reprojection of a point cloud into a view as a depth-tested
+mask, and the tint. Parity with the FP64 selection oracle on the same seeded inputs:
+the unprojected count and order exactly, the points within float32 rounding, the mask
+between the oracle's sure and possible sets, the tint bit-exact.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import selection as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2511_18441_amd as R
+    return R
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a if dtype is None else np.asarray(a, dtype))).cuda()
+
+
+def _depth_of(orc, scene, cam, tau=0.5):
+    """The oracle's rough depth map of a view, rounded to float32 (the stored map)."""
+    pr = orc.project(scene, cam)
+    d, _ = orc.depth_windows(pr, [(0, 0, cam.width, cam.height)], tau)
+    return d.reshape(cam.height, cam.width).astype(np.float32)
+
+
+def _synthetic_depth(seed, H, W, zero_frac=0.1):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(1.0, 6.0, (H, W)).astype(np.float32)
+    d[rng.random((H, W)) < zero_frac] = 0
+    return d
+
+
+CAMS = {
+    "tiny": lambda: synth.make_tiny().view.camera,
+    "ragged": lambda: synth.orbit_camera(97, 61, 60.0, 3.0, 0.4, 0.3),
+    "1080p": lambda: synth.make_precision(n=1000).view.camera,
+}
+
+
+@pytest.mark.parametrize("which", ["tiny", "ragged", "1080p"])
+def test_unproject_parity(R, which):
+    cam = CAMS[which]()
+    H, W = cam.height, cam.width
+    mask = synth.brush_mask(W, H, 0.45 * W, 0.55 * H, 0.35 * min(W, H))
+    keep = synth.sample_keep(11, mask)
+    depth = _synthetic_depth(12, H, W)
+    X, pix = S.unproject(cam, mask, keep, depth)
+    pts, n = R.unproject(cam, _t(mask), _t(keep), _t(depth))
+    assert n == X.shape[0] and n > 0
+    got = pts.cpu().numpy().T.astype(np.float64)
+    tol = S.unproject_tolerance(cam, depth.reshape(-1)[pix])[:, None]
+    err = np.abs(got - X)
+    assert np.all(err <= tol), (which, float((err / tol).max()))
+    print(f"{which}: {n} points, max err / bound {float((err / tol).max()):.3f}")
+
+
+def test_unproject_keep_none_capacity_and_empty(R):
+    cam = CAMS["ragged"]()
+    H, W = cam.height, cam.width
+    mask = synth.brush_mask(W, H, 40.0, 30.0, 20.0)
+    depth = _synthetic_depth(13, H, W)
+    X, _ = S.unproject(cam, mask, None, depth)
+    pts, n = R.unproject(cam, _t(mask), None, _t(depth))
+    assert n == X.shape[0]
+    # capacity below the count: the first `capacity` points, the full count
+    cap = n // 3
+    pts_c, n_c = R.unproject(cam, _t(mask), None, _t(depth), capacity=cap)
+    assert n_c == n and pts_c.shape[1] == cap
+    assert np.array_equal(pts_c.cpu().numpy(), pts[:, :cap].cpu().numpy())
+    # nothing selected
+    pts0, n0 = R.unproject(cam, _t(np.zeros((H, W), np.uint8)), None, _t(depth))
+    assert n0 == 0 and pts0.shape[1] == 0
+
+
+@pytest.mark.parametrize("quad,eps", [(1.0, 0.1), (2.5, 0.05), (4.0, 0.0)])
+def test_reproject_parity_across_views(R, orc, quad, eps):
+    """The selection of one view, unprojected with that view's rough depth (oracle),
+    drawn into a second view against the second view's rough depth."""
+    w = synth.make_tiny()
+    camA = w.view.camera
+    camB = synth.orbit_camera(128, 96, 60.0, 3.0, 0.9, 0.25)
+    dA = _depth_of(orc, w.scene, camA)
+    dB = _depth_of(orc, w.scene, camB)
+    mask = synth.brush_mask(128, 128, 64.0, 64.0, 30.0)
+    keep = synth.sample_keep(14, mask)
+    X, _ = S.unproject(camA, mask, keep, dA)
+    X32 = X.astype(np.float32)
+    lo, hi = S.reproject_mask(camB, X32, quad, dB, eps)
+    got = R.reproject_mask(camB, _t(X32.T), quad, _t(dB), eps).cpu().numpy()
+    assert np.all(lo <= got) and np.all(got <= hi), (int((got < lo).sum()), int((got > hi).sum()))
+    assert lo.sum() > 100 and (hi != lo).sum() <= 0.01 * lo.sum()
+    # no depth test
+    lo, hi = S.reproject_mask(camB, X32, quad)
+    got = R.reproject_mask(camB, _t(X32.T), quad).cpu().numpy()
+    assert np.all(lo <= got) and np.all(got <= hi)
+
+
+def test_reproject_1080p_large_cloud_and_stride(R):
+    import torch
+    cam = CAMS["1080p"]()
+    rng = np.random.default_rng(15)
+    X = rng.normal(0.0, 1.0, (200_000, 3)).astype(np.float32)
+    d = _synthetic_depth(16, cam.height, cam.width, zero_frac=0.2) * np.float32(0.8)
+    lo, hi = S.reproject_mask(cam, X, 2.0, d, 0.02)
+    buf = torch.zeros((3, 200_128), dtype=torch.float32, device="cuda")   # stride > n
+    buf[:, :200_000] = _t(X.T)
+    out = torch.full((cam.height, cam.width), 7, dtype=torch.uint8, device="cuda")   # overwritten
+    got = R.reproject_mask(cam, buf[:, :200_000], 2.0, _t(d), 0.02, mask=out).cpu().numpy()
+    assert np.all(lo <= got) and np.all(got <= hi)
+    assert got.max() == 1 and lo.sum() > 10_000
+    # an empty cloud clears the mask
+    got = R.reproject_mask(cam, buf[:, :0], 2.0, _t(d), 0.02, mask=out).cpu().numpy()
+    assert got.sum() == 0
+
+
+def test_tint_bit_exact(R):
+    import torch
+    rng = np.random.default_rng(17)
+    img = rng.random((61, 97, 3)).astype(np.float32)
+    mask = (rng.random((61, 97)) < 0.4).astype(np.uint8)
+    t = np.float32([0.3, 0.7, 1.1])
+    want = S.tint(img, mask, t)
+    got = R.tint(_t(img), _t(mask), t).cpu().numpy()
+    assert np.array_equal(got, want)
+    x = _t(img)
+    R.tint(x, _t(mask), t, out=x)      # in place
+    assert np.array_equal(x.cpu().numpy(), want)
+    torch.cuda.synchronize()
+
+
+def test_render_depth_unproject_reproject_round_trip(R):
+    """A property that holds at any size: the selection unprojected with the GPU's own
+    rough depth map and drawn back into the same view as unit squares against that
+    map marks exactly the kept selected pixels that have a depth."""
+    import torch
+    w = synth.make_precision()
+    cam = w.view.camera
+    d = R.DeviceScene(w.scene)
+    ws = R.DeviceWorkspace(d.n, cam.width, cam.height, (32, 32))
+    depth = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
+    R.render(d, cam, ws, (32, 32), 1, depth=depth, depth_tau=0.5)
+    mask = synth.brush_mask(cam.width, cam.height, 960.0, 540.0, 300.0)
+    keep = synth.sample_keep(18, mask)
+    pts, n = R.unproject(cam, _t(mask), _t(keep), depth)
+    back = R.reproject_mask(cam, pts, 1.0, depth, 1e-4).cpu().numpy()
+    want = ((mask != 0) & (keep != 0) & (depth.cpu().numpy() > 0)).astype(np.uint8)
+    assert n == int(want.sum()) and n > 100_000
+    assert np.array_equal(back, want)
