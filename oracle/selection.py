@@ -166,3 +166,54 @@ def tint(image, mask, t):
     m = np.asarray(mask).reshape(img.shape[:-1]) != 0
     prod = (img.astype(np.float64) * np.asarray(t, np.float32).astype(np.float64)).astype(np.float32)
     return np.where(m[..., None], prod, img)
+
+
+# ---------------------------------------------------------------------------
+# Statistical outlier removal of the unprojected cloud (Sec. 3.2, Fig. 2 caption:
+# mean distance to 16 neighbours, standard-deviation scale 0.007).
+# Reading: D_i = mean Euclidean distance from point i to its k nearest other points
+# (all others when there are fewer than k); mu, sigma = mean and population standard
+# deviation of D over the cloud; point i is kept iff D_i <= mu + std_ratio * sigma.
+# ---------------------------------------------------------------------------
+def knn_mean_distance(points, k=16):
+    """D_i for every point of a (P, 3) cloud. The k + 1 smallest distances from a point
+    to the cloud include its own zero; their sum is the sum of the k smallest distances
+    to the other points (a duplicate's zero and the point's own are interchangeable).
+    scipy's k-d tree query is the library step."""
+    from scipy.spatial import cKDTree
+    X = np.asarray(points, np.float64).reshape(-1, 3)
+    P = X.shape[0]
+    if P <= 1:
+        return np.zeros(P)
+    kk = min(k, P - 1)
+    d, _ = cKDTree(X).query(X, k=kk + 1)
+    return d.reshape(P, kk + 1).sum(axis=1) / kk
+
+
+def knn_mean_distance_brute(points, k=16):
+    """The same by sorting every row of the full distance matrix (tiny clouds)."""
+    X = np.asarray(points, np.float64).reshape(-1, 3)
+    P = X.shape[0]
+    if P <= 1:
+        return np.zeros(P)
+    kk = min(k, P - 1)
+    out = np.empty(P)
+    for i in range(P):
+        dist = np.sqrt(((X - X[i]) ** 2).sum(axis=1))
+        dist = np.delete(dist, i)
+        out[i] = np.sort(dist)[:kk].mean()
+    return out
+
+
+def outlier_filter(points, k=16, std_ratio=0.007):
+    """(keep, flag, D, threshold): keep[i] = D_i <= mu + std_ratio sigma; flag marks the
+    points whose D lies within float32 rounding of the threshold."""
+    D = knn_mean_distance(points, k)
+    if D.size == 0:
+        return np.zeros(0, bool), np.zeros(0, bool), D, 0.0
+    mu = D.mean()
+    sigma = D.std()
+    thr = mu + float(np.float32(std_ratio)) * sigma
+    keep = D <= thr
+    flag = np.abs(D - thr) <= 1e-5 * max(thr, 1e-30) + 1e-30
+    return keep, flag, D, thr

@@ -140,3 +140,57 @@ def test_tint_exact_products():
     t = np.float32([0.3, 0.7, 1.1])
     out = S.tint(img, mask, t)
     np.testing.assert_array_equal(out[m], img[m] * t)    # numpy's float32 product is rounded once too
+
+
+# ---------------------------------------------------------------------------
+# statistical outlier removal (Sec. 3.2, Fig. 2)
+# ---------------------------------------------------------------------------
+def test_knn_mean_distance_matches_brute_force():
+    rng = np.random.default_rng(21)
+    X = rng.normal(0, 1, (300, 3))
+    X[:5] = X[5]                                    # duplicates: zero distances
+    for k in (1, 4, 16, 32):
+        np.testing.assert_allclose(S.knn_mean_distance(X, k), S.knn_mean_distance_brute(X, k), rtol=1e-12)
+    # fewer points than k: the mean over all the others
+    Y = X[:7]
+    np.testing.assert_allclose(S.knn_mean_distance(Y, 16), S.knn_mean_distance_brute(Y, 6), rtol=1e-12)
+
+
+def test_knn_mean_distance_on_a_lattice():
+    # interior point of a cubic lattice of spacing s: 6 neighbours at s, 12 at s sqrt(2)
+    s = 0.25
+    g = np.arange(8) * s
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    D = S.knn_mean_distance(X, 16)
+    interior = np.all((X > 1.5 * s) & (X < g[-1] - 1.5 * s), axis=1)
+    np.testing.assert_allclose(D[interior], (6 * s + 10 * math.sqrt(2) * s) / 16, rtol=1e-13)
+    D6 = S.knn_mean_distance(X, 6)
+    np.testing.assert_allclose(D6[interior], s, rtol=1e-13)
+
+
+def test_outlier_filter_removes_isolated_points_and_is_rigid_invariant():
+    s = 0.25
+    g = np.arange(8) * s
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    X = np.concatenate([X, [[10.0, 10.0, 10.0], [-8.0, 1.0, 0.5]]])
+    keep, flag, D, thr = S.outlier_filter(X, 16, 0.007)
+    assert not keep[-1] and not keep[-2]
+    interior = np.all((X > 1.5 * s) & (X < g[-1] - 1.5 * s), axis=1)
+    assert np.all(keep[interior])
+    mu, sd = D.mean(), math.sqrt(((D - D.mean()) ** 2).mean())
+    assert thr == pytest.approx(mu + float(np.float32(0.007)) * sd, rel=1e-14)
+    # a rotation and a translation change no distance
+    th = 0.7
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    keep2, _, D2, _ = S.outlier_filter(X @ Rz.T + [3.0, -1.0, 2.0], 16, 0.007)
+    np.testing.assert_allclose(D2, D, rtol=1e-12, atol=1e-14)
+    assert np.array_equal(keep2, keep)
+
+
+def test_outlier_filter_degenerate_clouds():
+    keep, flag, D, thr = S.outlier_filter(np.zeros((0, 3)))
+    assert keep.size == 0
+    keep, _, D, _ = S.outlier_filter(np.array([[1.0, 2.0, 3.0]]))
+    assert keep.tolist() == [True] and D.tolist() == [0.0]
+    keep, _, D, _ = S.outlier_filter(np.ones((5, 3)))     # all coincident: every distance 0, all kept
+    assert keep.all() and np.all(D == 0)
