@@ -347,6 +347,24 @@ recogs_status recogs_reproject_mask(const recogs_camera *cam, const float *point
 recogs_status recogs_tint(const float *image, const uint8_t *mask, const float t[3], float *out, int64_t pixels,
                           hipStream_t stream);
 
+/* Statistical outlier removal of the unprojected cloud (Sec. 3.2, Fig. 2 caption: the
+ * mean distance to 16 neighbours, a standard-deviation scale of 0.007). For each of
+ * the n points (points float [3][stride], finite coordinates) D_i = mean Euclidean
+ * distance to its k nearest other points (to all others when n - 1 < k; 0 when n = 1);
+ * with mu and sigma the mean and population standard deviation of D over the cloud,
+ * point i is kept iff D_i <= mu + std_ratio sigma. Outputs (device, overwritten):
+ * mean_dist float [n] = D; keep uint8 [n] (1 kept); out_count uint32 [1] = kept count;
+ * out_points float [3][out_stride] (NULL = no compaction) = the kept points in input
+ * order. The nearest neighbours are exact (a hashed-grid search with a whole-cloud
+ * scan for points far from the rest). workspace: recogs_outlier_workspace_bytes(n)
+ * bytes of device memory, 256-byte aligned, overwritten. No host synchronisation.
+ * INVALID: n < 0, stride < n, out_stride < n, std_ratio < 0, NULL pointer, workspace
+ * too small or misaligned; UNSUPPORTED: k not one of 4, 8, 16, 32. */
+size_t recogs_outlier_workspace_bytes(int64_t n);
+recogs_status recogs_remove_outliers(const float *points, int64_t n, int64_t stride, int32_t k, float std_ratio,
+                                     float *mean_dist, uint8_t *keep, float *out_points, int64_t out_stride,
+                                     uint32_t *out_count, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- batched form ------------------------------------------------------------ */
 
 /* One render of a batch (host struct): a scene, a camera, an optional fused recolour

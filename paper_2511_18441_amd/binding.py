@@ -29,7 +29,7 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
-                "recogs_last_error")
+                "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -120,10 +120,14 @@ def lib():
         L.recogs_unproject.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         L.recogs_reproject_mask.argtypes = [P(Camera), vp, i64, i64, f32, vp, f32, vp, vp]
         L.recogs_tint.argtypes = [vp, vp, P(f32), vp, i64, vp]
+        L.recogs_outlier_workspace_bytes.argtypes = [i64]
+        L.recogs_outlier_workspace_bytes.restype = ctypes.c_size_t
+        L.recogs_remove_outliers.argtypes = [vp, i64, i64, i32, f32, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         L.recogs_last_error.restype = ctypes.c_char_p
         for name in ENTRY_POINTS:
             if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release",
-                            "recogs_dssim_workspace_bytes", "recogs_unproject_workspace_bytes"):
+                            "recogs_dssim_workspace_bytes", "recogs_unproject_workspace_bytes",
+                            "recogs_outlier_workspace_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -263,11 +267,45 @@ def reproject_mask(cam, points, quad_px, depth=None, depth_eps=0.0, mask=None):
         mask = torch.empty((cam.height, cam.width), dtype=torch.uint8, device=points.device)
     n = points.shape[1]
     stride = points.stride(0) if n > 0 else 0
-    if n > 0 and points.stride(1) != 1:
+    if n > 1 and points.stride(1) != 1:
         raise ValueError("points must have unit column stride")
     recogs_reproject_mask(c, points.data_ptr() if n > 0 else None, n, stride, quad_px,
                           depth.data_ptr() if depth is not None else None, depth_eps, mask.data_ptr())
     return mask
+
+
+def recogs_outlier_workspace_bytes(n) -> int:
+    return int(lib().recogs_outlier_workspace_bytes(int(n)))
+
+
+def recogs_remove_outliers(points, n, stride, k, std_ratio, mean_dist, keep, out_points, out_stride, out_count,
+                           workspace, workspace_bytes, stream=None):
+    return _check("recogs_remove_outliers", lib().recogs_remove_outliers(
+        points, int(n), int(stride), int(k), float(std_ratio), mean_dist, keep, out_points, int(out_stride), out_count,
+        workspace, int(workspace_bytes), _stream(stream)))
+
+
+def remove_outliers(points, k=16, std_ratio=0.007):
+    """recogs_remove_outliers of a (3, n) float32 device tensor (unit column stride).
+    Returns (kept points (3, m), keep uint8 (n,), mean distances (n,))."""
+    import torch
+    n = points.shape[1]
+    dev = points.device
+    if n > 1 and points.stride(1) != 1:
+        raise ValueError("points must have unit column stride")
+    stride = points.stride(0) if n > 0 else 0
+    dmean = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    keep = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((3, max(n, 1)), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    nb = recogs_outlier_workspace_bytes(n)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    recogs_remove_outliers(points.data_ptr() if n > 0 else None, n, stride, k, std_ratio, dmean.data_ptr(),
+                           keep.data_ptr(), out.data_ptr(), max(n, 1), cnt.data_ptr(), aligned, nb)
+    m = int(cnt.item())
+    return out[:, :m], keep[:n], dmean[:n]
 
 
 def tint(image, mask, t, out=None):

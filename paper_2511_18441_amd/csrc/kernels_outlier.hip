@@ -1,0 +1,459 @@
+// Statistical outlier removal of a point cloud (Sec. 3.2, Fig. 2 caption: mean distance
+// to 16 neighbours, standard-deviation scale 0.007):
+//   D_i = mean distance from point i to its k nearest other points (all others when
+//         there are fewer), mu / sigma = mean and population standard deviation of D,
+//   keep i  iff  D_i <= mu + std_ratio sigma.
+//
+// Exact k-nearest neighbours through a hashed uniform grid:
+//   1. bounding box (reduction), then per-axis 1024-bin histograms over it; the cell
+//      size h is the largest 1%-99% quantile extent divided by ceil(2 n^(1/3)) (at most
+//      128), so far-away stray points do not coarsen the grid for the rest;
+//   2. each point's cell (floor((x - min) / h) per axis) is hashed into a table of
+//      2^b slots (b = log2 of about 2n); a radix sort by slot and a range pass give each
+//      slot its run of points (slot order is also the query order: queries of one wave
+//      start in nearby cells);
+//   3. per query, the cells of Chebyshev rings r = 0, 1, ... are scanned (points of other
+//      cells that share a slot are skipped by re-deriving their cell), keeping the k
+//      smallest squared distances in registers (sorted insertion); after ring r >= 1 the
+//      search stops once the k-th distance is within (r - 1/16) h, the distance below
+//      which no unscanned cell lies (the 1/16 absorbs float32 rounding of the cell
+//      coordinates). A query whose rings reach kOlMaxRing without that bound (a far
+//      stray point) scans the whole cloud instead.
+//   4. double-precision block sums of D and D^2 give mu, sigma and the threshold; the
+//      keep mask and the compaction of the kept points (input order) follow.
+#include "recogs_internal.hpp"
+
+namespace recogs {
+
+int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
+                   hipStream_t);
+void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
+void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
+void launch_excl_scan_u32(uint32_t *, uint32_t, uint32_t *, hipStream_t);
+
+constexpr int kOlBins = 1024;
+constexpr int kOlMaxDim = 128;
+constexpr int kOlMaxRing = 4;
+constexpr int kOlRedBlocks = 512;              // grid of the reductions (grid-stride)
+constexpr int kOlItems = 4;                    // points per thread of the keep/compaction passes
+constexpr int kOlBlock = 256 * kOlItems;
+constexpr float kOlClamp = 1048576.f;          // cell coordinates are clamped to +-2^20
+// Ring-search guard: a float32 cell coordinate f = (v - min) / h is within 3 2^-24 |f|
+// of its exact value, so for |f| <= 2^16 two coordinates are within 0.024 cells of the
+// exact difference; the stop bound keeps kOlMargin = 1/16 cell of slack for it. Queries
+// beyond 2^16 cells from the box corner scan the whole cloud.
+constexpr float kOlQueryLimit = 65536.f;
+constexpr float kOlMargin = 1.f / 16.f;
+
+// Workspace header (device, written by the setup kernels).
+struct OlHdr {
+    float mn[3], mx[3];   // bounding box
+    float h, inv_h;       // cell size and its reciprocal
+    uint32_t mask;        // slots - 1
+    uint32_t pad[7];
+    double thr;           // mu + std_ratio sigma
+    double mu, sigma;
+};
+
+__device__ __forceinline__ void ol_load(const float *__restrict__ pts, int64_t stride, int64_t i, float &x, float &y,
+                                        float &z) {
+    x = pts[i];
+    y = pts[stride + i];
+    z = pts[2 * stride + i];
+}
+
+__device__ __forceinline__ int ol_coord(float v, float mn, float inv_h) {
+    const float f = fminf(fmaxf(floorf((v - mn) * inv_h), -kOlClamp), kOlClamp);
+    return (int)f;
+}
+
+__device__ __forceinline__ uint32_t ol_hash(int cx, int cy, int cz, uint32_t mask) {
+    return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u)) & mask;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// 1a. per-workgroup bounding boxes -> part[blk][6]
+__global__ __launch_bounds__(256) void k_ol_bbox(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                 float *__restrict__ part) {
+    __shared__ float s[4][6];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float p[3];
+        ol_load(pts, stride, i, p[0], p[1], p[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], p[a]);
+            hi[a] = fmaxf(hi[a], p[a]);
+        }
+    }
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (lane_id() == 0)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            s[w][a] = lo[a];
+            s[w][3 + a] = hi[a];
+        }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float v = s[0][threadIdx.x];
+        for (int k = 1; k < 4; ++k) v = threadIdx.x < 3 ? fminf(v, s[k][threadIdx.x]) : fmaxf(v, s[k][threadIdx.x]);
+        part[blockIdx.x * 6 + threadIdx.x] = v;
+    }
+}
+
+// 1b. final box (one workgroup)
+__global__ __launch_bounds__(64) void k_ol_bbox_final(const float *__restrict__ part, int nblk, OlHdr *__restrict__ hdr) {
+    const int a = threadIdx.x;
+    if (a >= 6) return;
+    float v = a < 3 ? INFINITY : -INFINITY;
+    for (int b = 0; b < nblk; ++b) v = a < 3 ? fminf(v, part[b * 6 + a]) : fmaxf(v, part[b * 6 + a]);
+    if (a < 3) hdr->mn[a] = v;
+    else hdr->mx[a - 3] = v;
+}
+
+// 1c. per-axis histograms over the box (LDS counts, then one atomic per bin and
+// workgroup; integer counts, so the result is independent of the order)
+__global__ __launch_bounds__(256) void k_ol_hist(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                 const OlHdr *__restrict__ hdr, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[3 * kOlBins];
+    for (int k = threadIdx.x; k < 3 * kOlBins; k += 256) s_h[k] = 0;
+    __syncthreads();
+    float mn[3], sc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mn[a] = hdr->mn[a];
+        const float e = hdr->mx[a] - mn[a];
+        sc[a] = e > 0.f ? (float)kOlBins / e : 0.f;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float p[3];
+        ol_load(pts, stride, i, p[0], p[1], p[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int b = (int)((p[a] - mn[a]) * sc[a]);
+            b = b < 0 ? 0 : (b >= kOlBins ? kOlBins - 1 : b);
+            atomicAdd(&s_h[a * kOlBins + b], 1u);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 3 * kOlBins; k += 256)
+        if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
+}
+
+// 1d. cell size from the 1%-99% quantile extents (one thread per axis, then thread 0)
+__global__ __launch_bounds__(64) void k_ol_setup(const uint32_t *__restrict__ hist, int64_t n, uint32_t slot_mask,
+                                                 OlHdr *__restrict__ hdr) {
+    __shared__ float s_ext[3];
+    const int a = threadIdx.x;
+    if (a < 3) {
+        const float e = hdr->mx[a] - hdr->mn[a];
+        const uint64_t lo_need = (uint64_t)((double)n * 0.01), hi_need = (uint64_t)((double)n * 0.99);
+        uint64_t cum = 0;
+        int blo = -1, bhi = kOlBins - 1;
+        for (int b = 0; b < kOlBins; ++b) {
+            cum += hist[a * kOlBins + b];
+            if (blo < 0 && cum > lo_need) blo = b;
+            if (cum > hi_need || cum >= (uint64_t)n) { bhi = b; break; }
+        }
+        if (blo < 0) blo = 0;
+        s_ext[a] = (float)(bhi - blo + 1) * (e / (float)kOlBins);
+    }
+    __syncthreads();
+    if (a == 0) {
+        const float L = fmaxf(s_ext[0], fmaxf(s_ext[1], s_ext[2]));
+        int D = (int)ceil(2.0 * cbrt((double)n));
+        D = D < 1 ? 1 : (D > kOlMaxDim ? kOlMaxDim : D);
+        float h = L / (float)D;
+        if (!(h > 0.f) || !isfinite(h)) h = 1.f;   // all points coincide (or a degenerate box)
+        hdr->h = h;
+        hdr->inv_h = 1.f / h;
+        hdr->mask = slot_mask;
+    }
+}
+
+// 2. slot keys
+__global__ __launch_bounds__(256) void k_ol_key(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                const OlHdr *__restrict__ hdr, uint32_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float x, y, z;
+    ol_load(pts, stride, i, x, y, z);
+    const float ih = hdr->inv_h;
+    keys[i] = ol_hash(ol_coord(x, hdr->mn[0], ih), ol_coord(y, hdr->mn[1], ih), ol_coord(z, hdr->mn[2], ih), hdr->mask);
+    vals[i] = (uint32_t)i;
+}
+
+template <int K>
+__device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
+    if (!(d2 < best[K - 1])) return;
+#pragma unroll
+    for (int q = K - 1; q > 0; --q) best[q] = d2 < best[q - 1] ? best[q - 1] : (d2 < best[q] ? d2 : best[q]);
+    best[0] = d2 < best[0] ? d2 : best[0];
+}
+
+// 3. k nearest neighbours of every point (one thread per point, slot order)
+template <int K>
+__global__ __launch_bounds__(256) void k_ol_knn(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                const OlHdr *__restrict__ hdr, const uint32_t *__restrict__ svals,
+                                                const uint2 *__restrict__ ranges, float *__restrict__ dmean) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t i = svals[s];
+    float x, y, z;
+    ol_load(pts, stride, i, x, y, z);
+    const float mnx = hdr->mn[0], mny = hdr->mn[1], mnz = hdr->mn[2], ih = hdr->inv_h, h = hdr->h;
+    const uint32_t mask = hdr->mask;
+    const int cx = ol_coord(x, mnx, ih), cy = ol_coord(y, mny, ih), cz = ol_coord(z, mnz, ih);
+    const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
+    float best[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) best[q] = INFINITY;
+    bool done = want == 0;
+    const bool clamped = fabsf((x - mnx) * ih) > kOlQueryLimit || fabsf((y - mny) * ih) > kOlQueryLimit ||
+                         fabsf((z - mnz) * ih) > kOlQueryLimit;
+    for (int r = 0; !done && !clamped && r < kOlMaxRing; ++r) {
+        for (int dz = -r; dz <= r; ++dz)
+            for (int dy = -r; dy <= r; ++dy) {
+                const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                const int step = face ? 1 : 2 * r;   // inside the ring's slab only dx = -r, r
+                for (int dx = -r; dx <= r; dx += step) {
+                    const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
+                    const uint2 rg = ranges[ol_hash(qx, qy, qz, mask)];
+                    for (uint32_t j = rg.x; j < rg.y; ++j) {
+                        const uint32_t o = svals[j];
+                        if (o == i) continue;
+                        float px, py, pz;
+                        ol_load(pts, stride, o, px, py, pz);
+                        if (ol_coord(px, mnx, ih) != qx || ol_coord(py, mny, ih) != qy || ol_coord(pz, mnz, ih) != qz)
+                            continue;   // another cell in the same slot
+                        const float ex = px - x, ey = py - y, ez = pz - z;
+                        ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+                    }
+                }
+            }
+        if (r >= 1) {
+            float kth = best[0];
+#pragma unroll
+            for (int q = 1; q < K; ++q) kth = q == want - 1 ? best[q] : kth;
+            const float bound = ((float)r - kOlMargin) * h;
+            done = kth <= bound * bound;
+        }
+    }
+    if (!done) {   // far from the rest: scan everything
+#pragma unroll
+        for (int q = 0; q < K; ++q) best[q] = INFINITY;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == (int64_t)i) continue;
+            float px, py, pz;
+            ol_load(pts, stride, j, px, py, pz);
+            const float ex = px - x, ey = py - y, ez = pz - z;
+            ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+        }
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int q = 0; q < K; ++q) sum += q < want ? sqrtf(best[q]) : 0.f;
+    dmean[i] = want > 0 ? sum / (float)want : 0.f;
+}
+
+// 4a. block sums of D and D^2 in double -> part[blk][2]
+__global__ __launch_bounds__(256) void k_ol_stats(const float *__restrict__ dmean, int64_t n, double *__restrict__ part) {
+    __shared__ double s[4][2];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double d = dmean[i];
+        a += d;
+        b += d * d;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if (lane_id() == 0) {
+        s[threadIdx.x >> 6][0] = a;
+        s[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s[0][0] + s[1][0] + s[2][0] + s[3][0];
+        part[2 * blockIdx.x + 1] = s[0][1] + s[1][1] + s[2][1] + s[3][1];
+    }
+}
+
+// 4b. threshold (one thread, fixed order)
+__global__ __launch_bounds__(64) void k_ol_thr(const double *__restrict__ part, int nblk, int64_t n, float std_ratio,
+                                               OlHdr *__restrict__ hdr) {
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    const double mu = n > 0 ? a / (double)n : 0.0;
+    double var = n > 0 ? b / (double)n - mu * mu : 0.0;
+    var = var > 0.0 ? var : 0.0;
+    hdr->mu = mu;
+    hdr->sigma = sqrt(var);
+    hdr->thr = mu + (double)std_ratio * sqrt(var);
+}
+
+// 4c. keep mask and kept count per workgroup of kOlBlock points
+__global__ __launch_bounds__(256) void k_ol_keep(const float *__restrict__ dmean, int64_t n, const OlHdr *__restrict__ hdr,
+                                                 uint8_t *__restrict__ keep, uint32_t *__restrict__ part) {
+    __shared__ uint32_t s_w[4];
+    const double thr = hdr->thr;
+    const int64_t base = (int64_t)blockIdx.x * kOlBlock;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kOlItems; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < n) {
+            const bool kp = (double)dmean[i] <= thr;
+            keep[i] = kp ? 1 : 0;
+            c += kp ? 1u : 0u;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// 4d. compaction of the kept points in input order (offsets from the scanned counts)
+__global__ __launch_bounds__(256) void k_ol_write(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                  const uint8_t *__restrict__ keep, const uint32_t *__restrict__ part,
+                                                  float *__restrict__ out, int64_t out_stride) {
+    __shared__ uint32_t s_w[4];
+    const int64_t base = (int64_t)blockIdx.x * kOlBlock;
+    const int l = (int)lane_id(), w = (int)(threadIdx.x >> 6);
+    uint32_t run = part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kOlItems; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        const bool take = i < n && keep[i] != 0;
+        const uint64_t bal = __ballot(take);
+        const uint32_t below = (uint32_t)__popcll(bal & ((1ull << l) - 1ull));
+        if (l == 0) s_w[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = run;
+        for (int q = 0; q < w; ++q) before += s_w[q];
+        const uint32_t total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+        if (take) {
+            const int64_t o = (int64_t)before + below;
+            out[o] = pts[i];
+            out[out_stride + o] = pts[stride + i];
+            out[2 * out_stride + o] = pts[2 * stride + i];
+        }
+        run += total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int outlier_slot_bits(int64_t n) {
+    int b = 10;
+    while (b < 22 && ((int64_t)1 << b) < 2 * n) ++b;
+    return b;
+}
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace pieces for n points (offsets in bytes, in this order).
+struct OlLayout {
+    size_t hdr, keys0, vals0, keys1, vals1, hist, shist, scount, ranges, bpart, spart, kpart, total;
+};
+
+size_t sort_count_words(uint64_t);
+
+static OlLayout ol_layout(int64_t n) {
+    OlLayout L;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t slots = (size_t)1 << outlier_slot_bits(n);
+    size_t o = 0;
+    auto take = [&](size_t b) { const size_t at = o; o += al(b); return at; };
+    L.hdr = take(sizeof(OlHdr));
+    L.keys0 = take(4 * nn);
+    L.vals0 = take(4 * nn);
+    L.keys1 = take(4 * nn);
+    L.vals1 = take(4 * nn);
+    L.hist = take(4 * 256 * kMaxPasses);
+    L.shist = take(4 * 3 * kOlBins);
+    L.scount = take(4 * sort_count_words((uint64_t)nn));
+    L.ranges = take(8 * slots);
+    L.bpart = take(4 * 6 * kOlRedBlocks);
+    L.spart = take(8 * 2 * kOlRedBlocks);
+    L.kpart = take(4 * ((nn + kOlBlock - 1) / kOlBlock + 1));
+    L.total = o;
+    return L;
+}
+
+size_t outlier_workspace_bytes(int64_t n) { return ol_layout(n).total; }
+
+template <int K>
+static void knn_launch(const float *pts, int64_t n, int64_t stride, const OlHdr *hdr, const uint32_t *svals,
+                       const uint2 *ranges, float *dmean, hipStream_t st) {
+    hipLaunchKernelGGL((k_ol_knn<K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, hdr, svals,
+                       ranges, dmean);
+}
+
+// k in {4, 8, 16, 32}: false (nothing launched) otherwise. out may be null (no compaction).
+bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float std_ratio, float *dmean, uint8_t *keep,
+                     float *out, int64_t out_stride, uint32_t *count, void *ws, hipStream_t st) {
+    if (k != 4 && k != 8 && k != 16 && k != 32) return false;
+    const OlLayout L = ol_layout(n);
+    char *b = (char *)ws;
+    OlHdr *hdr = (OlHdr *)(b + L.hdr);
+    uint32_t *k0 = (uint32_t *)(b + L.keys0), *v0 = (uint32_t *)(b + L.vals0);
+    uint32_t *k1 = (uint32_t *)(b + L.keys1), *v1 = (uint32_t *)(b + L.vals1);
+    uint32_t *kpart = (uint32_t *)(b + L.kpart);
+    if (n == 0) {
+        launch_excl_scan_u32(kpart, 0u, count, st);   // writes the count 0
+        return true;
+    }
+    const int bits = outlier_slot_bits(n);
+    const uint32_t slots = 1u << bits;
+    const int rb = (int)((n + 255) / 256 < kOlRedBlocks ? (n + 255) / 256 : kOlRedBlocks);
+    hipLaunchKernelGGL(k_ol_bbox, dim3(rb), dim3(256), 0, st, pts, n, stride, (float *)(b + L.bpart));
+    hipLaunchKernelGGL(k_ol_bbox_final, dim3(1), dim3(64), 0, st, (const float *)(b + L.bpart), rb, hdr);
+    launch_fill_u32((uint32_t *)(b + L.shist), 0u, 3 * kOlBins, st);
+    hipLaunchKernelGGL(k_ol_hist, dim3(rb), dim3(256), 0, st, pts, n, stride, hdr, (uint32_t *)(b + L.shist));
+    hipLaunchKernelGGL(k_ol_setup, dim3(1), dim3(64), 0, st, (const uint32_t *)(b + L.shist), n, slots - 1u, hdr);
+    hipLaunchKernelGGL(k_ol_key, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, hdr, k0, v0);
+    launch_fill_u32((uint32_t *)(b + L.hist), 0u, 256 * kMaxPasses, st);
+    const int alt = radix_sort_u32(k0, v0, k1, v1, (uint32_t)n, 0u, bits, (uint32_t *)(b + L.hist),
+                                   (uint32_t *)(b + L.scount), st);
+    const uint32_t *sk = alt ? k1 : k0, *sv = alt ? v1 : v0;
+    uint2 *ranges = (uint2 *)(b + L.ranges);
+    launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)slots, st);
+    launch_ranges32(sk, (uint32_t)n, ranges, st, nullptr);
+    if (k == 4) knn_launch<4>(pts, n, stride, hdr, sv, ranges, dmean, st);
+    else if (k == 8) knn_launch<8>(pts, n, stride, hdr, sv, ranges, dmean, st);
+    else if (k == 16) knn_launch<16>(pts, n, stride, hdr, sv, ranges, dmean, st);
+    else knn_launch<32>(pts, n, stride, hdr, sv, ranges, dmean, st);
+    hipLaunchKernelGGL(k_ol_stats, dim3(rb), dim3(256), 0, st, dmean, n, (double *)(b + L.spart));
+    hipLaunchKernelGGL(k_ol_thr, dim3(1), dim3(64), 0, st, (const double *)(b + L.spart), rb, n, std_ratio, hdr);
+    const uint32_t nblk = (uint32_t)((n + kOlBlock - 1) / kOlBlock);
+    hipLaunchKernelGGL(k_ol_keep, dim3(nblk), dim3(256), 0, st, dmean, n, hdr, keep, kpart);
+    launch_excl_scan_u32(kpart, nblk, count, st);
+    if (out)
+        hipLaunchKernelGGL(k_ol_write, dim3(nblk), dim3(256), 0, st, pts, n, stride, keep, kpart, out, out_stride);
+    return true;
+}
+
+}  // namespace recogs

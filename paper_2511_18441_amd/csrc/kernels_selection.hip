@@ -159,9 +159,16 @@ uint32_t unproject_blocks(int64_t pixels) { return (uint32_t)((pixels + kUnpBloc
 void launch_unproject(const CamDev &cam, const uint8_t *mask, const uint8_t *keep, const float *depth, int64_t P,
                       uint32_t *part, uint32_t *count, float *pts, int64_t cap, hipStream_t st) {
     const uint32_t nblk = unproject_blocks(P);
-    hipLaunchKernelGGL(k_unp_count, dim3(nblk), dim3(256), 0, st, mask, keep, depth, P, part);
+    if (nblk) hipLaunchKernelGGL(k_unp_count, dim3(nblk), dim3(256), 0, st, mask, keep, depth, P, part);
     hipLaunchKernelGGL(k_unp_scan, dim3(1), dim3(1024), 0, st, part, nblk, count);
-    hipLaunchKernelGGL(k_unp_write, dim3(nblk), dim3(256), 0, st, mask, keep, depth, P, (int)cam.W, part, cam, pts, cap);
+    if (nblk)
+        hipLaunchKernelGGL(k_unp_write, dim3(nblk), dim3(256), 0, st, mask, keep, depth, P, (int)cam.W, part, cam, pts, cap);
+}
+
+// exclusive scan of nblk counts in place, total to *count (the compaction step shared
+// with the outlier filter)
+void launch_excl_scan_u32(uint32_t *part, uint32_t nblk, uint32_t *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_unp_scan, dim3(1), dim3(1024), 0, st, part, nblk, count);
 }
 
 void launch_reproject(const CamDev &cam, const float *pts, int64_t n, int64_t stride, float quad_px, const float *depth,

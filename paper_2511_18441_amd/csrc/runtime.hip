@@ -49,6 +49,9 @@ void launch_unproject(const CamDev &, const uint8_t *, const uint8_t *, const fl
                       float *, int64_t, hipStream_t);
 void launch_reproject(const CamDev &, const float *, int64_t, int64_t, float, const float *, float, uint8_t *, hipStream_t);
 void launch_tint(const float *, const uint8_t *, const float *, float *, int64_t, hipStream_t);
+size_t outlier_workspace_bytes(int64_t);
+bool launch_outliers(const float *, int64_t, int64_t, int, float, float *, uint8_t *, float *, int64_t, uint32_t *, void *,
+                     hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
                        uint32_t *, uint32_t *, hipStream_t);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
@@ -748,6 +751,28 @@ recogs_status recogs_tint(const float *image, const uint8_t *mask, const float t
     if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(t[2])) return fail(RECOGS_ERR_INVALID, "tint not finite");
     launch_tint(image, mask, t, out, pixels, stream);
     return hip_check("tint");
+}
+
+size_t recogs_outlier_workspace_bytes(int64_t n) {
+    if (n < 0 || n > 0x7fffffffLL) return 0;
+    return outlier_workspace_bytes(n);
+}
+
+recogs_status recogs_remove_outliers(const float *points, int64_t n, int64_t stride, int32_t k, float std_ratio,
+                                     float *mean_dist, uint8_t *keep, float *out_points, int64_t out_stride,
+                                     uint32_t *out_count, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n < 0 || n > 0x7fffffffLL || stride < n) return fail(RECOGS_ERR_INVALID, "n %lld / stride %lld", (long long)n, (long long)stride);
+    if (k != 4 && k != 8 && k != 16 && k != 32) return fail(RECOGS_ERR_UNSUPPORTED, "k = %d not one of 4, 8, 16, 32", k);
+    if (!(std_ratio >= 0.f) || !std::isfinite(std_ratio)) return fail(RECOGS_ERR_INVALID, "std_ratio %g not finite and >= 0", (double)std_ratio);
+    if (!out_count || !workspace || (n > 0 && (!points || !mean_dist || !keep)))
+        return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    if (out_points && out_stride < n) return fail(RECOGS_ERR_INVALID, "out_stride %lld < n %lld", (long long)out_stride, (long long)n);
+    if (workspace_bytes < outlier_workspace_bytes(n))
+        return fail(RECOGS_ERR_INVALID, "workspace of %zu bytes, needs %zu", workspace_bytes, outlier_workspace_bytes(n));
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(RECOGS_ERR_INVALID, "workspace not 256-byte aligned");
+    launch_outliers(points, n, stride, k, std_ratio, mean_dist, keep, out_points, out_stride, out_count, workspace, stream);
+    return hip_check("remove_outliers");
 }
 
 }  // extern "C"

@@ -128,6 +128,16 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 2.0, 0, 0.0, 0, 0) == -1      # mask NULL
     assert status(B.recogs_tint, 8, 8, (1.0, float("nan"), 1.0), 8, 10, 0) == -1
     assert status(B.recogs_tint, 0, 8, (1.0, 1.0, 1.0), 8, 10, 0) == -1
+    # outlier removal
+    nb = R.recogs_outlier_workspace_bytes(100)
+    assert nb > 0 and R.recogs_outlier_workspace_bytes(-1) == 0
+    assert status(B.recogs_remove_outliers, 8, 100, 50, 16, 0.007, 8, 8, 0, 0, 8, 256, nb, 0) == -1   # stride < n
+    assert status(B.recogs_remove_outliers, 8, 100, 100, 12, 0.007, 8, 8, 0, 0, 8, 256, nb, 0) == -3  # k
+    assert status(B.recogs_remove_outliers, 8, 100, 100, 16, -1.0, 8, 8, 0, 0, 8, 256, nb, 0) == -1   # ratio < 0
+    assert status(B.recogs_remove_outliers, 8, 100, 100, 16, 0.007, 8, 8, 8, 50, 8, 256, nb, 0) == -1  # out_stride
+    assert status(B.recogs_remove_outliers, 8, 100, 100, 16, 0.007, 8, 8, 0, 0, 8, 256, nb - 1, 0) == -1
+    assert status(B.recogs_remove_outliers, 8, 100, 100, 16, 0.007, 8, 8, 0, 0, 8, 128, nb, 0) == -1  # misaligned
+    assert status(B.recogs_remove_outliers, 0, 100, 100, 16, 0.007, 8, 8, 0, 0, 8, 256, nb, 0) == -1  # NULL points
     # invalid scene fields
     bad = B.Scene()
     bad.n, bad.stride, bad.sh_degree = 10, 5, 0

@@ -154,3 +154,81 @@ def test_render_depth_unproject_reproject_round_trip(R):
     want = ((mask != 0) & (keep != 0) & (depth.cpu().numpy() > 0)).astype(np.uint8)
     assert n == int(want.sum()) and n > 100_000
     assert np.array_equal(back, want)
+
+
+# ---------------------------------------------------------------------------
+# statistical outlier removal (Sec. 3.2, Fig. 2)
+# ---------------------------------------------------------------------------
+def _cloud(seed, n, strays=0.02):
+    """Seeded clusters on thin slabs (surface-like), uniform strays and exact duplicates."""
+    rng = np.random.default_rng(seed)
+    m = n - int(strays * n)
+    centres = rng.uniform(-2, 2, (8, 3))
+    lab = rng.integers(0, 8, m)
+    pts = centres[lab] + rng.normal(0, 1, (m, 3)) * np.array([0.3, 0.3, 0.01])
+    pts = np.concatenate([pts, rng.uniform(-4, 4, (n - m, 3))])
+    pts[1:20] = pts[0]
+    return pts.astype(np.float32)
+
+
+def _check_outliers(R, X32, k, ratio, what):
+    Xd = X32.astype(np.float64)
+    keep_o, flag_o, D_o, thr = S.outlier_filter(Xd, k, ratio)
+    out, keep, D = R.remove_outliers(_t(X32.T), k, ratio)
+    D = D.cpu().numpy().astype(np.float64)
+    keep = keep.cpu().numpy().astype(bool)
+    err = np.abs(D - D_o)
+    tol = 4e-6 * D_o + 1e-7
+    assert np.all(err <= tol), (what, float((err / tol).max()))
+    ok = ~flag_o
+    assert np.array_equal(keep[ok], keep_o[ok]), (what, int((keep[ok] != keep_o[ok]).sum()))
+    assert np.array_equal(out.cpu().numpy(), X32[keep].T), what
+    return int(keep.sum()), int(flag_o.sum())
+
+
+@pytest.mark.parametrize("k", [16, 4, 8, 32])
+def test_outliers_parity_clusters(R, k):
+    X = _cloud(31, 20_000 if k == 16 else 5_000)
+    kept, flagged = _check_outliers(R, X, k, 0.007, f"clusters k={k}")
+    print(f"k={k}: kept {kept} of {X.shape[0]}, flagged {flagged}")
+
+
+def test_outliers_parity_unprojected_selection(R, orc):
+    """The cloud of the selection pipeline: the tiny view's selection unprojected with
+    the oracle's rough depth map."""
+    w = synth.make_tiny()
+    cam = w.view.camera
+    d = _depth_of(orc, w.scene, cam)
+    mask = synth.brush_mask(128, 128, 64.0, 64.0, 40.0)
+    X, _ = S.unproject(cam, mask, synth.sample_keep(32, mask), d)
+    kept, flagged = _check_outliers(R, X.astype(np.float32), 16, 0.007, "unprojected")
+    assert 0 < kept < X.shape[0]
+
+
+def test_outliers_parity_large_surface_cloud(R):
+    """A 1080p selection's worth of points (~280k) from a smooth seeded depth field."""
+    cam = CAMS["1080p"]()
+    H, W = cam.height, cam.width
+    yy, xx = np.mgrid[0:H, 0:W]
+    depth = (3.0 + 0.5 * np.sin(xx / 150.0) * np.cos(yy / 110.0)).astype(np.float32)
+    rng = np.random.default_rng(33)
+    spikes = rng.random((H, W)) < 0.002
+    depth[spikes] *= np.float32(1.5)            # flying pixels: the outliers to remove
+    mask = synth.brush_mask(W, H, 960.0, 540.0, 378.0)
+    X, _ = S.unproject(cam, mask, synth.sample_keep(34, mask), depth)
+    kept, flagged = _check_outliers(R, X.astype(np.float32), 16, 0.007, "surface")
+    print(f"surface: kept {kept} of {X.shape[0]}, flagged {flagged}")
+
+
+def test_outliers_degenerate_clouds(R):
+    import torch
+    for X in [np.zeros((0, 3), np.float32), np.float32([[1, 2, 3]]), np.ones((5, 3), np.float32),
+              np.float32([[0, 0, 0], [1e4, 0, 0], [0, 1e4, 0], [0.1, 0, 0], [0, 0.1, 0], [0.1, 0.1, 0]]),
+              _cloud(35, 12)]:
+        keep_o, flag_o, D_o, _ = S.outlier_filter(X.astype(np.float64), 16, 0.007)
+        out, keep, D = R.remove_outliers(_t(X.T) if X.shape[0] else torch.zeros((3, 0), device="cuda"), 16, 0.007)
+        assert D.shape[0] == X.shape[0]
+        np.testing.assert_allclose(D.cpu().numpy(), D_o, rtol=4e-6, atol=1e-7)
+        ok = ~flag_o
+        assert np.array_equal(keep.cpu().numpy().astype(bool)[ok], keep_o[ok])
+        assert out.shape[1] == int(keep.cpu().numpy().sum())
