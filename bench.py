@@ -1,6 +1,6 @@
 """Benchmark: recolour + render frames/s of a 1,000,000-Gaussian, SH-degree-3 scene at
-1920x1080 (16x16 tiles) on one MI355X, with the roofline of the dominant kernel and
-the FP64 CPU oracle timed beside it.
+1920x1080 (32x32 sort tiles, one pixel per blend thread by default) on one MI355X, with
+the roofline of the dominant kernel and the FP64 CPU oracle timed beside it.
 
 A step (frame) = recogs_recolor of the selected Gaussians (out of place, from the
 pristine SH into the render copy, so frames do not compound the edit) followed by
@@ -16,10 +16,12 @@ Besides the headline (FP32 storage) the same run measures the other forms on the
 GPU: FP16 and BF16 storage of the same scene, the batched form (8 scenes of 0.1M-3M
 Gaussians x 4 views, one HIP-graph replay per batch, tile shape and pixels per thread
 from the autotuner; beside it the same 32 renders one call at a time), and the
-differentiation form (8 views at 1280x720: forward, L2 loss and backward).
+differentiation form (8 views at 1280x720: forward, L2 loss and backward), the SH refit
+(eq. 7 loss, Adam), the pixel-selection chain (rough depth map, unprojection, outlier
+removal, reprojection, tint) and the selection-driven edit loop of Sec. 3.3.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|bf16]
-                  [--no-cpu-baseline] [--no-forms] [--copy-calibration]
+                  [--no-cpu-baseline] [--no-forms] [--forms LIST] [--copy-calibration]
 """
 import argparse
 import hashlib
@@ -455,6 +457,179 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             "loss_mean_end": float((loss + lss).mean().item())}
 
 
+def _event_ms(fn, reps):
+    """Mean device time of fn() over reps calls, bracketed by events on the current stream."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def form_selection(R, steps, warmup, dev, tile=(32, 32), ppt=1):
+    """The pixel-selection chain of Sec. 3.2 on the 1M-Gaussian 1920x1080 frame: the
+    render with and without the fused rough depth map (tau 0.5), the unprojection of a
+    brush selection (disk of radius 378 px, 70% sample), the statistical outlier removal
+    (16 neighbours, scale 0.007), and, in a second view 0.3 rad of azimuth away, the
+    reprojection of the cloud as a mask (2 px squares, depth test with 1% slack) and the
+    tint of that view's image."""
+    import torch
+
+    import synth
+    log("bench: form selection: depth map, unprojection, outlier removal, reprojection, tint at 1920x1080")
+    w = synth.make_precision()
+    cam = w.view.camera
+    W, H = cam.width, cam.height
+    d = R.DeviceScene(w.scene, device=dev)
+    ws = R.DeviceWorkspace(d.n, W, H, tile, device=dev)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+    R.render(d, cam, ws, tile, ppt, image=img)     # grows the workspace once if needed
+    reps = max(10, steps // 4)
+    ms_plain = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img), reps)
+    ms_depth = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img, depth=depth, depth_tau=0.5), reps)
+    mask = torch.from_numpy(synth.brush_mask(W, H, 960.0, 540.0, 378.0)).to(dev)
+    keep = torch.from_numpy(synth.sample_keep(41, mask.cpu().numpy())).to(dev)
+    c = R.camera_struct(cam)
+    cap = int(mask.numel())
+    pts = torch.empty((3, cap), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    nb = R.recogs_unproject_workspace_bytes(W, H)
+    uws = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def unp():
+        R.recogs_unproject(c, mask.data_ptr(), keep.data_ptr(), depth.data_ptr(), pts.data_ptr(), cap, cnt.data_ptr(),
+                           uws.data_ptr(), nb)
+    ms_unp = _event_ms(unp, reps)
+    n_pts = int(cnt.item())
+    cloud = pts[:, :n_pts].contiguous()
+    dmean = torch.empty(n_pts, dtype=torch.float32, device=dev)
+    kp = torch.empty(n_pts, dtype=torch.uint8, device=dev)
+    out = torch.empty((3, n_pts), dtype=torch.float32, device=dev)
+    ocnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    onb = R.recogs_outlier_workspace_bytes(n_pts)
+    ows = torch.empty(onb, dtype=torch.uint8, device=dev)
+
+    def outl():
+        R.recogs_remove_outliers(cloud.data_ptr(), n_pts, n_pts, 16, 0.007, dmean.data_ptr(), kp.data_ptr(),
+                                 out.data_ptr(), n_pts, ocnt.data_ptr(), ows.data_ptr(), onb)
+    ms_out = _event_ms(outl, reps)
+    n_kept = int(ocnt.item())
+    cam2 = synth.nearby_orbit(cam, 0.3)
+    c2 = R.camera_struct(cam2)
+    depth2 = torch.empty((H, W), dtype=torch.float32, device=dev)
+    img2 = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    ws2 = R.DeviceWorkspace(d.n, W, H, tile, device=dev)
+    R.render(d, cam2, ws2, tile, ppt, image=img2, depth=depth2, depth_tau=0.5)
+    vmask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    tinted = torch.empty_like(img2)
+    t = [1.0, 0.6, 0.5]
+
+    def rep():
+        R.recogs_reproject_mask(c2, out.data_ptr(), n_kept, n_pts, 2.0, depth2.data_ptr(), 0.01, vmask.data_ptr())
+    ms_rep = _event_ms(rep, reps)
+    ms_tint = _event_ms(lambda: R.recogs_tint(img2.data_ptr(), vmask.data_ptr(), t, tinted.data_ptr(), H * W), reps)
+    marked = int(vmask.sum().item())
+    return {"width": W, "height": H, "gaussians": d.n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
+            "frame_ms": round(ms_plain, 4), "frame_with_depth_ms": round(ms_depth, 4),
+            "depth_overhead_ms": round(ms_depth - ms_plain, 4),
+            "selected_pixels": int(mask.sum().item()), "unprojected_points": n_pts, "unproject_ms": round(ms_unp, 4),
+            "outlier_kept": n_kept, "outlier_ms": round(ms_out, 4),
+            "reproject_ms": round(ms_rep, 4), "reprojected_pixels": marked, "tint_ms": round(ms_tint, 4)}
+
+
+def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
+    """The background optimiser of Sec. 3.3 with the selection of Sec. 3.2: 1M Gaussians
+    (FP32, SH 3), 8 training views at 1280x720. Once: view 0 rendered with its rough
+    depth map, a brush selection (disk of radius 0.15 H at the centre, 70% sample)
+    unprojected and cleaned by the outlier removal; the training views' original images
+    rendered. Per step (one view, in turn): render the current SH keeping the backward
+    state and the rough depth map, draw the cloud into the view as its mask (2 px squares,
+    depth test with 1% slack), tint the view's original image there (t = (1, 0.6, 0.5)),
+    the loss of eq. 7 against it, the gradient of every SH coefficient, one Adam step."""
+    import torch
+
+    import synth
+    log("bench: form edit: selection-driven SH refit, 1M Gaussians at 1280x720")
+    w = synth.make_diff()
+    d = R.DeviceScene(w.scene, device=dev)
+    n, K = d.n, (w.scene.sh_degree + 1) ** 2
+    v0 = w.views[0]
+    W, H = v0.camera.width, v0.camera.height
+    ws = R.DeviceWorkspace(n, W, H, tile, device=dev)
+    depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+    R.render(d, v0.camera, ws, tile, ppt, depth=depth, depth_tau=0.5)
+    sel = synth.brush_mask(W, H, W / 2, H / 2, 0.15 * H)
+    keep = synth.sample_keep(w.extra["keep_seed"], sel)
+    cloud, n_sel = R.unproject(v0.camera, torch.from_numpy(sel).to(dev), torch.from_numpy(keep).to(dev), depth)
+    cloud, _, _ = R.remove_outliers(cloud.contiguous(), 16, 0.007)
+    cloud = cloud.contiguous()
+    originals = [R.render(d, v.camera, ws, tile, ppt).clone() for v in w.views]
+    t = [float(x) for x in w.extra["tint"]]
+    sh = d.sh.clone()
+    m, v = torch.zeros_like(sh), torch.zeros_like(sh)
+    img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    target = torch.empty_like(img)
+    vmask = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    dimg = torch.empty_like(img)
+    loss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
+    lss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
+    dop = torch.empty(n, dtype=torch.float32, device=dev)
+    dsh = torch.zeros((3 * K, d.stride), dtype=torch.float32, device=dev)
+    dM = torch.empty(9, dtype=torch.float32, device=dev)
+    cams = [R.camera_struct(v.camera) for v in w.views]
+    o = R.opts_struct(tile, ppt, keep_backward=True)
+    sc = d.c_struct(sh)
+    cnt_px = H * W * 3
+    lam = 0.2
+    nb = R.recogs_dssim_workspace_bytes(W, H)
+    sws = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    n_pts = cloud.shape[1]
+    marked = torch.zeros(len(w.views), dtype=torch.int64, device=dev)
+    state = {"step": 0}
+
+    def step():
+        k = state["step"] % len(w.views)
+        state["step"] += 1
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, depth=depth, depth_tau=0.5)
+        R.recogs_reproject_mask(cams[k], cloud.data_ptr(), n_pts, n_pts, 2.0, depth.data_ptr(), 0.01, vmask.data_ptr())
+        R.recogs_tint(originals[k].data_ptr(), vmask.data_ptr(), t, target.data_ptr(), H * W)
+        R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
+                         loss.data_ptr() + 4 * k)
+        R.recogs_loss_dssim(img.data_ptr(), target.data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
+                            sws.data_ptr(), nb)
+        R.recogs_render_backward_sh(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
+                                    dsh.data_ptr(), dM.data_ptr())
+        R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
+                           step=state["step"])
+    for _ in range(len(w.views)):
+        step()
+        marked[(state["step"] - 1) % len(w.views)] = vmask.sum()
+    torch.cuda.synchronize()
+    first = float((loss + lss).mean().item())
+    for _ in range(max(0, warmup - len(w.views))):
+        step()
+    reps = max(16, steps // 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
+            "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "selected_pixels": int(sel.sum()),
+            "cloud_points": int(n_pts), "unprojected_points": int(n_sel),
+            "marked_pixels_per_view": [int(x) for x in marked.cpu().tolist()],
+            "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
+            "loss": "0.8 L1 + 0.2 (1 - SSIM) against the tinted view", "loss_mean_first_pass": first,
+            "loss_mean_end": float((loss + lss).mean().item())}
+
+
 def cpu_baseline(w):
     """The oracle as it stands on this host, on one whole frame of the same workload:
     recolour and projection of every Gaussian (one thread), then per-pixel compositing
@@ -502,7 +677,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison frames (16x16 tiles, the other output layout)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched and differentiation forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16, batched, differentiation, refit, "
+                    "selection and edit forms")
+    ap.add_argument("--forms", default="", help="comma-separated subset of the forms to run (f16, bf16, f32, batch, "
+                    "diff, refit, selection, edit); default all")
     ap.add_argument("--only-form", choices=["f16", "bf16", "batch", "diff", "refit"], default=None,
                     help="run only this form and print its JSON (for profiling it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -621,12 +799,23 @@ def main():
         del src, dst
     if not args.no_forms:
         forms = {}
+        only = set(args.forms.split(",")) if args.forms else None
+
+        def want(name):
+            return only is None or name in only
         for stg in ("f32", "f16", "bf16"):
-            if stg != args.storage:
+            if stg != args.storage and want(stg):
                 forms[stg] = form_single(R, stg, tile, args.ppt, args.steps, args.warmup, dev)
-        forms["batch"] = form_batch(R, args.steps, args.warmup, dev)
-        forms["diff"] = form_diff(R, args.steps, args.warmup, dev)
-        forms["refit"] = form_refit(R, args.steps, args.warmup, dev)
+        if want("batch"):
+            forms["batch"] = form_batch(R, args.steps, args.warmup, dev)
+        if want("diff"):
+            forms["diff"] = form_diff(R, args.steps, args.warmup, dev)
+        if want("refit"):
+            forms["refit"] = form_refit(R, args.steps, args.warmup, dev)
+        if want("selection"):
+            forms["selection"] = form_selection(R, args.steps, args.warmup, dev)
+        if want("edit"):
+            forms["edit"] = form_edit(R, args.steps, args.warmup, dev)
         res["forms"] = forms
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -18,7 +18,8 @@
 //      search stops once the k-th distance is within (r - 1/16) h, the distance below
 //      which no unscanned cell lies (the 1/16 absorbs float32 rounding of the cell
 //      coordinates). A query whose rings reach kOlMaxRing without that bound (a far
-//      stray point) scans the whole cloud instead.
+//      stray point) is deferred to a second kernel that scans the whole cloud with one
+//      workgroup per query (strided per-thread lists merged in LDS).
 //   4. double-precision block sums of D and D^2 give mu, sigma and the threshold; the
 //      keep mask and the compaction of the kept points (input order) follow.
 #include "recogs_internal.hpp"
@@ -33,7 +34,8 @@ void launch_excl_scan_u32(uint32_t *, uint32_t, uint32_t *, hipStream_t);
 
 constexpr int kOlBins = 1024;
 constexpr int kOlMaxDim = 128;
-constexpr int kOlMaxRing = 4;
+constexpr int kOlMaxRing = 6;
+constexpr int kOlFarBlocks = 1024;             // grid of the whole-cloud scans (grid-stride over the queries)
 constexpr int kOlRedBlocks = 512;              // grid of the reductions (grid-stride)
 constexpr int kOlItems = 4;                    // points per thread of the keep/compaction passes
 constexpr int kOlBlock = 256 * kOlItems;
@@ -50,7 +52,8 @@ struct OlHdr {
     float mn[3], mx[3];   // bounding box
     float h, inv_h;       // cell size and its reciprocal
     uint32_t mask;        // slots - 1
-    uint32_t pad[7];
+    uint32_t ndefer;      // queries left to the whole-cloud scan
+    uint32_t pad[6];
     double thr;           // mu + std_ratio sigma
     double mu, sigma;
 };
@@ -114,14 +117,18 @@ __global__ __launch_bounds__(256) void k_ol_bbox(const float *__restrict__ pts, 
     }
 }
 
-// 1b. final box (one workgroup)
-__global__ __launch_bounds__(64) void k_ol_bbox_final(const float *__restrict__ part, int nblk, OlHdr *__restrict__ hdr) {
-    const int a = threadIdx.x;
-    if (a >= 6) return;
-    float v = a < 3 ? INFINITY : -INFINITY;
-    for (int b = 0; b < nblk; ++b) v = a < 3 ? fminf(v, part[b * 6 + a]) : fmaxf(v, part[b * 6 + a]);
-    if (a < 3) hdr->mn[a] = v;
-    else hdr->mx[a - 3] = v;
+// 1b. final box: wave w (of 6) reduces bound w over the partials
+__global__ __launch_bounds__(384) void k_ol_bbox_final(const float *__restrict__ part, int nblk, OlHdr *__restrict__ hdr) {
+    const int a = threadIdx.x >> 6, l = (int)lane_id();
+    const bool lo = a < 3;
+    float v = lo ? INFINITY : -INFINITY;
+    for (int b = l; b < nblk; b += 64) v = lo ? fminf(v, part[b * 6 + a]) : fmaxf(v, part[b * 6 + a]);
+    v = lo ? wave_min(v) : wave_max(v);
+    if (l == 0) {
+        if (lo) hdr->mn[a] = v;
+        else hdr->mx[a - 3] = v;
+        if (a == 0) hdr->ndefer = 0;
+    }
 }
 
 // 1c. per-axis histograms over the box (LDS counts, then one atomic per bin and
@@ -153,26 +160,46 @@ __global__ __launch_bounds__(256) void k_ol_hist(const float *__restrict__ pts, 
         if (s_h[k]) atomicAdd(&hist[k], s_h[k]);
 }
 
-// 1d. cell size from the 1%-99% quantile extents (one thread per axis, then thread 0)
-__global__ __launch_bounds__(64) void k_ol_setup(const uint32_t *__restrict__ hist, int64_t n, uint32_t slot_mask,
-                                                 OlHdr *__restrict__ hdr) {
+// 1d. cell size from the 1%-99% quantile extents: wave a scans axis a's 1024 bins (16
+// per lane, then a wave scan) and finds the first bins whose cumulative count passes 1%
+// and 99% of the points; then thread 0 sets h.
+__global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ hist, int64_t n, uint32_t slot_mask,
+                                                  OlHdr *__restrict__ hdr) {
     __shared__ float s_ext[3];
-    const int a = threadIdx.x;
-    if (a < 3) {
-        const float e = hdr->mx[a] - hdr->mn[a];
-        const uint64_t lo_need = (uint64_t)((double)n * 0.01), hi_need = (uint64_t)((double)n * 0.99);
-        uint64_t cum = 0;
-        int blo = -1, bhi = kOlBins - 1;
-        for (int b = 0; b < kOlBins; ++b) {
-            cum += hist[a * kOlBins + b];
-            if (blo < 0 && cum > lo_need) blo = b;
-            if (cum > hi_need || cum >= (uint64_t)n) { bhi = b; break; }
+    constexpr int PER = kOlBins / 64;
+    const int a = threadIdx.x >> 6, l = (int)lane_id();
+    const uint64_t lo_need = (uint64_t)((double)n * 0.01), hi_need = (uint64_t)((double)n * 0.99);
+    uint32_t c[PER];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        c[q] = hist[a * kOlBins + l * PER + q];
+        mine += c[q];
+    }
+    const uint32_t incl = wave_incl_scan(mine);
+    // first bin (in lane-major order) where the running count exceeds `need`
+    auto first_over = [&](uint64_t need) -> int {
+        int bin = kOlBins;
+        uint64_t cum = incl - mine;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            cum += c[q];
+            if (bin == kOlBins && cum > need) bin = l * PER + q;
         }
-        if (blo < 0) blo = 0;
+        int best = bin;
+        for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o));
+        return best;
+    };
+    int blo = first_over(lo_need);
+    int bhi = first_over(hi_need < (uint64_t)n ? hi_need : (uint64_t)n - 1);
+    blo = blo >= kOlBins ? 0 : blo;
+    bhi = bhi >= kOlBins ? kOlBins - 1 : bhi;
+    if (l == 0) {
+        const float e = hdr->mx[a] - hdr->mn[a];
         s_ext[a] = (float)(bhi - blo + 1) * (e / (float)kOlBins);
     }
     __syncthreads();
-    if (a == 0) {
+    if (threadIdx.x == 0) {
         const float L = fmaxf(s_ext[0], fmaxf(s_ext[1], s_ext[2]));
         int D = (int)ceil(2.0 * cbrt((double)n));
         D = D < 1 ? 1 : (D > kOlMaxDim ? kOlMaxDim : D);
@@ -197,6 +224,18 @@ __global__ __launch_bounds__(256) void k_ol_key(const float *__restrict__ pts, i
     vals[i] = (uint32_t)i;
 }
 
+// 2b. the points in slot order as float4 (x, y, z, input index bits): one 16-byte load
+// per candidate in the searches below
+__global__ __launch_bounds__(256) void k_ol_gather(const float *__restrict__ pts, int64_t n, int64_t stride,
+                                                   const uint32_t *__restrict__ svals, float4 *__restrict__ spts) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t i = svals[j];
+    float x, y, z;
+    ol_load(pts, stride, i, x, y, z);
+    spts[j] = make_float4(x, y, z, __uint_as_float(i));
+}
+
 template <int K>
 __device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
     if (!(d2 < best[K - 1])) return;
@@ -207,14 +246,14 @@ __device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
 
 // 3. k nearest neighbours of every point (one thread per point, slot order)
 template <int K>
-__global__ __launch_bounds__(256) void k_ol_knn(const float *__restrict__ pts, int64_t n, int64_t stride,
-                                                const OlHdr *__restrict__ hdr, const uint32_t *__restrict__ svals,
-                                                const uint2 *__restrict__ ranges, float *__restrict__ dmean) {
+__global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts, int64_t n, OlHdr *hdr,
+                                                const uint2 *__restrict__ ranges, uint32_t *__restrict__ defer,
+                                                float *__restrict__ dmean) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
-    const uint32_t i = svals[s];
-    float x, y, z;
-    ol_load(pts, stride, i, x, y, z);
+    const float4 me = spts[s];
+    const uint32_t i = __float_as_uint(me.w);
+    const float x = me.x, y = me.y, z = me.z;
     const float mnx = hdr->mn[0], mny = hdr->mn[1], mnz = hdr->mn[2], ih = hdr->inv_h, h = hdr->h;
     const uint32_t mask = hdr->mask;
     const int cx = ol_coord(x, mnx, ih), cy = ol_coord(y, mny, ih), cz = ol_coord(z, mnz, ih);
@@ -234,13 +273,11 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float *__restrict__ pts, i
                     const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
                     const uint2 rg = ranges[ol_hash(qx, qy, qz, mask)];
                     for (uint32_t j = rg.x; j < rg.y; ++j) {
-                        const uint32_t o = svals[j];
-                        if (o == i) continue;
-                        float px, py, pz;
-                        ol_load(pts, stride, o, px, py, pz);
-                        if (ol_coord(px, mnx, ih) != qx || ol_coord(py, mny, ih) != qy || ol_coord(pz, mnz, ih) != qz)
+                        const float4 c = spts[j];
+                        if (__float_as_uint(c.w) == i) continue;
+                        if (ol_coord(c.x, mnx, ih) != qx || ol_coord(c.y, mny, ih) != qy || ol_coord(c.z, mnz, ih) != qz)
                             continue;   // another cell in the same slot
-                        const float ex = px - x, ey = py - y, ez = pz - z;
+                        const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
                         ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
                     }
                 }
@@ -253,21 +290,70 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float *__restrict__ pts, i
             done = kth <= bound * bound;
         }
     }
-    if (!done) {   // far from the rest: scan everything
-#pragma unroll
-        for (int q = 0; q < K; ++q) best[q] = INFINITY;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == (int64_t)i) continue;
-            float px, py, pz;
-            ol_load(pts, stride, j, px, py, pz);
-            const float ex = px - x, ey = py - y, ez = pz - z;
-            ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
-        }
+    if (!done) {   // far from the rest: left to the whole-cloud scan of k_ol_knn_far
+        defer[atomicAdd(&hdr->ndefer, 1u)] = i;
+        return;
     }
     float sum = 0.f;
 #pragma unroll
     for (int q = 0; q < K; ++q) sum += q < want ? sqrtf(best[q]) : 0.f;
     dmean[i] = want > 0 ? sum / (float)want : 0.f;
+}
+
+// 3b. the deferred queries, one workgroup each (grid-stride over the list): every
+// thread keeps the k smallest squared distances of a strided share of the cloud, then
+// the 256 sorted lists are merged pairwise in LDS (8 rounds).
+template <int K>
+__global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ spts, const float *__restrict__ pts,
+                                                    int64_t n, int64_t stride, const OlHdr *__restrict__ hdr,
+                                                    const uint32_t *__restrict__ defer, float *__restrict__ dmean) {
+    __shared__ float s_l[256 * K];
+    __shared__ float s_t[K];
+    const uint32_t nd = hdr->ndefer;
+    const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
+    for (uint32_t q = blockIdx.x; q < nd; q += gridDim.x) {
+        const uint32_t i = defer[q];
+        float x, y, z;
+        ol_load(pts, stride, i, x, y, z);
+        float best[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) best[a] = INFINITY;
+        for (int64_t j = threadIdx.x; j < n; j += 256) {
+            const float4 c = spts[j];
+            if (__float_as_uint(c.w) == i) continue;
+            const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
+            ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a) s_l[threadIdx.x * K + a] = best[a];
+        __syncthreads();
+        for (int sp = 1; sp < 256; sp <<= 1) {
+            if ((threadIdx.x & (2 * sp - 1)) == 0) {
+                const float *A = s_l + threadIdx.x * K, *B = s_l + (threadIdx.x + sp) * K;
+                float m[K];
+                int ia = 0, ib = 0;
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    const float va = A[ia], vb = B[ib];
+                    const bool ta = va <= vb;
+                    m[a] = ta ? va : vb;
+                    ia += ta ? 1 : 0;
+                    ib += ta ? 0 : 1;
+                }
+#pragma unroll
+                for (int a = 0; a < K; ++a) s_l[threadIdx.x * K + a] = m[a];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < K) s_t[threadIdx.x] = s_l[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float sum = 0.f;
+            for (int a = 0; a < want; ++a) sum += sqrtf(s_t[a]);
+            dmean[i] = want > 0 ? sum / (float)want : 0.f;
+        }
+        __syncthreads();   // s_l and s_t are reused by the next query
+    }
 }
 
 // 4a. block sums of D and D^2 in double -> part[blk][2]
@@ -294,15 +380,21 @@ __global__ __launch_bounds__(256) void k_ol_stats(const float *__restrict__ dmea
     }
 }
 
-// 4b. threshold (one thread, fixed order)
+// 4b. threshold: one wave, lanes stride over the partials, then a butterfly (a fixed
+// order, so the threshold is the same on every run)
 __global__ __launch_bounds__(64) void k_ol_thr(const double *__restrict__ part, int nblk, int64_t n, float std_ratio,
                                                OlHdr *__restrict__ hdr) {
-    if (threadIdx.x != 0) return;
+    const int l = (int)lane_id();
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < nblk; ++k) {
+    for (int k = l; k < nblk; k += 64) {
         a += part[2 * k];
         b += part[2 * k + 1];
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if (l != 0) return;
     const double mu = n > 0 ? a / (double)n : 0.0;
     double var = n > 0 ? b / (double)n - mu * mu : 0.0;
     var = var > 0.0 ? var : 0.0;
@@ -376,7 +468,7 @@ static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace pieces for n points (offsets in bytes, in this order).
 struct OlLayout {
-    size_t hdr, keys0, vals0, keys1, vals1, hist, shist, scount, ranges, bpart, spart, kpart, total;
+    size_t hdr, keys0, vals0, keys1, vals1, hist, shist, scount, ranges, bpart, spart, kpart, defer, spts, total;
 };
 
 size_t sort_count_words(uint64_t);
@@ -399,6 +491,8 @@ static OlLayout ol_layout(int64_t n) {
     L.bpart = take(4 * 6 * kOlRedBlocks);
     L.spart = take(8 * 2 * kOlRedBlocks);
     L.kpart = take(4 * ((nn + kOlBlock - 1) / kOlBlock + 1));
+    L.defer = take(4 * nn);
+    L.spts = take(16 * nn);
     L.total = o;
     return L;
 }
@@ -406,10 +500,12 @@ static OlLayout ol_layout(int64_t n) {
 size_t outlier_workspace_bytes(int64_t n) { return ol_layout(n).total; }
 
 template <int K>
-static void knn_launch(const float *pts, int64_t n, int64_t stride, const OlHdr *hdr, const uint32_t *svals,
-                       const uint2 *ranges, float *dmean, hipStream_t st) {
-    hipLaunchKernelGGL((k_ol_knn<K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, hdr, svals,
-                       ranges, dmean);
+static void knn_launch(const float *pts, int64_t n, int64_t stride, OlHdr *hdr, const float4 *spts,
+                       const uint2 *ranges, uint32_t *defer, float *dmean, hipStream_t st) {
+    hipLaunchKernelGGL((k_ol_knn<K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, spts, n, hdr, ranges, defer,
+                       dmean);
+    const unsigned far = (unsigned)(n < kOlFarBlocks ? n : kOlFarBlocks);
+    hipLaunchKernelGGL((k_ol_knn_far<K>), dim3(far), dim3(256), 0, st, spts, pts, n, stride, hdr, defer, dmean);
 }
 
 // k in {4, 8, 16, 32}: false (nothing launched) otherwise. out may be null (no compaction).
@@ -430,10 +526,10 @@ bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float s
     const uint32_t slots = 1u << bits;
     const int rb = (int)((n + 255) / 256 < kOlRedBlocks ? (n + 255) / 256 : kOlRedBlocks);
     hipLaunchKernelGGL(k_ol_bbox, dim3(rb), dim3(256), 0, st, pts, n, stride, (float *)(b + L.bpart));
-    hipLaunchKernelGGL(k_ol_bbox_final, dim3(1), dim3(64), 0, st, (const float *)(b + L.bpart), rb, hdr);
+    hipLaunchKernelGGL(k_ol_bbox_final, dim3(1), dim3(384), 0, st, (const float *)(b + L.bpart), rb, hdr);
     launch_fill_u32((uint32_t *)(b + L.shist), 0u, 3 * kOlBins, st);
     hipLaunchKernelGGL(k_ol_hist, dim3(rb), dim3(256), 0, st, pts, n, stride, hdr, (uint32_t *)(b + L.shist));
-    hipLaunchKernelGGL(k_ol_setup, dim3(1), dim3(64), 0, st, (const uint32_t *)(b + L.shist), n, slots - 1u, hdr);
+    hipLaunchKernelGGL(k_ol_setup, dim3(1), dim3(192), 0, st, (const uint32_t *)(b + L.shist), n, slots - 1u, hdr);
     hipLaunchKernelGGL(k_ol_key, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, hdr, k0, v0);
     launch_fill_u32((uint32_t *)(b + L.hist), 0u, 256 * kMaxPasses, st);
     const int alt = radix_sort_u32(k0, v0, k1, v1, (uint32_t)n, 0u, bits, (uint32_t *)(b + L.hist),
@@ -442,10 +538,13 @@ bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float s
     uint2 *ranges = (uint2 *)(b + L.ranges);
     launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)slots, st);
     launch_ranges32(sk, (uint32_t)n, ranges, st, nullptr);
-    if (k == 4) knn_launch<4>(pts, n, stride, hdr, sv, ranges, dmean, st);
-    else if (k == 8) knn_launch<8>(pts, n, stride, hdr, sv, ranges, dmean, st);
-    else if (k == 16) knn_launch<16>(pts, n, stride, hdr, sv, ranges, dmean, st);
-    else knn_launch<32>(pts, n, stride, hdr, sv, ranges, dmean, st);
+    uint32_t *defer = (uint32_t *)(b + L.defer);
+    float4 *spts = (float4 *)(b + L.spts);
+    hipLaunchKernelGGL(k_ol_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, sv, spts);
+    if (k == 4) knn_launch<4>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
+    else if (k == 8) knn_launch<8>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
+    else if (k == 16) knn_launch<16>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
+    else knn_launch<32>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
     hipLaunchKernelGGL(k_ol_stats, dim3(rb), dim3(256), 0, st, dmean, n, (double *)(b + L.spart));
     hipLaunchKernelGGL(k_ol_thr, dim3(1), dim3(64), 0, st, (const double *)(b + L.spart), rb, n, std_ratio, hdr);
     const uint32_t nblk = (uint32_t)((n + kOlBlock - 1) / kOlBlock);

@@ -368,7 +368,8 @@ def make_diff(seed: int = 4, n: int = 1_000_000, n_views: int = 8,
     1280x720 (orbit radius 4, 60 deg horizontal). Selection from view 0 (disk
     r = 0.15 H at the centre, colour ball 0.3) applied in every view. Optimised
     recolour M0 = I + 0.1 N(0,1); target recolour Mt = I + 0.3 N(0,1); target pixel
-    noise N(0, 0.01) drawn from `extra['noise_seed']`."""
+    noise N(0, 0.01) drawn from `extra['noise_seed']`. For the pixel-selection edit: the
+    tint t = (1, 0.6, 0.5) and the seed of the 70% sample of the selected pixels."""
     rng = np.random.default_rng(seed)
     scene = make_scene_mid_like(rng, n)
     cams = [random_orbit(rng, width, height, 60.0, 4.0) for _ in range(n_views)]
@@ -378,7 +379,8 @@ def make_diff(seed: int = 4, n: int = 1_000_000, n_views: int = 8,
     z = np.zeros(3, np.float32)
     views = [View(0, c, sel, RecolorParams(M0, z)) for c in cams]
     return Workload("diff", [scene], views, (16, 16),
-                    {"M_target": Mt, "noise_sd": 0.01, "noise_seed": seed * 1000 + 7})
+                    {"M_target": Mt, "noise_sd": 0.01, "noise_seed": seed * 1000 + 7,
+                     "tint": np.float32([1.0, 0.6, 0.5]), "keep_seed": seed * 1000 + 11})
 
 
 def make_diff_fd(seed: int = 4, n_sub: int = 4096, size: int = 64, n: int = 1_000_000) -> Workload:
@@ -433,3 +435,15 @@ def sample_keep(seed: int, mask: np.ndarray, frac: float = 0.7) -> np.ndarray:
     keep = np.zeros(np.asarray(mask).size, np.uint8)
     keep[rng.choice(flat, size=int(frac * flat.size), replace=False)] = 1
     return keep.reshape(np.asarray(mask).shape)
+
+
+def nearby_orbit(cam: Camera, daz: float, del_: float = 0.0) -> Camera:
+    """The orbit camera `daz` / `del_` radians of azimuth / elevation away from `cam`
+    (same radius, size and field of view), looking at the origin."""
+    R = np.asarray(cam.R, np.float64)
+    C = -R.T @ np.asarray(cam.t, np.float64)
+    r = float(np.linalg.norm(C))
+    az = math.atan2(C[0], C[2])
+    el = math.asin(C[1] / r)
+    fov = 2.0 * math.degrees(math.atan((cam.width / 2.0) / cam.fx))
+    return orbit_camera(cam.width, cam.height, fov, r, az + daz, el + del_, cam.znear)

@@ -220,6 +220,16 @@ def test_outliers_parity_large_surface_cloud(R):
     print(f"surface: kept {kept} of {X.shape[0]}, flagged {flagged}")
 
 
+def test_outliers_far_points_take_the_whole_cloud_scan(R):
+    """Stray points thousands of cells away (ring search gives up) and a million units
+    away (beyond the cell-coordinate guard): both go to the whole-cloud scan."""
+    X = _cloud(36, 20_000, strays=0.0)
+    X[-6:] = np.float32([[1e3, 0, 0], [1e3, 0.5, 0], [-1e3, 2e3, 7], [1e6, 1e6, 1e6], [1e6, 1e6, 1.001e6], [0, -4e5, 9]])
+    _check_outliers(R, X, 16, 0.007, "far points")
+    for k in (4, 32):
+        _check_outliers(R, X, k, 0.007, f"far points k={k}")
+
+
 def test_outliers_degenerate_clouds(R):
     import torch
     for X in [np.zeros((0, 3), np.float32), np.float32([[1, 2, 3]]), np.ones((5, 3), np.float32),
