@@ -14,7 +14,9 @@
 //      start in nearby cells);
 //   3. per query, the cells of Chebyshev rings r = 0, 1, ... are scanned (points of other
 //      cells that share a slot are skipped by re-deriving their cell), keeping the k
-//      smallest squared distances in registers (sorted insertion); after ring r >= 1 the
+//      smallest squared distances in registers (sorted insertion): rings 0-1 one thread
+//      per query, further rings one wave per query (the lanes split a ring's cells, so a
+//      few sparse neighbourhoods do not hold whole waves back); after ring r >= 1 the
 //      search stops once the k-th distance is within (r - 1/16) h, the distance below
 //      which no unscanned cell lies (the 1/16 absorbs float32 rounding of the cell
 //      coordinates). A query whose rings reach kOlMaxRing without that bound (a far
@@ -34,7 +36,9 @@ void launch_excl_scan_u32(uint32_t *, uint32_t, uint32_t *, hipStream_t);
 
 constexpr int kOlBins = 1024;
 constexpr int kOlMaxDim = 128;
-constexpr int kOlMaxRing = 6;
+constexpr int kOlThreadRing = 2;               // rings searched by the one-thread-per-query pass
+constexpr int kOlMaxRing = 5;                  // rings searched by the wave-per-query pass
+constexpr int kOlWaveBlocks = 2048;            // grid of the wave-per-query pass (4 waves each)
 constexpr int kOlFarBlocks = 1024;             // grid of the whole-cloud scans (grid-stride over the queries)
 constexpr int kOlRedBlocks = 512;              // grid of the reductions (grid-stride)
 constexpr int kOlItems = 4;                    // points per thread of the keep/compaction passes
@@ -53,7 +57,8 @@ struct OlHdr {
     float h, inv_h;       // cell size and its reciprocal
     uint32_t mask;        // slots - 1
     uint32_t ndefer;      // queries left to the whole-cloud scan
-    uint32_t pad[6];
+    uint32_t nslow;       // queries left to the wave-per-query search
+    uint32_t pad[5];
     double thr;           // mu + std_ratio sigma
     double mu, sigma;
 };
@@ -127,7 +132,10 @@ __global__ __launch_bounds__(384) void k_ol_bbox_final(const float *__restrict__
     if (l == 0) {
         if (lo) hdr->mn[a] = v;
         else hdr->mx[a - 3] = v;
-        if (a == 0) hdr->ndefer = 0;
+        if (a == 0) {
+            hdr->ndefer = 0;
+            hdr->nslow = 0;
+        }
     }
 }
 
@@ -244,11 +252,13 @@ __device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
     best[0] = d2 < best[0] ? d2 : best[0];
 }
 
-// 3. k nearest neighbours of every point (one thread per point, slot order)
+// 3. k nearest neighbours of every point (one thread per point, slot order), rings 0
+// and 1 only: a query not settled by then goes to the wave-per-query search (slow list,
+// slot positions), a query beyond the coordinate guard to the whole-cloud scan.
 template <int K>
 __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts, int64_t n, OlHdr *hdr,
-                                                const uint2 *__restrict__ ranges, uint32_t *__restrict__ defer,
-                                                float *__restrict__ dmean) {
+                                                const uint2 *__restrict__ ranges, uint32_t *__restrict__ slow,
+                                                uint32_t *__restrict__ defer, float *__restrict__ dmean) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const float4 me = spts[s];
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
     bool done = want == 0;
     const bool clamped = fabsf((x - mnx) * ih) > kOlQueryLimit || fabsf((y - mny) * ih) > kOlQueryLimit ||
                          fabsf((z - mnz) * ih) > kOlQueryLimit;
-    for (int r = 0; !done && !clamped && r < kOlMaxRing; ++r) {
+    for (int r = 0; !done && !clamped && r < kOlThreadRing; ++r) {
         for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy) {
                 const bool face = dz == -r || dz == r || dy == -r || dy == r;
@@ -290,8 +300,9 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
             done = kth <= bound * bound;
         }
     }
-    if (!done) {   // far from the rest: left to the whole-cloud scan of k_ol_knn_far
-        defer[atomicAdd(&hdr->ndefer, 1u)] = i;
+    if (!done) {
+        if (clamped) defer[atomicAdd(&hdr->ndefer, 1u)] = i;
+        else slow[atomicAdd(&hdr->nslow, 1u)] = (uint32_t)s;
         return;
     }
     float sum = 0.f;
@@ -300,7 +311,94 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
     dmean[i] = want > 0 ? sum / (float)want : 0.f;
 }
 
-// 3b. the deferred queries, one workgroup each (grid-stride over the list): every
+// 3b. the slow queries, one wave each (grid-stride over the list): the lanes split
+// each ring's cells (cube index t -> offsets, ring cells only) and keep their own k
+// smallest squared distances. The stop test after ring r counts, over the lanes, the
+// entries of their lists within the bound: the k-th smallest of the union is within it
+// iff at least k are (each of the k smallest overall is in its lane's k smallest). The
+// 64 lists are then merged pairwise in LDS (6 rounds, wave-level ordering only).
+// Queries not settled by ring kOlMaxRing - 1 go to the whole-cloud scan.
+template <int K>
+__global__ __launch_bounds__(256) void k_ol_knn_wave(const float4 *__restrict__ spts, int64_t n, OlHdr *hdr,
+                                                     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ slow,
+                                                     uint32_t *__restrict__ defer, float *__restrict__ dmean) {
+    __shared__ float s_l[4][64 * K];
+    const int wv = (int)(threadIdx.x >> 6), l = (int)lane_id();
+    float *Ls = s_l[wv];
+    const uint32_t ns = hdr->nslow;
+    const uint32_t waves = gridDim.x * 4u;
+    const float mnx = hdr->mn[0], mny = hdr->mn[1], mnz = hdr->mn[2], ih = hdr->inv_h, h = hdr->h;
+    const uint32_t mask = hdr->mask;
+    const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
+    for (uint32_t q = blockIdx.x * 4u + (uint32_t)wv; q < ns; q += waves) {
+        const float4 me = spts[slow[q]];
+        const uint32_t i = __float_as_uint(me.w);
+        const float x = me.x, y = me.y, z = me.z;
+        const int cx = ol_coord(x, mnx, ih), cy = ol_coord(y, mny, ih), cz = ol_coord(z, mnz, ih);
+        float best[K];
+#pragma unroll
+        for (int a = 0; a < K; ++a) best[a] = INFINITY;
+        bool done = false;
+        for (int r = 0; r < kOlMaxRing && !done; ++r) {
+            const int side = 2 * r + 1, cube = side * side * side;
+            for (int t = l; t < cube; t += 64) {
+                const int dx = t % side - r, dy = (t / side) % side - r, dz = t / (side * side) - r;
+                if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;   // inner cells: earlier rings
+                const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
+                const uint2 rg = ranges[ol_hash(qx, qy, qz, mask)];
+                for (uint32_t j = rg.x; j < rg.y; ++j) {
+                    const float4 c = spts[j];
+                    if (__float_as_uint(c.w) == i) continue;
+                    if (ol_coord(c.x, mnx, ih) != qx || ol_coord(c.y, mny, ih) != qy || ol_coord(c.z, mnz, ih) != qz)
+                        continue;
+                    const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
+                    ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+                }
+            }
+            if (r >= 1) {
+                const float bound = ((float)r - kOlMargin) * h, b2 = bound * bound;
+                int c = 0;
+#pragma unroll
+                for (int a = 0; a < K; ++a) c += best[a] <= b2 ? 1 : 0;
+                for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+                done = c >= want;
+            }
+        }
+        if (!done) {
+            if (l == 0) defer[atomicAdd(&hdr->ndefer, 1u)] = i;
+            continue;
+        }
+#pragma unroll
+        for (int a = 0; a < K; ++a) Ls[l * K + a] = best[a];
+        wave_sync();
+        for (int sp = 1; sp < 64; sp <<= 1) {
+            if ((l & (2 * sp - 1)) == 0) {
+                const float *A = Ls + l * K, *B = Ls + (l + sp) * K;
+                float m[K];
+                int ia = 0, ib = 0;
+#pragma unroll
+                for (int a = 0; a < K; ++a) {
+                    const float va = A[ia], vb = B[ib];
+                    const bool ta = va <= vb;
+                    m[a] = ta ? va : vb;
+                    ia += ta ? 1 : 0;
+                    ib += ta ? 0 : 1;
+                }
+#pragma unroll
+                for (int a = 0; a < K; ++a) Ls[l * K + a] = m[a];
+            }
+            wave_sync();
+        }
+        if (l == 0) {
+            float sum = 0.f;
+            for (int a = 0; a < want; ++a) sum += sqrtf(Ls[a]);
+            dmean[i] = want > 0 ? sum / (float)want : 0.f;
+        }
+        wave_sync();   // the lists are rewritten by the next query
+    }
+}
+
+// 3c. the deferred queries, one workgroup each (grid-stride over the list): every
 // thread keeps the k smallest squared distances of a strided share of the cloud, then
 // the 256 sorted lists are merged pairwise in LDS (8 rounds).
 template <int K>
@@ -318,7 +416,20 @@ __global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ s
         float best[K];
 #pragma unroll
         for (int a = 0; a < K; ++a) best[a] = INFINITY;
-        for (int64_t j = threadIdx.x; j < n; j += 256) {
+        // four loads in flight per iteration (the scan is latency bound otherwise)
+        int64_t j = threadIdx.x;
+        for (; j + 3 * 256 < n; j += 4 * 256) {
+            float4 c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = spts[j + u * 256];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (__float_as_uint(c[u].w) == i) continue;
+                const float ex = c[u].x - x, ey = c[u].y - y, ez = c[u].z - z;
+                ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+            }
+        }
+        for (; j < n; j += 256) {
             const float4 c = spts[j];
             if (__float_as_uint(c.w) == i) continue;
             const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
@@ -468,7 +579,7 @@ static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace pieces for n points (offsets in bytes, in this order).
 struct OlLayout {
-    size_t hdr, keys0, vals0, keys1, vals1, hist, shist, scount, ranges, bpart, spart, kpart, defer, spts, total;
+    size_t hdr, keys0, vals0, keys1, vals1, hist, shist, scount, ranges, bpart, spart, kpart, defer, slow, spts, total;
 };
 
 size_t sort_count_words(uint64_t);
@@ -492,6 +603,7 @@ static OlLayout ol_layout(int64_t n) {
     L.spart = take(8 * 2 * kOlRedBlocks);
     L.kpart = take(4 * ((nn + kOlBlock - 1) / kOlBlock + 1));
     L.defer = take(4 * nn);
+    L.slow = take(4 * nn);
     L.spts = take(16 * nn);
     L.total = o;
     return L;
@@ -501,9 +613,11 @@ size_t outlier_workspace_bytes(int64_t n) { return ol_layout(n).total; }
 
 template <int K>
 static void knn_launch(const float *pts, int64_t n, int64_t stride, OlHdr *hdr, const float4 *spts,
-                       const uint2 *ranges, uint32_t *defer, float *dmean, hipStream_t st) {
-    hipLaunchKernelGGL((k_ol_knn<K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, spts, n, hdr, ranges, defer,
-                       dmean);
+                       const uint2 *ranges, uint32_t *slow, uint32_t *defer, float *dmean, hipStream_t st) {
+    hipLaunchKernelGGL((k_ol_knn<K>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, spts, n, hdr, ranges, slow,
+                       defer, dmean);
+    const unsigned wb = (unsigned)((n + 3) / 4 < kOlWaveBlocks ? (n + 3) / 4 : kOlWaveBlocks);
+    hipLaunchKernelGGL((k_ol_knn_wave<K>), dim3(wb), dim3(256), 0, st, spts, n, hdr, ranges, slow, defer, dmean);
     const unsigned far = (unsigned)(n < kOlFarBlocks ? n : kOlFarBlocks);
     hipLaunchKernelGGL((k_ol_knn_far<K>), dim3(far), dim3(256), 0, st, spts, pts, n, stride, hdr, defer, dmean);
 }
@@ -538,13 +652,13 @@ bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float s
     uint2 *ranges = (uint2 *)(b + L.ranges);
     launch_fill_u32((uint32_t *)ranges, 0u, 2 * (int64_t)slots, st);
     launch_ranges32(sk, (uint32_t)n, ranges, st, nullptr);
-    uint32_t *defer = (uint32_t *)(b + L.defer);
+    uint32_t *defer = (uint32_t *)(b + L.defer), *slow = (uint32_t *)(b + L.slow);
     float4 *spts = (float4 *)(b + L.spts);
     hipLaunchKernelGGL(k_ol_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, sv, spts);
-    if (k == 4) knn_launch<4>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
-    else if (k == 8) knn_launch<8>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
-    else if (k == 16) knn_launch<16>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
-    else knn_launch<32>(pts, n, stride, hdr, spts, ranges, defer, dmean, st);
+    if (k == 4) knn_launch<4>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
+    else if (k == 8) knn_launch<8>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
+    else if (k == 16) knn_launch<16>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
+    else knn_launch<32>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
     hipLaunchKernelGGL(k_ol_stats, dim3(rb), dim3(256), 0, st, dmean, n, (double *)(b + L.spart));
     hipLaunchKernelGGL(k_ol_thr, dim3(1), dim3(64), 0, st, (const double *)(b + L.spart), rb, n, std_ratio, hdr);
     const uint32_t nblk = (uint32_t)((n + kOlBlock - 1) / kOlBlock);
