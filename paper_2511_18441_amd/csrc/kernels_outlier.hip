@@ -252,6 +252,27 @@ __device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
     best[0] = d2 < best[0] ? d2 : best[0];
 }
 
+// One cell's candidates [rg.x, rg.y) of the slot-ordered points against query i at
+// (x, y, z): points of another cell sharing the slot are skipped; four loads in flight.
+template <int K>
+__device__ __forceinline__ void ol_scan_cell(const float4 *__restrict__ spts, uint2 rg, uint32_t i, float x, float y,
+                                             float z, int qx, int qy, int qz, float mnx, float mny, float mnz, float ih,
+                                             float (&best)[K]) {
+    for (uint32_t j = rg.x; j < rg.y; j += 4) {
+        float4 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = j + u < rg.y ? spts[j + u] : make_float4(0.f, 0.f, 0.f, __uint_as_float(i));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (__float_as_uint(c[u].w) == i) continue;   // the query itself, or past the range
+            if (ol_coord(c[u].x, mnx, ih) != qx || ol_coord(c[u].y, mny, ih) != qy || ol_coord(c[u].z, mnz, ih) != qz)
+                continue;   // another cell in the same slot
+            const float ex = c[u].x - x, ey = c[u].y - y, ez = c[u].z - z;
+            ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
+        }
+    }
+}
+
 // 3. k nearest neighbours of every point (one thread per point, slot order), rings 0
 // and 1 only: a query not settled by then goes to the wave-per-query search (slow list,
 // slot positions), a query beyond the coordinate guard to the whole-cloud scan.
@@ -274,31 +295,21 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
     bool done = want == 0;
     const bool clamped = fabsf((x - mnx) * ih) > kOlQueryLimit || fabsf((y - mny) * ih) > kOlQueryLimit ||
                          fabsf((z - mnz) * ih) > kOlQueryLimit;
-    for (int r = 0; !done && !clamped && r < kOlThreadRing; ++r) {
-        for (int dz = -r; dz <= r; ++dz)
-            for (int dy = -r; dy <= r; ++dy) {
-                const bool face = dz == -r || dz == r || dy == -r || dy == r;
-                const int step = face ? 1 : 2 * r;   // inside the ring's slab only dx = -r, r
-                for (int dx = -r; dx <= r; dx += step) {
-                    const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
-                    const uint2 rg = ranges[ol_hash(qx, qy, qz, mask)];
-                    for (uint32_t j = rg.x; j < rg.y; ++j) {
-                        const float4 c = spts[j];
-                        if (__float_as_uint(c.w) == i) continue;
-                        if (ol_coord(c.x, mnx, ih) != qx || ol_coord(c.y, mny, ih) != qy || ol_coord(c.z, mnz, ih) != qz)
-                            continue;   // another cell in the same slot
-                        const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
-                        ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
-                    }
-                }
-            }
-        if (r >= 1) {
-            float kth = best[0];
+    static_assert(kOlThreadRing == 2, "the one-thread pass covers the 3 x 3 x 3 cells of rings 0 and 1");
+    if (!done && !clamped) {
+        // the 27 slot ranges first (independent loads), then the cells' candidates
+        uint2 rg[27];
 #pragma unroll
-            for (int q = 1; q < K; ++q) kth = q == want - 1 ? best[q] : kth;
-            const float bound = ((float)r - kOlMargin) * h;
-            done = kth <= bound * bound;
-        }
+        for (int t = 0; t < 27; ++t) rg[t] = ranges[ol_hash(cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1, mask)];
+#pragma unroll 1
+        for (int t = 0; t < 27; ++t)
+            ol_scan_cell<K>(spts, rg[t], i, x, y, z, cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1, mnx, mny, mnz,
+                            ih, best);
+        float kth = best[0];
+#pragma unroll
+        for (int q = 1; q < K; ++q) kth = q == want - 1 ? best[q] : kth;
+        const float bound = (1.f - kOlMargin) * h;
+        done = kth <= bound * bound;
     }
     if (!done) {
         if (clamped) defer[atomicAdd(&hdr->ndefer, 1u)] = i;
@@ -345,15 +356,7 @@ __global__ __launch_bounds__(256) void k_ol_knn_wave(const float4 *__restrict__ 
                 const int dx = t % side - r, dy = (t / side) % side - r, dz = t / (side * side) - r;
                 if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;   // inner cells: earlier rings
                 const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
-                const uint2 rg = ranges[ol_hash(qx, qy, qz, mask)];
-                for (uint32_t j = rg.x; j < rg.y; ++j) {
-                    const float4 c = spts[j];
-                    if (__float_as_uint(c.w) == i) continue;
-                    if (ol_coord(c.x, mnx, ih) != qx || ol_coord(c.y, mny, ih) != qy || ol_coord(c.z, mnz, ih) != qz)
-                        continue;
-                    const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
-                    ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
-                }
+                ol_scan_cell<K>(spts, ranges[ol_hash(qx, qy, qz, mask)], i, x, y, z, qx, qy, qz, mnx, mny, mnz, ih, best);
             }
             if (r >= 1) {
                 const float bound = ((float)r - kOlMargin) * h, b2 = bound * bound;
