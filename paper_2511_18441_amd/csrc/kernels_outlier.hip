@@ -37,9 +37,10 @@ void launch_excl_scan_u32(uint32_t *, uint32_t, uint32_t *, hipStream_t);
 constexpr int kOlBins = 1024;
 constexpr int kOlMaxDim = 128;
 constexpr int kOlThreadRing = 2;               // rings searched by the one-thread-per-query pass
-constexpr int kOlMaxRing = 5;                  // rings searched by the wave-per-query pass
+constexpr int kOlMaxRing = 6;                  // rings searched by the wave-per-query pass
 constexpr int kOlWaveBlocks = 2048;            // grid of the wave-per-query pass (4 waves each)
 constexpr int kOlFarBlocks = 1024;             // grid of the whole-cloud scans (grid-stride over the queries)
+constexpr int kOlFarThreads = 512;             // threads per whole-cloud scan (LDS: 512 k floats, 64 KB at k = 32)
 constexpr int kOlRedBlocks = 512;              // grid of the reductions (grid-stride)
 constexpr int kOlItems = 4;                    // points per thread of the keep/compaction passes
 constexpr int kOlBlock = 256 * kOlItems;
@@ -403,12 +404,12 @@ __global__ __launch_bounds__(256) void k_ol_knn_wave(const float4 *__restrict__ 
 
 // 3c. the deferred queries, one workgroup each (grid-stride over the list): every
 // thread keeps the k smallest squared distances of a strided share of the cloud, then
-// the 256 sorted lists are merged pairwise in LDS (8 rounds).
+// the kOlFarThreads sorted lists are merged pairwise in LDS (9 rounds).
 template <int K>
-__global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ spts, const float *__restrict__ pts,
+__global__ __launch_bounds__(kOlFarThreads) void k_ol_knn_far(const float4 *__restrict__ spts, const float *__restrict__ pts,
                                                     int64_t n, int64_t stride, const OlHdr *__restrict__ hdr,
                                                     const uint32_t *__restrict__ defer, float *__restrict__ dmean) {
-    __shared__ float s_l[256 * K];
+    __shared__ float s_l[kOlFarThreads * K];
     __shared__ float s_t[K];
     const uint32_t nd = hdr->ndefer;
     const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
@@ -421,10 +422,10 @@ __global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ s
         for (int a = 0; a < K; ++a) best[a] = INFINITY;
         // four loads in flight per iteration (the scan is latency bound otherwise)
         int64_t j = threadIdx.x;
-        for (; j + 3 * 256 < n; j += 4 * 256) {
+        for (; j + 3 * kOlFarThreads < n; j += 4 * kOlFarThreads) {
             float4 c[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] = spts[j + u * 256];
+            for (int u = 0; u < 4; ++u) c[u] = spts[j + u * kOlFarThreads];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (__float_as_uint(c[u].w) == i) continue;
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ s
                 ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
             }
         }
-        for (; j < n; j += 256) {
+        for (; j < n; j += kOlFarThreads) {
             const float4 c = spts[j];
             if (__float_as_uint(c.w) == i) continue;
             const float ex = c.x - x, ey = c.y - y, ez = c.z - z;
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(256) void k_ol_knn_far(const float4 *__restrict__ s
 #pragma unroll
         for (int a = 0; a < K; ++a) s_l[threadIdx.x * K + a] = best[a];
         __syncthreads();
-        for (int sp = 1; sp < 256; sp <<= 1) {
+        for (int sp = 1; sp < kOlFarThreads; sp <<= 1) {
             if ((threadIdx.x & (2 * sp - 1)) == 0) {
                 const float *A = s_l + threadIdx.x * K, *B = s_l + (threadIdx.x + sp) * K;
                 float m[K];
@@ -622,7 +623,8 @@ static void knn_launch(const float *pts, int64_t n, int64_t stride, OlHdr *hdr, 
     const unsigned wb = (unsigned)((n + 3) / 4 < kOlWaveBlocks ? (n + 3) / 4 : kOlWaveBlocks);
     hipLaunchKernelGGL((k_ol_knn_wave<K>), dim3(wb), dim3(256), 0, st, spts, n, hdr, ranges, slow, defer, dmean);
     const unsigned far = (unsigned)(n < kOlFarBlocks ? n : kOlFarBlocks);
-    hipLaunchKernelGGL((k_ol_knn_far<K>), dim3(far), dim3(256), 0, st, spts, pts, n, stride, hdr, defer, dmean);
+    hipLaunchKernelGGL((k_ol_knn_far<K>), dim3(far), dim3(kOlFarThreads), 0, st, spts, pts, n, stride, hdr, defer,
+                       dmean);
 }
 
 // k in {4, 8, 16, 32}: false (nothing launched) otherwise. out may be null (no compaction).

@@ -174,13 +174,13 @@ __device__ __forceinline__ void store_pixel(float *__restrict__ image, int64_t p
 // `idx` is the record's 1-based position in its tile list (kept, with STATE, as the
 // count up to the last blended entry). With DEPTH, cross[j] takes the position of the
 // blended splat that takes the pixel's transmittance from >= tau to < tau (the rough
-// depth of Sec. 3.2; at most one splat per pixel does, as T only decreases): the first
-// blended splat with T' < tau, tracked with a per-pixel flag instead of a second
-// compare of T.
+// depth of Sec. 3.2; at most one splat per pixel does, as T only decreases). Two
+// compares and a select; a per-pixel flag in a lane mask instead of the compare of T
+// measured slower (its mask updates put scalar instructions between the vector ones).
 template <int PPT, bool STATE, bool DEPTH = false>
 __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const float *pyc, float *T, float *C0, float *C1,
                                            float *C2, uint32_t *last, uint32_t idx, uint32_t *cross = nullptr,
-                                           bool *armed = nullptr, float tau = 0.f) {
+                                           float tau = 0.f) {
 #pragma clang fp contract(off)
     const float2 uv = b.uv;
     const float4 r1 = b.r1, r2 = b.rgb;
@@ -198,11 +198,7 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
         C1[j] = __builtin_fmaf(r2.y, wgt, C1[j]);
         C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
         if constexpr (STATE) last[j] = bl ? idx : last[j];
-        if constexpr (DEPTH) {   // armed: T has not yet fallen below tau (a lane mask, scalar ALU)
-            const bool c = bl && Tn < tau && armed[j];
-            cross[j] = c ? idx : cross[j];
-            armed[j] = armed[j] && !c;
-        }
+        if constexpr (DEPTH) cross[j] = (bl && Tn < tau && T[j] >= tau) ? idx : cross[j];
         const float Ts = stop ? -T[j] : Tn;   // two selects: this form compiles to v_cndmask
         T[j] = ok ? Ts : T[j];
     }
@@ -341,7 +337,6 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
     const float y0 = (float)by + 0.5f, y1 = y0 + (float)(8 * PPT - 1);
     float pyc[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
     uint32_t last[PPT], cross[PPT];
-    bool armed[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const int py = by + (l >> 3) * PPT + j;
@@ -350,7 +345,6 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
         C0[j] = C1[j] = C2[j] = 0.f;
         last[j] = 0;
         cross[j] = 0;
-        armed[j] = true;
     }
     // Software pipeline over chunks of 64 list entries (one per lane): the records of
     // chunk c are in registers while chunk c - 1 is composited, and the list values of
@@ -394,7 +388,7 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
 #pragma unroll
             for (int j = 0; j < PPT; ++j) live = live || T[j] > 0.f;
             if (!wave_ballot(live)) break;
-            blend_step<PPT, STATE, DEPTH>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q, cross, armed, tau);
+            blend_step<PPT, STATE, DEPTH>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q, cross, tau);
         }
         wave_sync();   // all reads of this chunk before the next chunk's writes
     }
