@@ -190,7 +190,9 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
         const float e = exp_at(er, r1, pyc[j] - uv.y);
         const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(e));
         const float Tn = __builtin_fmaf(-a, T[j], T[j]);   // T (1 - alpha), rounded once
-        const bool ok = T[j] > 0.f && !(e < kLog2AlphaMin);
+        // A stopped pixel (T < 0) needs no test of its own: its T' = T (1 - alpha) is
+        // negative too, so `stop` holds, nothing is blended and T stays -|T| = T.
+        const bool ok = !(e < kLog2AlphaMin);
         const bool stop = Tn < kTMin;
         const bool bl = ok && !stop;
         const float wgt = bl ? a * T[j] : 0.f;
@@ -199,7 +201,7 @@ __device__ __forceinline__ void blend_step(const BlendRec &b, float pxc, const f
         C2[j] = __builtin_fmaf(r2.z, wgt, C2[j]);
         if constexpr (STATE) last[j] = bl ? idx : last[j];
         if constexpr (DEPTH) cross[j] = (bl && Tn < tau && T[j] >= tau) ? idx : cross[j];
-        const float Ts = stop ? -T[j] : Tn;   // two selects: this form compiles to v_cndmask
+        const float Ts = stop ? -fabsf(T[j]) : Tn;   // two selects: this form compiles to v_cndmask
         T[j] = ok ? Ts : T[j];
     }
 }
@@ -312,13 +314,16 @@ __device__ __forceinline__ void blend_tile(int tile, uint2 rg, const uint32_t *_
 // Region form of the same blend: one wave, alone in its workgroup, composites the
 // 8 x 8*PPT pixel region `sub` of tile `tile` (regions numbered row-major, TW / 8 per
 // row). It reads the tile's whole list 64 records at a time, one per lane, and takes
-// those that pass region_hit for its own region, in list order. No barrier couples
+// those that pass region_hit for its own region, in list order (compacted into the
+// first LDS slots, with their list positions where STATE or DEPTH needs them). No barrier couples
 // the regions of a tile: a region whose pixels have all stopped retires at once, so
 // the sort tile can be larger than the region without the early-stopped pixels
 // holding the rest. The per-pixel arithmetic and the list positions kept with STATE
 // are those of blend_tile, so both forms give bit-identical outputs. With DEPTH the
 // rough depth map (Sec. 3.2) is written too: per pixel, the float32 depth (zbits, per
 // record) of the splat whose blending takes T below tau, 0 where none does.
+constexpr int kRegionUnroll = 4;
+
 template <int TW, int TH, int PPT, bool STATE, bool DEPTH = false>
 __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const uint32_t *__restrict__ vals,
                                              const SplatRec *__restrict__ rec, int W, int H, int tiles_x, float bg0,
@@ -365,12 +370,15 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
         for (int j = 0; j < PPT; ++j) alive = alive || T[j] > 0.f;
         if (!wave_ballot(alive)) break;
         const bool hit = start + (uint32_t)l < rg.y && region_hit(p0, p1, x0, x1, y0, y1);
-        if (hit) {   // (the mask fields of the record are not used in this form)
-            sm[l].uv = make_float2(p0.x, p0.y);
-            sm[l].r1 = p1;
-            sm[l].rgb = p2;
+        const uint64_t mm = wave_ballot(hit);
+        if (hit) {   // compacted in list order: slot = passing lanes below this one
+            const uint32_t slot = rank_below(mm);
+            sm[slot].uv = make_float2(p0.x, p0.y);
+            sm[slot].r1 = p1;
+            sm[slot].rgb = p2;
+            if constexpr (STATE || DEPTH) sm[slot].pad = start + 1u - rg.x + (uint32_t)l;   // 1-based list position
         }
-        uint64_t mm = wave_ballot(hit);
+        const int nh = (int)__builtin_popcountll(mm);
         wave_sync();   // the lanes' LDS writes before any lane reads
         {
             const uint32_t k = start + 64u + (uint32_t)l;
@@ -380,15 +388,23 @@ __device__ __forceinline__ void blend_region(int tile, int sub, uint2 rg, const 
             }
             if (k + 64u < rg.y) vnext = vals[k + 64u];
         }
-        const uint32_t krel0 = start + 1 - rg.x;
-        while (mm) {
-            const int q = (int)__builtin_ctzll(mm);
-            mm &= mm - 1;
+        // kRegionUnroll records per liveness check: consecutive slots, so their LDS
+        // addresses are one base plus immediate offsets
+        for (int q = 0; q < nh; q += kRegionUnroll) {
             bool live = false;
 #pragma unroll
             for (int j = 0; j < PPT; ++j) live = live || T[j] > 0.f;
             if (!wave_ballot(live)) break;
-            blend_step<PPT, STATE, DEPTH>(sm[q], pxc, pyc, T, C0, C1, C2, last, krel0 + (uint32_t)q, cross, tau);
+            // the group's LDS base as an opaque vector value: kept in one register for
+            // the group (a copy per step otherwise), the records at immediate offsets
+            uint32_t off = (uint32_t)q * (uint32_t)sizeof(BlendRec);
+            asm volatile("" : "+v"(off));
+            const BlendRec *g = reinterpret_cast<const BlendRec *>(reinterpret_cast<const char *>(sm) + off);
+#pragma unroll
+            for (int u = 0; u < kRegionUnroll; ++u)
+                if (q + u < nh)
+                    blend_step<PPT, STATE, DEPTH>(g[u], pxc, pyc, T, C0, C1, C2, last, (STATE || DEPTH) ? g[u].pad : 0u,
+                                                  cross, tau);
         }
         wave_sync();   // all reads of this chunk before the next chunk's writes
     }
