@@ -8,12 +8,12 @@
 //   1. bounding box (reduction), then per-axis 1024-bin histograms over it; the cell
 //      size h is the largest 1%-99% quantile extent divided by ceil(2 n^(1/3)) (at most
 //      128), so far-away stray points do not coarsen the grid for the rest;
-//   2. each point's cell (floor((x - min) / h) per axis) is hashed into a table of
-//      2^b slots (b = log2 of about 2n); a radix sort by slot and a range pass give each
-//      slot its run of points (slot order is also the query order: queries of one wave
-//      start in nearby cells);
-//   3. per query, the cells of Chebyshev rings r = 0, 1, ... are scanned (points of other
-//      cells that share a slot are skipped by re-deriving their cell), keeping the k
+//   2. each point's cell (floor((x - min) / h) per axis) goes to the slot made of its
+//      coordinates modulo powers of two (2^b slots, b = log2 of about 2n, at least 4 bits
+//      per axis); a radix sort by slot and a range pass give each slot its run of points
+//      (slot order is also the query order: queries of one wave start in nearby cells);
+//   3. per query, the cells of Chebyshev rings r = 0, 1, ... are scanned (no two cells of
+//      one search share a slot; points of far cells that do are scanned too), keeping the k
 //      smallest squared distances in registers (sorted insertion): rings 0-1 one thread
 //      per query, further rings one wave per query (the lanes split a ring's cells, so a
 //      few sparse neighbourhoods do not hold whole waves back); after ring r >= 1 the
@@ -56,10 +56,10 @@ constexpr float kOlMargin = 1.f / 16.f;
 struct OlHdr {
     float mn[3], mx[3];   // bounding box
     float h, inv_h;       // cell size and its reciprocal
-    uint32_t mask;        // slots - 1
+    uint32_t bx, by, bz;  // slot bits per axis
     uint32_t ndefer;      // queries left to the whole-cloud scan
     uint32_t nslow;       // queries left to the wave-per-query search
-    uint32_t pad[5];
+    uint32_t pad[3];
     double thr;           // mu + std_ratio sigma
     double mu, sigma;
 };
@@ -76,8 +76,14 @@ __device__ __forceinline__ int ol_coord(float v, float mn, float inv_h) {
     return (int)f;
 }
 
-__device__ __forceinline__ uint32_t ol_hash(int cx, int cy, int cz, uint32_t mask) {
-    return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u)) & mask;
+// Slot of a cell: its coordinates modulo 2^bx, 2^by, 2^bz, packed (bx + by + bz = the
+// slot bits, each at least 4). Cells that differ by less than 16 along every axis get
+// different slots, so the cells of one search (at most 11 x 11 x 11) never share a slot
+// and a slot's run can be scanned without checking each point's cell: the points of
+// far cells that share it are real points of the cloud, and only add candidates.
+__device__ __forceinline__ uint32_t ol_slot(int cx, int cy, int cz, uint32_t bx, uint32_t by, uint32_t bz) {
+    return ((uint32_t)cx & ((1u << bx) - 1u)) | (((uint32_t)cy & ((1u << by) - 1u)) << bx) |
+           (((uint32_t)cz & ((1u << bz) - 1u)) << (bx + by));
 }
 
 __device__ __forceinline__ float wave_min(float v) {
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(256) void k_ol_hist(const float *__restrict__ pts, 
 // 1d. cell size from the 1%-99% quantile extents: wave a scans axis a's 1024 bins (16
 // per lane, then a wave scan) and finds the first bins whose cumulative count passes 1%
 // and 99% of the points; then thread 0 sets h.
-__global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ hist, int64_t n, uint32_t slot_mask,
+__global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ hist, int64_t n, uint32_t slot_bits,
                                                   OlHdr *__restrict__ hdr) {
     __shared__ float s_ext[3];
     constexpr int PER = kOlBins / 64;
@@ -216,7 +222,9 @@ __global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ h
         if (!(h > 0.f) || !isfinite(h)) h = 1.f;   // all points coincide (or a degenerate box)
         hdr->h = h;
         hdr->inv_h = 1.f / h;
-        hdr->mask = slot_mask;
+        hdr->bz = slot_bits / 3;
+        hdr->by = (slot_bits - slot_bits / 3) / 2;
+        hdr->bx = slot_bits - hdr->bz - hdr->by;
     }
 }
 
@@ -229,7 +237,8 @@ __global__ __launch_bounds__(256) void k_ol_key(const float *__restrict__ pts, i
     float x, y, z;
     ol_load(pts, stride, i, x, y, z);
     const float ih = hdr->inv_h;
-    keys[i] = ol_hash(ol_coord(x, hdr->mn[0], ih), ol_coord(y, hdr->mn[1], ih), ol_coord(z, hdr->mn[2], ih), hdr->mask);
+    keys[i] = ol_slot(ol_coord(x, hdr->mn[0], ih), ol_coord(y, hdr->mn[1], ih), ol_coord(z, hdr->mn[2], ih), hdr->bx,
+                      hdr->by, hdr->bz);
     vals[i] = (uint32_t)i;
 }
 
@@ -253,12 +262,11 @@ __device__ __forceinline__ void ol_insert(float (&best)[K], float d2) {
     best[0] = d2 < best[0] ? d2 : best[0];
 }
 
-// One cell's candidates [rg.x, rg.y) of the slot-ordered points against query i at
-// (x, y, z): points of another cell sharing the slot are skipped; four loads in flight.
+// One slot's candidates [rg.x, rg.y) of the slot-ordered points against query i at
+// (x, y, z); four loads in flight.
 template <int K>
 __device__ __forceinline__ void ol_scan_cell(const float4 *__restrict__ spts, uint2 rg, uint32_t i, float x, float y,
-                                             float z, int qx, int qy, int qz, float mnx, float mny, float mnz, float ih,
-                                             float (&best)[K]) {
+                                             float z, float (&best)[K]) {
     for (uint32_t j = rg.x; j < rg.y; j += 4) {
         float4 c[4];
 #pragma unroll
@@ -266,8 +274,6 @@ __device__ __forceinline__ void ol_scan_cell(const float4 *__restrict__ spts, ui
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (__float_as_uint(c[u].w) == i) continue;   // the query itself, or past the range
-            if (ol_coord(c[u].x, mnx, ih) != qx || ol_coord(c[u].y, mny, ih) != qy || ol_coord(c[u].z, mnz, ih) != qz)
-                continue;   // another cell in the same slot
             const float ex = c[u].x - x, ey = c[u].y - y, ez = c[u].z - z;
             ol_insert<K>(best, __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)));
         }
@@ -287,7 +293,7 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
     const uint32_t i = __float_as_uint(me.w);
     const float x = me.x, y = me.y, z = me.z;
     const float mnx = hdr->mn[0], mny = hdr->mn[1], mnz = hdr->mn[2], ih = hdr->inv_h, h = hdr->h;
-    const uint32_t mask = hdr->mask;
+    const uint32_t bx = hdr->bx, by = hdr->by, bz = hdr->bz;
     const int cx = ol_coord(x, mnx, ih), cy = ol_coord(y, mny, ih), cz = ol_coord(z, mnz, ih);
     const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
     float best[K];
@@ -301,11 +307,10 @@ __global__ __launch_bounds__(256) void k_ol_knn(const float4 *__restrict__ spts,
         // the 27 slot ranges first (independent loads), then the cells' candidates
         uint2 rg[27];
 #pragma unroll
-        for (int t = 0; t < 27; ++t) rg[t] = ranges[ol_hash(cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1, mask)];
-#pragma unroll 1
         for (int t = 0; t < 27; ++t)
-            ol_scan_cell<K>(spts, rg[t], i, x, y, z, cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1, mnx, mny, mnz,
-                            ih, best);
+            rg[t] = ranges[ol_slot(cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1, bx, by, bz)];
+#pragma unroll 1
+        for (int t = 0; t < 27; ++t) ol_scan_cell<K>(spts, rg[t], i, x, y, z, best);
         float kth = best[0];
 #pragma unroll
         for (int q = 1; q < K; ++q) kth = q == want - 1 ? best[q] : kth;
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(256) void k_ol_knn_wave(const float4 *__restrict__ 
     const uint32_t ns = hdr->nslow;
     const uint32_t waves = gridDim.x * 4u;
     const float mnx = hdr->mn[0], mny = hdr->mn[1], mnz = hdr->mn[2], ih = hdr->inv_h, h = hdr->h;
-    const uint32_t mask = hdr->mask;
+    const uint32_t bx = hdr->bx, by = hdr->by, bz = hdr->bz;
     const int want = n - 1 < (int64_t)K ? (int)(n - 1) : K;
     for (uint32_t q = blockIdx.x * 4u + (uint32_t)wv; q < ns; q += waves) {
         const float4 me = spts[slow[q]];
@@ -357,7 +362,7 @@ __global__ __launch_bounds__(256) void k_ol_knn_wave(const float4 *__restrict__ 
                 const int dx = t % side - r, dy = (t / side) % side - r, dz = t / (side * side) - r;
                 if (max(abs(dx), max(abs(dy), abs(dz))) != r) continue;   // inner cells: earlier rings
                 const int qx = cx + dx, qy = cy + dy, qz = cz + dz;
-                ol_scan_cell<K>(spts, ranges[ol_hash(qx, qy, qz, mask)], i, x, y, z, qx, qy, qz, mnx, mny, mnz, ih, best);
+                ol_scan_cell<K>(spts, ranges[ol_slot(qx, qy, qz, bx, by, bz)], i, x, y, z, best);
             }
             if (r >= 1) {
                 const float bound = ((float)r - kOlMargin) * h, b2 = bound * bound;
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(256) void k_ol_write(const float *__restrict__ pts,
 // host side
 // ---------------------------------------------------------------------------
 int outlier_slot_bits(int64_t n) {
-    int b = 10;
+    int b = 12;   // at least 4 bits per axis
     while (b < 22 && ((int64_t)1 << b) < 2 * n) ++b;
     return b;
 }
@@ -648,7 +653,7 @@ bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float s
     hipLaunchKernelGGL(k_ol_bbox_final, dim3(1), dim3(384), 0, st, (const float *)(b + L.bpart), rb, hdr);
     launch_fill_u32((uint32_t *)(b + L.shist), 0u, 3 * kOlBins, st);
     hipLaunchKernelGGL(k_ol_hist, dim3(rb), dim3(256), 0, st, pts, n, stride, hdr, (uint32_t *)(b + L.shist));
-    hipLaunchKernelGGL(k_ol_setup, dim3(1), dim3(192), 0, st, (const uint32_t *)(b + L.shist), n, slots - 1u, hdr);
+    hipLaunchKernelGGL(k_ol_setup, dim3(1), dim3(192), 0, st, (const uint32_t *)(b + L.shist), n, (uint32_t)bits, hdr);
     hipLaunchKernelGGL(k_ol_key, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pts, n, stride, hdr, k0, v0);
     launch_fill_u32((uint32_t *)(b + L.hist), 0u, 256 * kMaxPasses, st);
     const int alt = radix_sort_u32(k0, v0, k1, v1, (uint32_t)n, 0u, bits, (uint32_t *)(b + L.hist),
