@@ -39,6 +39,7 @@ constexpr int kOlMaxDim = 128;
 constexpr int kOlThreadRing = 2;               // rings searched by the one-thread-per-query pass
 constexpr int kOlMaxRing = 6;                  // rings searched by the wave-per-query pass
 constexpr int kOlWaveBlocks = 2048;            // grid of the wave-per-query pass (4 waves each)
+static_assert(2 * (kOlMaxRing - 1) + 1 <= 16, "one search's cells must fit in 16 slot residues per axis");
 constexpr int kOlFarBlocks = 1024;             // grid of the whole-cloud scans (grid-stride over the queries)
 constexpr int kOlFarThreads = 512;             // threads per whole-cloud scan (LDS: 512 k floats, 64 KB at k = 32)
 constexpr int kOlRedBlocks = 512;              // grid of the reductions (grid-stride)
