@@ -440,6 +440,18 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
                                     dsh.data_ptr(), dM.data_ptr())
         R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
                            step=state["step"])
+    def step_fused():
+        # the same step with the SH backward and the Adam step fused (the gradient does
+        # not go through memory)
+        k = state["step"] % len(w.views)
+        state["step"] += 1
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh)
+        R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
+                         loss.data_ptr() + 4 * k)
+        R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
+                            sws.data_ptr(), nb)
+        R.recogs_render_backward_sh_adam(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
+                                         dM.data_ptr(), m.data_ptr(), v.data_ptr(), 2e-3, step=state["step"])
     for _ in range(max(8, warmup)):
         step()
     torch.cuda.synchronize()
@@ -450,11 +462,17 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         step()
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / reps
+    end = float((loss + lss).mean().item())
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step_fused()
+    torch.cuda.synchronize()
+    ms_fused = 1000.0 * (time.perf_counter() - t0) / reps
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "ms_per_step": round(ms, 3),
-            "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
-            "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first,
-            "loss_mean_end": float((loss + lss).mean().item())}
+            "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps, "ms_per_step_fused_adam": round(ms_fused, 3),
+            "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first, "loss_mean_end": end,
+            "loss_mean_after_fused_steps": float((loss + lss).mean().item())}
 
 
 def _event_ms(fn, reps):
@@ -551,7 +569,8 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     rendered. Per step (one view, in turn): render the current SH keeping the backward
     state and the rough depth map, draw the cloud into the view as its mask (2 px squares,
     depth test with 1% slack), tint the view's original image there (t = (1, 0.6, 0.5)),
-    the loss of eq. 7 against it, the gradient of every SH coefficient, one Adam step."""
+    the loss of eq. 7 against it, the gradient of every SH coefficient and one Adam step,
+    fused (the gradient goes straight into the update, never to memory)."""
     import torch
 
     import synth
@@ -580,7 +599,6 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     loss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
     lss = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
     dop = torch.empty(n, dtype=torch.float32, device=dev)
-    dsh = torch.zeros((3 * K, d.stride), dtype=torch.float32, device=dev)
     dM = torch.empty(9, dtype=torch.float32, device=dev)
     cams = [R.camera_struct(v.camera) for v in w.views]
     o = R.opts_struct(tile, ppt, keep_backward=True)
@@ -603,10 +621,8 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
                          loss.data_ptr() + 4 * k)
         R.recogs_loss_dssim(img.data_ptr(), target.data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
                             sws.data_ptr(), nb)
-        R.recogs_render_backward_sh(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
-                                    dsh.data_ptr(), dM.data_ptr())
-        R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
-                           step=state["step"])
+        R.recogs_render_backward_sh_adam(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
+                                         dM.data_ptr(), m.data_ptr(), v.data_ptr(), 2e-3, step=state["step"])
     for _ in range(len(w.views)):
         step()
         marked[(state["step"] - 1) % len(w.views)] = vmask.sum()

@@ -308,6 +308,20 @@ recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t
 recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr,
                                float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
 
+/* recogs_render_backward_sh followed by recogs_adam_step on the scene's SH, fused: the
+ * gradient of every coefficient of each Gaussian goes straight into its Adam update
+ * (the same arithmetic as the two calls, so the same bits) and never to memory. The
+ * scene's SH planes (scene->sh, float32 storage, [3 (deg + 1)^2][stride]) are updated
+ * in place; m and v (device float, same layout, zero at step 1) are the moments.
+ * Columns n..stride-1 are left untouched. dL_dopacity and dL_dM are written as by
+ * recogs_render_backward_sh. UNSUPPORTED: storage other than float32; otherwise the
+ * errors of the two calls. */
+recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const recogs_camera *cam,
+                                             const recogs_render_opts *opts, const recogs_workspace *ws,
+                                             const float *image, const float *dL_dimage, float *dL_dopacity, float *dL_dM,
+                                             float *m, float *v, float lr, float beta1, float beta2, float eps,
+                                             int32_t step, hipStream_t stream);
+
 /* ---- pixel selection (Sec. 3.2, 3.3) ----------------------------------------- */
 
 /* Unprojection of a 2D selection to a world point cloud (Sec. 3.2, 3D selection).

@@ -29,7 +29,8 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
-                "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_last_error")
+                "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_render_backward_sh_adam",
+                "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -120,6 +121,8 @@ def lib():
         L.recogs_unproject.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
         L.recogs_reproject_mask.argtypes = [P(Camera), vp, i64, i64, f32, vp, f32, vp, vp]
         L.recogs_tint.argtypes = [vp, vp, P(f32), vp, i64, vp]
+        L.recogs_render_backward_sh_adam.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp,
+                                                     vp, vp, f32, f32, f32, f32, i32, vp]
         L.recogs_outlier_workspace_bytes.argtypes = [i64]
         L.recogs_outlier_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_remove_outliers.argtypes = [vp, i64, i64, i32, f32, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
@@ -208,6 +211,13 @@ def recogs_render_backward_sh(scene: Scene, cam: Camera, opts: RenderOpts, ws: W
     return _check("recogs_render_backward_sh", lib().recogs_render_backward_sh(
         ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage, dL_dopacity,
         dL_dsh, dL_dM, _stream(stream)))
+
+
+def recogs_render_backward_sh_adam(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
+                                   dL_dopacity, dL_dM, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
+    return _check("recogs_render_backward_sh_adam", lib().recogs_render_backward_sh_adam(
+        ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage, dL_dopacity,
+        dL_dM, m, v, float(lr), float(beta1), float(beta2), float(eps), int(step), _stream(stream)))
 
 
 def recogs_loss_l1(image, target, count, scale, dL_dimage, loss, stream=None):

@@ -175,12 +175,16 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 //             plane layout), d the view direction.
 // dL/dM is reduced without atomics: each workgroup writes its 9 partial sums to
 // part[block][9] and k_dm_reduce adds them in a fixed order (deterministic).
-template <int DEG>
+// ADAM (DEG >= 0): instead of writing dL/dSH, apply one Adam step with it to the SH
+// planes psh in place (moments am, av, same layout): the gradient never goes to memory.
+template <int DEG, bool ADAM>
 __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ gk, const uint32_t *__restrict__ koff,
                                                      const float4 *__restrict__ bwd, const uint32_t *__restrict__ count,
                                                      int64_t n, const float *__restrict__ M, float *__restrict__ dop,
                                                      float *__restrict__ out, float *__restrict__ part,
-                                                     const float *__restrict__ means, int64_t stride, CamDev cam) {
+                                                     const float *__restrict__ means, int64_t stride, CamDev cam,
+                                                     float *__restrict__ psh, float *__restrict__ am,
+                                                     float *__restrict__ av, AdamArgs aa) {
     __shared__ float s_dm[4][9];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool sel = false;
@@ -227,7 +231,18 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) out[(int64_t)(k * 3 + c) * stride + i] = Y[k] * g[c];
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t o = (int64_t)(k * 3 + c) * stride + i;
+                    if constexpr (ADAM) {
+                        float pp = psh[o], mm = am[o], vv = av[o];
+                        adam_update(pp, Y[k] * g[c], mm, vv, aa);
+                        am[o] = mm;
+                        av[o] = vv;
+                        psh[o] = pp;
+                    } else {
+                        out[o] = Y[k] * g[c];
+                    }
+                }
         }
     }
     if (!M) return;  // uniform: no recolour, no dL/dM
@@ -330,20 +345,32 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
 // part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n).
 // deg < 0: out = dL/dC0 [3][n]; deg 0..3: out = dL/dSH [3 (deg + 1)^2][stride], which needs
 // the centres (means, plane stride) and the camera.
+// adam non-null (deg 0..3): one Adam step on psh / am / av instead of writing out.
 void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bwd, const uint32_t *count, int64_t n,
                         const float *M, float *dop, float *out, float *dM, float *part, int deg, const float *means,
-                        int64_t stride, const CamDev &cam, hipStream_t st) {
+                        int64_t stride, const CamDev &cam, hipStream_t st, float *psh, float *am, float *av,
+                        const AdamArgs *adam) {
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
+    const AdamArgs aa = adam ? *adam : AdamArgs{0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
     if (n > 0) {
-#define RECOGS_FIN(D)                                                                                             \
-    hipLaunchKernelGGL(k_grad_finish<D>, dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, out, part, \
-                       means, stride, cam)
-        switch (deg) {
-        case 0: RECOGS_FIN(0); break;
-        case 1: RECOGS_FIN(1); break;
-        case 2: RECOGS_FIN(2); break;
-        case 3: RECOGS_FIN(3); break;
-        default: RECOGS_FIN(-1); break;
+#define RECOGS_FIN(D, A)                                                                                              \
+    hipLaunchKernelGGL((k_grad_finish<D, A>), dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, out, part, \
+                       means, stride, cam, psh, am, av, aa)
+        if (adam) {
+            switch (deg) {
+            case 0: RECOGS_FIN(0, true); break;
+            case 1: RECOGS_FIN(1, true); break;
+            case 2: RECOGS_FIN(2, true); break;
+            default: RECOGS_FIN(3, true); break;
+            }
+        } else {
+            switch (deg) {
+            case 0: RECOGS_FIN(0, false); break;
+            case 1: RECOGS_FIN(1, false); break;
+            case 2: RECOGS_FIN(2, false); break;
+            case 3: RECOGS_FIN(3, false); break;
+            default: RECOGS_FIN(-1, false); break;
+            }
         }
 #undef RECOGS_FIN
     }

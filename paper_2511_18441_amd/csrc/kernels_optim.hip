@@ -52,40 +52,30 @@ void launch_loss_l1(const float *y, const float *tg, int64_t count, float scale,
 // p <- p - lr (m / c1) / (sqrt(v / c2) + eps) with the bias corrections c1 = 1 - b1^step,
 // c2 = 1 - b2^step (computed by the host in double precision).
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
-                                              float *__restrict__ v, int64_t count, float lr, float b1, float b2,
-                                              float eps, float c1, float c2) {
+                                              float *__restrict__ v, int64_t count, AdamArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        const float gi = g[i];
-        const float mi = b1 * m[i] + (1.f - b1) * gi;
-        const float vi = b2 * v[i] + (1.f - b2) * (gi * gi);
+        float pi = p[i], mi = m[i], vi = v[i];
+        adam_update(pi, g[i], mi, vi, a);
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
     }
 }
 
 // The same update on four consecutive values per thread (16-byte loads and stores: the
 // step moves 28 bytes per coefficient and is bound by HBM).
-__device__ __forceinline__ float adam_one(float &pi, float gi, float &mi, float &vi, float lr, float b1, float b2,
-                                          float eps, float c1, float c2) {
-    mi = b1 * mi + (1.f - b1) * gi;
-    vi = b2 * vi + (1.f - b2) * (gi * gi);
-    pi -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    return pi;
-}
-
 __global__ __launch_bounds__(256) void k_adam4(float4 *__restrict__ p, const float4 *__restrict__ g,
-                                               float4 *__restrict__ m, float4 *__restrict__ v, int64_t count4, float lr,
-                                               float b1, float b2, float eps, float c1, float c2) {
+                                               float4 *__restrict__ m, float4 *__restrict__ v, int64_t count4,
+                                               AdamArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count4; i += stride) {
         const float4 gi = g[i];
         float4 mi = m[i], vi = v[i], pi = p[i];
-        adam_one(pi.x, gi.x, mi.x, vi.x, lr, b1, b2, eps, c1, c2);
-        adam_one(pi.y, gi.y, mi.y, vi.y, lr, b1, b2, eps, c1, c2);
-        adam_one(pi.z, gi.z, mi.z, vi.z, lr, b1, b2, eps, c1, c2);
-        adam_one(pi.w, gi.w, mi.w, vi.w, lr, b1, b2, eps, c1, c2);
+        adam_update(pi.x, gi.x, mi.x, vi.x, a);
+        adam_update(pi.y, gi.y, mi.y, vi.y, a);
+        adam_update(pi.z, gi.z, mi.z, vi.z, a);
+        adam_update(pi.w, gi.w, mi.w, vi.w, a);
         m[i] = mi;
         v[i] = vi;
         p[i] = pi;
@@ -95,6 +85,7 @@ __global__ __launch_bounds__(256) void k_adam4(float4 *__restrict__ p, const flo
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t st) {
     if (count <= 0) return;
+    const AdamArgs a{lr, b1, b2, eps, c1, c2};
     const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) | reinterpret_cast<uintptr_t>(m) |
                        reinterpret_cast<uintptr_t>(v)) & 15u) == 0;
     int64_t done = 0;
@@ -103,15 +94,14 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, fl
         int64_t blocks = (c4 + 255) / 256;
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_adam4, dim3((unsigned)blocks), dim3(256), 0, st, (float4 *)p, (const float4 *)g, (float4 *)m,
-                           (float4 *)v, c4, lr, b1, b2, eps, c1, c2);
+                           (float4 *)v, c4, a);
         done = 4 * c4;
     }
     const int64_t rest = count - done;
     if (rest <= 0) return;
     int64_t blocks = (rest + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p + done, g + done, m + done, v + done, rest, lr,
-                       b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, st, p + done, g + done, m + done, v + done, rest, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,8 @@ int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uin
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
-                        float *, float *, float *, int, const float *, int64_t, const CamDev &, hipStream_t);
+                        float *, float *, float *, int, const float *, int64_t, const CamDev &, hipStream_t, float *, float *,
+                        float *, const AdamArgs *);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
@@ -605,7 +606,8 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
 // dL/dSH [3 (deg + 1)^2][scene stride].
 static recogs_status backward_impl(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
                                    const recogs_workspace *ws, const float *image, const float *dL_dimage,
-                                   float *dL_dopacity, float *out, float *dL_dM, bool all_bands, hipStream_t stream) {
+                                   float *dL_dopacity, float *out, float *dL_dM, bool all_bands, hipStream_t stream,
+                                   float *am = nullptr, float *av = nullptr, const AdamArgs *adam = nullptr) {
     g_err[0] = 0;
     recogs_status s;
     if ((s = check_scene(scene)) != RECOGS_OK) return s;
@@ -618,7 +620,7 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     if (ws->num_keys < 0)
         return fail(RECOGS_ERR_INVALID, "after a graph_mode render, call recogs_workspace_readback before the backward");
     if (ws->num_keys > ws->key_capacity) return fail(RECOGS_ERR_INVALID, "the render overflowed its key capacity");
-    if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || !out)))
+    if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || (!out && !adam))))
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
     const int64_t n = scene->n;
     const int ntiles = ws->tiles_x * ws->tiles_y;
@@ -637,7 +639,7 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
     launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, out,
                        dL_dM, at<float>(ws, ws->off_gpart), all_bands ? scene->sh_degree : -1, scene->means,
-                       scene->stride, cd, stream);
+                       scene->stride, cd, stream, adam ? (float *)scene->sh : nullptr, am, av, adam);
     return hip_check("backward");
 }
 
@@ -652,6 +654,23 @@ recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_
                                         const float *dL_dimage, float *dL_dopacity, float *dL_dsh, float *dL_dM,
                                         hipStream_t stream) {
     return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh, dL_dM, true, stream);
+}
+
+recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const recogs_camera *cam,
+                                             const recogs_render_opts *opts, const recogs_workspace *ws,
+                                             const float *image, const float *dL_dimage, float *dL_dopacity, float *dL_dM,
+                                             float *m, float *v, float lr, float beta1, float beta2, float eps,
+                                             int32_t step, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!scene) return fail(RECOGS_ERR_INVALID, "scene is NULL");
+    if (scene->storage != RECOGS_F32) return fail(RECOGS_ERR_UNSUPPORTED, "the fused Adam step updates float32 SH only");
+    if (step < 1) return fail(RECOGS_ERR_INVALID, "step %d < 1", step);
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(RECOGS_ERR_INVALID, "beta1, beta2 must lie in [0, 1) and eps > 0");
+    if (scene->n > 0 && (!m || !v)) return fail(RECOGS_ERR_INVALID, "NULL moment pointer");
+    const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
+    const AdamArgs a{lr, beta1, beta2, eps, (float)c1, (float)c2};
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, nullptr, dL_dM, true, stream, m, v, &a);
 }
 
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,

@@ -48,6 +48,56 @@ def test_backward_sh_vs_oracle(R, orc, tile, ppt):
     print(f"{tile} ppt {ppt}: dL/dSH rel max err {e:.2e}")
 
 
+def test_backward_sh_adam_fused_equals_the_two_calls(R, orc):
+    """recogs_render_backward_sh_adam gives the bits of recogs_render_backward_sh followed by
+    recogs_adam_step on the SH planes, over three steps (with the fused recolour, and a
+    plane stride above n whose extra columns stay untouched)."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    gt = torch.from_numpy(np.asarray(g, np.float32)).cuda()
+    n, K = d.n, (w.scene.sh_degree + 1) ** 2
+    o = R.opts_struct((32, 16), 1, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    ws = R.DeviceWorkspace(n, cam.width, cam.height, (32, 16))
+    d = R.DeviceScene(w.scene, stride=n + 29)          # every plane with 29 spare columns
+    base = d.sh.clone()
+    base[:, n:] = 0.25                                  # spare columns: must stay as they are
+    sh_a, sh_b = base.clone(), base.clone()
+    ma, va, mb, vb = (torch.zeros_like(base) for _ in range(4))
+    dsh = torch.zeros_like(base)
+    dop_a, dop_b = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    dM_a, dM_b = torch.empty(9, device="cuda"), torch.empty(9, device="cuda")
+
+    def scene(sh):
+        return d.c_struct(sh)
+    for step in (1, 2, 3):
+        sa = scene(sh_a)
+        img = R.render(d, cam, ws, (32, 16), 1, mask=tm, M=tM, b=tb, keep_backward=True, sh=sh_a)
+        R.recogs_render_backward_sh(sa, R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(), dop_a.data_ptr(),
+                                    dsh.data_ptr(), dM_a.data_ptr())
+        R.recogs_adam_step(sh_a.data_ptr(), dsh.data_ptr(), ma.data_ptr(), va.data_ptr(), sh_a.numel(), 2e-3, step=step)
+        sb = scene(sh_b)
+        img_b = R.render(d, cam, ws, (32, 16), 1, mask=tm, M=tM, b=tb, keep_backward=True, sh=sh_b)
+        assert torch.equal(img, img_b)
+        R.recogs_render_backward_sh_adam(sb, R.camera_struct(cam), o, ws.ws, img_b.data_ptr(), gt.data_ptr(),
+                                         dop_b.data_ptr(), dM_b.data_ptr(), mb.data_ptr(), vb.data_ptr(), 2e-3,
+                                         step=step)
+        torch.cuda.synchronize()
+        # the separate Adam call also steps the spare columns (with a zero gradient from
+        # zero moments: no change), the fused one skips them
+        assert torch.equal(sh_a, sh_b) and torch.equal(ma, mb) and torch.equal(va, vb), step
+        assert torch.equal(dop_a, dop_b) and torch.equal(dM_a, dM_b), step
+    assert torch.equal(sh_b[:, n:], base[:, n:])
+    assert not torch.equal(sh_b[:, :n], base[:, :n])
+    bad = d.c_struct()
+    bad.storage = 1
+    with pytest.raises(R.RecogsError) as e:
+        R.recogs_render_backward_sh_adam(bad, R.camera_struct(cam), o, ws.ws, img_b.data_ptr(), gt.data_ptr(),
+                                         dop_b.data_ptr(), dM_b.data_ptr(), mb.data_ptr(), vb.data_ptr(), 2e-3, step=1)
+    assert e.value.status == -3
+
+
 def test_loss_l1_vs_oracle(R, orc):
     import torch
     y = synth.random_image(7, (72, 128, 3))
