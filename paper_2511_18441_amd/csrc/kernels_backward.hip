@@ -15,6 +15,7 @@
 // from DPP reductions, the waves of the tile add theirs in LDS, and one float4 store
 // per (splat, tile) writes the slot; k_grad_finish then sums each Gaussian's slots in
 // a fixed order, so the gradients are deterministic.
+#include "optim_device.hpp"
 #include "render_device.hpp"
 
 namespace recogs {

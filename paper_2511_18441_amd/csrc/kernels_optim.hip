@@ -3,7 +3,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "recogs_internal.hpp"
+#include "optim_device.hpp"
 
 namespace recogs {
 

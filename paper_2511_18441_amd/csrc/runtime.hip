@@ -8,7 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 
-#include "recogs_internal.hpp"
+#include "optim_device.hpp"
 
 namespace recogs {
 // launchers (kernels_*.hip)
