@@ -124,15 +124,7 @@ constexpr float kSsimC1 = 0.01f * 0.01f, kSsimC2 = 0.03f * 0.03f;
 
 struct SsimWindow { float g[2 * kSsimR + 1]; };
 
-// loads channel c of an HWC image's halo tile (zero outside the image) into s[26][26]
-__device__ __forceinline__ void ssim_load(const float *__restrict__ img, int W, int H, int c, int ox, int oy,
-                                          float *s /* [kSsimH * kSsimH] */) {
-    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
-        const int x = ox + k % kSsimH - kSsimR, y = oy + k / kSsimH - kSsimR;
-        s[k] = (x >= 0 && x < W && y >= 0 && y < H) ? img[((int64_t)y * W + x) * 3 + c] : 0.f;
-    }
-}
-// the same for a planar map [H][W]
+// loads the halo tile of a planar map [H][W] (zero outside the image) into s[26][26]
 __device__ __forceinline__ void ssim_load_plane(const float *__restrict__ m, int W, int H, int ox, int oy, float *s) {
     for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
         const int x = ox + k % kSsimH - kSsimR, y = oy + k / kSsimH - kSsimR;
@@ -143,7 +135,7 @@ __device__ __forceinline__ void ssim_load_plane(const float *__restrict__ m, int
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
                                                   SsimWindow win, float *__restrict__ maps, float *__restrict__ loss,
                                                   float neg_scale) {
-    __shared__ float s_y[kSsimH * kSsimH], s_t[kSsimH * kSsimH];
+    __shared__ float s_y[3][kSsimH * kSsimH], s_t[3][kSsimH * kSsimH];
     __shared__ float s_h[5][kSsimH][kSsimT];   // x-blurred y, t, y^2, t^2, y t
     __shared__ float s_w[4];
     const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
@@ -151,17 +143,26 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, c
     const int px = ox + tx, py = oy + ty;
     const int64_t HW = (int64_t)W * H;
     float ssum = 0.f;
+    // the halo tiles of both images, all three channels of a pixel read together (12
+    // contiguous bytes of the HWC image), zero outside the image
+    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
+        const int x = ox + k % kSsimH - kSsimR, yy = oy + k / kSsimH - kSsimR;
+        const bool in = x >= 0 && x < W && yy >= 0 && yy < H;
+        const int64_t q = ((int64_t)yy * W + x) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s_y[c][k] = in ? y[q + c] : 0.f;
+            s_t[c][k] = in ? t[q + c] : 0.f;
+        }
+    }
     for (int c = 0; c < 3; ++c) {
-        __syncthreads();
-        ssim_load(y, W, H, c, ox, oy, s_y);
-        ssim_load(t, W, H, c, ox, oy, s_t);
-        __syncthreads();
+        __syncthreads();   // the tiles loaded; the previous channel's s_h reads done
         for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
             const int r = k / kSsimT, cx = k % kSsimT;
             float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
             for (int j = 0; j <= 2 * kSsimR; ++j) {
-                const float u = s_y[r * kSsimH + cx + j], v = s_t[r * kSsimH + cx + j], g = win.g[j];
+                const float u = s_y[c][r * kSsimH + cx + j], v = s_t[c][r * kSsimH + cx + j], g = win.g[j];
                 a0 += g * u; a1 += g * v; a2 += g * (u * u); a3 += g * (v * v); a4 += g * (u * v);
             }
             s_h[0][r][cx] = a0; s_h[1][r][cx] = a1; s_h[2][r][cx] = a2; s_h[3][r][cx] = a3; s_h[4][r][cx] = a4;
