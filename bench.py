@@ -703,7 +703,7 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this path has no multi-GPU form (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: this path has no multi-GPU form (sharding across GPUs is designed, not built)",
               file=sys.stderr)
         sys.exit(2)
 
