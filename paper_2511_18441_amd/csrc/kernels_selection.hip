@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_unp_write(const uint8_t *__restrict__ m
         uint32_t before = run;
         for (int q = 0; q < w; ++q) before += s_w[q];
         const uint32_t total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        __syncthreads();   // s_w is rewritten by the next round
+        __syncthreads();   // s_w is rewritten in the next iteration
         if (take) {
             const int64_t o = (int64_t)before + below;
             if (o < cap) {
