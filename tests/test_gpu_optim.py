@@ -225,3 +225,41 @@ def test_sh_refit_lowers_the_l1_loss(R, orc):
         losses.append(loss.item())
     print("L1 loss over the refit:", [round(x, 5) for x in losses[::5]], round(losses[-1], 5))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_backward_sh_adam_fused_at_full_size(R):
+    """The benchmarked refit step's size (1M Gaussians, SH degree 3, 1280x720, 32x16 tiles,
+    1 px/thread): the fused step and the two calls agree bit for bit over two steps."""
+    import torch
+    w = synth.make_diff()
+    v0 = w.views[0]
+    cam = v0.camera
+    d = R.DeviceScene(w.scene)
+    n = d.n
+    ws = R.DeviceWorkspace(n, cam.width, cam.height, (32, 16))
+    o = R.opts_struct((32, 16), 1, keep_backward=True)
+    H, W = cam.height, cam.width
+    target = torch.from_numpy(synth.random_image(61, (H, W, 3), 0.5) + np.float32(0.5)).cuda()
+    dimg = torch.empty((H, W, 3), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    sh_a, sh_b = d.sh.clone(), d.sh.clone()
+    ma, va, mb, vb = (torch.zeros_like(sh_a) for _ in range(4))
+    dsh = torch.zeros_like(sh_a)
+    dop, dM = torch.empty(n, device="cuda"), torch.empty(9, device="cuda")
+    for step in (1, 2):
+        for sh, fused in ((sh_a, False), (sh_b, True)):
+            img = R.render(d, cam, ws, (32, 16), 1, keep_backward=True, sh=sh)
+            R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), img.numel(), 1.0 / img.numel(), dimg.data_ptr(),
+                             loss.data_ptr())
+            if fused:
+                R.recogs_render_backward_sh_adam(d.c_struct(sh), R.camera_struct(cam), o, ws.ws, img.data_ptr(),
+                                                 dimg.data_ptr(), dop.data_ptr(), dM.data_ptr(), mb.data_ptr(),
+                                                 vb.data_ptr(), 2e-3, step=step)
+            else:
+                R.recogs_render_backward_sh(d.c_struct(sh), R.camera_struct(cam), o, ws.ws, img.data_ptr(),
+                                            dimg.data_ptr(), dop.data_ptr(), dsh.data_ptr(), dM.data_ptr())
+                R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), ma.data_ptr(), va.data_ptr(), sh.numel(), 2e-3,
+                                   step=step)
+        torch.cuda.synchronize()
+        assert torch.equal(sh_a, sh_b) and torch.equal(ma, mb) and torch.equal(va, vb), step
+    assert not torch.equal(sh_a, d.sh)
