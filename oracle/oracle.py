@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 PCOLS = ["z", "z32", "u", "v", "sa", "sb", "sc", "ca", "cb", "cc", "r", "g", "b",
          "pr", "pg", "pb", "fr", "fg", "fb", "sigma", "qext", "ex", "ey", "det"]
 ICOLS = ["status", "pxlo", "pxhi", "pylo", "pyhi", "txlo", "txhi", "tylo", "tyhi",
-         "count", "flag", "z32bits", "sel"]
+         "count", "flag", "z32bits", "sel", "rule"]
 P = {k: i for i, k in enumerate(PCOLS)}
 I = {k: i for i, k in enumerate(ICOLS)}
 
@@ -66,7 +66,7 @@ def lib():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.orc_sh_basis.argtypes = [i32, f64, f64, f64, vp]
         L.orc_covariance.argtypes = [i64, vp, vp, vp]
-        L.orc_project.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(_Cam), i32, i32, vp, vp, vp, vp, vp]
+        L.orc_project.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(_Cam), i32, i32, vp, vp, vp, vp, vp, i32]
         L.orc_select.argtypes = [i64, vp, vp, ctypes.POINTER(_Cam), f64, f64, f64, vp, f64, vp, vp]
         L.orc_recolor.argtypes = [i64, i32, vp, vp, vp, vp, vp]
         L.orc_emit_keys.argtypes = [i64, vp, i32, i64, vp, vp, vp]
@@ -139,9 +139,11 @@ class Projection:
         return -(-self.height // self.tile[1])
 
 
-def project(scene, cam, tile=(16, 16), cov=None, mask=None, M=None, b=None) -> Projection:
+def project(scene, cam, tile=(16, 16), cov=None, mask=None, M=None, b=None, extent_rule: int = 0) -> Projection:
     """Per-Gaussian depth, EWA conic, colour (eq. 2, optional fused recolour, eq. 6)
-    and tile rectangle (see orc_project)."""
+    and tile rectangle (see orc_project): extent_rule 0 = the alpha >= 1/255 box (tiles
+    never change a pixel), 1 = the 3DGS rasteriser's ceil(3 sqrt(lambda_max)) square
+    (a splat reaches only the pixels of its tiles)."""
     n = scene.n
     means = _d(scene.means)
     if cov is None:
@@ -160,7 +162,7 @@ def project(scene, cam, tile=(16, 16), cov=None, mask=None, M=None, b=None) -> P
     lib().orc_project(n, _p(means), _p(cov), _p(op), _p(sh), scene.sh_degree, ctypes.byref(c),
                       int(tile[0]), int(tile[1]),
                       _p(mk) if mk is not None else None, _p(Mv) if Mv is not None else None,
-                      _p(bv) if bv is not None else None, _p(f), _p(i))
+                      _p(bv) if bv is not None else None, _p(f), _p(i), int(extent_rule))
     return Projection(f, i, tuple(tile), int(cam.width), int(cam.height))
 
 

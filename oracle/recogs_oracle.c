@@ -71,6 +71,7 @@ enum {
     I_FLAG,                /* 1 when a tile/cull decision lies within the rounding band */
     I_Z32BITS,             /* bit pattern of the float32 depth */
     I_SEL,                 /* 1 when the fused recolour was applied */
+    I_RULE,                /* extent rule of the tile rectangle: 0 alpha box, 1 3DGS square */
     I_NCOL
 };
 
@@ -194,6 +195,41 @@ static void rect_from_edges(double ax, double bx, double ay, double by, int32_t 
     r[8] = (r[5] - r[4] + 1) * (r[7] - r[6] + 1);
 }
 
+/* Tile rectangle of the 3DGS rasteriser's square (extent rule 1): a radius of rad
+ * pixels around the centre (xc, yc) in pixel-index coordinates (pixel k's centre at
+ * k); tiles floor((xc - rad) / tw) up to, not including, floor((xc + rad + tw - 1) / tw),
+ * clipped to the grid (the same in y). Empty when either span is. The pixel range
+ * written is the one the listed tiles cover inside the image. */
+static void rect_square(double xc, double yc, double rad, int32_t W, int32_t H, int32_t tw, int32_t th,
+                        int64_t *r /* as rect_from_edges */)
+{
+    const double ntx = (double)((W + tw - 1) / tw), nty = (double)((H + th - 1) / th);
+    double a = floor((xc - rad) / tw), b = floor((xc + rad + tw - 1) / tw);
+    double c = floor((yc - rad) / th), d = floor((yc + rad + th - 1) / th);
+    a = a < 0 ? 0 : (a > ntx ? ntx : a);
+    b = b < 0 ? 0 : (b > ntx ? ntx : b);
+    c = c < 0 ? 0 : (c > nty ? nty : c);
+    d = d < 0 ? 0 : (d > nty ? nty : d);
+    if (!(b > a) || !(d > c)) {
+        for (int k = 0; k < 9; ++k) r[k] = (k == 0 || k == 2 || k == 4 || k == 6) ? 0 : -1;
+        r[8] = 0;
+        return;
+    }
+    r[4] = (int64_t)a; r[5] = (int64_t)b - 1; r[6] = (int64_t)c; r[7] = (int64_t)d - 1;
+    r[0] = r[4] * tw; r[1] = (r[5] + 1) * tw - 1; r[2] = r[6] * th; r[3] = (r[7] + 1) * th - 1;
+    if (r[1] > W - 1) r[1] = W - 1;
+    if (r[3] > H - 1) r[3] = H - 1;
+    r[8] = (r[5] - r[4] + 1) * (r[7] - r[6] + 1);
+}
+
+/* Largest eigenvalue of the 2D covariance [[a, b], [b, c]] with the 3DGS rasteriser's
+ * floor of 0.1 px^2 under the discriminant: (a + c)/2 + sqrt(max(0.1, ((a - c)/2)^2 + b^2)). */
+static double lambda_max_3dgs(double a, double b, double c)
+{
+    const double hd = 0.5 * (a - c), disc = hd * hd + b * b;
+    return 0.5 * (a + c) + sqrt(disc > 0.1 ? disc : 0.1);
+}
+
 /* ---------------------------------------------------------------------------
  * Per-Gaussian projection, colour and tile rectangle.
  *   m = R mu + t; cull when float32 depth <= znear (no far plane).
@@ -206,13 +242,18 @@ static void rect_from_edges(double ax, double bx, double ay, double by, int32_t 
  *   extent: alpha >= 1/255 <=> q <= 2 ln(255 sigma); the box covers q <= that level
  *   plus 1/64 so its edges never decide a pixel; half-extents sqrt(level Sigma_xx),
  *   sqrt(level Sigma_yy); tiles of tw x th pixels.
+ *   rule 1 (the 3DGS rasteriser's extent, for comparison with it): the tiles of the
+ *   square of radius ceil(3 sqrt(lambda_max)) pixels (rect_square), and a splat then
+ *   reaches only the pixels of those tiles (the image depends on the tile shape).
+ *   Gaussians with 255 sigma < 1, which can reach no pixel, get no tiles under
+ *   either rule.
  * Arrays: means/cov planes (double, [3][n] / [6][n]); opacity [n]; sh [3K][n]
  * (plane k*3+c). mask may be NULL (no recolour), otherwise M (row-major) and b.
  * ------------------------------------------------------------------------- */
 void orc_project(int64_t n, const double *means, const double *cov, const double *opacity,
                  const double *sh, int32_t deg, const orc_camera *cam, int32_t tw, int32_t th,
                  const uint8_t *mask, const double *M, const double *b,
-                 double *proj /* [n][P_NCOL] */, int64_t *iproj /* [n][I_NCOL] */)
+                 double *proj /* [n][P_NCOL] */, int64_t *iproj /* [n][I_NCOL] */, int32_t rule)
 {
     double campos[3];
     camera_centre(cam, campos);
@@ -223,6 +264,7 @@ void orc_project(int64_t n, const double *means, const double *cov, const double
         int64_t *q = iproj + i * I_NCOL;
         for (int k = 0; k < P_NCOL; ++k) p[k] = NAN;
         for (int k = 0; k < I_NCOL; ++k) q[k] = 0;
+        q[I_RULE] = rule;
         q[I_PXLO] = q[I_PYLO] = q[I_TXLO] = q[I_TYLO] = 0;
         q[I_PXHI] = q[I_PYHI] = q[I_TXHI] = q[I_TYHI] = -1;
         p[P_QEXT] = -1;
@@ -316,9 +358,33 @@ void orc_project(int64_t n, const double *means, const double *cov, const double
         const double level = 2.0 * log(255.0 * sigma) + Q_SLACK;
         const double ex = sqrt(level * sa), ey = sqrt(level * sc);
         p[P_QEXT] = level; p[P_EX] = ex; p[P_EY] = ey;
+        int64_t r0[9];
+        if (rule == 1) {
+            const double r3 = 3.0 * sqrt(lambda_max_3dgs(sa, sb, sc));
+            const double xc = p[P_U] - 0.5, yc = p[P_V] - 0.5;
+            rect_square(xc, yc, ceil(r3), cam->width, cam->height, tw, th, r0);
+            for (int k = 0; k < 4; ++k) q[I_PXLO + k] = r0[k];
+            for (int k = 0; k < 4; ++k) q[I_TXLO + k] = r0[4 + k];
+            q[I_COUNT] = r0[8];
+            q[I_STATUS] = r0[8] > 0 ? 0 : 4;
+            /* flag when a sub-pixel move of the centre, or 3 sqrt(lambda) near an integer
+               (its float32 value may round the radius the other way), changes the tiles */
+            const double e = EDGE_BAND_PX, er = EDGE_BAND_PX + 1e-5 * r3;
+            const double pert[7][3] = {{xc - e, yc, ceil(r3)}, {xc + e, yc, ceil(r3)}, {xc, yc - e, ceil(r3)},
+                                       {xc, yc + e, ceil(r3)}, {xc, yc, ceil(r3 - er)}, {xc, yc, ceil(r3 + er)},
+                                       {xc, yc, ceil(r3)}};
+            for (int k = 0; k < 6; ++k) {
+                int64_t r1[9];
+                rect_square(pert[k][0], pert[k][1], pert[k][2], cam->width, cam->height, tw, th, r1);
+                int same = r1[8] == r0[8];
+                if (same && r0[8] > 0)
+                    for (int j = 4; j < 8; ++j) same &= r1[j] == r0[j];
+                if (!same) q[I_FLAG] = 1;
+            }
+            continue;
+        }
         const double ax = p[P_U] - ex - 0.5, bx = p[P_U] + ex - 0.5;
         const double ay = p[P_V] - ey - 0.5, by = p[P_V] + ey - 0.5;
-        int64_t r0[9];
         rect_from_edges(ax, bx, ay, by, cam->width, cam->height, tw, th, r0);
         q[I_PXLO] = r0[0]; q[I_PXHI] = r0[1]; q[I_PYLO] = r0[2]; q[I_PYHI] = r0[3];
         q[I_TXLO] = r0[4]; q[I_TXHI] = r0[5]; q[I_TYLO] = r0[6]; q[I_TYHI] = r0[7];
@@ -490,14 +556,37 @@ static double box_level(const double *p)
     return 2.0 * log(s) + Q_SLACK;
 }
 
+/* 1 when Gaussian q may reach pixel (px, py): always under the alpha-box rule (its
+ * box holds every pixel it reaches); under the 3DGS square rule only in its tiles. */
+static int tile_reaches(const int64_t *q, int64_t px, int64_t py)
+{
+    return !q[I_RULE] || (q[I_PXLO] <= px && px <= q[I_PXHI] && q[I_PYLO] <= py && py <= q[I_PYHI]);
+}
+
+/* 1 when Gaussian (p, q) may reach a pixel of the window (x0, y0, w, h): its alpha >= 1/255
+ * box meets the window and, under the square rule, so does its tiles' pixel range. */
+static int window_reaches(const double *p, const int64_t *q, int32_t x0, int32_t y0, int32_t ww, int32_t wh)
+{
+    const double lev = box_level(p);
+    if (!(lev > 0)) return 0;
+    const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
+    /* pixel centres k + 1/2 within [u - ex, u + ex] */
+    if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) return 0;
+    if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) return 0;
+    if (q[I_RULE] && (q[I_PXHI] < x0 || q[I_PXLO] > x0 + ww - 1 || q[I_PYHI] < y0 || q[I_PYLO] > y0 + wh - 1)) return 0;
+    return 1;
+}
+
 /* The splats of `list` whose alpha at the pixel centre reaches the threshold (less
  * its rounding band), sorted front to back (z32, then index); returns their count. */
-static int64_t gather_candidates(int64_t ncand_all, const int64_t *list, const double *proj, double pxc, double pyc,
-                                 double du, cand_t *buf)
+static int64_t gather_candidates(int64_t ncand_all, const int64_t *list, const double *proj, const int64_t *iproj,
+                                 double pxc, double pyc, double du, cand_t *buf)
 {
     int64_t nc = 0;
+    const int64_t px = (int64_t)floor(pxc), py = (int64_t)floor(pyc);
     for (int64_t j = 0; j < ncand_all; ++j) {
         const int64_t i = list[j];
+        if (!tile_reaches(iproj + i * I_NCOL, px, py)) continue;
         const double *p = proj + i * P_NCOL;
         const double dx = pxc - p[P_U], dy = pyc - p[P_V];
         const double qv = p[P_CA] * dx * dx + 2.0 * p[P_CB] * dx * dy + p[P_CC] * dy * dy;
@@ -519,8 +608,7 @@ static void composite_pixel(int64_t ncand_all, const int64_t *list, const double
                             double *out_rgb, double *out_T, int64_t *out_last, int64_t *out_nb,
                             double *out_slack)
 {
-    (void)iproj;
-    const int64_t nc = gather_candidates(ncand_all, list, proj, pxc, pyc, du, buf);
+    const int64_t nc = gather_candidates(ncand_all, list, proj, iproj, pxc, pyc, du, buf);
 
     /* forward pass */
     double T = 1.0, C[3] = {0, 0, 0};
@@ -610,14 +698,7 @@ void orc_render_windows(int64_t n, const double *proj, const int64_t *iproj, int
             const int64_t *q = iproj + i * I_NCOL;
             const double *p = proj + i * P_NCOL;
             if (!visible_for_pixels(q, p)) continue;
-            if (!brute) {
-                const double lev = box_level(p);
-                if (!(lev > 0)) continue;
-                const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
-                /* pixel centres k + 1/2 within [u - ex, u + ex] */
-                if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) continue;
-                if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) continue;
-            }
+            if (!brute && !window_reaches(p, q, x0, y0, ww, wh)) continue;
             list[nl++] = i;
         }
         cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
@@ -639,10 +720,10 @@ void orc_render_windows(int64_t n, const double *proj, const int64_t *iproj, int
  * (z32, the sort key). flag = 1 where a float32 evaluation could decide differently:
  * an alpha near 1/255, or the transmittance within its rounding band of tau, at one of
  * the splats up to and including the crossing. */
-static void depth_pixel(int64_t ncand_all, const int64_t *list, const double *proj, double pxc, double pyc, double du,
-                        double tau, cand_t *buf, double *out_depth, int32_t *out_flag)
+static void depth_pixel(int64_t ncand_all, const int64_t *list, const double *proj, const int64_t *iproj, double pxc,
+                        double pyc, double du, double tau, cand_t *buf, double *out_depth, int32_t *out_flag)
 {
-    const int64_t nc = gather_candidates(ncand_all, list, proj, pxc, pyc, du, buf);
+    const int64_t nc = gather_candidates(ncand_all, list, proj, iproj, pxc, pyc, du, buf);
     double T = 1.0, relT = TERM_BAND_MIN;
     double depth = 0.0;
     int32_t flag = 0;
@@ -682,19 +763,15 @@ void orc_depth_windows(int64_t n, const double *proj, const int64_t *iproj, int3
         for (int64_t i = 0; i < n; ++i) {
             const int64_t *q = iproj + i * I_NCOL;
             const double *p = proj + i * P_NCOL;
-            if (!visible_for_pixels(q, p)) continue;
-            const double lev = box_level(p);
-            if (!(lev > 0)) continue;
-            const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
-            if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) continue;
-            if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) continue;
+            if (!visible_for_pixels(q, p) || !window_reaches(p, q, x0, y0, ww, wh)) continue;
             list[nl++] = i;
         }
         cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
         for (int32_t yy = 0; yy < wh; ++yy)
             for (int32_t xx = 0; xx < ww; ++xx) {
                 const int64_t o = offs[w] + (int64_t)yy * ww + xx;
-                depth_pixel(nl, list, proj, x0 + xx + 0.5, y0 + yy + 0.5, du, tau, buf, out_depth + o, out_flag + o);
+                depth_pixel(nl, list, proj, iproj, x0 + xx + 0.5, y0 + yy + 0.5, du, tau, buf, out_depth + o,
+                            out_flag + o);
             }
         free(buf);
         free(list);
@@ -720,12 +797,15 @@ void orc_depth_windows(int64_t n, const double *proj, const int64_t *iproj, int3
 
 /* One pixel's terms, over the candidate Gaussians list[0..nl) (a superset of the
  * Gaussians with alpha >= 1/255 at the pixel), accumulated into dsigma and drgb. */
-static void backward_pixel(int64_t nl, const int64_t *list, const double *proj, double pxc, double pyc,
-                           const double *bg, const double *g, cand_t *buf, double *Tl, double *dsigma, double *drgb)
+static void backward_pixel(int64_t nl, const int64_t *list, const double *proj, const int64_t *iproj, int64_t px,
+                           int64_t py, const double *bg, const double *g, cand_t *buf, double *Tl, double *dsigma,
+                           double *drgb)
 {
+    const double pxc = px + 0.5, pyc = py + 0.5;
     int64_t nc = 0;
     for (int64_t j = 0; j < nl; ++j) {
         const int64_t i = list[j];
+        if (!tile_reaches(iproj + i * I_NCOL, px, py)) continue;
         const double *p = proj + i * P_NCOL;
         const double dx = pxc - p[P_U], dy = pyc - p[P_V];
         const double qv = p[P_CA] * dx * dx + 2.0 * p[P_CB] * dx * dy + p[P_CC] * dy * dy;
@@ -817,7 +897,7 @@ void orc_backward(int64_t n, const double *proj, const int64_t *iproj, int32_t W
     double *Tl = (double *)malloc(sizeof(double) * (size_t)(nl > 0 ? nl : 1));
     for (int32_t py = 0; py < H; ++py)
         for (int32_t px = 0; px < W; ++px)
-            backward_pixel(nl, list, proj, px + 0.5, py + 0.5, bg, dldy + ((int64_t)py * W + px) * 3, buf, Tl, dsigma,
+            backward_pixel(nl, list, proj, iproj, px, py, bg, dldy + ((int64_t)py * W + px) * 3, buf, Tl, dsigma,
                            drgb);
     backward_chain(n, proj, iproj, M, drgb, dc0, dM);
     free(Tl);
@@ -843,12 +923,7 @@ void orc_backward_windows(int64_t n, const double *proj, const int64_t *iproj, i
         for (int64_t i = 0; i < n; ++i) {
             const int64_t *q = iproj + i * I_NCOL;
             const double *p = proj + i * P_NCOL;
-            if (!visible_for_pixels(q, p)) continue;
-            const double lev = box_level(p);
-            if (!(lev > 0)) continue;
-            const double ex = sqrt(lev * p[P_SA]), ey = sqrt(lev * p[P_SC]);
-            if (p[P_U] + ex - 0.5 < x0 || p[P_U] - ex - 0.5 > x0 + ww - 1) continue;
-            if (p[P_V] + ey - 0.5 < y0 || p[P_V] - ey - 0.5 > y0 + wh - 1) continue;
+            if (!visible_for_pixels(q, p) || !window_reaches(p, q, x0, y0, ww, wh)) continue;
             list[nl++] = i;
         }
         cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nl > 0 ? nl : 1));
@@ -856,8 +931,7 @@ void orc_backward_windows(int64_t n, const double *proj, const int64_t *iproj, i
         for (int32_t yy = 0; yy < wh; ++yy)
             for (int32_t xx = 0; xx < ww; ++xx) {
                 const int64_t px = x0 + xx, py = y0 + yy;
-                backward_pixel(nl, list, proj, px + 0.5, py + 0.5, bg, dldy + (py * W + px) * 3, buf, Tl, dsigma,
-                               drgb);
+                backward_pixel(nl, list, proj, iproj, px, py, bg, dldy + (py * W + px) * 3, buf, Tl, dsigma, drgb);
             }
         free(Tl);
         free(buf);

@@ -59,11 +59,15 @@ def crop_windows(w, crops, size=32):
     return [(int(x), int(y), size, size) for x, y in crops]
 
 
-def assert_pixels(gpu_rgb, orc_rgb, slack, tol, what=""):
-    """|gpu - oracle| <= tol + slack element-wise; return (max err outside band, n in band)."""
+def assert_pixels(gpu_rgb, orc_rgb, slack, tol, what="", max_band_frac=1e-3):
+    """|gpu - oracle| <= tol + slack element-wise, and at most max(8, max_band_frac of
+    the pixels) whose slack exceeds half the tolerance (so a wrong slack cannot quietly
+    loosen the check); return (max err outside band, n in band)."""
     err = np.abs(gpu_rgb - orc_rgb).max(axis=-1)
     bad = err > tol + slack
     assert not bad.any(), (f"{what}: {int(bad.sum())} pixels off by more than {tol} + slack; worst "
                            f"{err[bad].max():.3e} at {np.argwhere(bad)[:5].tolist()}")
     band = slack > 0.5 * tol
-    return float(err[~band].max()) if (~band).any() else 0.0, int(band.sum())
+    nband = int(band.sum())
+    assert nband <= max(8, int(max_band_frac * err.size)), f"{what}: {nband} of {err.size} pixels in band"
+    return float(err[~band].max()) if (~band).any() else 0.0, nband

@@ -56,10 +56,16 @@ def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1):
         dM.cpu().numpy().astype(np.float64).reshape(3, 3)
 
 
-def _close(got, ref, rel, what):
+# Gradient tolerance: 2e-5 of the largest entry plus 1e-4 of each entry. The float32
+# sums of a few thousand per-pixel terms carry about 1e-6 of the largest; the oracle's
+# FP64 gradient is pinned to central differences on the CPU.
+GRAD_ABS, GRAD_REL = 2e-5, 1e-4
+
+
+def _close(got, ref, what, abs_of_max=GRAD_ABS, rel=GRAD_REL):
     scale = max(np.abs(ref).max(), 1e-12)
     err = np.abs(got - ref)
-    bad = err > rel * scale + rel * np.abs(ref)
+    bad = err > abs_of_max * scale + rel * np.abs(ref)
     assert not bad.any(), f"{what}: {int(bad.sum())} entries off; max err {err.max():.3e} (scale {scale:.3e})"
     return float(err.max() / scale)
 
@@ -77,9 +83,9 @@ def test_backward_vs_oracle(R, orc, tile, ppt):
     d_ws = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
     img, dop, ddc, dM = _gpu_grads(R, d, d_ws, cam, tm, tM, tb, g, tile, ppt)
     gr = orc.backward(pr, g, M=M.astype(np.float64))
-    e1 = _close(dop, gr.dsigma, 2e-3, "dL/dopacity")
-    e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
-    e3 = _close(dM, gr.dM, 2e-3, "dL/dM")
+    e1 = _close(dop, gr.dsigma, "dL/dopacity")
+    e2 = _close(ddc, gr.dc0, "dL/dC0")
+    e3 = _close(dM, gr.dM, "dL/dM")
     assert mask.sum() > 0 and np.abs(gr.dM).max() > 0
     print(f"relative max errors: dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")
 
@@ -207,7 +213,7 @@ def test_backward_without_recolor_and_zero_gradient(R, orc):
             assert np.all(dop.cpu().numpy() == 0) and np.all(ddc.cpu().numpy() == 0)
         else:
             gr = orc.backward(pr, g)
-            _close(ddc.cpu().numpy().astype(np.float64), gr.dc0, 2e-3, "dC0 without recolour")
+            _close(ddc.cpu().numpy().astype(np.float64), gr.dc0, "dC0 without recolour")
 
 
 def test_backward_full_size_on_windows_vs_oracle(R, orc):
@@ -241,9 +247,9 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
     tM = torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda()
     tb = torch.from_numpy(v.recolor.b.copy()).cuda()
     img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (32, 16), 1)
-    e1 = _close(dop, gr.dsigma, 2e-3, "dL/dopacity")
-    e2 = _close(ddc, gr.dc0, 2e-3, "dL/dC0")
-    e3 = _close(dM, gr.dM, 2e-3, "dL/dM")
+    e1 = _close(dop, gr.dsigma, "dL/dopacity")
+    e2 = _close(ddc, gr.dc0, "dL/dC0")
+    e3 = _close(dM, gr.dM, "dL/dM")
     assert np.abs(gr.dsigma).max() > 0 and np.abs(gr.dM).max() > 0
     # every SH coefficient, on the Gaussians the windows reach
     K = (sc.sh_degree + 1) ** 2
@@ -257,6 +263,6 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
     touched = np.nonzero(np.abs(gr.drgb).sum(axis=1) > 0)[0]
     assert len(touched) > 100
     ref_sh = orc.sh_grad(sc, cam, pr, gr, M=M, idx=touched)
-    e4 = _close(dsh[:, touched].cpu().numpy().astype(np.float64), ref_sh, 2e-3, "dL/dSH")
+    e4 = _close(dsh[:, touched].cpu().numpy().astype(np.float64), ref_sh, "dL/dSH")
     print(f"full size: relative max errors dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e} dSH {e4:.2e} "
           f"({len(touched)} Gaussians)")

@@ -505,7 +505,7 @@ def _scene64_loss(orc, s2, cam, mask, M, b, g):
     mk = np.ascontiguousarray(mask.astype(np.uint8))
     c = camera(cam)
     lib().orc_project(n, _p(means), _p(cov), _p(op), _p(sh), s2.sh_degree, ctypes.byref(c), 16, 16,
-                      _p(mk), _p(_d(M).reshape(9)), _p(_d(b)), _p(f), _p(i))
+                      _p(mk), _p(_d(M).reshape(9)), _p(_d(b)), _p(f), _p(i), 0)
     pr = Projection(f, i, (16, 16), cam.width, cam.height)
     r = orc.render_image(pr, brute=True)
     return float((r.rgb * g).sum()), r
