@@ -321,7 +321,8 @@ DIFF_TILE, DIFF_PPT = (32, 16), 1
 def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     """1M Gaussians (FP32, SH 3), 8 views at 1280x720: render with the fused recolour
     (keeping the backward state), L2 loss against a seeded target, backward to the
-    opacities, the SH DC coefficients and M."""
+    opacities, the SH DC coefficients and M, summed over the 8 views (the loss is their
+    mean)."""
     import torch
 
     import synth
@@ -359,8 +360,9 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
             R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
                              loss.data_ptr() + 4 * k)
+            # the loss sums the views: the first view writes the gradients, the others add to them
             R.recogs_render_backward(sc, cams[k], o, ws[k].ws, imgs[k].data_ptr(), dimg.data_ptr(), dop.data_ptr(),
-                                     ddc.data_ptr(), dM.data_ptr())
+                                     ddc.data_ptr(), dM.data_ptr(), 1 if k else 0)
     for _ in range(max(2, warmup // 4)):
         step()
     reps = max(3, steps // 20)
@@ -381,7 +383,8 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
             "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
             "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.sum().item()),
-            "grad_M_norm": float(dM.norm().item())}
+            "grad_M_norm": float(dM.norm().item()), "grad_opacity_norm": float(dop.norm().item()),
+            "grad_dc_norm": float(ddc.norm().item()), "grad_over_views": len(w.views)}
 
 
 def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):

@@ -16,8 +16,10 @@
  *     one stride >= n.
  *   - Every call is enqueued on `stream` (NULL = the null stream) and returns a
  *     status. Argument errors are found on the host before anything is enqueued.
- *     recogs_render synchronises `stream` once (to read the number of tile keys);
- *     the other calls never synchronise.
+ *     recogs_render in its default (eager) mode synchronises `stream` once, to read
+ *     the number of tile keys; the read-back calls (recogs_workspace_readback,
+ *     recogs_workspace_keys_needed, recogs_batch_readback) wait for `stream`; the
+ *     other calls never synchronise.
  *   - On error, recogs_last_error() returns a message (thread-local, valid until
  *     the next call on the same thread). No call aborts or throws.
  *   - Float math on the GPU is float32; storage may be f16 / bf16 for opacity and SH.
@@ -135,6 +137,19 @@ typedef struct {
      * workspaces reject it). NULL: no depth map, depth_tau ignored. */
     float *depth_map;
     float depth_tau;
+    /* Which tiles list a splat (the paper renders with the original 3DGS rasteriser,
+     * Sec. 4; its extent is not stated there). 0 (default): every tile meeting the box
+     * that holds all pixels where alpha >= 1/255 (2 ln(255 sigma) + 1/64 of the conic's
+     * quadratic form), so tiles never change a pixel and every tile shape draws the
+     * same bits. 1: the 3DGS rasteriser's square, for comparison with it: radius
+     * r = ceil(3 sqrt(lambda_max)) pixels, lambda_max = (a + c)/2 +
+     * sqrt(max(0.1, ((a - c)/2)^2 + b^2)) of the 2D covariance [[a, b], [b, c]], tiles
+     * floor((x - r) / tile_w) up to, not including, floor((x + r + tile_w - 1) / tile_w)
+     * around x = u - 1/2 (the same in y), clipped to the image's tiles; a splat then
+     * reaches only the pixels of the tiles that list it, so the image depends on the
+     * tile shape. Either rule gives no tiles to a splat with 255 sigma < 1. INVALID
+     * otherwise. */
+    int32_t extent_rule;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds
@@ -176,6 +191,10 @@ typedef struct {
     double stage_ms_sum[8];
     int64_t profiled_frames;
     void *profile_state;         /* host-side event objects of mode 2 (library-owned) */
+    /* incremented by every recogs_render call on this workspace that passes its argument
+     * checks (zeroed by recogs_workspace_init): a caller that keeps a render's state for a
+     * later backward can tell whether another render has overwritten it since */
+    int64_t generation;
 } recogs_workspace;
 
 /* ---- support --------------------------------------------------------------- */
@@ -194,6 +213,13 @@ recogs_status recogs_workspace_init(recogs_workspace *ws, void *dev_mem, size_t 
 /* After a graph_mode render: wait for it and fill ws->num_keys (keys the view needs),
  * ws->num_visible and ws->depth_min_bits from the device header. */
 recogs_status recogs_workspace_readback(recogs_workspace *ws, hipStream_t stream);
+
+/* Tile keys the workspace's last render needed (eager or graph mode, whether or not they
+ * fitted ws->key_capacity), read from the device header into *out_keys (host). Waits for
+ * `stream`. 0 before the first render and for an empty scene. INVALID: NULL or
+ * uninitialised workspace, NULL out_keys. A render that returned CAPACITY is repeated
+ * with a workspace of at least this many keys. */
+recogs_status recogs_workspace_keys_needed(const recogs_workspace *ws, int64_t *out_keys, hipStream_t stream);
 
 /* Wait for the workspace's last profile_stages = 2 render and add its stage durations
  * to stage_ms_sum / profiled_frames. OK when nothing is pending. */
@@ -241,17 +267,20 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
 
 /* Backward of the render and of the fused recolour (eq. 8, restricted to opacity,
  * SH DC and the recolour matrix). Needs the workspace of the matching render (run
- * with keep_backward_state = 1) and its output image. dL_dimage float [H][W][3].
- * Outputs (overwritten): dL_dopacity float [n], dL_dsh_dc float [3][n] (gradient
- * w.r.t. the DC coefficients C_0 of each channel), dL_dM float [9] (zero when no
- * fused recolour). No atomics: every sum is taken in a fixed order, so results are
- * bit-identical between runs. The backward uses the workspace's sorted-key buffers
+ * with keep_backward_state = 1, no other render on the workspace since) and its output
+ * image. dL_dimage float [H][W][3].
+ * Outputs: dL_dopacity float [n], dL_dsh_dc float [3][n] (gradient w.r.t. the DC
+ * coefficients C_0 of each channel), dL_dM float [9] (zero when no fused recolour).
+ * accumulate 0: they are overwritten; 1: this view's gradients are added to them (a
+ * loss summed over views: render and backward each view in turn, accumulate 0 for the
+ * first); INVALID otherwise. No atomics: every sum is taken in a fixed order, so results
+ * are bit-identical between runs. The backward uses the workspace's sorted-key buffers
  * (keys0/keys1) as per-key gradient scratch; the tile lists and the rest of the
  * render's state stay valid, so it may be called again on the same render. */
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
                                      const recogs_render_opts *opts, const recogs_workspace *ws,
                                      const float *image, const float *dL_dimage, float *dL_dopacity,
-                                     float *dL_dsh_dc, float *dL_dM, hipStream_t stream);
+                                     float *dL_dsh_dc, float *dL_dM, int32_t accumulate, hipStream_t stream);
 
 /* L2 loss of an image against a target (the differentiable form's loss, an analog of
  * eq. 7): loss (device float, overwritten) = scale * sum (y - t)^2 and
@@ -271,12 +300,12 @@ recogs_status recogs_loss_l2(const float *image, const float *target, int64_t co
  * SH layout, so an optimiser can step the coefficient planes with it directly. Entries
  * 0..n-1 of every plane are written (zero for Gaussians that reach no pixel); the
  * padding entries n..stride-1 are left as they are.
- * Everything else (arguments, requirements, determinism, errors) as for
+ * Everything else (arguments, accumulate, requirements, determinism, errors) as for
  * recogs_render_backward; the DC planes equal its dL_dsh_dc bit for bit. */
 recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_camera *cam,
                                         const recogs_render_opts *opts, const recogs_workspace *ws,
                                         const float *image, const float *dL_dimage, float *dL_dopacity,
-                                        float *dL_dsh, float *dL_dM, hipStream_t stream);
+                                        float *dL_dsh, float *dL_dM, int32_t accumulate, hipStream_t stream);
 
 /* L1 term of the loss of eq. 7, with the gradient Sec. 4.1 writes out:
  * loss (device float, overwritten) = scale * sum |y - t| and
@@ -314,8 +343,8 @@ recogs_status recogs_adam_step(float *param, const float *grad, float *m, float 
  * scene's SH planes (scene->sh, float32 storage, [3 (deg + 1)^2][stride]) are updated
  * in place; m and v (device float, same layout, zero at step 1) are the moments.
  * Columns n..stride-1 are left untouched. dL_dopacity and dL_dM are written as by
- * recogs_render_backward_sh. UNSUPPORTED: storage other than float32; otherwise the
- * errors of the two calls. */
+ * recogs_render_backward_sh (overwritten). UNSUPPORTED: storage other than float32;
+ * otherwise the errors of the two calls. */
 recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const recogs_camera *cam,
                                              const recogs_render_opts *opts, const recogs_workspace *ws,
                                              const float *image, const float *dL_dimage, float *dL_dopacity, float *dL_dM,

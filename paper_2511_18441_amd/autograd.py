@@ -3,6 +3,11 @@
 Differentiable inputs: the activated opacities, the SH DC coefficients (the first
 three planes of the scene's SH array) and the fused recolour matrix M; gradients of
 eq. (8) restricted to those, as the refit of the paper updates colour only (Sec. 3.3).
+
+The backward replays the per-tile state the forward left in its workspace, so the
+workspace must not render anything else in between: a loss over several views uses
+one workspace per view. The forward records the workspace's render generation and the
+backward raises if another render has run on it since.
 """
 from __future__ import annotations
 
@@ -19,6 +24,7 @@ class RecogsRenderFn(torch.autograd.Function):
         Mc = M.detach().contiguous().reshape(9) if M is not None else None
         image = render(dscene, cam, ws, tile, ppt, bg, mask, Mc, b, keep_backward=True)
         ctx.save_for_backward(image)
+        ctx.stamp = (ws.ws, int(ws.ws.generation))
         ctx.args = (dscene, cam, ws, mask, Mc, b, tile, ppt, bg, opacity.dtype, sh_dc.dtype, M is not None)
         return image
 
@@ -26,6 +32,9 @@ class RecogsRenderFn(torch.autograd.Function):
     def backward(ctx, grad_image):
         (image,) = ctx.saved_tensors
         dscene, cam, ws, mask, Mc, b, tile, ppt, bg, op_dt, sh_dt, has_M = ctx.args
+        if ws.ws is not ctx.stamp[0] or int(ws.ws.generation) != ctx.stamp[1]:
+            raise RuntimeError("the workspace rendered again after this forward: its state now belongs to another "
+                               "render (use one workspace per view)")
         n = dscene.n
         dev = image.device
         g = grad_image.detach().to(torch.float32).contiguous()

@@ -30,7 +30,7 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
                 "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_render_backward_sh_adam",
-                "recogs_last_error")
+                "recogs_workspace_keys_needed", "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -61,7 +61,7 @@ class RenderOpts(ctypes.Structure):
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("output_chw", ctypes.c_int32),
-                ("depth_map", ctypes.c_void_p), ("depth_tau", ctypes.c_float)]
+                ("depth_map", ctypes.c_void_p), ("depth_tau", ctypes.c_float), ("extent_rule", ctypes.c_int32)]
 
 
 class Workspace(ctypes.Structure):
@@ -79,7 +79,7 @@ class Workspace(ctypes.Structure):
                 ("depth_passes", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32),
                 ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8),
                 ("stage_ms_sum", ctypes.c_double * 8), ("profiled_frames", ctypes.c_int64),
-                ("profile_state", ctypes.c_void_p)]
+                ("profile_state", ctypes.c_void_p), ("generation", ctypes.c_int64)]
 
 STAGES = ("preprocess", "scan", "readback", "depth_sort", "emit", "key_sort", "ranges", "blend")
 
@@ -107,10 +107,12 @@ def lib():
         L.recogs_select.argtypes = [P(Scene), P(Camera), P(SelectParams), vp, vp, vp]
         L.recogs_recolor.argtypes = [P(Scene), vp, vp, vp, vp, i32, vp]
         L.recogs_render.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp]
-        L.recogs_render_backward.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp, vp]
+        L.recogs_render_backward.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp, i32,
+                                             vp]
         L.recogs_loss_l2.argtypes = [vp, vp, i64, f32, vp, vp, vp]
         L.recogs_render_backward_sh.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp,
-                                                vp]
+                                                i32, vp]
+        L.recogs_workspace_keys_needed.argtypes = [P(Workspace), P(i64), vp]
         L.recogs_loss_l1.argtypes = [vp, vp, i64, f32, vp, vp, vp]
         L.recogs_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
         L.recogs_dssim_workspace_bytes.argtypes = [i32, i32]
@@ -195,10 +197,10 @@ def recogs_render(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, im
 
 
 def recogs_render_backward(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
-                           dL_dopacity, dL_dsh_dc, dL_dM, stream=None):
+                           dL_dopacity, dL_dsh_dc, dL_dM, accumulate=0, stream=None):
     return _check("recogs_render_backward", lib().recogs_render_backward(
         ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage,
-        dL_dopacity, dL_dsh_dc, dL_dM, _stream(stream)))
+        dL_dopacity, dL_dsh_dc, dL_dM, int(accumulate), _stream(stream)))
 
 
 def recogs_loss_l2(image, target, count, scale, dL_dimage, loss, stream=None):
@@ -207,10 +209,17 @@ def recogs_loss_l2(image, target, count, scale, dL_dimage, loss, stream=None):
 
 
 def recogs_render_backward_sh(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
-                              dL_dopacity, dL_dsh, dL_dM, stream=None):
+                              dL_dopacity, dL_dsh, dL_dM, accumulate=0, stream=None):
     return _check("recogs_render_backward_sh", lib().recogs_render_backward_sh(
         ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage, dL_dopacity,
-        dL_dsh, dL_dM, _stream(stream)))
+        dL_dsh, dL_dM, int(accumulate), _stream(stream)))
+
+
+def recogs_workspace_keys_needed(ws: Workspace, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check("recogs_workspace_keys_needed", lib().recogs_workspace_keys_needed(ctypes.byref(ws), ctypes.byref(out),
+                                                                              _stream(stream)))
+    return int(out.value)
 
 
 def recogs_render_backward_sh_adam(scene: Scene, cam: Camera, opts: RenderOpts, ws: Workspace, image, dL_dimage,
@@ -367,7 +376,8 @@ def select_struct(sp) -> SelectParams:
 
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
-                profile=False, sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5) -> RenderOpts:
+                profile=False, sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5,
+                extent_rule=0) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -383,6 +393,7 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.output_chw = 1 if chw else 0
     o.depth_map = depth.data_ptr() if depth is not None else None
     o.depth_tau = float(depth_tau)
+    o.extent_rule = int(extent_rule)
     return o
 
 
@@ -530,12 +541,12 @@ class DeviceWorkspace:
 
 def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None,
            M=None, b=None, keep_backward=False, image=None, sh=None, grow=True, stream=None, profile=False,
-           sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5):
+           sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5, extent_rule=0):
     """recogs_render into a (H, W, 3) float32 tensor ((3, H, W) with chw); grows the
     workspace once when the view needs more tile keys than it holds (eager mode). With
     graph_mode nothing is read back: check ws.readback() (num_keys > key_capacity means
     it overflowed). depth: a (H, W) float32 tensor that receives the rough depth map
-    (Sec. 3.2) at threshold depth_tau."""
+    (Sec. 3.2) at threshold depth_tau. extent_rule 1: the 3DGS rasteriser's square."""
     import torch
     c = camera_struct(cam)
     if image is None:
@@ -544,7 +555,8 @@ def render(dscene: DeviceScene, cam, ws: DeviceWorkspace, tile=(16, 16), ppt=1, 
     if depth is not None:
         if tuple(depth.shape) != (cam.height, cam.width) or depth.dtype != torch.float32 or not depth.is_contiguous():
             raise ValueError("depth must be a contiguous float32 (H, W) tensor")
-    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode, chw, depth, depth_tau)
+    o = opts_struct(tile, ppt, bg, mask, M, b, keep_backward, profile, sort_mode, graph_mode, chw, depth, depth_tau,
+                    extent_rule)
     sc = dscene.c_struct(sh)
     st = recogs_render(sc, c, o, ws.ws, image.data_ptr(), stream, check=False)
     if st == -2 and grow:
@@ -622,7 +634,7 @@ class DeviceBatch:
     the counts are computed, nothing is drawn) times `headroom`."""
 
     def __init__(self, dscenes, views, tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), key_capacity=None,
-                 headroom=1.25, device="cuda"):
+                 headroom=1.25, device="cuda", extent_rule=0):
         import torch
         self.dscenes = list(dscenes)
         self.device = device
@@ -642,7 +654,7 @@ class DeviceBatch:
                 self._keep += [mask, Mc, bc]
                 bv.mask, bv.M, bv.b = mask.data_ptr(), Mc.data_ptr(), bc.data_ptr()
             bv.image = self.images[k].data_ptr()
-        self.opts = opts_struct(tile, ppt, bg)
+        self.opts = opts_struct(tile, ppt, bg, extent_rule=extent_rule)
         self.tile, self.ppt = tuple(tile), int(ppt)
         if key_capacity is None:
             self._init(0)

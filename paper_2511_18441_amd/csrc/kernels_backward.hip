@@ -178,13 +178,20 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 // part[block][9] and k_dm_reduce adds them in a fixed order (deterministic).
 // ADAM (DEG >= 0): instead of writing dL/dSH, apply one Adam step with it to the SH
 // planes psh in place (moments am, av, same layout): the gradient never goes to memory.
+// prev + x for the accumulate mode, never fused with the multiply that produced x: an
+// accumulated gradient is then the float32 sum of the single-view gradients
+__device__ __forceinline__ float acc_add(float prev, float x) {
+#pragma clang fp contract(off)
+    return prev + x;
+}
+
 template <int DEG, bool ADAM>
 __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ gk, const uint32_t *__restrict__ koff,
                                                      const float4 *__restrict__ bwd, const uint32_t *__restrict__ count,
                                                      int64_t n, const float *__restrict__ M, float *__restrict__ dop,
                                                      float *__restrict__ out, float *__restrict__ part,
                                                      const float *__restrict__ means, int64_t stride, CamDev cam,
-                                                     float *__restrict__ psh, float *__restrict__ am,
+                                                     int acc, float *__restrict__ psh, float *__restrict__ am,
                                                      float *__restrict__ av, AdamArgs aa) {
     __shared__ float s_dm[4][9];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         gh[1] = (flags & 2u) ? a.z : 0.f;
         gh[2] = (flags & 4u) ? a.w : 0.f;
         sel = (flags & 8u) != 0;
-        dop[i] = a.x;
+        dop[i] = acc ? acc_add(dop[i], a.x) : a.x;
         float g[3];
         if (sel) {
 #pragma unroll
@@ -219,7 +226,10 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         }
         if constexpr (DEG < 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) out[c * n + i] = kSH0 * g[c];
+            for (int c = 0; c < 3; ++c) {
+                const float x = kSH0 * g[c];
+                out[c * n + i] = acc ? acc_add(out[c * n + i], x) : x;
+            }
         } else {
             constexpr int NC = (DEG + 1) * (DEG + 1);
             float Y[16];
@@ -241,7 +251,8 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
                         av[o] = vv;
                         psh[o] = pp;
                     } else {
-                        out[o] = Y[k] * g[c];
+                        const float x = Y[k] * g[c];
+                        out[o] = acc ? acc_add(out[o], x) : x;
                     }
                 }
         }
@@ -265,8 +276,10 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
             ((s_dm[0][threadIdx.x] + s_dm[1][threadIdx.x]) + s_dm[2][threadIdx.x]) + s_dm[3][threadIdx.x];
 }
 
-// dM[k] = sum over blocks of part[block][k], one workgroup, fixed summation order
-__global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ part, uint32_t nblocks, float *__restrict__ dM) {
+// dM[k] = sum over blocks of part[block][k] (added to dM[k] with acc), one workgroup,
+// fixed summation order
+__global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ part, uint32_t nblocks, float *__restrict__ dM,
+                                                   int acc) {
     // thread t adds blocks t, t + 256, ... in order, all nine sums at once (independent
     // loads); then a fixed tree over lanes and waves: the order never depends on timing
     __shared__ float s_w[4][9];
@@ -285,7 +298,8 @@ __global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ par
     __syncthreads();
     if (threadIdx.x < 9) {
         const int k = threadIdx.x;
-        dM[k] = ((s_w[0][k] + s_w[1][k]) + s_w[2][k]) + s_w[3][k];
+        const float v = ((s_w[0][k] + s_w[1][k]) + s_w[2][k]) + s_w[3][k];
+        dM[k] = acc ? acc_add(dM[k], v) : v;
     }
 }
 
@@ -346,17 +360,18 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
 // part: (ceil(n / 256)) x 9 floats of scratch; dM is written whole (zeros without M or n).
 // deg < 0: out = dL/dC0 [3][n]; deg 0..3: out = dL/dSH [3 (deg + 1)^2][stride], which needs
 // the centres (means, plane stride) and the camera.
+// acc: dop, out and dM are added to instead of written (a loss over several views).
 // adam non-null (deg 0..3): one Adam step on psh / am / av instead of writing out.
 void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bwd, const uint32_t *count, int64_t n,
                         const float *M, float *dop, float *out, float *dM, float *part, int deg, const float *means,
-                        int64_t stride, const CamDev &cam, hipStream_t st, float *psh, float *am, float *av,
+                        int64_t stride, const CamDev &cam, int acc, hipStream_t st, float *psh, float *am, float *av,
                         const AdamArgs *adam) {
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
     const AdamArgs aa = adam ? *adam : AdamArgs{0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
     if (n > 0) {
 #define RECOGS_FIN(D, A)                                                                                              \
     hipLaunchKernelGGL((k_grad_finish<D, A>), dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, out, part, \
-                       means, stride, cam, psh, am, av, aa)
+                       means, stride, cam, acc, psh, am, av, aa)
         if (adam) {
             switch (deg) {
             case 0: RECOGS_FIN(0, true); break;
@@ -375,8 +390,8 @@ void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bw
         }
 #undef RECOGS_FIN
     }
-    if (M && n > 0) hipLaunchKernelGGL(k_dm_reduce, dim3(1), dim3(256), 0, st, part, blocks, dM);
-    else launch_fill_u32((uint32_t *)dM, 0u, 9, st);
+    if (M && n > 0) hipLaunchKernelGGL(k_dm_reduce, dim3(1), dim3(256), 0, st, part, blocks, dM, acc);
+    else if (!acc) launch_fill_u32((uint32_t *)dM, 0u, 9, st);
 }
 
 void launch_loss_l2(const float *y, const float *tg, int64_t count, float scale, float *dldy, float *loss, hipStream_t st) {

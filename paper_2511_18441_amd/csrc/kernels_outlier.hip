@@ -22,8 +22,10 @@
 //      coordinates). A query whose rings reach kOlMaxRing without that bound (a far
 //      stray point) is deferred to a second kernel that scans the whole cloud with one
 //      workgroup per query (strided per-thread lists merged in LDS).
-//   4. double-precision block sums of D and D^2 give mu, sigma and the threshold; the
-//      keep mask and the compaction of the kept points (input order) follow.
+//   4. mu and sigma from compensated float32 sums (float-float, TwoSum) in a fixed order:
+//      a pass for the sum of D, a pass for the sum of (D - mu)^2; the threshold, the keep
+//      mask (float32 comparison) and the compaction of the kept points (input order)
+//      follow. No double precision on the GPU.
 #include "recogs_internal.hpp"
 
 namespace recogs {
@@ -60,9 +62,8 @@ struct OlHdr {
     uint32_t bx, by, bz;  // slot bits per axis
     uint32_t ndefer;      // queries left to the whole-cloud scan
     uint32_t nslow;       // queries left to the wave-per-query search
-    uint32_t pad[3];
-    double thr;           // mu + std_ratio sigma
-    double mu, sigma;
+    float thr;            // mu + std_ratio sigma
+    float mu, sigma;
 };
 
 __device__ __forceinline__ void ol_load(const float *__restrict__ pts, int64_t stride, int64_t i, float &x, float &y,
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ h
     __shared__ float s_ext[3];
     constexpr int PER = kOlBins / 64;
     const int a = threadIdx.x >> 6, l = (int)lane_id();
-    const uint64_t lo_need = (uint64_t)((double)n * 0.01), hi_need = (uint64_t)((double)n * 0.99);
+    const uint64_t lo_need = (uint64_t)n / 100u, hi_need = (uint64_t)n * 99u / 100u;
     uint32_t c[PER];
     uint32_t mine = 0;
 #pragma unroll
@@ -217,8 +218,9 @@ __global__ __launch_bounds__(192) void k_ol_setup(const uint32_t *__restrict__ h
     __syncthreads();
     if (threadIdx.x == 0) {
         const float L = fmaxf(s_ext[0], fmaxf(s_ext[1], s_ext[2]));
-        int D = (int)ceil(2.0 * cbrt((double)n));
-        D = D < 1 ? 1 : (D > kOlMaxDim ? kOlMaxDim : D);
+        // D = ceil(2 n^(1/3)), the least D with D^3 >= 8 n, capped at kOlMaxDim
+        int D = 1;
+        while (D < kOlMaxDim && (uint64_t)D * D * D < 8u * (uint64_t)n) ++D;
         float h = L / (float)D;
         if (!(h > 0.f) || !isfinite(h)) h = 1.f;   // all points coincide (or a degenerate box)
         hdr->h = h;
@@ -477,65 +479,90 @@ __global__ __launch_bounds__(kOlFarThreads) void k_ol_knn_far(const float4 *__re
     }
 }
 
-// 4a. block sums of D and D^2 in double -> part[blk][2]
-__global__ __launch_bounds__(256) void k_ol_stats(const float *__restrict__ dmean, int64_t n, double *__restrict__ part) {
-    __shared__ double s[4][2];
-    double a = 0.0, b = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const double d = dmean[i];
-        a += d;
-        b += d * d;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-    }
-    if (lane_id() == 0) {
-        s[threadIdx.x >> 6][0] = a;
-        s[threadIdx.x >> 6][1] = b;
+// Compensated float32 sums: a value held as hi + lo, each addition through Knuth's
+// TwoSum (the rounding error of hi + b is exact and goes to lo).
+struct FF { float hi, lo; };
+__device__ __forceinline__ FF ff_add(FF a, float b) {
+    const float s = a.hi + b, bb = s - a.hi;
+    return FF{s, a.lo + ((a.hi - (s - bb)) + (b - bb))};
+}
+__device__ __forceinline__ FF ff_merge(FF a, FF b) {
+    const float s = a.hi + b.hi, bb = s - a.hi;
+    return FF{s, (a.lo + b.lo) + ((a.hi - (s - bb)) + (b.hi - bb))};
+}
+__device__ __forceinline__ FF ff_wave(FF a) {   // butterfly over the wave, the same order every run
+    for (int o = 32; o > 0; o >>= 1) a = ff_merge(a, FF{__shfl_xor(a.hi, o), __shfl_xor(a.lo, o)});
+    return a;
+}
+// the workgroup's 256-thread sum (every wave reaches it), fixed order; valid in thread 0
+__device__ __forceinline__ FF ff_block(FF a, FF (*s)[1]) {
+    a = ff_wave(a);
+    if (lane_id() == 0) s[threadIdx.x >> 6][0] = a;
+    __syncthreads();
+    return ff_merge(ff_merge(s[0][0], s[1][0]), ff_merge(s[2][0], s[3][0]));
+}
+// sum of the nblk partials part[0..nblk) by one wave (lanes stride, then the butterfly)
+__device__ __forceinline__ FF ff_parts(const float2 *__restrict__ part, int nblk) {
+    FF a{0.f, 0.f};
+    for (int k = (int)lane_id(); k < nblk; k += 64) a = ff_merge(a, FF{part[k].x, part[k].y});
+    return ff_wave(a);
+}
+
+// 4a. per workgroup: compensated sum of D -> part[blk]
+__global__ __launch_bounds__(256) void k_ol_sum(const float *__restrict__ dmean, int64_t n, float2 *__restrict__ part) {
+    __shared__ FF s[4][1];
+    FF a{0.f, 0.f};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a = ff_add(a, dmean[i]);
+    a = ff_block(a, s);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_float2(a.hi, a.lo);
+}
+
+// 4b. per workgroup: mu from the partial sums (every workgroup the same bits), then the
+// compensated sum of (D - mu)^2 -> part2[blk]; workgroup 0 stores mu
+__global__ __launch_bounds__(256) void k_ol_var(const float *__restrict__ dmean, int64_t n, const float2 *__restrict__ part,
+                                                int nblk, float2 *__restrict__ part2, OlHdr *__restrict__ hdr) {
+    __shared__ FF s[4][1];
+    __shared__ float s_mu;
+    if (threadIdx.x < 64) {
+        const FF t = ff_parts(part, nblk);
+        if (threadIdx.x == 0) s_mu = (t.hi + t.lo) / (float)n;
     }
     __syncthreads();
+    const float mu = s_mu;
+    FF a{0.f, 0.f};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float d = dmean[i] - mu;
+        a = ff_add(a, d * d);
+    }
+    a = ff_block(a, s);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s[0][0] + s[1][0] + s[2][0] + s[3][0];
-        part[2 * blockIdx.x + 1] = s[0][1] + s[1][1] + s[2][1] + s[3][1];
+        part2[blockIdx.x] = make_float2(a.hi, a.lo);
+        if (blockIdx.x == 0) hdr->mu = mu;
     }
 }
 
-// 4b. threshold: one wave, lanes stride over the partials, then a butterfly (a fixed
-// order, so the threshold is the same on every run)
-__global__ __launch_bounds__(64) void k_ol_thr(const double *__restrict__ part, int nblk, int64_t n, float std_ratio,
+// 4c. threshold from the summed squares: one wave, a fixed order (the same on every run)
+__global__ __launch_bounds__(64) void k_ol_thr(const float2 *__restrict__ part2, int nblk, int64_t n, float std_ratio,
                                                OlHdr *__restrict__ hdr) {
-    const int l = (int)lane_id();
-    double a = 0.0, b = 0.0;
-    for (int k = l; k < nblk; k += 64) {
-        a += part[2 * k];
-        b += part[2 * k + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-    }
-    if (l != 0) return;
-    const double mu = n > 0 ? a / (double)n : 0.0;
-    double var = n > 0 ? b / (double)n - mu * mu : 0.0;
-    var = var > 0.0 ? var : 0.0;
-    hdr->mu = mu;
-    hdr->sigma = sqrt(var);
-    hdr->thr = mu + (double)std_ratio * sqrt(var);
+    const FF t = ff_parts(part2, nblk);
+    if (lane_id() != 0) return;
+    const float sigma = sqrtf(fmaxf((t.hi + t.lo) / (float)n, 0.f));
+    hdr->sigma = sigma;
+    hdr->thr = hdr->mu + std_ratio * sigma;
 }
 
-// 4c. keep mask and kept count per workgroup of kOlBlock points
+// 4d. keep mask and kept count per workgroup of kOlBlock points
 __global__ __launch_bounds__(256) void k_ol_keep(const float *__restrict__ dmean, int64_t n, const OlHdr *__restrict__ hdr,
                                                  uint8_t *__restrict__ keep, uint32_t *__restrict__ part) {
     __shared__ uint32_t s_w[4];
-    const double thr = hdr->thr;
+    const float thr = hdr->thr;
     const int64_t base = (int64_t)blockIdx.x * kOlBlock;
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < kOlItems; ++k) {
         const int64_t i = base + k * 256 + threadIdx.x;
         if (i < n) {
-            const bool kp = (double)dmean[i] <= thr;
+            const bool kp = dmean[i] <= thr;
             keep[i] = kp ? 1 : 0;
             c += kp ? 1u : 0u;
         }
@@ -546,7 +573,7 @@ __global__ __launch_bounds__(256) void k_ol_keep(const float *__restrict__ dmean
     if (threadIdx.x == 0) part[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-// 4d. compaction of the kept points in input order (offsets from the scanned counts)
+// 4e. compaction of the kept points in input order (offsets from the scanned counts)
 __global__ __launch_bounds__(256) void k_ol_write(const float *__restrict__ pts, int64_t n, int64_t stride,
                                                   const uint8_t *__restrict__ keep, const uint32_t *__restrict__ part,
                                                   float *__restrict__ out, int64_t out_stride) {
@@ -610,7 +637,7 @@ static OlLayout ol_layout(int64_t n) {
     L.scount = take(4 * sort_count_words((uint64_t)nn));
     L.ranges = take(8 * slots);
     L.bpart = take(4 * 6 * kOlRedBlocks);
-    L.spart = take(8 * 2 * kOlRedBlocks);
+    L.spart = take(8 * 2 * kOlRedBlocks);   // two float2 partials per reduction workgroup
     L.kpart = take(4 * ((nn + kOlBlock - 1) / kOlBlock + 1));
     L.defer = take(4 * nn);
     L.slow = take(4 * nn);
@@ -670,8 +697,10 @@ bool launch_outliers(const float *pts, int64_t n, int64_t stride, int k, float s
     else if (k == 8) knn_launch<8>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
     else if (k == 16) knn_launch<16>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
     else knn_launch<32>(pts, n, stride, hdr, spts, ranges, slow, defer, dmean, st);
-    hipLaunchKernelGGL(k_ol_stats, dim3(rb), dim3(256), 0, st, dmean, n, (double *)(b + L.spart));
-    hipLaunchKernelGGL(k_ol_thr, dim3(1), dim3(64), 0, st, (const double *)(b + L.spart), rb, n, std_ratio, hdr);
+    float2 *sp1 = (float2 *)(b + L.spart), *sp2 = sp1 + kOlRedBlocks;
+    hipLaunchKernelGGL(k_ol_sum, dim3(rb), dim3(256), 0, st, dmean, n, sp1);
+    hipLaunchKernelGGL(k_ol_var, dim3(rb), dim3(256), 0, st, dmean, n, sp1, rb, sp2, hdr);
+    hipLaunchKernelGGL(k_ol_thr, dim3(1), dim3(64), 0, st, sp2, rb, n, std_ratio, hdr);
     const uint32_t nblk = (uint32_t)((n + kOlBlock - 1) / kOlBlock);
     hipLaunchKernelGGL(k_ol_keep, dim3(nblk), dim3(256), 0, st, dmean, n, hdr, keep, kpart);
     launch_excl_scan_u32(kpart, nblk, count, st);

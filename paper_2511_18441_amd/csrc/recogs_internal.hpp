@@ -161,6 +161,7 @@ struct CamDev {
     float limx, limy;       // 1.3 * (W/2)/fx, 1.3 * (H/2)/fy
     float campos[3];
     int32_t W, H, tw, th, tiles_x, tiles_y;
+    int32_t extent_rule;    // 0: alpha >= 1/255 box; 1: the 3DGS rasteriser's square (recogs_render_opts)
 };
 
 struct SceneDev {

@@ -42,6 +42,11 @@ __device__ __forceinline__ void view_basis(const CamDev &cam, float mx, float my
 //   EWA: J at the 1.3x-frustum-clamped position, Sigma2D = J R Sigma R^T J^T + 0.3 I.
 //   Cull det <= 0 and 255 sigma < 1. Box of q <= 2 ln(255 sigma) + 1/64 -> pixel range
 //   [ceil(u - ex - 1/2), floor(u + ex - 1/2)] clipped -> tile rectangle and count.
+//   Extent rule 1 instead lists the tiles of the 3DGS rasteriser's square: radius
+//   r = ceil(3 sqrt(lambda_max)), lambda_max = (A + C)/2 + sqrt(max(0.1, ((A - C)/2)^2 + B^2))
+//   (the discriminant as a sum of squares: no cancellation), tiles floor((x - r) / tw) up
+//   to floor((x + r + tw - 1) / tw) exclusive around x = u - 1/2 (the same in y), clipped
+//   to the grid. The record keeps the box: the blend's region test stays exact.
 //   Colour max(0, f + 1/2) or, for selected Gaussians of a fused recolour,
 //   max(0, M (f + 1/2) + b).
 // Writes the splat record, depth bits, packed tile rectangle and count; folds the
@@ -91,13 +96,35 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev 
                     const float level = 2.f * logf(255.f * sigma) + kQSlack;
                     const float ex = sqrtf(level * A), ey = sqrtf(level * C);
                     const float u = cam.fx * (x / z) + cam.cx, v = cam.fy * (y / z) + cam.cy;
-                    const float fx0 = fmaxf(ceilf(u - ex - 0.5f), 0.f), fx1 = fminf(floorf(u + ex - 0.5f), (float)(cam.W - 1));
-                    const float fy0 = fmaxf(ceilf(v - ey - 0.5f), 0.f), fy1 = fminf(floorf(v + ey - 0.5f), (float)(cam.H - 1));
-                    if (fx0 <= fx1 && fy0 <= fy1) {
-                        const uint32_t tx0 = (uint32_t)fx0 / cam.tw, tx1 = (uint32_t)fx1 / cam.tw;
-                        const uint32_t ty0 = (uint32_t)fy0 / cam.th, ty1 = (uint32_t)fy1 / cam.th;
-                        cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-                        rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                    if (cam.extent_rule == 0) {
+                        const float fx0 = fmaxf(ceilf(u - ex - 0.5f), 0.f), fx1 = fminf(floorf(u + ex - 0.5f), (float)(cam.W - 1));
+                        const float fy0 = fmaxf(ceilf(v - ey - 0.5f), 0.f), fy1 = fminf(floorf(v + ey - 0.5f), (float)(cam.H - 1));
+                        if (fx0 <= fx1 && fy0 <= fy1) {
+                            const uint32_t tx0 = (uint32_t)fx0 / cam.tw, tx1 = (uint32_t)fx1 / cam.tw;
+                            const uint32_t ty0 = (uint32_t)fy0 / cam.th, ty1 = (uint32_t)fy1 / cam.th;
+                            cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                            rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                        }
+                    } else {
+                        const float hd = 0.5f * (A - C);
+                        const float lam = 0.5f * (A + C) + sqrtf(fmaxf(0.1f, hd * hd + B * B));
+                        const float r = ceilf(3.f * sqrtf(lam));
+                        const float xc = u - 0.5f, yc = v - 0.5f;
+                        const float twf = (float)cam.tw, thf = (float)cam.th;
+                        // tile sizes are powers of two: the divisions are exact
+                        const float gx = (float)cam.tiles_x, gy = (float)cam.tiles_y;
+                        const float ax = fminf(fmaxf(floorf((xc - r) / twf), 0.f), gx);
+                        const float bx = fminf(fmaxf(floorf((xc + r + (twf - 1.f)) / twf), 0.f), gx);
+                        const float ay = fminf(fmaxf(floorf((yc - r) / thf), 0.f), gy);
+                        const float by = fminf(fmaxf(floorf((yc + r + (thf - 1.f)) / thf), 0.f), gy);
+                        if (bx > ax && by > ay) {
+                            const uint32_t tx0 = (uint32_t)ax, tx1 = (uint32_t)bx - 1u;
+                            const uint32_t ty0 = (uint32_t)ay, ty1 = (uint32_t)by - 1u;
+                            cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                            rr = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+                        }
+                    }
+                    if (cnt > 0) {
                         // colour (eq. 2) at the view direction of the centre
                         constexpr int NC = (DEG + 1) * (DEG + 1);
                         float Y[16];

@@ -39,8 +39,8 @@ int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uin
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
-                        float *, float *, float *, int, const float *, int64_t, const CamDev &, hipStream_t, float *, float *,
-                        float *, const AdamArgs *);
+                        float *, float *, float *, int, const float *, int64_t, const CamDev &, int, hipStream_t, float *,
+                        float *, float *, const AdamArgs *);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
@@ -259,8 +259,9 @@ recogs_status check_camera(const recogs_camera *c) {
     return RECOGS_OK;
 }
 
-CamDev make_cam(const recogs_camera &c, int tw, int th) {
+CamDev make_cam(const recogs_camera &c, int tw, int th, int extent_rule = 0) {
     CamDev d;
+    d.extent_rule = extent_rule;
     for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
     for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
     d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy; d.znear = c.znear;
@@ -301,6 +302,7 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (o->px_per_thread != 1 && o->px_per_thread != 2 && o->px_per_thread != 4)
         return fail(RECOGS_ERR_UNSUPPORTED, "px_per_thread %d not one of 1, 2, 4", o->px_per_thread);
     if (o->output_chw != 0 && o->output_chw != 1) return fail(RECOGS_ERR_INVALID, "output_chw %d not 0 or 1", o->output_chw);
+    if (o->extent_rule != 0 && o->extent_rule != 1) return fail(RECOGS_ERR_INVALID, "extent_rule %d not 0 or 1", o->extent_rule);
     if (o->depth_map && !region_shape(o->tile_w, o->tile_h, o->px_per_thread))
         return fail(RECOGS_ERR_UNSUPPORTED, "depth_map needs tile_h a multiple of 8 * px_per_thread (%dx%d, %d)",
                     o->tile_w, o->tile_h, o->px_per_thread);
@@ -438,6 +440,21 @@ recogs_status recogs_workspace_readback(recogs_workspace *ws, hipStream_t stream
     return RECOGS_OK;
 }
 
+recogs_status recogs_workspace_keys_needed(const recogs_workspace *ws, int64_t *out_keys, hipStream_t stream) {
+    g_err[0] = 0;
+    if (!ws || !ws->base) return fail(RECOGS_ERR_INVALID, "workspace not initialised");
+    if (!out_keys) return fail(RECOGS_ERR_INVALID, "out_keys is NULL");
+    if (ws->generation == 0 || ws->last_n == 0) {  // no render yet, or an empty scene
+        *out_keys = 0;
+        return RECOGS_OK;
+    }
+    uint32_t h[2] = {0, 0};
+    RECOGS_TRY_HIP(hipMemcpyAsync(h, at<uint32_t>(ws, ws->off_header) + H_K_LO, sizeof(h), hipMemcpyDeviceToHost, stream));
+    RECOGS_TRY_HIP(hipStreamSynchronize(stream));
+    *out_keys = (int64_t)((uint64_t)h[0] | ((uint64_t)h[1] << 32));
+    return RECOGS_OK;
+}
+
 void recogs_workspace_release(recogs_workspace *ws) {
     if (!ws || !ws->profile_state) return;
     ProfileState *ps = (ProfileState *)ws->profile_state;
@@ -492,10 +509,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     if (scene->n > 0 && !scene->cov3d) return fail(RECOGS_ERR_INVALID, "scene cov3d is NULL");
 
     const int64_t n = scene->n;
-    const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
+    const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h, opts->extent_rule);
     const int ntiles = cd.tiles_x * cd.tiles_y;
     uint32_t *hdr = at<uint32_t>(ws, ws->off_header);
     SplatRec *rec = at<SplatRec>(ws, ws->off_rec);
+    ++ws->generation;
     float4 *bwd = at<float4>(ws, ws->off_bwd);
     uint32_t *zb = at<uint32_t>(ws, ws->off_zbits);
     uint2 *rect = at<uint2>(ws, ws->off_rect);
@@ -606,8 +624,9 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
 // dL/dSH [3 (deg + 1)^2][scene stride].
 static recogs_status backward_impl(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
                                    const recogs_workspace *ws, const float *image, const float *dL_dimage,
-                                   float *dL_dopacity, float *out, float *dL_dM, bool all_bands, hipStream_t stream,
-                                   float *am = nullptr, float *av = nullptr, const AdamArgs *adam = nullptr) {
+                                   float *dL_dopacity, float *out, float *dL_dM, int32_t accumulate, bool all_bands,
+                                   hipStream_t stream, float *am = nullptr, float *av = nullptr,
+                                   const AdamArgs *adam = nullptr) {
     g_err[0] = 0;
     recogs_status s;
     if ((s = check_scene(scene)) != RECOGS_OK) return s;
@@ -622,6 +641,7 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     if (ws->num_keys > ws->key_capacity) return fail(RECOGS_ERR_INVALID, "the render overflowed its key capacity");
     if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || (!out && !adam))))
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
+    if (accumulate != 0 && accumulate != 1) return fail(RECOGS_ERR_INVALID, "accumulate %d not 0 or 1", accumulate);
     const int64_t n = scene->n;
     const int ntiles = ws->tiles_x * ws->tiles_y;
     // per-(Gaussian, tile) gradient slots, 16 bytes per key: the span of both sorted-key
@@ -639,21 +659,22 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
     launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, out,
                        dL_dM, at<float>(ws, ws->off_gpart), all_bands ? scene->sh_degree : -1, scene->means,
-                       scene->stride, cd, stream, adam ? (float *)scene->sh : nullptr, am, av, adam);
+                       scene->stride, cd, accumulate, stream, adam ? (float *)scene->sh : nullptr, am, av, adam);
     return hip_check("backward");
 }
 
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
                                      const recogs_workspace *ws, const float *image, const float *dL_dimage,
-                                     float *dL_dopacity, float *dL_dsh_dc, float *dL_dM, hipStream_t stream) {
-    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh_dc, dL_dM, false, stream);
+                                     float *dL_dopacity, float *dL_dsh_dc, float *dL_dM, int32_t accumulate,
+                                     hipStream_t stream) {
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh_dc, dL_dM, accumulate, false, stream);
 }
 
 recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_camera *cam,
                                         const recogs_render_opts *opts, const recogs_workspace *ws, const float *image,
                                         const float *dL_dimage, float *dL_dopacity, float *dL_dsh, float *dL_dM,
-                                        hipStream_t stream) {
-    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh, dL_dM, true, stream);
+                                        int32_t accumulate, hipStream_t stream) {
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, dL_dsh, dL_dM, accumulate, true, stream);
 }
 
 recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const recogs_camera *cam,
@@ -670,7 +691,7 @@ recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const re
     if (scene->n > 0 && (!m || !v)) return fail(RECOGS_ERR_INVALID, "NULL moment pointer");
     const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
     const AdamArgs a{lr, beta1, beta2, eps, (float)c1, (float)c2};
-    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, nullptr, dL_dM, true, stream, m, v, &a);
+    return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, nullptr, dL_dM, 0, true, stream, m, v, &a);
 }
 
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale, float *dL_dimage,
@@ -920,7 +941,7 @@ recogs_status recogs_batch_init(recogs_batch_workspace *ws, void *dev_mem, size_
     for (int v = 0; v < nviews; ++v) {
         const recogs_batch_view &bv = views[v];
         vd[v].sc = make_scene(bv.scene);
-        vd[v].cam = make_cam(bv.cam, opts->tile_w, opts->tile_h);
+        vd[v].cam = make_cam(bv.cam, opts->tile_w, opts->tile_h, opts->extent_rule);
         vd[v].rc = RecolorDev{bv.mask, bv.M, bv.b};
         vd[v].image = bv.image;
         for (int c = 0; c < 3; ++c) vd[v].bg[c] = opts->bg[c];

@@ -6,7 +6,7 @@ import synth
 
 
 def gpu_run(w, view=0, tile=(16, 16), ppt=1, fused=None, keep_backward=False, key_capacity=None, ws=None,
-            dscene=None, bg=(0.0, 0.0, 0.0), sort_mode=0):
+            dscene=None, bg=(0.0, 0.0, 0.0), sort_mode=0, extent_rule=0):
     """Render view `view` of workload `w` through recogs_render. `fused` = (mask uint8 np, M, b)."""
     import torch
     import paper_2511_18441_amd as R
@@ -22,7 +22,8 @@ def gpu_run(w, view=0, tile=(16, 16), ppt=1, fused=None, keep_backward=False, ke
         mask = torch.from_numpy(np.asarray(fused[0], np.uint8)).cuda()
         M = torch.from_numpy(np.asarray(fused[1], np.float32).reshape(9)).cuda()
         b = torch.from_numpy(np.asarray(fused[2], np.float32).reshape(3)).cuda()
-    img = R.render(dscene, cam, ws, tile, ppt, bg, mask, M, b, keep_backward, sort_mode=sort_mode)
+    img = R.render(dscene, cam, ws, tile, ppt, bg, mask, M, b, keep_backward, sort_mode=sort_mode,
+                   extent_rule=extent_rule)
     torch.cuda.synchronize()
     return dict(img=img, ws=ws, dscene=dscene, mask=mask, M=M, b=b, cam=cam, tile=tile, ppt=ppt)
 

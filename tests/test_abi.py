@@ -44,8 +44,9 @@ int main(void) {
   S(recogs_scene) S(recogs_camera) S(recogs_select_params) S(recogs_render_opts) S(recogs_workspace)
   S(recogs_batch_view) S(recogs_batch_workspace)
   O(recogs_render_opts, mask) O(recogs_render_opts, sort_mode) O(recogs_render_opts, depth_map)
-  O(recogs_render_opts, depth_tau)
+  O(recogs_render_opts, depth_tau) O(recogs_render_opts, extent_rule)
   O(recogs_workspace, off_rec) O(recogs_workspace, num_keys) O(recogs_workspace, stage_ms)
+  O(recogs_workspace, generation)
   O(recogs_batch_workspace, pairs) O(recogs_batch_workspace, off_views) O(recogs_batch_workspace, num_keys)
   O(recogs_batch_view, image)
   return 0;
@@ -104,10 +105,26 @@ def test_host_argument_errors_before_any_launch(R):
     # unsupported tile shape / pixels per thread
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 8), 1), ws, 1, 0) == -3
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 3), ws, 1, 0) == -3
-    # output layout flag outside {0, 1}
+    # output layout flag and extent rule outside {0, 1}
     o_bad = B.opts_struct((16, 16), 1)
     o_bad.output_chw = 2
     assert status(B.recogs_render, sc, cam, o_bad, ws, 1, 0) == -1
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, extent_rule=2), ws, 1, 0) == -1
+    assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, extent_rule=-1), ws, 1, 0) == -1
+    # key count of a workspace: not initialised; before any render it is 0 without a device access
+    with pytest.raises(R.RecogsError) as e:
+        B.recogs_workspace_keys_needed(ws, 0)
+    assert e.value.status == -1
+    fake = B.Workspace()
+    fake.base, fake.width, fake.height, fake.tile_w, fake.tile_h = 256, 64, 64, 16, 16
+    assert B.recogs_workspace_keys_needed(fake, 0) == 0
+    # backward: accumulate outside {0, 1}, refused before any launch (an empty scene's
+    # workspace state, faked on the host)
+    ok = B.opts_struct((16, 16), 1, keep_backward=True)
+    assert status(B.recogs_render_backward, sc, cam, ok, fake, 8, 8, 8, 8, 8, 2, 0) == -1
+    assert "accumulate" in R.recogs_last_error()
+    assert status(B.recogs_render_backward_sh, sc, cam, ok, fake, 8, 8, 8, 8, 8, -1, 0) == -1
+    assert status(B.recogs_render_backward, sc, cam, B.opts_struct((16, 16), 1), fake, 8, 8, 8, 8, 8, 0, 0) == -1
     # rough depth map: threshold outside (0, 1], a tile form without one wave per region
     dep = 64  # any non-NULL device address: the options are refused before any launch
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, depth=_Ptr(dep), depth_tau=0.0), ws, 1, 0) == -1

@@ -216,6 +216,99 @@ def test_fused_recolor_render(R, orc):
     assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, "fused recolour")
 
 
+@pytest.mark.parametrize("deg", [1, 2])
+def test_sh_degrees_one_and_two(R, orc, deg):
+    """Scenes of SH degree 1 and 2 (eq. 2 sums bands l <= deg): the whole 800x800 image
+    with the fused recolour against the oracle, then the gradient of every coefficient
+    on the Gaussians that a windowed upstream gradient reaches."""
+    import torch
+    rng = np.random.default_rng(90 + deg)
+    sc = synth.make_scene_mid_like(rng, 60_000, deg=deg)
+    base = synth.make_mid(n=1000)
+    cam = base.view.camera
+    w = synth.Workload(f"deg{deg}", [sc], [synth.View(0, cam, base.view.select, base.view.recolor)])
+    mask, _ = orc.select(sc, cam, base.view.select)
+    rec = base.view.recolor
+    out = gpu_run(w, tile=(32, 32), fused=(mask, rec.M, rec.b), keep_backward=True)
+    p = pull(out, sc.n)
+    M64, b64 = rec.M.astype(np.float64), rec.b.astype(np.float64)
+    pr = orc.project(sc, cam, (32, 32), mask=mask, M=M64, b=b64)
+    _check_integer_steps(w, orc, p, pr, sc.n)
+    ref = orc.render_image(pr)
+    err, nband = assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, f"degree {deg}")
+    assert mask.sum() > 0
+    # every SH coefficient's gradient, upstream gradient on two 32x32 windows
+    wins = [(384, 384, 32, 32), (160, 544, 32, 32)]
+    rw = orc.render_windows(pr, wins)
+    g = np.zeros((cam.height, cam.width, 3), np.float32)
+    rg = np.random.default_rng(91)
+    o = 0
+    for (x0, y0, ww, wh) in wins:
+        blk = rg.standard_normal((wh, ww, 3)).astype(np.float32)
+        blk[rw.slack[o:o + ww * wh].reshape(wh, ww) > 0] = 0.0
+        g[y0:y0 + wh, x0:x0 + ww] = blk
+        o += ww * wh
+    gr = orc.backward(pr, g.astype(np.float64), M=M64, windows=wins)
+    touched = np.nonzero(np.abs(gr.drgb).sum(axis=1) > 0)[0]
+    assert len(touched) > 50
+    ref_sh = orc.sh_grad(sc, cam, pr, gr, M=M64, idx=touched)
+    K = (deg + 1) ** 2
+    d = out["dscene"]
+    dsh = torch.zeros((3 * K, d.stride), device="cuda")
+    t1, t9 = torch.empty(sc.n, device="cuda"), torch.empty(9, device="cuda")
+    oo = R.opts_struct((32, 32), 1, (0, 0, 0), out["mask"], out["M"], out["b"], keep_backward=True)
+    R.recogs_render_backward_sh(d.c_struct(), R.camera_struct(cam), oo, out["ws"].ws, out["img"].data_ptr(),
+                                torch.from_numpy(g).cuda().data_ptr(), t1.data_ptr(), dsh.data_ptr(), t9.data_ptr())
+    torch.cuda.synchronize()
+    got = dsh[:, touched].cpu().numpy().astype(np.float64)
+    scale = np.abs(ref_sh).max()
+    assert scale > 0 and np.all(np.abs(got - ref_sh) <= 2e-5 * scale + 1e-4 * np.abs(ref_sh))
+    assert np.abs(ref_sh[3:]).max() > 0   # the higher bands carry gradient
+    print(f"degree {deg}: max|err| {err:.2e}, in-band {nband}, dSH rel err {np.abs(got - ref_sh).max() / scale:.2e}")
+
+
+def test_benchmarked_frame_sequence_1m_crops(R, orc):
+    """The benchmarked frame at its size: recogs_recolor of the selection out of place
+    (from the pristine SH into the render copy) then recogs_render of the recoloured
+    coefficients in graph mode, 32x32 tiles, 1 pixel per thread, 1M Gaussians at
+    1920x1080; pixels on the 64 seeded crops against the oracle of the recoloured
+    projection (eq. 6 in its colour form)."""
+    import torch
+    w = synth.make_precision()
+    v = w.view
+    sc = w.scene
+    d = R.DeviceScene(sc)
+    mask_t = torch.empty(sc.n, dtype=torch.uint8, device="cuda")
+    count = torch.empty(1, dtype=torch.int32, device="cuda")
+    R.recogs_select(d.c_struct(), R.camera_struct(v.camera), R.select_struct(v.select), mask_t.data_ptr(),
+                    count.data_ptr())
+    M = torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda()
+    b = torch.from_numpy(v.recolor.b.copy()).cuda()
+    render_sh = d.sh.clone()
+    ws = R.DeviceWorkspace(sc.n, v.camera.width, v.camera.height, (32, 32), key_capacity=16 * sc.n)
+    img = torch.empty((v.camera.height, v.camera.width, 3), device="cuda")
+    for _ in range(2):   # two frames: the second starts from the first's state
+        R.recogs_recolor(d.c_struct(), render_sh.data_ptr(), mask_t.data_ptr(), M.data_ptr(), b.data_ptr(), 0)
+        R.render(d, v.camera, ws, (32, 32), 1, image=img, sh=render_sh, graph_mode=True)
+    K, _ = ws.readback()
+    assert 0 < K <= ws.ws.key_capacity
+    torch.cuda.synchronize()
+    mask = mask_t.cpu().numpy()
+    ref_mask, flag = orc.select(sc, v.camera, v.select)
+    assert np.array_equal(mask[flag == 0], ref_mask[flag == 0])
+    pr = orc.project(sc, v.camera, (32, 32), mask=mask, M=v.recolor.M.astype(np.float64),
+                     b=v.recolor.b.astype(np.float64))
+    wins = crop_windows(w, w.extra["crops"])
+    ref = orc.render_windows(pr, wins)
+    got = np.concatenate([img[y:y + 32, x:x + 32].reshape(-1, 3).cpu().numpy().astype(np.float64)
+                          for (x, y, _, _) in wins])
+    err, nband = assert_pixels(got, ref.rgb, ref.slack, TOL_F32, "benchmarked frame")
+    # the unselected coefficients of the render copy are the pristine ones
+    keep = mask == 0
+    assert torch.equal(render_sh[:, torch.from_numpy(keep).cuda()], d.sh[:, torch.from_numpy(keep).cuda()])
+    print(f"benchmarked frame: K={K}, {int(mask.sum())} selected, crops max|err| {err:.2e}, in-band {nband}")
+
+
 def test_separate_recolor_then_render_equals_fused(R, orc):
     """recogs_recolor on coefficients then render == render with the fused recolour
     (within float32 rounding), tying eq. (6)'s coefficient form to its colour form."""
@@ -368,9 +461,14 @@ def test_capacity_error_reports_needed_keys(R):
     assert e.value.status == -2
     need = int(ws.ws.num_keys)
     assert need > 100
+    assert R.recogs_workspace_keys_needed(ws.ws) == need
     R.render(d, w.view.camera, ws, image=img, grow=True)
     torch.cuda.synchronize()
     assert int(ws.ws.num_keys) == need
+    assert R.recogs_workspace_keys_needed(ws.ws) == need
+    # a graph-mode render reads nothing back; the call reports what it needed
+    R.render(d, w.view.camera, ws, image=img, graph_mode=True)
+    assert R.recogs_workspace_keys_needed(ws.ws) == need
 
 
 def test_stride_larger_than_n(R, orc):
