@@ -9,8 +9,9 @@
  *
  * Conventions shared by every call
  *   - Pointers are DEVICE pointers unless marked (host). The caller owns every
- *     buffer. The library keeps no device state between calls and allocates no
- *     device memory; render state lives in a caller-provided workspace.
+ *     buffer. The library allocates no device memory and keeps no device state
+ *     between calls (one exception: the fixed array of recogs_unproject_noalloc);
+ *     render state lives in a caller-provided workspace.
  *   - Scene arrays are structure-of-arrays "planes": plane p of an array with
  *     stride s occupies elements [p*s, p*s + n). All planes of one scene share
  *     one stride >= n.
@@ -368,6 +369,20 @@ size_t recogs_unproject_workspace_bytes(int32_t width, int32_t height);
 recogs_status recogs_unproject(const recogs_camera *cam, const uint8_t *mask, const uint8_t *keep, const float *depth,
                                float *points, int64_t capacity, uint32_t *count, void *workspace,
                                size_t workspace_bytes, hipStream_t stream);
+
+/* recogs_unproject for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same arguments,
+ * results and errors, without the workspace. Its per-workgroup counts live in a fixed
+ * device array of the library (256 KB on each GPU it runs on, held until the process
+ * ends), which covers images of at most 67,108,864 pixels (e.g. 8192 x 8192); larger
+ * images are refused with INVALID before any launch. The call allocates nothing and every
+ * count it uses is written before it is read, so nothing carries over between calls; but
+ * all calls on one GPU share the array, so calls that overlap in time on one GPU (other
+ * streams or threads) race and must be serialised by the caller. HIP: the array's device
+ * address could not be obtained. */
+recogs_status recogs_unproject_noalloc(const recogs_camera *cam, const uint8_t *mask, const uint8_t *keep,
+                                       const float *depth, float *points, int64_t capacity, uint32_t *count,
+                                       hipStream_t stream);
 
 /* A point cloud drawn into a view as its selection mask (Sec. 3.2: the cloud is drawn
  * as screen-space squares of one size, depth-tested against the rough depth map;

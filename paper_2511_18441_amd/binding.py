@@ -30,7 +30,7 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
                 "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_render_backward_sh_adam",
-                "recogs_workspace_keys_needed", "recogs_last_error")
+                "recogs_workspace_keys_needed", "recogs_unproject_noalloc", "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -121,6 +121,7 @@ def lib():
         L.recogs_unproject_workspace_bytes.argtypes = [i32, i32]
         L.recogs_unproject_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_unproject.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
+        L.recogs_unproject_noalloc.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp]
         L.recogs_reproject_mask.argtypes = [P(Camera), vp, i64, i64, f32, vp, f32, vp, vp]
         L.recogs_tint.argtypes = [vp, vp, P(f32), vp, i64, vp]
         L.recogs_render_backward_sh_adam.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp,
@@ -246,6 +247,11 @@ def recogs_unproject_workspace_bytes(width, height) -> int:
 def recogs_unproject(cam: Camera, mask, keep, depth, points, capacity, count, workspace, workspace_bytes, stream=None):
     return _check("recogs_unproject", lib().recogs_unproject(ctypes.byref(cam), mask, keep, depth, points, int(capacity),
                                                              count, workspace, int(workspace_bytes), _stream(stream)))
+
+
+def recogs_unproject_noalloc(cam: Camera, mask, keep, depth, points, capacity, count, stream=None):
+    return _check("recogs_unproject_noalloc", lib().recogs_unproject_noalloc(ctypes.byref(cam), mask, keep, depth, points,
+                                                                             int(capacity), count, _stream(stream)))
 
 
 def recogs_reproject_mask(cam: Camera, points, n, stride, quad_px, depth, depth_eps, mask, stream=None):

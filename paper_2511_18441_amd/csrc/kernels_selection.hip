@@ -6,6 +6,9 @@
 //   - the tint c* = t c on the pixels a mask marks.
 // All three are streaming per-pixel / per-point work (HBM and launch bound): no LDS
 // tiling beyond the workgroup scan of the unprojection's compaction.
+#include <atomic>
+#include <mutex>
+
 #include "recogs_internal.hpp"
 
 namespace recogs {
@@ -163,6 +166,46 @@ void launch_unproject(const CamDev &cam, const uint8_t *mask, const uint8_t *kee
     hipLaunchKernelGGL(k_unp_scan, dim3(1), dim3(1024), 0, st, part, nblk, count);
     if (nblk)
         hipLaunchKernelGGL(k_unp_write, dim3(nblk), dim3(256), 0, st, mask, keep, depth, P, (int)cam.W, part, cam, pts, cap);
+}
+
+// ---------------------------------------------------------------------------
+// Unprojection without caller or library allocations: the per-workgroup counts live in
+// a fixed device array (one per GPU, for the life of the process) instead of a workspace.
+// ---------------------------------------------------------------------------
+constexpr int64_t kUnpScratchMaxPixels = (int64_t)1 << 26;   // 67,108,864 pixels, e.g. 8192 x 8192
+constexpr uint32_t kUnpScratchWords = (uint32_t)(kUnpScratchMaxPixels / kUnpBlock);   // 65,536 counts, 256 KB
+static __device__ __align__(256) uint32_t scratch[kUnpScratchWords];
+
+int64_t unproject_scratch_max_pixels() { return kUnpScratchMaxPixels; }
+
+// Device address of `scratch` on the current device, looked up once per device (the
+// host-side name of the array is not a device address). nullptr (with *err set) on failure.
+uint32_t *unproject_scratch_ptr(hipError_t *err) {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<uint32_t *> ptrs[kMaxDevices];
+    static std::mutex lock;
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    uint32_t *p = ptrs[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> g(lock);
+    p = ptrs[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        void *a = nullptr;
+        *err = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess || !a) {
+            if (*err == hipSuccess) *err = hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        p = (uint32_t *)a;
+        ptrs[dev].store(p, std::memory_order_release);
+    }
+    return p;
 }
 
 // exclusive scan of nblk counts in place, total to *count (the compaction step shared

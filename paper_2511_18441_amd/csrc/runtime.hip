@@ -46,6 +46,8 @@ void launch_loss_l1(const float *, const float *, int64_t, float, float *, float
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
 void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t);
 uint32_t unproject_blocks(int64_t);
+int64_t unproject_scratch_max_pixels();
+uint32_t *unproject_scratch_ptr(hipError_t *);
 void launch_unproject(const CamDev &, const uint8_t *, const uint8_t *, const float *, int64_t, uint32_t *, uint32_t *,
                       float *, int64_t, hipStream_t);
 void launch_reproject(const CamDev &, const float *, int64_t, int64_t, float, const float *, float, uint8_t *, hipStream_t);
@@ -767,6 +769,25 @@ recogs_status recogs_unproject(const recogs_camera *cam, const uint8_t *mask, co
     launch_unproject(make_cam(*cam, 16, 16), mask, keep, depth, (int64_t)cam->width * cam->height, (uint32_t *)workspace,
                      count, points, capacity, stream);
     return hip_check("unproject");
+}
+
+recogs_status recogs_unproject_noalloc(const recogs_camera *cam, const uint8_t *mask, const uint8_t *keep,
+                                       const float *depth, float *points, int64_t capacity, uint32_t *count,
+                                       hipStream_t stream) {
+    g_err[0] = 0;
+    recogs_status s;
+    if ((s = check_camera(cam)) != RECOGS_OK) return s;
+    if (capacity < 0 || capacity > 0xffffffffLL) return fail(RECOGS_ERR_INVALID, "capacity %lld not in 0..2^32-1", (long long)capacity);
+    if (!mask || !depth || !count || (capacity > 0 && !points)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    const int64_t P = (int64_t)cam->width * cam->height;
+    if (P > unproject_scratch_max_pixels())
+        return fail(RECOGS_ERR_INVALID, "image of %lld pixels exceeds the %lld this call's fixed scratch covers",
+                    (long long)P, (long long)unproject_scratch_max_pixels());
+    hipError_t e = hipSuccess;
+    uint32_t *part = unproject_scratch_ptr(&e);
+    if (!part) return fail(RECOGS_ERR_HIP, "device address of the unprojection scratch: %s", hipGetErrorString(e));
+    launch_unproject(make_cam(*cam, 16, 16), mask, keep, depth, P, part, count, points, capacity, stream);
+    return hip_check("unproject_noalloc");
 }
 
 recogs_status recogs_reproject_mask(const recogs_camera *cam, const float *points, int64_t n, int64_t stride,

@@ -143,6 +143,12 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 65.0, 0, 0.0, 8, 0) == -1     # quad_px > 64
     assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 2.0, 0, -1.0, 8, 0) == -1     # depth_eps < 0
     assert status(B.recogs_reproject_mask, cam, 8, 10, 10, 2.0, 0, 0.0, 0, 0) == -1      # mask NULL
+    big = B.Camera()
+    big.width, big.height, big.fx, big.fy, big.cx, big.cy = 8193, 8192, 50.0, 50.0, 32.0, 32.0
+    big.R[0] = big.R[4] = big.R[8] = 1.0
+    assert status(B.recogs_unproject_noalloc, big, 8, 0, 8, 8, 10, 8, 0) == -1          # beyond the fixed scratch
+    assert "scratch" in R.recogs_last_error()
+    assert status(B.recogs_unproject_noalloc, cam, 0, 0, 8, 8, 10, 8, 0) == -1          # mask NULL
     assert status(B.recogs_tint, 8, 8, (1.0, float("nan"), 1.0), 8, 10, 0) == -1
     assert status(B.recogs_tint, 0, 8, (1.0, 1.0, 1.0), 8, 10, 0) == -1
     # outlier removal
