@@ -38,6 +38,7 @@ METRIC = "recolor+render frames/s (1M Gaussians, 1080p) and HBM-roofline fractio
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz, packed FMA)
 BLEND_FLOPS_PER_EVAL = 23        # dx, dy, exponent (2 mul + 3 fma), test, exp2, clamp, T, weight, 3 fma
+SORT_MODE = 0                    # (tile, depth, index) order: 0 depth-first, 2 tile-first; --sort-mode
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
@@ -72,22 +73,29 @@ def recorded_traffic(kernel, tile, ppt):
         return None
 
 
-def algorithmic_model(st, storage_bytes, deg, keep_bwd=False):
-    """Bytes (and blend flops) each stage must move for this frame's counts
-    (default sort: depth sort of the V Gaussians with keys, then 32-bit tile keys)."""
+def algorithmic_model(st, storage_bytes, deg, keep_bwd=False, sort_mode=0):
+    """Bytes (and blend flops) each stage must move for this frame's counts. Sort mode 0:
+    depth sort of the V Gaussians with keys, emission in depth order, then 32-bit tile
+    keys; mode 2: emission in index order, 32-bit tile keys, then each tile's list
+    sorted by depth (list read, depth bits gathered, list written)."""
     N, V, K, S, P, Pd, T, Pix, E, Keff = (st[k] for k in ("N", "V", "K", "S", "passes", "dpasses", "tiles", "pix",
                                                            "evals", "keff"))
     nc = 3 * (deg + 1) ** 2
     b = {
         "recolor": N * 1 + S * nc * storage_bytes * 2,
         "preprocess": N * (12 + 24 + storage_bytes) + V * nc * storage_bytes + V * 48 + N * 16 + (V * 16 if keep_bwd else 0),
-        "scan": N * 8 + V * 12,
-        "depth_sort": V * 4 + Pd * V * 16,
-        "emit": V * 16 + K * 8,
         "key_sort": K * 4 + P * K * 16,
         "ranges": K * 4 + T * 8,
         "blend": Keff * 52 + T * 8 + Pix * (20 if keep_bwd else 12),
     }
+    if sort_mode == 2:
+        b["scan"] = N * 12 + V * 8 + V * 16        # counts, depth bits, offsets; rectangles read, compaction written
+        b["emit"] = V * 16 + K * 8
+        b["tile_sort"] = K * 12
+    else:
+        b["scan"] = N * 8 + V * 12
+        b["depth_sort"] = V * 4 + Pd * V * 16
+        b["emit"] = V * 16 + K * 8
     return b, {"blend": E * BLEND_FLOPS_PER_EVAL}
 
 
@@ -126,7 +134,7 @@ class Single:
     def frame(self, profile=0, graph_mode=True):
         self.recolor()
         self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
-                      profile=profile, graph_mode=graph_mode, chw=self.chw)
+                      profile=profile, graph_mode=graph_mode, chw=self.chw, sort_mode=SORT_MODE)
 
     def timed(self, steps, profile, graph_mode=True):
         """Wall-clock ms per frame over `steps` frames, bracketed by device syncs."""
@@ -159,7 +167,7 @@ class Single:
             self.frame()
         ws = self.ws.ws
         self.R.recogs_workspace_profile_flush(ws)
-        for k in range(8):
+        for k in range(len(ws.stage_ms_sum)):
             ws.stage_ms_sum[k] = 0.0
         ws.profiled_frames = 0
         ms = self.timed(steps, 2)
@@ -170,7 +178,7 @@ class Single:
         ms_plain = self.timed(steps, 0)
         ms_eager = self.timed(steps, 0, graph_mode=False)
         nprof = max(5, min(20, steps))
-        acc = np.zeros(8)
+        acc = np.zeros(len(ws.stage_ms))
         for _ in range(nprof):
             self.frame(1, graph_mode=False)
             acc += np.array(ws.stage_ms[:])
@@ -188,7 +196,8 @@ class Single:
         pixels; one more render at 16x16 tiles that also writes the per-pixel state
         gives it. `keff` is the per-tile maximum of that count, summed over 16x16 tiles."""
         import torch
-        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh)
+        self.R.render(self.d, self.cam, self.ws, self.tile, self.ppt, image=self.image, sh=self.render_sh,
+                      sort_mode=SORT_MODE)
         ws = self.ws
         K = int(ws.ws.num_keys)
         cnt = ws.counts(self.n)
@@ -198,7 +207,8 @@ class Single:
         passes, dpasses = int(ws.ws.sort_passes), int(ws.ws.depth_passes)
         ref = self.R.DeviceWorkspace(self.n, self.cam.width, self.cam.height, (16, 16), key_capacity=16 * self.n,
                                      device=self.image.device)
-        self.R.render(self.d, self.cam, ref, (16, 16), 1, image=self.image, sh=self.render_sh, keep_backward=True)
+        self.R.render(self.d, self.cam, ref, (16, 16), 1, image=self.image, sh=self.render_sh, keep_backward=True,
+                      sort_mode=SORT_MODE)
         nproc = ref.nproc().to(torch.int64)
         E = int(nproc.sum().item())
         Hp, Wp = ref.ws.tiles_y * 16, ref.ws.tiles_x * 16
@@ -214,9 +224,9 @@ def stage_table(stages, bytes_, flops, st):
     launches = {"key_sort": 3 * st["passes"], "depth_sort": 3 * st["dpasses"]}
     out = {}
     for k, t in stages.items():
-        if k == "readback":
+        if k == "readback" or k not in bytes_:   # (the stages this sort mode does not run)
             continue
-        nl = launches.get(k, 1)
+        nl = max(1, launches.get(k, 1))
         ent = {"ms_per_frame": round(t, 4), "launches": nl, "avg_launch_ms": round(t / nl, 4)}
         if k in bytes_ and t > 0:
             ent["alg_bytes"] = int(bytes_[k])
@@ -235,7 +245,7 @@ def form_single(R, storage, tile, ppt, steps, warmup, dev):
     m = s.measure(steps, warmup)
     st = s.counts()
     sb = {"f32": 4, "f16": 2, "bf16": 2}[storage]
-    bytes_, _ = algorithmic_model(st, sb, w.scene.sh_degree)
+    bytes_, _ = algorithmic_model(st, sb, w.scene.sh_degree, sort_mode=SORT_MODE)
     fps = 1000.0 / m["ms"]
     tot = sum(bytes_.values())
     res = {"storage": storage, "frames_per_s": round(fps, 2), "ms_per_frame": round(m["ms"], 4),
@@ -296,7 +306,7 @@ def form_batch(R, steps, warmup, dev):
     def singles():
         for k, (si, cam, mask, M, bb) in enumerate(views):
             R.render(dscenes[si], cam, wss[(si, cam.width, cam.height)], tile, ppt, mask=mask, M=M, b=bb,
-                     image=imgs[k])
+                     image=imgs[k], sort_mode=SORT_MODE)
     singles()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -342,7 +352,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     ws = [R.DeviceWorkspace(n, W, H, tile, device=dev) for _ in w.views]
     targets = []
     for k, v in enumerate(w.views):
-        t = R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=Mt, b=b).clone()
+        t = R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=Mt, b=b, sort_mode=SORT_MODE).clone()
         t += torch.from_numpy(synth.random_image(w.extra["noise_seed"] + k, (H, W, 3), w.extra["noise_sd"])).to(dev)
         targets.append(t)
     imgs = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in w.views]
@@ -357,7 +367,8 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
 
     def step():
         for k, v in enumerate(w.views):
-            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k],
+                     sort_mode=SORT_MODE)
             R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
                              loss.data_ptr() + 4 * k)
             # the loss sums the views: the first view writes the gradients, the others add to them
@@ -377,7 +388,8 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     t0 = time.perf_counter()
     for _ in range(reps):
         for k, v in enumerate(w.views):
-            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k])
+            R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k],
+                     sort_mode=SORT_MODE)
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / reps
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
@@ -410,7 +422,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     ws = R.DeviceWorkspace(n, W, H, tile, device=dev)
     targets = []
     for k, v in enumerate(w.views):
-        t = R.render(d, v.camera, ws, tile, ppt, mask=mask, M=Mt, b=b).clone()
+        t = R.render(d, v.camera, ws, tile, ppt, mask=mask, M=Mt, b=b, sort_mode=SORT_MODE).clone()
         t += torch.from_numpy(synth.random_image(w.extra["noise_seed"] + k, (H, W, 3), w.extra["noise_sd"])).to(dev)
         targets.append(t)
     sh = d.sh.clone()
@@ -434,7 +446,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     def step():
         k = state["step"] % len(w.views)
         state["step"] += 1
-        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh)
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE)
         R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
                          loss.data_ptr() + 4 * k)
         R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
@@ -448,7 +460,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         # not go through memory)
         k = state["step"] % len(w.views)
         state["step"] += 1
-        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh)
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE)
         R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
                          loss.data_ptr() + 4 * k)
         R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
@@ -510,10 +522,11 @@ def form_selection(R, steps, warmup, dev, tile=(32, 32), ppt=1):
     ws = R.DeviceWorkspace(d.n, W, H, tile, device=dev)
     img = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
     depth = torch.empty((H, W), dtype=torch.float32, device=dev)
-    R.render(d, cam, ws, tile, ppt, image=img)     # grows the workspace once if needed
+    R.render(d, cam, ws, tile, ppt, image=img, sort_mode=SORT_MODE)     # grows the workspace once if needed
     reps = max(10, steps // 4)
-    ms_plain = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img), reps)
-    ms_depth = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img, depth=depth, depth_tau=0.5), reps)
+    ms_plain = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img, sort_mode=SORT_MODE), reps)
+    ms_depth = _event_ms(lambda: R.render(d, cam, ws, tile, ppt, image=img, depth=depth, depth_tau=0.5,
+                                          sort_mode=SORT_MODE), reps)
     mask = torch.from_numpy(synth.brush_mask(W, H, 960.0, 540.0, 378.0)).to(dev)
     keep = torch.from_numpy(synth.sample_keep(41, mask.cpu().numpy())).to(dev)
     c = R.camera_struct(cam)
@@ -546,7 +559,7 @@ def form_selection(R, steps, warmup, dev, tile=(32, 32), ppt=1):
     depth2 = torch.empty((H, W), dtype=torch.float32, device=dev)
     img2 = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
     ws2 = R.DeviceWorkspace(d.n, W, H, tile, device=dev)
-    R.render(d, cam2, ws2, tile, ppt, image=img2, depth=depth2, depth_tau=0.5)
+    R.render(d, cam2, ws2, tile, ppt, image=img2, depth=depth2, depth_tau=0.5, sort_mode=SORT_MODE)
     vmask = torch.empty((H, W), dtype=torch.uint8, device=dev)
     tinted = torch.empty_like(img2)
     t = [1.0, 0.6, 0.5]
@@ -585,13 +598,13 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     W, H = v0.camera.width, v0.camera.height
     ws = R.DeviceWorkspace(n, W, H, tile, device=dev)
     depth = torch.empty((H, W), dtype=torch.float32, device=dev)
-    R.render(d, v0.camera, ws, tile, ppt, depth=depth, depth_tau=0.5)
+    R.render(d, v0.camera, ws, tile, ppt, depth=depth, depth_tau=0.5, sort_mode=SORT_MODE)
     sel = synth.brush_mask(W, H, W / 2, H / 2, 0.15 * H)
     keep = synth.sample_keep(w.extra["keep_seed"], sel)
     cloud, n_sel = R.unproject(v0.camera, torch.from_numpy(sel).to(dev), torch.from_numpy(keep).to(dev), depth)
     cloud, _, _ = R.remove_outliers(cloud.contiguous(), 16, 0.007)
     cloud = cloud.contiguous()
-    originals = [R.render(d, v.camera, ws, tile, ppt).clone() for v in w.views]
+    originals = [R.render(d, v.camera, ws, tile, ppt, sort_mode=SORT_MODE).clone() for v in w.views]
     t = [float(x) for x in w.extra["tint"]]
     sh = d.sh.clone()
     m, v = torch.zeros_like(sh), torch.zeros_like(sh)
@@ -617,7 +630,8 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     def step():
         k = state["step"] % len(w.views)
         state["step"] += 1
-        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, depth=depth, depth_tau=0.5)
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, depth=depth, depth_tau=0.5,
+                 sort_mode=SORT_MODE)
         R.recogs_reproject_mask(cams[k], cloud.data_ptr(), n_pts, n_pts, 2.0, depth.data_ptr(), 0.01, vmask.data_ptr())
         R.recogs_tint(originals[k].data_ptr(), vmask.data_ptr(), t, target.data_ptr(), H * W)
         R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
@@ -682,6 +696,7 @@ def cpu_baseline(w):
 
 
 def main():
+    global SORT_MODE
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -689,6 +704,8 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--tile", type=int, nargs=2, default=[32, 32])
     ap.add_argument("--ppt", type=int, default=1)
+    ap.add_argument("--sort-mode", type=int, choices=[0, 2], default=SORT_MODE,
+                    help="key order of every render: 0 depth-first, 2 tile-first (both graph-capturable)")
     ap.add_argument("--diff-tile", type=int, nargs=2, default=None,
                     help="tile shape of the differentiation form when run alone (--only-form diff)")
     ap.add_argument("--diff-ppt", type=int, default=DIFF_PPT)
@@ -705,6 +722,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
     args = ap.parse_args()
+    SORT_MODE = args.sort_mode
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU form (sharding across GPUs is designed, not built)",
               file=sys.stderr)
@@ -740,7 +758,7 @@ def main():
     fps = 1000.0 / ms
     st = s.counts()
     sb = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
-    bytes_, flops = algorithmic_model(st, sb, w.scene.sh_degree)
+    bytes_, flops = algorithmic_model(st, sb, w.scene.sh_degree, sort_mode=SORT_MODE)
     per_kernel, launches = stage_table(m["stages"], bytes_, flops, st)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_frame"])
     nl = launches.get(dom, 1)
@@ -772,7 +790,7 @@ def main():
         "config": {"workload": f"1M Gaussians SH deg 3, 1920x1080, {tw}x{th} tiles, {args.storage} storage; "
                                "recolor(selected) + render", "gaussians": s.n, "width": s.cam.width,
                    "height": s.cam.height, "sh_degree": 3, "storage": args.storage, "tile": f"{tw}x{th}",
-                   "px_per_thread": args.ppt, "layout": args.layout},
+                   "px_per_thread": args.ppt, "layout": args.layout, "sort_mode": SORT_MODE},
         "gaussians_per_s": round(fps * s.n, 1),
         "frame_hbm_roofline": {"alg_bytes_per_frame": int(tot_bytes),
                                "GBps": round(tot_bytes * fps / 1e9, 1),

@@ -107,21 +107,23 @@ typedef struct {
      * events are recorded just before and after the blend launch only (an event between
      * two kernels delays the second one's dispatch by microseconds), and the duration
      * of the workspace's previous mode-2 call (complete by then) is added to
-     * ws->stage_ms_sum[7] with ws->profiled_frames incremented, at this call's
+     * ws->stage_ms_sum[8] with ws->profiled_frames incremented, at this call's
      * key-count read-back; recogs_workspace_profile_flush adds the last one. Mode 2
      * creates its event objects on first use; recogs_workspace_release destroys them. */
     int32_t profile_stages;
-    /* How the (tile, depth, index) order of the tile lists is produced; both give the
+    /* How the (tile, depth, index) order of the tile lists is produced; all give the
      * same order. 0 (default): sort the Gaussians with keys by depth (32-bit keys),
      * emit their tile keys in that order, then stable-sort the tile ids (the LSD
      * depth digits sorted before the keys are duplicated). 1: emit 64-bit keys
-     * (tile << 32) | depth bits in index order and radix-sort them. */
+     * (tile << 32) | depth bits in index order and radix-sort them. 2: emit the tile
+     * ids in index order, stable-sort them, then sort each tile's list by depth with
+     * one workgroup (lists of up to 8,192 keys in LDS, longer ones through memory). */
     int32_t sort_mode;
     /* 1: no host synchronisation (the render may be captured in a HIP graph). The
      * key count, capacity decision and overflow flag stay on the device: a view with
      * more keys than ws->key_capacity draws only the background, and
      * recogs_workspace_readback reports num_keys / num_visible afterwards
-     * (num_keys > key_capacity: overflowed). Needs sort_mode 0; profile_stages 0 or 2.
+     * (num_keys > key_capacity: overflowed). Needs sort_mode 0 or 2; profile_stages 0 or 2.
      * 0: the render reads the key count back once (eager capacity check). */
     int32_t graph_mode;
     /* Output layout (Sec. 4.2 compares the two). 0 (default): image float [H][W][3]
@@ -185,11 +187,12 @@ typedef struct {
     uint32_t depth_min_bits;     /* smallest float32 depth bit pattern among keys */
     int32_t last_n;
     /* with profile_stages: milliseconds of [0] preprocess, [1] scan, [2] key-count read-back,
-     * [3] depth sort, [4] key emission, [5] key sort, [6] tile ranges, [7] blend */
-    float stage_ms[8];
-    /* with profile_stages = 2: [7] sums the blend's milliseconds over profiled_frames
+     * [3] depth sort (sort_mode 0), [4] key emission, [5] key sort, [6] tile ranges,
+     * [7] per-tile depth sort (sort_mode 2), [8] blend */
+    float stage_ms[9];
+    /* with profile_stages = 2: [8] sums the blend's milliseconds over profiled_frames
      * calls (the other entries stay 0); zeroed by recogs_workspace_init */
-    double stage_ms_sum[8];
+    double stage_ms_sum[9];
     int64_t profiled_frames;
     void *profile_state;         /* host-side event objects of mode 2 (library-owned) */
     /* incremented by every recogs_render call on this workspace that passes its argument

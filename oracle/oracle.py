@@ -22,7 +22,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "recogs_oracle.c")
-_LIB = os.path.join(_HERE, "liborc.so")
+# RECOGS_ORACLE_LIB: another build of the same source (the sanitizer run of the host code)
+_LIB = os.environ.get("RECOGS_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
 
 # column layout of the per-Gaussian records (mirrors the enums in recogs_oracle.c)
 PCOLS = ["z", "z32", "u", "v", "sa", "sb", "sc", "ca", "cb", "cc", "r", "g", "b",

@@ -16,7 +16,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librecogs.so")
+# RECOGS_LIB: another build of the same sources (the sanitizer run of the host code)
+LIB_PATH = os.environ.get("RECOGS_LIB") or os.path.join(_HERE, "librecogs.so")
 
 RECOGS_F32, RECOGS_F16, RECOGS_BF16 = 0, 1, 2
 STATUS = {0: "OK", -1: "INVALID", -2: "CAPACITY", -3: "UNSUPPORTED", -4: "HIP"}
@@ -77,11 +78,11 @@ class Workspace(ctypes.Structure):
                [("num_keys", ctypes.c_int64), ("num_visible", ctypes.c_int64), ("sort_mode", ctypes.c_int32),
                 ("key_bytes", ctypes.c_int32), ("sorted_in_alt", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("depth_passes", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("depth_bits", ctypes.c_int32),
-                ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 8),
-                ("stage_ms_sum", ctypes.c_double * 8), ("profiled_frames", ctypes.c_int64),
+                ("depth_min_bits", ctypes.c_uint32), ("last_n", ctypes.c_int32), ("stage_ms", ctypes.c_float * 9),
+                ("stage_ms_sum", ctypes.c_double * 9), ("profiled_frames", ctypes.c_int64),
                 ("profile_state", ctypes.c_void_p), ("generation", ctypes.c_int64)]
 
-STAGES = ("preprocess", "scan", "readback", "depth_sort", "emit", "key_sort", "ranges", "blend")
+STAGES = ("preprocess", "scan", "readback", "depth_sort", "emit", "key_sort", "ranges", "tile_sort", "blend")
 
 
 _lib = None
@@ -489,7 +490,7 @@ class DeviceWorkspace:
         last one) and their count."""
         recogs_workspace_profile_flush(self.ws)
         n = int(self.ws.profiled_frames)
-        return (self.ws.stage_ms_sum[7] / n if n else 0.0), n
+        return (self.ws.stage_ms_sum[8] / n if n else 0.0), n
 
     def grow(self, needed):
         self._alloc(int(needed * 1.25) + 1024)

@@ -127,11 +127,19 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, ui
 // Down-sweep over one chunk of 4,096 counts. Loads and stores are coalesced through
 // LDS: counts and depth bits come in striped, each thread scans 16 consecutive ones,
 // and the offsets and the compacted (depth bits, index) pairs go out striped.
+// EMIT (tile-first order): instead of the depth bits, the compaction carries what the
+// key emission of index-ordered Gaussians needs: each one's tile rectangle (srect) and
+// key offset (eoff), and efirst[b] = the compacted Gaussian owning key b * kEmitKeys for
+// the blocks b < nblk of the key capacity.
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }   // LDS padding: no 16-way bank conflicts
+constexpr uint32_t kEmitKeys = 2048;   // keys per workgroup of k_emit_down (256 threads x 8)
+template <bool EMIT>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                                    uint32_t *__restrict__ off, int64_t n, const uint64_t *__restrict__ pk,
                                                    const uint32_t *__restrict__ pv, uint32_t *__restrict__ dkeys,
-                                                   uint32_t *__restrict__ dvals) {
+                                                   uint32_t *__restrict__ dvals, const uint2 *__restrict__ rect,
+                                                   uint2 *__restrict__ srect, uint32_t *__restrict__ eoff,
+                                                   uint32_t *__restrict__ efirst, uint32_t nblk) {
     __shared__ uint64_t s_wk[4];
     __shared__ uint32_t s_wv[4];
     __shared__ uint32_t s_a[kScanChunk + kScanChunk / 32];
@@ -157,22 +165,47 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
     uint32_t vtot;
     uint64_t run = pk[blockIdx.x] + block_excl_scan<uint64_t, 4>(tsum, s_wk, ktot);
     uint32_t vloc = block_excl_scan<uint32_t, 4>(vsum, s_wv, vtot);   // (the scans end with a barrier)
+    const uint32_t vbase = pv[blockIdx.x];
+    if constexpr (EMIT) {
+        // compacted key offsets; the owners of the key blocks starting in this chunk
+        uint64_t r = run;
+        uint32_t q = vloc;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int i = k * 256 + t;
-        s_a[scan_pad(i)] = (c0 + i < n) ? zbits[c0 + i] : 0u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (v[k]) {
-            const int i = t * kScanItems + k;
-            s_dk[vloc] = s_a[scan_pad(i)];
-            s_dv[vloc] = (uint32_t)(c0 + i);
-            ++vloc;
+        for (int k = 0; k < kScanItems; ++k) {
+            if (v[k]) {
+                s_dk[q] = (uint32_t)r;
+                for (uint64_t b = (r + kEmitKeys - 1) / kEmitKeys; b < nblk && b * kEmitKeys < r + v[k]; ++b)
+                    efirst[b] = vbase + q;
+                s_dv[q] = (uint32_t)(c0 + t * kScanItems + k);
+                ++q;
+            }
+            r += v[k];
         }
+        __syncthreads();
+        for (uint32_t j = t; j < vtot; j += 256) {
+            eoff[vbase + j] = s_dk[j];
+            dvals[vbase + j] = s_dv[j];
+            srect[vbase + j] = rect[s_dv[j]];   // within the chunk's 4,096 Gaussians: few lines
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int i = k * 256 + t;
+            s_a[scan_pad(i)] = (c0 + i < n) ? zbits[c0 + i] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (v[k]) {
+                const int i = t * kScanItems + k;
+                s_dk[vloc] = s_a[scan_pad(i)];
+                s_dv[vloc] = (uint32_t)(c0 + i);
+                ++vloc;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         s_a[scan_pad(t * kScanItems + k)] = (uint32_t)run;
@@ -184,10 +217,11 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
         const int i = k * 256 + t;
         if (c0 + i < n) off[c0 + i] = s_a[scan_pad(i)];
     }
-    const uint32_t vbase = pv[blockIdx.x];
-    for (uint32_t j = t; j < vtot; j += 256) {
-        dkeys[vbase + j] = s_dk[j];
-        dvals[vbase + j] = s_dv[j];
+    if constexpr (!EMIT) {
+        for (uint32_t j = t; j < vtot; j += 256) {
+            dkeys[vbase + j] = s_dk[j];
+            dvals[vbase + j] = s_dv[j];
+        }
     }
 }
 
@@ -295,8 +329,6 @@ __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict_
     __syncthreads();
     if (threadIdx.x == 0) esum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
-
-constexpr uint32_t kEmitKeys = 2048;   // keys per workgroup of k_emit_down (256 threads x 8)
 
 __global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ srect, uint32_t V,
                                                       const uint32_t *__restrict__ epre, uint32_t *__restrict__ eoff,
@@ -549,14 +581,36 @@ void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, c
     else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
 }
 
+// emit non-null (tile-first order): the compaction carries rect -> emit->srect, key offsets
+// -> emit->eoff and the key blocks' owners -> emit->efirst (blocks of the key capacity);
+// otherwise the depth bits -> dkeys.
 void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *pk, uint32_t *pv,
                  uint32_t *pzmn, uint32_t *pzmx, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, int64_t key_capacity,
-                 hipStream_t st) {
+                 hipStream_t st, const ScanEmit *emit) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr);
-    hipLaunchKernelGGL(k_scan_down, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals);
+    if (emit) {
+        const uint32_t nblk = (uint32_t)(((uint64_t)key_capacity + kEmitKeys - 1) / kEmitKeys);
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
+                           emit->rect, emit->srect, emit->eoff, emit->efirst, nblk);
+    } else {
+        hipLaunchKernelGGL(k_scan_down<false>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
+                           nullptr, nullptr, nullptr, nullptr, 0u);
+    }
+}
+
+// Key emission of the Gaussians the scan compacted in index order (tile-first order):
+// one workgroup per block of kEmitKeys keys, from the compaction's rectangles, offsets
+// and block owners (k_emit_down). V and K are counts or, with dynV / dynK, bounds.
+void launch_emit_compacted(const uint32_t *order, uint32_t V, const uint2 *srect, const uint32_t *eoff,
+                           const uint32_t *efirst, uint32_t K, int tiles_x, uint32_t *tkeys, uint32_t *tvals, hipStream_t st,
+                           const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr, const uint4 *vtab, int nviews) {
+    if (V == 0 || K == 0) return;
+    const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
+    hipLaunchKernelGGL(k_emit_down, dim3(nblk), dim3(256), 0, st, order, V, K, srect, eoff, efirst, tiles_x, tkeys, tvals,
+                       dynV, dynK, hdr ? hdr + H_OVERFLOW : nullptr, vtab, nviews);
 }
 
 // V is the count or, with dynV, its upper bound; hdr (optional) supplies the overflow flag.

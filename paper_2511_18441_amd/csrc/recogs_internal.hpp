@@ -206,6 +206,14 @@ struct ViewDev {
     uint32_t pair_base, blk_base, tile_base, ntiles;
 };
 
+// Outputs of the count scan's compaction for the tile-first key order (see launch_scan).
+struct ScanEmit {
+    const uint2 *rect;     // tile rectangles, index order
+    uint2 *srect;          // compacted rectangles
+    uint32_t *eoff;        // compacted key offsets
+    uint32_t *efirst;      // owner of the first key of each emission block
+};
+
 constexpr int kScanItems = 16;                       // counts per thread of the scan
 constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
 constexpr int kMaxPasses = 8;

@@ -19,9 +19,14 @@ void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
                        uint32_t *, uint2 *, uint32_t *, hipStream_t);
 void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
-                 uint32_t *, uint32_t *, uint32_t *, int64_t, hipStream_t);
+                 uint32_t *, uint32_t *, uint32_t *, int64_t, hipStream_t, const ScanEmit *);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
+void launch_emit_compacted(const uint32_t *, uint32_t, const uint2 *, const uint32_t *, const uint32_t *, uint32_t, int,
+                           uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *, const uint32_t *,
+                           const uint4 *, int);
+void launch_tile_depth_sort(const uint2 *, uint32_t, uint32_t *, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
+                            hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
                         uint32_t, uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *,
                         const uint32_t *, const uint4 *, int);
@@ -149,8 +154,13 @@ template <typename T> T *at(const recogs_workspace *ws, size_t off) { return (T 
 // brackets the blend with one of the workspace's two event pairs, does not wait, and
 // harvests the other pair (recorded by the previous call, complete once this call's
 // read-back returned).
+// Stage events: 0 start, then the end of [0] preprocess, [1] scan, [2] key-count read-back,
+// [3] depth sort, [4] key emission, [5] key sort, [6] tile ranges, [7] per-tile depth sort,
+// [8] blend (kStages stages, kStages + 1 events; the blend is the last).
+constexpr int kStages = 9;
+constexpr int kBlendStage = kStages - 1;
 struct ProfileSet {
-    hipEvent_t ev[9];
+    hipEvent_t ev[kStages + 1];
     bool pending;
 };
 struct ProfileState {
@@ -161,14 +171,15 @@ struct ProfileState {
 void harvest(recogs_workspace *ws, ProfileSet &p) {
     if (!p.pending) return;
     p.pending = false;
-    if (hipEventSynchronize(p.ev[8]) != hipSuccess) return;
+    if (hipEventSynchronize(p.ev[kBlendStage + 1]) != hipSuccess) return;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.ev[7], p.ev[8]) == hipSuccess) ws->stage_ms_sum[7] += ms;
+    if (hipEventElapsedTime(&ms, p.ev[kBlendStage], p.ev[kBlendStage + 1]) == hipSuccess)
+        ws->stage_ms_sum[kBlendStage] += ms;
     ws->profiled_frames += 1;
 }
 
 struct StageTimer {
-    hipEvent_t own[9] = {};
+    hipEvent_t own[kStages + 1] = {};
     bool own_ready = false;
     hipEvent_t *ev = nullptr;
     ProfileSet *set = nullptr;
@@ -202,10 +213,10 @@ struct StageTimer {
         ev = set->ev;
         return RECOGS_OK;
     }
-    // mode 2 records only the blend's bracket (7, 8): each event between two kernels
-    // delays the second one's dispatch by a few microseconds
+    // mode 2 records only the blend's bracket: each event between two kernels delays the
+    // second one's dispatch by a few microseconds
     recogs_status mark(int k) {
-        if (mode == 0 || (mode == 2 && k < 7)) return RECOGS_OK;
+        if (mode == 0 || (mode == 2 && k < kBlendStage)) return RECOGS_OK;
         if (hipEventRecord(ev[k], st) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventRecord failed");
         return RECOGS_OK;
     }
@@ -224,7 +235,7 @@ struct StageTimer {
         }
         if (mode != 1) return RECOGS_OK;
         if (hipEventSynchronize(ev[last]) != hipSuccess) return fail(RECOGS_ERR_HIP, "hipEventSynchronize failed");
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < kStages; ++k) {
             float ms = 0.f;
             if (k < last && hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) ms = 0.f;
             ws->stage_ms[k] = ms;
@@ -294,9 +305,9 @@ recogs_status check_opts(const recogs_render_opts *o) {
     if (!o) return fail(RECOGS_ERR_INVALID, "render opts is NULL");
     if (!tile_supported(o->tile_w, o->tile_h))
         return fail(RECOGS_ERR_UNSUPPORTED, "tile %dx%d not one of 16x16, 8x8, 32x8, 32x16, 32x32", o->tile_w, o->tile_h);
-    if (o->sort_mode != 0 && o->sort_mode != 1) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0 or 1", o->sort_mode);
+    if (o->sort_mode < 0 || o->sort_mode > 2) return fail(RECOGS_ERR_INVALID, "sort_mode %d not 0, 1 or 2", o->sort_mode);
     if (o->graph_mode != 0 && o->graph_mode != 1) return fail(RECOGS_ERR_INVALID, "graph_mode %d not 0 or 1", o->graph_mode);
-    if (o->graph_mode && o->sort_mode != 0) return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode needs sort_mode 0");
+    if (o->graph_mode && o->sort_mode == 1) return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode needs sort_mode 0 or 2");
     if (o->graph_mode && o->profile_stages == 1)
         return fail(RECOGS_ERR_UNSUPPORTED, "graph_mode renders do not wait: use profile_stages 0 or 2");
     if (o->profile_stages < 0 || o->profile_stages > 2)
@@ -339,6 +350,7 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     const int64_t n = scene->n;
     const int ntiles = cd.tiles_x * cd.tiles_y;
     const uint32_t cap = (uint32_t)ws->key_capacity;
+    const int mode = opts->sort_mode;
     uint32_t *hdr = at<uint32_t>(ws, ws->off_header);
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
     uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
@@ -351,30 +363,40 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     ws->num_keys = -1;   // known after recogs_workspace_readback
     ws->num_visible = -1;
     ws->last_n = (int32_t)n;
-    ws->sort_mode = 0;
+    ws->sort_mode = mode;
     ws->depth_bits = 32;
     ws->depth_min_bits = 0;
     ws->key_bits = tbits + 32;
     ws->sort_passes = sort_passes(tbits);
-    ws->depth_passes = sort_passes(32);
+    ws->depth_passes = mode == 0 ? sort_passes(32) : 0;
     ws->key_bytes = 4;
     int alt = 0;
     if (n > 0 && cap > 0) {
-        const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, (uint32_t)n, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist, scount,
-                                            stream);
-        if ((s = tm.mark(4)) != RECOGS_OK) return s;
-        launch_emit_sorted(dalt ? dv1 : dv0, (uint32_t)n, at<uint2>(ws, ws->off_rect), (uint2 *)dk0, cd.tiles_x,
-                           at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1, at<uint32_t>(ws, ws->off_efirst), cap, t0, v0,
-                           stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+        if (mode == 0) {
+            const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, (uint32_t)n, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist,
+                                                scount, stream);
+            if ((s = tm.mark(4)) != RECOGS_OK) return s;
+            launch_emit_sorted(dalt ? dv1 : dv0, (uint32_t)n, at<uint2>(ws, ws->off_rect), (uint2 *)dk0, cd.tiles_x,
+                               at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1, at<uint32_t>(ws, ws->off_efirst), cap, t0,
+                               v0, stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+        } else {
+            if ((s = tm.mark(4)) != RECOGS_OK) return s;
+            launch_emit_compacted(dv0, (uint32_t)n, (const uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst), cap,
+                                  cd.tiles_x, t0, v0, stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+        }
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32_dyn(t0, v0, t1, v1, cap, hdr + H_KEFF, nullptr, tbits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, cap, ranges, stream, hdr + H_KEFF);
+        if ((s = tm.mark(7)) != RECOGS_OK) return s;
+        if (mode == 2)
+            launch_tile_depth_sort(ranges, (uint32_t)ntiles, alt ? v1 : v0, at<uint32_t>(ws, ws->off_zbits), hdr,
+                                   alt ? t0 : t1, alt ? v0 : v1, stream);
     } else {
-        for (int k = 4; k <= 6; ++k)
+        for (int k = 4; k <= 7; ++k)
             if ((s = tm.mark(k)) != RECOGS_OK) return s;
     }
-    if ((s = tm.mark(7)) != RECOGS_OK) return s;
+    if ((s = tm.mark(kBlendStage)) != RECOGS_OK) return s;
     ws->sorted_in_alt = alt;
     if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0,
@@ -383,9 +405,9 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
                       opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr,
                       at<uint32_t>(ws, ws->off_zbits), opts->depth_tau, opts->depth_map, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
-    if ((s = tm.mark(8)) != RECOGS_OK) return s;
+    if ((s = tm.mark(kBlendStage + 1)) != RECOGS_OK) return s;
     if ((s = hip_check("blend")) != RECOGS_OK) return s;
-    return tm.finish(ws, 8);
+    return tm.finish(ws, kBlendStage + 1);
 }
 
 extern "C" {
@@ -524,7 +546,7 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     uint2 *ranges = at<uint2>(ws, ws->off_ranges);
 
     StageTimer &tm = g_timer;
-    for (int k = 0; k < 8; ++k) ws->stage_ms[k] = 0.f;
+    for (int k = 0; k < kStages; ++k) ws->stage_ms[k] = 0.f;
     if ((s = tm.start(opts->profile_stages, ws, stream)) != RECOGS_OK) return s;
     const int mode = opts->sort_mode;
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
@@ -542,7 +564,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         const size_t sc_n = ws->scan_chunks;
         uint64_t *pk = at<uint64_t>(ws, ws->off_scan);
         uint32_t *pv = (uint32_t *)(pk + sc_n);
-        launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream);
+        // tile-first order: the compaction carries rectangles (over both depth-key buffers,
+        // adjacent), key offsets (dvals1) and the emission blocks' owners
+        const ScanEmit em{rect, (uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst)};
+        launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream,
+                    mode == 2 ? &em : nullptr);
     }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
@@ -565,13 +591,13 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     const uint32_t zmin = ~h[H_ZMIN], zmax = h[H_ZMAX];
     const int dbits = K ? bits_for((uint64_t)(zmax - zmin)) : 0;
     const int tbits = bits_for((uint64_t)(ntiles - 1));
-    const int key_bits = mode == 0 ? tbits : tbits + dbits;
+    const int key_bits = mode == 1 ? tbits + dbits : tbits;
     ws->depth_bits = dbits;
     ws->depth_min_bits = zmin;
     ws->key_bits = tbits + dbits;
     ws->sort_passes = K ? sort_passes(key_bits) : 0;
     ws->depth_passes = (mode == 0 && V) ? sort_passes(dbits) : 0;
-    ws->key_bytes = mode == 0 ? 4 : 8;
+    ws->key_bytes = mode == 1 ? 8 : 4;
 
     // zero the histograms (adjacent) and the tile ranges
     uint32_t *hist = at<uint32_t>(ws, ws->off_hist), *dhist = at<uint32_t>(ws, ws->off_dhist);
@@ -597,6 +623,20 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream, nullptr);
+        if ((s = tm.mark(7)) != RECOGS_OK) return s;
+    } else if (K > 0 && mode == 2) {
+        // tile-first: keys of the index-ordered compaction, a stable sort by tile, then each
+        // tile's list sorted by depth
+        uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
+        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        launch_emit_compacted(dv0, V, (const uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, cd.tiles_x,
+                              t0, v0, stream, nullptr, nullptr, nullptr, nullptr, 1);
+        if ((s = tm.mark(5)) != RECOGS_OK) return s;
+        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
+        if ((s = tm.mark(6)) != RECOGS_OK) return s;
+        launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream, nullptr);
+        if ((s = tm.mark(7)) != RECOGS_OK) return s;
+        launch_tile_depth_sort(ranges, (uint32_t)ntiles, alt ? v1 : v0, zb, hdr, alt ? t0 : t1, alt ? v0 : v1, stream);
     } else if (K > 0) {
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         launch_emit(cnt, off, rect, zb, n, cd.tiles_x, k0, v0, stream);
@@ -604,11 +644,12 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         alt = radix_sort_tile_depth64(k0, v0, k1, v1, (uint32_t)K, zmin, dbits, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges(alt ? k1 : k0, (uint32_t)K, ranges, stream);
+        if ((s = tm.mark(7)) != RECOGS_OK) return s;
     } else {
-        for (int k = 4; k <= 6; ++k)
+        for (int k = 4; k <= 7; ++k)
             if ((s = tm.mark(k)) != RECOGS_OK) return s;
     }
-    if ((s = tm.mark(7)) != RECOGS_OK) return s;
+    if ((s = tm.mark(kBlendStage)) != RECOGS_OK) return s;
     ws->sorted_in_alt = alt;
     if ((s = hip_check("emit/sort/ranges")) != RECOGS_OK) return s;
     if (!launch_blend(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, ranges, alt ? v1 : v0, rec, cam->width,
@@ -617,9 +658,9 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
                       opts->keep_backward_state ? at<uint32_t>(ws, ws->off_nproc) : nullptr,
                       at<uint32_t>(ws, ws->off_zbits), opts->depth_tau, opts->depth_map, stream))
         return fail(RECOGS_ERR_UNSUPPORTED, "no blend kernel for this tile / px_per_thread");
-    if ((s = tm.mark(8)) != RECOGS_OK) return s;
+    if ((s = tm.mark(kBlendStage + 1)) != RECOGS_OK) return s;
     if ((s = hip_check("blend")) != RECOGS_OK) return s;
-    return tm.finish(ws, 8);
+    return tm.finish(ws, kBlendStage + 1);
 }
 
 // The backward of both entry points: out = dL/dC0 [3][n], or with all_bands
@@ -1009,7 +1050,7 @@ recogs_status recogs_render_batch(const recogs_batch_workspace *ws, hipStream_t 
         const size_t sc_n = ws->scan_chunks;
         uint64_t *pk = (uint64_t *)B(ws->off_scan);
         uint32_t *pv = (uint32_t *)(pk + sc_n);
-        launch_scan(cnt, zb, off, P, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream);
+        launch_scan(cnt, zb, off, P, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream, nullptr);
     }
     // depth sort of the pairs with keys over all 32 depth bits above the minimum
     const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, P, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist, scount, stream);

@@ -27,15 +27,16 @@ def _setup(R, n=100_000):
     return w, v, d, mask, M, b
 
 
+@pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("tile,ppt", [((16, 16), 2), ((8, 8), 1), ((32, 8), 4), ((32, 32), 2)])
-def test_graph_mode_equals_eager(R, tile, ppt):
+def test_graph_mode_equals_eager(R, tile, ppt, mode):
     import torch
     w, v, d, mask, M, b = _setup(R)
     cam = v.camera
     ws_e = R.DeviceWorkspace(d.n, cam.width, cam.height, tile)
-    eager = R.render(d, cam, ws_e, tile, ppt, (0.1, 0.2, 0.3), mask, M, b).clone()  # grows on demand
+    eager = R.render(d, cam, ws_e, tile, ppt, (0.1, 0.2, 0.3), mask, M, b, sort_mode=mode).clone()  # grows on demand
     ws_g = R.DeviceWorkspace(d.n, cam.width, cam.height, tile, key_capacity=int(ws_e.ws.num_keys) + 1024)
-    img = R.render(d, cam, ws_g, tile, ppt, (0.1, 0.2, 0.3), mask, M, b, graph_mode=True)
+    img = R.render(d, cam, ws_g, tile, ppt, (0.1, 0.2, 0.3), mask, M, b, graph_mode=True, sort_mode=mode)
     k, nv = ws_g.readback()
     assert torch.equal(img, eager)
     assert k == int(ws_e.ws.num_keys) and nv == int(ws_e.ws.num_visible)
@@ -44,7 +45,8 @@ def test_graph_mode_equals_eager(R, tile, ppt):
     assert torch.equal(ws_g.ranges(), ws_e.ranges())
 
 
-def test_graph_mode_captured_recolor_and_render_replays(R):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_mode_captured_recolor_and_render_replays(R, mode):
     import torch
     w, v, d, mask, M, b = _setup(R)
     cam = v.camera
@@ -55,7 +57,7 @@ def test_graph_mode_captured_recolor_and_render_replays(R):
 
     def frame():
         R.recogs_recolor(sc, sh2.data_ptr(), mask.data_ptr(), M.data_ptr(), b.data_ptr(), 0)
-        R.render(d, cam, ws, (16, 16), 2, image=img, sh=sh2, graph_mode=True)
+        R.render(d, cam, ws, (16, 16), 2, image=img, sh=sh2, graph_mode=True, sort_mode=mode)
 
     frame()
     torch.cuda.synchronize()
@@ -79,12 +81,13 @@ def test_graph_mode_captured_recolor_and_render_replays(R):
     assert ws.readback()[0] > 0
 
 
-def test_graph_mode_overflow_draws_background_and_reports(R):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_mode_overflow_draws_background_and_reports(R, mode):
     import torch
     w, v, d, mask, M, b = _setup(R, n=50_000)
     cam = v.camera
     ws = R.DeviceWorkspace(d.n, cam.width, cam.height, (16, 16), key_capacity=100)
-    img = R.render(d, cam, ws, (16, 16), 1, (0.25, 0.5, 0.75), graph_mode=True)
+    img = R.render(d, cam, ws, (16, 16), 1, (0.25, 0.5, 0.75), graph_mode=True, sort_mode=mode)
     k, _ = ws.readback()
     assert k > 100
     assert torch.equal(img, torch.tensor([0.25, 0.5, 0.75], device="cuda").expand_as(img))

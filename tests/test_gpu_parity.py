@@ -151,7 +151,7 @@ def _check_integer_steps(w, orc, p, pr, n):
     return zmis
 
 
-@pytest.mark.parametrize("sort_mode", [0, 1])
+@pytest.mark.parametrize("sort_mode", [0, 1, 2])
 @pytest.mark.parametrize("cfg", ["tiny", "mid"])
 def test_render_full_image(R, orc, cfg, sort_mode):
     w = synth.make_tiny() if cfg == "tiny" else synth.make_mid()
@@ -179,6 +179,7 @@ def test_render_full_image(R, orc, cfg, sort_mode):
 
 
 @pytest.mark.parametrize("storage,sort_mode,tile,ppt", [("f32", 0, (32, 32), 1), ("f32", 0, (16, 16), 1),
+                                                       ("f32", 2, (32, 32), 1), ("f32", 2, (16, 16), 1),
                                                        ("f32", 1, (32, 32), 2), ("f16", 0, (32, 32), 1),
                                                        ("bf16", 0, (16, 16), 1)])
 def test_render_1m_1080p_crops(R, orc, storage, sort_mode, tile, ppt):
@@ -334,7 +335,7 @@ def test_tile_shape_ppt_and_sort_mode_do_not_change_bits(R):
     base = gpu_run(w, tile=(16, 16), ppt=1)["img"].cpu().numpy()
     for tile in [(16, 16), (8, 8), (32, 8), (32, 16), (32, 32)]:
         for ppt in [1, 2, 4]:
-            for mode in [0, 1]:
+            for mode in [0, 1, 2]:
                 img = gpu_run(w, tile=tile, ppt=ppt, sort_mode=mode)["img"].cpu().numpy()
                 assert np.array_equal(img, base), (tile, ppt, mode, np.abs(img - base).max())
         # the blend that also writes the backward's per-pixel state draws the same bits
@@ -394,7 +395,7 @@ def test_stage_profiling_modes_leave_the_image_unchanged(R):
     ref = R.render(d, v.camera, ws, (16, 16), 2).clone()
     img = R.render(d, v.camera, ws, (16, 16), 2, profile=1)
     assert torch.equal(img, ref)
-    assert ws.ws.stage_ms[7] > 0 and ws.ws.profiled_frames == 0
+    assert ws.ws.stage_ms[8] > 0 and ws.ws.profiled_frames == 0
     for _ in range(3):
         img = R.render(d, v.camera, ws, (16, 16), 2, profile=2)
     assert torch.equal(img, ref)
@@ -408,6 +409,31 @@ def test_stage_profiling_modes_leave_the_image_unchanged(R):
     img = R.render(d, v.camera, ws, (16, 16), 2, profile=2)  # recreated on demand
     assert torch.equal(img, ref)
     assert ws.blend_time()[1] == 4
+
+
+def test_tile_first_order_long_lists(R, orc):
+    """Tile lists longer than one workgroup's LDS sort (8,192 keys): 200,000 Gaussians in a
+    small view, the per-tile depth sort going through memory; the sorted lists and the
+    image equal those of the depth-first order, and the lists the oracle's."""
+    import torch
+    w = synth.make_mid()
+    c = synth.orbit_camera(96, 80, 50.0, 4.0, 0.7, 0.3)
+    w1 = synth.Workload("dense", [w.scene], [synth.View(0, c, w.view.select, w.view.recolor)])
+    n = w.scene.n
+    for tile in [(32, 32), (16, 16)]:
+        a = gpu_run(w1, tile=tile, sort_mode=0)
+        b = gpu_run(w1, tile=tile, sort_mode=2, dscene=a["dscene"])
+        lens = (b["ws"].ranges()[:, 1] - b["ws"].ranges()[:, 0]).cpu().numpy()
+        assert lens.max() > 8192 and (lens > 1).sum() > 1, lens.max()
+        assert torch.equal(a["img"], b["img"])
+        K = int(a["ws"].ws.num_keys)
+        assert int(b["ws"].ws.num_keys) == K
+        assert torch.equal(a["ws"].vals_sorted()[:K], b["ws"].vals_sorted()[:K])
+        assert torch.equal(a["ws"].ranges(), b["ws"].ranges())
+        p = pull(b, n)
+        pr = orc.project(w.scene, c, tile)
+        _check_integer_steps(w1, orc, p, pr, n)
+        print(f"{tile}: K={K}, longest list {lens.max()}")
 
 
 # ---------------------------------------------------------------------------
@@ -441,7 +467,7 @@ def test_ragged_image_sizes(R, orc, size):
     w = synth.make_tiny()
     c = synth.orbit_camera(W, H, 60.0, 3.0, 0.4, 0.3)
     w1 = synth.Workload("ragged", [w.scene], [synth.View(0, c, w.view.select, w.view.recolor)])
-    for tile, mode in [((16, 16), 0), ((32, 8), 0), ((8, 8), 1)]:
+    for tile, mode in [((16, 16), 0), ((32, 8), 0), ((8, 8), 1), ((32, 32), 2), ((8, 8), 2)]:
         out = gpu_run(w1, tile=tile, sort_mode=mode)
         p = pull(out, w.scene.n)
         pr = orc.project(w.scene, c, tile)
