@@ -39,6 +39,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X fp32 vector (256 CU x 2.4 GHz, packed FMA)
 BLEND_FLOPS_PER_EVAL = 23        # dx, dy, exponent (2 mul + 3 fma), test, exp2, clamp, T, weight, 3 fma
 SORT_MODE = 0                    # (tile, depth, index) order: 0 depth-first, 2 tile-first; --sort-mode
+BWD_FORM = "tile"                # the backward: "tile" (one workgroup per tile) or "block" (a wave per 8x8 block)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
@@ -363,7 +364,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     dM = torch.empty(9, dtype=torch.float32, device=dev)
     scale = 1.0 / (len(w.views) * H * W * 3)
     cams = [R.camera_struct(v.camera) for v in w.views]
-    o = R.opts_struct(tile, ppt, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True)
+    o = R.opts_struct(tile, ppt, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True, bwd_scratch=ws[0].backward_scratch(tile, ppt) if BWD_FORM == "block" else None)
 
     def step():
         for k, v in enumerate(w.views):
@@ -396,7 +397,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
             "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.sum().item()),
             "grad_M_norm": float(dM.norm().item()), "grad_opacity_norm": float(dop.norm().item()),
-            "grad_dc_norm": float(ddc.norm().item()), "grad_over_views": len(w.views)}
+            "grad_dc_norm": float(ddc.norm().item()), "grad_over_views": len(w.views), "backward_form": BWD_FORM}
 
 
 def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
@@ -434,7 +435,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     dsh = torch.zeros((3 * K, d.stride), dtype=torch.float32, device=dev)
     dM = torch.empty(9, dtype=torch.float32, device=dev)
     cams = [R.camera_struct(v.camera) for v in w.views]
-    o = R.opts_struct(tile, ppt, keep_backward=True)
+    o = R.opts_struct(tile, ppt, keep_backward=True, bwd_scratch=ws.backward_scratch(tile, ppt) if BWD_FORM == "block" else None)
     sc = d.c_struct(sh)
     cnt_px = H * W * 3
     lam = 0.2
@@ -484,7 +485,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     torch.cuda.synchronize()
     ms_fused = 1000.0 * (time.perf_counter() - t0) / reps
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
-            "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "ms_per_step": round(ms, 3),
+            "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "backward_form": BWD_FORM, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps, "ms_per_step_fused_adam": round(ms_fused, 3),
             "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first, "loss_mean_end": end,
             "loss_mean_after_fused_steps": float((loss + lss).mean().item())}
@@ -617,7 +618,7 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     dop = torch.empty(n, dtype=torch.float32, device=dev)
     dM = torch.empty(9, dtype=torch.float32, device=dev)
     cams = [R.camera_struct(v.camera) for v in w.views]
-    o = R.opts_struct(tile, ppt, keep_backward=True)
+    o = R.opts_struct(tile, ppt, keep_backward=True, bwd_scratch=ws.backward_scratch(tile, ppt) if BWD_FORM == "block" else None)
     sc = d.c_struct(sh)
     cnt_px = H * W * 3
     lam = 0.2
@@ -658,7 +659,7 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "selected_pixels": int(sel.sum()),
             "cloud_points": int(n_pts), "unprojected_points": int(n_sel),
             "marked_pixels_per_view": [int(x) for x in marked.cpu().tolist()],
-            "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
+            "backward_form": BWD_FORM, "ms_per_step": round(ms, 3), "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps,
             "loss": "0.8 L1 + 0.2 (1 - SSIM) against the tinted view", "loss_mean_first_pass": first,
             "loss_mean_end": float((loss + lss).mean().item())}
 
@@ -696,7 +697,7 @@ def cpu_baseline(w):
 
 
 def main():
-    global SORT_MODE
+    global SORT_MODE, BWD_FORM
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -709,6 +710,9 @@ def main():
     ap.add_argument("--diff-tile", type=int, nargs=2, default=None,
                     help="tile shape of the differentiation form when run alone (--only-form diff)")
     ap.add_argument("--diff-ppt", type=int, default=DIFF_PPT)
+    ap.add_argument("--bwd-form", choices=["block", "tile"], default=BWD_FORM,
+                    help="backward of the differentiation, refit and edit forms: one workgroup per tile, or one "
+                         "wave per 8x8 block (with its scratch)")
     ap.add_argument("--layout", choices=["hwc", "chw"], default="hwc", help="output layout of the timed frame")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison frames (16x16 tiles, the other output layout)")
@@ -723,6 +727,7 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for rocprof traffic counters)")
     args = ap.parse_args()
     SORT_MODE = args.sort_mode
+    BWD_FORM = args.bwd_form
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU form (sharding across GPUs is designed, not built)",
               file=sys.stderr)

@@ -153,6 +153,18 @@ typedef struct {
      * tile shape. Either rule gives no tiles to a splat with 255 sigma < 1. INVALID
      * otherwise. */
     int32_t extent_rule;
+    /* Backward only (ignored by the render): optional device scratch of at least
+     * recogs_backward_scratch_bytes bytes, 256-byte aligned, caller-owned, its contents
+     * not kept between calls (so calls that share one scratch must not overlap). Given,
+     * and where the tile height is a multiple of 8 * px_per_thread, the backward
+     * replays each 8 x 8*px_per_thread block of a tile with its own wave, which walks
+     * the tile's list without waiting for the others (as the forward blend does), and
+     * the tile's workgroup then adds the blocks' parts of each (Gaussian, tile)
+     * gradient in block order; NULL: one workgroup per tile whose waves step through
+     * the list together. Both are deterministic and give the same gradients up to
+     * float32 summation order. INVALID: too small or misaligned. */
+    void *bwd_scratch;
+    size_t bwd_scratch_bytes;
 } recogs_render_opts;
 
 /* Workspace: caller-provided device memory carved by recogs_workspace_init. It holds
@@ -281,6 +293,13 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
  * are bit-identical between runs. The backward uses the workspace's sorted-key buffers
  * (keys0/keys1) as per-key gradient scratch; the tile lists and the rest of the
  * render's state stay valid, so it may be called again on the same render. */
+/* Bytes of the scratch the backward's block form needs (opts->bwd_scratch) for this
+ * workspace and opts' tile shape and px_per_thread, with B blocks per tile: a float4
+ * per block and key of ws->key_capacity, rounded up to 256 bytes, then B * (capacity / 64
+ * + tiles + 2) flag words of 16 bytes. 0 where the shape has no block form or an
+ * argument is NULL / unsupported. */
+size_t recogs_backward_scratch_bytes(const recogs_workspace *ws, const recogs_render_opts *opts);
+
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
                                      const recogs_render_opts *opts, const recogs_workspace *ws,
                                      const float *image, const float *dL_dimage, float *dL_dopacity,

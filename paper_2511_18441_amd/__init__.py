@@ -14,7 +14,7 @@ from .binding import (  # noqa: F401
     recogs_adam_step, recogs_dssim_workspace_bytes, recogs_loss_dssim, recogs_last_error,
     recogs_unproject_workspace_bytes, recogs_unproject, recogs_reproject_mask, recogs_tint, unproject, reproject_mask, tint,
     recogs_outlier_workspace_bytes, recogs_remove_outliers, remove_outliers, recogs_render_backward_sh_adam,
-    recogs_workspace_keys_needed, recogs_unproject_noalloc,
+    recogs_workspace_keys_needed, recogs_unproject_noalloc, recogs_backward_scratch_bytes,
     BATCH_ENTRY_POINTS, BatchView, BatchWorkspace, DeviceBatch, recogs_batch_workspace_bytes, recogs_batch_init,
     recogs_render_batch, recogs_batch_readback,
 )

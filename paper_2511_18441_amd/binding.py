@@ -31,7 +31,8 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
                 "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_render_backward_sh_adam",
-                "recogs_workspace_keys_needed", "recogs_unproject_noalloc", "recogs_last_error")
+                "recogs_workspace_keys_needed", "recogs_unproject_noalloc", "recogs_backward_scratch_bytes",
+                "recogs_last_error")
 
 
 class RecogsError(RuntimeError):
@@ -62,7 +63,8 @@ class RenderOpts(ctypes.Structure):
                 ("bg", ctypes.c_float * 3), ("mask", ctypes.c_void_p), ("M", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("keep_backward_state", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("sort_mode", ctypes.c_int32), ("graph_mode", ctypes.c_int32), ("output_chw", ctypes.c_int32),
-                ("depth_map", ctypes.c_void_p), ("depth_tau", ctypes.c_float), ("extent_rule", ctypes.c_int32)]
+                ("depth_map", ctypes.c_void_p), ("depth_tau", ctypes.c_float), ("extent_rule", ctypes.c_int32),
+                ("bwd_scratch", ctypes.c_void_p), ("bwd_scratch_bytes", ctypes.c_size_t)]
 
 
 class Workspace(ctypes.Structure):
@@ -114,6 +116,8 @@ def lib():
         L.recogs_render_backward_sh.argtypes = [P(Scene), P(Camera), P(RenderOpts), P(Workspace), vp, vp, vp, vp, vp,
                                                 i32, vp]
         L.recogs_workspace_keys_needed.argtypes = [P(Workspace), P(i64), vp]
+        L.recogs_backward_scratch_bytes.argtypes = [P(Workspace), P(RenderOpts)]
+        L.recogs_backward_scratch_bytes.restype = ctypes.c_size_t
         L.recogs_loss_l1.argtypes = [vp, vp, i64, f32, vp, vp, vp]
         L.recogs_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
         L.recogs_dssim_workspace_bytes.argtypes = [i32, i32]
@@ -134,7 +138,7 @@ def lib():
         for name in ENTRY_POINTS:
             if name not in ("recogs_workspace_bytes", "recogs_last_error", "recogs_workspace_release",
                             "recogs_dssim_workspace_bytes", "recogs_unproject_workspace_bytes",
-                            "recogs_outlier_workspace_bytes"):
+                            "recogs_outlier_workspace_bytes", "recogs_backward_scratch_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -215,6 +219,10 @@ def recogs_render_backward_sh(scene: Scene, cam: Camera, opts: RenderOpts, ws: W
     return _check("recogs_render_backward_sh", lib().recogs_render_backward_sh(
         ctypes.byref(scene), ctypes.byref(cam), ctypes.byref(opts), ctypes.byref(ws), image, dL_dimage, dL_dopacity,
         dL_dsh, dL_dM, int(accumulate), _stream(stream)))
+
+
+def recogs_backward_scratch_bytes(ws: Workspace, opts: RenderOpts) -> int:
+    return int(lib().recogs_backward_scratch_bytes(ctypes.byref(ws), ctypes.byref(opts)))
 
 
 def recogs_workspace_keys_needed(ws: Workspace, stream=None) -> int:
@@ -384,7 +392,7 @@ def select_struct(sp) -> SelectParams:
 
 def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=None, keep_backward=False,
                 profile=False, sort_mode=0, graph_mode=False, chw=False, depth=None, depth_tau=0.5,
-                extent_rule=0) -> RenderOpts:
+                extent_rule=0, bwd_scratch=None) -> RenderOpts:
     o = RenderOpts()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
     o.px_per_thread = int(ppt)
@@ -401,6 +409,9 @@ def opts_struct(tile=(16, 16), ppt=1, bg=(0.0, 0.0, 0.0), mask=None, M=None, b=N
     o.depth_map = depth.data_ptr() if depth is not None else None
     o.depth_tau = float(depth_tau)
     o.extent_rule = int(extent_rule)
+    if bwd_scratch is not None:   # a device tensor (e.g. DeviceWorkspace.backward_scratch)
+        o.bwd_scratch = bwd_scratch.data_ptr()
+        o.bwd_scratch_bytes = bwd_scratch.numel() * bwd_scratch.element_size()
     return o
 
 
@@ -494,6 +505,19 @@ class DeviceWorkspace:
 
     def grow(self, needed):
         self._alloc(int(needed * 1.25) + 1024)
+
+    def backward_scratch(self, tile, ppt):
+        """Device scratch for the backward's block form at this tile shape and pixels per
+        thread (None where the shape has none), kept for reuse; 256-byte aligned."""
+        import torch
+        o = opts_struct(tile, ppt)
+        nb = recogs_backward_scratch_bytes(self.ws, o)
+        if nb == 0:
+            return None
+        cur = getattr(self, "_bwd", None)
+        if cur is None or cur.numel() < nb or cur.data_ptr() % 256:
+            self._bwd = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        return self._bwd[:nb]
 
     # views of internal buffers (inspection and tests)
     def view(self, off, count, dtype):

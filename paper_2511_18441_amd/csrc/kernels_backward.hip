@@ -11,8 +11,9 @@
 //   dL/dsigma_i += dL/dalpha_i G_i(p)   (0 where alpha is clamped at 0.99)
 // No float atomics: every (Gaussian, tile) pair owns one slot of a per-key gradient
 // array, Gaussian-contiguous (slot = the Gaussian's key offset from the count scan +
-// the tile's row-major rank in its tile rectangle). A splat's sums over one wave come
-// from DPP reductions, the waves of the tile add theirs in LDS, and one float4 store
+// the tile's row-major rank in its tile rectangle). A splat's four sums over one wave
+// come from one transposed reduction (wave_sum4), the waves of the tile add theirs in
+// LDS, and one float4 store
 // per (splat, tile) writes the slot; k_grad_finish then sums each Gaussian's slots in
 // a fixed order, so the gradients are deterministic.
 #include "optim_device.hpp"
@@ -118,9 +119,9 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                     quit = true;
                     break;
                 }
-                const BlendRec &b = sm.r[q];
-                const float2 uv = b.uv;
-                const float4 r1 = b.r1, r2 = b.rgb;
+                const float4 *br = reinterpret_cast<const float4 *>(&sm.r[q]);
+                const float4 h = br[0], r1 = br[1], r2 = br[2];
+                const float2 uv = make_float2(h.x, h.y);
                 // 1 / sigma to about 1 ulp: it only scales this splat's opacity gradient
                 const float inv_sigma = __builtin_amdgcn_rcpf(r2.w);
                 const ExpRow er = exp_row(r1, pxc - uv.x);
@@ -138,8 +139,9 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                     const float wgt = act ? a * T[j] : 0.f;
                     const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
                     const float ws = wgt * sg;
+                    // (finite: 1 - a >= 0.01) computed on every lane, selected by a factor
                     const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
-                    const float vs = (act && araw < kAlphaMax) ? dal * (araw * inv_sigma) : 0.f;
+                    const float vs = dal * ((act && araw < kAlphaMax) ? araw * inv_sigma : 0.f);
                     if (j == 0) {   // (no adds of zero: x + 0 is not folded, for the sign of zero)
                         dr = wgt * g0[j]; dg = wgt * g1[j]; db = wgt * g2[j]; ds = vs;
                     } else {
@@ -149,8 +151,14 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                     T[j] = act ? __builtin_fmaf(-a, T[j], T[j]) : T[j];
                 }
                 if (wave_ballot(any)) {
-                    ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
-                    if (lane_id() == 0) s_acc[wv][q] = make_float4(ds, dr, dg, db);
+                    if constexpr (L == 64) {
+                        const float tot = wave_sum4(ds, dr, dg, db);
+                        const uint32_t l = lane_id();
+                        if (l < 4) ((float *)&s_acc[wv][q])[sum4_part(l)] = tot;
+                    } else {
+                        ds = wave_sum_dpp<L>(ds); dr = wave_sum_dpp<L>(dr); dg = wave_sum_dpp<L>(dg); db = wave_sum_dpp<L>(db);
+                        if (lane_id() == 0) s_acc[wv][q] = make_float4(ds, dr, dg, db);
+                    }
                 }
             }
         }
@@ -163,6 +171,202 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 v.x += x.x; v.y += x.y; v.z += x.z; v.w += x.w;
             }
             if (v.x != 0.f || v.y != 0.f || v.z != 0.f || v.w != 0.f) gk[sm.r[q].pad] = v;
+        }
+    }
+}
+
+// Block form of the backward: a workgroup per tile with one wave per 8 x 8*PPT pixel
+// block (the forward's region form, its blocks in the same order). Each wave walks the
+// tile's list on its own, 64 entries at a time, one per lane: the entries region_hit
+// admits for its block are compacted into the wave's LDS in list order and replayed,
+// with the arithmetic of k_blend_bwd, until every pixel of the block has passed its
+// last blended entry. No barrier couples the waves while they replay.
+// Gradients stay deterministic without float atomics: a wave writes its sums, one float4
+// per entry with an active pixel, densely in list order from sub[b * cap + first] (b: the
+// block, first: the tile's first list position), and per chunk of 64 positions the word
+// fw[b * fstride + first / 64 + tile + chunk] = (bit set per position written, count
+// written before the chunk) (the tile term keeps the words of neighbouring tiles apart);
+// the words of chunks past the block's replay count are never read. After the one
+// barrier the workgroup adds, for each position of the tile, the written block sums in
+// block order and writes the (Gaussian, tile) slot of k_blend_bwd, so k_grad_finish reads
+// the same slots in either form.
+template <int TW, int TH, int PPT>
+__global__ __launch_bounds__((TW / 8) * (TH / (8 * PPT)) * 64) void k_blend_bwd_blocks(
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals, const SplatRec *__restrict__ rec,
+    const uint2 *__restrict__ rect, const uint32_t *__restrict__ koff, int W, int H, int tiles_x,
+    const float *__restrict__ image, const float *__restrict__ dldy, const uint32_t *__restrict__ nproc,
+    float4 *__restrict__ sub, ulonglong2 *__restrict__ fw, uint32_t cap, uint32_t fstride, float4 *__restrict__ gk) {
+#pragma clang fp contract(off)
+    constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
+    constexpr int NT = (int)NR * 64;
+    __shared__ float4 sm[NR][64][3];   // per wave: (u, v, -, 1-based position), conic row, colour and sigma
+    __shared__ uint32_t s_npl[NR];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t region = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t tcx = tile % (uint32_t)tiles_x, tcy = tile / (uint32_t)tiles_x;
+    const int l = (int)lane_id();
+    const int bx = (int)tcx * TW + (int)(region % (TW / 8)) * 8;
+    const int by = (int)tcy * TH + (int)(region / (TW / 8)) * 8 * PPT;
+    const int px = bx + (l & 7);
+    const float pxc = (float)px + 0.5f;
+    const float x0 = (float)bx + 0.5f, x1 = x0 + 7.f;
+    const float y0 = (float)by + 0.5f, y1 = y0 + (float)(8 * PPT - 1);
+    float pyc[PPT], T[PPT], Gr[PPT], g0[PPT], g1[PPT], g2[PPT];
+    uint32_t np[PPT], npl = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int py = by + (l >> 3) * PPT + j;
+        pyc[j] = (float)py + 0.5f;
+        T[j] = 1.f;
+        np[j] = 0;
+        Gr[j] = g0[j] = g1[j] = g2[j] = 0.f;
+        if (px < W && py < H) {
+            const int64_t p = (int64_t)py * W + px;
+            np[j] = nproc[p];
+            g0[j] = dldy[p * 3]; g1[j] = dldy[p * 3 + 1]; g2[j] = dldy[p * 3 + 2];
+            Gr[j] = g0[j] * image[p * 3] + g1[j] * image[p * 3 + 1] + g2[j] * image[p * 3 + 2];
+        }
+        npl = max(npl, np[j]);
+    }
+    // the block's largest replay count: entries past it are read by no pixel here
+    npl = wave_max(npl);
+    const uint2 rg = ranges[tile];
+    float4 *wsub = sub + (size_t)region * cap + rg.x;
+    ulonglong2 *wfw = fw + (size_t)region * fstride + (rg.x >> 6) + tile;
+    uint32_t wcount = 0;   // sums written so far
+    // software pipeline as in the forward: the records of chunk c are in registers while
+    // chunk c - 1 is replayed, the list values of chunk c + 1 on their way
+    float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    uint32_t vnext = 0;
+    {
+        const uint32_t k = rg.x + (uint32_t)l;
+        if (k < rg.y) {
+            const SplatRec *sp = rec + vals[k];
+            p0 = sp->r0; p1 = sp->r1; p2 = sp->r2;
+        }
+        if (k + 64u < rg.y) vnext = vals[k + 64u];
+    }
+    for (uint32_t start = rg.x; start < rg.y && start - rg.x < npl; start += 64) {
+        const uint32_t pos = start + 1u - rg.x + (uint32_t)l;
+        const bool in = start + (uint32_t)l < rg.y;
+        // replayed: admitted for the block and within its replay count (the admitted
+        // entries are compacted in list order, so these are the first nh of them)
+        const bool hit = in && region_hit(p0, p1, x0, x1, y0, y1) && pos <= npl;
+        const uint64_t mm = wave_ballot(hit);
+        const int nh = (int)__builtin_popcountll(mm);
+        const uint32_t rank = rank_below(mm);
+        if (hit) {
+            sm[region][rank][0] = make_float4(p0.x, p0.y, 0.f, __uint_as_float(pos));
+            sm[region][rank][1] = p1;
+            sm[region][rank][2] = p2;
+        }
+        wave_sync();   // the lanes' LDS writes before any lane reads
+        {
+            const uint32_t k = start + 64u + (uint32_t)l;
+            if (k < rg.y) {
+                const SplatRec *sp = rec + vnext;
+                p0 = sp->r0; p1 = sp->r1; p2 = sp->r2;
+            }
+            if (k + 64u < rg.y) vnext = vals[k + 64u];
+        }
+        uint64_t wrote = 0;   // bit q: compacted entry q had an active pixel here
+        for (int q = 0; q < nh; ++q) {
+            const float4 h = sm[region][q][0], r1 = sm[region][q][1], r2 = sm[region][q][2];
+            const uint32_t krel = __float_as_uint(h.w);
+            const float2 uv = make_float2(h.x, h.y);
+            // 1 / sigma to about 1 ulp: it only scales this splat's opacity gradient
+            const float inv_sigma = __builtin_amdgcn_rcpf(r2.w);
+            const ExpRow er = exp_row(r1, pxc - uv.x);
+            float ds, dr, dg, db;
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const float e = exp_at(er, r1, pyc[j] - uv.y);
+                const bool act = krel <= np[j] && !(e < kLog2AlphaMin);
+                any = any || act;
+                const float araw = __builtin_amdgcn_exp2f(e);
+                const float a = fminf(kAlphaMax, araw);
+                const float wgt = act ? a * T[j] : 0.f;
+                const float sg = g0[j] * r2.x + g1[j] * r2.y + g2[j] * r2.z;
+                const float ws = wgt * sg;
+                // (finite: 1 - a >= 0.01) computed on every lane, selected by a factor
+                const float dal = T[j] * sg - (Gr[j] - ws) * __builtin_amdgcn_rcpf(1.f - a);
+                const float vs = dal * ((act && araw < kAlphaMax) ? araw * inv_sigma : 0.f);
+                if (j == 0) {   // (no adds of zero: x + 0 is not folded, for the sign of zero)
+                    dr = wgt * g0[j]; dg = wgt * g1[j]; db = wgt * g2[j]; ds = vs;
+                } else {
+                    dr += wgt * g0[j]; dg += wgt * g1[j]; db += wgt * g2[j]; ds += vs;
+                }
+                Gr[j] -= ws;
+                T[j] = act ? __builtin_fmaf(-a, T[j], T[j]) : T[j];
+            }
+            if (wave_ballot(any)) {
+                const float tot = wave_sum4(ds, dr, dg, db);
+                if (l < 4) ((float *)(wsub + wcount + __builtin_popcountll(wrote)))[sum4_part((uint32_t)l)] = tot;
+                wrote |= 1ull << q;
+            }
+        }
+        const uint64_t wm = wave_ballot(hit && ((wrote >> rank) & 1ull));
+        if (l == 0) wfw[(start - rg.x) >> 6] = make_ulonglong2(wm, wcount);
+        wcount += (uint32_t)__builtin_popcountll(wm);
+        wave_sync();   // all reads of this chunk before the next chunk's writes
+    }
+    // wave w adds the chunks w, w + NR, ... of the tile's list, U at a time so that their
+    // loads are in flight together. The slots of its first U chunks (gathers of the
+    // Gaussians' rectangles and key offsets) are fetched before the barrier, while other
+    // waves may still replay.
+    const uint32_t L = rg.y - rg.x;
+    const uint32_t nchunks = (L + 63u) >> 6;
+    constexpr int U = NR >= 16 ? 2 : 4;
+    uint32_t slot[U];
+    auto slots = [&](uint32_t c0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = (c0 + (uint32_t)u * NR) * 64u + (uint32_t)l;
+            slot[u] = 0;
+            if (i < L) {
+                const uint32_t gid = vals[rg.x + i];
+                const uint2 rc = rect[gid];
+                const uint32_t rx0 = rc.x & 0xffffu, rx1 = rc.x >> 16, ry0 = rc.y & 0xffffu;
+                slot[u] = koff[gid] + (tcy - ry0) * (rx1 - rx0 + 1u) + (tcx - rx0);
+            }
+        }
+    };
+    slots(region);
+    if (l == 0) s_npl[region] = npl;
+    __syncthreads();   // every block's sums and flags, and the replay counts, before the adds
+    const ulonglong2 *words = fw + (rg.x >> 6) + tile;
+    const uint64_t below = (1ull << l) - 1ull;   // lanes under this one
+    for (uint32_t c0 = region; c0 < nchunks; c0 += NR * U) {
+        if (c0 != region) slots(c0);
+        uint32_t fm[U], at[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t c = c0 + (uint32_t)u * NR;   // wave-uniform
+            const uint32_t i = c * 64u + (uint32_t)l;
+            fm[u] = 0;
+#pragma unroll
+            for (uint32_t r = 0; r < NR; ++r) {
+                at[u][r] = 0;
+                if (c < nchunks && c * 64u < s_npl[r]) {   // chunk walked by block r: its word was written
+                    const ulonglong2 wd = words[(size_t)r * fstride + c];
+                    fm[u] |= (i < s_npl[r] ? (uint32_t)(wd.x >> l) & 1u : 0u) << r;
+                    at[u][r] = (uint32_t)wd.y + (uint32_t)__builtin_popcountll(wd.x & below);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if ((c0 + (uint32_t)u * NR) * 64u + (uint32_t)l >= L) continue;
+            float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (uint32_t r = 0; r < NR; ++r) {
+                if ((fm[u] >> r) & 1u) {
+                    const float4 x = sub[(size_t)r * cap + rg.x + at[u][r]];
+                    a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+                }
+            }
+            gk[slot[u]] = a;
         }
     }
 }
@@ -354,6 +558,40 @@ bool launch_blend_bwd(int tw, int th, int ppt, int ntiles, const uint2 *ranges, 
     RECOGS_BWD_CASE(32, 16, 1) RECOGS_BWD_CASE(32, 16, 2) RECOGS_BWD_CASE(32, 16, 4)
     RECOGS_BWD_CASE(32, 32, 1) RECOGS_BWD_CASE(32, 32, 2) RECOGS_BWD_CASE(32, 32, 4)
 #undef RECOGS_BWD_CASE
+    return false;
+}
+
+// Block form of the backward (tile shapes with one wave per 8 x 8*PPT block): false when
+// the shape has none. sub: nr * cap float4, fw: nr * fstride (bits, count) words (fstride >=
+// cap / 64 + ntiles + 1); gk: the slots, all written.
+template <int TW, int TH, int PPT>
+static void bwd_blocks_one(int ntiles, hipStream_t st, const uint2 *ranges, const uint32_t *vals, const SplatRec *rec,
+                           const uint2 *rect, const uint32_t *koff, int W, int H, int tiles_x, const float *image,
+                           const float *dldy, const uint32_t *nproc, float4 *sub, ulonglong2 *fw, uint32_t cap,
+                           uint32_t fstride, float4 *gk) {
+    constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
+    hipLaunchKernelGGL((k_blend_bwd_blocks<TW, TH, PPT>), dim3((unsigned)ntiles), dim3(NR * 64), 0, st, ranges, vals, rec,
+                       rect, koff, W, H, tiles_x, image, dldy, nproc, sub, fw, cap, fstride, gk);
+}
+
+uint32_t bwd_blocks(int tw, int th, int ppt) { return region_shape(tw, th, ppt) ? (uint32_t)((tw / 8) * (th / (8 * ppt))) : 0u; }
+
+bool launch_blend_bwd_blocks(int tw, int th, int ppt, int ntiles, const uint2 *ranges, const uint32_t *vals,
+                             const SplatRec *rec, const uint2 *rect, const uint32_t *koff, int W, int H, int tiles_x,
+                             const float *image, const float *dldy, const uint32_t *nproc, float4 *sub, ulonglong2 *fw,
+                             uint32_t cap, uint32_t fstride, float4 *gk, hipStream_t st) {
+#define RECOGS_BWDB_CASE(A, B, P)                                                                                   \
+    if (tw == A && th == B && ppt == P) {                                                                           \
+        bwd_blocks_one<A, B, P>(ntiles, st, ranges, vals, rec, rect, koff, W, H, tiles_x, image, dldy, nproc, sub, \
+                                fw, cap, fstride, gk);                                                              \
+        return true;                                                                                                \
+    }
+    RECOGS_BWDB_CASE(16, 16, 1) RECOGS_BWDB_CASE(16, 16, 2)
+    RECOGS_BWDB_CASE(8, 8, 1)
+    RECOGS_BWDB_CASE(32, 8, 1)
+    RECOGS_BWDB_CASE(32, 16, 1) RECOGS_BWDB_CASE(32, 16, 2)
+    RECOGS_BWDB_CASE(32, 32, 1) RECOGS_BWDB_CASE(32, 32, 2) RECOGS_BWDB_CASE(32, 32, 4)
+#undef RECOGS_BWDB_CASE
     return false;
 }
 

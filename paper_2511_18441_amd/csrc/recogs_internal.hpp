@@ -141,6 +141,35 @@ template <int LANES> __device__ __forceinline__ float wave_sum_dpp(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), LANES - 1));
 }
 
+// Totals of four floats over the 64 lanes of a wave, transposed as they are summed so
+// that each step moves one value per lane: lanes l and l^1 trade halves (even lanes keep
+// a and b, odd lanes c and d), lanes l and l^2 trade again (one value per lane: a, c, b,
+// d in lanes 4m + 0, 1, 2, 3), the four same-value lanes of a row by rotations of 4 and
+// 8 lanes, then the rows by lane exchanges across 16 and 32. Lanes 0..3 return the
+// totals of a, c, b, d (lane l holds value ((l & 1) << 1) | ((l >> 1) & 1) of the
+// four). Every addition has a fixed place, so the totals are the same bits on every run.
+// All 64 lanes must be active.
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_sum4(float a, float b, float c, float d) {
+    const uint32_t l = lane_id();
+    const bool o1 = (l & 1u) != 0, o2 = (l & 2u) != 0;
+    float k0 = o1 ? c : a;
+    float k1 = o1 ? d : b;
+    k0 += dpp_mov<0xb1>(o1 ? a : c);   // quad_perm [1,0,3,2]
+    k1 += dpp_mov<0xb1>(o1 ? b : d);
+    float k = o2 ? k1 : k0;
+    k += dpp_mov<0x4e>(o2 ? k0 : k1);  // quad_perm [2,3,0,1]
+    k = dpp_add<0x124, 0xf>(k);        // row_ror:4
+    k = dpp_add<0x128, 0xf>(k);        // row_ror:8
+    k += __shfl_xor(k, 16, 64);
+    k += __shfl_xor(k, 32, 64);
+    return k;
+}
+// which of the four totals of wave_sum4 lane l (0..3) holds: 0 a, 1 b, 2 c, 3 d
+__device__ __forceinline__ uint32_t sum4_part(uint32_t l) { return ((l & 1u) << 1) | ((l >> 1) & 1u); }
+
 // inclusive prefix sum across the wave
 template <typename T> __device__ __forceinline__ T wave_incl_scan(T v) {
     const uint32_t l = lane_id();

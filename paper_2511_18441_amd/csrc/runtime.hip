@@ -46,6 +46,10 @@ bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
                         float *, float *, float *, int, const float *, int64_t, const CamDev &, int, hipStream_t, float *,
                         float *, float *, const AdamArgs *);
+uint32_t bwd_blocks(int, int, int);
+bool launch_blend_bwd_blocks(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *,
+                             const uint32_t *, int, int, int, const float *, const float *, const uint32_t *, float4 *,
+                             ulonglong2 *, uint32_t, uint32_t, float4 *, hipStream_t);
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
@@ -663,6 +667,18 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     return tm.finish(ws, kBlendStage + 1);
 }
 
+// The block backward's scratch for this workspace and launch shape: per block of a tile,
+// one float4 per key of capacity, then a 16-byte (written flags, count) word per 64 keys
+// of capacity and per tile (plus two). 0 bytes: the shape has no block form.
+static size_t bwd_flag_stride(const recogs_workspace *ws) {
+    return (size_t)ws->key_capacity / 64 + (size_t)ws->tiles_x * (size_t)ws->tiles_y + 2;
+}
+static size_t backward_scratch_bytes(const recogs_workspace *ws, const recogs_render_opts *o) {
+    const uint32_t nr = bwd_blocks(o->tile_w, o->tile_h, o->px_per_thread);
+    if (!nr || !ws || ws->key_capacity <= 0) return 0;
+    return align_up(16 * (size_t)nr * (size_t)ws->key_capacity) + 16 * (size_t)nr * bwd_flag_stride(ws);
+}
+
 // The backward of both entry points: out = dL/dC0 [3][n], or with all_bands
 // dL/dSH [3 (deg + 1)^2][scene stride].
 static recogs_status backward_impl(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,
@@ -687,23 +703,48 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     if (accumulate != 0 && accumulate != 1) return fail(RECOGS_ERR_INVALID, "accumulate %d not 0 or 1", accumulate);
     const int64_t n = scene->n;
     const int ntiles = ws->tiles_x * ws->tiles_y;
+    const uint32_t *koff = at<uint32_t>(ws, ws->off_offset);
+    const uint32_t *vals = ws->sorted_in_alt ? at<uint32_t>(ws, ws->off_vals1) : at<uint32_t>(ws, ws->off_vals0);
+    // the block form when the caller gives its scratch, else one workgroup per tile with
+    // a barrier per batch of the list
+    const uint32_t nr = bwd_blocks(opts->tile_w, opts->tile_h, opts->px_per_thread);
+    const bool blocks = opts->bwd_scratch && nr > 0;
+    if (blocks && opts->bwd_scratch_bytes < backward_scratch_bytes(ws, opts))
+        return fail(RECOGS_ERR_INVALID, "bwd_scratch of %zu bytes, the block backward needs %zu", opts->bwd_scratch_bytes,
+                    backward_scratch_bytes(ws, opts));
+    if (blocks && (uintptr_t)opts->bwd_scratch % kAlign) return fail(RECOGS_ERR_INVALID, "bwd_scratch not 256-byte aligned");
     // per-(Gaussian, tile) gradient slots, 16 bytes per key: the span of both sorted-key
     // buffers (adjacent, 16 bytes per key of capacity), which the backward does not read
     float4 *gk = at<float4>(ws, ws->off_keys0);
-    const uint32_t *koff = at<uint32_t>(ws, ws->off_offset);
-    const uint32_t *vals = ws->sorted_in_alt ? at<uint32_t>(ws, ws->off_vals1) : at<uint32_t>(ws, ws->off_vals0);
     if (ws->num_keys > 0) {
-        launch_fill_u32((uint32_t *)gk, 0u, 4 * ws->num_keys, stream);
-        if (!launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges), vals,
-                              at<SplatRec>(ws, ws->off_rec), at<uint2>(ws, ws->off_rect), koff, cam->width, cam->height,
-                              ws->tiles_x, image, dL_dimage, at<uint32_t>(ws, ws->off_nproc), gk, stream))
-            return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
+        bool ok;
+        if (blocks) {   // writes every slot
+            const size_t cap = (size_t)ws->key_capacity;
+            float4 *sub = (float4 *)opts->bwd_scratch;
+            ulonglong2 *fw = (ulonglong2 *)((char *)opts->bwd_scratch + align_up(16 * (size_t)nr * cap));
+            ok = launch_blend_bwd_blocks(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles,
+                                         at<uint2>(ws, ws->off_ranges), vals, at<SplatRec>(ws, ws->off_rec),
+                                         at<uint2>(ws, ws->off_rect), koff, cam->width, cam->height, ws->tiles_x, image,
+                                         dL_dimage, at<uint32_t>(ws, ws->off_nproc), sub, fw, (uint32_t)cap,
+                                         (uint32_t)bwd_flag_stride(ws), gk, stream);
+        } else {
+            launch_fill_u32((uint32_t *)gk, 0u, 4 * ws->num_keys, stream);
+            ok = launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges),
+                                  vals, at<SplatRec>(ws, ws->off_rec), at<uint2>(ws, ws->off_rect), koff, cam->width,
+                                  cam->height, ws->tiles_x, image, dL_dimage, at<uint32_t>(ws, ws->off_nproc), gk, stream);
+        }
+        if (!ok) return fail(RECOGS_ERR_UNSUPPORTED, "no backward kernel for this tile / px_per_thread");
     }
     const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
     launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, out,
                        dL_dM, at<float>(ws, ws->off_gpart), all_bands ? scene->sh_degree : -1, scene->means,
                        scene->stride, cd, accumulate, stream, adam ? (float *)scene->sh : nullptr, am, av, adam);
     return hip_check("backward");
+}
+
+size_t recogs_backward_scratch_bytes(const recogs_workspace *ws, const recogs_render_opts *opts) {
+    if (!ws || !opts || !tile_supported(opts->tile_w, opts->tile_h)) return 0;
+    return backward_scratch_bytes(ws, opts);
 }
 
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam, const recogs_render_opts *opts,

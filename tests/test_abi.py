@@ -44,7 +44,8 @@ int main(void) {
   S(recogs_scene) S(recogs_camera) S(recogs_select_params) S(recogs_render_opts) S(recogs_workspace)
   S(recogs_batch_view) S(recogs_batch_workspace)
   O(recogs_render_opts, mask) O(recogs_render_opts, sort_mode) O(recogs_render_opts, depth_map)
-  O(recogs_render_opts, depth_tau) O(recogs_render_opts, extent_rule)
+  O(recogs_render_opts, depth_tau) O(recogs_render_opts, extent_rule) O(recogs_render_opts, bwd_scratch)
+  O(recogs_render_opts, bwd_scratch_bytes)
   O(recogs_workspace, off_rec) O(recogs_workspace, num_keys) O(recogs_workspace, stage_ms)
   O(recogs_workspace, generation)
   O(recogs_batch_workspace, pairs) O(recogs_batch_workspace, off_views) O(recogs_batch_workspace, num_keys)
@@ -82,6 +83,20 @@ class _Ptr:
 
     def data_ptr(self):
         return self.addr
+
+
+class _Buf(_Ptr):
+    """A device byte buffer stand-in: address and size."""
+
+    def __init__(self, addr, nbytes):
+        super().__init__(addr)
+        self.nbytes = nbytes
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
 
 
 def test_host_argument_errors_before_any_launch(R):
@@ -125,6 +140,21 @@ def test_host_argument_errors_before_any_launch(R):
     assert "accumulate" in R.recogs_last_error()
     assert status(B.recogs_render_backward_sh, sc, cam, ok, fake, 8, 8, 8, 8, 8, -1, 0) == -1
     assert status(B.recogs_render_backward, sc, cam, B.opts_struct((16, 16), 1), fake, 8, 8, 8, 8, 8, 0, 0) == -1
+    # the block form's scratch: its size, and a scratch too small or misaligned refused
+    # (per block of a tile: a float4 per key of capacity, 256-byte rounded, then a 16-byte
+    # flag word per 64 keys and per tile, plus two)
+    fake.key_capacity, fake.tiles_x, fake.tiles_y = 1000, 4, 4
+    assert R.recogs_backward_scratch_bytes(fake, B.opts_struct((16, 16), 1)) == 16 * 4 * 1000 + 16 * 4 * (15 + 16 + 2)
+    assert R.recogs_backward_scratch_bytes(fake, B.opts_struct((32, 32), 1)) == 16 * 16 * 1000 + 16 * 16 * (15 + 16 + 2)
+    assert R.recogs_backward_scratch_bytes(fake, B.opts_struct((32, 16), 2)) == 16 * 4 * 1000 + 16 * 4 * (15 + 16 + 2)
+    fake.key_capacity = 1001
+    assert R.recogs_backward_scratch_bytes(fake, B.opts_struct((16, 16), 1)) == 64256 + 16 * 4 * (15 + 16 + 2)
+    assert R.recogs_backward_scratch_bytes(fake, B.opts_struct((32, 8), 2)) == 0   # no block form
+    small = B.opts_struct((16, 16), 1, keep_backward=True, bwd_scratch=_Buf(512, 100))
+    assert status(B.recogs_render_backward, sc, cam, small, fake, 8, 8, 8, 8, 8, 0, 0) == -1
+    assert "bwd_scratch" in R.recogs_last_error()
+    odd = B.opts_struct((16, 16), 1, keep_backward=True, bwd_scratch=_Buf(520, 1 << 20))
+    assert status(B.recogs_render_backward, sc, cam, odd, fake, 8, 8, 8, 8, 8, 0, 0) == -1
     # rough depth map: threshold outside (0, 1], a tile form without one wave per region
     dep = 64  # any non-NULL device address: the options are refused before any launch
     assert status(B.recogs_render, sc, cam, B.opts_struct((16, 16), 1, depth=_Ptr(dep), depth_tau=0.0), ws, 1, 0) == -1

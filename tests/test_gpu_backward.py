@@ -40,7 +40,9 @@ def _setup(R, orc, w, g_seed=21):
     return d, ws, tm, tM, tb, mask, M, b, g
 
 
-def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1):
+def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1, blocks=False):
+    """Render keeping the backward state, then recogs_render_backward; blocks: the
+    backward's block form (one wave per 8 x 8 ppt block, with its scratch)."""
     import torch
     img = R.render(d, cam, ws, tile, ppt, mask=tm, M=tM, b=tb, keep_backward=True)
     gt = torch.from_numpy(g).cuda()
@@ -48,7 +50,9 @@ def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1):
     dop = torch.empty(n, device="cuda")
     ddc = torch.empty((3, n), device="cuda")
     dM = torch.empty(9, device="cuda")
-    o = R.opts_struct(tile, ppt, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    scratch = ws.backward_scratch(tile, ppt) if blocks else None
+    assert (scratch is not None) == blocks
+    o = R.opts_struct(tile, ppt, (0, 0, 0), tm, tM, tb, keep_backward=True, bwd_scratch=scratch)
     R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
                              dop.data_ptr(), ddc.data_ptr(), dM.data_ptr())
     torch.cuda.synchronize()
@@ -70,8 +74,12 @@ def _close(got, ref, what, abs_of_max=GRAD_ABS, rel=GRAD_REL):
     return float(err.max() / scale)
 
 
-@pytest.mark.parametrize("tile,ppt", [((16, 16), 1), ((8, 8), 2), ((32, 8), 4), ((32, 32), 2), ((32, 16), 1)])
-def test_backward_vs_oracle(R, orc, tile, ppt):
+@pytest.mark.parametrize("tile,ppt,blocks", [((16, 16), 1, False), ((8, 8), 2, False), ((32, 8), 4, False),
+                                             ((32, 32), 2, False), ((32, 16), 1, False), ((16, 16), 1, True),
+                                             ((16, 16), 2, True), ((8, 8), 1, True), ((32, 8), 1, True),
+                                             ((32, 16), 1, True), ((32, 16), 2, True), ((32, 32), 1, True),
+                                             ((32, 32), 4, True)])
+def test_backward_vs_oracle(R, orc, tile, ppt, blocks):
     w = _wfd()
     cam = w.view.camera
     d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
@@ -81,13 +89,41 @@ def test_backward_vs_oracle(R, orc, tile, ppt):
     g = np.where((ref.slack > 0)[..., None], 0.0, g).astype(np.float32)
     assert (ref.slack > 0).mean() < 0.02
     d_ws = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
-    img, dop, ddc, dM = _gpu_grads(R, d, d_ws, cam, tm, tM, tb, g, tile, ppt)
+    img, dop, ddc, dM = _gpu_grads(R, d, d_ws, cam, tm, tM, tb, g, tile, ppt, blocks)
     gr = orc.backward(pr, g, M=M.astype(np.float64))
     e1 = _close(dop, gr.dsigma, "dL/dopacity")
     e2 = _close(ddc, gr.dc0, "dL/dC0")
     e3 = _close(dM, gr.dM, "dL/dM")
     assert mask.sum() > 0 and np.abs(gr.dM).max() > 0
     print(f"relative max errors: dsigma {e1:.2e} dC0 {e2:.2e} dM {e3:.2e}")
+
+
+def test_block_form_backward_is_deterministic_and_matches_the_tile_form(R, orc):
+    """The block form sums each (Gaussian, tile) gradient's block parts in a fixed order:
+    two runs give the same bits; against the tile form it differs by float32 summation
+    order only."""
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    for tile in [(16, 16), (32, 32)]:
+        wsx = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
+        a = _gpu_grads(R, d, wsx, cam, tm, tM, tb, g, tile, 1, blocks=True)
+        c = _gpu_grads(R, d, wsx, cam, tm, tM, tb, g, tile, 1, blocks=True)
+        t = _gpu_grads(R, d, wsx, cam, tm, tM, tb, g, tile, 1, blocks=False)
+        for x, y, z in zip(a[1:], c[1:], t[1:]):
+            assert np.array_equal(x, y)
+            scale = np.abs(z).max()
+            assert np.all(np.abs(x - z) <= 1e-5 * scale + 1e-5 * np.abs(z))
+    # a scratch of too few bytes is refused
+    import torch
+    o = R.opts_struct((16, 16), 1, (0, 0, 0), tm, tM, tb, keep_backward=True,
+                      bwd_scratch=torch.empty(256, dtype=torch.uint8, device="cuda"))
+    img = R.render(d, cam, ws, mask=tm, M=tM, b=tb, keep_backward=True)
+    buf = [torch.empty(d.n, device="cuda"), torch.empty((3, d.n), device="cuda"), torch.empty(9, device="cuda")]
+    with pytest.raises(R.RecogsError) as e:
+        R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), img.data_ptr(),
+                                 buf[0].data_ptr(), buf[1].data_ptr(), buf[2].data_ptr())
+    assert e.value.status == -1
 
 
 def test_backward_is_deterministic_and_repeatable(R, orc):
@@ -246,14 +282,14 @@ def test_backward_full_size_on_windows_vs_oracle(R, orc):
     tm = torch.from_numpy(mask).cuda()
     tM = torch.from_numpy(v.recolor.M.reshape(9).copy()).cuda()
     tb = torch.from_numpy(v.recolor.b.copy()).cuda()
-    img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (32, 16), 1)
+    img, dop, ddc, dM = _gpu_grads(R, d, ws, cam, tm, tM, tb, g, (32, 16), 1, blocks=True)
     e1 = _close(dop, gr.dsigma, "dL/dopacity")
     e2 = _close(ddc, gr.dc0, "dL/dC0")
     e3 = _close(dM, gr.dM, "dL/dM")
     assert np.abs(gr.dsigma).max() > 0 and np.abs(gr.dM).max() > 0
     # every SH coefficient, on the Gaussians the windows reach
     K = (sc.sh_degree + 1) ** 2
-    o = R.opts_struct((32, 16), 1, (0, 0, 0), tm, tM, tb, keep_backward=True)
+    o = R.opts_struct((32, 16), 1, (0, 0, 0), tm, tM, tb, keep_backward=True, bwd_scratch=ws.backward_scratch((32, 16), 1))
     gt = torch.from_numpy(g).cuda()
     dsh = torch.zeros((3 * K, d.stride), device="cuda")
     t1, t9 = torch.empty(sc.n, device="cuda"), torch.empty(9, device="cuda")
@@ -423,7 +459,7 @@ def test_backward_full_size_eight_views_accumulated(R, orc):
         ref[2] += gr.dM
         ws = R.DeviceWorkspace(n, cam.width, cam.height, tile)
         img = R.render(d, cam, ws, tile, 1, mask=tm, M=tM, b=tb, keep_backward=True)
-        o = R.opts_struct(tile, 1, (0, 0, 0), tm, tM, tb, keep_backward=True)
+        o = R.opts_struct(tile, 1, (0, 0, 0), tm, tM, tb, keep_backward=True, bwd_scratch=ws.backward_scratch(tile, 1))
         gt = torch.from_numpy(g).cuda()
         R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), gt.data_ptr(),
                                  acc[0].data_ptr(), acc[1].data_ptr(), acc[2].data_ptr(), 1 if k else 0)
