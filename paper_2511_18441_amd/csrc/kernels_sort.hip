@@ -78,7 +78,8 @@ __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, ui
     if (t <= dmask) cnt[(size_t)t * chunks + blockIdx.x] = h[t];
 }
 
-// workgroup d: cnt[d][c] <- sum_{c' < c} cnt[d][c'];  tot[d] <- sum_c cnt[d][c]
+// workgroup d: cnt[d][c] <- sum_{c' < c} cnt[d][c'];  tot[d] <- sum_c cnt[d][c].
+// Four counts per thread, so a row of up to 1,024 chunks is one round of loads.
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks, uint32_t chunk_keys,
                                                        uint32_t *__restrict__ tot, uint32_t K,
                                                        const uint32_t *dyn_count) {
@@ -88,11 +89,20 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cn
     const uint32_t d = blockIdx.x, t = threadIdx.x;
     uint32_t run = 0, total;
     uint32_t *row = cnt + (size_t)d * chunks;
-    for (uint32_t c0 = 0; c0 < live; c0 += 256) {
-        const uint32_t c = c0 + t;
-        const uint32_t v = c < live ? row[c] : 0u;
-        const uint32_t e = block_excl_scan256(v, s_w, total);
-        if (c < live) row[c] = run + e;
+    for (uint32_t c0 = 0; c0 < live; c0 += 1024) {
+        const uint32_t c = c0 + 4 * t;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = c + i < live ? row[c + i] : 0u;
+            sum += v[i];
+        }
+        uint32_t e = run + block_excl_scan256(sum, s_w, total);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (c + i < live) row[c + i] = e;
+            e += v[i];
+        }
         run += total;
     }
     if (t == 0) tot[d] = run;
