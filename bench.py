@@ -41,6 +41,7 @@ BLEND_FLOPS_PER_EVAL = 23        # dx, dy, exponent (2 mul + 3 fma), test, exp2,
 SORT_MODE = 0                    # (tile, depth, index) order: 0 depth-first, 2 tile-first; --sort-mode
 BWD_FORM = "tile"                # the backward: "tile" (one workgroup per tile) or "block" (a wave per 8x8 block)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.sq.txt")
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
 
@@ -71,6 +72,23 @@ def recorded_traffic(kernel, tile, ppt):
     try:
         return int(float(kv["traffic_bytes_per_launch"]))
     except (KeyError, ValueError):
+        return None
+
+
+def recorded_sq(kernel, tile, ppt):
+    """The blend's shader-instruction counters per launch from the committed rocprof
+    summary ({name: value}), or None when there is none or the blend sources changed."""
+    try:
+        kv = dict(l.split(":", 1) for l in open(SQ_FILE.format(tw=tile[0], th=tile[1], ppt=ppt)).read().splitlines()
+                  if ":" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("blend_sources_sha1") != blend_source_sha1():
+        return None
+    try:
+        return {k: int(float(v)) for k, v in kv.items() if k not in ("kernel", "blend_sources_sha1")}
+    except ValueError:
         return None
 
 
@@ -779,8 +797,19 @@ def main():
                 "avg_launch_ms": round(avg, 4), "launches_timed": m["profiled_frames"],
                 "work_per_launch": f"{st['evals']} pixel-splat evaluations (16x16-tile lists) x "
                                    f"{BLEND_FLOPS_PER_EVAL} flops",
+                "achieved_is": "nominal: the 16x16-tile-list work of the reference rasteriser over the measured time",
                 "alg_bytes_per_launch": int(bytes_["blend"]),
                 "hbm_GBps_alg": round(bytes_["blend"] / (avg * 1e-3) / 1e9, 1)}
+        sq = recorded_sq(kname, tile, args.ppt) if args.storage == "f32" else None
+        if sq and "executed_evals_max" in sq:
+            # the evaluations the region waves actually execute (64 pixels per wave step,
+            # wave steps bounded by the LDS instruction count), from the committed counters
+            ex = sq["executed_evals_max"]
+            roof["executed_evals_max"] = ex
+            roof["achieved_executed_max"] = round(ex * BLEND_FLOPS_PER_EVAL / (avg * 1e-3) / 1e12, 3)
+            roof["valu_insts_per_launch"] = sq.get("sq_insts_valu")
+        else:
+            roof["executed_evals_max"] = None
     else:
         ach = bytes_[dom] / nl / (avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
