@@ -17,7 +17,7 @@ GPU: FP16 and BF16 storage of the same scene, the batched form (8 scenes of 0.1M
 Gaussians x 4 views, one HIP-graph replay per batch, tile shape and pixels per thread
 from the autotuner; beside it the same 32 renders one call at a time), and the
 differentiation form (8 views at 1280x720: forward, L2 loss and backward), the SH refit
-(eq. 7 loss, Adam), the pixel-selection chain (rough depth map, unprojection, outlier
+(eq. 4 loss and its gradient, eq. 7; Adam), the pixel-selection chain (rough depth map, unprojection, outlier
 removal, reprojection, tint) and the selection-driven edit loop of Sec. 3.3.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|bf16]
@@ -421,7 +421,7 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
 def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     """SH-only refitting (the background optimiser, Sec. 3.3): 1M Gaussians (FP32, SH 3),
     the 8 views at 1280x720 taken in turn, one per step: render keeping the backward
-    state, the loss of eq. 7 (0.8 L1 + 0.2 (1 - SSIM)) against the view recoloured by the
+    state, the loss of eq. 4 (0.8 L1 + 0.2 (1 - SSIM)) against the view recoloured by the
     target matrix (plus seeded noise), the gradient of every SH coefficient, one Adam
     step on all of them."""
     import torch
@@ -604,7 +604,7 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     rendered. Per step (one view, in turn): render the current SH keeping the backward
     state and the rough depth map, draw the cloud into the view as its mask (2 px squares,
     depth test with 1% slack), tint the view's original image there (t = (1, 0.6, 0.5)),
-    the loss of eq. 7 against it, the gradient of every SH coefficient and one Adam step,
+    the loss of eq. 4 against it, the gradient of every SH coefficient and one Adam step,
     fused (the gradient goes straight into the update, never to memory)."""
     import torch
 

@@ -305,7 +305,7 @@ def loss_l2_grad(y, target, count: Optional[int] = None) -> np.ndarray:
 
 
 def loss_l1(y, target) -> float:
-    """L1 = mean over all pixels and channels of |y - t| (the L1 term of eq. 7)."""
+    """L1 = mean over all pixels and channels of |y - t| (the L1 term of eq. 4; its gradient is in eq. 7)."""
     return float(np.mean(np.abs(np.asarray(y, np.float64) - np.asarray(target, np.float64))))
 
 
@@ -354,7 +354,7 @@ def _blur(a: np.ndarray) -> np.ndarray:
 
 def ssim(y, target):
     """Mean SSIM over all pixels and channels of two (H, W, 3) images (the SSIM term of
-    eq. 7): per channel, local means, variances and covariance under the 11 x 11 Gaussian
+    eq. 4): per channel, local means, variances and covariance under the 11 x 11 Gaussian
     window (zero padding), S = (2 mu_y mu_t + C1)(2 s_yt + C2) / ((mu_y^2 + mu_t^2 + C1)
     (s_y^2 + s_t^2 + C2)) with C1 = 0.01^2, C2 = 0.03^2. Returns (value, dSSIM/dy).
     The gradient: S depends on y through mu_y = G*y, E_yy = G*(y^2) and E_yt = G*(y t),

@@ -17,7 +17,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # hardware float atomics for the backward's gradient accumulation
+    # hardware float atomics for the loss kernels' scalar sums (each workgroup adds its
+    # partial loss once; the gradients use no float atomics)
     "-munsafe-fp-atomics",
     "-Wno-unused-command-line-argument",
 ]

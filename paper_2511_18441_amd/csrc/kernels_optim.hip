@@ -1,5 +1,5 @@
 // Pieces of the background optimiser (Sec. 3.3 / 4.1): the L1 and SSIM terms of the
-// loss of eq. 7 with their gradients, and the Adam step that moves the SH coefficients.
+// loss of eq. 4 with their gradients (eq. 7), and the Adam step that moves the SH coefficients.
 #include <cmath>
 #include <cstring>
 
@@ -105,7 +105,7 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, fl
 }
 
 // ---------------------------------------------------------------------------
-// SSIM term of eq. 7 over HWC float images, per channel, with the 11 x 11 Gaussian
+// SSIM term of eq. 4 over HWC float images, per channel, with the 11 x 11 Gaussian
 // window (sigma 1.5, zero outside the image): local means, variances and covariance
 // are separable blurs; S = (2 mu_y mu_t + C1)(2 s_yt + C2) / ((mu_y^2 + mu_t^2 + C1)
 // (s_y^2 + s_t^2 + C2)). Its gradient: S depends on y through mu_y = G*y, E_yy = G*(y^2)

@@ -1,5 +1,5 @@
 """Pieces of the background optimiser (Sec. 3.3 / 4.1) through the C ABI: the gradient
-of every SH coefficient, the L1 and SSIM terms of eq. 7 and the Adam step, against the FP64
+of every SH coefficient, the L1 and SSIM terms of eq. 4 and the Adam step, against the FP64
 oracle (pinned on the CPU by central differences and closed forms); then a few steps of
 SH-only refitting toward a recoloured target, which must lower the loss."""
 import numpy as np
@@ -116,7 +116,7 @@ def test_loss_l1_vs_oracle(R, orc):
 
 @pytest.mark.parametrize("H,W", [(72, 128), (37, 50)])
 def test_dssim_vs_oracle(R, orc, H, W):
-    """The SSIM term of eq. 7 and its gradient (written, then accumulated onto an L1
+    """The SSIM term of eq. 4 and its gradient (written, then accumulated onto an L1
     gradient as eq. 7 combines them), on images whose size is not a multiple of the
     kernels' 16 x 16 tiles."""
     import torch
@@ -133,7 +133,7 @@ def test_dssim_vs_oracle(R, orc, H, W):
     val, g = orc.ssim(y, t)
     assert abs(loss.item() - lam * (1.0 - val)) <= 1e-5
     e = _close(dl.cpu().numpy().astype(np.float64), -lam * g, "dL/dy (SSIM)")
-    # eq. 7: (1 - lambda) L1 + lambda (1 - SSIM), the SSIM gradient added to the L1 one
+    # eq. 4: (1 - lambda) L1 + lambda (1 - SSIM); eq. 7: the SSIM gradient added to the L1 one
     n = y.size
     l1 = torch.empty(1, device="cuda")
     R.recogs_loss_l1(ty.data_ptr(), tt.data_ptr(), n, (1 - lam) / n, dl.data_ptr(), l1.data_ptr())
@@ -193,7 +193,7 @@ def test_adam_vs_oracle(R, orc):
 def test_sh_refit_lowers_the_l1_loss(R, orc):
     """SH-only refitting (geometry frozen, Sec. 3.3): the target is the same view with
     the selection recoloured by another matrix; Adam steps on the SH coefficients
-    driven by the loss of eq. 7 must bring the render toward it (L1 distance tracked)."""
+    driven by the loss of eq. 4 must bring the render toward it (L1 distance tracked)."""
     import torch
     w = _wfd()
     cam = w.view.camera
@@ -214,7 +214,7 @@ def test_sh_refit_lowers_the_l1_loss(R, orc):
     ls = torch.empty(1, device="cuda")
     for step in range(1, 31):
         img = R.render(d, cam, ws, keep_backward=True, sh=sh)
-        # eq. 7: (1 - lambda) L1 + lambda (1 - SSIM)
+        # eq. 4: (1 - lambda) L1 + lambda (1 - SSIM)
         R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt, 1.0 / cnt, dl.data_ptr(), loss.data_ptr())
         R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt, (1 - lam) / cnt, dl.data_ptr(), ls.data_ptr())
         R.recogs_loss_dssim(img.data_ptr(), target.data_ptr(), cam.width, cam.height, lam, dl.data_ptr(), 1,

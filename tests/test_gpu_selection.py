@@ -249,7 +249,7 @@ def test_edit_loop_moves_the_render_toward_the_tinted_views(R):
     tiny scene: a brush selection in view A, lifted with A's rough depth and cleaned;
     in turn for views A and B, the current SH rendered with its rough depth, the cloud
     drawn into the view as its mask, the original image tinted there as the target,
-    eq. 7's loss, the all-band backward and an Adam step. The L1 distance to the
+    eq. 4's loss, the all-band backward and an Adam step. The L1 distance to the
     targets must fall, and the masks must not be empty."""
     import torch
     w = synth.make_tiny()

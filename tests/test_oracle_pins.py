@@ -540,7 +540,7 @@ def test_loss_gradient_definition(orc):
 
 
 # ---------------------------------------------------------------------------
-# background optimiser pieces (Sec. 3.3 / 4.1): L1 term of eq. 7, gradients of every
+# background optimiser pieces (Sec. 3.3 / 4.1): L1 term of eq. 4, gradients of every
 # SH band (eq. 2 is linear in the coefficients), the Adam step
 # ---------------------------------------------------------------------------
 def test_sh_grad_matches_central_differences(orc):
@@ -613,7 +613,7 @@ def test_adam_closed_forms(orc):
 
 
 def test_ssim_against_brute_force_windows(orc):
-    """The SSIM term of eq. 7 against a direct evaluation: for every pixel and channel,
+    """The SSIM term of eq. 4 against a direct evaluation: for every pixel and channel,
     explicit 11 x 11 window sums with weights g_i g_j (zero outside the image)."""
     rng = np.random.default_rng(4)
     H, W = 6, 7
