@@ -34,8 +34,12 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
     using Map = TileMap<TW, TH, PPT>;
     constexpr int NT = Map::NT;
     constexpr int NW = (NT + 63) / 64;
-    constexpr int BATCH = kBlendBatch;
-    __shared__ BlendStage sm;   // BlendRec.pad holds the (Gaussian, tile) slot, rgb.w the opacity
+    // records staged per batch: 256 where the workgroup has a thread for each (half the
+    // barriers of 128; the LDS, 44 KB, still fits the three workgroups per CU that the
+    // registers allow)
+    constexpr int BATCH = NT >= 256 ? 256 : kBlendBatch;
+    struct Stage { BlendRec r[BATCH]; };
+    __shared__ Stage sm;   // BlendRec.pad holds the (Gaussian, tile) slot, rgb.w the opacity
     __shared__ float4 s_acc[NW][BATCH];
     const int tile = blockIdx.x;
     const uint32_t tcx = (uint32_t)(tile % tiles_x), tcy = (uint32_t)(tile / tiles_x);
@@ -72,27 +76,56 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
     for (int j = 0; j < PPT; ++j) npmax = max(npmax, np[j]);
 
     const uint2 rg = ranges[tile];
+    // With a thread per staged record (NT >= BATCH), the records of batch b + 1, their
+    // tile rectangles and key offsets are loaded into registers while batch b is
+    // replayed, so the dependent list -> record loads are off the critical path.
+    constexpr bool PIPE = NT >= BATCH;
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0, f2 = f0;
+    uint2 frc = make_uint2(0u, 0u);
+    uint32_t fko = 0;
+    auto fetch = [&](uint32_t start) {
+        const uint32_t k = start + (uint32_t)t;
+        if (t < BATCH && k < rg.y) {
+            const uint32_t gid = vals[k];
+            const SplatRec *sp = rec + gid;
+            f0 = sp->r0; f1 = sp->r1; f2 = sp->r2;
+            frc = rect[gid];
+            fko = koff[gid];
+        }
+    };
+    auto stage = [&](int q, float4 r0, float4 r1, float4 r2, uint2 rc, uint32_t ko) {
+        const uint32_t rx0 = rc.x & 0xffffu, rx1 = rc.x >> 16, ry0 = rc.y & 0xffffu;
+        BlendRec b;
+        b.uv = make_float2(r0.x, r0.y);
+        b.mask = Map::wave_mask(r0, r1, (float)tx0, (float)ty0);
+        b.pad = ko + (tcy - ry0) * (rx1 - rx0 + 1) + (tcx - rx0);
+        b.r1 = r1;
+        b.rgb = r2;
+        sm.r[q] = b;
+    };
+    if constexpr (PIPE) fetch(rg.x);
     for (uint32_t start = rg.x; start < rg.y; start += BATCH) {
         if (__syncthreads_and(start - rg.x >= npmax)) break;
-        for (int q = t; q < BATCH; q += NT) {
-            const uint32_t k = start + q;
-            if (k < rg.y) {
-                const uint32_t gid = vals[k];
-                const SplatRec s = rec[gid];
-                const uint2 rc = rect[gid];
-                const uint32_t rx0 = rc.x & 0xffffu, rx1 = rc.x >> 16, ry0 = rc.y & 0xffffu;
-                BlendRec b;
-                b.uv = make_float2(s.r0.x, s.r0.y);
-                b.mask = Map::wave_mask(s.r0, s.r1, (float)tx0, (float)ty0);
-                b.pad = koff[gid] + (tcy - ry0) * (rx1 - rx0 + 1) + (tcx - rx0);
-                b.r1 = s.r1;
-                b.rgb = s.r2;
-                sm.r[q] = b;
-            }
+        if constexpr (PIPE) {
+            if (t < BATCH) {
+                if (start + (uint32_t)t < rg.y) stage(t, f0, f1, f2, frc, fko);
 #pragma unroll
-            for (int ww = 0; ww < NW; ++ww) s_acc[ww][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int ww = 0; ww < NW; ++ww) s_acc[ww][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        } else {
+            for (int q = t; q < BATCH; q += NT) {
+                const uint32_t k = start + q;
+                if (k < rg.y) {
+                    const uint32_t gid = vals[k];
+                    const SplatRec sp = rec[gid];
+                    stage(q, sp.r0, sp.r1, sp.r2, rect[gid], koff[gid]);
+                }
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) s_acc[ww][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         __syncthreads();
+        if constexpr (PIPE) fetch(start + BATCH);
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
         // the batch's records this wave takes (scalar bit sets), walked in order while
         // some pixel of the wave still replays
