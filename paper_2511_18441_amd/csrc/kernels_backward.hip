@@ -439,8 +439,17 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         uint32_t flags = 0;
         const uint32_t c = count[i];
         if (c > 0) {
+            // the Gaussian's (Gaussian, tile) slots, added in order; four loads in flight
             const float4 *slot = gk + koff[i];
-            for (uint32_t k = 0; k < c; ++k) {  // the Gaussian's (Gaussian, tile) slots, in order
+            uint32_t k = 0;
+            for (; k + 4u <= c; k += 4u) {
+                const float4 x0 = slot[k], x1 = slot[k + 1], x2 = slot[k + 2], x3 = slot[k + 3];
+                a.x += x0.x; a.y += x0.y; a.z += x0.z; a.w += x0.w;
+                a.x += x1.x; a.y += x1.y; a.z += x1.z; a.w += x1.w;
+                a.x += x2.x; a.y += x2.y; a.z += x2.z; a.w += x2.w;
+                a.x += x3.x; a.y += x3.y; a.z += x3.z; a.w += x3.w;
+            }
+            for (; k < c; ++k) {
                 const float4 x = slot[k];
                 a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
             }
