@@ -156,7 +156,10 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const float4 h = br[0], r1 = br[1], r2 = br[2];
                 const float2 uv = make_float2(h.x, h.y);
                 // 1 / sigma to about 1 ulp: it only scales this splat's opacity gradient
-                const float inv_sigma = __builtin_amdgcn_rcpf(r2.w);
+                float inv_sigma = __builtin_amdgcn_rcpf(r2.w);
+                // here, not sunk into the branch below: the record's last 16 bytes then
+                // come in one LDS read with the rest, not a second read and wait
+                asm volatile("" : "+v"(inv_sigma));
                 const ExpRow er = exp_row(r1, pxc - uv.x);
                 float ds, dr, dg, db;
                 bool any = false;
