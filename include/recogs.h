@@ -306,7 +306,7 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
                                      float *dL_dsh_dc, float *dL_dM, int32_t accumulate, hipStream_t stream);
 
 /* L2 loss of an image against a target (the differentiable form's loss, an analog of
- * eq. 7): loss (device float, overwritten) = scale * sum (y - t)^2 and
+ * eq. 4 with its gradient, eq. 7): loss (device float, overwritten) = scale * sum (y - t)^2 and
  * dL_dimage = 2 scale (y - t), over `count` floats. scale = 1 / count gives the mean. */
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
@@ -330,14 +330,14 @@ recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_
                                         const float *image, const float *dL_dimage, float *dL_dopacity,
                                         float *dL_dsh, float *dL_dM, int32_t accumulate, hipStream_t stream);
 
-/* L1 term of the loss of eq. 7, with the gradient Sec. 4.1 writes out:
+/* L1 term of the loss of eq. 4, with the gradient Sec. 4.1 writes out (eq. 7):
  * loss (device float, overwritten) = scale * sum |y - t| and
  * dL_dimage = scale * sign(y - t) (sign(0) = 0), over `count` floats; scale = 1 / count
  * gives the mean. Device pointers of any alignment. INVALID: count < 0, NULL pointer. */
 recogs_status recogs_loss_l1(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
-/* SSIM term of eq. 7, lambda (1 - SSIM), over two HWC float images [height][width][3]:
+/* SSIM term of eq. 4, lambda (1 - SSIM), over two HWC float images [height][width][3]:
  * per channel, local means, variances and covariance under the 11 x 11 Gaussian window
  * (sigma 1.5, zero outside the image), S = (2 mu_y mu_t + C1)(2 s_yt + C2) /
  * ((mu_y^2 + mu_t^2 + C1)(s_y^2 + s_t^2 + C2)), C1 = 0.01^2, C2 = 0.03^2, averaged over
@@ -345,7 +345,9 @@ recogs_status recogs_loss_l1(const float *image, const float *target, int64_t co
  * dL_dimage = -weight dSSIM/dimage, written (accumulate 0) or added (accumulate 1, so
  * that eq. 7 is recogs_loss_l1 with scale (1 - lambda) / count, then this with weight
  * lambda). workspace: device scratch of recogs_dssim_workspace_bytes (9 floats per
- * pixel), 4-byte aligned. INVALID: bad size, flag, pointer or workspace. */
+ * pixel, then 3 per 16 x 16 tile of the image), 4-byte aligned. The loss is summed in a
+ * fixed order (the same bits on every run). INVALID: bad size, flag, pointer or
+ * workspace. */
 size_t recogs_dssim_workspace_bytes(int32_t width, int32_t height);
 recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t width, int32_t height, float weight,
                                 float *dL_dimage, int32_t accumulate, float *loss, void *workspace,

@@ -110,10 +110,12 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, fl
 // are separable blurs; S = (2 mu_y mu_t + C1)(2 s_yt + C2) / ((mu_y^2 + mu_t^2 + C1)
 // (s_y^2 + s_t^2 + C2)). Its gradient: S depends on y through mu_y = G*y, E_yy = G*(y^2)
 // and E_yt = G*(y t), so dS/dy = G*a + 2 y (G*b) + t (G*c) with a, b, c the partial
-// derivatives of S in those maps. Two passes, each a 16 x 16 output tile per
-// workgroup with its 26 x 26 input halo in LDS, blurred along x then along y:
-//   k_ssim_fwd: the three maps a, b, c per pixel and channel, and the sum of S;
-//   k_ssim_bwd: the blurs of a, b, c and the gradient.
+// derivatives of S in those maps. Two passes over 16 x 16 output tiles, each with its
+// 26 x 26 input halo in LDS, blurred along x then along y:
+//   k_ssim_fwd: a workgroup per (tile, channel): the three maps a, b, c per pixel and
+//               the tile's sum of S (k_ssim_loss adds the sums in a fixed order);
+//   k_ssim_bwd: a workgroup per tile, the channels in turn: the blurs of a, b, c and the
+//               gradient.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kSsimR = 5;                     // window radius (11 taps)
@@ -124,77 +126,91 @@ constexpr float kSsimC1 = 0.01f * 0.01f, kSsimC2 = 0.03f * 0.03f;
 
 struct SsimWindow { float g[2 * kSsimR + 1]; };
 
-// loads the halo tile of a planar map [H][W] (zero outside the image) into s[26][26]
-__device__ __forceinline__ void ssim_load_plane(const float *__restrict__ m, int W, int H, int ox, int oy, float *s) {
-    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
-        const int x = ox + k % kSsimH - kSsimR, y = oy + k / kSsimH - kSsimR;
-        s[k] = (x >= 0 && x < W && y >= 0 && y < H) ? m[(int64_t)y * W + x] : 0.f;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
-                                                  SsimWindow win, float *__restrict__ maps, float *__restrict__ loss,
-                                                  float neg_scale) {
-    __shared__ float s_y[3][kSsimH * kSsimH], s_t[3][kSsimH * kSsimH];
+                                                  SsimWindow win, float *__restrict__ maps, float *__restrict__ part) {
+    __shared__ float s_y[kSsimH * kSsimH], s_t[kSsimH * kSsimH];
     __shared__ float s_h[5][kSsimH][kSsimT];   // x-blurred y, t, y^2, t^2, y t
     __shared__ float s_w[4];
+    const int c = blockIdx.z;   // the channel: one workgroup per (tile, channel)
     const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
     const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
     const int px = ox + tx, py = oy + ty;
     const int64_t HW = (int64_t)W * H;
-    float ssum = 0.f;
-    // the halo tiles of both images, all three channels of a pixel read together (12
-    // contiguous bytes of the HWC image), zero outside the image
-    for (int k = threadIdx.x; k < kSsimH * kSsimH; k += 256) {
-        const int x = ox + k % kSsimH - kSsimR, yy = oy + k / kSsimH - kSsimR;
-        const bool in = x >= 0 && x < W && yy >= 0 && yy < H;
-        const int64_t q = ((int64_t)yy * W + x) * 3;
+    // the channel's halo tiles of both images (zero outside the image); every load of the
+    // thread is issued before the first LDS store, so the tile costs one memory round trip
+    constexpr int NL = (kSsimH * kSsimH + 255) / 256;
+    float ly[NL], lt[NL];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            s_y[c][k] = in ? y[q + c] : 0.f;
-            s_t[c][k] = in ? t[q + c] : 0.f;
+    for (int i = 0; i < NL; ++i) {
+        const int k = (int)threadIdx.x + 256 * i;
+        const int x = ox + k % kSsimH - kSsimR, yy = oy + k / kSsimH - kSsimR;
+        const bool in = k < kSsimH * kSsimH && x >= 0 && x < W && yy >= 0 && yy < H;
+        const int64_t q = in ? ((int64_t)yy * W + x) * 3 + c : 0;
+        ly[i] = in ? y[q] : 0.f;
+        lt[i] = in ? t[q] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int k = (int)threadIdx.x + 256 * i;
+        if (k < kSsimH * kSsimH) {
+            s_y[k] = ly[i];
+            s_t[k] = lt[i];
         }
     }
-    for (int c = 0; c < 3; ++c) {
-        __syncthreads();   // the tiles loaded; the previous channel's s_h reads done
-        for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
-            const int r = k / kSsimT, cx = k % kSsimT;
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
-#pragma unroll
-            for (int j = 0; j <= 2 * kSsimR; ++j) {
-                const float u = s_y[c][r * kSsimH + cx + j], v = s_t[c][r * kSsimH + cx + j], g = win.g[j];
-                a0 += g * u; a1 += g * v; a2 += g * (u * u); a3 += g * (v * v); a4 += g * (u * v);
-            }
-            s_h[0][r][cx] = a0; s_h[1][r][cx] = a1; s_h[2][r][cx] = a2; s_h[3][r][cx] = a3; s_h[4][r][cx] = a4;
-        }
-        __syncthreads();
-        float my = 0.f, mt = 0.f, eyy = 0.f, ett = 0.f, eyt = 0.f;
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
+        const int r = k / kSsimT, cx = k % kSsimT;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
 #pragma unroll
         for (int j = 0; j <= 2 * kSsimR; ++j) {
-            const float g = win.g[j];
-            my += g * s_h[0][ty + j][tx]; mt += g * s_h[1][ty + j][tx];
-            eyy += g * s_h[2][ty + j][tx]; ett += g * s_h[3][ty + j][tx]; eyt += g * s_h[4][ty + j][tx];
+            const float u = s_y[r * kSsimH + cx + j], v = s_t[r * kSsimH + cx + j], g = win.g[j];
+            a0 += g * u; a1 += g * v; a2 += g * (u * u); a3 += g * (v * v); a4 += g * (u * v);
         }
-        if (px < W && py < H) {
-            const float syy = eyy - my * my, stt = ett - mt * mt, syt = eyt - my * mt;
-            const float l1 = 2.f * my * mt + kSsimC1, l2 = my * my + mt * mt + kSsimC1;
-            const float c1 = 2.f * syt + kSsimC2, c2 = syy + stt + kSsimC2;
-            const float il2c2 = 1.f / (l2 * c2);
-            const float S = l1 * c1 * il2c2;
-            const float dS_dsyt = 2.f * l1 * il2c2;
-            const float dS_dsyy = -S / c2;
-            const float dS_dmy = 2.f * mt * c1 * il2c2 - S * 2.f * my / l2;
-            const int64_t p = (int64_t)py * W + px;
-            maps[(3 * c + 0) * HW + p] = dS_dmy - 2.f * my * dS_dsyy - mt * dS_dsyt;   // a
-            maps[(3 * c + 1) * HW + p] = dS_dsyy;                                    // b
-            maps[(3 * c + 2) * HW + p] = dS_dsyt;                                    // c
-            ssum += S;
-        }
+        s_h[0][r][cx] = a0; s_h[1][r][cx] = a1; s_h[2][r][cx] = a2; s_h[3][r][cx] = a3; s_h[4][r][cx] = a4;
+    }
+    __syncthreads();
+    float my = 0.f, mt = 0.f, eyy = 0.f, ett = 0.f, eyt = 0.f;
+#pragma unroll
+    for (int j = 0; j <= 2 * kSsimR; ++j) {
+        const float g = win.g[j];
+        my += g * s_h[0][ty + j][tx]; mt += g * s_h[1][ty + j][tx];
+        eyy += g * s_h[2][ty + j][tx]; ett += g * s_h[3][ty + j][tx]; eyt += g * s_h[4][ty + j][tx];
+    }
+    float ssum = 0.f;
+    if (px < W && py < H) {
+        const float syy = eyy - my * my, stt = ett - mt * mt, syt = eyt - my * mt;
+        const float l1 = 2.f * my * mt + kSsimC1, l2 = my * my + mt * mt + kSsimC1;
+        const float c1 = 2.f * syt + kSsimC2, c2 = syy + stt + kSsimC2;
+        const float il2c2 = 1.f / (l2 * c2);
+        const float S = l1 * c1 * il2c2;
+        const float dS_dsyt = 2.f * l1 * il2c2;
+        const float dS_dsyy = -S / c2;
+        const float dS_dmy = 2.f * mt * c1 * il2c2 - S * 2.f * my / l2;
+        const int64_t p = (int64_t)py * W + px;
+        maps[(3 * c + 0) * HW + p] = dS_dmy - 2.f * my * dS_dsyy - mt * dS_dsyt;   // a
+        maps[(3 * c + 1) * HW + p] = dS_dsyy;                                    // b
+        maps[(3 * c + 2) * HW + p] = dS_dsyt;                                    // c
+        ssum = S;
     }
     ssum = wave_sum(ssum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = ssum;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, neg_scale * (((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]));
+    // the workgroup's sum of S, added to the others in a fixed order by k_ssim_loss
+    if (threadIdx.x == 0)
+        part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
+// loss = weight + neg_scale * (sum of the n partial sums), the partials added in a fixed
+// order (one workgroup): the loss is the same bits on every run
+__global__ __launch_bounds__(256) void k_ssim_loss(const float *__restrict__ part, uint32_t n, float weight,
+                                                   float neg_scale, float *__restrict__ loss) {
+    __shared__ float s_w[4];
+    float acc = 0.f;
+    for (uint32_t k = threadIdx.x; k < n; k += 256) acc += part[k];
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *loss = weight + neg_scale * (((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]);
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
@@ -206,11 +222,36 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, c
     const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
     const int px = ox + tx, py = oy + ty;
     const int64_t HW = (int64_t)W * H;
-    for (int c = 0; c < 3; ++c) {
-        __syncthreads();
+    // The three channels in turn (a pixel's three gradient values are then written by one
+    // workgroup); the three maps of channel c + 1 are loaded into registers while channel
+    // c is blurred, so the loads after the first channel's are off the critical path.
+    constexpr int NL = (kSsimH * kSsimH + 255) / 256;
+    float lm[3][NL];
+    int64_t lp[NL];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) ssim_load_plane(maps + (3 * c + q) * HW, W, H, ox, oy, s_m[q]);
+    for (int i = 0; i < NL; ++i) {
+        const int k = (int)threadIdx.x + 256 * i;
+        const int x = ox + k % kSsimH - kSsimR, yy = oy + k / kSsimH - kSsimR;
+        lp[i] = (k < kSsimH * kSsimH && x >= 0 && x < W && yy >= 0 && yy < H) ? (int64_t)yy * W + x : -1;
+    }
+    auto load_maps = [&](int c) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int i = 0; i < NL; ++i) lm[q][i] = lp[i] >= 0 ? maps[(3 * c + q) * HW + lp[i]] : 0.f;
+    };
+    load_maps(0);
+    for (int c = 0; c < 3; ++c) {
+        __syncthreads();   // the previous channel's reads of s_m and s_h done
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int k = (int)threadIdx.x + 256 * i;
+                if (k < kSsimH * kSsimH) s_m[q][k] = lm[q][i];
+            }
         __syncthreads();
+        if (c < 2) load_maps(c + 1);
         for (int k = threadIdx.x; k < kSsimH * kSsimT; k += 256) {
             const int r = k / kSsimT, cx = k % kSsimT;
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -236,8 +277,16 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, c
     }
 }
 
-// maps: 9 floats per pixel of scratch. loss <- weight (1 - mean S) (filled with weight
-// first); dL/dy (=, or += with accumulate) -weight dS/dy averaged over 3 H W values.
+// Scratch floats of the SSIM term: 9 per pixel (the maps), then one per (16 x 16 tile,
+// channel) (the partial sums of S).
+size_t dssim_scratch_floats(int W, int H) {
+    if (W <= 0 || H <= 0) return 0;
+    const size_t tiles = (size_t)((W + kSsimT - 1) / kSsimT) * (size_t)((H + kSsimT - 1) / kSsimT);
+    return (size_t)9 * (size_t)W * (size_t)H + 3 * tiles;
+}
+
+// maps: dssim_scratch_floats(W, H) floats of scratch. loss <- weight (1 - mean S); dL/dy
+// (=, or += with accumulate) -weight dS/dy averaged over 3 H W values.
 void launch_dssim(const float *y, const float *t, int W, int H, float weight, float *dldy, int accumulate, float *loss,
                   float *maps, hipStream_t st) {
     SsimWindow win;
@@ -248,14 +297,20 @@ void launch_dssim(const float *y, const float *t, int W, int H, float weight, fl
         sum += g[j];
     }
     for (int j = 0; j <= 2 * kSsimR; ++j) win.g[j] = (float)(g[j] / sum);
-    uint32_t wbits;
-    std::memcpy(&wbits, &weight, 4);
-    launch_fill_u32(reinterpret_cast<uint32_t *>(loss), wbits, 1, st);
-    if (W <= 0 || H <= 0) return;
+    if (W <= 0 || H <= 0) {   // no pixels: weight (1 - SSIM) with SSIM taken as 0
+        uint32_t wbits;
+        std::memcpy(&wbits, &weight, 4);
+        launch_fill_u32(reinterpret_cast<uint32_t *>(loss), wbits, 1, st);
+        return;
+    }
     const double N = 3.0 * (double)W * (double)H;
-    const dim3 grid((unsigned)((W + kSsimT - 1) / kSsimT), (unsigned)((H + kSsimT - 1) / kSsimT));
-    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, loss, (float)(-weight / N));
-    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, (float)(-weight / N), accumulate, dldy);
+    const dim3 grid((unsigned)((W + kSsimT - 1) / kSsimT), (unsigned)((H + kSsimT - 1) / kSsimT), 3u);
+    float *part = maps + (size_t)9 * (size_t)W * (size_t)H;
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, part);
+    hipLaunchKernelGGL(k_ssim_loss, dim3(1), dim3(256), 0, st, part, grid.x * grid.y * grid.z, weight, (float)(-weight / N),
+                       loss);
+    hipLaunchKernelGGL(k_ssim_bwd, dim3(grid.x, grid.y), dim3(256), 0, st, y, t, W, H, win, maps, (float)(-weight / N),
+                       accumulate, dldy);
 }
 
 }  // namespace recogs

@@ -54,6 +54,7 @@ void launch_loss_l2(const float *, const float *, int64_t, float, float *, float
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
 void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t);
+size_t dssim_scratch_floats(int, int);
 uint32_t unproject_blocks(int64_t);
 int64_t unproject_scratch_max_pixels();
 uint32_t *unproject_scratch_ptr(hipError_t *);
@@ -799,8 +800,7 @@ recogs_status recogs_loss_l1(const float *image, const float *target, int64_t co
 }
 
 size_t recogs_dssim_workspace_bytes(int32_t width, int32_t height) {
-    if (width <= 0 || height <= 0) return 0;
-    return (size_t)9 * sizeof(float) * (size_t)width * (size_t)height;
+    return sizeof(float) * dssim_scratch_floats(width, height);
 }
 
 recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t width, int32_t height, float weight,

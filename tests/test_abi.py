@@ -219,7 +219,8 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(B.recogs_loss_l2, 0, 0, 10, 1.0, 0, 0, 0) == -1
     assert status(B.recogs_loss_l1, 0, 0, 10, 1.0, 0, 0, 0) == -1
     assert status(B.recogs_loss_l1, 0, 0, -1, 1.0, 0, 0, 0) == -1
-    assert R.recogs_dssim_workspace_bytes(0, 10) == 0 and R.recogs_dssim_workspace_bytes(4, 5) == 9 * 4 * 20
+    assert R.recogs_dssim_workspace_bytes(0, 10) == 0 and R.recogs_dssim_workspace_bytes(4, 5) == 4 * (9 * 20 + 3)
+    assert R.recogs_dssim_workspace_bytes(33, 17) == 4 * (9 * 33 * 17 + 3 * 3 * 2)
     assert status(B.recogs_loss_dssim, 0, 0, 0, 8, 0.2, 0, 0, 0, 0, 0, 0) == -1           # width 0
     assert status(B.recogs_loss_dssim, 8, 8, 4, 5, 0.2, 8, 0, 8, 8, 9 * 4 * 20 - 1, 0) == -1  # workspace too small
         # (param, grad, m, v, count, lr, beta1, beta2, eps, step, stream)
