@@ -133,13 +133,64 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, ui
 // the blocks b < nblk of the key capacity.
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }   // LDS padding: no 16-way bank conflicts
 constexpr uint32_t kEmitKeys = 2048;   // keys per workgroup of k_emit_down (256 threads x 8)
+// With few chunks the down pass scans the chunk partials itself (FOLD): each workgroup
+// sums the partials of the chunks before its own, and workgroup 0 also the totals and
+// the depth range, which it writes to the header as k_scan_top would; one launch fewer.
+struct ScanFold {
+    const uint32_t *pzmn, *pzmx;
+    uint32_t nchunks;
+    uint64_t key_capacity;
+    uint32_t *header;
+};
+__device__ __forceinline__ void scan_fold_prefix(const uint64_t *__restrict__ pk, const uint32_t *__restrict__ pv,
+                                                 const ScanFold &f, uint64_t &pre_k, uint32_t &pre_v) {
+    __shared__ uint64_t s_k[4];
+    __shared__ uint32_t s_v[4], s_mn[4], s_mx[4];
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    const uint32_t upto = blockIdx.x == 0 ? f.nchunks : blockIdx.x;   // workgroup 0: the totals
+    uint64_t k = 0;
+    uint32_t v = 0, mn = 0xffffffffu, mx = 0u;
+    for (uint32_t c = t; c < upto; c += 256) {
+        k += pk[c];
+        v += pv[c];
+        if (blockIdx.x == 0) { mn = min(mn, f.pzmn[c]); mx = max(mx, f.pzmx[c]); }
+    }
+    k = wave_sum(k);
+    v = wave_sum(v);
+    if (blockIdx.x == 0) { mn = wave_min(mn); mx = wave_max(mx); }
+    if (lane_id() == 0) { s_k[w] = k; s_v[w] = v; s_mn[w] = mn; s_mx[w] = mx; }
+    __syncthreads();
+    k = ((s_k[0] + s_k[1]) + s_k[2]) + s_k[3];
+    v = ((s_v[0] + s_v[1]) + s_v[2]) + s_v[3];
+    if (blockIdx.x == 0) {
+        if (t == 0) {
+            mn = min(min(s_mn[0], s_mn[1]), min(s_mn[2], s_mn[3]));
+            mx = max(max(s_mx[0], s_mx[1]), max(s_mx[2], s_mx[3]));
+            f.header[H_K_LO] = (uint32_t)k;
+            f.header[H_K_HI] = (uint32_t)(k >> 32);
+            f.header[H_V] = v;
+            f.header[H_ZMIN] = v ? ~mn : 0u;
+            f.header[H_ZMAX] = v ? mx : 0u;
+            f.header[H_ZMIN_RAW] = v ? mn : 0u;
+            f.header[H_KEFF] = k <= f.key_capacity ? (uint32_t)k : 0u;
+            f.header[H_OVERFLOW] = k > f.key_capacity ? 1u : 0u;
+        }
+        pre_k = 0;
+        pre_v = 0;
+    } else {
+        pre_k = k;
+        pre_v = v;
+    }
+    __syncthreads();
+}
+
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                                    uint32_t *__restrict__ off, int64_t n, const uint64_t *__restrict__ pk,
                                                    const uint32_t *__restrict__ pv, uint32_t *__restrict__ dkeys,
                                                    uint32_t *__restrict__ dvals, const uint2 *__restrict__ rect,
                                                    uint2 *__restrict__ srect, uint32_t *__restrict__ eoff,
-                                                   uint32_t *__restrict__ efirst, uint32_t nblk) {
+                                                   uint32_t *__restrict__ efirst, uint32_t nblk, int fold, ScanFold f) {
     __shared__ uint64_t s_wk[4];
     __shared__ uint32_t s_wv[4];
     __shared__ uint32_t s_a[kScanChunk + kScanChunk / 32];
@@ -161,11 +212,17 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
         tsum += v[k];
         vsum += v[k] ? 1u : 0u;
     }
-    uint64_t ktot;
-    uint32_t vtot;
-    uint64_t run = pk[blockIdx.x] + block_excl_scan<uint64_t, 4>(tsum, s_wk, ktot);
+    uint64_t ktot, pre_k;
+    uint32_t vtot, pre_v;
+    if (fold) {
+        scan_fold_prefix(pk, pv, f, pre_k, pre_v);
+    } else {   // scanned by k_scan_top
+        pre_k = pk[blockIdx.x];
+        pre_v = pv[blockIdx.x];
+    }
+    uint64_t run = pre_k + block_excl_scan<uint64_t, 4>(tsum, s_wk, ktot);
     uint32_t vloc = block_excl_scan<uint32_t, 4>(vsum, s_wv, vtot);   // (the scans end with a barrier)
-    const uint32_t vbase = pv[blockIdx.x];
+    const uint32_t vbase = pre_v;
     if constexpr (EMIT) {
         // compacted key offsets; the owners of the key blocks starting in this chunk
         uint64_t r = run;
@@ -330,16 +387,30 @@ __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) esum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
+// fold: epre holds the chunks' unscanned key counts, and each workgroup adds those of the
+// chunks before its own (few chunks; one launch fewer than a separate scan)
 __global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ srect, uint32_t V,
                                                       const uint32_t *__restrict__ epre, uint32_t *__restrict__ eoff,
                                                       uint32_t *__restrict__ efirst, uint32_t nblk,
-                                                      const uint32_t *dynV, const uint32_t *overflow) {
+                                                      const uint32_t *dynV, const uint32_t *overflow, int fold) {
     if (dynV) V = *dynV;
     if (overflow && *overflow) return;
     const uint32_t base = blockIdx.x * (uint32_t)kEmitChunk;
     if (base >= V) return;
     __shared__ uint32_t s_w[4];
     const uint32_t t = threadIdx.x;
+    uint32_t pre;
+    if (fold) {
+        uint32_t a = 0;
+        for (uint32_t c = t; c < blockIdx.x; c += 256) a += epre[c];
+        a = wave_sum(a);
+        if (lane_id() == 0) s_w[t >> 6] = a;
+        __syncthreads();
+        pre = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+        __syncthreads();
+    } else {
+        pre = epre[blockIdx.x];
+    }
     constexpr int R = kEmitChunk / 256;
     uint32_t c[R], sum = 0;
 #pragma unroll
@@ -349,7 +420,7 @@ __global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ 
         sum += c[r];
     }
     uint32_t tot;
-    uint32_t run = epre[blockIdx.x] + block_excl_scan<uint32_t, 4>(sum, s_w, tot);
+    uint32_t run = pre + block_excl_scan<uint32_t, 4>(sum, s_w, tot);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t j = base + R * t + r;
@@ -590,14 +661,18 @@ void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int6
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr);
+    // up to 1,024 chunks (4M Gaussians) the down pass scans the partials itself
+    const int fold = nchunks <= 1024u;
+    const ScanFold f{pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr};
+    if (!fold)
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr);
     if (emit) {
         const uint32_t nblk = (uint32_t)(((uint64_t)key_capacity + kEmitKeys - 1) / kEmitKeys);
         hipLaunchKernelGGL(k_scan_down<true>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
-                           emit->rect, emit->srect, emit->eoff, emit->efirst, nblk);
+                           emit->rect, emit->srect, emit->eoff, emit->efirst, nblk, fold, f);
     } else {
         hipLaunchKernelGGL(k_scan_down<false>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
-                           nullptr, nullptr, nullptr, nullptr, 0u);
+                           nullptr, nullptr, nullptr, nullptr, 0u, fold, f);
     }
 }
 
@@ -623,8 +698,10 @@ void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, ui
     const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
     const uint32_t *ovf = hdr ? hdr + H_OVERFLOW : nullptr;
     hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum, dynV);
-    hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
-    hipLaunchKernelGGL(k_emit_offsets, dim3(chunks), dim3(256), 0, st, srect, V, esum, eoff, efirst, nblk, dynV, ovf);
+    // up to 2,048 chunks (2M depth-ordered Gaussians) the offsets pass scans the sums itself
+    const int fold = chunks <= 2048u;
+    if (!fold) hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
+    hipLaunchKernelGGL(k_emit_offsets, dim3(chunks), dim3(256), 0, st, srect, V, esum, eoff, efirst, nblk, dynV, ovf, fold);
     hipLaunchKernelGGL(k_emit_down, dim3(nblk), dim3(256), 0, st, order, V, K, srect, eoff, efirst, tiles_x, tkeys, tvals,
                        dynV, dynK, ovf, vtab, nviews);
 }
