@@ -133,6 +133,14 @@ def test_dssim_vs_oracle(R, orc, H, W):
     val, g = orc.ssim(y, t)
     assert abs(loss.item() - lam * (1.0 - val)) <= 1e-5
     e = _close(dl.cpu().numpy().astype(np.float64), -lam * g, "dL/dy (SSIM)")
+    # the loss is summed in a fixed order: the same bits again (the workspace holding the
+    # previous call's partial sums), and the gradient too
+    loss2 = torch.empty(1, device="cuda")
+    dl2 = torch.empty_like(ty)
+    R.recogs_loss_dssim(ty.data_ptr(), tt.data_ptr(), W, H, lam, dl2.data_ptr(), 0, loss2.data_ptr(), ws.data_ptr(), nb)
+    torch.cuda.synchronize()
+    assert loss2.cpu().numpy().tobytes() == loss.cpu().numpy().tobytes()
+    assert torch.equal(dl2, dl)
     # eq. 4: (1 - lambda) L1 + lambda (1 - SSIM); eq. 7: the SSIM gradient added to the L1 one
     n = y.size
     l1 = torch.empty(1, device="cuda")
