@@ -281,6 +281,13 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
                             const recogs_render_opts *opts, recogs_workspace *ws, float *image,
                             hipStream_t stream);
 
+/* Bytes of the scratch the backward's block form needs (opts->bwd_scratch) for this
+ * workspace and opts' tile shape and px_per_thread, with B blocks per tile: a float4
+ * per block and key of ws->key_capacity, rounded up to 256 bytes, then B * (capacity / 64
+ * + tiles + 2) flag words of 16 bytes. 0 where the shape has no block form or an
+ * argument is NULL / unsupported. */
+size_t recogs_backward_scratch_bytes(const recogs_workspace *ws, const recogs_render_opts *opts);
+
 /* Backward of the render and of the fused recolour (eq. 8, restricted to opacity,
  * SH DC and the recolour matrix). Needs the workspace of the matching render (run
  * with keep_backward_state = 1, no other render on the workspace since) and its output
@@ -293,13 +300,6 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
  * are bit-identical between runs. The backward uses the workspace's sorted-key buffers
  * (keys0/keys1) as per-key gradient scratch; the tile lists and the rest of the
  * render's state stay valid, so it may be called again on the same render. */
-/* Bytes of the scratch the backward's block form needs (opts->bwd_scratch) for this
- * workspace and opts' tile shape and px_per_thread, with B blocks per tile: a float4
- * per block and key of ws->key_capacity, rounded up to 256 bytes, then B * (capacity / 64
- * + tiles + 2) flag words of 16 bytes. 0 where the shape has no block form or an
- * argument is NULL / unsupported. */
-size_t recogs_backward_scratch_bytes(const recogs_workspace *ws, const recogs_render_opts *opts);
-
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
                                      const recogs_render_opts *opts, const recogs_workspace *ws,
                                      const float *image, const float *dL_dimage, float *dL_dopacity,
