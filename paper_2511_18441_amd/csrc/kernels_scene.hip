@@ -71,48 +71,43 @@ __global__ __launch_bounds__(256) void k_select(SceneDev sc, CamDev cam, float s
 }
 
 // Recolour on coefficients: C'_k = M C_k (k >= 1), C'_0 = M C_0 + ((M - I) 1/2 + b)/Y00.
-// A selected thread loads all its coefficients before it stores any (dst may alias
-// the source), so the loads of one Gaussian overlap instead of taking one memory
-// round trip per coefficient.
-template <int DT, int NC>
-__device__ __forceinline__ void recolor_one(const SceneDev &sc, void *__restrict__ dst, int64_t i, const float *M,
-                                            const float *off) {
-    float c[3 * NC];
-#pragma unroll
-    for (int p = 0; p < 3 * NC; ++p) c[p] = Store<DT>::ldc(sc.sh, p * sc.stride + i);
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            float v = M[r * 3] * c[3 * k] + M[r * 3 + 1] * c[3 * k + 1] + M[r * 3 + 2] * c[3 * k + 2];
-            if (k == 0) v += off[r];
-            Store<DT>::st(dst, (int64_t)(3 * k + r) * sc.stride + i, v);
-        }
-    }
-}
-
 template <int DT>
 __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *__restrict__ dst,
                                                  const uint8_t *__restrict__ mask, const float *__restrict__ Mp,
                                                  const float *__restrict__ bp, int copy_unselected) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc.n) return;
-    const bool sel = mask[i] != 0;
-    if (!sel) {
-        if (copy_unselected && dst != sc.sh)
-            for (int p = 0; p < ncoef * 3; ++p) Store<DT>::st(dst, p * sc.stride + i, Store<DT>::ldc(sc.sh, p * sc.stride + i));
-        return;
-    }
+    const bool valid = i < sc.n;
+    const bool sel = valid && mask[i] != 0;
+    if (valid && !sel && copy_unselected && dst != sc.sh)
+        for (int p = 0; p < ncoef * 3; ++p) Store<DT>::st(dst, p * sc.stride + i, Store<DT>::ldc(sc.sh, p * sc.stride + i));
+    // The selected Gaussians of the wave (a sparse selection leaves about one per wave)
+    // are recoloured one after the other by the whole wave: lane k takes coefficient k's
+    // three planes, so a Gaussian costs three loads and three stores of up to 16 lanes
+    // each instead of 48 of each from one lane. A lane loads its planes before it
+    // stores them, so the destination may alias the source.
+    uint64_t m = wave_ballot(sel);
+    if (!m) return;
     float M[9], off[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) M[k] = Mp[k];
 #pragma unroll
     for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bp[r]) / kSH0;
-    switch (ncoef) {
-    case 1: recolor_one<DT, 1>(sc, dst, i, M, off); break;
-    case 4: recolor_one<DT, 4>(sc, dst, i, M, off); break;
-    case 9: recolor_one<DT, 9>(sc, dst, i, M, off); break;
-    default: recolor_one<DT, 16>(sc, dst, i, M, off); break;
+    const int l = (int)lane_id();
+    const int64_t wbase = i - l;   // the Gaussian of lane 0
+    while (m) {
+        const int64_t g = wbase + (int64_t)__builtin_ctzll(m);
+        m &= m - 1;
+        if (l < ncoef) {
+            const float c0 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l) * sc.stride + g);
+            const float c1 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 1) * sc.stride + g);
+            const float c2 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 2) * sc.stride + g);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
+                if (l == 0) v += off[r];
+                Store<DT>::st(dst, (int64_t)(3 * l + r) * sc.stride + g, v);
+            }
+        }
     }
 }
 
