@@ -555,9 +555,9 @@ __global__ __launch_bounds__(256) void k_dm_reduce(const float *__restrict__ par
 // L2 loss: loss += scale sum (y - t)^2, dL/dy = 2 scale (y - t). With vec (all three
 // arrays 16-byte aligned) each thread takes 4 consecutive elements per step with one
 // 16-byte access per array; the remainder (or everything, without vec) one by one.
-__global__ __launch_bounds__(256) void k_loss_l2(const float *__restrict__ y, const float *__restrict__ tg, int64_t count,
+__global__ __launch_bounds__(1024) void k_loss_l2(const float *__restrict__ y, const float *__restrict__ tg, int64_t count,
                                                  float scale, float *__restrict__ dldy, float *__restrict__ loss, int vec) {
-    __shared__ float s_w[4];
+    __shared__ float s_w[16];
     float sum = 0.f;
     const int64_t n4 = vec ? count / 4 : 0;
     const float4 *y4 = reinterpret_cast<const float4 *>(y), *t4 = reinterpret_cast<const float4 *>(tg);
@@ -577,7 +577,11 @@ __global__ __launch_bounds__(256) void k_loss_l2(const float *__restrict__ y, co
     sum = wave_sum(sum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, scale * (s_w[0] + s_w[1] + s_w[2] + s_w[3]));
+    if (threadIdx.x == 0) {
+        float w = 0.f;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) w += s_w[k];   // the waves' sums in order
+        atomicAdd(loss, scale * w);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -679,12 +683,12 @@ void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bw
 
 void launch_loss_l2(const float *y, const float *tg, int64_t count, float scale, float *dldy, float *loss, hipStream_t st) {
     if (count <= 0) return;
-    // few workgroups: each adds its partial sum with one same-address atomic
-    int64_t blocks = (count + 255) / 256;
+    // few workgroups (of 16 waves): each adds its partial sum with one same-address atomic
+    int64_t blocks = (count + 1023) / 1024;
     if (blocks > 512) blocks = 512;
     const int vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(tg) | reinterpret_cast<uintptr_t>(dldy)) &
                      15u) == 0;
-    hipLaunchKernelGGL(k_loss_l2, dim3((unsigned)blocks), dim3(256), 0, st, y, tg, count, scale, dldy, loss, vec);
+    hipLaunchKernelGGL(k_loss_l2, dim3((unsigned)blocks), dim3(1024), 0, st, y, tg, count, scale, dldy, loss, vec);
 }
 
 }  // namespace recogs

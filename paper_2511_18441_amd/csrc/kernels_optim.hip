@@ -13,9 +13,9 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 // with sign(0) = 0. With vec (all three arrays 16-byte aligned) 4 elements per step.
 __device__ __forceinline__ float sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
 
-__global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ y, const float *__restrict__ tg, int64_t count,
+__global__ __launch_bounds__(1024) void k_loss_l1(const float *__restrict__ y, const float *__restrict__ tg, int64_t count,
                                                  float scale, float *__restrict__ dldy, float *__restrict__ loss, int vec) {
-    __shared__ float s_w[4];
+    __shared__ float s_w[16];
     float sum = 0.f;
     const int64_t n4 = vec ? count / 4 : 0;
     const float4 *y4 = reinterpret_cast<const float4 *>(y), *t4 = reinterpret_cast<const float4 *>(tg);
@@ -35,17 +35,21 @@ __global__ __launch_bounds__(256) void k_loss_l1(const float *__restrict__ y, co
     sum = wave_sum(sum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, scale * (s_w[0] + s_w[1] + s_w[2] + s_w[3]));
+    if (threadIdx.x == 0) {
+        float w = 0.f;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) w += s_w[k];   // the waves' sums in order
+        atomicAdd(loss, scale * w);
+    }
 }
 
 void launch_loss_l1(const float *y, const float *tg, int64_t count, float scale, float *dldy, float *loss, hipStream_t st) {
     if (count <= 0) return;
-    // few workgroups: each adds its partial sum with one same-address atomic
-    int64_t blocks = (count + 255) / 256;
+    // few workgroups (of 16 waves): each adds its partial sum with one same-address atomic
+    int64_t blocks = (count + 1023) / 1024;
     if (blocks > 512) blocks = 512;
     const int vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(tg) | reinterpret_cast<uintptr_t>(dldy)) &
                      15u) == 0;
-    hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)blocks), dim3(256), 0, st, y, tg, count, scale, dldy, loss, vec);
+    hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)blocks), dim3(1024), 0, st, y, tg, count, scale, dldy, loss, vec);
 }
 
 // Adam, element-wise: m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,

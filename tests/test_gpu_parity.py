@@ -94,6 +94,12 @@ def test_recolor(R, orc, storage, which):
         for k in range(16):
             assert np.array_equal(got[3 * k + 0, sel], src[3 * k + 2, sel])
             assert np.array_equal(got[3 * k + 1, sel], src[3 * k + 0, sel])
+    # into a zeroed buffer with the unselected copied over, and in place: the same bits
+    dst2 = torch.zeros_like(d.sh)
+    R.recogs_recolor(d.c_struct(), dst2.data_ptr(), mask.data_ptr(), M.data_ptr(), b.data_ptr(), 1)
+    assert torch.equal(dst2, dst)
+    R.recogs_recolor(d.c_struct(), d.sh.data_ptr(), mask.data_ptr(), M.data_ptr(), b.data_ptr(), 0)
+    assert torch.equal(d.sh, dst)
 
 
 # ---------------------------------------------------------------------------
