@@ -74,6 +74,11 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
     uint32_t npmax = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) npmax = max(npmax, np[j]);
+    // with full waves, the wave's largest replay count: entries at or past it are left
+    // out of the wave's bit sets, so the walk needs no test per entry
+    constexpr int L = NT < 64 ? NT : 64;
+    uint32_t npw = 0;
+    if constexpr (L == 64) npw = wave_max(npmax);
 
     const uint2 rg = ranges[tile];
     // With a thread per staged record (NT >= BATCH), the records of batch b + 1, their
@@ -129,7 +134,6 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
         const int nb = (int)min((uint32_t)BATCH, rg.y - start);
         // the batch's records this wave takes (scalar bit sets), walked in order while
         // some pixel of the wave still replays
-        constexpr int L = NT < 64 ? NT : 64;
         uint64_t todo[BATCH / 64];
 #pragma unroll
         for (int c = 0; c < BATCH / 64; ++c) {
@@ -137,7 +141,8 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
 #pragma unroll
             for (int sub = 0; sub < 64 / L; ++sub) {
                 const int q = c * 64 + sub * L + (int)lane_id();
-                todo[c] |= wave_ballot(q < nb && ((sm.r[q].mask >> w) & 1u)) << (sub * L);
+                const bool live = L < 64 || start + (uint32_t)q - rg.x < npw;
+                todo[c] |= wave_ballot(q < nb && live && ((sm.r[q].mask >> w) & 1u)) << (sub * L);
             }
         }
         bool quit = false;
@@ -148,9 +153,11 @@ __global__ __launch_bounds__(TW *TH / PPT) void k_blend_bwd(const uint2 *__restr
                 const int q = c * 64 + (int)__builtin_ctzll(mm);
                 mm &= mm - 1;
                 const uint32_t krel = start + q - rg.x;
-                if (!wave_ballot(krel < npmax)) {
-                    quit = true;
-                    break;
+                if constexpr (L < 64) {
+                    if (!wave_ballot(krel < npmax)) {
+                        quit = true;
+                        break;
+                    }
                 }
                 const float4 *br = reinterpret_cast<const float4 *>(&sm.r[q]);
                 const float4 h = br[0], r1 = br[1], r2 = br[2];
