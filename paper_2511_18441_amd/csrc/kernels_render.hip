@@ -8,12 +8,16 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, uint
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Also zeroes zero[0, zero_words) (the render's header, histograms, emission sums and
+// tile ranges, which only later kernels use): one launch fewer than a separate fill.
 template <int DT, int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(SceneDev sc, CamDev cam, RecolorDev rc, int keep_bwd,
                                                     SplatRec *__restrict__ rec, float4 *__restrict__ bwd,
                                                     uint32_t *__restrict__ zbits, uint2 *__restrict__ rect,
-                                                    uint32_t *__restrict__ count) {
+                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ zero,
+                                                    int64_t zero_words) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t z = i; z < zero_words; z += (int64_t)gridDim.x * blockDim.x) zero[z] = 0u;
     if (i < sc.n) preprocess_one<DT, DEG>(sc, cam, rc, keep_bwd, i, i, rec, bwd, zbits, rect, count);
 }
 
@@ -46,26 +50,41 @@ __device__ __forceinline__ T block_excl_scan(T v, T *s_w, T &total) {
     return pre + inc - v;
 }
 
+// HIST: also the chunk's counts of the low 8 depth bits (ScanSort), dcnt[d * nchunks + chunk]
+template <bool HIST>
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                                      int64_t n, uint64_t *__restrict__ pk, uint32_t *__restrict__ pv,
-                                                     uint32_t *__restrict__ pzmn, uint32_t *__restrict__ pzmx) {
+                                                     uint32_t *__restrict__ pzmn, uint32_t *__restrict__ pzmx,
+                                                     uint32_t *__restrict__ dcnt, uint32_t nchunks) {
     __shared__ uint64_t s_k[4];
     __shared__ uint32_t s_v[4], s_zmn[4], s_zmx[4];
+    __shared__ uint32_t s_h[HIST ? 256 : 1];
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    if constexpr (HIST) {
+        s_h[threadIdx.x] = 0u;
+        __syncthreads();
+    }
     // striped (coalesced): only sums, minima and maxima are taken here
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
     uint64_t tsum = 0;
     uint32_t vsum = 0, zmn = 0xffffffffu, zmx = 0u;
+    uint32_t cv[kScanItems], zv[kScanItems];   // every load issued before any is used
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         const int64_t i = base + (int64_t)k * 256;
-        const uint32_t v = (i < n) ? cnt[i] : 0u;
+        cv[k] = (i < n) ? cnt[i] : 0u;
+        zv[k] = (i < n) ? zbits[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const uint32_t v = cv[k];
         tsum += v;
         if (v) {
-            const uint32_t z = zbits[i];
+            const uint32_t z = zv[k];
             zmn = min(zmn, z);
             zmx = max(zmx, z);
             ++vsum;
+            if constexpr (HIST) atomicAdd(&s_h[z & 255u], 1u);
         }
     }
     tsum = wave_sum(tsum);
@@ -80,6 +99,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
         pzmn[blockIdx.x] = min(min(s_zmn[0], s_zmn[1]), min(s_zmn[2], s_zmn[3]));
         pzmx[blockIdx.x] = max(max(s_zmx[0], s_zmx[1]), max(s_zmx[2], s_zmx[3]));
     }
+    if constexpr (HIST) dcnt[(size_t)threadIdx.x * nchunks + blockIdx.x] = s_h[threadIdx.x];
 }
 
 // One workgroup: exclusive scans of the chunk partials in place; header gets K, V and
@@ -184,23 +204,53 @@ __device__ __forceinline__ void scan_fold_prefix(const uint64_t *__restrict__ pk
     __syncthreads();
 }
 
-template <bool EMIT>
+// MODE: SD_COMPACT writes the (depth bits, index) pairs of the Gaussians with keys
+// compacted in index order; SD_EMIT the tile-first order's compaction (ScanEmit);
+// SD_SORT the pairs ordered by their low 8 depth bits (ScanSort: the depth sort's
+// first pass, ranked as k_radix_down ranks, from the digit offsets in dcnt).
+enum : int { SD_COMPACT = 0, SD_EMIT = 1, SD_SORT = 2 };
+template <int MODE>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ zbits,
                                                    uint32_t *__restrict__ off, int64_t n, const uint64_t *__restrict__ pk,
                                                    const uint32_t *__restrict__ pv, uint32_t *__restrict__ dkeys,
                                                    uint32_t *__restrict__ dvals, const uint2 *__restrict__ rect,
                                                    uint2 *__restrict__ srect, uint32_t *__restrict__ eoff,
-                                                   uint32_t *__restrict__ efirst, uint32_t nblk, int fold, ScanFold f) {
+                                                   uint32_t *__restrict__ efirst, uint32_t nblk, int fold, ScanFold f,
+                                                   const uint32_t *__restrict__ dcnt, const uint32_t *__restrict__ dtot) {
+    constexpr bool EMIT = MODE == SD_EMIT;
     __shared__ uint64_t s_wk[4];
     __shared__ uint32_t s_wv[4];
     __shared__ uint32_t s_a[kScanChunk + kScanChunk / 32];
     __shared__ uint32_t s_dk[kScanChunk], s_dv[kScanChunk];
     const int t = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * kScanChunk;
+    // SD_SORT loads the counts wave-striped (wave w: entries 1024 w + 64 r + lane, the
+    // order its ranking takes them in) and keeps them, with the depth bits and the digit
+    // offsets, in registers: every global load of the workgroup is issued here
+    uint32_t cw[MODE == SD_SORT ? kScanItems : 1], zk[MODE == SD_SORT ? kScanItems : 1];
+    uint32_t dtot_t = 0, dcnt_t = 0;
+    if constexpr (MODE == SD_SORT) {
+        const uint32_t wl = (uint32_t)t >> 6, ln = lane_id();
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const int i = k * 256 + t;
-        s_a[scan_pad(i)] = (c0 + i < n) ? cnt[c0 + i] : 0u;
+        for (int r = 0; r < kScanItems; ++r) {
+            const int i = (int)(wl * (64 * kScanItems) + r * 64 + ln);
+            cw[r] = (c0 + i < n) ? cnt[c0 + i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            const int i = (int)(wl * (64 * kScanItems) + r * 64 + ln);
+            zk[r] = (c0 + i < n) ? zbits[c0 + i] : 0u;
+        }
+        dtot_t = dtot[t];
+        dcnt_t = dcnt[(size_t)t * gridDim.x + blockIdx.x];
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) s_a[scan_pad((int)(wl * (64 * kScanItems) + r * 64 + ln))] = cw[r];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const int i = k * 256 + t;
+            s_a[scan_pad(i)] = (c0 + i < n) ? cnt[c0 + i] : 0u;
+        }
     }
     __syncthreads();
     uint32_t v[kScanItems];
@@ -245,7 +295,7 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
             srect[vbase + j] = rect[s_dv[j]];   // within the chunk's 4,096 Gaussians: few lines
         }
         __syncthreads();
-    } else {
+    } else if constexpr (MODE == SD_COMPACT) {
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const int i = k * 256 + t;
@@ -262,6 +312,68 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
             }
         }
         __syncthreads();
+    } else {
+        // wave w ranks Gaussians [1024 w, 1024 w + 1024) of the chunk, 64 per round, so
+        // the ranks follow index order; then digit order through LDS (s_dk, s_dv) and out
+        // as contiguous runs at the digits' offsets
+        __shared__ uint32_t s_whist[4][256];
+        __shared__ uint32_t s_gbase[256], s_lstart[256];
+        const uint32_t lane = lane_id(), w = (uint32_t)t >> 6;
+        for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0u;
+        {
+            uint32_t all;
+            const uint32_t dbase = block_excl_scan<uint32_t, 4>(dtot_t, s_wv, all);
+            s_gbase[t] = dbase + dcnt_t;
+        }
+        __syncthreads();
+        uint32_t rk[kScanItems], vm = 0u;
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) vm |= (cw[r] != 0u ? 1u : 0u) << r;
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            const bool valid = (vm >> r) & 1u;
+            const uint32_t d = zk[r] & 255u;
+            uint64_t m = wave_ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = wave_ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            const uint32_t below = rank_below(m);
+            uint32_t prior = 0;
+            if (valid) prior = s_whist[w][d];
+            rk[r] = prior + below;
+            if (valid && below == 0) s_whist[w][d] = prior + (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        uint32_t dt = 0;   // thread t = digit t: prefix over the waves, then over the digits
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+            const uint32_t x = s_whist[ww][t];
+            s_whist[ww][t] = dt;
+            dt += x;
+        }
+        uint32_t ntot;
+        const uint32_t ls = block_excl_scan<uint32_t, 4>(dt, s_wv, ntot);
+        s_lstart[t] = ls;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kScanItems; ++r) {
+            if ((vm >> r) & 1u) {
+                const uint32_t d = zk[r] & 255u;
+                const uint32_t pos = s_lstart[d] + s_whist[w][d] + rk[r];
+                s_dk[pos] = zk[r];
+                s_dv[pos] = (uint32_t)(c0 + (int64_t)(w * (64 * kScanItems) + r * 64 + lane));
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = t; j < ntot; j += 256) {
+            const uint32_t z = s_dk[j], d = z & 255u;
+            const uint32_t dst = s_gbase[d] + (j - s_lstart[d]);
+            dkeys[dst] = z;
+            dvals[dst] = s_dv[j];
+        }
     }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
@@ -274,7 +386,7 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *__restrict__ 
         const int i = k * 256 + t;
         if (c0 + i < n) off[c0 + i] = s_a[scan_pad(i)];
     }
-    if constexpr (!EMIT) {
+    if constexpr (MODE == SD_COMPACT) {
         for (uint32_t j = t; j < vtot; j += 256) {
             dkeys[vbase + j] = s_dk[j];
             dvals[vbase + j] = s_dv[j];
@@ -350,8 +462,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
 // index), emit (tile id, index) pairs; a stable sort on the tile id then yields the
 // (tile, depth, index) order.
 //   k_emit_reduce:  per chunk of 1,024 depth-ordered Gaussians, gathers each one's
-//                   tile rectangle once and sums the chunk's key counts
-//   k_scan_top_u32: chunk sums -> chunk key offsets
+//                   tile rectangle once and sums the chunk's key counts (for one view
+//                   the depth sort's last pass does this as it writes the order)
+//   k_scan_top_u32: chunk sums -> chunk key offsets (more than 2,048 chunks)
 //   k_emit_offsets: per-Gaussian key offsets, and for every block of kEmitKeys keys
 //                   the Gaussian owning its first key
 //   k_emit_down:    one workgroup per block of kEmitKeys keys (the work is balanced by
@@ -359,10 +472,6 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t *__restrict__ cnt, 
 //                   the owner of each key comes from a max-scan of the Gaussians'
 //                   start positions in LDS, and keys are written coalesced
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t rect_count(uint2 r) {
-    return ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
-}
-
 // also gathers each depth-ordered Gaussian's tile rectangle once (srect, coalesced
 // for k_emit_down); every Gaussian in the order has at least one key
 __global__ __launch_bounds__(256) void k_emit_reduce(const uint32_t *__restrict__ order, uint32_t V,
@@ -632,35 +741,56 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, v, count);
 }
 
+#define RECOGS_PRE(D)                                                                                                  \
+    hipLaunchKernelGGL((k_preprocess<DT, D>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, zero, zw)
 template <int DT>
 static void preprocess_dt(int deg, dim3 g, hipStream_t st, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc,
-                          int keep, SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt) {
+                          int keep, SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, uint32_t *zero,
+                          int64_t zw) {
     switch (deg) {
-    case 0: hipLaunchKernelGGL((k_preprocess<DT, 0>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
-    case 1: hipLaunchKernelGGL((k_preprocess<DT, 1>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
-    case 2: hipLaunchKernelGGL((k_preprocess<DT, 2>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
-    default: hipLaunchKernelGGL((k_preprocess<DT, 3>), g, dim3(256), 0, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt); break;
+    case 0: RECOGS_PRE(0); break;
+    case 1: RECOGS_PRE(1); break;
+    case 2: RECOGS_PRE(2); break;
+    default: RECOGS_PRE(3); break;
     }
 }
+#undef RECOGS_PRE
 
+// zero (optional): zero_words words zeroed by the same launch (with no Gaussian, a fill)
 void launch_preprocess(int dt, int deg, const SceneDev &sc, const CamDev &cam, const RecolorDev &rc, int keep,
-                       SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, hipStream_t st) {
-    if (sc.n <= 0) return;
+                       SplatRec *rec, float4 *bwd, uint32_t *zb, uint2 *rect, uint32_t *cnt, hipStream_t st,
+                       uint32_t *zero, int64_t zero_words) {
+    if (!zero) zero_words = 0;
+    if (sc.n <= 0) {
+        launch_fill_u32(zero, 0u, zero_words, st);
+        return;
+    }
     const dim3 g((unsigned)((sc.n + 255) / 256));
-    if (dt == RECOGS_F32) preprocess_dt<RECOGS_F32>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
-    else if (dt == RECOGS_F16) preprocess_dt<RECOGS_F16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
-    else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt);
+    if (dt == RECOGS_F32) preprocess_dt<RECOGS_F32>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, zero, zero_words);
+    else if (dt == RECOGS_F16) preprocess_dt<RECOGS_F16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, zero, zero_words);
+    else preprocess_dt<RECOGS_BF16>(deg, g, st, sc, cam, rc, keep, rec, bwd, zb, rect, cnt, zero, zero_words);
 }
+
+void launch_rowscan(uint32_t *cnt, uint32_t chunks, uint32_t chunk_keys, uint32_t *tot, uint32_t K, int nbits,
+                    hipStream_t st);
 
 // emit non-null (tile-first order): the compaction carries rect -> emit->srect, key offsets
 // -> emit->eoff and the key blocks' owners -> emit->efirst (blocks of the key capacity);
-// otherwise the depth bits -> dkeys.
+// otherwise the depth bits -> dkeys. sort (optional, not with emit): the scan is also the
+// depth sort's first pass (ScanSort).
 void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int64_t n, uint64_t *pk, uint32_t *pv,
                  uint32_t *pzmn, uint32_t *pzmx, uint32_t *dkeys, uint32_t *dvals, uint32_t *hdr, int64_t key_capacity,
-                 hipStream_t st, const ScanEmit *emit) {
+                 hipStream_t st, const ScanEmit *emit, const ScanSort *sort) {
     if (n <= 0) return;
     const uint32_t nchunks = (uint32_t)((n + kScanChunk - 1) / kScanChunk);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx);
+    if (sort) {
+        hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx,
+                           sort->dcnt, nchunks);
+        launch_rowscan(sort->dcnt, nchunks, (uint32_t)kScanChunk, sort->dtot, (uint32_t)n, 8, st);
+    } else {
+        hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, n, pk, pv, pzmn, pzmx,
+                           nullptr, nchunks);
+    }
     // up to 1,024 chunks (4M Gaussians) the down pass scans the partials itself
     const int fold = nchunks <= 1024u;
     const ScanFold f{pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr};
@@ -668,11 +798,14 @@ void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int6
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, pk, pv, pzmn, pzmx, nchunks, (uint64_t)key_capacity, hdr);
     if (emit) {
         const uint32_t nblk = (uint32_t)(((uint64_t)key_capacity + kEmitKeys - 1) / kEmitKeys);
-        hipLaunchKernelGGL(k_scan_down<true>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
-                           emit->rect, emit->srect, emit->eoff, emit->efirst, nblk, fold, f);
+        hipLaunchKernelGGL(k_scan_down<SD_EMIT>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
+                           emit->rect, emit->srect, emit->eoff, emit->efirst, nblk, fold, f, nullptr, nullptr);
+    } else if (sort) {
+        hipLaunchKernelGGL(k_scan_down<SD_SORT>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, sort->keys,
+                           sort->vals, nullptr, nullptr, nullptr, nullptr, 0u, fold, f, sort->dcnt, sort->dtot);
     } else {
-        hipLaunchKernelGGL(k_scan_down<false>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys, dvals,
-                           nullptr, nullptr, nullptr, nullptr, 0u, fold, f);
+        hipLaunchKernelGGL(k_scan_down<SD_COMPACT>, dim3(nchunks), dim3(256), 0, st, cnt, zbits, off, n, pk, pv, dkeys,
+                           dvals, nullptr, nullptr, nullptr, nullptr, 0u, fold, f, nullptr, nullptr);
     }
 }
 
@@ -692,12 +825,13 @@ void launch_emit_compacted(const uint32_t *order, uint32_t V, const uint2 *srect
 void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, uint2 *srect, int tiles_x,
                         uint32_t *esum, uint32_t *eoff, uint32_t *efirst, uint32_t K, uint32_t *tkeys, uint32_t *tvals,
                         hipStream_t st, const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr,
-                        const uint4 *vtab, int nviews) {
+                        const uint4 *vtab, int nviews, int folded) {
     if (V == 0 || K == 0) return;
     const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
     const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
     const uint32_t *ovf = hdr ? hdr + H_OVERFLOW : nullptr;
-    hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum, dynV);
+    // folded: the depth sort's last pass has gathered srect and summed esum (EmitFold)
+    if (!folded) hipLaunchKernelGGL(k_emit_reduce, dim3(chunks), dim3(256), 0, st, order, V, rect, srect, esum, dynV);
     // up to 2,048 chunks (2M depth-ordered Gaussians) the offsets pass scans the sums itself
     const int fold = chunks <= 2048u;
     if (!fold) hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);

@@ -108,13 +108,14 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cn
     if (t == 0) tot[d] = run;
 }
 
-template <typename KT, int VIEW, int ITEMS>
+// EF (the last pass of the depth order): also the emission fold (EmitFold).
+template <typename KT, int VIEW, int ITEMS, bool EF>
 __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     KT *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t K,
                                                     uint32_t zmin, int dbits, int shift, int nbits,
                                                     const uint32_t *__restrict__ off, const uint32_t *__restrict__ dtot,
                                                     uint32_t chunks, const uint32_t *dyn_count,
-                                                    const uint32_t *dyn_zmin) {
+                                                    const uint32_t *dyn_zmin, EmitFold ef) {
     constexpr uint32_t CHUNK = 256 * ITEMS;
     dyn_args(dyn_count, dyn_zmin, K, zmin);
     if (blockIdx.x * CHUNK >= K) return;
@@ -188,12 +189,40 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
     }
     __syncthreads();
     const uint32_t nvalid = min((uint32_t)CHUNK, K - cbase);
-    for (uint32_t j = t; j < nvalid; j += 256) {
-        const KT k = s_keys[j];
-        const uint32_t d = digit_of<KT, VIEW>(k, zmin, dbits, shift, dmask);
-        const uint32_t dst = s_gbase[d] + (j - s_lstart[d]);
-        kout[dst] = k;
-        vout[dst] = s_vals[j];
+    if constexpr (!EF) {
+        for (uint32_t j = t; j < nvalid; j += 256) {
+            const KT k = s_keys[j];
+            const uint32_t d = digit_of<KT, VIEW>(k, zmin, dbits, shift, dmask);
+            const uint32_t dst = s_gbase[d] + (j - s_lstart[d]);
+            kout[dst] = k;
+            vout[dst] = s_vals[j];
+        }
+    } else {
+        // dst grows with j (the digit runs are laid out in digit order), so each emission
+        // chunk present in a wave is a run of its lanes: from one prefix sum over the wave,
+        // the run's last lane adds the inclusive sum and its first lane subtracts the
+        // exclusive one (integer adds: the order of the atomics does not matter)
+        for (uint32_t j0 = 0; j0 < nvalid; j0 += 256) {
+            const uint32_t j = j0 + t;
+            const bool ok = j < nvalid;
+            uint32_t cid = 0xffffffffu, c = 0u;
+            if (ok) {
+                const KT k = s_keys[j];
+                const uint32_t d = digit_of<KT, VIEW>(k, zmin, dbits, shift, dmask);
+                const uint32_t dst = s_gbase[d] + (j - s_lstart[d]);
+                kout[dst] = k;
+                const uint32_t v = s_vals[j];
+                vout[dst] = v;
+                const uint2 r = ef.rect[v];
+                if (dst < ef.srect_cap) ef.srect[dst] = r;
+                c = rect_count(r);
+                cid = dst / (uint32_t)kEmitChunk;
+            }
+            const uint32_t inc = wave_incl_scan(c);
+            const uint32_t prev = __shfl_up(cid, 1, 64), next = __shfl_down(cid, 1, 64);
+            if (ok && (lane == 63 || next != cid)) atomicAdd(ef.esum + cid, inc);
+            if (ok && lane > 0 && prev != cid) atomicAdd(ef.esum + cid, c - inc);
+        }
     }
 }
 
@@ -227,7 +256,7 @@ size_t sort_count_words(uint64_t K_max) {
 template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
                       uint32_t *ghist, uint32_t *cnt, hipStream_t st, const uint32_t *dyn_count = nullptr,
-                      const uint32_t *dyn_zmin = nullptr) {
+                      const uint32_t *dyn_zmin = nullptr, const EmitFold *ef = nullptr, int first_shift = 0) {
     if (K == 0 || total_bits == 0) return 0;   // K is the count, or its upper bound with dyn_count
     const int passes = sort_passes(total_bits);
     const int per = (total_bits + passes - 1) / passes;
@@ -241,7 +270,8 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
     const int items = sort_items(K);
     const uint32_t chunk_keys = 256u * (uint32_t)items;
     const uint32_t chunks = (K + chunk_keys - 1) / chunk_keys;
-    int alt = 0, shift = 0;
+    const EmitFold none{nullptr, nullptr, nullptr, 0u};
+    int alt = 0, shift = first_shift;
     for (int p = 0; p < passes; ++p) {
         const int nb = (bits >> (4 * p)) & 15;
         const KT *kin = alt ? kb : ka;
@@ -249,12 +279,17 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         KT *kout = alt ? ka : kb;
         uint32_t *vout = alt ? va : vb;
         uint32_t *tot = ghist + 256 * p;
+        const bool fold = ef && p == passes - 1;
 #define RECOGS_PASS(IT)                                                                                                    \
     hipLaunchKernelGGL((k_radix_up<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,    \
                        chunks, dyn_count, dyn_zmin);                                                                       \
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, chunk_keys, tot, K, dyn_count);     \
-    hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K, zmin, dbits, \
-                       shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin);
+    if (fold)                                                                                                              \
+        hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT, true>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K,    \
+                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, *ef);                            \
+    else                                                                                                                   \
+        hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT, false>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K,   \
+                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, none);
         if (items == 16) { RECOGS_PASS(16) }
         else if (items == 8) { RECOGS_PASS(8) }
         else { RECOGS_PASS(4) }
@@ -265,21 +300,31 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
     return alt;
 }
 
+// One row scan of a digit-count matrix [2^nbits][chunks] (K keys, chunk_keys per chunk).
+void launch_rowscan(uint32_t *cnt, uint32_t chunks, uint32_t chunk_keys, uint32_t *tot, uint32_t K, int nbits,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nbits), dim3(256), 0, st, cnt, chunks, chunk_keys, tot, K, nullptr);
+}
+
 int radix_sort_tile_depth64(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits,
                             int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
     return radix_sort<uint64_t, KV_TILE_DEPTH>(ka, va, kb, vb, K, zmin, dbits, total_bits, ghist, cnt, st);
 }
 
+// ef (optional): the depth order's last pass also does the emission fold.
 int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K, uint32_t sub, int total_bits,
-                   uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
-    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st);
+                   uint32_t *ghist, uint32_t *cnt, hipStream_t st, const EmitFold *ef) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st, nullptr, nullptr, ef);
 }
 
 // The same with the count and the subtracted minimum read from device memory; K_max
-// bounds the count (sizes the grids and the count matrix).
+// bounds the count (sizes the grids and the count matrix). The digits start at bit
+// first_shift of the key (bits below it already ordered by an earlier pass).
 int radix_sort_u32_dyn(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K_max, const uint32_t *dyn_count,
-                       const uint32_t *dyn_sub, int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st) {
-    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K_max, 0u, 0, total_bits, ghist, cnt, st, dyn_count, dyn_sub);
+                       const uint32_t *dyn_sub, int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st,
+                       const EmitFold *ef, int first_shift) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K_max, 0u, 0, total_bits, ghist, cnt, st, dyn_count, dyn_sub, ef,
+                                        first_shift);
 }
 
 }  // namespace recogs

@@ -243,11 +243,40 @@ struct ScanEmit {
     uint32_t *efirst;      // owner of the first key of each emission block
 };
 
+// The count scan as the first pass of the depth sort (one view, no host read-back): the
+// scan's chunks are that pass's chunks. k_scan_reduce counts the low 8 bits of the depth
+// bits of each chunk's Gaussians with keys into dcnt[digit][chunk] (row stride: the
+// chunk count), a row scan makes them the chunks' digit offsets and dtot the digit
+// totals, and k_scan_down writes the chunk's (depth bits, index) pairs stably ordered
+// by those 8 bits (keys, vals) instead of compacted in index order.
+struct ScanSort {
+    uint32_t *dcnt;
+    uint32_t *dtot;
+    uint32_t *keys;
+    uint32_t *vals;
+};
+
 constexpr int kScanItems = 16;                       // counts per thread of the scan
 constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
 constexpr int kMaxPasses = 8;
 constexpr int kEmitItems = 4;                        // depth-ordered Gaussians per thread (emission reduce / offsets)
 constexpr int kEmitChunk = 256 * kEmitItems;         // depth-ordered Gaussians per emission workgroup
+
+// Tiles of a packed tile rectangle (x0 | x1 << 16, y0 | y1 << 16): its key count.
+__device__ __forceinline__ uint32_t rect_count(uint2 r) {
+    return ((r.x >> 16) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.y & 0xffffu) + 1u);
+}
+
+// Work of the key emission's reduce pass, done by the last pass of the depth sort as it
+// writes the depth order: each Gaussian's tile rectangle gathered in that order (srect)
+// and the key count of every kEmitChunk consecutive depth-ordered Gaussians added into
+// esum (zeroed beforehand).
+struct EmitFold {
+    const uint2 *rect;   // tile rectangles, indexed by the sort's values
+    uint2 *srect;        // srect_cap entries (positions past it are not written)
+    uint32_t *esum;
+    uint32_t srect_cap;
+};
 
 // Per-Gaussian splat record for compositing: three float4
 //   r0 = (u, v, ex, ey)   centre (pixels) and half-extents of the alpha >= 1/255 box

@@ -17,9 +17,9 @@ void launch_select(int, const SceneDev &, const CamDev &, const recogs_select_pa
 void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const float *, const float *, int, hipStream_t);
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
-                       uint32_t *, uint2 *, uint32_t *, hipStream_t);
+                       uint32_t *, uint2 *, uint32_t *, hipStream_t, uint32_t *, int64_t);
 void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
-                 uint32_t *, uint32_t *, uint32_t *, int64_t, hipStream_t, const ScanEmit *);
+                 uint32_t *, uint32_t *, uint32_t *, int64_t, hipStream_t, const ScanEmit *, const ScanSort * = nullptr);
 void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32_t *, int64_t, int, uint64_t *, uint32_t *,
                  hipStream_t);
 void launch_emit_compacted(const uint32_t *, uint32_t, const uint2 *, const uint32_t *, const uint32_t *, uint32_t, int,
@@ -29,7 +29,7 @@ void launch_tile_depth_sort(const uint2 *, uint32_t, uint32_t *, const uint32_t 
                             hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
                         uint32_t, uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *,
-                        const uint32_t *, const uint4 *, int);
+                        const uint32_t *, const uint4 *, int, int = 0);
 uint32_t emit_blocks(uint32_t K);
 size_t sort_count_words(uint64_t K_max);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
@@ -40,7 +40,7 @@ int sort_passes(int total_bits);
 int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
                             uint32_t *, hipStream_t);
 int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                   hipStream_t);
+                   hipStream_t, const EmitFold * = nullptr);
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
@@ -66,7 +66,7 @@ size_t outlier_workspace_bytes(int64_t);
 bool launch_outliers(const float *, int64_t, int64_t, int, float, float *, uint8_t *, float *, int64_t, uint32_t *, void *,
                      hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
-                       uint32_t *, uint32_t *, hipStream_t);
+                       uint32_t *, uint32_t *, hipStream_t, const EmitFold * = nullptr, int = 0);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
                              hipStream_t);
 void launch_tile_order(const uint2 *, uint32_t, uint32_t *, uint32_t *, uint32_t *, hipStream_t);
@@ -136,15 +136,16 @@ size_t layout(recogs_workspace *ws, int64_t n, int32_t W, int32_t H, int32_t tw,
     ws->off_dvals1 = take(4 * nn);
     // scan partials per chunk: key count (u64), count with keys, depth min, depth max
     ws->off_scan = take(20 * (size_t)scan_chunks);
-    ws->off_esum = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
     ws->off_efirst = take(4 * ((size_t)emit_blocks((uint32_t)(cap > 0 ? cap : 1)) + 1));
     // radix digit-count matrix [256][chunks], shared by the depth sort (up to n keys) and
     // the key sort (up to cap keys)
     ws->off_sort_count = take(4 * std::max(sort_count_words((uint64_t)nn), sort_count_words((uint64_t)(cap > 0 ? cap : 1))));
-    // zeroed each render: header; histograms; tile ranges
+    // zeroed each render: header; histograms; key counts of the depth-ordered emission
+    // chunks (summed by the depth sort's last pass); tile ranges
     ws->off_header = take(4 * H_WORDS);
     ws->off_hist = take(4 * 256 * kMaxPasses);
     ws->off_dhist = take(4 * 256 * kMaxPasses);
+    ws->off_esum = take(4 * (size_t)((nn + kEmitChunk - 1) / kEmitChunk));
     ws->off_ranges = take(8 * (size_t)T);
     ws->scan_chunks = (size_t)scan_chunks;
     ws->sort_chunks = std::max(sort_count_words((uint64_t)nn), sort_count_words((uint64_t)(cap > 0 ? cap : 1))) / 256;
@@ -378,12 +379,19 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     int alt = 0;
     if (n > 0 && cap > 0) {
         if (mode == 0) {
-            const int dalt = radix_sort_u32_dyn(dk0, dv0, dk1, dv1, (uint32_t)n, hdr + H_V, hdr + H_ZMIN_RAW, 32, dhist,
-                                                scount, stream);
+            // the depth order's rectangles go to keys1, free until the key sort (cap entries;
+            // past them the view overflows and emits nothing)
+            uint2 *srect = (uint2 *)t1;
+            const EmitFold ef{at<uint2>(ws, ws->off_rect), srect, at<uint32_t>(ws, ws->off_esum), cap};
+            // the scan left the pairs ordered by their low 8 depth bits in dkeys1 (digit
+            // totals in dhist[0..255]); three passes over the upper 24 bits remain
+            const int dalt = radix_sort_u32_dyn(dk1, dv1, dk0, dv0, (uint32_t)n, hdr + H_V, nullptr, 24, dhist + 256,
+                                                scount, stream, &ef, 8);
+            uint32_t *order = dalt ? dv0 : dv1, *spare = dalt ? dv1 : dv0;
             if ((s = tm.mark(4)) != RECOGS_OK) return s;
-            launch_emit_sorted(dalt ? dv1 : dv0, (uint32_t)n, at<uint2>(ws, ws->off_rect), (uint2 *)dk0, cd.tiles_x,
-                               at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1, at<uint32_t>(ws, ws->off_efirst), cap, t0,
-                               v0, stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+            launch_emit_sorted(order, (uint32_t)n, at<uint2>(ws, ws->off_rect), srect, cd.tiles_x,
+                               at<uint32_t>(ws, ws->off_esum), spare, at<uint32_t>(ws, ws->off_efirst), cap, t0, v0, stream,
+                               hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1, 1);
         } else {
             if ((s = tm.mark(4)) != RECOGS_OK) return s;
             launch_emit_compacted(dv0, (uint32_t)n, (const uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst), cap,
@@ -556,14 +564,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     const int mode = opts->sort_mode;
     uint32_t *dk0 = at<uint32_t>(ws, ws->off_dkeys0), *dk1 = at<uint32_t>(ws, ws->off_dkeys1);
     uint32_t *dv0 = at<uint32_t>(ws, ws->off_dvals0), *dv1 = at<uint32_t>(ws, ws->off_dvals1);
-    // zero the header (in graph mode also the digit totals and tile ranges, adjacent)
-    launch_fill_u32(hdr, 0u,
-                    opts->graph_mode ? (int64_t)((ws->off_ranges - ws->off_header) / 4) + 2 * (int64_t)ntiles
-                                     : (int64_t)H_WORDS,
-                    stream);
+    // the preprocess launch also zeroes the header, the digit totals, the emission sums
+    // and the tile ranges (adjacent)
     RecolorDev rc{opts->mask, opts->M, opts->b};
     launch_preprocess(scene->storage, scene->sh_degree, make_scene(*scene), cd, rc, opts->keep_backward_state, rec, bwd, zb,
-                      rect, cnt, stream);
+                      rect, cnt, stream, hdr, (int64_t)((ws->off_ranges - ws->off_header) / 4) + 2 * (int64_t)ntiles);
     if ((s = tm.mark(1)) != RECOGS_OK) return s;
     {
         const size_t sc_n = ws->scan_chunks;
@@ -572,8 +577,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         // tile-first order: the compaction carries rectangles (over both depth-key buffers,
         // adjacent), key offsets (dvals1) and the emission blocks' owners
         const ScanEmit em{rect, (uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst)};
+        // depth-first order without read-back: the scan also does the depth sort's first
+        // pass (on the raw depth bits: the same order as above the minimum), into dkeys1
+        const ScanSort so{at<uint32_t>(ws, ws->off_sort_count), at<uint32_t>(ws, ws->off_dhist), dk1, dv1};
         launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream,
-                    mode == 2 ? &em : nullptr);
+                    mode == 2 ? &em : nullptr, (mode == 0 && opts->graph_mode) ? &so : nullptr);
     }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
@@ -604,26 +612,27 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     ws->depth_passes = (mode == 0 && V) ? sort_passes(dbits) : 0;
     ws->key_bytes = mode == 1 ? 8 : 4;
 
-    // zero the histograms (adjacent) and the tile ranges
+    // (histograms, emission sums and tile ranges zeroed by the preprocess launch)
     uint32_t *hist = at<uint32_t>(ws, ws->off_hist), *dhist = at<uint32_t>(ws, ws->off_dhist);
     uint32_t *scount = at<uint32_t>(ws, ws->off_sort_count);
-    launch_fill_u32(hist, 0u, (int64_t)((ws->off_ranges - ws->off_hist) / 4) + 2 * (int64_t)ntiles, stream);
 
     uint64_t *k0 = at<uint64_t>(ws, ws->off_keys0), *k1 = at<uint64_t>(ws, ws->off_keys1);
     uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
     int alt = 0;
     if (K > 0 && mode == 0) {
-        // depth sort of the V Gaussians with keys (compacted in index order by the scan)
-        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, scount, stream);
-        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        // depth sort of the V Gaussians with keys (compacted in index order by the scan);
+        // its last pass gathers the depth-ordered rectangles (8 bytes each) into keys1, free
+        // until the key sort (K <= cap, so V <= cap), and sums the emission chunks' counts
         uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
-        // the depth-ordered rectangles (8 bytes each) reuse both depth-key buffers, which are
-        // adjacent and no longer needed once the order (values) is known
-        uint2 *srect = (uint2 *)dk0;
-        // per-Gaussian key offsets go to the depth-value buffer the sort left free
+        uint2 *srect = (uint2 *)k1;
+        const EmitFold ef{rect, srect, at<uint32_t>(ws, ws->off_esum), (uint32_t)ws->key_capacity};
+        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, scount, stream, &ef);
+        if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        // per-Gaussian key offsets go to the depth-value buffer the sort left free; with no
+        // sort pass (a single depth) the emission does its own reduce
         launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1,
                            at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, t0, v0, stream, nullptr, nullptr, nullptr,
-                           nullptr, 1);
+                           nullptr, 1, sort_passes(dbits) > 0 ? 1 : 0);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
