@@ -31,7 +31,7 @@
 namespace recogs {
 
 int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                   hipStream_t, const EmitFold * = nullptr);
+                   hipStream_t, const EmitFold * = nullptr, bool = false);
 void launch_ranges32(const uint32_t *, uint32_t, uint2 *, hipStream_t, const uint32_t *);
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_excl_scan_u32(uint32_t *, uint32_t, uint32_t *, hipStream_t);

@@ -152,7 +152,6 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint64_t *__restrict__ pk, ui
 // key offset (eoff), and efirst[b] = the compacted Gaussian owning key b * kEmitKeys for
 // the blocks b < nblk of the key capacity.
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }   // LDS padding: no 16-way bank conflicts
-constexpr uint32_t kEmitKeys = 2048;   // keys per workgroup of k_emit_down (256 threads x 8)
 // With few chunks the down pass scans the chunk partials itself (FOLD): each workgroup
 // sums the partials of the chunks before its own, and workgroup 0 also the totals and
 // the depth range, which it writes to the header as k_scan_top would; one launch fewer.
@@ -569,7 +568,7 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
                                                    const uint32_t *__restrict__ efirst, int tiles_x,
                                                    uint32_t *__restrict__ tkeys, uint32_t *__restrict__ tvals,
                                                    const uint32_t *dynV, const uint32_t *dynK, const uint32_t *overflow,
-                                                   const uint4 *__restrict__ vtab, int nviews) {
+                                                   const uint4 *__restrict__ vtab, int nviews, KeyCount kc) {
     if (dynV) V = *dynV;
     if (dynK) K = *dynK;
     if (overflow && *overflow) return;
@@ -582,7 +581,10 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
     __shared__ uint2 s_rect[256];
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_end;
+    __shared__ uint32_t s_kc[256];
     const uint32_t t = threadIdx.x;
+    const uint32_t kmask = (1u << kc.nbits) - 1u;
+    if (kc.cnt) s_kc[t] = 0u;   // (the first round's barriers order these before the adds)
     uint32_t g = efirst[blockIdx.x];  // owns key k0
     uint32_t kb = k0;
     while (kb < k1) {
@@ -639,13 +641,16 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
             const uint32_t tx0 = rc.x & 0xffffu, tx1 = rc.x >> 16, ty0 = rc.y & 0xffffu;
             const uint32_t wd = tx1 - tx0 + 1;
             const uint32_t ty = ty0 + k / wd, tx = tx0 + k % wd;
-            tkeys[q] = s_tb[i] + ty * s_tx[i] + tx;
+            const uint32_t tile = s_tb[i] + ty * s_tx[i] + tx;
+            tkeys[q] = tile;
             tvals[q] = s_val[i];
+            if (kc.cnt) atomicAdd(&s_kc[tile & kmask], 1u);
         }
         __syncthreads();
         kb = ke;
         g += 256;
     }
+    if (kc.cnt && t <= kmask) kc.cnt[(size_t)t * kc.chunks + blockIdx.x] = s_kc[t];
 }
 
 // [first, last+1) of each tile in tile-sorted 32-bit tile ids (ranges zeroed beforehand).
@@ -814,18 +819,20 @@ void launch_scan(const uint32_t *cnt, const uint32_t *zbits, uint32_t *off, int6
 // and block owners (k_emit_down). V and K are counts or, with dynV / dynK, bounds.
 void launch_emit_compacted(const uint32_t *order, uint32_t V, const uint2 *srect, const uint32_t *eoff,
                            const uint32_t *efirst, uint32_t K, int tiles_x, uint32_t *tkeys, uint32_t *tvals, hipStream_t st,
-                           const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr, const uint4 *vtab, int nviews) {
+                           const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr, const uint4 *vtab, int nviews,
+                           const KeyCount *kc) {
     if (V == 0 || K == 0) return;
     const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
+    const KeyCount none{nullptr, 0u, 0};
     hipLaunchKernelGGL(k_emit_down, dim3(nblk), dim3(256), 0, st, order, V, K, srect, eoff, efirst, tiles_x, tkeys, tvals,
-                       dynV, dynK, hdr ? hdr + H_OVERFLOW : nullptr, vtab, nviews);
+                       dynV, dynK, hdr ? hdr + H_OVERFLOW : nullptr, vtab, nviews, kc ? *kc : none);
 }
 
 // V is the count or, with dynV, its upper bound; hdr (optional) supplies the overflow flag.
 void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, uint2 *srect, int tiles_x,
                         uint32_t *esum, uint32_t *eoff, uint32_t *efirst, uint32_t K, uint32_t *tkeys, uint32_t *tvals,
                         hipStream_t st, const uint32_t *dynV, const uint32_t *dynK, const uint32_t *hdr,
-                        const uint4 *vtab, int nviews, int folded) {
+                        const uint4 *vtab, int nviews, int folded, const KeyCount *kc) {
     if (V == 0 || K == 0) return;
     const uint32_t chunks = (V + kEmitChunk - 1) / kEmitChunk;
     const uint32_t nblk = (K + kEmitKeys - 1) / kEmitKeys;
@@ -836,8 +843,9 @@ void launch_emit_sorted(const uint32_t *order, uint32_t V, const uint2 *rect, ui
     const int fold = chunks <= 2048u;
     if (!fold) hipLaunchKernelGGL(k_scan_top_u32, dim3(1), dim3(1024), 0, st, esum, chunks);
     hipLaunchKernelGGL(k_emit_offsets, dim3(chunks), dim3(256), 0, st, srect, V, esum, eoff, efirst, nblk, dynV, ovf, fold);
+    const KeyCount none{nullptr, 0u, 0};
     hipLaunchKernelGGL(k_emit_down, dim3(nblk), dim3(256), 0, st, order, V, K, srect, eoff, efirst, tiles_x, tkeys, tvals,
-                       dynV, dynK, ovf, vtab, nviews);
+                       dynV, dynK, ovf, vtab, nviews, kc ? *kc : none);
 }
 
 uint32_t emit_blocks(uint32_t K) { return (K + kEmitKeys - 1) / kEmitKeys; }

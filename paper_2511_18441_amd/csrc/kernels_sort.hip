@@ -238,25 +238,30 @@ int sort_passes(int total_bits) { return (total_bits + 7) / 8; }
 // there are enough keys to fill the GPU with them, shorter ones otherwise
 static int sort_items(uint32_t K) { return K >= (1u << 22) ? 16 : (K >= (1u << 20) ? 8 : 4); }
 
-// words of the digit-count matrix a sort of K keys needs, and the most any sort of at
-// most K_max keys needs (the chunk length grows with K, so the need is not monotonic)
-static size_t count_words(uint64_t K) {
-    const uint64_t kk = K > 0xffffffffull ? 0xffffffffull : K;
-    const uint64_t chunk = 256ull * (uint64_t)sort_items((uint32_t)kk);
-    const uint64_t chunks = (K + chunk - 1) / chunk;
+// Words of the digit-count matrix any sort of at most K_max keys needs: chunks of the
+// shortest length (1,024 keys), whatever length a sort takes or is given.
+size_t sort_count_words(uint64_t K_max) {
+    const uint64_t chunks = (K_max + 1023) / 1024;
     return 256 * (size_t)(chunks > 0 ? chunks : 1);
 }
-size_t sort_count_words(uint64_t K_max) {
-    const uint64_t a = K_max < (1ull << 20) - 1 ? K_max : (1ull << 20) - 1;
-    const uint64_t b = K_max < (1ull << 22) - 1 ? K_max : (1ull << 22) - 1;
-    const size_t wa = count_words(a), wb = count_words(b), wc = count_words(K_max);
-    return wa > wb ? (wa > wc ? wa : wc) : (wb > wc ? wb : wc);
+
+// The first pass of a sort whose digit counts the key emission writes (KeyCount): the
+// sort then runs with chunks of 2,048 keys (kKeyCountItems per thread).
+constexpr int kKeyCountItems = 8;
+static_assert(256u * kKeyCountItems == kEmitKeys, "a counted chunk is one emission block");
+KeyCount key_sort_first_count(uint32_t *cnt, uint32_t K_max, int total_bits) {
+    if (total_bits <= 0) return KeyCount{nullptr, 0u, 0};   // one tile: no pass to count for
+    const int passes = sort_passes(total_bits);
+    const int per = (total_bits + passes - 1) / passes;
+    const uint32_t chunk = 256u * (uint32_t)kKeyCountItems;
+    return KeyCount{cnt, (K_max + chunk - 1) / chunk, per < total_bits ? per : total_bits};
 }
 
 template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
                       uint32_t *ghist, uint32_t *cnt, hipStream_t st, const uint32_t *dyn_count = nullptr,
-                      const uint32_t *dyn_zmin = nullptr, const EmitFold *ef = nullptr, int first_shift = 0) {
+                      const uint32_t *dyn_zmin = nullptr, const EmitFold *ef = nullptr, int first_shift = 0,
+                      bool first_counted = false) {
     if (K == 0 || total_bits == 0) return 0;   // K is the count, or its upper bound with dyn_count
     const int passes = sort_passes(total_bits);
     const int per = (total_bits + passes - 1) / passes;
@@ -267,7 +272,8 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         bits |= (uint32_t)nb << (4 * p);
         rem -= nb;
     }
-    const int items = sort_items(K);
+    // first_counted: the first pass's counts are in cnt already (KeyCount), in its chunks
+    const int items = first_counted ? kKeyCountItems : sort_items(K);
     const uint32_t chunk_keys = 256u * (uint32_t)items;
     const uint32_t chunks = (K + chunk_keys - 1) / chunk_keys;
     const EmitFold none{nullptr, nullptr, nullptr, 0u};
@@ -281,8 +287,9 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
         uint32_t *tot = ghist + 256 * p;
         const bool fold = ef && p == passes - 1;
 #define RECOGS_PASS(IT)                                                                                                    \
-    hipLaunchKernelGGL((k_radix_up<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb, cnt,    \
-                       chunks, dyn_count, dyn_zmin);                                                                       \
+    if (p > 0 || !first_counted)                                                                                           \
+        hipLaunchKernelGGL((k_radix_up<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb,     \
+                           cnt, chunks, dyn_count, dyn_zmin);                                                              \
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, chunk_keys, tot, K, dyn_count);     \
     if (fold)                                                                                                              \
         hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT, true>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K,    \
@@ -312,9 +319,11 @@ int radix_sort_tile_depth64(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *
 }
 
 // ef (optional): the depth order's last pass also does the emission fold.
+// first_counted: the key emission wrote the first pass's counts (key_sort_first_count).
 int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K, uint32_t sub, int total_bits,
-                   uint32_t *ghist, uint32_t *cnt, hipStream_t st, const EmitFold *ef) {
-    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st, nullptr, nullptr, ef);
+                   uint32_t *ghist, uint32_t *cnt, hipStream_t st, const EmitFold *ef, bool first_counted) {
+    return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K, sub, 0, total_bits, ghist, cnt, st, nullptr, nullptr, ef, 0,
+                                        first_counted);
 }
 
 // The same with the count and the subtracted minimum read from device memory; K_max
@@ -322,9 +331,9 @@ int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint3
 // first_shift of the key (bits below it already ordered by an earlier pass).
 int radix_sort_u32_dyn(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K_max, const uint32_t *dyn_count,
                        const uint32_t *dyn_sub, int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st,
-                       const EmitFold *ef, int first_shift) {
+                       const EmitFold *ef, int first_shift, bool first_counted) {
     return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K_max, 0u, 0, total_bits, ghist, cnt, st, dyn_count, dyn_sub, ef,
-                                        first_shift);
+                                        first_shift, first_counted);
 }
 
 }  // namespace recogs

@@ -256,6 +256,16 @@ struct ScanSort {
     uint32_t *vals;
 };
 
+// The first pass of the key sort counted by the key emission: block b of the emission
+// (its keys [2048 b, 2048 b + 2048)) is chunk b of that pass, whose digit counts (the
+// low nbits of the tile id) it writes to cnt[digit * chunks + b].
+struct KeyCount {
+    uint32_t *cnt;   // null: not counted
+    uint32_t chunks;
+    int nbits;
+};
+
+constexpr uint32_t kEmitKeys = 2048;                 // keys per workgroup of k_emit_down (256 threads x 8)
 constexpr int kScanItems = 16;                       // counts per thread of the scan
 constexpr int kScanChunk = 256 * kScanItems;         // counts per scan workgroup
 constexpr int kMaxPasses = 8;

@@ -24,12 +24,12 @@ void launch_emit(const uint32_t *, const uint32_t *, const uint2 *, const uint32
                  hipStream_t);
 void launch_emit_compacted(const uint32_t *, uint32_t, const uint2 *, const uint32_t *, const uint32_t *, uint32_t, int,
                            uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *, const uint32_t *,
-                           const uint4 *, int);
+                           const uint4 *, int, const KeyCount * = nullptr);
 void launch_tile_depth_sort(const uint2 *, uint32_t, uint32_t *, const uint32_t *, const uint32_t *, uint32_t *, uint32_t *,
                             hipStream_t);
 void launch_emit_sorted(const uint32_t *, uint32_t, const uint2 *, uint2 *, int, uint32_t *, uint32_t *, uint32_t *,
                         uint32_t, uint32_t *, uint32_t *, hipStream_t, const uint32_t *, const uint32_t *,
-                        const uint32_t *, const uint4 *, int, int = 0);
+                        const uint32_t *, const uint4 *, int, int = 0, const KeyCount * = nullptr);
 uint32_t emit_blocks(uint32_t K);
 size_t sort_count_words(uint64_t K_max);
 void launch_ranges(const uint64_t *, uint32_t, uint2 *, hipStream_t);
@@ -40,7 +40,7 @@ int sort_passes(int total_bits);
 int radix_sort_tile_depth64(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint32_t, uint32_t, int, int, uint32_t *,
                             uint32_t *, hipStream_t);
 int radix_sort_u32(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, uint32_t, int, uint32_t *, uint32_t *,
-                   hipStream_t, const EmitFold * = nullptr);
+                   hipStream_t, const EmitFold * = nullptr, bool = false);
 bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *, const uint32_t *,
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
@@ -66,7 +66,8 @@ size_t outlier_workspace_bytes(int64_t);
 bool launch_outliers(const float *, int64_t, int64_t, int, float, float *, uint8_t *, float *, int64_t, uint32_t *, void *,
                      hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
-                       uint32_t *, uint32_t *, hipStream_t, const EmitFold * = nullptr, int = 0);
+                       uint32_t *, uint32_t *, hipStream_t, const EmitFold * = nullptr, int = 0, bool = false);
+KeyCount key_sort_first_count(uint32_t *, uint32_t, int);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
                              hipStream_t);
 void launch_tile_order(const uint2 *, uint32_t, uint32_t *, uint32_t *, uint32_t *, hipStream_t);
@@ -378,6 +379,8 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     ws->key_bytes = 4;
     int alt = 0;
     if (n > 0 && cap > 0) {
+        // the emission counts the key sort's first digit (KeyCount)
+        const KeyCount kc = key_sort_first_count(scount, cap, tbits);
         if (mode == 0) {
             // the depth order's rectangles go to keys1, free until the key sort (cap entries;
             // past them the view overflows and emits nothing)
@@ -391,14 +394,14 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
             if ((s = tm.mark(4)) != RECOGS_OK) return s;
             launch_emit_sorted(order, (uint32_t)n, at<uint2>(ws, ws->off_rect), srect, cd.tiles_x,
                                at<uint32_t>(ws, ws->off_esum), spare, at<uint32_t>(ws, ws->off_efirst), cap, t0, v0, stream,
-                               hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1, 1);
+                               hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1, 1, &kc);
         } else {
             if ((s = tm.mark(4)) != RECOGS_OK) return s;
             launch_emit_compacted(dv0, (uint32_t)n, (const uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst), cap,
-                                  cd.tiles_x, t0, v0, stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1);
+                                  cd.tiles_x, t0, v0, stream, hdr + H_V, hdr + H_KEFF, hdr, nullptr, 1, &kc);
         }
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        alt = radix_sort_u32_dyn(t0, v0, t1, v1, cap, hdr + H_KEFF, nullptr, tbits, hist, scount, stream);
+        alt = radix_sort_u32_dyn(t0, v0, t1, v1, cap, hdr + H_KEFF, nullptr, tbits, hist, scount, stream, nullptr, 0, true);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, cap, ranges, stream, hdr + H_KEFF);
         if ((s = tm.mark(7)) != RECOGS_OK) return s;
@@ -630,11 +633,12 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         // per-Gaussian key offsets go to the depth-value buffer the sort left free; with no
         // sort pass (a single depth) the emission does its own reduce
+        const KeyCount kc = key_sort_first_count(scount, (uint32_t)K, key_bits);
         launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1,
                            at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, t0, v0, stream, nullptr, nullptr, nullptr,
-                           nullptr, 1, sort_passes(dbits) > 0 ? 1 : 0);
+                           nullptr, 1, sort_passes(dbits) > 0 ? 1 : 0, &kc);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
+        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream, nullptr, true);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream, nullptr);
         if ((s = tm.mark(7)) != RECOGS_OK) return s;
@@ -643,10 +647,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         // tile's list sorted by depth
         uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
+        const KeyCount kc = key_sort_first_count(scount, (uint32_t)K, key_bits);
         launch_emit_compacted(dv0, V, (const uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, cd.tiles_x,
-                              t0, v0, stream, nullptr, nullptr, nullptr, nullptr, 1);
+                              t0, v0, stream, nullptr, nullptr, nullptr, nullptr, 1, &kc);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
-        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream);
+        alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream, nullptr, true);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
         launch_ranges32(alt ? t1 : t0, (uint32_t)K, ranges, stream, nullptr);
         if ((s = tm.mark(7)) != RECOGS_OK) return s;
