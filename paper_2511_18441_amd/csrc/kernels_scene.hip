@@ -71,21 +71,31 @@ __global__ __launch_bounds__(256) void k_select(SceneDev sc, CamDev cam, float s
 }
 
 // Recolour on coefficients: C'_k = M C_k (k >= 1), C'_0 = M C_0 + ((M - I) 1/2 + b)/Y00.
+// A thread reads the mask bytes of four consecutive Gaussians with one load.
+constexpr int kRecolorPer = 4;
 template <int DT>
 __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *__restrict__ dst,
                                                  const uint8_t *__restrict__ mask, const float *__restrict__ Mp,
                                                  const float *__restrict__ bp, int copy_unselected) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < sc.n;
-    const bool sel = valid && mask[i] != 0;
-    if (valid && !sel && copy_unselected && dst != sc.sh)
-        for (int p = 0; p < ncoef * 3; ++p) Store<DT>::st(dst, p * sc.stride + i, Store<DT>::ldc(sc.sh, p * sc.stride + i));
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRecolorPer;
+    uint32_t sel = 0;   // byte k: Gaussian i0 + k selected
+    if (i0 + kRecolorPer <= sc.n && ((uintptr_t)mask & 3u) == 0) {
+        sel = *reinterpret_cast<const uint32_t *>(mask + i0);
+    } else {
+        for (int k = 0; k < kRecolorPer; ++k)
+            if (i0 + k < sc.n && mask[i0 + k]) sel |= 1u << (8 * k);
+    }
+    if (copy_unselected && dst != sc.sh)
+        for (int k = 0; k < kRecolorPer; ++k)
+            if (i0 + k < sc.n && !((sel >> (8 * k)) & 0xffu))
+                for (int p = 0; p < ncoef * 3; ++p)
+                    Store<DT>::st(dst, p * sc.stride + i0 + k, Store<DT>::ldc(sc.sh, p * sc.stride + i0 + k));
     // The selected Gaussians of the wave (a sparse selection leaves about one per wave)
     // are recoloured one after the other by the whole wave: lane k takes coefficient k's
     // three planes, so a Gaussian costs three loads and three stores of up to 16 lanes
     // each instead of 48 of each from one lane. A lane loads its planes before it
     // stores them, so the destination may alias the source.
-    uint64_t m = wave_ballot(sel);
+    uint64_t m = wave_ballot(sel != 0u);
     if (!m) return;
     float M[9], off[3];
 #pragma unroll
@@ -93,19 +103,25 @@ __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *_
 #pragma unroll
     for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bp[r]) / kSH0;
     const int l = (int)lane_id();
-    const int64_t wbase = i - l;   // the Gaussian of lane 0
+    const int64_t wbase = i0 - (int64_t)l * kRecolorPer;   // the first Gaussian of lane 0
     while (m) {
-        const int64_t g = wbase + (int64_t)__builtin_ctzll(m);
+        const int src = __builtin_ctzll(m);
         m &= m - 1;
-        if (l < ncoef) {
-            const float c0 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l) * sc.stride + g);
-            const float c1 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 1) * sc.stride + g);
-            const float c2 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 2) * sc.stride + g);
+        uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)sel, src);
+        while (bits) {
+            const int k = __builtin_ctz(bits) >> 3;
+            bits &= ~(0xffu << (8 * k));
+            const int64_t g = wbase + (int64_t)src * kRecolorPer + k;
+            if (l < ncoef) {
+                const float c0 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l) * sc.stride + g);
+                const float c1 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 1) * sc.stride + g);
+                const float c2 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 2) * sc.stride + g);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
-                if (l == 0) v += off[r];
-                Store<DT>::st(dst, (int64_t)(3 * l + r) * sc.stride + g, v);
+                for (int r = 0; r < 3; ++r) {
+                    float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
+                    if (l == 0) v += off[r];
+                    Store<DT>::st(dst, (int64_t)(3 * l + r) * sc.stride + g, v);
+                }
             }
         }
     }
@@ -133,7 +149,8 @@ void launch_select(int dt, const SceneDev &sc, const CamDev &cam, const recogs_s
 void launch_recolor(int dt, const SceneDev &sc, int ncoef, void *dst, const uint8_t *mask, const float *M,
                     const float *b, int copy_unselected, hipStream_t st) {
     if (sc.n <= 0) return;
-    const dim3 g((unsigned)((sc.n + 255) / 256)), bl(256);
+    const int64_t threads = (sc.n + kRecolorPer - 1) / kRecolorPer;
+    const dim3 g((unsigned)((threads + 255) / 256)), bl(256);
     if (dt == RECOGS_F32) hipLaunchKernelGGL(k_recolor<RECOGS_F32>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);
     else if (dt == RECOGS_F16) hipLaunchKernelGGL(k_recolor<RECOGS_F16>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);
     else hipLaunchKernelGGL(k_recolor<RECOGS_BF16>, g, bl, 0, st, sc, ncoef, dst, mask, M, b, copy_unselected);

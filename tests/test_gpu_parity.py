@@ -66,13 +66,21 @@ def test_select(R, orc, cfg, storage):
 @pytest.mark.parametrize("which", ["affine", "hue"])
 def test_recolor(R, orc, storage, which):
     import torch
-    w = synth.make_mid(n=60_000)
+    # the hue case: a ragged count (not a multiple of the 4 mask bytes a thread reads)
+    # and a mask that does not start on a 4-byte boundary (read byte by byte)
+    w = synth.make_mid(n=60_000 if which == "affine" else 60_003)
     sc = w.scene if storage == "f32" else w.scene.with_storage(storage)
     rng = np.random.default_rng(3)
     maskn = (rng.random(sc.n) < 0.3).astype(np.uint8)
     rec = w.view.recolor if which == "affine" else synth.RecolorParams(synth.hue_rotation(120.0), np.zeros(3, np.float32))
     d = R.DeviceScene(sc)
-    mask = torch.from_numpy(maskn).cuda()
+    if which == "affine":
+        mask = torch.from_numpy(maskn).cuda()
+    else:
+        mbuf = torch.zeros(sc.n + 4, dtype=torch.uint8, device="cuda")
+        mbuf[1:sc.n + 1] = torch.from_numpy(maskn).cuda()
+        mask = mbuf[1:sc.n + 1]
+        assert mask.data_ptr() % 4 == 1
     M = torch.from_numpy(rec.M.reshape(9)).cuda()
     b = torch.from_numpy(rec.b).cuda()
     dst = d.sh.clone()
