@@ -193,7 +193,7 @@ typedef struct {
     int32_t key_bytes;           /* 8: sorted keys are (tile << 32) | depth bits; 4: tile ids */
     int32_t sorted_in_alt;       /* 1 if the sorted keys/values are in keys1/vals1 */
     int32_t sort_passes;         /* passes over the K keys */
-    int32_t depth_passes;        /* passes over the V depth keys (sort_mode 0) */
+    int32_t depth_passes;        /* sort_mode 0: passes over the V depth keys after the count scan's (which orders them by their low 8 depth bits) */
     int32_t key_bits;            /* significant bits sorted: tile bits + depth bits */
     int32_t depth_bits;
     uint32_t depth_min_bits;     /* smallest float32 depth bit pattern among keys */

@@ -375,7 +375,7 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
     ws->depth_min_bits = 0;
     ws->key_bits = tbits + 32;
     ws->sort_passes = sort_passes(tbits);
-    ws->depth_passes = mode == 0 ? sort_passes(32) : 0;
+    ws->depth_passes = mode == 0 ? sort_passes(24) : 0;   // after the scan's pass
     ws->key_bytes = 4;
     int alt = 0;
     if (n > 0 && cap > 0) {
@@ -580,11 +580,12 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
         // tile-first order: the compaction carries rectangles (over both depth-key buffers,
         // adjacent), key offsets (dvals1) and the emission blocks' owners
         const ScanEmit em{rect, (uint2 *)dk0, dv1, at<uint32_t>(ws, ws->off_efirst)};
-        // depth-first order without read-back: the scan also does the depth sort's first
-        // pass (on the raw depth bits: the same order as above the minimum), into dkeys1
+        // depth-first order: the scan also does the depth sort's first pass, on the low 8
+        // raw depth bits (the minimum is not known yet; raw bits give the same order), into
+        // dkeys1
         const ScanSort so{at<uint32_t>(ws, ws->off_sort_count), at<uint32_t>(ws, ws->off_dhist), dk1, dv1};
         launch_scan(cnt, zb, off, n, pk, pv, pv + sc_n, pv + 2 * sc_n, dk0, dv0, hdr, ws->key_capacity, stream,
-                    mode == 2 ? &em : nullptr, (mode == 0 && opts->graph_mode) ? &so : nullptr);
+                    mode == 2 ? &em : nullptr, mode == 0 ? &so : nullptr);
     }
     if ((s = tm.mark(2)) != RECOGS_OK) return s;
     if ((s = hip_check("preprocess/scan")) != RECOGS_OK) return s;
@@ -612,7 +613,11 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     ws->depth_min_bits = zmin;
     ws->key_bits = tbits + dbits;
     ws->sort_passes = K ? sort_passes(key_bits) : 0;
-    ws->depth_passes = (mode == 0 && V) ? sort_passes(dbits) : 0;
+    // sort mode 0: raw depth bits up to the highest one in which the depths differ; the
+    // scan sorted bits 0-7, the depth sort takes the rest
+    const int rbits = K ? bits_for((uint64_t)(zmin ^ zmax)) : 0;
+    const int rest_bits = rbits > 8 ? rbits - 8 : 0;
+    ws->depth_passes = (mode == 0 && V) ? sort_passes(rest_bits) : 0;
     ws->key_bytes = mode == 1 ? 8 : 4;
 
     // (histograms, emission sums and tile ranges zeroed by the preprocess launch)
@@ -623,20 +628,23 @@ recogs_status recogs_render(const recogs_scene *scene, const recogs_camera *cam,
     uint32_t *v0 = at<uint32_t>(ws, ws->off_vals0), *v1 = at<uint32_t>(ws, ws->off_vals1);
     int alt = 0;
     if (K > 0 && mode == 0) {
-        // depth sort of the V Gaussians with keys (compacted in index order by the scan);
-        // its last pass gathers the depth-ordered rectangles (8 bytes each) into keys1, free
-        // until the key sort (K <= cap, so V <= cap), and sums the emission chunks' counts
+        // the rest of the depth sort of the V Gaussians with keys (the scan left them ordered
+        // by their low 8 depth bits in dkeys1); its last pass gathers the depth-ordered
+        // rectangles (8 bytes each) into keys1, free until the key sort (K <= cap, so
+        // V <= cap), and sums the emission chunks' counts
         uint32_t *t0 = (uint32_t *)k0, *t1 = (uint32_t *)k1;
         uint2 *srect = (uint2 *)k1;
         const EmitFold ef{rect, srect, at<uint32_t>(ws, ws->off_esum), (uint32_t)ws->key_capacity};
-        const int dalt = radix_sort_u32(dk0, dv0, dk1, dv1, V, zmin, dbits, dhist, scount, stream, &ef);
+        const int dalt = radix_sort_u32_dyn(dk1, dv1, dk0, dv0, V, nullptr, nullptr, rest_bits, dhist + 256, scount,
+                                            stream, &ef, 8);
+        uint32_t *order = dalt ? dv0 : dv1, *spare = dalt ? dv1 : dv0;
         if ((s = tm.mark(4)) != RECOGS_OK) return s;
         // per-Gaussian key offsets go to the depth-value buffer the sort left free; with no
-        // sort pass (a single depth) the emission does its own reduce
+        // pass left (depths equal above bit 7) the emission does its own reduce
         const KeyCount kc = key_sort_first_count(scount, (uint32_t)K, key_bits);
-        launch_emit_sorted(dalt ? dv1 : dv0, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), dalt ? dv0 : dv1,
+        launch_emit_sorted(order, V, rect, srect, cd.tiles_x, at<uint32_t>(ws, ws->off_esum), spare,
                            at<uint32_t>(ws, ws->off_efirst), (uint32_t)K, t0, v0, stream, nullptr, nullptr, nullptr,
-                           nullptr, 1, sort_passes(dbits) > 0 ? 1 : 0, &kc);
+                           nullptr, 1, rest_bits > 0 ? 1 : 0, &kc);
         if ((s = tm.mark(5)) != RECOGS_OK) return s;
         alt = radix_sort_u32(t0, v0, t1, v1, (uint32_t)K, 0u, key_bits, hist, scount, stream, nullptr, true);
         if ((s = tm.mark(6)) != RECOGS_OK) return s;
