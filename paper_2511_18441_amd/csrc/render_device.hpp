@@ -49,8 +49,9 @@ __device__ __forceinline__ void view_basis(const CamDev &cam, float mx, float my
 //   to the grid. The record keeps the box: the blend's region test stays exact.
 //   Colour max(0, f + 1/2) or, for selected Gaussians of a fused recolour,
 //   max(0, M (f + 1/2) + b).
-// Writes the splat record, depth bits, packed tile rectangle and count; folds the
-// depth range of Gaussians with keys into the workspace header.
+// Writes the splat record, depth bits, packed tile rectangle and count (the count
+// scan reduces the depth range). The colour is evaluated for every Gaussian, so its
+// coefficient loads go out with the position and covariance loads, ahead of the culls.
 // ---------------------------------------------------------------------------
 // Gaussian i of the scene, outputs at index o (o = i for one view; the (view,
 // Gaussian) pair index in a batch).
@@ -64,6 +65,21 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev 
     {
         const int64_t S = sc.stride;
         const float mx = sc.means[i], my = sc.means[S + i], mz = sc.means[2 * S + i];
+        // colour (eq. 2) at the view direction of the centre, for every Gaussian: its
+        // coefficient loads are issued with the others, before any cull decision
+        constexpr int NC = (DEG + 1) * (DEG + 1);
+        float f[3];
+        {
+            float Y[16];
+            view_basis<DEG>(cam, mx, my, mz, Y);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) acc += Store<DT>::ld(sc.sh, (int64_t)(k * 3 + c) * S + i) * Y[k];
+                f[c] = acc + 0.5f;
+            }
+        }
         const float z = dot3c(cam.R[6], mx, cam.R[7], my, cam.R[8], mz, cam.t[2]);
         zb = __float_as_uint(z);
         if (z > cam.znear) {
@@ -125,18 +141,6 @@ __device__ __forceinline__ void preprocess_one(const SceneDev &sc, const CamDev 
                         }
                     }
                     if (cnt > 0) {
-                        // colour (eq. 2) at the view direction of the centre
-                        constexpr int NC = (DEG + 1) * (DEG + 1);
-                        float Y[16];
-                        view_basis<DEG>(cam, mx, my, mz, Y);
-                        float f[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            float acc = 0.f;
-#pragma unroll
-                            for (int k = 0; k < NC; ++k) acc += Store<DT>::ld(sc.sh, (int64_t)(k * 3 + c) * S + i) * Y[k];
-                            f[c] = acc + 0.5f;
-                        }
                         float pre[3] = {f[0], f[1], f[2]};
                         uint32_t flags = 0;
                         if (rc.mask && rc.mask[i]) {
