@@ -117,9 +117,10 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, fl
 // derivatives of S in those maps. Two passes over 16 x 16 output tiles, each with its
 // 26 x 26 input halo in LDS, blurred along x then along y:
 //   k_ssim_fwd: a workgroup per (tile, channel): the three maps a, b, c per pixel and
-//               the tile's sum of S (k_ssim_loss adds the sums in a fixed order);
+//               the tile's sum of S;
 //   k_ssim_bwd: a workgroup per tile, the channels in turn: the blurs of a, b, c and the
-//               gradient.
+//               gradient; its first workgroup first adds the tiles' sums in a fixed
+//               order (the loss).
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kSsimR = 5;                     // window radius (11 taps)
@@ -199,29 +200,40 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, c
     ssum = wave_sum(ssum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = ssum;
     __syncthreads();
-    // the workgroup's sum of S, added to the others in a fixed order by k_ssim_loss
+    // the workgroup's sum of S, added to the others in a fixed order by the backward
     if (threadIdx.x == 0)
         part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
 
 // loss = weight + neg_scale * (sum of the n partial sums), the partials added in a fixed
-// order (one workgroup): the loss is the same bits on every run
-__global__ __launch_bounds__(256) void k_ssim_loss(const float *__restrict__ part, uint32_t n, float weight,
-                                                   float neg_scale, float *__restrict__ loss) {
-    __shared__ float s_w[4];
+// order by one workgroup (thread t: entries t, t + 256, ... in turn, then the waves'
+// sums): the loss is the same bits on every run. Eight loads in flight per thread.
+__device__ __forceinline__ void ssim_loss_sum(const float *__restrict__ part, uint32_t n, float weight, float neg_scale,
+                                              float *__restrict__ loss, float *s_w /* [4] */) {
     float acc = 0.f;
-    for (uint32_t k = threadIdx.x; k < n; k += 256) acc += part[k];
+    for (uint32_t k0 = threadIdx.x; k0 < n; k0 += 256u * 8u) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = k0 + 256u * i < n ? part[k0 + 256u * i] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (k0 + 256u * i < n) acc += v[i];
+    }
     acc = wave_sum(acc);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) *loss = weight + neg_scale * (((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]);
 }
 
+// part / nparts / weight / loss: the loss, summed by workgroup (0, 0) before its tile
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
                                                   SsimWindow win, const float *__restrict__ maps, float gscale,
-                                                  int accumulate, float *__restrict__ dldy) {
+                                                  int accumulate, float *__restrict__ dldy, const float *__restrict__ part,
+                                                  uint32_t nparts, float weight, float *__restrict__ loss) {
     __shared__ float s_m[3][kSsimH * kSsimH];
     __shared__ float s_h[3][kSsimH][kSsimT];
+    __shared__ float s_lw[4];
+    if (blockIdx.x == 0 && blockIdx.y == 0) ssim_loss_sum(part, nparts, weight, gscale, loss, s_lw);
     const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
     const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
     const int px = ox + tx, py = oy + ty;
@@ -311,10 +323,8 @@ void launch_dssim(const float *y, const float *t, int W, int H, float weight, fl
     const dim3 grid((unsigned)((W + kSsimT - 1) / kSsimT), (unsigned)((H + kSsimT - 1) / kSsimT), 3u);
     float *part = maps + (size_t)9 * (size_t)W * (size_t)H;
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, part);
-    hipLaunchKernelGGL(k_ssim_loss, dim3(1), dim3(256), 0, st, part, grid.x * grid.y * grid.z, weight, (float)(-weight / N),
-                       loss);
     hipLaunchKernelGGL(k_ssim_bwd, dim3(grid.x, grid.y), dim3(256), 0, st, y, t, W, H, win, maps, (float)(-weight / N),
-                       accumulate, dldy);
+                       accumulate, dldy, part, grid.x * grid.y * grid.z, weight, loss);
 }
 
 }  // namespace recogs
