@@ -423,7 +423,9 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     the 8 views at 1280x720 taken in turn, one per step: render keeping the backward
     state, the loss of eq. 4 (0.8 L1 + 0.2 (1 - SSIM)) against the view recoloured by the
     target matrix (plus seeded noise), the gradient of every SH coefficient, one Adam
-    step on all of them."""
+    step on all of them, with the two loss terms as two calls and the gradient written
+    and read back (`ms_per_step`); `ms_per_step_fused_adam` is the same step with both
+    loss terms in one pass and the Adam update inside the SH-gradient pass."""
     import torch
 
     import synth
@@ -474,16 +476,16 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
                                     dsh.data_ptr(), dM.data_ptr())
         R.recogs_adam_step(sh.data_ptr(), dsh.data_ptr(), m.data_ptr(), v.data_ptr(), sh.numel(), 2e-3,
                            step=state["step"])
+    lfs = torch.zeros(len(w.views), dtype=torch.float32, device=dev)
+
     def step_fused():
-        # the same step with the SH backward and the Adam step fused (the gradient does
-        # not go through memory)
+        # the same step with both loss terms in one pass and the SH backward and the Adam
+        # step fused (the gradient does not go through memory)
         k = state["step"] % len(w.views)
         state["step"] += 1
         R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE)
-        R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
-                         loss.data_ptr() + 4 * k)
-        R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
-                            sws.data_ptr(), nb)
+        R.recogs_loss_l1_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, (1.0 - lam) / cnt_px, lam, dimg.data_ptr(),
+                               0, lfs.data_ptr() + 4 * k, sws.data_ptr(), nb)
         R.recogs_render_backward_sh_adam(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
                                          dM.data_ptr(), m.data_ptr(), v.data_ptr(), 2e-3, step=state["step"])
     for _ in range(max(8, warmup)):
@@ -506,7 +508,7 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "backward_form": BWD_FORM, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps, "ms_per_step_fused_adam": round(ms_fused, 3),
             "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first, "loss_mean_end": end,
-            "loss_mean_after_fused_steps": float((loss + lss).mean().item())}
+            "loss_mean_after_fused_steps": float(lfs.mean().item())}
 
 
 def _event_ms(fn, reps):
@@ -604,8 +606,9 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     rendered. Per step (one view, in turn): render the current SH keeping the backward
     state and the rough depth map, draw the cloud into the view as its mask (2 px squares,
     depth test with 1% slack), tint the view's original image there (t = (1, 0.6, 0.5)),
-    the loss of eq. 4 against it, the gradient of every SH coefficient and one Adam step,
-    fused (the gradient goes straight into the update, never to memory)."""
+    the loss of eq. 4 against it (both terms in one pass), the gradient of every SH
+    coefficient and one Adam step, fused (the gradient goes straight into the update,
+    never to memory)."""
     import torch
 
     import synth
@@ -653,10 +656,9 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
                  sort_mode=SORT_MODE)
         R.recogs_reproject_mask(cams[k], cloud.data_ptr(), n_pts, n_pts, 2.0, depth.data_ptr(), 0.01, vmask.data_ptr())
         R.recogs_tint(originals[k].data_ptr(), vmask.data_ptr(), t, target.data_ptr(), H * W)
-        R.recogs_loss_l1(img.data_ptr(), target.data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
-                         loss.data_ptr() + 4 * k)
-        R.recogs_loss_dssim(img.data_ptr(), target.data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
-                            sws.data_ptr(), nb)
+        # eq. 4 in one pass (L1 and SSIM terms; the L1 slots stay zero)
+        R.recogs_loss_l1_dssim(img.data_ptr(), target.data_ptr(), W, H, (1.0 - lam) / cnt_px, lam, dimg.data_ptr(), 0,
+                               lss.data_ptr() + 4 * k, sws.data_ptr(), nb)
         R.recogs_render_backward_sh_adam(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
                                          dM.data_ptr(), m.data_ptr(), v.data_ptr(), 2e-3, step=state["step"])
     for _ in range(len(w.views)):

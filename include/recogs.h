@@ -307,7 +307,9 @@ recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_cam
 
 /* L2 loss of an image against a target (the differentiable form's loss, an analog of
  * eq. 4 with its gradient, eq. 7): loss (device float, overwritten) = scale * sum (y - t)^2 and
- * dL_dimage = 2 scale (y - t), over `count` floats. scale = 1 / count gives the mean. */
+ * dL_dimage = 2 scale (y - t), over `count` floats. scale = 1 / count gives the mean.
+ * The workgroups' sums are added to the loss with float atomics, so its last bits may
+ * change between runs; the gradient does not. */
 recogs_status recogs_loss_l2(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
@@ -333,7 +335,9 @@ recogs_status recogs_render_backward_sh(const recogs_scene *scene, const recogs_
 /* L1 term of the loss of eq. 4, with the gradient Sec. 4.1 writes out (eq. 7):
  * loss (device float, overwritten) = scale * sum |y - t| and
  * dL_dimage = scale * sign(y - t) (sign(0) = 0), over `count` floats; scale = 1 / count
- * gives the mean. Device pointers of any alignment. INVALID: count < 0, NULL pointer. */
+ * gives the mean. Device pointers of any alignment. The loss's last bits may change
+ * between runs (float atomics, as recogs_loss_l2); recogs_loss_l1_dssim sums in a fixed
+ * order. INVALID: count < 0, NULL pointer. */
 recogs_status recogs_loss_l1(const float *image, const float *target, int64_t count, float scale,
                              float *dL_dimage, float *loss, hipStream_t stream);
 
@@ -345,13 +349,26 @@ recogs_status recogs_loss_l1(const float *image, const float *target, int64_t co
  * dL_dimage = -weight dSSIM/dimage, written (accumulate 0) or added (accumulate 1, so
  * that eq. 7 is recogs_loss_l1 with scale (1 - lambda) / count, then this with weight
  * lambda). workspace: device scratch of recogs_dssim_workspace_bytes (9 floats per
- * pixel, then 3 per 16 x 16 tile of the image), 4-byte aligned. The loss is summed in a
+ * pixel, then 6 per 16 x 16 tile of the image), 4-byte aligned. The loss is summed in a
  * fixed order (the same bits on every run). INVALID: bad size, flag, pointer or
  * workspace. */
 size_t recogs_dssim_workspace_bytes(int32_t width, int32_t height);
 recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t width, int32_t height, float weight,
                                 float *dL_dimage, int32_t accumulate, float *loss, void *workspace,
                                 size_t workspace_bytes, hipStream_t stream);
+
+/* Both terms of the loss of eq. 4 in one pass, with the gradient of eq. 7:
+ * loss (device float, overwritten) = l1_scale * sum |y - t| + weight (1 - SSIM) and
+ * dL_dimage = l1_scale * sign(y - t) - weight dSSIM/dimage, written (accumulate 0) or
+ * added (accumulate 1); eq. 4 with lambda is l1_scale = (1 - lambda) / (3 width height),
+ * weight = lambda. Images, SSIM and workspace as for recogs_loss_dssim. The gradient has
+ * the bits of recogs_loss_l1 (scale l1_scale) followed by recogs_loss_dssim with
+ * accumulate 1; both sums of the loss are taken in a fixed order (the same bits on every
+ * run), where recogs_loss_l1 adds its per-workgroup sums atomically. INVALID as for
+ * recogs_loss_dssim. */
+recogs_status recogs_loss_l1_dssim(const float *image, const float *target, int32_t width, int32_t height,
+                                   float l1_scale, float weight, float *dL_dimage, int32_t accumulate, float *loss,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* One Adam step over `count` float parameters (the optimiser that moves the SH
  * coefficients toward the edited views, Sec. 3.3): m <- beta1 m + (1 - beta1) g,

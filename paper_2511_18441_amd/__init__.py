@@ -11,7 +11,7 @@ from .binding import (  # noqa: F401
     recogs_workspace_bytes, recogs_workspace_init, recogs_workspace_readback, recogs_workspace_profile_flush, recogs_workspace_release,
     recogs_prepare_covariance, recogs_select, recogs_recolor,
     recogs_render, recogs_render_backward, recogs_loss_l2, recogs_render_backward_sh, recogs_loss_l1,
-    recogs_adam_step, recogs_dssim_workspace_bytes, recogs_loss_dssim, recogs_last_error,
+    recogs_adam_step, recogs_dssim_workspace_bytes, recogs_loss_dssim, recogs_loss_l1_dssim, recogs_last_error,
     recogs_unproject_workspace_bytes, recogs_unproject, recogs_reproject_mask, recogs_tint, unproject, reproject_mask, tint,
     recogs_outlier_workspace_bytes, recogs_remove_outliers, remove_outliers, recogs_render_backward_sh_adam,
     recogs_workspace_keys_needed, recogs_unproject_noalloc, recogs_backward_scratch_bytes,

@@ -29,6 +29,7 @@ ENTRY_POINTS = ("recogs_workspace_bytes", "recogs_workspace_init", "recogs_works
                 "recogs_workspace_release", "recogs_prepare_covariance", "recogs_select", "recogs_recolor",
                 "recogs_render", "recogs_render_backward", "recogs_loss_l2", "recogs_render_backward_sh",
                 "recogs_loss_l1", "recogs_adam_step", "recogs_dssim_workspace_bytes", "recogs_loss_dssim",
+                "recogs_loss_l1_dssim",
                 "recogs_unproject_workspace_bytes", "recogs_unproject", "recogs_reproject_mask", "recogs_tint",
                 "recogs_outlier_workspace_bytes", "recogs_remove_outliers", "recogs_render_backward_sh_adam",
                 "recogs_workspace_keys_needed", "recogs_unproject_noalloc", "recogs_backward_scratch_bytes",
@@ -123,6 +124,7 @@ def lib():
         L.recogs_dssim_workspace_bytes.argtypes = [i32, i32]
         L.recogs_dssim_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_loss_dssim.argtypes = [vp, vp, i32, i32, f32, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.recogs_loss_l1_dssim.argtypes = [vp, vp, i32, i32, f32, f32, vp, i32, vp, vp, ctypes.c_size_t, vp]
         L.recogs_unproject_workspace_bytes.argtypes = [i32, i32]
         L.recogs_unproject_workspace_bytes.restype = ctypes.c_size_t
         L.recogs_unproject.argtypes = [P(Camera), vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp]
@@ -360,6 +362,14 @@ def recogs_loss_dssim(image, target, width, height, weight, dL_dimage, accumulat
     return _check("recogs_loss_dssim", lib().recogs_loss_dssim(image, target, int(width), int(height), float(weight),
                                                                dL_dimage, int(accumulate), loss, workspace,
                                                                int(workspace_bytes), _stream(stream)))
+
+
+def recogs_loss_l1_dssim(image, target, width, height, l1_scale, weight, dL_dimage, accumulate, loss, workspace,
+                         workspace_bytes, stream=None):
+    return _check("recogs_loss_l1_dssim", lib().recogs_loss_l1_dssim(image, target, int(width), int(height),
+                                                                     float(l1_scale), float(weight), dL_dimage,
+                                                                     int(accumulate), loss, workspace,
+                                                                     int(workspace_bytes), _stream(stream)))
 
 
 def recogs_last_error() -> str:

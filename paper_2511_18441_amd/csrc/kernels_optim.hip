@@ -131,11 +131,13 @@ constexpr float kSsimC1 = 0.01f * 0.01f, kSsimC2 = 0.03f * 0.03f;
 
 struct SsimWindow { float g[2 * kSsimR + 1]; };
 
+// part_l1 (optional): also the tile's sum of |y - t| for the channel (the L1 term)
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
-                                                  SsimWindow win, float *__restrict__ maps, float *__restrict__ part) {
+                                                  SsimWindow win, float *__restrict__ maps, float *__restrict__ part,
+                                                  float *__restrict__ part_l1) {
     __shared__ float s_y[kSsimH * kSsimH], s_t[kSsimH * kSsimH];
     __shared__ float s_h[5][kSsimH][kSsimT];   // x-blurred y, t, y^2, t^2, y t
-    __shared__ float s_w[4];
+    __shared__ float s_w[4], s_w1[4];
     const int c = blockIdx.z;   // the channel: one workgroup per (tile, channel)
     const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
     const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
@@ -181,7 +183,11 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, c
         my += g * s_h[0][ty + j][tx]; mt += g * s_h[1][ty + j][tx];
         eyy += g * s_h[2][ty + j][tx]; ett += g * s_h[3][ty + j][tx]; eyt += g * s_h[4][ty + j][tx];
     }
-    float ssum = 0.f;
+    float ssum = 0.f, asum = 0.f;
+    if (part_l1 && px < W && py < H) {
+        const int k = (ty + kSsimR) * kSsimH + tx + kSsimR;
+        asum = fabsf(s_y[k] - s_t[k]);
+    }
     if (px < W && py < H) {
         const float syy = eyy - my * my, stt = ett - mt * mt, syt = eyt - my * mt;
         const float l1 = 2.f * my * mt + kSsimC1, l2 = my * my + mt * mt + kSsimC1;
@@ -199,17 +205,21 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float *__restrict__ y, c
     }
     ssum = wave_sum(ssum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = ssum;
+    if (part_l1) {
+        asum = wave_sum(asum);
+        if (lane_id() == 0) s_w1[threadIdx.x >> 6] = asum;
+    }
     __syncthreads();
-    // the workgroup's sum of S, added to the others in a fixed order by the backward
-    if (threadIdx.x == 0)
-        part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+    // the workgroup's sums, added to the others in a fixed order by the backward
+    const size_t at = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0) part[at] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+    if (part_l1 && threadIdx.x == 0) part_l1[at] = ((s_w1[0] + s_w1[1]) + s_w1[2]) + s_w1[3];
 }
 
-// loss = weight + neg_scale * (sum of the n partial sums), the partials added in a fixed
-// order by one workgroup (thread t: entries t, t + 256, ... in turn, then the waves'
-// sums): the loss is the same bits on every run. Eight loads in flight per thread.
-__device__ __forceinline__ void ssim_loss_sum(const float *__restrict__ part, uint32_t n, float weight, float neg_scale,
-                                              float *__restrict__ loss, float *s_w /* [4] */) {
+// The n partial sums added in a fixed order by one workgroup (thread t: entries t,
+// t + 256, ... in turn, then the waves' sums in order): the same bits on every run.
+// Eight loads in flight per thread. The total is returned to thread 0.
+__device__ __forceinline__ float fixed_order_sum(const float *__restrict__ part, uint32_t n, float *s_w /* [4] */) {
     float acc = 0.f;
     for (uint32_t k0 = threadIdx.x; k0 < n; k0 += 256u * 8u) {
         float v[8];
@@ -222,18 +232,30 @@ __device__ __forceinline__ void ssim_loss_sum(const float *__restrict__ part, ui
     acc = wave_sum(acc);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) *loss = weight + neg_scale * (((s_w[0] + s_w[1]) + s_w[2]) + s_w[3]);
+    return ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
 }
 
-// part / nparts / weight / loss: the loss, summed by workgroup (0, 0) before its tile
+// part / nparts / weight / loss: the loss weight + gscale (sum of S), plus l1_scale (sum
+// of |y - t|) with part_l1, summed by workgroup (0, 0) before its tile. With part_l1 the
+// gradient also takes l1_scale sign(y - t), added before the SSIM term is (the bits of
+// the L1 gradient written first and the SSIM gradient added to it).
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, const float *__restrict__ t, int W, int H,
                                                   SsimWindow win, const float *__restrict__ maps, float gscale,
                                                   int accumulate, float *__restrict__ dldy, const float *__restrict__ part,
-                                                  uint32_t nparts, float weight, float *__restrict__ loss) {
+                                                  uint32_t nparts, float weight, float *__restrict__ loss,
+                                                  const float *__restrict__ part_l1, float l1_scale) {
     __shared__ float s_m[3][kSsimH * kSsimH];
     __shared__ float s_h[3][kSsimH][kSsimT];
-    __shared__ float s_lw[4];
-    if (blockIdx.x == 0 && blockIdx.y == 0) ssim_loss_sum(part, nparts, weight, gscale, loss, s_lw);
+    __shared__ float s_lw[4], s_lw1[4];
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        const float ss = fixed_order_sum(part, nparts, s_lw);
+        if (part_l1) {
+            const float sa = fixed_order_sum(part_l1, nparts, s_lw1);
+            if (threadIdx.x == 0) *loss = (weight + gscale * ss) + l1_scale * sa;
+        } else if (threadIdx.x == 0) {
+            *loss = weight + gscale * ss;
+        }
+    }
     const int ox = blockIdx.x * kSsimT, oy = blockIdx.y * kSsimT;
     const int tx = threadIdx.x % kSsimT, ty = threadIdx.x / kSsimT;
     const int px = ox + tx, py = oy + ty;
@@ -287,24 +309,27 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float *__restrict__ y, c
         }
         if (px < W && py < H) {
             const int64_t p = ((int64_t)py * W + px) * 3 + c;
-            const float d = gscale * (ga + 2.f * y[p] * gb + t[p] * gc);
+            const float yp = y[p], tp = t[p];
+            float d = gscale * (ga + 2.f * yp * gb + tp * gc);
+            if (part_l1) d = l1_scale * sgn(yp - tp) + d;
             dldy[p] = accumulate ? dldy[p] + d : d;
         }
     }
 }
 
-// Scratch floats of the SSIM term: 9 per pixel (the maps), then one per (16 x 16 tile,
-// channel) (the partial sums of S).
+// Scratch floats of the SSIM term: 9 per pixel (the maps), then two per (16 x 16 tile,
+// channel) (the partial sums of S, then those of |y - t|).
 size_t dssim_scratch_floats(int W, int H) {
     if (W <= 0 || H <= 0) return 0;
     const size_t tiles = (size_t)((W + kSsimT - 1) / kSsimT) * (size_t)((H + kSsimT - 1) / kSsimT);
-    return (size_t)9 * (size_t)W * (size_t)H + 3 * tiles;
+    return (size_t)9 * (size_t)W * (size_t)H + 6 * tiles;
 }
 
 // maps: dssim_scratch_floats(W, H) floats of scratch. loss <- weight (1 - mean S); dL/dy
 // (=, or += with accumulate) -weight dS/dy averaged over 3 H W values.
+// with_l1: also the L1 term, l1_scale sum |y - t| and its gradient (eq. 4 and eq. 7 in one pass)
 void launch_dssim(const float *y, const float *t, int W, int H, float weight, float *dldy, int accumulate, float *loss,
-                  float *maps, hipStream_t st) {
+                  float *maps, hipStream_t st, int with_l1, float l1_scale) {
     SsimWindow win;
     double g[2 * kSsimR + 1], sum = 0.0;
     for (int j = 0; j <= 2 * kSsimR; ++j) {
@@ -321,10 +346,12 @@ void launch_dssim(const float *y, const float *t, int W, int H, float weight, fl
     }
     const double N = 3.0 * (double)W * (double)H;
     const dim3 grid((unsigned)((W + kSsimT - 1) / kSsimT), (unsigned)((H + kSsimT - 1) / kSsimT), 3u);
+    const uint32_t nparts = grid.x * grid.y * grid.z;
     float *part = maps + (size_t)9 * (size_t)W * (size_t)H;
-    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, part);
+    float *part_l1 = with_l1 ? part + nparts : nullptr;
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, st, y, t, W, H, win, maps, part, part_l1);
     hipLaunchKernelGGL(k_ssim_bwd, dim3(grid.x, grid.y), dim3(256), 0, st, y, t, W, H, win, maps, (float)(-weight / N),
-                       accumulate, dldy, part, grid.x * grid.y * grid.z, weight, loss);
+                       accumulate, dldy, part, nparts, weight, loss, part_l1, l1_scale);
 }
 
 }  // namespace recogs

@@ -53,7 +53,7 @@ bool launch_blend_bwd_blocks(int, int, int, int, const uint2 *, const uint32_t *
 void launch_loss_l2(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_loss_l1(const float *, const float *, int64_t, float, float *, float *, hipStream_t);
 void launch_adam(float *, const float *, float *, float *, int64_t, float, float, float, float, float, float, hipStream_t);
-void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t);
+void launch_dssim(const float *, const float *, int, int, float, float *, int, float *, float *, hipStream_t, int, float);
 size_t dssim_scratch_floats(int, int);
 uint32_t unproject_blocks(int64_t);
 int64_t unproject_scratch_max_pixels();
@@ -836,8 +836,23 @@ recogs_status recogs_loss_dssim(const float *image, const float *target, int32_t
         return fail(RECOGS_ERR_INVALID, "workspace of %zu bytes, needs %zu", workspace_bytes,
                     recogs_dssim_workspace_bytes(width, height));
     if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(RECOGS_ERR_INVALID, "workspace not 4-byte aligned");
-    launch_dssim(image, target, width, height, weight, dL_dimage, accumulate, loss, (float *)workspace, stream);
+    launch_dssim(image, target, width, height, weight, dL_dimage, accumulate, loss, (float *)workspace, stream, 0, 0.f);
     return hip_check("loss_dssim");
+}
+
+recogs_status recogs_loss_l1_dssim(const float *image, const float *target, int32_t width, int32_t height, float l1_scale,
+                                   float weight, float *dL_dimage, int32_t accumulate, float *loss, void *workspace,
+                                   size_t workspace_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    if (width <= 0 || height <= 0) return fail(RECOGS_ERR_INVALID, "image %dx%d", width, height);
+    if (accumulate != 0 && accumulate != 1) return fail(RECOGS_ERR_INVALID, "accumulate %d not 0 or 1", accumulate);
+    if (!image || !target || !dL_dimage || !loss || !workspace) return fail(RECOGS_ERR_INVALID, "NULL pointer");
+    if (workspace_bytes < recogs_dssim_workspace_bytes(width, height))
+        return fail(RECOGS_ERR_INVALID, "workspace of %zu bytes, needs %zu", workspace_bytes,
+                    recogs_dssim_workspace_bytes(width, height));
+    if (reinterpret_cast<uintptr_t>(workspace) % 4) return fail(RECOGS_ERR_INVALID, "workspace not 4-byte aligned");
+    launch_dssim(image, target, width, height, weight, dL_dimage, accumulate, loss, (float *)workspace, stream, 1, l1_scale);
+    return hip_check("loss_l1_dssim");
 }
 
 recogs_status recogs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,

@@ -219,10 +219,17 @@ def test_host_argument_errors_before_any_launch(R):
     assert status(B.recogs_loss_l2, 0, 0, 10, 1.0, 0, 0, 0) == -1
     assert status(B.recogs_loss_l1, 0, 0, 10, 1.0, 0, 0, 0) == -1
     assert status(B.recogs_loss_l1, 0, 0, -1, 1.0, 0, 0, 0) == -1
-    assert R.recogs_dssim_workspace_bytes(0, 10) == 0 and R.recogs_dssim_workspace_bytes(4, 5) == 4 * (9 * 20 + 3)
-    assert R.recogs_dssim_workspace_bytes(33, 17) == 4 * (9 * 33 * 17 + 3 * 3 * 2)
+    # 9 floats per pixel, then 2 x 3 per 16 x 16 tile (partial sums of S and of |y - t|)
+    assert R.recogs_dssim_workspace_bytes(0, 10) == 0 and R.recogs_dssim_workspace_bytes(4, 5) == 4 * (9 * 20 + 6)
+    assert R.recogs_dssim_workspace_bytes(33, 17) == 4 * (9 * 33 * 17 + 6 * 3 * 2)
     assert status(B.recogs_loss_dssim, 0, 0, 0, 8, 0.2, 0, 0, 0, 0, 0, 0) == -1           # width 0
-    assert status(B.recogs_loss_dssim, 8, 8, 4, 5, 0.2, 8, 0, 8, 8, 9 * 4 * 20 - 1, 0) == -1  # workspace too small
+    assert status(B.recogs_loss_dssim, 8, 8, 4, 5, 0.2, 8, 0, 8, 8, 4 * (9 * 20 + 6) - 1, 0) == -1  # workspace too small
+    # (image, target, width, height, l1_scale, weight, dL, accumulate, loss, workspace, bytes, stream)
+    assert status(B.recogs_loss_l1_dssim, 8, 8, 0, 5, 0.1, 0.2, 8, 0, 8, 8, 10 ** 6, 0) == -1       # width 0
+    assert status(B.recogs_loss_l1_dssim, 8, 8, 4, 5, 0.1, 0.2, 8, 2, 8, 8, 10 ** 6, 0) == -1       # accumulate 2
+    assert status(B.recogs_loss_l1_dssim, 8, 0, 4, 5, 0.1, 0.2, 8, 0, 8, 8, 10 ** 6, 0) == -1       # NULL target
+    assert status(B.recogs_loss_l1_dssim, 8, 8, 4, 5, 0.1, 0.2, 8, 0, 8, 8, 4 * (9 * 20 + 6) - 1, 0) == -1
+    assert status(B.recogs_loss_l1_dssim, 8, 8, 4, 5, 0.1, 0.2, 8, 0, 8, 10, 10 ** 6, 0) == -1      # workspace alignment
         # (param, grad, m, v, count, lr, beta1, beta2, eps, step, stream)
     assert status(B.recogs_adam_step, 0, 0, 0, 0, 10, 1e-3, 0.9, 0.999, 1e-15, 1, 0) == -1  # NULL arrays
     assert status(B.recogs_adam_step, 0, 0, 0, 0, 0, 1e-3, 0.9, 0.999, 1e-15, 0, 0) == -1   # step counts from 1

@@ -151,6 +151,22 @@ def test_dssim_vs_oracle(R, orc, H, W):
     e2 = _close(dl.cpu().numpy().astype(np.float64), ref, "dL/dy (eq. 7)")
     assert abs(l1.item() - (1 - lam) * orc.loss_l1(y, t)) <= 1e-5
     print(f"{H}x{W}: SSIM {val:.6f}, gradient rel err {e:.2e}, eq. 7 gradient rel err {e2:.2e}")
+    # both terms in one pass: the two calls' gradient bits, written or added; the loss
+    # against the oracle, and the same bits on every run (both sums in a fixed order)
+    dlf = torch.empty_like(ty)
+    lf = torch.empty(1, device="cuda")
+    R.recogs_loss_l1_dssim(ty.data_ptr(), tt.data_ptr(), W, H, (1 - lam) / n, lam, dlf.data_ptr(), 0, lf.data_ptr(),
+                           ws.data_ptr(), nb)
+    torch.cuda.synchronize()
+    assert torch.equal(dlf, dl)
+    assert abs(lf.item() - ((1 - lam) * orc.loss_l1(y, t) + lam * (1.0 - val))) <= 1e-5
+    lf2 = torch.empty(1, device="cuda")
+    dacc = torch.full_like(ty, 0.25)
+    R.recogs_loss_l1_dssim(ty.data_ptr(), tt.data_ptr(), W, H, (1 - lam) / n, lam, dacc.data_ptr(), 1, lf2.data_ptr(),
+                           ws.data_ptr(), nb)
+    torch.cuda.synchronize()
+    assert lf2.cpu().numpy().tobytes() == lf.cpu().numpy().tobytes()
+    assert torch.equal(dacc, torch.full_like(ty, 0.25) + dlf)
 
 
 def test_adam_vector_and_scalar_paths_agree(R):
