@@ -384,15 +384,18 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     cams = [R.camera_struct(v.camera) for v in w.views]
     o = R.opts_struct(tile, ppt, (0.0, 0.0, 0.0), mask, M, b, keep_backward=True, bwd_scratch=ws[0].backward_scratch(tile, ppt) if BWD_FORM == "block" else None)
 
-    def step():
+    def step(graph=True):
+        # graph mode: no host synchronisation in the step (the backward reads the key
+        # count on the device); the eager warm-up grows the workspaces if a view needs it
         for k, v in enumerate(w.views):
             R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k],
-                     sort_mode=SORT_MODE)
+                     sort_mode=SORT_MODE, graph_mode=graph)
             R.recogs_loss_l2(imgs[k].data_ptr(), targets[k].data_ptr(), H * W * 3, scale, dimg.data_ptr(),
                              loss.data_ptr() + 4 * k)
             # the loss sums the views: the first view writes the gradients, the others add to them
             R.recogs_render_backward(sc, cams[k], o, ws[k].ws, imgs[k].data_ptr(), dimg.data_ptr(), dop.data_ptr(),
                                      ddc.data_ptr(), dM.data_ptr(), 1 if k else 0)
+    step(False)
     for _ in range(max(2, warmup // 4)):
         step()
     reps = max(3, steps // 20)
@@ -408,9 +411,10 @@ def form_diff(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     for _ in range(reps):
         for k, v in enumerate(w.views):
             R.render(d, v.camera, ws[k], tile, ppt, mask=mask, M=M, b=b, keep_backward=True, image=imgs[k],
-                     sort_mode=SORT_MODE)
+                     sort_mode=SORT_MODE, graph_mode=True)
     torch.cuda.synchronize()
     ms_fwd = 1000.0 * (time.perf_counter() - t0) / reps
+    _no_overflow(ws)
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt,
             "ms_per_step": round(ms, 3), "views_per_s": round(len(w.views) * 1000.0 / ms, 1),
             "forward_ms_per_step": round(ms_fwd, 3), "loss": float(loss.sum().item()),
@@ -467,7 +471,8 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
     def step():
         k = state["step"] % len(w.views)
         state["step"] += 1
-        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE)
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE,
+                 graph_mode=True)
         R.recogs_loss_l1(img.data_ptr(), targets[k].data_ptr(), cnt_px, (1.0 - lam) / cnt_px, dimg.data_ptr(),
                          loss.data_ptr() + 4 * k)
         R.recogs_loss_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, lam, dimg.data_ptr(), 1, lss.data_ptr() + 4 * k,
@@ -483,7 +488,8 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         # step fused (the gradient does not go through memory)
         k = state["step"] % len(w.views)
         state["step"] += 1
-        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE)
+        R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, sort_mode=SORT_MODE,
+                 graph_mode=True)
         R.recogs_loss_l1_dssim(img.data_ptr(), targets[k].data_ptr(), W, H, (1.0 - lam) / cnt_px, lam, dimg.data_ptr(),
                                0, lfs.data_ptr() + 4 * k, sws.data_ptr(), nb)
         R.recogs_render_backward_sh_adam(sc, cams[k], o, ws.ws, img.data_ptr(), dimg.data_ptr(), dop.data_ptr(),
@@ -504,11 +510,21 @@ def form_refit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         step_fused()
     torch.cuda.synchronize()
     ms_fused = 1000.0 * (time.perf_counter() - t0) / reps
+    _no_overflow([ws])
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "backward_form": BWD_FORM, "ms_per_step": round(ms, 3),
             "steps_per_s": round(1000.0 / ms, 1), "steps_timed": reps, "ms_per_step_fused_adam": round(ms_fused, 3),
             "loss": "0.8 L1 + 0.2 (1 - SSIM)", "loss_mean_after_warmup": first, "loss_mean_end": end,
             "loss_mean_after_fused_steps": float(lfs.mean().item())}
+
+
+def _no_overflow(wss):
+    """After graph-mode renders: each workspace's last render held all its keys (a render
+    that overflowed draws the background and gives zero gradients)."""
+    for ws in wss:
+        k, _ = ws.readback()
+        if k > ws.ws.key_capacity:
+            raise RuntimeError(f"a timed render needed {k} keys, its workspace holds {ws.ws.key_capacity}")
 
 
 def _event_ms(fn, reps):
@@ -653,7 +669,7 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         k = state["step"] % len(w.views)
         state["step"] += 1
         R.render(d, w.views[k].camera, ws, tile, ppt, keep_backward=True, image=img, sh=sh, depth=depth, depth_tau=0.5,
-                 sort_mode=SORT_MODE)
+                 sort_mode=SORT_MODE, graph_mode=True)
         R.recogs_reproject_mask(cams[k], cloud.data_ptr(), n_pts, n_pts, 2.0, depth.data_ptr(), 0.01, vmask.data_ptr())
         R.recogs_tint(originals[k].data_ptr(), vmask.data_ptr(), t, target.data_ptr(), H * W)
         # eq. 4 in one pass (L1 and SSIM terms; the L1 slots stay zero)
@@ -675,6 +691,7 @@ def form_edit(R, steps, warmup, dev, tile=DIFF_TILE, ppt=DIFF_PPT):
         step()
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / reps
+    _no_overflow([ws])
     return {"views": len(w.views), "width": W, "height": H, "gaussians": n, "sh_coefficients": int(3 * K * n),
             "tile": f"{tile[0]}x{tile[1]}", "px_per_thread": ppt, "selected_pixels": int(sel.sum()),
             "cloud_points": int(n_pts), "unprojected_points": int(n_sel),

@@ -299,7 +299,12 @@ size_t recogs_backward_scratch_bytes(const recogs_workspace *ws, const recogs_re
  * first); INVALID otherwise. No atomics: every sum is taken in a fixed order, so results
  * are bit-identical between runs. The backward uses the workspace's sorted-key buffers
  * (keys0/keys1) as per-key gradient scratch; the tile lists and the rest of the
- * render's state stay valid, so it may be called again on the same render. */
+ * render's state stay valid, so it may be called again on the same render. After a
+ * graph_mode render it needs no recogs_workspace_readback and does not synchronise
+ * either: the key count is read on the device, and a render that overflowed its key
+ * capacity (no tile lists) gives zero gradients (the overflow shows in the read-back).
+ * INVALID: a render read back as overflowed, no kept state, a CHW render, another
+ * scene size, NULL pointers, bad accumulate or bwd_scratch. */
 recogs_status recogs_render_backward(const recogs_scene *scene, const recogs_camera *cam,
                                      const recogs_render_opts *opts, const recogs_workspace *ws,
                                      const float *image, const float *dL_dimage, float *dL_dopacity,

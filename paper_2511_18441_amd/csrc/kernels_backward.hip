@@ -439,8 +439,10 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
                                                      float *__restrict__ out, float *__restrict__ part,
                                                      const float *__restrict__ means, int64_t stride, CamDev cam,
                                                      int acc, float *__restrict__ psh, float *__restrict__ am,
-                                                     float *__restrict__ av, AdamArgs aa) {
+                                                     float *__restrict__ av, AdamArgs aa, uint64_t slots,
+                                                     const uint32_t *overflow) {
     __shared__ float s_dm[4][9];
+    const bool ovf = overflow && *overflow;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool sel = false;
     float gh[3] = {0.f, 0.f, 0.f}, f[3] = {0.f, 0.f, 0.f};
@@ -448,7 +450,10 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
         uint32_t flags = 0;
         const uint32_t c = count[i];
-        if (c > 0) {
+        // a render that overflowed its key capacity (overflow flag set) has empty tile
+        // lists and no slot written: nothing is read and the sums stay zero; slots (the
+        // gradient buffer's capacity) bounds the reads in any case
+        if (!ovf && c > 0 && (uint64_t)koff[i] + c <= slots) {
             // the Gaussian's (Gaussian, tile) slots, added in order; four loads in flight
             const float4 *slot = gk + koff[i];
             uint32_t k = 0;
@@ -659,13 +664,13 @@ bool launch_blend_bwd_blocks(int tw, int th, int ppt, int ntiles, const uint2 *r
 void launch_grad_finish(const float4 *gk, const uint32_t *koff, const float4 *bwd, const uint32_t *count, int64_t n,
                         const float *M, float *dop, float *out, float *dM, float *part, int deg, const float *means,
                         int64_t stride, const CamDev &cam, int acc, hipStream_t st, float *psh, float *am, float *av,
-                        const AdamArgs *adam) {
+                        const AdamArgs *adam, uint64_t slots, const uint32_t *overflow) {
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
     const AdamArgs aa = adam ? *adam : AdamArgs{0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
     if (n > 0) {
 #define RECOGS_FIN(D, A)                                                                                              \
     hipLaunchKernelGGL((k_grad_finish<D, A>), dim3(blocks), dim3(256), 0, st, gk, koff, bwd, count, n, M, dop, out, part, \
-                       means, stride, cam, acc, psh, am, av, aa)
+                       means, stride, cam, acc, psh, am, av, aa, slots, overflow)
         if (adam) {
             switch (deg) {
             case 0: RECOGS_FIN(0, true); break;

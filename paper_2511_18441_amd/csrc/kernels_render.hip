@@ -739,6 +739,21 @@ __global__ __launch_bounds__(64) void k_blend_region(const uint2 *__restrict__ r
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// p[0, mult * (*dyn)) = v, the count read on the device (at most max_count words)
+__global__ __launch_bounds__(256) void k_fill_u32_dyn(uint32_t *__restrict__ p, uint32_t v, const uint32_t *dyn,
+                                                      uint32_t mult, int64_t max_count) {
+    const int64_t c = (int64_t)mult * (int64_t)*dyn;
+    const int64_t count = c < max_count ? c : max_count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+void launch_fill_u32_dyn(uint32_t *p, uint32_t v, const uint32_t *dyn, uint32_t mult, int64_t max_count, hipStream_t st) {
+    if (max_count <= 0) return;
+    int64_t blocks = (max_count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32_dyn, dim3((unsigned)blocks), dim3(256), 0, st, p, v, dyn, mult, max_count);
+}
+
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
     if (count <= 0) return;
     int64_t blocks = (count + 255) / 256;

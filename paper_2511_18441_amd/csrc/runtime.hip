@@ -16,6 +16,7 @@ void launch_covariance(const float *, const float *, float *, int64_t, int64_t, 
 void launch_select(int, const SceneDev &, const CamDev &, const recogs_select_params &, uint8_t *, int32_t *, hipStream_t);
 void launch_recolor(int, const SceneDev &, int, void *, const uint8_t *, const float *, const float *, int, hipStream_t);
 void launch_fill_u32(uint32_t *, uint32_t, int64_t, hipStream_t);
+void launch_fill_u32_dyn(uint32_t *, uint32_t, const uint32_t *, uint32_t, int64_t, hipStream_t);
 void launch_preprocess(int, int, const SceneDev &, const CamDev &, const RecolorDev &, int, SplatRec *, float4 *,
                        uint32_t *, uint2 *, uint32_t *, hipStream_t, uint32_t *, int64_t);
 void launch_scan(const uint32_t *, const uint32_t *, uint32_t *, int64_t, uint64_t *, uint32_t *, uint32_t *, uint32_t *,
@@ -45,7 +46,7 @@ bool launch_blend_bwd(int, int, int, int, const uint2 *, const uint32_t *, const
                       int, int, int, const float *, const float *, const uint32_t *, float4 *, hipStream_t);
 void launch_grad_finish(const float4 *, const uint32_t *, const float4 *, const uint32_t *, int64_t, const float *, float *,
                         float *, float *, float *, int, const float *, int64_t, const CamDev &, int, hipStream_t, float *,
-                        float *, float *, const AdamArgs *);
+                        float *, float *, const AdamArgs *, uint64_t, const uint32_t *);
 uint32_t bwd_blocks(int, int, int);
 bool launch_blend_bwd_blocks(int, int, int, int, const uint2 *, const uint32_t *, const SplatRec *, const uint2 *,
                              const uint32_t *, int, int, int, const float *, const float *, const uint32_t *, float4 *,
@@ -718,8 +719,10 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     if (!opts->keep_backward_state) return fail(RECOGS_ERR_INVALID, "render must keep backward state for the backward");
     if (opts->output_chw) return fail(RECOGS_ERR_UNSUPPORTED, "the backward takes an HWC render (output_chw 0)");
     if (ws->last_n != scene->n) return fail(RECOGS_ERR_INVALID, "workspace holds a render of %d Gaussians, scene has %lld", ws->last_n, (long long)scene->n);
-    if (ws->num_keys < 0)
-        return fail(RECOGS_ERR_INVALID, "after a graph_mode render, call recogs_workspace_readback before the backward");
+    // after a graph_mode render not read back, the key count stays on the device (no host
+    // synchronisation here either); a render that overflowed emitted no key, so every
+    // tile list is empty and the gradients are zero
+    const bool dyn_keys = ws->num_keys < 0;
     if (ws->num_keys > ws->key_capacity) return fail(RECOGS_ERR_INVALID, "the render overflowed its key capacity");
     if (!image || !dL_dimage || !dL_dM || (scene->n > 0 && (!dL_dopacity || (!out && !adam))))
         return fail(RECOGS_ERR_INVALID, "NULL image / gradient pointer");
@@ -739,7 +742,7 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     // per-(Gaussian, tile) gradient slots, 16 bytes per key: the span of both sorted-key
     // buffers (adjacent, 16 bytes per key of capacity), which the backward does not read
     float4 *gk = at<float4>(ws, ws->off_keys0);
-    if (ws->num_keys > 0) {
+    if (ws->num_keys > 0 || dyn_keys) {
         bool ok;
         if (blocks) {   // writes every slot
             const size_t cap = (size_t)ws->key_capacity;
@@ -750,6 +753,12 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
                                          at<uint2>(ws, ws->off_rect), koff, cam->width, cam->height, ws->tiles_x, image,
                                          dL_dimage, at<uint32_t>(ws, ws->off_nproc), sub, fw, (uint32_t)cap,
                                          (uint32_t)bwd_flag_stride(ws), gk, stream);
+        } else if (dyn_keys) {
+            launch_fill_u32_dyn((uint32_t *)gk, 0u, at<uint32_t>(ws, ws->off_header) + H_KEFF, 4u,
+                                4 * ws->key_capacity, stream);
+            ok = launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges),
+                                  vals, at<SplatRec>(ws, ws->off_rec), at<uint2>(ws, ws->off_rect), koff, cam->width,
+                                  cam->height, ws->tiles_x, image, dL_dimage, at<uint32_t>(ws, ws->off_nproc), gk, stream);
         } else {
             launch_fill_u32((uint32_t *)gk, 0u, 4 * ws->num_keys, stream);
             ok = launch_blend_bwd(opts->tile_w, opts->tile_h, opts->px_per_thread, ntiles, at<uint2>(ws, ws->off_ranges),
@@ -761,7 +770,8 @@ static recogs_status backward_impl(const recogs_scene *scene, const recogs_camer
     const CamDev cd = make_cam(*cam, opts->tile_w, opts->tile_h);
     launch_grad_finish(gk, koff, at<float4>(ws, ws->off_bwd), at<uint32_t>(ws, ws->off_count), n, opts->M, dL_dopacity, out,
                        dL_dM, at<float>(ws, ws->off_gpart), all_bands ? scene->sh_degree : -1, scene->means,
-                       scene->stride, cd, accumulate, stream, adam ? (float *)scene->sh : nullptr, am, av, adam);
+                       scene->stride, cd, accumulate, stream, adam ? (float *)scene->sh : nullptr, am, av, adam,
+                       (uint64_t)ws->key_capacity, at<uint32_t>(ws, ws->off_header) + H_OVERFLOW);
     return hip_check("backward");
 }
 

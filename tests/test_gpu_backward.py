@@ -40,11 +40,13 @@ def _setup(R, orc, w, g_seed=21):
     return d, ws, tm, tM, tb, mask, M, b, g
 
 
-def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1, blocks=False):
+def _gpu_grads(R, d, ws, cam, tm, tM, tb, g, tile=(16, 16), ppt=1, blocks=False, graph=False):
     """Render keeping the backward state, then recogs_render_backward; blocks: the
-    backward's block form (one wave per 8 x 8 ppt block, with its scratch)."""
+    backward's block form (one wave per 8 x 8 ppt block, with its scratch); graph: the
+    render in graph mode, not read back (the backward then reads the key count on the
+    device)."""
     import torch
-    img = R.render(d, cam, ws, tile, ppt, mask=tm, M=tM, b=tb, keep_backward=True)
+    img = R.render(d, cam, ws, tile, ppt, mask=tm, M=tM, b=tb, keep_backward=True, graph_mode=graph)
     gt = torch.from_numpy(g).cuda()
     n = d.n
     dop = torch.empty(n, device="cuda")
@@ -124,6 +126,30 @@ def test_block_form_backward_is_deterministic_and_matches_the_tile_form(R, orc):
         R.recogs_render_backward(d.c_struct(), R.camera_struct(cam), o, ws.ws, img.data_ptr(), img.data_ptr(),
                                  buf[0].data_ptr(), buf[1].data_ptr(), buf[2].data_ptr())
     assert e.value.status == -1
+
+
+def test_backward_after_graph_render_without_readback(R, orc):
+    """After a graph-mode render that is not read back, the backward (tile and block
+    forms) gives the bits of the backward of the same render made with a read-back; a
+    render that overflowed its key capacity gives zero gradients, with no out-of-bounds
+    read of the per-key gradient slots, and its overflow shows in the read-back."""
+    import torch
+    w = _wfd()
+    cam = w.view.camera
+    d, ws, tm, tM, tb, mask, M, b, g = _setup(R, orc, w)
+    for tile, ppt, blocks in [((16, 16), 1, False), ((32, 16), 1, False), ((8, 8), 2, False), ((16, 16), 1, True)]:
+        wsx = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, tile)
+        a = _gpu_grads(R, d, wsx, cam, tm, tM, tb, g, tile, ppt, blocks=blocks)
+        c = _gpu_grads(R, d, wsx, cam, tm, tM, tb, g, tile, ppt, blocks=blocks, graph=True)
+        assert wsx.ws.num_keys == -1   # not read back
+        assert torch.equal(a[0], c[0])
+        for x, y in zip(a[1:], c[1:]):
+            assert np.array_equal(x, y), (tile, ppt, blocks)
+    small = R.DeviceWorkspace(w.scene.n, cam.width, cam.height, (16, 16), key_capacity=64)
+    img, dop, ddc, dM = _gpu_grads(R, d, small, cam, tm, tM, tb, g, (16, 16), 1, graph=True)
+    assert not dop.any() and not ddc.any() and not dM.any()
+    k, _ = small.readback()
+    assert k > 64
 
 
 def test_backward_is_deterministic_and_repeatable(R, orc):
