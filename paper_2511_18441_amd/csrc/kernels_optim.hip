@@ -21,12 +21,20 @@ __global__ __launch_bounds__(1024) void k_loss_l1(const float *__restrict__ y, c
     const float4 *y4 = reinterpret_cast<const float4 *>(y), *t4 = reinterpret_cast<const float4 *>(tg);
     float4 *d4 = reinterpret_cast<float4 *>(dldy);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        const float4 a = y4[i], b = t4[i];
+    auto one = [&](const float4 a, const float4 b, int64_t i) {
         const float4 d = make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
         d4[i] = make_float4(scale * sgn(d.x), scale * sgn(d.y), scale * sgn(d.z), scale * sgn(d.w));
         sum += fabsf(d.x) + fabsf(d.y) + fabsf(d.z) + fabsf(d.w);
+    };
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {   // four groups' loads in flight
+        float4 a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { a[u] = y4[i + u * stride]; b[u] = t4[i + u * stride]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) one(a[u], b[u], i + u * stride);
     }
+    for (; i < n4; i += stride) one(y4[i], t4[i], i);
     for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         const float d = y[i] - tg[i];
         dldy[i] = scale * sgn(d);
@@ -46,7 +54,7 @@ void launch_loss_l1(const float *y, const float *tg, int64_t count, float scale,
     if (count <= 0) return;
     // few workgroups (of 16 waves): each adds its partial sum with one same-address atomic
     int64_t blocks = (count + 1023) / 1024;
-    if (blocks > 512) blocks = 512;
+    if (blocks > 128) blocks = 128;
     const int vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(tg) | reinterpret_cast<uintptr_t>(dldy)) &
                      15u) == 0;
     hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)blocks), dim3(1024), 0, st, y, tg, count, scale, dldy, loss, vec);
