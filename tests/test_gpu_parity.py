@@ -231,6 +231,42 @@ def test_fused_recolor_render(R, orc):
     assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, "fused recolour")
 
 
+@pytest.mark.parametrize("spread", [0, 100, 3000])
+def test_depth_sort_with_few_depth_bits(R, orc, spread):
+    """All Gaussians at one depth (no depth bit left for the sort after the count scan's
+    pass on the low 8 bits: the emission then makes its own reduce), depths within 100
+    float32 steps (the scan's pass covers them) or 3,000 (one more pass): the eager
+    render gives the oracle's (tile, depth, index) order and image, the graph-mode render
+    (all 32 bits) the eager render's bits."""
+    import torch
+    from tests.scenes_by_hand import axis_camera, scene_from
+    rng = np.random.default_rng(11 + spread)
+    n = 2000
+    z = np.full(n, np.float32(4.0))
+    if spread:
+        z = (z.view(np.uint32) + rng.integers(0, spread, n).astype(np.uint32)).view(np.float32)
+    means = np.column_stack([rng.uniform(-2.4, 2.4, n), rng.uniform(-2.0, 2.0, n), z.astype(np.float64)])
+    sc = scene_from(means, np.log(rng.uniform(0.04, 0.15, (n, 3))), rng.uniform(0.3, 0.95, n),
+                    rng.uniform(0.0, 1.0, (n, 3)))
+    cam = axis_camera(96, 80, 60.0)
+    base = synth.make_tiny()
+    w = synth.Workload(f"depths{spread}", [sc], [synth.View(0, cam, base.view.select, base.view.recolor)])
+    out = gpu_run(w, keep_backward=True)
+    p = pull(out, n)
+    pr = _oracle(w, orc)
+    _check_integer_steps(w, orc, p, pr, n)
+    ref = orc.render_image(pr, brute=True)
+    assert_pixels(p["img"], ref.rgb, ref.slack, TOL_F32, f"depth spread {spread}")
+    assert int(out["ws"].ws.depth_passes) == {0: 0, 100: 0, 3000: 1}[spread]
+    wsg = R.DeviceWorkspace(n, cam.width, cam.height, (16, 16), key_capacity=p["K"] + 1024)
+    img = R.render(out["dscene"], cam, wsg, (16, 16), 1, keep_backward=True, graph_mode=True)
+    k, _ = wsg.readback()
+    assert k == p["K"]
+    assert torch.equal(img, out["img"])
+    assert torch.equal(wsg.vals_sorted()[:k], out["ws"].vals_sorted()[:k])
+    assert torch.equal(wsg.ranges(), out["ws"].ranges())
+
+
 @pytest.mark.parametrize("deg", [1, 2])
 def test_sh_degrees_one_and_two(R, orc, deg):
     """Scenes of SH degree 1 and 2 (eq. 2 sums bands l <= deg): the whole 800x800 image
