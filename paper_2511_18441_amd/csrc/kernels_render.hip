@@ -507,6 +507,13 @@ __global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ 
     if (base >= V) return;
     __shared__ uint32_t s_w[4];
     const uint32_t t = threadIdx.x;
+    constexpr int R = kEmitChunk / 256;
+    uint2 rr[R];   // the chunk's rectangles, loaded before the chunk sums
+#pragma unroll
+    for (int r = 0; r < R; ++r) {  // thread t holds Gaussians base + R t + r (blocked)
+        const uint32_t j = base + R * t + r;
+        rr[r] = j < V ? srect[j] : make_uint2(0u, 0u);
+    }
     uint32_t pre;
     if (fold) {
         uint32_t a = 0;
@@ -519,12 +526,11 @@ __global__ __launch_bounds__(256) void k_emit_offsets(const uint2 *__restrict__ 
     } else {
         pre = epre[blockIdx.x];
     }
-    constexpr int R = kEmitChunk / 256;
     uint32_t c[R], sum = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {  // thread t holds Gaussians base + R t + r (blocked)
+    for (int r = 0; r < R; ++r) {
         const uint32_t j = base + R * t + r;
-        c[r] = j < V ? rect_count(srect[j]) : 0u;
+        c[r] = j < V ? rect_count(rr[r]) : 0u;
         sum += c[r];
     }
     uint32_t tot;
@@ -590,11 +596,13 @@ __global__ __launch_bounds__(256) void k_emit_down(const uint32_t *__restrict__ 
     while (kb < k1) {
         // a round: up to 256 consecutive Gaussians from g, and the keys they own in [kb, k1)
         const uint32_t gi = g + t;
+        // the three loads go out together (the rectangle and value are not known to be
+        // needed until the start offset is in)
         const uint32_t st = gi < V ? eoff[gi] : 0xffffffffu;
+        const uint2 rc = gi < V ? srect[gi] : make_uint2(0u, 0u);
+        const uint32_t gv = gi < V ? order[gi] : 0u;
         const bool in = gi < V && st < k1;
         if (in) {
-            const uint2 rc = srect[gi];
-            const uint32_t gv = order[gi];
             uint32_t tb = 0, txn = (uint32_t)tiles_x;
             if (nviews > 1) {  // view of the pair: last v with pair_base <= gv
                 int lo = 0, hi = nviews - 1;

@@ -130,14 +130,8 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
     const uint32_t dmask = (1u << nbits) - 1u;
     const uint32_t chunk = blockIdx.x;
     const uint32_t cbase = chunk * (uint32_t)CHUNK;
-    for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
-    {
-        uint32_t all;
-        const uint32_t dbase = block_excl_scan256(t <= dmask ? dtot[t] : 0u, s_w, all);
-        if (t <= dmask) s_gbase[t] = dbase + off[(size_t)t * chunks + chunk];
-    }
-    __syncthreads();
-
+    // every global load of the workgroup goes out first (the chunk's keys and values, the
+    // digit totals, this chunk's digit offsets): one memory round trip, not three
     KT key[ITEMS];
     uint32_t val[ITEMS], rank[ITEMS];
 #pragma unroll
@@ -147,6 +141,15 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
         key[r] = valid ? kin[idx] : (KT)0;
         val[r] = valid ? vin[idx] : 0u;
     }
+    const uint32_t tot_t = t <= dmask ? dtot[t] : 0u;
+    const uint32_t off_t = t <= dmask ? off[(size_t)t * chunks + chunk] : 0u;
+    for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
+    {
+        uint32_t all;
+        const uint32_t dbase = block_excl_scan256(tot_t, s_w, all);
+        if (t <= dmask) s_gbase[t] = dbase + off_t;
+    }
+    __syncthreads();
     // stable rank within the wave, round by round (wave w holds a contiguous quarter)
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
