@@ -55,24 +55,31 @@ __device__ __forceinline__ void dyn_args(const uint32_t *dyn_count, const uint32
     if (dyn_zmin) zmin = *dyn_zmin;
 }
 
-// per-chunk digit counts -> cnt[digit * chunks + chunk]; a chunk is 256 x ITEMS keys
+// per-chunk digit counts -> cnt[digit * chunks + chunk]; a chunk is 256 x ITEMS keys.
+// spec (a device count whose bound K is near it): the chunk's keys are loaded below the
+// bound before the count arrives, so the count costs no round trip of its own
 template <typename KT, int VIEW, int ITEMS>
 __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, uint32_t K, uint32_t zmin, int dbits,
                                                   int shift, int nbits, uint32_t *__restrict__ cnt, uint32_t chunks,
-                                                  const uint32_t *dyn_count, const uint32_t *dyn_zmin) {
+                                                  const uint32_t *dyn_count, const uint32_t *dyn_zmin, int spec) {
     constexpr uint32_t CHUNK = 256 * ITEMS;
-    dyn_args(dyn_count, dyn_zmin, K, zmin);
-    if (blockIdx.x * CHUNK >= K) return;
-    __shared__ uint32_t h[256];
     const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * CHUNK;
+    KT kk[ITEMS];
+    if (spec) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) kk[r] = base + r * 256 + t < K ? kin[base + r * 256 + t] : (KT)0;
+    }
+    dyn_args(dyn_count, dyn_zmin, K, zmin);
+    if (base >= K) return;
+    __shared__ uint32_t h[256];
     h[t] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << nbits) - 1u;
-    const uint32_t base = blockIdx.x * CHUNK;
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = base + r * 256 + t;
-        if (idx < K) atomicAdd(&h[digit_of<KT, VIEW>(kin[idx], zmin, dbits, shift, dmask)], 1u);
+        if (idx < K) atomicAdd(&h[digit_of<KT, VIEW>(spec ? kk[r] : kin[idx], zmin, dbits, shift, dmask)], 1u);
     }
     __syncthreads();
     if (t <= dmask) cnt[(size_t)t * chunks + blockIdx.x] = h[t];
@@ -83,18 +90,23 @@ __global__ __launch_bounds__(256) void k_radix_up(const KT *__restrict__ kin, ui
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t *__restrict__ cnt, uint32_t chunks, uint32_t chunk_keys,
                                                        uint32_t *__restrict__ tot, uint32_t K,
                                                        const uint32_t *dyn_count) {
-    if (dyn_count) K = *dyn_count;
-    const uint32_t live = (K + chunk_keys - 1) / chunk_keys;   // chunks holding keys; row stride stays `chunks`
     __shared__ uint32_t s_w[4];
     const uint32_t d = blockIdx.x, t = threadIdx.x;
-    uint32_t run = 0, total;
     uint32_t *row = cnt + (size_t)d * chunks;
+    // the row's first 1,024 entries are loaded before the device count arrives (it would
+    // cost a memory round trip of its own); entries past the live chunks are not summed
+    uint32_t v0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v0[i] = 4 * t + i < chunks ? row[4 * t + i] : 0u;
+    if (dyn_count) K = *dyn_count;
+    const uint32_t live = (K + chunk_keys - 1) / chunk_keys;   // chunks holding keys; row stride stays `chunks`
+    uint32_t run = 0, total;
     for (uint32_t c0 = 0; c0 < live; c0 += 1024) {
         const uint32_t c = c0 + 4 * t;
         uint32_t v[4], sum = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            v[i] = c + i < live ? row[c + i] : 0u;
+            v[i] = c + i < live ? (c0 == 0 ? v0[i] : row[c + i]) : 0u;
             sum += v[i];
         }
         uint32_t e = run + block_excl_scan256(sum, s_w, total);
@@ -115,10 +127,29 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
                                                     uint32_t zmin, int dbits, int shift, int nbits,
                                                     const uint32_t *__restrict__ off, const uint32_t *__restrict__ dtot,
                                                     uint32_t chunks, const uint32_t *dyn_count,
-                                                    const uint32_t *dyn_zmin, EmitFold ef) {
+                                                    const uint32_t *dyn_zmin, EmitFold ef, int spec) {
     constexpr uint32_t CHUNK = 256 * ITEMS;
+    const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    const uint32_t chunk = blockIdx.x;
+    const uint32_t cbase = chunk * (uint32_t)CHUNK;
+    // every global load of the workgroup goes out first (the chunk's keys and values, the
+    // digit totals, this chunk's digit offsets): one memory round trip, not three; with
+    // spec (as k_radix_up) the keys and values go out before a device count too
+    KT key[ITEMS];
+    uint32_t val[ITEMS], rank[ITEMS];
+    auto load_items = [&]() {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t idx = cbase + w * (64 * ITEMS) + r * 64 + lane;
+            const bool valid = idx < K;
+            key[r] = valid ? kin[idx] : (KT)0;
+            val[r] = valid ? vin[idx] : 0u;
+        }
+    };
+    if (spec) load_items();
     dyn_args(dyn_count, dyn_zmin, K, zmin);
-    if (blockIdx.x * CHUNK >= K) return;
+    if (cbase >= K) return;
+    if (!spec) load_items();
     __shared__ uint32_t s_whist[4][256];   // per-wave digit counts, then per-wave digit prefix
     __shared__ uint32_t s_gbase[256];      // global position of this chunk's first key of each digit
     __shared__ uint32_t s_lstart[256];     // position in the LDS stage of each digit
@@ -126,21 +157,7 @@ __global__ __launch_bounds__(256) void k_radix_down(const KT *__restrict__ kin, 
     __shared__ KT s_keys[CHUNK];
     __shared__ uint32_t s_vals[CHUNK];
 
-    const uint32_t t = threadIdx.x, lane = lane_id(), w = t >> 6;
     const uint32_t dmask = (1u << nbits) - 1u;
-    const uint32_t chunk = blockIdx.x;
-    const uint32_t cbase = chunk * (uint32_t)CHUNK;
-    // every global load of the workgroup goes out first (the chunk's keys and values, the
-    // digit totals, this chunk's digit offsets): one memory round trip, not three
-    KT key[ITEMS];
-    uint32_t val[ITEMS], rank[ITEMS];
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t idx = cbase + w * (64 * ITEMS) + r * 64 + lane;
-        const bool valid = idx < K;
-        key[r] = valid ? kin[idx] : (KT)0;
-        val[r] = valid ? vin[idx] : 0u;
-    }
     const uint32_t tot_t = t <= dmask ? dtot[t] : 0u;
     const uint32_t off_t = t <= dmask ? off[(size_t)t * chunks + chunk] : 0u;
     for (int i = t; i < 4 * 256; i += 256) (&s_whist[0][0])[i] = 0;
@@ -264,7 +281,7 @@ template <typename KT, int VIEW>
 static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, uint32_t zmin, int dbits, int total_bits,
                       uint32_t *ghist, uint32_t *cnt, hipStream_t st, const uint32_t *dyn_count = nullptr,
                       const uint32_t *dyn_zmin = nullptr, const EmitFold *ef = nullptr, int first_shift = 0,
-                      bool first_counted = false) {
+                      bool first_counted = false, bool spec = false) {
     if (K == 0 || total_bits == 0) return 0;   // K is the count, or its upper bound with dyn_count
     const int passes = sort_passes(total_bits);
     const int per = (total_bits + passes - 1) / passes;
@@ -292,14 +309,14 @@ static int radix_sort(KT *ka, uint32_t *va, KT *kb, uint32_t *vb, uint32_t K, ui
 #define RECOGS_PASS(IT)                                                                                                    \
     if (p > 0 || !first_counted)                                                                                           \
         hipLaunchKernelGGL((k_radix_up<KT, VIEW, IT>), dim3(chunks), dim3(256), 0, st, kin, K, zmin, dbits, shift, nb,     \
-                           cnt, chunks, dyn_count, dyn_zmin);                                                              \
+                           cnt, chunks, dyn_count, dyn_zmin, (int)spec);                                                   \
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << nb), dim3(256), 0, st, cnt, chunks, chunk_keys, tot, K, dyn_count);     \
     if (fold)                                                                                                              \
         hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT, true>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K,    \
-                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, *ef);                            \
+                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, *ef, (int)spec);                 \
     else                                                                                                                   \
         hipLaunchKernelGGL((k_radix_down<KT, VIEW, IT, false>), dim3(chunks), dim3(256), 0, st, kin, vin, kout, vout, K,   \
-                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, none);
+                           zmin, dbits, shift, nb, cnt, tot, chunks, dyn_count, dyn_zmin, none, (int)spec);
         if (items == 16) { RECOGS_PASS(16) }
         else if (items == 8) { RECOGS_PASS(8) }
         else { RECOGS_PASS(4) }
@@ -331,12 +348,14 @@ int radix_sort_u32(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint3
 
 // The same with the count and the subtracted minimum read from device memory; K_max
 // bounds the count (sizes the grids and the count matrix). The digits start at bit
-// first_shift of the key (bits below it already ordered by an earlier pass).
+// first_shift of the key (bits below it already ordered by an earlier pass). spec: the
+// count is expected near K_max (the workgroups past it then load their chunk for
+// nothing), and the chunks are loaded before it arrives.
 int radix_sort_u32_dyn(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb, uint32_t K_max, const uint32_t *dyn_count,
                        const uint32_t *dyn_sub, int total_bits, uint32_t *ghist, uint32_t *cnt, hipStream_t st,
-                       const EmitFold *ef, int first_shift, bool first_counted) {
+                       const EmitFold *ef, int first_shift, bool first_counted, bool spec) {
     return radix_sort<uint32_t, KV_SUB>(ka, va, kb, vb, K_max, 0u, 0, total_bits, ghist, cnt, st, dyn_count, dyn_sub, ef,
-                                        first_shift, first_counted);
+                                        first_shift, first_counted, spec);
 }
 
 }  // namespace recogs

@@ -67,7 +67,8 @@ size_t outlier_workspace_bytes(int64_t);
 bool launch_outliers(const float *, int64_t, int64_t, int, float, float *, uint8_t *, float *, int64_t, uint32_t *, void *,
                      hipStream_t);
 int radix_sort_u32_dyn(uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t, const uint32_t *, const uint32_t *, int,
-                       uint32_t *, uint32_t *, hipStream_t, const EmitFold * = nullptr, int = 0, bool = false);
+                       uint32_t *, uint32_t *, hipStream_t, const EmitFold * = nullptr, int = 0, bool = false,
+                       bool = false);
 KeyCount key_sort_first_count(uint32_t *, uint32_t, int);
 void launch_preprocess_batch(int, int, uint32_t, const ViewDev *, int, SplatRec *, uint32_t *, uint2 *, uint32_t *,
                              hipStream_t);
@@ -389,8 +390,10 @@ static recogs_status render_async(const recogs_scene *scene, const recogs_camera
             const EmitFold ef{at<uint2>(ws, ws->off_rect), srect, at<uint32_t>(ws, ws->off_esum), cap};
             // the scan left the pairs ordered by their low 8 depth bits in dkeys1 (digit
             // totals in dhist[0..255]); three passes over the upper 24 bits remain
+            // (the passes load their chunks below n before the live count V arrives: at worst
+            // the n - V pairs past it are read for nothing)
             const int dalt = radix_sort_u32_dyn(dk1, dv1, dk0, dv0, (uint32_t)n, hdr + H_V, nullptr, 24, dhist + 256,
-                                                scount, stream, &ef, 8);
+                                                scount, stream, &ef, 8, false, true);
             uint32_t *order = dalt ? dv0 : dv1, *spare = dalt ? dv1 : dv0;
             if ((s = tm.mark(4)) != RECOGS_OK) return s;
             launch_emit_sorted(order, (uint32_t)n, at<uint2>(ws, ws->off_rect), srect, cd.tiles_x,
