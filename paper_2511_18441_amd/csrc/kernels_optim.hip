@@ -62,7 +62,7 @@ void launch_loss_l1(const float *y, const float *tg, int64_t count, float scale,
 
 // Adam, element-wise: m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
 // p <- p - lr (m / c1) / (sqrt(v / c2) + eps) with the bias corrections c1 = 1 - b1^step,
-// c2 = 1 - b2^step (computed by the host in double precision).
+// c2 = 1 - b2^step (their reciprocals computed by the host in double precision).
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
                                               float *__restrict__ v, int64_t count, AdamArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(256) void k_adam4(float4 *__restrict__ p, const flo
 }
 
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr, float b1, float b2, float eps,
-                 float c1, float c2, hipStream_t st) {
+                 float ic1, float ic2, hipStream_t st) {
     if (count <= 0) return;
-    const AdamArgs a{lr, b1, b2, eps, c1, c2};
+    const AdamArgs a{lr, b1, b2, eps, ic1, ic2};
     const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) | reinterpret_cast<uintptr_t>(m) |
                        reinterpret_cast<uintptr_t>(v)) & 15u) == 0;
     int64_t done = 0;

@@ -810,7 +810,7 @@ recogs_status recogs_render_backward_sh_adam(const recogs_scene *scene, const re
         return fail(RECOGS_ERR_INVALID, "beta1, beta2 must lie in [0, 1) and eps > 0");
     if (scene->n > 0 && (!m || !v)) return fail(RECOGS_ERR_INVALID, "NULL moment pointer");
     const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
-    const AdamArgs a{lr, beta1, beta2, eps, (float)c1, (float)c2};
+    const AdamArgs a{lr, beta1, beta2, eps, (float)(1.0 / c1), (float)(1.0 / c2)};
     return backward_impl(scene, cam, opts, ws, image, dL_dimage, dL_dopacity, nullptr, dL_dM, 0, true, stream, m, v, &a);
 }
 
@@ -877,7 +877,7 @@ recogs_status recogs_adam_step(float *param, const float *grad, float *m, float 
         return fail(RECOGS_ERR_INVALID, "beta1, beta2 must lie in [0, 1) and eps > 0");
     if (count > 0 && (!param || !grad || !m || !v)) return fail(RECOGS_ERR_INVALID, "NULL pointer");
     const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
-    launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, (float)c1, (float)c2, stream);
+    launch_adam(param, grad, m, v, count, lr, beta1, beta2, eps, (float)(1.0 / c1), (float)(1.0 / c2), stream);
     return hip_check("adam_step");
 }
 
