@@ -78,6 +78,12 @@ __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *_
                                                  const uint8_t *__restrict__ mask, const float *__restrict__ Mp,
                                                  const float *__restrict__ bp, int copy_unselected) {
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRecolorPer;
+    // the matrix and offset (uniform) are loaded with the mask, not after it
+    float M[9], bb[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) M[k] = Mp[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) bb[r] = bp[r];
     uint32_t sel = 0;   // byte k: Gaussian i0 + k selected
     if (i0 + kRecolorPer <= sc.n && ((uintptr_t)mask & 3u) == 0) {
         sel = *reinterpret_cast<const uint32_t *>(mask + i0);
@@ -90,38 +96,44 @@ __global__ __launch_bounds__(256) void k_recolor(SceneDev sc, int ncoef, void *_
             if (i0 + k < sc.n && !((sel >> (8 * k)) & 0xffu))
                 for (int p = 0; p < ncoef * 3; ++p)
                     Store<DT>::st(dst, p * sc.stride + i0 + k, Store<DT>::ldc(sc.sh, p * sc.stride + i0 + k));
-    // The selected Gaussians of the wave (a sparse selection leaves about one per wave)
-    // are recoloured one after the other by the whole wave: lane k takes coefficient k's
-    // three planes, so a Gaussian costs three loads and three stores of up to 16 lanes
-    // each instead of 48 of each from one lane. A lane loads its planes before it
-    // stores them, so the destination may alias the source.
-    uint64_t m = wave_ballot(sel != 0u);
+    // The selected Gaussians of the wave (a sparse selection leaves one or two per wave)
+    // are listed in index order in LDS; then each group of 16 lanes recolours one of them,
+    // four at a time: lane k of a group takes coefficient k's three planes, so a Gaussian
+    // costs three loads and three stores of up to 16 lanes each, and a wave's Gaussians
+    // cost one memory round trip per four instead of one each. A lane loads its planes
+    // before it stores them, so the destination may alias the source.
+    __shared__ uint16_t s_list[4][64 * kRecolorPer];
+    const uint64_t m = wave_ballot(sel != 0u);
     if (!m) return;
-    float M[9], off[3];
+    const int l = (int)lane_id(), w = (int)(threadIdx.x >> 6);
+    const uint32_t nsel_l = ((sel & 0xffu) ? 1u : 0u) + ((sel >> 8 & 0xffu) ? 1u : 0u) +
+                            ((sel >> 16 & 0xffu) ? 1u : 0u) + ((sel >> 24) ? 1u : 0u);   // selected of the lane
+    const uint32_t incl = wave_incl_scan(nsel_l);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    {
+        uint32_t pos = incl - nsel_l;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) M[k] = Mp[k];
+        for (int k = 0; k < kRecolorPer; ++k)
+            if ((sel >> (8 * k)) & 0xffu) s_list[w][pos++] = (uint16_t)(l * kRecolorPer + k);
+    }
+    wave_sync();   // the list written before any lane reads it
+    float off[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bp[r]) / kSH0;
-    const int l = (int)lane_id();
+    for (int r = 0; r < 3; ++r) off[r] = ((M[r * 3] + M[r * 3 + 1] + M[r * 3 + 2] - 1.0f) * 0.5f + bb[r]) / kSH0;
     const int64_t wbase = i0 - (int64_t)l * kRecolorPer;   // the first Gaussian of lane 0
-    while (m) {
-        const int src = __builtin_ctzll(m);
-        m &= m - 1;
-        uint32_t bits = (uint32_t)__builtin_amdgcn_readlane((int)sel, src);
-        while (bits) {
-            const int k = __builtin_ctz(bits) >> 3;
-            bits &= ~(0xffu << (8 * k));
-            const int64_t g = wbase + (int64_t)src * kRecolorPer + k;
-            if (l < ncoef) {
-                const float c0 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l) * sc.stride + g);
-                const float c1 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 1) * sc.stride + g);
-                const float c2 = Store<DT>::ldc(sc.sh, (int64_t)(3 * l + 2) * sc.stride + g);
+    const int grp = l >> 4, co = l & 15;
+    for (uint32_t j0 = 0; j0 < total; j0 += 4) {
+        const uint32_t j = j0 + (uint32_t)grp;
+        if (j < total && co < ncoef) {
+            const int64_t g = wbase + (int64_t)s_list[w][j];
+            const float c0 = Store<DT>::ldc(sc.sh, (int64_t)(3 * co) * sc.stride + g);
+            const float c1 = Store<DT>::ldc(sc.sh, (int64_t)(3 * co + 1) * sc.stride + g);
+            const float c2 = Store<DT>::ldc(sc.sh, (int64_t)(3 * co + 2) * sc.stride + g);
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
-                    if (l == 0) v += off[r];
-                    Store<DT>::st(dst, (int64_t)(3 * l + r) * sc.stride + g, v);
-                }
+            for (int r = 0; r < 3; ++r) {
+                float v = M[r * 3] * c0 + M[r * 3 + 1] * c1 + M[r * 3 + 2] * c2;
+                if (co == 0) v += off[r];
+                Store<DT>::st(dst, (int64_t)(3 * co + r) * sc.stride + g, v);
             }
         }
     }
