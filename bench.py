@@ -240,7 +240,13 @@ class Single:
 
 
 def stage_table(stages, bytes_, flops, st):
-    launches = {"key_sort": 3 * st["passes"], "depth_sort": 3 * st["dpasses"]}
+    if SORT_MODE == 0:
+        # the count scan: reduce, rowscan and down (which also does the depth sort's first
+        # pass); the emission: offsets and down (its reduce is in the depth sort's last
+        # pass, and it counts the key sort's first digit, whose up pass is then skipped)
+        launches = {"key_sort": max(0, 3 * st["passes"] - 1), "depth_sort": 3 * st["dpasses"], "scan": 3, "emit": 2}
+    else:
+        launches = {"key_sort": 3 * st["passes"], "depth_sort": 3 * st["dpasses"]}
     out = {}
     for k, t in stages.items():
         if k == "readback" or k not in bytes_:   # (the stages this sort mode does not run)
