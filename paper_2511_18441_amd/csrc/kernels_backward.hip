@@ -241,7 +241,6 @@ __global__ __launch_bounds__((TW / 8) * (TH / (8 * PPT)) * 64) void k_blend_bwd_
     float4 *__restrict__ sub, ulonglong2 *__restrict__ fw, uint32_t cap, uint32_t fstride, float4 *__restrict__ gk) {
 #pragma clang fp contract(off)
     constexpr uint32_t NR = (TW / 8) * (TH / (8 * PPT));
-    constexpr int NT = (int)NR * 64;
     __shared__ float4 sm[NR][64][3];   // per wave: (u, v, -, 1-based position), conic row, colour and sigma
     __shared__ uint32_t s_npl[NR];
     const uint32_t tile = blockIdx.x;
