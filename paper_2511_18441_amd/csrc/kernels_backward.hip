@@ -440,33 +440,41 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
                                                      int acc, float *__restrict__ psh, float *__restrict__ am,
                                                      float *__restrict__ av, AdamArgs aa, uint64_t slots,
                                                      const uint32_t *overflow) {
+    constexpr uint32_t kPiece = 256;   // slots staged per wave and round
     __shared__ float s_dm[4][9];
+    __shared__ float4 s_slot[4][kPiece];
     const bool ovf = overflow && *overflow;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     bool sel = false;
     float gh[3] = {0.f, 0.f, 0.f}, f[3] = {0.f, 0.f, 0.f};
-    if (i < n) {
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint32_t flags = 0;
-        const uint32_t c = count[i];
-        // a render that overflowed its key capacity (overflow flag set) has empty tile
-        // lists and no slot written: nothing is read and the sums stay zero; slots (the
-        // gradient buffer's capacity) bounds the reads in any case
-        if (!ovf && c > 0 && (uint64_t)koff[i] + c <= slots) {
-            // the Gaussian's (Gaussian, tile) slots, added in order; four loads in flight
-            const float4 *slot = gk + koff[i];
-            uint32_t k = 0;
-            for (; k + 4u <= c; k += 4u) {
-                const float4 x0 = slot[k], x1 = slot[k + 1], x2 = slot[k + 2], x3 = slot[k + 3];
-                a.x += x0.x; a.y += x0.y; a.z += x0.z; a.w += x0.w;
-                a.x += x1.x; a.y += x1.y; a.z += x1.z; a.w += x1.w;
-                a.x += x2.x; a.y += x2.y; a.z += x2.z; a.w += x2.w;
-                a.x += x3.x; a.y += x3.y; a.z += x3.z; a.w += x3.w;
-            }
-            for (; k < c; ++k) {
-                const float4 x = slot[k];
+    // The Gaussian's (Gaussian, tile) slots [s0, s1), added in order. A render that
+    // overflowed its key capacity (overflow flag set) has empty tile lists and no slot
+    // written: nothing is read and the sums stay zero; slots (the gradient buffer's
+    // capacity) bounds the reads in any case. The slots are Gaussian-major and the wave's
+    // Gaussians consecutive, so the wave's slots are one run [lo, hi): it is read
+    // coalesced into LDS, a piece at a time, and each lane adds its own from there.
+    const uint32_t c = i < n ? count[i] : 0u;
+    const uint32_t ko = i < n ? koff[i] : 0u;
+    const bool use = !ovf && c > 0 && (uint64_t)ko + c <= slots;
+    const uint32_t s0 = use ? ko : 0xffffffffu, s1 = use ? ko + c : 0u;
+    const uint32_t lo = wave_min(s0), hi = wave_max(s1);
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t base = lo; base < hi; base += kPiece) {
+        for (uint32_t j = lane; j < kPiece && base + j < hi; j += 64) s_slot[w][j] = gk[base + j];
+        wave_sync();
+        if (use) {
+            const uint32_t k0 = s0 > base ? s0 : base, k1 = s1 < base + kPiece ? s1 : base + kPiece;
+            for (uint32_t k = k0; k < k1; ++k) {
+                const float4 x = s_slot[w][k - base];
                 a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
             }
+        }
+        wave_sync();
+    }
+    if (i < n) {
+        uint32_t flags = 0;
+        if (use) {
             const float4 b = bwd[i];
             flags = __float_as_uint(b.w);
             f[0] = b.x; f[1] = b.y; f[2] = b.z;
@@ -518,7 +526,6 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
         }
     }
     if (!M) return;  // uniform: no recolour, no dL/dM
-    const uint32_t w = threadIdx.x >> 6;
     if (wave_ballot(sel)) {
 #pragma unroll
         for (int r = 0; r < 3; ++r)
