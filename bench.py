@@ -42,6 +42,7 @@ SORT_MODE = 0                    # (tile, depth, index) order: 0 depth-first, 2 
 BWD_FORM = "tile"                # the backward: "tile" (one workgroup per tile) or "block" (a wave per 8x8 block)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.sq.txt")
+LDS_PEAK_BPS = 128.0 * 256 * 2.4e9   # LDS return bandwidth: 128 B per CU per clock, 256 CUs, 2.4 GHz
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
 
@@ -833,6 +834,14 @@ def main():
             roof["executed_evals_max"] = ex
             roof["achieved_executed_max"] = round(ex * BLEND_FLOPS_PER_EVAL / (avg * 1e-3) / 1e12, 3)
             roof["valu_insts_per_launch"] = sq.get("sq_insts_valu")
+            if "lds_load_bytes" in sq:
+                # the second limit of the blend: bytes the LDS returns to the lanes (every
+                # wave step broadcasts its 36-byte record to 64 lanes), against 128 bytes per
+                # CU per clock at the 2.4 GHz peak clock
+                lds = sq["lds_load_bytes"] / (avg * 1e-3)
+                roof["lds_load_bytes_per_launch"] = sq["lds_load_bytes"]
+                roof["lds_TBps"] = round(lds / 1e12, 2)
+                roof["lds_frac"] = round(lds / LDS_PEAK_BPS, 4)
         else:
             roof["executed_evals_max"] = None
     else:
