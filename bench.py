@@ -42,7 +42,7 @@ SORT_MODE = 0                    # (tile, depth, index) order: 0 depth-first, 2 
 BWD_FORM = "tile"                # the backward: "tile" (one workgroup per tile) or "block" (a wave per 8x8 block)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.traffic.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_blend_{tw}x{th}_ppt{ppt}_1M_1080p_f32.sq.txt")
-LDS_PEAK_BPS = 128.0 * 256 * 2.4e9   # LDS return bandwidth: 128 B per CU per clock, 256 CUs, 2.4 GHz
+LDS_PEAK_BPS = 128.0 * 256 * 2.4e9   # LDS return rate: 128 B per CU per clock (CDNA3's figure), 256 CUs, 2.4 GHz
 BLEND_SOURCES = ("paper_2511_18441_amd/csrc/render_device.hpp", "paper_2511_18441_amd/csrc/kernels_render.hip",
                  "paper_2511_18441_amd/csrc/recogs_internal.hpp")
 
