@@ -513,11 +513,11 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float4 *__restrict__ 
                 for (int c = 0; c < 3; ++c) {
                     const int64_t o = (int64_t)(k * 3 + c) * stride + i;
                     if constexpr (ADAM) {
-                        float pp = psh[o], mm = am[o], vv = av[o];
+                        float pp = ld_stream(psh + o), mm = ld_stream(am + o), vv = ld_stream(av + o);
                         adam_update(pp, Y[k] * g[c], mm, vv, aa);
-                        am[o] = mm;
-                        av[o] = vv;
-                        psh[o] = pp;
+                        st_stream(am + o, mm);
+                        st_stream(av + o, vv);
+                        st_stream(psh + o, pp);
                     } else {
                         const float x = Y[k] * g[c];
                         out[o] = acc ? acc_add(out[o], x) : x;

@@ -67,11 +67,11 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ p, const float
                                               float *__restrict__ v, int64_t count, AdamArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        float pi = p[i], mi = m[i], vi = v[i];
-        adam_update(pi, g[i], mi, vi, a);
-        m[i] = mi;
-        v[i] = vi;
-        p[i] = pi;
+        float pi = ld_stream(p + i), mi = ld_stream(m + i), vi = ld_stream(v + i);
+        adam_update(pi, ld_stream(g + i), mi, vi, a);
+        st_stream(m + i, mi);
+        st_stream(v + i, vi);
+        st_stream(p + i, pi);
     }
 }
 
@@ -82,15 +82,15 @@ __global__ __launch_bounds__(256) void k_adam4(float4 *__restrict__ p, const flo
                                                AdamArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count4; i += stride) {
-        const float4 gi = g[i];
-        float4 mi = m[i], vi = v[i], pi = p[i];
+        const float4 gi = ld_stream(g + i);
+        float4 mi = ld_stream(m + i), vi = ld_stream(v + i), pi = ld_stream(p + i);
         adam_update(pi.x, gi.x, mi.x, vi.x, a);
         adam_update(pi.y, gi.y, mi.y, vi.y, a);
         adam_update(pi.z, gi.z, mi.z, vi.z, a);
         adam_update(pi.w, gi.w, mi.w, vi.w, a);
-        m[i] = mi;
-        v[i] = vi;
-        p[i] = pi;
+        st_stream(m + i, mi);
+        st_stream(v + i, vi);
+        st_stream(p + i, pi);
     }
 }
 
